@@ -1,0 +1,786 @@
+/*
+ * oracle.c -- plain, slow, FP64 CPU reference of the sparse-grid WENO5 method
+ * of Zhu & Zhang, "Fast sparse grid simulations of fifth order WENO scheme for
+ * high dimensional hyperbolic PDEs" (arXiv 2007.10196).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU library; neither side includes or
+ * links the other.
+ *
+ * Every function follows the paper's description step by step:
+ *   - eq. (1)                      : u_t + div f(u) = 0 (the flux families below)
+ *   - eq. (2.9)                    : conservative flux difference
+ *   - eqs. (2.7), (2.7.1)          : WENO5 candidate fluxes and their convex combination
+ *   - eq. (2.6)                    : nonlinear weights from linear weights d = (0.1, 0.6, 0.3)
+ *   - eq. (2.7.2)                  : Jiang-Shu smoothness indicators
+ *   - the negative-wind paragraph  : mirrored stencil about x_{i+1/2}
+ *   - eq. (LFflux)                 : global Lax-Friedrichs splitting
+ *   - Sec. 2.2                     : TVD-RK3 time marching, root grid, semi-coarsened grids,
+ *                                    index set I; Sec. 3 intro: one dt for all grids from
+ *                                    the finest spacing
+ *   - Sec. 2.2.1, eqs. (lwlag), (eqnlnwe), (si), (nlweno) : WENO5 interpolation with
+ *                                    the positive linear weights C_k(x)
+ *   - Sec. 2.2.2 and eq. (genformusgc) : the algorithm summary and the combination formula
+ *
+ * Readings of points the paper leaves open (all of them listed in the design
+ * notes of the repository):
+ *   - epsilon = 1e-6 in both the flux weights and the interpolation weights;
+ *   - the LF speed alpha is global per component grid, per direction and per
+ *     Runge-Kutta stage, taken over the stage input;
+ *   - CFL time step dt = CFL / sum_k (A_k / h_k^fine), A_k the maximum wave
+ *     speed over all component grids at u^n; the last step is clipped to T;
+ *   - nodes are x_{k,j} = lo_k + j h_k, j = 0..n_k-1, periodic (node n_k == node 0);
+ *   - fine node J refines to coarse node i = floor(J/R + 1/2), offset s = J/R - i,
+ *     s in [-1/2, 1/2) (the half-open interval of Sec. 2.2.1);
+ *   - prolongation runs over the directions in increasing order;
+ *   - L1 error = mean absolute error over the finest nodes, Linf = maximum.
+ *
+ * Compiled with -O2 -ffp-contract=off (no fused multiply-add, no fast math).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAXD 4
+
+/* flux families of eq. (1) used by the examples of Sec. 3 */
+enum { ORC_FLUX_ADVECTION = 0, ORC_FLUX_BURGERS = 1, ORC_FLUX_VLASOV = 2 };
+/* initial conditions */
+enum { ORC_IC_SINE = 0, ORC_IC_MAXWELL_COS = 1 };
+enum { ORC_DT_CFL = 0, ORC_DT_POW53 = 1 };
+enum { ORC_PROLONG_WENO5 = 0, ORC_PROLONG_LAGRANGE5 = 1 };
+
+typedef struct {
+    int32_t d;
+    int32_t flux;
+    int32_t ic;
+    int32_t pad_;
+    double lo[ORC_MAXD];
+    double hi[ORC_MAXD];
+    /* advection: fp[k] = a_k.  Vlasov with a fixed field: fp[0] = field amplitude,
+       fp[1] = field wavenumber; directions 0..d/2-1 are x, d/2..d-1 are v. */
+    double fp[ORC_MAXD];
+    /* sine:        u0 = ip[0] + ip[1] * sin(ip[2] * sum_k x_k + ip[3])
+       maxwell_cos: f0 = M(v) * (1 + ip[0] * prod_k cos(ip[1] * x_k + ip[2+k])) */
+    double ip[8];
+} orc_problem;
+
+typedef struct {
+    int32_t nr;          /* root cells per direction, N_r */
+    int32_t nl;          /* finest level, N_L */
+    int32_t dt_mode;
+    int32_t prolong;
+    int32_t linear;      /* 1: flux weights replaced by the linear weights d_r */
+    int32_t nthreads;    /* 0: library default */
+    double cfl;
+    double eps_flux;
+    double eps_interp;
+} orc_config;
+
+typedef struct {
+    int64_t steps;
+    double t;
+    double last_dt;
+    double min_dt;
+    double max_dt;
+} orc_stats;
+
+/* ------------------------------------------------------------------------- */
+/* Sparse-grid index set and combination coefficients (Sec. 2.2, eq. genformusgc) */
+
+static int64_t orc_binom(int n, int k)
+{
+    if (k < 0 || k > n) return 0;
+    int64_t r = 1;
+    for (int i = 1; i <= k; i++) r = r * (n - k + i) / i;
+    return r;
+}
+
+/* Enumerate all l in Z_{>=0}^d with |l| = s in lexicographic order of (l_1..l_d).
+   Returns the number written (levels may be NULL to count only). */
+static int orc_enum_sum(int d, int s, int *levels, int cap)
+{
+    if (s < 0) return 0;
+    int cnt = 0;
+    int l[ORC_MAXD] = {0, 0, 0, 0};
+    /* odometer over l_1..l_{d-1}, l_d = s - sum */
+    for (;;) {
+        int part = 0;
+        for (int k = 0; k < d - 1; k++) part += l[k];
+        if (part <= s) {
+            if (levels && cnt < cap) {
+                for (int k = 0; k < d - 1; k++) levels[cnt * ORC_MAXD + k] = l[k];
+                levels[cnt * ORC_MAXD + d - 1] = s - part;
+                for (int k = d; k < ORC_MAXD; k++) levels[cnt * ORC_MAXD + k] = 0;
+            }
+            cnt++;
+        }
+        /* advance odometer: last free digit fastest, so the order is lexicographic */
+        int k = d - 2;
+        while (k >= 0) {
+            l[k]++;
+            if (l[k] <= s) break;
+            l[k] = 0;
+            k--;
+        }
+        if (k < 0) break;
+    }
+    return cnt;
+}
+
+int orc_num_grids(int d, int nl)
+{
+    int cnt = 0;
+    for (int q = 0; q < d; q++) cnt += orc_enum_sum(d, nl - q, NULL, 0);
+    return cnt;
+}
+
+/* levels: [G][4], coefs: [G].  Grids with |l| = N_L - q carry (-1)^q C(d-1, q). */
+int orc_grid_set(int d, int nl, int *levels, int *coefs)
+{
+    int g = 0;
+    for (int q = 0; q < d; q++) {
+        int cnt = orc_enum_sum(d, nl - q, levels + g * ORC_MAXD, 1 << 30);
+        int c = (int)orc_binom(d - 1, q) * ((q % 2) ? -1 : 1);
+        for (int i = 0; i < cnt; i++) coefs[g + i] = c;
+        g += cnt;
+    }
+    return g;
+}
+
+/* ------------------------------------------------------------------------- */
+/* WENO5 pieces (Sec. 2.1) */
+
+/* eq. (2.7.2): smoothness indicators of the three substencils of (a,b,c,d,e) */
+void orc_smoothness(double a, double b, double c, double d, double e, double *beta)
+{
+    double t;
+    t = a - 2.0 * b + c;
+    beta[0] = (13.0 / 12.0) * t * t;
+    t = a - 4.0 * b + 3.0 * c;
+    beta[0] += 0.25 * t * t;
+    t = b - 2.0 * c + d;
+    beta[1] = (13.0 / 12.0) * t * t;
+    t = b - d;
+    beta[1] += 0.25 * t * t;
+    t = c - 2.0 * d + e;
+    beta[2] = (13.0 / 12.0) * t * t;
+    t = 3.0 * c - 4.0 * d + e;
+    beta[2] += 0.25 * t * t;
+}
+
+/* eqs. (2.7), (2.7.1), (2.6): numerical flux at x_{i+1/2} from the positive-wind
+   big stencil (a,b,c,d,e) = (f_{i-2}, f_{i-1}, f_i, f_{i+1}, f_{i+2}). */
+double orc_weno5(double a, double b, double c, double d, double e, double eps, int linear)
+{
+    double q0 = a / 3.0 - 7.0 * b / 6.0 + 11.0 * c / 6.0;
+    double q1 = -b / 6.0 + 5.0 * c / 6.0 + d / 3.0;
+    double q2 = c / 3.0 + 5.0 * d / 6.0 - e / 6.0;
+    double w0, w1, w2;
+    if (linear) {
+        w0 = 0.1;
+        w1 = 0.6;
+        w2 = 0.3;
+    } else {
+        double beta[3];
+        orc_smoothness(a, b, c, d, e, beta);
+        double a0 = 0.1 / ((eps + beta[0]) * (eps + beta[0]));
+        double a1 = 0.6 / ((eps + beta[1]) * (eps + beta[1]));
+        double a2 = 0.3 / ((eps + beta[2]) * (eps + beta[2]));
+        double s = a0 + a1 + a2;
+        w0 = a0 / s;
+        w1 = a1 / s;
+        w2 = a2 / s;
+    }
+    return w0 * q0 + w1 * q1 + w2 * q2;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Flux families, eq. (1) and the examples of Sec. 3 */
+
+static double orc_coord(const orc_problem *p, int k, int j, int n)
+{
+    double h = (p->hi[k] - p->lo[k]) / n;
+    return p->lo[k] + j * h;
+}
+
+/* f_k(u, x) and f_k'(u, x) */
+static void orc_flux(const orc_problem *p, int k, double u, const double *x, double *f, double *fp)
+{
+    switch (p->flux) {
+    case ORC_FLUX_ADVECTION:
+        *f = p->fp[k] * u;
+        *fp = p->fp[k];
+        break;
+    case ORC_FLUX_BURGERS:
+        *f = 0.5 * u * u;
+        *fp = u;
+        break;
+    default: { /* Vlasov with a fixed field: f_{x_k} = v_k u, f_{v_k} = E_k(x_k) u */
+        int dx = p->d / 2;
+        double c;
+        if (k < dx) c = x[dx + k];
+        else c = p->fp[0] * sin(p->fp[1] * x[k - dx]);
+        *f = c * u;
+        *fp = c;
+        break;
+    }
+    }
+}
+
+static double orc_u0(const orc_problem *p, const double *x)
+{
+    if (p->ic == ORC_IC_SINE) {
+        double s = 0.0;
+        for (int k = 0; k < p->d; k++) s += x[k];
+        return p->ip[0] + p->ip[1] * sin(p->ip[2] * s + p->ip[3]);
+    }
+    /* Maxwellian in v times a cosine perturbation in x */
+    int dx = p->d / 2;
+    double v2 = 0.0, pert = 1.0;
+    for (int k = 0; k < dx; k++) {
+        v2 += x[dx + k] * x[dx + k];
+        pert *= cos(p->ip[1] * x[k] + p->ip[2 + k]);
+    }
+    return exp(-0.5 * v2) / pow(2.0 * M_PI, 0.5 * dx) * (1.0 + p->ip[0] * pert);
+}
+
+/* ------------------------------------------------------------------------- */
+/* One component grid */
+
+typedef struct {
+    int d;
+    int n[ORC_MAXD];
+    int64_t stride[ORC_MAXD];
+    int64_t size;
+    double h[ORC_MAXD];
+} orc_grid;
+
+static void orc_grid_make(const orc_problem *p, int nr, const int *level, orc_grid *g)
+{
+    g->d = p->d;
+    g->size = 1;
+    for (int k = 0; k < ORC_MAXD; k++) {
+        if (k < p->d) {
+            g->n[k] = nr << level[k];
+            g->h[k] = (p->hi[k] - p->lo[k]) / g->n[k];
+        } else {
+            g->n[k] = 1;
+            g->h[k] = 0.0;
+        }
+        g->stride[k] = g->size;
+        g->size *= g->n[k];
+    }
+}
+
+static void orc_index_to_coords(const orc_grid *g, int64_t idx, int *j)
+{
+    for (int k = 0; k < ORC_MAXD; k++) {
+        j[k] = (int)(idx % g->n[k]);
+        idx /= g->n[k];
+    }
+}
+
+/* Alg. Step 1: evaluate the initial condition at the grid nodes */
+static void orc_restrict_grid(const orc_problem *p, const orc_grid *g, double *u)
+{
+    for (int64_t idx = 0; idx < g->size; idx++) {
+        int j[ORC_MAXD];
+        double x[ORC_MAXD] = {0, 0, 0, 0};
+        orc_index_to_coords(g, idx, j);
+        for (int k = 0; k < p->d; k++) x[k] = orc_coord(p, k, j[k], g->n[k]);
+        u[idx] = orc_u0(p, x);
+    }
+}
+
+/* Global LF speed of eq. (LFflux) on this grid, direction k: max over nodes of |f_k'(u)| */
+static double orc_alpha(const orc_problem *p, const orc_grid *g, const double *u, int k)
+{
+    double a = 0.0;
+    for (int64_t idx = 0; idx < g->size; idx++) {
+        int j[ORC_MAXD];
+        double x[ORC_MAXD] = {0, 0, 0, 0};
+        orc_index_to_coords(g, idx, j);
+        for (int kk = 0; kk < p->d; kk++) x[kk] = orc_coord(p, kk, j[kk], g->n[kk]);
+        double f, fp;
+        orc_flux(p, k, u[idx], x, &f, &fp);
+        if (fabs(fp) > a || isnan(fp)) a = fabs(fp);
+    }
+    return a;
+}
+
+/* Spatial operator L(u) = -sum_k (F_{i+1/2} - F_{i-1/2}) / h_k, eq. (2.9), with the
+   LF-split WENO5 fluxes F = F^+ + F^- of Sec. 2.1. */
+static void orc_rhs_grid(const orc_problem *p, const orc_config *c, const orc_grid *g,
+                         const double *u, double *L)
+{
+    for (int64_t i = 0; i < g->size; i++) L[i] = 0.0;
+    int nmax = 0;
+    for (int k = 0; k < g->d; k++)
+        if (g->n[k] > nmax) nmax = g->n[k];
+    double *pl = malloc(sizeof(double) * nmax);
+    double *mi = malloc(sizeof(double) * nmax);
+    double *F = malloc(sizeof(double) * nmax);
+    for (int k = 0; k < g->d; k++) {
+        int n = g->n[k];
+        int64_t st = g->stride[k];
+        double alpha = orc_alpha(p, g, u, k);
+        /* every line along direction k starts at a node with j_k = 0 */
+        for (int64_t base = 0; base < g->size; base++) {
+            int jb[ORC_MAXD];
+            orc_index_to_coords(g, base, jb);
+            if (jb[k] != 0) continue;
+            for (int i = 0; i < n; i++) {
+                int64_t idx = base + i * st;
+                double x[ORC_MAXD] = {0, 0, 0, 0};
+                for (int kk = 0; kk < g->d; kk++)
+                    x[kk] = orc_coord(p, kk, kk == k ? i : jb[kk], g->n[kk]);
+                double f, fp;
+                orc_flux(p, k, u[idx], x, &f, &fp);
+                pl[i] = 0.5 * (f + alpha * u[idx]); /* f^+ */
+                mi[i] = 0.5 * (f - alpha * u[idx]); /* f^- */
+            }
+            /* F[i] is the numerical flux at x_{i+1/2}; periodic indices */
+            for (int i = 0; i < n; i++) {
+#define W(j) (((j) % n + n) % n)
+                double fplus = orc_weno5(pl[W(i - 2)], pl[W(i - 1)], pl[W(i)], pl[W(i + 1)], pl[W(i + 2)],
+                                         c->eps_flux, c->linear);
+                double fminus = orc_weno5(mi[W(i + 3)], mi[W(i + 2)], mi[W(i + 1)], mi[W(i)], mi[W(i - 1)],
+                                          c->eps_flux, c->linear);
+                F[i] = fplus + fminus;
+            }
+            for (int i = 0; i < n; i++) {
+                L[base + i * st] -= (F[i] - F[W(i - 1)]) / g->h[k];
+#undef W
+            }
+        }
+    }
+    free(pl);
+    free(mi);
+    free(F);
+}
+
+/* ------------------------------------------------------------------------- */
+/* WENO5 / Lagrange5 interpolation (Sec. 2.2.1) */
+
+/* Value at x = x_i + s h, s in [-1/2, 1/2), from u[0..4] = u_{i-2..i+2}. */
+double orc_interp(const double *u, double s, double eps, int lagrange)
+{
+    /* positive linear weights of eq. (lwlag), written with x - x_{i+m} = (s - m) h */
+    double C0 = (s - 1.0) * (s - 2.0) / 12.0;
+    double C1 = (s + 2.0) * (s - 2.0) / -6.0;
+    double C2 = (s + 2.0) * (s + 1.0) / 12.0;
+    /* quadratic Lagrange interpolants on S_0, S_1, S_2 */
+    double P0 = u[0] * (s + 1.0) * s / 2.0 - u[1] * (s + 2.0) * s + u[2] * (s + 2.0) * (s + 1.0) / 2.0;
+    double P1 = u[1] * s * (s - 1.0) / 2.0 - u[2] * (s + 1.0) * (s - 1.0) + u[3] * (s + 1.0) * s / 2.0;
+    double P2 = u[2] * (s - 1.0) * (s - 2.0) / 2.0 - u[3] * s * (s - 2.0) + u[4] * s * (s - 1.0) / 2.0;
+    double w0, w1, w2;
+    if (lagrange) {
+        w0 = C0;
+        w1 = C1;
+        w2 = C2;
+    } else {
+        /* eq. (si) evaluates to the quadratic forms of eq. (2.7.2) on u */
+        double beta[3];
+        orc_smoothness(u[0], u[1], u[2], u[3], u[4], beta);
+        double t0 = C0 / ((eps + beta[0]) * (eps + beta[0]));
+        double t1 = C1 / ((eps + beta[1]) * (eps + beta[1]));
+        double t2 = C2 / ((eps + beta[2]) * (eps + beta[2]));
+        double sum = t0 + t1 + t2;
+        w0 = t0 / sum;
+        w1 = t1 / sum;
+        w2 = t2 / sum;
+    }
+    return w0 * P0 + w1 * P1 + w2 * P2;
+}
+
+/* Refine direction k of an array of shape n[] from n[k] to n[k] * R nodes. */
+static void orc_refine_dim(const int *n, int k, int R, const double *src, double *dst, double eps, int lagrange)
+{
+    int64_t inner = 1, outer = 1;
+    for (int kk = 0; kk < k; kk++) inner *= n[kk];
+    for (int kk = k + 1; kk < ORC_MAXD; kk++) outer *= n[kk];
+    int nc = n[k];
+    int64_t nf = (int64_t)nc * R;
+    for (int64_t o = 0; o < outer; o++)
+        for (int64_t a = 0; a < inner; a++)
+            for (int64_t J = 0; J < nf; J++) {
+                int64_t i = (2 * J + R) / (2 * (int64_t)R); /* floor(J/R + 1/2) */
+                double s = (double)(J - i * R) / R;          /* in [-1/2, 1/2) */
+                double st[5];
+                for (int m = 0; m < 5; m++) {
+                    int64_t ii = ((i + m - 2) % nc + nc) % nc;
+                    st[m] = src[(o * nc + ii) * inner + a];
+                }
+                dst[(o * nf + J) * inner + a] = orc_interp(st, s, eps, lagrange);
+            }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Public driver */
+
+typedef struct {
+    int G;
+    int *levels;
+    int *coefs;
+    orc_grid *grids;
+    int64_t *offsets;
+    int64_t total;
+} orc_set;
+
+static void orc_set_make(const orc_problem *p, const orc_config *c, orc_set *s)
+{
+    s->G = orc_num_grids(p->d, c->nl);
+    s->levels = malloc(sizeof(int) * ORC_MAXD * (s->G > 0 ? s->G : 1));
+    s->coefs = malloc(sizeof(int) * (s->G > 0 ? s->G : 1));
+    orc_grid_set(p->d, c->nl, s->levels, s->coefs);
+    s->grids = malloc(sizeof(orc_grid) * (s->G > 0 ? s->G : 1));
+    s->offsets = malloc(sizeof(int64_t) * (s->G + 1));
+    s->total = 0;
+    for (int g = 0; g < s->G; g++) {
+        orc_grid_make(p, c->nr, s->levels + g * ORC_MAXD, &s->grids[g]);
+        s->offsets[g] = s->total;
+        s->total += s->grids[g].size;
+    }
+    s->offsets[s->G] = s->total;
+}
+
+static void orc_set_free(orc_set *s)
+{
+    free(s->levels);
+    free(s->coefs);
+    free(s->grids);
+    free(s->offsets);
+}
+
+int64_t orc_total_nodes(const orc_problem *p, const orc_config *c)
+{
+    orc_set s;
+    orc_set_make(p, c, &s);
+    int64_t t = s.total;
+    orc_set_free(&s);
+    return t;
+}
+
+/* Alg. Step 1 on every component grid; state holds the grids back to back in
+   the order of orc_grid_set, each row-major with direction 1 fastest. */
+void orc_restrict(const orc_problem *p, const orc_config *c, double *state)
+{
+    orc_set s;
+    orc_set_make(p, c, &s);
+    for (int g = 0; g < s.G; g++) orc_restrict_grid(p, &s.grids[g], state + s.offsets[g]);
+    orc_set_free(&s);
+}
+
+/* Spatial operator of one component grid (exposed for the unit tests). */
+void orc_rhs(const orc_problem *p, const orc_config *c, const int *level, const double *u, double *L)
+{
+    orc_grid g;
+    orc_grid_make(p, c->nr, level, &g);
+    orc_rhs_grid(p, c, &g, u, L);
+}
+
+static void orc_rk3_step(const orc_problem *p, const orc_config *c, const orc_grid *g, double *u, double dt,
+                         double *u1, double *u2, double *L)
+{
+    int64_t n = g->size;
+    orc_rhs_grid(p, c, g, u, L);
+    for (int64_t i = 0; i < n; i++) u1[i] = u[i] + dt * L[i];
+    orc_rhs_grid(p, c, g, u1, L);
+    for (int64_t i = 0; i < n; i++) u2[i] = 0.75 * u[i] + 0.25 * (u1[i] + dt * L[i]);
+    orc_rhs_grid(p, c, g, u2, L);
+    for (int64_t i = 0; i < n; i++) u[i] = u[i] / 3.0 + 2.0 / 3.0 * (u2[i] + dt * L[i]);
+}
+
+/* Alg. Step 2: march every component grid (mask[g] != 0, or all when mask is NULL)
+   from t = 0 to T with one shared dt per step (Sec. 3 intro).  In CFL mode the
+   wave speed is taken over the masked grids only; a mask is therefore only
+   meaningful for problems whose wave speed does not depend on the state. */
+int orc_evolve(const orc_problem *p, const orc_config *c, double T, double *state, const unsigned char *mask,
+               orc_stats *st)
+{
+    orc_set s;
+    orc_set_make(p, c, &s);
+    double hfin[ORC_MAXD];
+    int nfin = c->nr << c->nl;
+    double hmin = INFINITY;
+    for (int k = 0; k < p->d; k++) {
+        hfin[k] = (p->hi[k] - p->lo[k]) / nfin;
+        if (hfin[k] < hmin) hmin = hfin[k];
+    }
+#ifdef _OPENMP
+    if (c->nthreads > 0) omp_set_num_threads(c->nthreads);
+#endif
+    double t = 0.0;
+    int64_t steps = 0;
+    double mindt = INFINITY, maxdt = 0.0, lastdt = 0.0;
+    while (T - t > 1e-12 * (T > 1.0 ? T : 1.0)) {
+        double dt;
+        if (c->dt_mode == ORC_DT_POW53) {
+            dt = pow(hmin, 5.0 / 3.0);
+        } else {
+            double denom = 0.0;
+            for (int k = 0; k < p->d; k++) {
+                double A = 0.0;
+                for (int g = 0; g < s.G; g++) {
+                    if (mask && !mask[g]) continue;
+                    double a = orc_alpha(p, &s.grids[g], state + s.offsets[g], k);
+                    if (a > A || isnan(a)) A = a;
+                }
+                denom += A / hfin[k];
+            }
+            if (isnan(denom)) {
+                orc_set_free(&s);
+                return -4;
+            }
+            dt = denom > 0.0 ? c->cfl / denom : T - t;
+        }
+        if (dt > T - t) dt = T - t;
+        int G = s.G;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int g = 0; g < G; g++) {
+            if (mask && !mask[g]) continue;
+            int64_t n = s.grids[g].size;
+            double *buf = malloc(sizeof(double) * 3 * n);
+            orc_rk3_step(p, c, &s.grids[g], state + s.offsets[g], dt, buf, buf + n, buf + 2 * n);
+            free(buf);
+        }
+        t += dt;
+        steps++;
+        if (dt < mindt) mindt = dt;
+        if (dt > maxdt) maxdt = dt;
+        lastdt = dt;
+    }
+    if (st) {
+        st->steps = steps;
+        st->t = t;
+        st->last_dt = lastdt;
+        st->min_dt = steps ? mindt : 0.0;
+        st->max_dt = maxdt;
+    }
+    orc_set_free(&s);
+    return 0;
+}
+
+/* Prolongation of one component grid onto the finest grid, directions in
+   increasing order (Sec. 2.2.1).  fine has (N_r 2^N_L)^d entries. */
+void orc_prolong(const orc_problem *p, const orc_config *c, const int *level, const double *u, double *fine)
+{
+    orc_grid g;
+    orc_grid_make(p, c->nr, level, &g);
+    int nfin = c->nr << c->nl;
+    int64_t ftot = 1;
+    for (int k = 0; k < p->d; k++) ftot *= nfin;
+    double *a = malloc(sizeof(double) * ftot);
+    double *b = malloc(sizeof(double) * ftot);
+    memcpy(a, u, sizeof(double) * g.size);
+    int n[ORC_MAXD];
+    for (int k = 0; k < ORC_MAXD; k++) n[k] = g.n[k];
+    for (int k = 0; k < p->d; k++) {
+        int m = c->nl - level[k];
+        if (m == 0) continue;
+        orc_refine_dim(n, k, 1 << m, a, b, c->eps_interp, c->prolong == ORC_PROLONG_LAGRANGE5);
+        n[k] = nfin;
+        double *t = a;
+        a = b;
+        b = t;
+    }
+    memcpy(fine, a, sizeof(double) * ftot);
+    free(a);
+    free(b);
+}
+
+/* Alg. Step 3: prolongate every grid and form the signed combination, grids
+   accumulated in the order of orc_grid_set. */
+void orc_prolong_combine(const orc_problem *p, const orc_config *c, const double *state, double *out)
+{
+    orc_set s;
+    orc_set_make(p, c, &s);
+    int nfin = c->nr << c->nl;
+    int64_t ftot = 1;
+    for (int k = 0; k < p->d; k++) ftot *= nfin;
+    double *tmp = malloc(sizeof(double) * ftot);
+    for (int64_t i = 0; i < ftot; i++) out[i] = 0.0;
+    for (int g = 0; g < s.G; g++) {
+        orc_prolong(p, c, s.levels + g * ORC_MAXD, state + s.offsets[g], tmp);
+        for (int64_t i = 0; i < ftot; i++) out[i] += s.coefs[g] * tmp[i];
+    }
+    free(tmp);
+    orc_set_free(&s);
+}
+
+/* The same value at one fine node J[] only: the dimension-by-dimension
+   prolongation restricted to the coarse lines that fine node depends on. */
+static double orc_prolong_point_grid(const orc_config *c, const orc_grid *g, const int *level, const double *u,
+                                     const int *J, int d)
+{
+    /* per direction: either a copy (m = 0) or a 5-point stencil with offset s */
+    int64_t ci[ORC_MAXD][5];
+    double s[ORC_MAXD];
+    int npts[ORC_MAXD];
+    for (int k = 0; k < d; k++) {
+        int m = c->nl - level[k];
+        int nc = g->n[k];
+        if (m == 0) {
+            ci[k][0] = J[k];
+            npts[k] = 1;
+            s[k] = 0.0;
+        } else {
+            int64_t R = (int64_t)1 << m;
+            int64_t i = (2 * (int64_t)J[k] + R) / (2 * R);
+            s[k] = (double)(J[k] - i * R) / R;
+            for (int q = 0; q < 5; q++) ci[k][q] = ((i + q - 2) % nc + nc) % nc;
+            npts[k] = 5;
+        }
+    }
+    /* gather the (up to) 5^d coarse values, then reduce direction 1 first */
+    int tot = 1;
+    for (int k = 0; k < d; k++) tot *= npts[k];
+    double *vals = malloc(sizeof(double) * tot);
+    for (int e = 0; e < tot; e++) {
+        int r = e;
+        int64_t idx = 0;
+        for (int k = 0; k < d; k++) {
+            int q = r % npts[k];
+            r /= npts[k];
+            idx += ci[k][q] * g->stride[k];
+        }
+        vals[e] = u[idx];
+    }
+    int cur = tot;
+    for (int k = 0; k < d; k++) {
+        if (npts[k] == 1) continue;
+        int next = cur / 5;
+        for (int e = 0; e < next; e++) {
+            double st[5];
+            for (int q = 0; q < 5; q++) st[q] = vals[e * 5 + q];
+            vals[e] = orc_interp(st, s[k], c->eps_interp, c->prolong == ORC_PROLONG_LAGRANGE5);
+        }
+        cur = next;
+    }
+    double v = vals[0];
+    free(vals);
+    return v;
+}
+
+/* Combined value at a list of fine nodes J[npts][4]. */
+void orc_prolong_combine_points(const orc_problem *p, const orc_config *c, const double *state, int64_t npts,
+                                const int *J, double *out)
+{
+    orc_set s;
+    orc_set_make(p, c, &s);
+    for (int64_t q = 0; q < npts; q++) {
+        double acc = 0.0;
+        for (int g = 0; g < s.G; g++)
+            acc += s.coefs[g] * orc_prolong_point_grid(c, &s.grids[g], s.levels + g * ORC_MAXD,
+                                                       state + s.offsets[g], J + q * ORC_MAXD, p->d);
+        out[q] = acc;
+    }
+    orc_set_free(&s);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Exact solutions used for the error norms */
+
+/* Burgers with u0 = g(sum_k x_k): u = w(xi, t), xi = sum x_k, w = g(xi - d w t);
+   Newton's method from w = g(xi).  Valid before the shock. */
+static double orc_burgers_exact(const orc_problem *p, const double *x, double t)
+{
+    double xi = 0.0;
+    for (int k = 0; k < p->d; k++) xi += x[k];
+    double c0 = p->ip[0], A = p->ip[1], kap = p->ip[2], ph = p->ip[3];
+    double d = p->d;
+    double w = c0 + A * sin(kap * xi + ph);
+    for (int it = 0; it < 100; it++) {
+        double arg = kap * (xi - d * w * t) + ph;
+        double F = w - c0 - A * sin(arg);
+        double dF = 1.0 + A * cos(arg) * kap * d * t;
+        double dw = F / dF;
+        w -= dw;
+        if (fabs(dw) < 1e-16 * (1.0 + fabs(w))) break;
+    }
+    return w;
+}
+
+/* Vlasov with E_k = amp sin(kE x_k): characteristics x' = v, v' = E(x) per pair
+   (x_k, v_k); integrate backward from t to 0 with classical RK4. */
+static void orc_pendulum_back(double amp, double kE, double t, double *x, double *v)
+{
+    int nsteps = (int)ceil(t / 1e-3);
+    if (nsteps < 1) return;
+    double h = -t / nsteps;
+    double X = *x, V = *v;
+    for (int s = 0; s < nsteps; s++) {
+        double k1x = V, k1v = amp * sin(kE * X);
+        double k2x = V + 0.5 * h * k1v, k2v = amp * sin(kE * (X + 0.5 * h * k1x));
+        double k3x = V + 0.5 * h * k2v, k3v = amp * sin(kE * (X + 0.5 * h * k2x));
+        double k4x = V + h * k3v, k4v = amp * sin(kE * (X + h * k3x));
+        X += h / 6.0 * (k1x + 2.0 * k2x + 2.0 * k3x + k4x);
+        V += h / 6.0 * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
+    }
+    *x = X;
+    *v = V;
+}
+
+double orc_exact(const orc_problem *p, const double *x, double t)
+{
+    double y[ORC_MAXD] = {0, 0, 0, 0};
+    switch (p->flux) {
+    case ORC_FLUX_ADVECTION:
+        for (int k = 0; k < p->d; k++) y[k] = x[k] - p->fp[k] * t;
+        return orc_u0(p, y);
+    case ORC_FLUX_BURGERS:
+        return orc_burgers_exact(p, x, t);
+    default: {
+        int dx = p->d / 2;
+        for (int k = 0; k < p->d; k++) y[k] = x[k];
+        for (int k = 0; k < dx; k++) orc_pendulum_back(p->fp[0], p->fp[1], t, &y[k], &y[dx + k]);
+        return orc_u0(p, y);
+    }
+    }
+}
+
+/* Fill the exact solution on the finest grid (N_r 2^N_L nodes per direction). */
+void orc_exact_fine(const orc_problem *p, const orc_config *c, double t, double *out)
+{
+    int nfin = c->nr << c->nl;
+    int64_t ftot = 1;
+    for (int k = 0; k < p->d; k++) ftot *= nfin;
+#pragma omp parallel for schedule(static)
+    for (int64_t idx = 0; idx < ftot; idx++) {
+        int64_t r = idx;
+        double x[ORC_MAXD] = {0, 0, 0, 0};
+        for (int k = 0; k < p->d; k++) {
+            x[k] = orc_coord(p, k, (int)(r % nfin), nfin);
+            r /= nfin;
+        }
+        out[idx] = orc_exact(p, x, t);
+    }
+}
+
+/* L1 = mean |a - b|, Linf = max |a - b| over n entries. */
+void orc_norms(const double *a, const double *b, int64_t n, double *l1, double *linf)
+{
+    double s = 0.0, m = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        double e = fabs(a[i] - b[i]);
+        s += e;
+        if (e > m || isnan(e)) m = e;
+    }
+    *l1 = n ? s / n : 0.0;
+    *linf = m;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
