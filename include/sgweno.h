@@ -1,0 +1,207 @@
+/*
+ * sgweno.h -- C ABI of libsgweno, the MI355X (gfx950) implementation of the
+ * sparse-grid fifth-order WENO method of Zhu & Zhang, "Fast sparse grid
+ * simulations of fifth order WENO scheme for high dimensional hyperbolic
+ * PDEs" (arXiv 2007.10196).
+ *
+ * The calls follow the paper's algorithm summary (Sec. 2.2.2):
+ *   Step 1  restrict the initial condition to the component grids   -> sgw_restrict_initial
+ *   Step 2  march every component grid to T with WENO5 + TVD-RK3     -> sgw_advance
+ *   Step 3  prolongate every grid to the finest grid and combine    -> sgw_prolongate_combine
+ * plus the error norms of Sec. 3 (sgw_exact, sgw_norms) and a batched
+ * runtime that advances many solves together (sgw_batch_*).
+ *
+ * Conventions
+ *   - Every call returns sgw_status: SGW_OK (0) or a negative error code; the
+ *     text of the last error of the calling thread is sgw_last_error().
+ *   - The library never allocates device memory.  The caller allocates the
+ *     state and scratch buffers with the sizes sgw_plan_footprint reports and
+ *     passes device pointers; the library keeps no reference to them after
+ *     sgw_solver_free.  Host-side objects (plans, solvers, batches) are owned
+ *     by the library and released by the matching *_free call.
+ *   - Device work is enqueued on the HIP stream given at creation (NULL means
+ *     the null stream) and is asynchronous unless a call says it synchronises.
+ *   - A solver must not be used from two host threads at once.
+ *   - Arrays on component grids and on the finest grid are row-major with
+ *     direction 1 fastest: index = j_1 + n_1 (j_2 + n_2 (j_3 + n_3 j_4)).
+ *     Node j of direction k sits at x = lo_k + j h_k, h_k = (hi_k - lo_k)/n_k,
+ *     periodic (node n_k is node 0).
+ */
+#ifndef SGWENO_H
+#define SGWENO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SGW_MAX_DIM 4
+
+typedef int32_t sgw_status;
+#define SGW_OK 0
+#define SGW_ERR_INVALID_ARG (-1)   /* an argument is out of range or inconsistent            */
+#define SGW_ERR_UNSUPPORTED (-2)   /* valid request the library does not implement           */
+#define SGW_ERR_OUT_OF_MEMORY (-3) /* a buffer or budget is too small                        */
+#define SGW_ERR_NONFINITE (-4)     /* a wave speed or time step became NaN/Inf on the device */
+#define SGW_ERR_HIP (-5)           /* a HIP runtime call failed                              */
+#define SGW_ERR_STATE (-6)         /* call out of order (e.g. advance before restrict)       */
+
+/* Flux of eq. (1): u_t + sum_k d/dx_k f_k(u, x) = 0 */
+#define SGW_FLUX_ADVECTION 0       /* f_k = a_k u, a_k = flux_params[k]                                 */
+#define SGW_FLUX_BURGERS 1         /* f_k = u^2 / 2                                                     */
+#define SGW_FLUX_VLASOV_FIXED_E 2  /* dim = 2 m: directions 1..m are x, m+1..2m are v;
+                                      f_{x_k} = v_k u, f_{v_k} = E_k(x_k) u with
+                                      E_k = flux_params[0] sin(flux_params[1] x_k)                     */
+
+/* Initial conditions */
+#define SGW_IC_SINE 0              /* u0 = p0 + p1 sin(p2 sum_k x_k + p3)                               */
+#define SGW_IC_MAXWELL_COS 1       /* f0 = exp(-|v|^2/2) / (2 pi)^(m/2) (1 + p0 prod_k cos(p1 x_k + p_{2+k})) */
+
+#define SGW_DT_CFL 0               /* dt = cfl / sum_k (A_k / h_k^fine), A_k = max wave speed (Sec. 3) */
+#define SGW_DT_POW53 1             /* dt = (min_k h_k^fine)^(5/3), the accuracy-test rule of Sec. 3     */
+
+#define SGW_PROLONG_WENO5 0        /* WENO5 interpolation, eqs. (eqnlnwe), (si), (nlweno)               */
+#define SGW_PROLONG_LAGRANGE5 1    /* degree-4 Lagrange interpolation, eq. (lwlag)                      */
+
+#define SGW_FP64 0                 /* state, sweeps and interpolation in FP64                           */
+#define SGW_FP32_SWEEP 1           /* state, sweeps and interpolation in FP32; t, dt, the combination
+                                      sum and the norms in FP64                                          */
+
+#define SGW_RUN_PLAIN 0            /* one launch per component grid per RK stage, no graph              */
+#define SGW_RUN_FUSED 1            /* one launch per RK stage over all component grids                  */
+#define SGW_RUN_GRAPH 2            /* SGW_RUN_FUSED with each time step captured in a HIP graph         */
+
+typedef struct sgw_problem {
+    int32_t dim;                   /* 1..4                                                   */
+    int32_t flux;                  /* SGW_FLUX_*                                              */
+    int32_t ic;                    /* SGW_IC_*                                                */
+    int32_t reserved0;             /* must be 0                                               */
+    double lo[SGW_MAX_DIM];        /* domain [lo_k, hi_k), periodic in every direction        */
+    double hi[SGW_MAX_DIM];
+    double flux_params[SGW_MAX_DIM];
+    double ic_params[8];
+} sgw_problem;
+
+typedef struct sgw_config {
+    int32_t root_cells;            /* N_r >= 4: cells per direction of the root grid (Sec. 2.2)   */
+    int32_t finest_level;          /* N_L in 0..12                                                 */
+    int32_t dt_mode;               /* SGW_DT_*                                                     */
+    int32_t prolong;               /* SGW_PROLONG_*                                                */
+    int32_t linear_weights;        /* 1: flux weights w_r replaced by d_r (the linear scheme)     */
+    int32_t precision;             /* SGW_FP64 or SGW_FP32_SWEEP                                   */
+    double cfl;                    /* 0 < cfl <= 1.5 (used in SGW_DT_CFL)                          */
+    double eps_flux;               /* epsilon of eq. (2.6); the paper's tables need 1e-3           */
+    double eps_interp;             /* epsilon of eq. (eqnlnwe); 1e-3 likewise                      */
+    int32_t box[SGW_MAX_DIM];      /* 0: automatic; else the stage-kernel box extent per direction
+                                      (must divide every grid's extent in that direction)         */
+    int32_t fine_tile[SGW_MAX_DIM];/* 0: automatic; else the prolongation tile per direction       */
+    int32_t box_target;            /* 0: automatic; else the largest box (nodes) the automatic
+                                      box search may pick, 256..2048                               */
+    int32_t reserved1;             /* must be 0                                                    */
+} sgw_config;
+
+typedef struct sgw_plan sgw_plan_t;
+typedef struct sgw_solver sgw_solver_t;
+typedef struct sgw_batch sgw_batch_t;
+
+/* ---------------------------------------------------------------- plans (host only)
+ * sgw_plan_create enumerates the component grids of the index set
+ * { l : N_L - dim + 1 <= |l| <= N_L } (Sec. 2.2 for 2D, eq. (genformusgc) for
+ * general dim), q = N_L - |l| from 0 to dim-1, each q in lexicographic order of
+ * (l_1..l_dim), with combination coefficient (-1)^q C(dim-1, q).  Grid l has
+ * N_r 2^{l_k} nodes in direction k.  Errors: SGW_ERR_INVALID_ARG for dim
+ * outside 1..4, N_r < 4, N_L outside 0..12, cfl outside (0, 1.5], eps <= 0,
+ * a Vlasov flux with odd dim, or a finest grid with more than 2^40 nodes;
+ * SGW_ERR_UNSUPPORTED for a box or tile that does not divide the extents. */
+sgw_status sgw_plan_create(const sgw_problem* problem, const sgw_config* config, sgw_plan_t** out);
+void sgw_plan_free(sgw_plan_t* plan);
+
+/* Bytes the caller must provide: state (three copies of every component grid:
+ * u^n and the two Runge-Kutta stage buffers), scratch (descriptors, work
+ * lists, wave speeds, time-step record, reductions), and the finest-grid FP64
+ * output of sgw_prolongate_combine.  Any pointer may be NULL. */
+sgw_status sgw_plan_footprint(const sgw_plan_t* plan, uint64_t* state_bytes, uint64_t* scratch_bytes,
+                              uint64_t* fine_bytes);
+
+/* Number of grids, component nodes (sum over grids), finest-grid nodes. */
+sgw_status sgw_plan_info(const sgw_plan_t* plan, int32_t* num_grids, int64_t* total_nodes,
+                         int64_t* fine_nodes);
+
+/* Grid g: level l_k, node counts, coefficient and element offset of its first
+ * node inside each state copy (copy u^n starts at byte 0 of the state buffer). */
+sgw_status sgw_plan_grid(const sgw_plan_t* plan, int32_t g, int32_t level[SGW_MAX_DIM],
+                         int32_t shape[SGW_MAX_DIM], int32_t* coef, int64_t* offset);
+
+/* Box extents the stage kernel uses for grid g (one workgroup per box). */
+sgw_status sgw_plan_grid_box(const sgw_plan_t* plan, int32_t g, int32_t box[SGW_MAX_DIM]);
+
+/* ---------------------------------------------------------------- solvers
+ * Binds a plan to caller-owned device memory (at least the footprint sizes,
+ * 256-byte aligned) and a HIP stream (hipStream_t passed as void*).  The plan
+ * must outlive the solver.  Uploads the grid descriptors (stream-ordered). */
+sgw_status sgw_solver_create(sgw_plan_t* plan, void* state_dev, void* scratch_dev, void* hip_stream,
+                             sgw_solver_t** out);
+void sgw_solver_free(sgw_solver_t* solver);
+
+/* Alg. Step 1: u^0 = u0 at the nodes of every component grid; t = 0. */
+sgw_status sgw_restrict_initial(sgw_solver_t* solver);
+
+/* Alg. Step 2: march every component grid from the current t to t_final with
+ * one shared dt per step (Sec. 3: set by the finest spacing, the CFL number
+ * and the current wave speed; the last step is clipped to land on t_final).
+ * Each step is three TVD-RK3 stages; each stage applies the LF-split WENO5
+ * operator of Sec. 2.1 in every direction with the global LF speed of that
+ * grid, direction and stage.  mode is SGW_RUN_*.  For state-dependent wave
+ * speeds the host polls a device flag every few steps (synchronises). */
+sgw_status sgw_advance(sgw_solver_t* solver, double t_final, int32_t mode);
+
+/* Alg. Step 3: out_dev (FP64, (N_r 2^N_L)^dim entries) = sum_g c_g P U_g, with
+ * P the dimension-by-dimension WENO5 (or Lagrange5) prolongation of Sec. 2.2.1
+ * in increasing direction order; accumulated in FP64 in grid order. */
+sgw_status sgw_prolongate_combine(sgw_solver_t* solver, double* out_dev);
+
+/* Exact solution at time t on the finest grid (FP64), for the error norms:
+ * advection: u0(x - a t); Burgers with a sine: characteristics solved by
+ * Newton's method (valid before the shock); Vlasov: f0 at the foot of the
+ * characteristic, classical RK4 with steps of at most 1e-3. */
+sgw_status sgw_exact(sgw_solver_t* solver, double t, double* out_dev);
+
+/* L1 = mean |a - b|, Linf = max |a - b| over the finest grid, in FP64 and in a
+ * fixed order (bitwise repeatable).  Writes result_host[0..1]; synchronises. */
+sgw_status sgw_norms(sgw_solver_t* solver, const double* a_dev, const double* b_dev, double* result_host);
+
+/* Current time and number of steps taken; synchronises.  Returns
+ * SGW_ERR_NONFINITE if a wave speed or dt became NaN/Inf. */
+sgw_status sgw_query(sgw_solver_t* solver, double* t, int64_t* steps);
+
+/* ---------------------------------------------------------------- batches
+ * A batch advances the component grids of many solvers together: one fused
+ * stage launch per RK stage over the grids of every active solver, each solver
+ * with its own t, dt and final time, one HIP graph per step.  All solvers in a
+ * batch share the batch's stream and precision.  hbm_budget bounds the sum of
+ * the footprints (state + scratch + fine) of the admitted solvers. */
+sgw_status sgw_batch_create(int32_t max_solvers, int32_t precision, uint64_t hbm_budget, void* hip_stream,
+                            void* scratch_dev, uint64_t scratch_bytes, sgw_batch_t** out);
+void sgw_batch_free(sgw_batch_t* batch);
+/* Scratch bytes a batch of max_solvers needs for at most max_items stage boxes. */
+uint64_t sgw_batch_scratch_bytes(int32_t max_solvers, int64_t max_items);
+/* Admit a restricted solver to advance to t_final.  SGW_ERR_OUT_OF_MEMORY when
+ * no slot is free or its footprint does not fit the remaining budget. */
+sgw_status sgw_batch_admit(sgw_batch_t* batch, sgw_solver_t* solver, double t_final, int32_t* slot);
+/* Advance every active solver by up to nsteps steps (finished ones do nothing). */
+sgw_status sgw_batch_step(sgw_batch_t* batch, int32_t nsteps);
+/* Which slots have reached their final time (synchronises).  done_slots has
+ * room for max_solvers entries. */
+sgw_status sgw_batch_poll(sgw_batch_t* batch, int32_t* done_slots, int32_t* n_done);
+/* Remove a solver from the batch; its budget and slot become free. */
+sgw_status sgw_batch_release(sgw_batch_t* batch, int32_t slot);
+
+/* ---------------------------------------------------------------- errors */
+const char* sgw_status_string(sgw_status status);
+const char* sgw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGWENO_H */

@@ -1,0 +1,813 @@
+// Host side of libsgweno: plans (grid enumeration, layout, tiling), solvers
+// bound to caller memory, the time loop and the C entry points of sgweno.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "sgw_api_internal.h"
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+sgw_status sgw_fail(sgw_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+sgw_status sgw_hip_fail(hipError_t e, const char* what)
+{
+    return sgw_fail(SGW_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char* sgw_last_error(void) { return g_err; }
+
+extern "C" const char* sgw_status_string(sgw_status s)
+{
+    switch (s) {
+    case SGW_OK: return "ok";
+    case SGW_ERR_INVALID_ARG: return "invalid argument";
+    case SGW_ERR_UNSUPPORTED: return "unsupported";
+    case SGW_ERR_OUT_OF_MEMORY: return "out of memory";
+    case SGW_ERR_NONFINITE: return "non-finite wave speed or time step";
+    case SGW_ERR_HIP: return "HIP error";
+    case SGW_ERR_STATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
+
+static int smallest_factor(int n)
+{
+    for (int p = 2; p * p <= n; p++)
+        if (n % p == 0) return p;
+    return n;
+}
+
+// ---------------------------------------------------------------- index set
+// All l in Z_{>=0}^d with |l| = s, lexicographic in (l_1..l_d): the first
+// component counts up from 0 and the rest are filled recursively.
+static void compositions(int d, int s, int pos, int* cur, std::vector<std::array<int, 4>>& out)
+{
+    if (pos == d - 1) {
+        cur[pos] = s;
+        std::array<int, 4> a = {0, 0, 0, 0};
+        for (int k = 0; k < d; k++) a[k] = cur[k];
+        out.push_back(a);
+        return;
+    }
+    for (int v = 0; v <= s; v++) {
+        cur[pos] = v;
+        compositions(d, s - v, pos + 1, cur, out);
+    }
+}
+
+static int64_t binom(int n, int k)
+{
+    if (k < 0 || k > n) return 0;
+    int64_t r = 1;
+    for (int i = 0; i < k; i++) r = r * (n - i) / (i + 1);
+    return r;
+}
+
+// ---------------------------------------------------------------- tiling
+
+static void fill_box_geometry(GridDev& g, int precision)
+{
+    (void)precision;
+    int core = 1, pad = 1;
+    for (int k = 0; k < SGW_MAX_DIM; k++) {
+        if (k >= g.d) {
+            g.t[k] = 1;
+            g.halo[k] = 0;
+            g.ntile[k] = 1;
+            g.P[k] = 1;
+            continue;
+        }
+        g.halo[k] = (g.t[k] < g.n[k]) ? 3 : 0;
+        g.ntile[k] = g.n[k] / g.t[k];
+        g.P[k] = g.t[k] + 2 * g.halo[k];
+    }
+    for (int k = 0; k < SGW_MAX_DIM; k++) {
+        g.CS[k] = core;
+        g.PS[k] = pad;
+        core *= g.t[k];
+        pad *= g.P[k];
+    }
+    g.core_total = core;
+    g.pad_total = pad;
+    g.nbox = 1;
+    for (int k = 0; k < g.d; k++) g.nbox *= g.ntile[k];
+    for (int k = 0; k < SGW_MAX_DIM; k++) {
+        g.I[k] = g.t[k] + (g.halo[k] ? 1 : 0);
+        g.flux_total[k] = (k < g.d) ? core / g.t[k] * g.I[k] : 0;
+        g.fd_P[k] = make_fastdiv((uint32_t)g.P[k]);
+        g.fd_t[k] = make_fastdiv((uint32_t)g.t[k]);
+        g.fd_I[k] = make_fastdiv((uint32_t)g.I[k]);
+        g.fd_CSt[k] = make_fastdiv((uint32_t)(g.CS[k] * g.t[k]));
+        g.fd_n[k] = make_fastdiv((uint32_t)(k < g.d ? g.n[k] : 1));
+    }
+}
+
+// Box search: every combination of divisors t_k | n_k with a core of at most
+// `target` nodes that fits the LDS budget; the cost per core node weighs the
+// staged values (halo included; narrow rows along the contiguous direction
+// count extra) against the interface fluxes (each costs two WENO5
+// reconstructions, ~25 times a staged load).
+static void choose_box(GridDev& g, int precision, int target, size_t lds_cap)
+{
+    std::vector<int> divs[SGW_MAX_DIM];
+    for (int k = 0; k < SGW_MAX_DIM; k++) {
+        if (k >= g.d) {
+            divs[k].push_back(1);
+            continue;
+        }
+        for (int v = 1; v <= g.n[k]; v++)
+            if (g.n[k] % v == 0) divs[k].push_back(v);
+    }
+    const int64_t grid_nodes = (int64_t)g.n[0] * g.n[1] * g.n[2] * g.n[3];
+    const int min_core = (int)(grid_nodes < SGW_BLOCK ? grid_nodes : SGW_BLOCK);
+    const double rs = precision == SGW_FP64 ? 8.0 : 4.0;
+    double best = 1e300;
+    int bt[SGW_MAX_DIM] = {g.n[0], g.n[1], g.n[2], g.n[3]};
+    for (int a : divs[0])
+        for (int b : divs[1])
+            for (int c : divs[2])
+                for (int e : divs[3]) {
+                    const int64_t core = (int64_t)a * b * c * e;
+                    if (core > target || core > SGW_BLOCK * SGW_MAXR || core < min_core) continue;
+                    g.t[0] = a;
+                    g.t[1] = b;
+                    g.t[2] = c;
+                    g.t[3] = e;
+                    fill_box_geometry(g, precision);
+                    if (stage_lds_bytes(g, precision) > lds_cap) continue;
+                    double flux = 0.0;
+                    for (int k = 0; k < g.d; k++) flux += (double)g.flux_total[k];
+                    const double row_bytes = g.P[0] * rs;
+                    const double load = g.pad_total * (row_bytes < 64.0 ? 64.0 / row_bytes : 1.0);
+                    const double cost = (load + 25.0 * flux) / (double)core + 2000.0 / (double)core;
+                    if (cost < best - 1e-12) {
+                        best = cost;
+                        for (int k = 0; k < SGW_MAX_DIM; k++) bt[k] = g.t[k];
+                    }
+                }
+    for (int k = 0; k < SGW_MAX_DIM; k++) g.t[k] = bt[k];
+    fill_box_geometry(g, precision);
+}
+
+static size_t prolong_buffer_elems(const sgw_plan& p, const int* T)
+{
+    size_t best = 0;
+    for (int g = 0; g < p.G; g++) {
+        int c[SGW_MAX_DIM];
+        for (int k = 0; k < p.pb.dim; k++) {
+            const int m = p.cfg.finest_level - p.levels[g][k];
+            c[k] = m == 0 ? T[k] : (T[k] - 1) / (1 << m) + 6;
+        }
+        size_t load = 1;
+        for (int k = 0; k < p.pb.dim; k++) load *= (size_t)c[k];
+        best = load > best ? load : best;
+        for (int k = 0; k < p.pb.dim; k++) {
+            size_t sz = 1;
+            for (int j = 0; j < p.pb.dim; j++) sz *= (size_t)(j <= k ? T[j] : c[j]);
+            best = sz > best ? sz : best;
+        }
+    }
+    return (best + 1) / 2 * 2;
+}
+
+static void choose_fine_tile(sgw_plan& p)
+{
+    const int d = p.pb.dim;
+    const size_t rs = p.cfg.precision == SGW_FP64 ? 8 : 4;
+    int T[SGW_MAX_DIM] = {1, 1, 1, 1};
+    bool manual = false;
+    for (int k = 0; k < d; k++) {
+        T[k] = p.cfg.fine_tile[k] > 0 ? p.cfg.fine_tile[k] : p.N;
+        manual |= p.cfg.fine_tile[k] > 0;
+    }
+    const int target = d <= 2 ? 1024 : 2048;
+    if (!manual) {
+        for (;;) {
+            int pts = 1;
+            for (int k = 0; k < d; k++) pts *= T[k];
+            const size_t lds = 2 * rs * prolong_buffer_elems(p, T);
+            if (pts <= target && lds <= 64 * 1024) break;
+            int kk = -1;
+            for (int k = d - 1; k >= 0; k--)
+                if (T[k] > 1 && (kk < 0 || T[k] > T[kk])) kk = k;
+            if (kk < 0) break;
+            T[kk] /= smallest_factor(T[kk]);
+        }
+    }
+    for (int k = 0; k < SGW_MAX_DIM; k++) p.fine_T[k] = k < d ? T[k] : 1;
+    p.pro_buf_elems = prolong_buffer_elems(p, p.fine_T);
+}
+
+// ---------------------------------------------------------------- plans
+
+extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* cfg, sgw_plan_t** out)
+{
+    if (!pb || !cfg || !out) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    const int d = pb->dim;
+    if (d < 1 || d > SGW_MAX_DIM) return sgw_fail(SGW_ERR_INVALID_ARG, "dim %d outside 1..4", d);
+    if (cfg->root_cells < 4) return sgw_fail(SGW_ERR_INVALID_ARG, "root_cells %d < 4", cfg->root_cells);
+    if (cfg->finest_level < 0 || cfg->finest_level > 12)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "finest_level %d outside 0..12", cfg->finest_level);
+    if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.5)) return sgw_fail(SGW_ERR_INVALID_ARG, "cfl %g outside (0, 1.5]", cfg->cfl);
+    if (!(cfg->eps_flux > 0.0) || !(cfg->eps_interp > 0.0))
+        return sgw_fail(SGW_ERR_INVALID_ARG, "epsilon must be positive");
+    if (pb->flux < 0 || pb->flux > 2) return sgw_fail(SGW_ERR_INVALID_ARG, "unknown flux %d", pb->flux);
+    if (pb->ic < 0 || pb->ic > 1) return sgw_fail(SGW_ERR_INVALID_ARG, "unknown initial condition %d", pb->ic);
+    if ((pb->flux == SGW_FLUX_VLASOV_FIXED_E || pb->ic == SGW_IC_MAXWELL_COS) && (d % 2))
+        return sgw_fail(SGW_ERR_INVALID_ARG, "phase-space problems need an even dim");
+    if (cfg->dt_mode != SGW_DT_CFL && cfg->dt_mode != SGW_DT_POW53)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "unknown dt_mode %d", cfg->dt_mode);
+    if (cfg->prolong != SGW_PROLONG_WENO5 && cfg->prolong != SGW_PROLONG_LAGRANGE5)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "unknown prolongation %d", cfg->prolong);
+    if (cfg->precision != SGW_FP64 && cfg->precision != SGW_FP32_SWEEP)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "unknown precision %d", cfg->precision);
+    for (int k = 0; k < d; k++)
+        if (!(pb->hi[k] > pb->lo[k])) return sgw_fail(SGW_ERR_INVALID_ARG, "empty domain in direction %d", k);
+    const int64_t N = (int64_t)cfg->root_cells << cfg->finest_level;
+    double fine_nodes = 1.0;
+    for (int k = 0; k < d; k++) fine_nodes *= (double)N;
+    if (N > (1 << 20) || fine_nodes > 1099511627776.0)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "finest grid too large (%lld per direction)", (long long)N);
+
+    sgw_plan* p = new sgw_plan();
+    p->pb = *pb;
+    p->cfg = *cfg;
+    p->N = (int)N;
+    p->fine_nodes = 1;
+    for (int k = 0; k < d; k++) p->fine_nodes *= N;
+    // index set: q = 0..d-1, |l| = N_L - q, coefficient (-1)^q C(d-1, q)
+    for (int q = 0; q < d; q++) {
+        const int s = cfg->finest_level - q;
+        if (s < 0) continue;
+        std::vector<std::array<int, 4>> ls;
+        int cur[4] = {0, 0, 0, 0};
+        compositions(d, s, 0, cur, ls);
+        for (auto& l : ls) {
+            p->levels.push_back(l);
+            p->coefs.push_back((int)(binom(d - 1, q) * ((q & 1) ? -1 : 1)));
+        }
+    }
+    p->G = (int)p->levels.size();
+    p->offsets.resize(p->G + 1);
+    p->grids.resize(p->G);
+    int64_t tot = 0;
+    const size_t lds_cap = 64 * 1024;
+    int target = cfg->precision == SGW_FP64 ? 1024 : 2048;
+    if (cfg->box_target) {
+        if (cfg->box_target < 64 || cfg->box_target > SGW_BLOCK * SGW_MAXR) {
+            delete p;
+            return sgw_fail(SGW_ERR_INVALID_ARG, "box_target %d outside 64..%d", cfg->box_target, SGW_BLOCK * SGW_MAXR);
+        }
+        target = cfg->box_target;
+    }
+    for (int g = 0; g < p->G; g++) {
+        GridDev& gd = p->grids[g];
+        std::memset(&gd, 0, sizeof(gd));
+        gd.d = d;
+        int64_t n = 1;
+        for (int k = 0; k < SGW_MAX_DIM; k++) {
+            gd.n[k] = k < d ? (cfg->root_cells << p->levels[g][k]) : 1;
+            gd.stride[k] = (int32_t)n;
+            n *= gd.n[k];
+        }
+        if (n > (1ll << 30)) {
+            delete p;
+            return sgw_fail(SGW_ERR_INVALID_ARG, "component grid too large");
+        }
+        p->offsets[g] = tot;
+        tot += n;
+        bool manual = false;
+        for (int k = 0; k < d; k++) manual |= cfg->box[k] > 0;
+        if (manual) {
+            for (int k = 0; k < SGW_MAX_DIM; k++) {
+                gd.t[k] = (k < d && cfg->box[k] > 0) ? (cfg->box[k] < gd.n[k] ? cfg->box[k] : gd.n[k])
+                                                     : (k < d ? gd.n[k] : 1);
+                if (k < d && gd.n[k] % gd.t[k]) {
+                    delete p;
+                    return sgw_fail(SGW_ERR_UNSUPPORTED, "box %d does not divide extent %d", gd.t[k], gd.n[k]);
+                }
+            }
+            fill_box_geometry(gd, cfg->precision);
+            if (gd.core_total > SGW_BLOCK * SGW_MAXR || stage_lds_bytes(gd, cfg->precision) > lds_cap) {
+                delete p;
+                return sgw_fail(SGW_ERR_UNSUPPORTED, "box too large for one workgroup");
+            }
+        } else {
+            choose_box(gd, cfg->precision, target, lds_cap);
+        }
+        // the kernel keeps SGW_MAXR nodes per thread and sizes LDS from these numbers
+        if (gd.core_total > SGW_BLOCK * SGW_MAXR || stage_lds_bytes(gd, cfg->precision) > lds_cap) {
+            delete p;
+            return sgw_fail(SGW_ERR_UNSUPPORTED, "no stage box fits one workgroup for grid %d", g);
+        }
+    }
+    p->offsets[p->G] = tot;
+    p->total_nodes = tot;
+    p->nitems = 0;
+    p->stage_lds = 0;
+    for (int g = 0; g < p->G; g++) {
+        p->grids[g].first_item = (int32_t)p->nitems;
+        p->nitems += p->grids[g].nbox;
+        const size_t l = stage_lds_bytes(p->grids[g], cfg->precision);
+        p->stage_lds = l > p->stage_lds ? l : p->stage_lds;
+    }
+    for (int k = 0; k < d; k++)
+        if (cfg->fine_tile[k] > 0 && N % cfg->fine_tile[k]) {
+            delete p;
+            return sgw_fail(SGW_ERR_UNSUPPORTED, "fine tile %d does not divide %lld", cfg->fine_tile[k], (long long)N);
+        }
+    choose_fine_tile(*p);
+    {
+        int pts = 1;
+        for (int k = 0; k < d; k++) pts *= p->fine_T[k];
+        const size_t rs = cfg->precision == SGW_FP64 ? 8 : 4;
+        if (pts > SGW_BLOCK * 16 || 2 * rs * p->pro_buf_elems > 64 * 1024) {
+            delete p;
+            return sgw_fail(SGW_ERR_UNSUPPORTED, "prolongation tile too large for one workgroup");
+        }
+    }
+    // byte layout
+    const uint64_t rs = cfg->precision == SGW_FP64 ? 8 : 4;
+    p->copy_bytes = align256((uint64_t)tot * rs);
+    p->state_bytes = 3 * p->copy_bytes;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    p->off_grids = take(sizeof(GridDev) * p->G);
+    p->off_req = take(sizeof(ReqDev));
+    p->off_items = take(sizeof(WorkItem) * p->nitems);
+    p->off_alpha = take(sizeof(unsigned long long) * 4 * p->G);
+    p->coef_off.assign((size_t)p->G * SGW_MAX_DIM, 0);
+    uint64_t coef_elems = 0;
+    if (pb->flux == SGW_FLUX_VLASOV_FIXED_E) {
+        const int m = d / 2;
+        for (int g = 0; g < p->G; g++)
+            for (int k = 0; k < d; k++) {
+                p->coef_off[(size_t)g * SGW_MAX_DIM + k] = (int64_t)coef_elems;
+                const int src = k < m ? m + k : k - m;
+                coef_elems += (uint64_t)p->grids[g].n[src];
+            }
+    }
+    p->off_coef = take(sizeof(double) * (coef_elems ? coef_elems : 1));
+    p->off_coef_off = take(sizeof(int64_t) * p->coef_off.size());
+    p->off_pro = take(sizeof(ProDev) * p->G);
+    p->off_fine = take(sizeof(FineDev));
+    p->off_partials = take(sizeof(double) * 2 * SGW_NPART);
+    p->off_result = take(sizeof(double) * 2);
+    uint64_t foot = 0;
+    if (pb->flux == SGW_FLUX_VLASOV_FIXED_E) foot = sizeof(double) * 2 * (uint64_t)(d / 2) * N * N;
+    p->off_foot = take(foot ? foot : 8);
+    p->scratch_bytes = off;
+    *out = p;
+    return SGW_OK;
+}
+
+extern "C" void sgw_plan_free(sgw_plan_t* p) { delete p; }
+
+extern "C" sgw_status sgw_plan_footprint(const sgw_plan_t* p, uint64_t* state_bytes, uint64_t* scratch_bytes,
+                                         uint64_t* fine_bytes)
+{
+    if (!p) return sgw_fail(SGW_ERR_INVALID_ARG, "null plan");
+    if (state_bytes) *state_bytes = p->state_bytes;
+    if (scratch_bytes) *scratch_bytes = p->scratch_bytes;
+    if (fine_bytes) *fine_bytes = (uint64_t)p->fine_nodes * sizeof(double);
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_plan_info(const sgw_plan_t* p, int32_t* num_grids, int64_t* total_nodes,
+                                    int64_t* fine_nodes)
+{
+    if (!p) return sgw_fail(SGW_ERR_INVALID_ARG, "null plan");
+    if (num_grids) *num_grids = p->G;
+    if (total_nodes) *total_nodes = p->total_nodes;
+    if (fine_nodes) *fine_nodes = p->fine_nodes;
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_plan_grid(const sgw_plan_t* p, int32_t g, int32_t level[SGW_MAX_DIM],
+                                    int32_t shape[SGW_MAX_DIM], int32_t* coef, int64_t* offset)
+{
+    if (!p) return sgw_fail(SGW_ERR_INVALID_ARG, "null plan");
+    if (g < 0 || g >= p->G) return sgw_fail(SGW_ERR_INVALID_ARG, "grid %d outside 0..%d", g, p->G - 1);
+    for (int k = 0; k < SGW_MAX_DIM; k++) {
+        if (level) level[k] = k < p->pb.dim ? p->levels[g][k] : 0;
+        if (shape) shape[k] = p->grids[g].n[k];
+    }
+    if (coef) *coef = p->coefs[g];
+    if (offset) *offset = p->offsets[g];
+    return SGW_OK;
+}
+
+// Box extents chosen for grid g (for tests and the tuner).
+extern "C" sgw_status sgw_plan_grid_box(const sgw_plan_t* p, int32_t g, int32_t box[SGW_MAX_DIM])
+{
+    if (!p || g < 0 || g >= p->G || !box) return sgw_fail(SGW_ERR_INVALID_ARG, "bad grid");
+    for (int k = 0; k < SGW_MAX_DIM; k++) box[k] = p->grids[g].t[k];
+    return SGW_OK;
+}
+
+// ---------------------------------------------------------------- solvers
+
+#define HIPCHK(expr, what)                                 \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return sgw_hip_fail(e_, what); \
+    } while (0)
+
+extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* scratch_dev, void* hip_stream,
+                                        sgw_solver_t** out)
+{
+    if (!p || !state_dev || !scratch_dev || !out) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    if (((uintptr_t)state_dev & 255) || ((uintptr_t)scratch_dev & 255))
+        return sgw_fail(SGW_ERR_INVALID_ARG, "device buffers must be 256-byte aligned");
+    *out = nullptr;
+    sgw_solver* s = new sgw_solver();
+    s->plan = p;
+    s->state = (unsigned char*)state_dev;
+    s->scratch = (unsigned char*)scratch_dev;
+    s->stream = (hipStream_t)hip_stream;
+    const int d = p->pb.dim;
+    const uint64_t rs = p->cfg.precision == SGW_FP64 ? 8 : 4;
+    s->grids_d = (GridDev*)(s->scratch + p->off_grids);
+    s->req_d = (ReqDev*)(s->scratch + p->off_req);
+    s->items_d = (WorkItem*)(s->scratch + p->off_items);
+    s->alpha_d = (unsigned long long*)(s->scratch + p->off_alpha);
+    s->coef_d = (double*)(s->scratch + p->off_coef);
+    s->coef_off_d = (int64_t*)(s->scratch + p->off_coef_off);
+    s->pro_d = (ProDev*)(s->scratch + p->off_pro);
+    s->fine_d = (FineDev*)(s->scratch + p->off_fine);
+    s->partials_d = (double*)(s->scratch + p->off_partials);
+    s->result_d = (double*)(s->scratch + p->off_result);
+    s->foot_d = (double*)(s->scratch + p->off_foot);
+
+    const bool dyn = p->pb.flux == SGW_FLUX_BURGERS;
+    const int N = p->N;
+    // grid descriptors
+    s->grids_h = p->grids;
+    for (int g = 0; g < p->G; g++) {
+        GridDev& gd = s->grids_h[g];
+        const uint64_t eoff = (uint64_t)p->offsets[g] * rs;
+        gd.u = s->state + eoff;
+        gd.a = s->state + p->copy_bytes + eoff;
+        gd.b = s->state + 2 * p->copy_bytes + eoff;
+        gd.alpha = s->alpha_d + 4 * g;
+        gd.req = s->req_d;
+        gd.flux = p->pb.flux;
+        gd.dyn_alpha = dyn ? 1 : 0;
+        gd.linear = p->cfg.linear_weights ? 1 : 0;
+        gd.eps = p->cfg.eps_flux;
+        for (int k = 0; k < SGW_MAX_DIM; k++) {
+            gd.coef[k] = nullptr;
+            gd.coef_src[k] = -1;
+            gd.lin_c[k] = 0.0;
+            gd.alpha_c[k] = 0.0;
+            if (k >= d) continue;
+            gd.lo[k] = p->pb.lo[k];
+            gd.h[k] = (p->pb.hi[k] - p->pb.lo[k]) / gd.n[k];
+            gd.inv_h[k] = 1.0 / gd.h[k];
+            if (p->pb.flux == SGW_FLUX_ADVECTION) {
+                gd.lin_c[k] = p->pb.flux_params[k];
+                gd.alpha_c[k] = std::fabs(p->pb.flux_params[k]);
+            } else if (p->pb.flux == SGW_FLUX_VLASOV_FIXED_E) {
+                const int m = d / 2;
+                gd.coef_src[k] = k < m ? m + k : k - m;
+                gd.coef[k] = s->coef_d + p->coef_off[(size_t)g * SGW_MAX_DIM + k];
+            }
+        }
+    }
+    // time-step record
+    std::memset(&s->req_h, 0, sizeof(ReqDev));
+    s->req_h.cfl = p->cfg.cfl;
+    s->req_h.d = d;
+    s->req_h.dt_mode = p->cfg.dt_mode;
+    s->req_h.grids = s->grids_d;
+    s->req_h.ngrids = p->G;
+    s->req_h.dyn_alpha = dyn ? 1 : 0;
+    s->req_h.active = 1;
+    double hmin = INFINITY;
+    for (int k = 0; k < d; k++) {
+        s->req_h.hfin[k] = (p->pb.hi[k] - p->pb.lo[k]) / N;
+        hmin = s->req_h.hfin[k] < hmin ? s->req_h.hfin[k] : hmin;
+    }
+    s->req_h.dt_pow53 = std::pow(hmin, 5.0 / 3.0);
+    // work list: boxes of every grid, grid by grid
+    s->items_h.resize(p->nitems);
+    for (int g = 0; g < p->G; g++)
+        for (int b = 0; b < p->grids[g].nbox; b++) {
+            WorkItem& it = s->items_h[p->grids[g].first_item + b];
+            it.g = s->grids_d + g;
+            it.box = b;
+            it.pad = 0;
+        }
+    // prolongation descriptors
+    s->pro_h.resize(p->G);
+    for (int g = 0; g < p->G; g++) {
+        ProDev& pd = s->pro_h[g];
+        std::memset(&pd, 0, sizeof(pd));
+        pd.u = s->grids_h[g].u;
+        pd.coef = p->coefs[g];
+        int load = 1;
+        for (int k = 0; k < SGW_MAX_DIM; k++) {
+            pd.n[k] = s->grids_h[g].n[k];
+            pd.stride[k] = s->grids_h[g].stride[k];
+            if (k < d) {
+                pd.m[k] = p->cfg.finest_level - p->levels[g][k];
+                pd.c[k] = pd.m[k] == 0 ? p->fine_T[k] : (p->fine_T[k] - 1) / (1 << pd.m[k]) + 6;
+            } else {
+                pd.m[k] = 0;
+                pd.c[k] = 1;
+            }
+            load *= pd.c[k];
+            pd.fd_c[k] = make_fastdiv((uint32_t)pd.c[k]);
+        }
+        pd.load_total = load;
+        for (int k = 0; k < SGW_MAX_DIM; k++) {
+            int o = 1;
+            for (int j = k + 1; j < SGW_MAX_DIM; j++) o *= pd.c[j];
+            pd.outer[k] = o;
+        }
+    }
+    std::memset(&s->fine_h, 0, sizeof(FineDev));
+    s->fine_h.d = d;
+    s->fine_h.N = N;
+    s->fine_h.G = p->G;
+    s->fine_h.lagrange = p->cfg.prolong == SGW_PROLONG_LAGRANGE5;
+    s->fine_h.eps = p->cfg.eps_interp;
+    s->fine_h.pad0 = (int32_t)p->pro_buf_elems;
+    int pts = 1;
+    for (int k = 0; k < SGW_MAX_DIM; k++) {
+        s->fine_h.T[k] = p->fine_T[k];
+        s->fine_h.ntile[k] = k < d ? N / p->fine_T[k] : 1;
+        s->fine_h.inner[k] = pts;
+        s->fine_h.fd_T[k] = make_fastdiv((uint32_t)p->fine_T[k]);
+        s->fine_h.fd_inner[k] = make_fastdiv((uint32_t)pts);
+        pts *= p->fine_T[k];
+    }
+    s->fine_h.tile_points = pts;
+
+    hipStream_t st = s->stream;
+    sgw_status rc = SGW_OK;
+    auto cp = [&](void* dst, const void* src, size_t n) {
+        if (rc != SGW_OK || n == 0) return;
+        hipError_t e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) rc = sgw_hip_fail(e, "upload descriptors");
+    };
+    cp(s->grids_d, s->grids_h.data(), sizeof(GridDev) * p->G);
+    cp(s->req_d, &s->req_h, sizeof(ReqDev));
+    cp(s->items_d, s->items_h.data(), sizeof(WorkItem) * p->nitems);
+    cp(s->coef_off_d, p->coef_off.data(), sizeof(int64_t) * p->coef_off.size());
+    cp(s->pro_d, s->pro_h.data(), sizeof(ProDev) * p->G);
+    cp(s->fine_d, &s->fine_h, sizeof(FineDev));
+    if (rc == SGW_OK && p->pb.flux == SGW_FLUX_VLASOV_FIXED_E) {
+        hipError_t e = launch_coef_init(s->grids_d, s->grids_h.data(), p->G, s->coef_d, s->coef_off_d, &p->pb, st);
+        if (e != hipSuccess) rc = sgw_hip_fail(e, "coefficient tables");
+        // the host mirrors the constant wave speeds to plan the number of steps
+        std::vector<GridDev> back(p->G);
+        if (rc == SGW_OK) {
+            e = hipMemcpyAsync(back.data(), s->grids_d, sizeof(GridDev) * p->G, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) rc = sgw_hip_fail(e, "read back wave speeds");
+        }
+        if (rc == SGW_OK)
+            for (int g = 0; g < p->G; g++)
+                for (int k = 0; k < SGW_MAX_DIM; k++) s->grids_h[g].alpha_c[k] = back[g].alpha_c[k];
+    }
+    if (rc == SGW_OK) {
+        hipError_t e = hipHostMalloc((void**)&s->req_pinned, sizeof(ReqDev), hipHostMallocDefault);
+        if (e != hipSuccess) rc = sgw_hip_fail(e, "pinned host record");
+    }
+    if (rc == SGW_OK) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = sgw_hip_fail(e, "solver set-up");
+    }
+    if (rc != SGW_OK) {
+        sgw_solver_free(s);
+        return rc;
+    }
+    s->occupancy = stage_occupancy(p->cfg.precision, p->stage_lds);
+    *out = s;
+    return SGW_OK;
+}
+
+static void destroy_graph(sgw_solver* s)
+{
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    s->graph_exec = nullptr;
+    s->graph = nullptr;
+    s->cap_stream = nullptr;
+}
+
+extern "C" void sgw_solver_free(sgw_solver_t* s)
+{
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    destroy_graph(s);
+    if (s->req_pinned) (void)hipHostFree(s->req_pinned);
+    delete s;
+}
+
+extern "C" sgw_status sgw_restrict_initial(sgw_solver_t* s)
+{
+    if (!s) return sgw_fail(SGW_ERR_INVALID_ARG, "null solver");
+    const sgw_plan* p = s->plan;
+    HIPCHK(launch_fill_u64(s->alpha_d, 4 * (int64_t)p->G, 0ull, s->stream), "clear wave speeds");
+    HIPCHK(launch_restrict(s->grids_d, s->grids_h.data(), p->G, p->cfg.precision, &p->pb, s->stream), "restrict");
+    HIPCHK(launch_req_reset(s->req_d, s->stream), "reset time");
+    s->restricted = true;
+    s->t_host = 0.0;
+    return SGW_OK;
+}
+
+static sgw_status read_req(sgw_solver* s)
+{
+    HIPCHK(hipMemcpyAsync(s->req_pinned, s->req_d, sizeof(ReqDev), hipMemcpyDeviceToHost, s->stream), "read time");
+    HIPCHK(hipStreamSynchronize(s->stream), "synchronise");
+    s->t_host = s->req_pinned->t;
+    return SGW_OK;
+}
+
+// Launch the work of one time step (dt + three stages) on stream st.
+static hipError_t enqueue_step(sgw_solver* s, int mode, hipStream_t st)
+{
+    const sgw_plan* p = s->plan;
+    hipError_t e = launch_dt_one(s->req_d, st);
+    if (e != hipSuccess) return e;
+    const int cap = s->occupancy * 256;
+    for (int stage = 0; stage < 3; stage++) {
+        if (mode == SGW_RUN_PLAIN) {
+            for (int g = 0; g < p->G; g++) {
+                e = launch_stage(s->items_d + p->grids[g].first_item, p->grids[g].nbox, stage, p->cfg.precision,
+                                 p->pb.dim, stage_lds_bytes(p->grids[g], p->cfg.precision), 0, st);
+                if (e != hipSuccess) return e;
+            }
+        } else {
+            e = launch_stage(s->items_d, (int)p->nitems, stage, p->cfg.precision, p->pb.dim, p->stage_lds, cap, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+static sgw_status build_graph(sgw_solver* s, int steps_per_graph)
+{
+    destroy_graph(s);
+    HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking), "capture stream");
+    HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < steps_per_graph && e == hipSuccess; i++) e = enqueue_step(s, SGW_RUN_FUSED, s->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
+    if (e != hipSuccess) return sgw_hip_fail(e, "capture step");
+    if (e2 != hipSuccess) return sgw_hip_fail(e2, "end capture");
+    s->graph = g;
+    HIPCHK(hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0), "instantiate graph");
+    s->graph_steps = steps_per_graph;
+    return SGW_OK;
+}
+
+// Number of steps the shared-dt loop takes from t to T when every wave speed is
+// constant (the same arithmetic the device performs).
+static int64_t planned_steps(const sgw_solver* s, double t, double T)
+{
+    const sgw_plan* p = s->plan;
+    const ReqDev& r = s->req_h;
+    double dt;
+    if (r.dt_mode == SGW_DT_POW53) {
+        dt = r.dt_pow53;
+    } else {
+        double denom = 0.0;
+        for (int k = 0; k < r.d; k++) {
+            double A = 0.0;
+            for (int g = 0; g < p->G; g++) {
+                double a;
+                if (r.dyn_alpha) {
+                    // bound of max|u0| for a sine initial condition; only an estimate
+                    a = std::fabs(p->pb.ic_params[0]) + std::fabs(p->pb.ic_params[1]);
+                } else {
+                    a = s->grids_h[g].alpha_c[k];
+                }
+                A = a > A ? a : A;
+            }
+            denom += A / r.hfin[k];
+        }
+        dt = denom > 0.0 ? r.cfl / denom : T - t;
+    }
+    int64_t n = 0;
+    const double tol = 1e-12 * (T > 1.0 ? T : 1.0);
+    while (T - t > tol && n < 10000000) {
+        double d = dt > T - t ? T - t : dt;
+        t += d;
+        n++;
+    }
+    return n;
+}
+
+extern "C" sgw_status sgw_advance(sgw_solver_t* s, double t_final, int32_t mode)
+{
+    if (!s) return sgw_fail(SGW_ERR_INVALID_ARG, "null solver");
+    if (!s->restricted) return sgw_fail(SGW_ERR_STATE, "advance before restrict");
+    if (mode < SGW_RUN_PLAIN || mode > SGW_RUN_GRAPH) return sgw_fail(SGW_ERR_INVALID_ARG, "unknown mode %d", mode);
+    if (!(t_final >= 0.0) || !std::isfinite(t_final)) return sgw_fail(SGW_ERR_INVALID_ARG, "bad final time");
+    HIPCHK(launch_req_set_final(s->req_d, t_final, s->stream), "set final time");
+    sgw_status rc = read_req(s);
+    if (rc != SGW_OK) return rc;
+    if (s->req_pinned->nonfinite) return sgw_fail(SGW_ERR_NONFINITE, "non-finite wave speed");
+    int64_t todo = planned_steps(s, s->t_host, t_final);
+    if (mode == SGW_RUN_GRAPH && !s->graph_exec) {
+        rc = build_graph(s, 4);
+        if (rc != SGW_OK) return rc;
+    }
+    int64_t launched = 0;
+    for (;;) {
+        if (launched > 10000000) return sgw_fail(SGW_ERR_STATE, "more than 1e7 steps without reaching t_final");
+        launched += todo;
+        if (mode == SGW_RUN_GRAPH) {
+            for (int64_t i = 0; i < todo; i += s->graph_steps)
+                HIPCHK(hipGraphLaunch(s->graph_exec, s->stream), "graph launch");
+        } else {
+            for (int64_t i = 0; i < todo; i++) HIPCHK(enqueue_step(s, mode, s->stream), "step");
+        }
+        rc = read_req(s);
+        if (rc != SGW_OK) return rc;
+        if (s->req_pinned->nonfinite) return sgw_fail(SGW_ERR_NONFINITE, "non-finite wave speed or time step");
+        if (s->req_pinned->done) break;
+        todo = 4; // state-dependent speed: a few more steps, then look again
+    }
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_prolongate_combine(sgw_solver_t* s, double* out_dev)
+{
+    if (!s || !out_dev) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    if (!s->restricted) return sgw_fail(SGW_ERR_STATE, "prolongate before restrict");
+    const sgw_plan* p = s->plan;
+    const size_t lds = 2 * (p->cfg.precision == SGW_FP64 ? 8 : 4) * p->pro_buf_elems;
+    HIPCHK(launch_prolong(s->pro_d, s->fine_d, s->fine_h, p->cfg.precision, lds, out_dev, s->stream), "prolongate");
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_exact(sgw_solver_t* s, double t, double* out_dev)
+{
+    if (!s || !out_dev) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    const sgw_plan* p = s->plan;
+    if (p->pb.flux == SGW_FLUX_BURGERS && p->pb.ic != SGW_IC_SINE)
+        return sgw_fail(SGW_ERR_UNSUPPORTED, "Burgers exact solution needs a sine initial condition");
+    if (p->pb.flux == SGW_FLUX_VLASOV_FIXED_E && p->pb.ic != SGW_IC_MAXWELL_COS)
+        return sgw_fail(SGW_ERR_UNSUPPORTED, "Vlasov exact solution needs the Maxwellian initial condition");
+    ExactDev e;
+    std::memset(&e, 0, sizeof(e));
+    e.d = p->pb.dim;
+    e.flux = p->pb.flux;
+    e.ic = p->pb.ic;
+    e.N = p->N;
+    for (int k = 0; k < SGW_MAX_DIM; k++) {
+        e.lo[k] = p->pb.lo[k];
+        e.h[k] = k < e.d ? (p->pb.hi[k] - p->pb.lo[k]) / p->N : 0.0;
+        e.fp[k] = p->pb.flux_params[k];
+    }
+    for (int i = 0; i < 8; i++) e.ip[i] = p->pb.ic_params[i];
+    e.t = t;
+    HIPCHK(launch_exact(e, out_dev, s->foot_d, s->stream), "exact solution");
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_norms(sgw_solver_t* s, const double* a, const double* b, double* result_host)
+{
+    if (!s || !a || !b || !result_host) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    HIPCHK(launch_norms(a, b, s->plan->fine_nodes, s->partials_d, s->result_d, s->stream), "norms");
+    HIPCHK(hipMemcpyAsync(result_host, s->result_d, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream),
+           "read norms");
+    HIPCHK(hipStreamSynchronize(s->stream), "synchronise");
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_query(sgw_solver_t* s, double* t, int64_t* steps)
+{
+    if (!s) return sgw_fail(SGW_ERR_INVALID_ARG, "null solver");
+    sgw_status rc = read_req(s);
+    if (rc != SGW_OK) return rc;
+    if (t) *t = s->req_pinned->t;
+    if (steps) *steps = s->req_pinned->steps;
+    if (s->req_pinned->nonfinite) return sgw_fail(SGW_ERR_NONFINITE, "non-finite wave speed or time step");
+    return SGW_OK;
+}

@@ -1,0 +1,252 @@
+// Batched runtime of libsgweno: many solves (any dimension, level and final
+// time, one precision) advance together.  Each time step is one captured HIP
+// graph: the time-step kernel for every slot, then the three TVD-RK3 stages,
+// each a single persistent launch over the boxes of every admitted solve.  The
+// box list and its length live in device memory, so admitting or releasing a
+// solve is a stream-ordered copy and the graph stays valid.
+#include <cstring>
+#include <vector>
+
+#include "sgw_api_internal.h"
+
+struct sgw_batch {
+    int max_solvers = 0;
+    int precision = 0;
+    uint64_t budget = 0, used = 0;
+    hipStream_t stream = nullptr;
+    unsigned char* scratch = nullptr;
+    uint64_t scratch_bytes = 0;
+    int64_t max_items = 0;
+    ReqDev** reqs_d = nullptr;      // [max_solvers], null for a free slot
+    WorkItem* items_d = nullptr;    // [max_items]
+    int* nitems_d = nullptr;
+    int* flags_d = nullptr;         // [max_solvers]
+    int* flags_pinned = nullptr;
+    std::vector<sgw_solver*> slots;
+    std::vector<uint64_t> slot_bytes;
+    std::vector<ReqDev*> reqs_h;
+    std::vector<WorkItem> items_h;
+    int nitems_h = 0;
+    bool dirty = true;
+    size_t lds = 0;                 // LDS of the captured stage launches
+    int blocks = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static uint64_t a256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
+
+extern "C" uint64_t sgw_batch_scratch_bytes(int32_t max_solvers, int64_t max_items)
+{
+    if (max_solvers < 1 || max_items < 1) return 0;
+    return a256(sizeof(ReqDev*) * (uint64_t)max_solvers) + a256(sizeof(WorkItem) * (uint64_t)max_items) + 256 +
+           a256(sizeof(int) * (uint64_t)max_solvers);
+}
+
+extern "C" sgw_status sgw_batch_create(int32_t max_solvers, int32_t precision, uint64_t hbm_budget, void* hip_stream,
+                                       void* scratch_dev, uint64_t scratch_bytes, sgw_batch_t** out)
+{
+    if (!out || !scratch_dev) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (max_solvers < 1 || max_solvers > 65536) return sgw_fail(SGW_ERR_INVALID_ARG, "max_solvers %d", max_solvers);
+    if (precision != SGW_FP64 && precision != SGW_FP32_SWEEP)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "unknown precision %d", precision);
+    if ((uintptr_t)scratch_dev & 255) return sgw_fail(SGW_ERR_INVALID_ARG, "scratch must be 256-byte aligned");
+    const uint64_t fixed = sgw_batch_scratch_bytes(max_solvers, 1) - a256(sizeof(WorkItem));
+    if (scratch_bytes < fixed + a256(sizeof(WorkItem))) return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "batch scratch too small");
+    sgw_batch* b = new sgw_batch();
+    b->max_solvers = max_solvers;
+    b->precision = precision;
+    b->budget = hbm_budget;
+    b->stream = (hipStream_t)hip_stream;
+    b->scratch = (unsigned char*)scratch_dev;
+    b->scratch_bytes = scratch_bytes;
+    b->max_items = (int64_t)((scratch_bytes - fixed) / sizeof(WorkItem));
+    if (b->max_items > (1ll << 30)) b->max_items = 1ll << 30;
+    uint64_t off = 0;
+    b->reqs_d = (ReqDev**)(b->scratch + off);
+    off += a256(sizeof(ReqDev*) * (uint64_t)max_solvers);
+    b->nitems_d = (int*)(b->scratch + off);
+    off += 256;
+    b->flags_d = (int*)(b->scratch + off);
+    off += a256(sizeof(int) * (uint64_t)max_solvers);
+    b->items_d = (WorkItem*)(b->scratch + off);
+    b->slots.assign(max_solvers, nullptr);
+    b->slot_bytes.assign(max_solvers, 0);
+    b->reqs_h.assign(max_solvers, nullptr);
+    hipError_t e = hipHostMalloc((void**)&b->flags_pinned, sizeof(int) * max_solvers, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete b;
+        return sgw_hip_fail(e, "pinned flags");
+    }
+    *out = b;
+    return SGW_OK;
+}
+
+static void batch_drop_graph(sgw_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->cap = nullptr;
+}
+
+extern "C" void sgw_batch_free(sgw_batch_t* b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    for (auto* s : b->slots)
+        if (s) s->batch_slot = -1;
+    if (b->flags_pinned) (void)hipHostFree(b->flags_pinned);
+    delete b;
+}
+
+static uint64_t solver_bytes(const sgw_solver* s)
+{
+    return s->plan->state_bytes + s->plan->scratch_bytes + (uint64_t)s->plan->fine_nodes * sizeof(double);
+}
+
+// Re-upload the box list and the slot table; recapture the step graph only when
+// an admitted grid needs more LDS than the captured launches provide.
+static sgw_status batch_sync(sgw_batch* b)
+{
+    if (!b->dirty) return SGW_OK;
+    b->items_h.clear();
+    size_t lds = 0;
+    for (int i = 0; i < b->max_solvers; i++) {
+        sgw_solver* s = b->slots[i];
+        if (!s) continue;
+        b->items_h.insert(b->items_h.end(), s->items_h.begin(), s->items_h.end());
+        lds = s->plan->stage_lds > lds ? s->plan->stage_lds : lds;
+    }
+    if ((int64_t)b->items_h.size() > b->max_items) return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "batch box list full");
+    b->nitems_h = (int)b->items_h.size();
+    hipError_t e = hipSuccess;
+    if (b->nitems_h)
+        e = hipMemcpyAsync(b->items_d, b->items_h.data(), sizeof(WorkItem) * b->items_h.size(), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->nitems_d, &b->nitems_h, sizeof(int), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->reqs_d, b->reqs_h.data(), sizeof(ReqDev*) * b->max_solvers, hipMemcpyHostToDevice,
+                           b->stream);
+    // the host vectors are read by the copies: wait before they can change
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return sgw_hip_fail(e, "upload batch lists");
+    if (!b->exec || lds > b->lds) {
+        batch_drop_graph(b);
+        b->lds = lds;
+        b->blocks = stage_occupancy(b->precision, lds) * 256;
+        e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+        if (e != hipSuccess) return sgw_hip_fail(e, "capture stream");
+        e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return sgw_hip_fail(e, "begin capture");
+        hipError_t el = launch_dt(b->reqs_d, b->max_solvers, b->cap);
+        for (int st = 0; st < 3 && el == hipSuccess; st++)
+            el = launch_stage_dev_count(b->items_d, b->nitems_d, b->blocks, st, b->precision, b->lds, b->cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->cap, &g);
+        if (el != hipSuccess) return sgw_hip_fail(el, "capture batch step");
+        if (e != hipSuccess) return sgw_hip_fail(e, "end capture");
+        b->graph = g;
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) return sgw_hip_fail(e, "instantiate batch graph");
+    }
+    b->dirty = false;
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_batch_admit(sgw_batch_t* b, sgw_solver_t* s, double t_final, int32_t* slot)
+{
+    if (!b || !s || !slot) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    if (!s->restricted) return sgw_fail(SGW_ERR_STATE, "admit before restrict");
+    if (s->batch_slot >= 0) return sgw_fail(SGW_ERR_STATE, "solver already in a batch");
+    if (s->plan->cfg.precision != b->precision) return sgw_fail(SGW_ERR_INVALID_ARG, "precision differs from batch");
+    if (!(t_final >= 0.0)) return sgw_fail(SGW_ERR_INVALID_ARG, "bad final time");
+    const uint64_t need = solver_bytes(s);
+    if (b->used + need > b->budget)
+        return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "footprint %llu exceeds remaining budget %llu",
+                        (unsigned long long)need, (unsigned long long)(b->budget - b->used));
+    int free_slot = -1;
+    for (int i = 0; i < b->max_solvers; i++)
+        if (!b->slots[i]) {
+            free_slot = i;
+            break;
+        }
+    if (free_slot < 0) return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "no free slot");
+    int64_t items = 0;
+    for (auto* o : b->slots)
+        if (o) items += (int64_t)o->items_h.size();
+    if (items + (int64_t)s->items_h.size() > b->max_items) return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "box list full");
+    // the solve's own work (restriction) is ordered before the batch's
+    if (s->stream != b->stream) {
+        hipError_t e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return sgw_hip_fail(e, "synchronise solver stream");
+    }
+    hipError_t e = launch_req_set_final(s->req_d, t_final, b->stream);
+    if (e != hipSuccess) return sgw_hip_fail(e, "set final time");
+    b->slots[free_slot] = s;
+    b->slot_bytes[free_slot] = need;
+    b->reqs_h[free_slot] = s->req_d;
+    b->used += need;
+    s->batch_slot = free_slot;
+    b->dirty = true;
+    *slot = free_slot;
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_batch_step(sgw_batch_t* b, int32_t nsteps)
+{
+    if (!b) return sgw_fail(SGW_ERR_INVALID_ARG, "null batch");
+    if (nsteps < 0) return sgw_fail(SGW_ERR_INVALID_ARG, "negative step count");
+    sgw_status rc = batch_sync(b);
+    if (rc != SGW_OK) return rc;
+    if (!b->nitems_h) return SGW_OK;
+    for (int i = 0; i < nsteps; i++) {
+        hipError_t e = hipGraphLaunch(b->exec, b->stream);
+        if (e != hipSuccess) return sgw_hip_fail(e, "batch graph launch");
+    }
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_batch_poll(sgw_batch_t* b, int32_t* done_slots, int32_t* n_done)
+{
+    if (!b || !done_slots || !n_done) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    sgw_status rc = batch_sync(b);
+    if (rc != SGW_OK) return rc;
+    hipError_t e = launch_gather_done(b->reqs_d, b->max_solvers, b->flags_d, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->flags_pinned, b->flags_d, sizeof(int) * b->max_solvers, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return sgw_hip_fail(e, "poll batch");
+    int n = 0;
+    bool bad = false;
+    for (int i = 0; i < b->max_solvers; i++) {
+        if (!b->slots[i]) continue;
+        if (b->flags_pinned[i] & 1) done_slots[n++] = i;
+        bad |= (b->flags_pinned[i] & 2) != 0;
+    }
+    *n_done = n;
+    if (bad) return sgw_fail(SGW_ERR_NONFINITE, "a solve in the batch hit a non-finite wave speed");
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_batch_release(sgw_batch_t* b, int32_t slot)
+{
+    if (!b) return sgw_fail(SGW_ERR_INVALID_ARG, "null batch");
+    if (slot < 0 || slot >= b->max_solvers || !b->slots[slot]) return sgw_fail(SGW_ERR_INVALID_ARG, "bad slot %d", slot);
+    // the slot's solve may still be referenced by queued graph launches
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return sgw_hip_fail(e, "synchronise batch");
+    b->slots[slot]->batch_slot = -1;
+    b->used -= b->slot_bytes[slot];
+    b->slots[slot] = nullptr;
+    b->slot_bytes[slot] = 0;
+    b->reqs_h[slot] = nullptr;
+    b->dirty = true;
+    return SGW_OK;
+}

@@ -1,0 +1,360 @@
+// Prolongation + combination, exact solutions and error norms of libsgweno.
+//
+// Prolongation (Sec. 2.2.1): along each direction k with m = N_L - l_k > 0 the
+// coarse line is refined by R = 2^m.  Fine node J falls in the half-open
+// interval [x_{i-1/2}, x_{i+1/2}) of coarse node i = floor(J/R + 1/2) at offset
+// s = J/R - i in [-1/2, 1/2); its value is the WENO5 interpolation of eqs.
+// (lwlag), (eqnlnwe), (si), (nlweno) from u_{i-2..i+2}: the three quadratic
+// interpolants P_r on the substencils, the positive linear weights C_r(s), the
+// smoothness indicators beta_r, nonlinear weights C_r/(eps+beta_r)^2
+// normalised.  Directions are refined in increasing order.  The combination
+// (eq. genformusgc) adds c_g P U_g in FP64, grids in plan order.
+//
+// Layout: one workgroup owns a tile of the finest grid.  For each component
+// grid it stages the coarse block the tile depends on in LDS, refines it
+// direction by direction between two LDS buffers, and adds the result to FP64
+// accumulators in registers; the tile is written once at the end.
+#include "sgw_internal.h"
+
+#define SGW_MAXRP 16 // finest-grid points per thread: tile <= SGW_BLOCK * SGW_MAXRP
+
+namespace {
+
+__device__ __forceinline__ float rdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double rdiv(double a, double b) { return a / b; }
+
+// P_r written about x_i: P_r(s) = c + s g_r + s^2 k_r with g_r, k_r the first and
+// second differences of substencil r; the integral of eq. (si) then equals
+// g_r^2 + (13/3) k_r^2, the Jiang-Shu quadratic forms of eq. (2.7.2).
+template <typename Real>
+__device__ __forceinline__ Real interp5(Real a, Real b, Real c, Real d, Real e, Real s, Real eps, int lagrange)
+{
+    const Real g0 = Real(0.5) * (a - Real(4) * b + Real(3) * c), k0 = Real(0.5) * (a - Real(2) * b + c);
+    const Real g1 = Real(0.5) * (d - b), k1 = Real(0.5) * (b - Real(2) * c + d);
+    const Real g2 = Real(0.5) * (Real(-3) * c + Real(4) * d - e), k2 = Real(0.5) * (c - Real(2) * d + e);
+    const Real P0 = c + s * (g0 + s * k0);
+    const Real P1 = c + s * (g1 + s * k1);
+    const Real P2 = c + s * (g2 + s * k2);
+    const Real C0 = (s - Real(1)) * (s - Real(2)) * Real(1.0 / 12.0);
+    const Real C1 = (Real(4) - s * s) * Real(1.0 / 6.0);
+    const Real C2 = (s + Real(1)) * (s + Real(2)) * Real(1.0 / 12.0);
+    if (lagrange) return C0 * P0 + C1 * P1 + C2 * P2;
+    Real e0 = eps + (g0 * g0 + Real(13.0 / 3.0) * k0 * k0);
+    Real e1 = eps + (g1 * g1 + Real(13.0 / 3.0) * k1 * k1);
+    Real e2 = eps + (g2 * g2 + Real(13.0 / 3.0) * k2 * k2);
+    e0 *= e0;
+    e1 *= e1;
+    e2 *= e2;
+    const Real w0 = C0 * (e1 * e2), w1 = C1 * (e0 * e2), w2 = C2 * (e0 * e1);
+    return rdiv(w0 * P0 + w1 * P1 + w2 * P2, w0 + w1 + w2);
+}
+
+template <typename Real, int D>
+__global__ void __launch_bounds__(SGW_BLOCK) prolong_kernel(const ProDev* __restrict__ pro,
+                                                            const FineDev* __restrict__ fdv, double* __restrict__ out)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x;
+    const FineDev& F = *fdv;
+    int J0[D];
+    {
+        int r = blockIdx.x;
+        for (int k = 0; k < D; k++) {
+            const int q = r / F.ntile[k];
+            J0[k] = (r - q * F.ntile[k]) * F.T[k];
+            r = q;
+        }
+    }
+    const int tile_points = F.tile_points;
+    const Real eps = (Real)F.eps;
+    const int lagrange = F.lagrange;
+    double acc[SGW_MAXRP];
+#pragma unroll
+    for (int r = 0; r < SGW_MAXRP; r++) acc[r] = 0.0;
+    Real* bufA = (Real*)smem;
+    Real* bufB = bufA + F.pad0; // pad0 holds the per-buffer element count (even)
+
+    for (int gidx = 0; gidx < F.G; gidx++) {
+        const ProDev& p = pro[gidx];
+        const Real* __restrict__ u = (const Real*)p.u;
+        int cl[D];
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            const int m = p.m[k];
+            cl[k] = (m == 0) ? J0[k] : (((2 * J0[k] + (1 << m)) >> (m + 1)) - 2);
+        }
+        // ---- coarse block this tile depends on (periodic wrap)
+        for (int e = tid; e < p.load_total; e += SGW_BLOCK) {
+            uint32_t r = (uint32_t)e;
+            int gi = 0;
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+                const uint32_t q = fdiv(r, p.fd_c[k]);
+                const int c = (int)(r - q * (uint32_t)p.c[k]);
+                r = q;
+                int x = cl[k] + c + 2 * p.n[k]; // >= 0
+                x = x % p.n[k];
+                gi += x * p.stride[k];
+            }
+            bufA[e] = u[gi];
+        }
+        __syncthreads();
+        Real* src = bufA;
+        Real* dst = bufB;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            const int m = p.m[k];
+            if (m == 0) continue;
+            const int Tk = F.T[k];
+            const int ck = p.c[k];
+            const int inner = F.inner[k];
+            const int total = inner * Tk * p.outer[k];
+            const int R = 1 << m;
+            const Real invR = Real(1) / Real(R);
+            for (int o = tid; o < total; o += SGW_BLOCK) {
+                const uint32_t r1 = fdiv((uint32_t)o, F.fd_inner[k]);
+                const int a = o - (int)r1 * inner;
+                const uint32_t bq = fdiv(r1, F.fd_T[k]);
+                const int jl = (int)r1 - (int)bq * Tk;
+                const int J = J0[k] + jl;
+                const int i = (2 * J + R) >> (m + 1);
+                const Real s = (Real)(J - i * R) * invR;
+                const int li = i - cl[k];
+                const int base = a + inner * ((li - 2) + ck * (int)bq);
+                dst[o] = interp5<Real>(src[base], src[base + inner], src[base + 2 * inner], src[base + 3 * inner],
+                                       src[base + 4 * inner], s, eps, lagrange);
+            }
+            __syncthreads();
+            Real* t = src;
+            src = dst;
+            dst = t;
+        }
+        const double cg = (double)p.coef;
+#pragma unroll
+        for (int r = 0; r < SGW_MAXRP; r++) {
+            const int e = tid + r * SGW_BLOCK;
+            if (e < tile_points) acc[r] += cg * (double)src[e];
+        }
+        __syncthreads();
+    }
+    // ---- write the tile
+#pragma unroll
+    for (int r = 0; r < SGW_MAXRP; r++) {
+        const int e = tid + r * SGW_BLOCK;
+        if (e < tile_points) {
+            uint32_t rr = (uint32_t)e;
+            int64_t gi = 0, st = 1;
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+                const uint32_t q = fdiv(rr, F.fd_T[k]);
+                const int c = (int)(rr - q * (uint32_t)F.T[k]);
+                rr = q;
+                gi += (int64_t)(J0[k] + c) * st;
+                st *= F.N;
+            }
+            out[gi] = acc[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- exact solutions
+
+__device__ double u0_sine(const ExactDev& e, const double* x)
+{
+    double s = 0.0;
+    for (int k = 0; k < e.d; k++) s += x[k];
+    return e.ip[0] + e.ip[1] * sin(e.ip[2] * s + e.ip[3]);
+}
+
+__device__ double f0_maxwell(const ExactDev& e, const double* x)
+{
+    const int m = e.d / 2;
+    double v2 = 0.0, pert = 1.0, norm = 1.0;
+    for (int k = 0; k < m; k++) {
+        v2 += x[m + k] * x[m + k];
+        pert *= cos(e.ip[1] * x[k] + e.ip[2 + k]);
+        norm *= 2.0 * M_PI;
+    }
+    return exp(-0.5 * v2) / sqrt(norm) * (1.0 + e.ip[0] * pert);
+}
+
+// Vlasov characteristics x' = v, v' = amp sin(kE x), integrated back from t to 0
+// with classical RK4 for every (x node, v node) pair of each x direction.
+__global__ void vlasov_foot_kernel(ExactDev e, double* foot)
+{
+    const int N = e.N;
+    const int m = e.d / 2;
+    const int64_t total = (int64_t)m * N * N;
+    const double amp = e.fp[0], kE = e.fp[1];
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int jx = (int)(idx % N);
+        const int jv = (int)((idx / N) % N);
+        const int k = (int)(idx / ((int64_t)N * N));
+        double X = e.lo[k] + jx * e.h[k];
+        double V = e.lo[m + k] + jv * e.h[m + k];
+        const int nsteps = (int)ceil(e.t / 1e-3);
+        if (nsteps >= 1) {
+            const double h = -e.t / nsteps;
+            for (int s = 0; s < nsteps; s++) {
+                const double k1x = V, k1v = amp * sin(kE * X);
+                const double k2x = V + 0.5 * h * k1v, k2v = amp * sin(kE * (X + 0.5 * h * k1x));
+                const double k3x = V + 0.5 * h * k2v, k3v = amp * sin(kE * (X + 0.5 * h * k2x));
+                const double k4x = V + h * k3v, k4v = amp * sin(kE * (X + h * k3x));
+                X += h / 6.0 * (k1x + 2.0 * k2x + 2.0 * k3x + k4x);
+                V += h / 6.0 * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
+            }
+        }
+        foot[2 * idx] = X;
+        foot[2 * idx + 1] = V;
+    }
+}
+
+__global__ void exact_kernel(ExactDev e, double* out)
+{
+    const int N = e.N;
+    int64_t total = 1;
+    for (int k = 0; k < e.d; k++) total *= N;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int j[SGW_MAX_DIM] = {0, 0, 0, 0};
+        double x[SGW_MAX_DIM] = {0.0, 0.0, 0.0, 0.0};
+        int64_t r = idx;
+        for (int k = 0; k < e.d; k++) {
+            j[k] = (int)(r % N);
+            r /= N;
+            x[k] = e.lo[k] + j[k] * e.h[k];
+        }
+        double v;
+        if (e.flux == SGW_FLUX_ADVECTION) {
+            for (int k = 0; k < e.d; k++) x[k] -= e.fp[k] * e.t;
+            v = (e.ic == SGW_IC_SINE) ? u0_sine(e, x) : f0_maxwell(e, x);
+        } else if (e.flux == SGW_FLUX_BURGERS) {
+            // u = w(xi), xi = sum x_k, w = g(xi - d w t): Newton's method from w = g(xi)
+            double xi = 0.0;
+            for (int k = 0; k < e.d; k++) xi += x[k];
+            const double c0 = e.ip[0], A = e.ip[1], kap = e.ip[2], ph = e.ip[3], dd = e.d;
+            double w = c0 + A * sin(kap * xi + ph);
+            for (int it = 0; it < 100; it++) {
+                const double arg = kap * (xi - dd * w * e.t) + ph;
+                const double Fv = w - c0 - A * sin(arg);
+                const double dF = 1.0 + A * cos(arg) * kap * dd * e.t;
+                const double dw = Fv / dF;
+                w -= dw;
+                if (fabs(dw) < 1e-16 * (1.0 + fabs(w))) break;
+            }
+            v = w;
+        } else {
+            const int m = e.d / 2;
+            double y[SGW_MAX_DIM] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = 0; k < m; k++) {
+                const int64_t p = ((int64_t)k * N + j[m + k]) * N + j[k];
+                y[k] = e.foot[2 * p];
+                y[m + k] = e.foot[2 * p + 1];
+            }
+            v = f0_maxwell(e, y);
+        }
+        out[idx] = v;
+    }
+}
+
+// ---------------------------------------------------------------- norms (fixed order)
+
+__global__ void norms_partial_kernel(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                                     double* partials)
+{
+    __shared__ double ss[SGW_BLOCK], sm[SGW_BLOCK];
+    double s = 0.0, mx = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)SGW_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * SGW_BLOCK) {
+        const double d = fabs(a[i] - b[i]);
+        s += d;
+        mx = (d > mx || d != d) ? d : mx;
+    }
+    ss[threadIdx.x] = s;
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = SGW_BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            ss[threadIdx.x] += ss[threadIdx.x + w];
+            const double o = sm[threadIdx.x + w];
+            sm[threadIdx.x] = (o > sm[threadIdx.x] || o != o) ? o : sm[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = ss[0];
+        partials[2 * blockIdx.x + 1] = sm[0];
+    }
+}
+
+__global__ void norms_final_kernel(const double* partials, int np, int64_t n, double* result)
+{
+    __shared__ double ss[SGW_NPART], sm[SGW_NPART];
+    for (int i = threadIdx.x; i < SGW_NPART; i += blockDim.x) {
+        ss[i] = i < np ? partials[2 * i] : 0.0;
+        sm[i] = i < np ? partials[2 * i + 1] : 0.0;
+    }
+    __syncthreads();
+    for (int w = SGW_NPART / 2; w > 0; w >>= 1) {
+        for (int i = threadIdx.x; i < w; i += blockDim.x) {
+            ss[i] += ss[i + w];
+            const double o = sm[i + w];
+            sm[i] = (o > sm[i] || o != o) ? o : sm[i];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        result[0] = n > 0 ? ss[0] / (double)n : 0.0;
+        result[1] = sm[0];
+    }
+}
+
+} // namespace
+
+hipError_t launch_prolong(const ProDev* pro_dev, const FineDev* fine_dev, const FineDev& fh, int precision,
+                          size_t lds_bytes, double* out, hipStream_t s)
+{
+    int tiles = 1;
+    for (int k = 0; k < fh.d; k++) tiles *= fh.ntile[k];
+#define SGW_PRO(R, DD) \
+    hipLaunchKernelGGL((prolong_kernel<R, DD>), dim3(tiles), dim3(SGW_BLOCK), lds_bytes, s, pro_dev, fine_dev, out)
+    if (precision == SGW_FP64) {
+        switch (fh.d) {
+        case 1: SGW_PRO(double, 1); break;
+        case 2: SGW_PRO(double, 2); break;
+        case 3: SGW_PRO(double, 3); break;
+        default: SGW_PRO(double, 4); break;
+        }
+    } else {
+        switch (fh.d) {
+        case 1: SGW_PRO(float, 1); break;
+        case 2: SGW_PRO(float, 2); break;
+        case 3: SGW_PRO(float, 3); break;
+        default: SGW_PRO(float, 4); break;
+        }
+    }
+#undef SGW_PRO
+    return hipGetLastError();
+}
+
+hipError_t launch_exact(const ExactDev& e, double* out, double* foot_scratch, hipStream_t s)
+{
+    ExactDev ee = e;
+    if (e.flux == SGW_FLUX_VLASOV_FIXED_E) {
+        ee.foot = foot_scratch;
+        hipLaunchKernelGGL(vlasov_foot_kernel, dim3(256), dim3(SGW_BLOCK), 0, s, ee, foot_scratch);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    hipLaunchKernelGGL(exact_kernel, dim3(2048), dim3(SGW_BLOCK), 0, s, ee, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_norms(const double* a, const double* b, int64_t n, double* partials, double* result, hipStream_t s)
+{
+    hipLaunchKernelGGL(norms_partial_kernel, dim3(SGW_NPART), dim3(SGW_BLOCK), 0, s, a, b, n, partials);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(norms_final_kernel, dim3(1), dim3(SGW_BLOCK), 0, s, partials, SGW_NPART, n, result);
+    return hipGetLastError();
+}

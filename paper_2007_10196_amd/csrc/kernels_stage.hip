@@ -1,0 +1,546 @@
+// Time-marching kernels of libsgweno: initial restriction, LF wave speeds,
+// the shared time step, and the fused WENO5-LF + TVD-RK3 stage.
+//
+// The stage kernel follows Sec. 2.1 of the paper: for every direction k the
+// flux f_k is split by the global Lax-Friedrichs rule (eq. LFflux) into
+// f^+ = (f + alpha u)/2 and f^- = (f - alpha u)/2, the interface flux at
+// x_{i+1/2} is the WENO5 reconstruction of f^+ from (i-2..i+2) plus the mirror
+// reconstruction of f^- from (i+3..i-1) (eqs. 2.7, 2.7.1, 2.6, 2.7.2), and the
+// operator is the conservative difference of eq. (2.9), summed over k.  The
+// TVD-RK3 (Shu-Osher) stage combination is applied in the same pass.
+//
+// Layout: one workgroup owns a box of one component grid.  The box and a
+// 3-node halo in every direction where the box does not span the grid are
+// staged in LDS (periodic wrap applied while loading), one direction at a
+// time the interface fluxes of the box go to a second LDS array, and each
+// thread accumulates the flux differences of its nodes in registers.
+#include "sgw_internal.h"
+
+namespace {
+
+__device__ __forceinline__ float rdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double rdiv(double a, double b) { return a / b; }
+
+// WENO5 flux from the positive-wind big stencil (a..e) = (f_{i-2} .. f_{i+2}).
+// Nonlinear weights alpha_r = d_r / (eps + beta_r)^2 normalised by their sum;
+// written with one division: multiply numerator and denominator by
+// prod_r (eps + beta_r)^2.
+template <typename Real>
+__device__ __forceinline__ Real weno5(Real a, Real b, Real c, Real d, Real e, Real eps, int linear)
+{
+    const Real q0 = a * Real(1.0 / 3.0) - b * Real(7.0 / 6.0) + c * Real(11.0 / 6.0);
+    const Real q1 = -b * Real(1.0 / 6.0) + c * Real(5.0 / 6.0) + d * Real(1.0 / 3.0);
+    const Real q2 = c * Real(1.0 / 3.0) + d * Real(5.0 / 6.0) - e * Real(1.0 / 6.0);
+    if (linear) return Real(0.1) * q0 + Real(0.6) * q1 + Real(0.3) * q2;
+    const Real t0 = a - Real(2) * b + c, s0 = a - Real(4) * b + Real(3) * c;
+    const Real t1 = b - Real(2) * c + d, s1 = b - d;
+    const Real t2 = c - Real(2) * d + e, s2 = Real(3) * c - Real(4) * d + e;
+    Real e0 = eps + (Real(13.0 / 12.0) * t0 * t0 + Real(0.25) * s0 * s0);
+    Real e1 = eps + (Real(13.0 / 12.0) * t1 * t1 + Real(0.25) * s1 * s1);
+    Real e2 = eps + (Real(13.0 / 12.0) * t2 * t2 + Real(0.25) * s2 * s2);
+    e0 *= e0;
+    e1 *= e1;
+    e2 *= e2;
+    const Real w0 = Real(0.1) * (e1 * e2);
+    const Real w1 = Real(0.6) * (e0 * e2);
+    const Real w2 = Real(0.3) * (e0 * e1);
+    return rdiv(w0 * q0 + w1 * q1 + w2 * q2, w0 + w1 + w2);
+}
+
+// max that keeps a NaN (a NaN wave speed must reach the time-step check)
+__device__ __forceinline__ double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Max over the workgroup, then one atomic max on the bit pattern (non-negative
+// doubles order like their unsigned bit patterns; NaN sorts above everything).
+__device__ __forceinline__ void block_atomic_max(double v, unsigned long long* dst, double* red)
+{
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < SGW_BLOCK / 64; w++) m = nanmax(m, red[w]);
+        atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+template <typename Real, int D>
+__device__ __forceinline__ void stage_box(const GridDev* __restrict__ g, int box, int stage, Real* su, Real* sf,
+                                          double* red)
+{
+    const int tid = threadIdx.x;
+    const ReqDev* req = g->req;
+    const double dt = req->dt;
+    const Real dtr = (Real)dt;
+
+    int o[D];
+    {
+        int r = box;
+        for (int k = 0; k < D; k++) {
+            const int q = r / g->ntile[k];
+            o[k] = (r - q * g->ntile[k]) * g->t[k];
+            r = q;
+        }
+    }
+    const Real* __restrict__ in = (const Real*)(stage == 0 ? g->u : stage == 1 ? g->a : g->b);
+    Real* __restrict__ out = (Real*)(stage == 0 ? g->a : stage == 1 ? g->b : g->u);
+    const Real* __restrict__ u0 = (const Real*)g->u;
+
+    // the wave-speed slot the next stage reads is cleared by the stage before it
+    if (g->dyn_alpha && box == 0 && tid == 0) g->alpha[(stage + 2) % 3] = 0ull;
+
+    // ---- stage the padded box (cross-shaped: at most one direction in the halo)
+    const int pad_total = g->pad_total;
+    for (int e = tid; e < pad_total; e += SGW_BLOCK) {
+        uint32_t r = (uint32_t)e;
+        int gi = 0, outside = 0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            const uint32_t q = fdiv(r, g->fd_P[k]);
+            const int c = (int)(r - q * (uint32_t)g->P[k]);
+            r = q;
+            const int hk = g->halo[k];
+            int x = o[k] + c - hk;
+            x += (x < 0) ? g->n[k] : 0;
+            x -= (x >= g->n[k]) ? g->n[k] : 0;
+            outside += (c < hk) | (c >= hk + g->t[k]);
+            gi += x * g->stride[k];
+        }
+        if (outside <= 1) su[e] = in[gi];
+    }
+    __syncthreads();
+
+    Real acc[SGW_MAXR];
+#pragma unroll
+    for (int r = 0; r < SGW_MAXR; r++) acc[r] = Real(0);
+
+    const Real eps = (Real)g->eps;
+    const int linear = g->linear;
+    const int core_total = g->core_total;
+    Real dyn_alpha = Real(0);
+    if (g->dyn_alpha) dyn_alpha = (Real)__longlong_as_double((long long)g->alpha[stage]);
+
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        const int hf = g->halo[k] ? 1 : 0;
+        const int tk = g->t[k];
+        const int PSk = g->PS[k];
+        const Real alpha = g->dyn_alpha ? dyn_alpha : (Real)g->alpha_c[k];
+        const double* __restrict__ ctab = g->coef[k];
+        const int csrc = g->coef_src[k];
+        const Real cconst = (Real)g->lin_c[k];
+        // ---- interface fluxes of the box in direction k -> sf
+        const int ftot = g->flux_total[k];
+        for (int f = tid; f < ftot; f += SGW_BLOCK) {
+            uint32_t r = (uint32_t)f;
+            int base = 0, ck = 0, csrc_coord = 0;
+#pragma unroll
+            for (int j = 0; j < D; j++) {
+                const FastDiv& fd = (j == k) ? g->fd_I[j] : g->fd_t[j];
+                const uint32_t q = fdiv(r, fd);
+                const int c = (int)(r - q * fd.d);
+                r = q;
+                if (j == k) ck = c;
+                else base += (c + g->halo[j]) * g->PS[j];
+                if (j == csrc) csrc_coord = o[j] + c;
+            }
+            const int i = ck - hf; // the flux is at x_{i+1/2}
+            Real v[6];
+#pragma unroll
+            for (int m = 0; m < 6; m++) {
+                int p = i + m - 2;
+                if (hf) {
+                    p += 3;
+                } else {
+                    p += (p < 0) ? tk : 0;
+                    p -= (p >= tk) ? tk : 0;
+                }
+                v[m] = su[base + p * PSk];
+            }
+            Real pl[6], mi[6];
+            if (g->flux == SGW_FLUX_BURGERS) {
+#pragma unroll
+                for (int m = 0; m < 6; m++) {
+                    const Real hu = Real(0.25) * v[m];
+                    pl[m] = v[m] * (hu + Real(0.5) * alpha);
+                    mi[m] = v[m] * (hu - Real(0.5) * alpha);
+                }
+            } else {
+                const Real c = (csrc >= 0) ? (Real)ctab[csrc_coord] : cconst;
+                const Real cp = Real(0.5) * (c + alpha), cm = Real(0.5) * (c - alpha);
+#pragma unroll
+                for (int m = 0; m < 6; m++) {
+                    pl[m] = cp * v[m];
+                    mi[m] = cm * v[m];
+                }
+            }
+            const Real F = weno5<Real>(pl[0], pl[1], pl[2], pl[3], pl[4], eps, linear) +
+                           weno5<Real>(mi[5], mi[4], mi[3], mi[2], mi[1], eps, linear);
+            sf[f] = F;
+        }
+        __syncthreads();
+        // ---- flux differences of eq. (2.9) for the nodes this thread owns
+        const Real ih = (Real)g->inv_h[k];
+        const int CSk = g->CS[k];
+        const int Ik = g->I[k];
+#pragma unroll
+        for (int r = 0; r < SGW_MAXR; r++) {
+            const int e = tid + r * SGW_BLOCK;
+            if (e < core_total) {
+                const uint32_t hi = fdiv((uint32_t)e, g->fd_CSt[k]);
+                const int lo = e - (int)hi * (int)g->fd_CSt[k].d;
+                const int fhi = lo + hf * CSk + (int)hi * CSk * Ik;
+                const int flo = (hf || lo >= CSk) ? fhi - CSk : fhi + (tk - 1) * CSk;
+                acc[r] -= (sf[fhi] - sf[flo]) * ih;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- TVD-RK3 stage: u1 = u + dt L(u); u2 = 3/4 u + 1/4 (u1 + dt L(u1)); u = 1/3 u + 2/3 (u2 + dt L(u2))
+    double amax = 0.0;
+#pragma unroll
+    for (int r = 0; r < SGW_MAXR; r++) {
+        const int e = tid + r * SGW_BLOCK;
+        if (e < core_total) {
+            uint32_t rr = (uint32_t)e;
+            int pidx = 0, gi = 0;
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+                const uint32_t q = fdiv(rr, g->fd_t[k]);
+                const int c = (int)(rr - q * (uint32_t)g->t[k]);
+                rr = q;
+                pidx += (c + g->halo[k]) * g->PS[k];
+                gi += (o[k] + c) * g->stride[k];
+            }
+            const Real val = su[pidx] + dtr * acc[r];
+            Real res;
+            if (stage == 0) res = val;
+            else if (stage == 1) res = Real(0.75) * u0[gi] + Real(0.25) * val;
+            else res = Real(1.0 / 3.0) * u0[gi] + Real(2.0 / 3.0) * val;
+            out[gi] = res;
+            const double ar = fabs((double)res);
+            amax = nanmax(amax, ar);
+        }
+    }
+    if (g->dyn_alpha) block_atomic_max(amax, g->alpha + (stage + 1) % 3, red);
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __restrict__ items, int nitems,
+                                                          const int* __restrict__ nitems_dev, int stage)
+{
+    // a batch keeps its box count in device memory so a captured graph stays valid as solves come and go
+    if (nitems_dev) nitems = *nitems_dev;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[SGW_BLOCK / 64];
+    // XCD-aware order: consecutive workgroup ids land on different XCDs, so hand
+    // each XCD a contiguous run of boxes (neighbouring boxes share halo lines in L2)
+    int nb = gridDim.x, bid = blockIdx.x;
+    if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+    for (int w = bid; w < nitems; w += nb) {
+        const WorkItem it = items[w];
+        const GridDev* g = it.g;
+        if (g->req->done) continue;
+        const size_t su_elems = (size_t)g->pad_total;
+        Real* su = (Real*)smem;
+        Real* sf = su + ((su_elems + 1) & ~(size_t)1);
+        switch (g->d) {
+        case 1: stage_box<Real, 1>(g, it.box, stage, su, sf, red); break;
+        case 2: stage_box<Real, 2>(g, it.box, stage, su, sf, red); break;
+        case 3: stage_box<Real, 3>(g, it.box, stage, su, sf, red); break;
+        default: stage_box<Real, 4>(g, it.box, stage, su, sf, red); break;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- set-up kernels
+
+__global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long long v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Coefficient tables of the fixed-field Vlasov flux and the constant LF speeds:
+// f_{x_k} = v_k u (coefficient indexed by the v_k node), f_{v_k} = E_k(x_k) u.
+// One workgroup per (grid, direction); the max over the table is the LF speed.
+__global__ void coef_init_kernel(GridDev* grids, double* coef_base, const int64_t* coef_off, double amp, double kE)
+{
+    __shared__ double red[SGW_BLOCK / 64];
+    GridDev* g = grids + blockIdx.x;
+    const int k = blockIdx.y;
+    if (k >= g->d) return;
+    const int m = g->d / 2;
+    const int src = g->coef_src[k];
+    double* tab = coef_base + coef_off[blockIdx.x * SGW_MAX_DIM + k];
+    const int n = g->n[src];
+    double amax = 0.0;
+    for (int j = threadIdx.x; j < n; j += SGW_BLOCK) {
+        const double x = g->lo[src] + j * g->h[src];
+        const double c = (k < m) ? x : amp * sin(kE * x);
+        tab[j] = c;
+        amax = fmax(amax, fabs(c));
+    }
+    amax = wave_max(amax);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mm = red[0];
+        for (int w = 1; w < SGW_BLOCK / 64; w++) mm = fmax(mm, red[w]);
+        g->alpha_c[k] = mm;
+    }
+}
+
+struct RestrictArgs {
+    int32_t ic, precision;
+    double ip[8];
+};
+
+// Alg. Step 1: evaluate the initial condition at the nodes x_j = lo + j h.
+template <typename Real>
+__global__ void restrict_kernel(const GridDev* grids, RestrictArgs a)
+{
+    __shared__ double red[SGW_BLOCK / 64];
+    const GridDev* g = grids + blockIdx.y;
+    int64_t total = 1;
+    for (int k = 0; k < g->d; k++) total *= g->n[k];
+    Real* u = (Real*)g->u;
+    double amax = 0.0;
+    for (int64_t idx = blockIdx.x * (int64_t)SGW_BLOCK + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * SGW_BLOCK) {
+        uint32_t r = (uint32_t)idx;
+        double x[SGW_MAX_DIM] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < g->d; k++) {
+            const uint32_t q = fdiv(r, g->fd_n[k]);
+            const int j = (int)(r - q * (uint32_t)g->n[k]);
+            r = q;
+            x[k] = g->lo[k] + j * g->h[k];
+        }
+        double v;
+        if (a.ic == SGW_IC_SINE) {
+            double s = 0.0;
+            for (int k = 0; k < g->d; k++) s += x[k];
+            v = a.ip[0] + a.ip[1] * sin(a.ip[2] * s + a.ip[3]);
+        } else {
+            const int m = g->d / 2;
+            double v2 = 0.0, pert = 1.0, norm = 1.0;
+            for (int k = 0; k < m; k++) {
+                v2 += x[m + k] * x[m + k];
+                pert *= cos(a.ip[1] * x[k] + a.ip[2 + k]);
+                norm *= 2.0 * M_PI;
+            }
+            v = exp(-0.5 * v2) / sqrt(norm) * (1.0 + a.ip[0] * pert);
+        }
+        const Real vr = (Real)v;
+        u[idx] = vr;
+        amax = nanmax(amax, fabs((double)vr));
+    }
+    if (g->dyn_alpha) block_atomic_max(amax, g->alpha + 0, red);
+}
+
+__global__ void req_reset_kernel(ReqDev* r)
+{
+    r->t = 0.0;
+    r->steps = 0;
+    r->done = 0;
+    r->nonfinite = 0;
+    r->dt = 0.0;
+}
+
+__global__ void req_set_final_kernel(ReqDev* r, double T)
+{
+    r->T = T;
+    r->done = r->nonfinite ? 1 : 0;
+}
+
+// The shared time step (Sec. 3): dt = cfl / sum_k (A_k / h_k^fine), A_k the
+// largest LF speed over all component grids of the solve at u^n, clipped so the
+// last step lands on T.  One thread per solve.
+__device__ void dt_one(ReqDev* r)
+{
+    if (!r->active || r->done) {
+        r->dt = 0.0;
+        return;
+    }
+    const double rem = r->T - r->t;
+    const double tol = 1e-12 * (r->T > 1.0 ? r->T : 1.0);
+    if (!(rem > tol)) {
+        r->done = 1;
+        r->dt = 0.0;
+        return;
+    }
+    double dt;
+    if (r->dt_mode == SGW_DT_POW53) {
+        dt = r->dt_pow53;
+    } else {
+        double denom = 0.0;
+        for (int k = 0; k < r->d; k++) {
+            double A = 0.0;
+            for (int g = 0; g < r->ngrids; g++) {
+                const GridDev* gd = r->grids + g;
+                const double a = gd->dyn_alpha ? __longlong_as_double((long long)gd->alpha[0]) : gd->alpha_c[k];
+                A = (a > A || a != a) ? a : A;
+            }
+            denom += A / r->hfin[k];
+        }
+        if (denom != denom || denom > 1.7e308) {
+            r->nonfinite = 1;
+            r->done = 1;
+            r->dt = 0.0;
+            return;
+        }
+        dt = denom > 0.0 ? r->cfl / denom : rem;
+    }
+    if (dt > rem) dt = rem;
+    r->dt = dt;
+    r->t += dt;
+    r->steps += 1;
+}
+
+__global__ void dt_kernel(ReqDev* const* reqs, int nreq)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nreq && reqs[i]) dt_one(reqs[i]);
+}
+
+__global__ void gather_done_kernel(ReqDev* const* reqs, int nreq, int* flags)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nreq) flags[i] = reqs[i] ? (reqs[i]->done ? 1 : 0) | (reqs[i]->nonfinite ? 2 : 0) : 0;
+}
+
+__global__ void dt_one_kernel(ReqDev* r) { dt_one(r); }
+
+} // namespace
+
+// ---------------------------------------------------------------- launchers
+
+size_t stage_lds_bytes(const GridDev& g, int precision)
+{
+    const size_t rs = precision == SGW_FP64 ? 8 : 4;
+    int fmax_ = 0;
+    for (int k = 0; k < g.d; k++) fmax_ = g.flux_total[k] > fmax_ ? g.flux_total[k] : fmax_;
+    return rs * (((size_t)g.pad_total + 1) / 2 * 2 + (size_t)fmax_);
+}
+
+int stage_occupancy(int precision, size_t lds_bytes)
+{
+    int nb = 0;
+    hipError_t e;
+    if (precision == SGW_FP64)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_kernel<double>, SGW_BLOCK, lds_bytes);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_kernel<float>, SGW_BLOCK, lds_bytes);
+    if (e != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)((n + SGW_BLOCK - 1) / SGW_BLOCK);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks), dim3(SGW_BLOCK), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_coef_init(GridDev* grids_dev, const GridDev* grids_host, int G, double* coef_base,
+                            const int64_t* coef_off_dev, const sgw_problem* pb, hipStream_t s)
+{
+    (void)grids_host;
+    if (G <= 0) return hipSuccess;
+    hipLaunchKernelGGL(coef_init_kernel, dim3(G, SGW_MAX_DIM), dim3(SGW_BLOCK), 0, s, grids_dev, coef_base,
+                       coef_off_dev, pb->flux_params[0], pb->flux_params[1]);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict(const GridDev* grids_dev, const GridDev* grids_host, int G, int precision,
+                           const sgw_problem* pb, hipStream_t s)
+{
+    int64_t maxn = 1;
+    for (int g = 0; g < G; g++) {
+        int64_t n = 1;
+        for (int k = 0; k < grids_host[g].d; k++) n *= grids_host[g].n[k];
+        maxn = n > maxn ? n : maxn;
+    }
+    int bx = (int)((maxn + SGW_BLOCK - 1) / SGW_BLOCK);
+    if (bx > 256) bx = 256;
+    RestrictArgs a;
+    a.ic = pb->ic;
+    a.precision = precision;
+    for (int i = 0; i < 8; i++) a.ip[i] = pb->ic_params[i];
+    if (precision == SGW_FP64)
+        hipLaunchKernelGGL(restrict_kernel<double>, dim3(bx, G), dim3(SGW_BLOCK), 0, s, grids_dev, a);
+    else
+        hipLaunchKernelGGL(restrict_kernel<float>, dim3(bx, G), dim3(SGW_BLOCK), 0, s, grids_dev, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_req_reset(ReqDev* r, hipStream_t s)
+{
+    hipLaunchKernelGGL(req_reset_kernel, dim3(1), dim3(1), 0, s, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_req_set_final(ReqDev* r, double T, hipStream_t s)
+{
+    hipLaunchKernelGGL(req_set_final_kernel, dim3(1), dim3(1), 0, s, r, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt(ReqDev* const* reqs, int nreq, hipStream_t s)
+{
+    if (nreq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dt_kernel, dim3((nreq + 63) / 64), dim3(64), 0, s, reqs, nreq);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt_one(ReqDev* req, hipStream_t s)
+{
+    hipLaunchKernelGGL(dt_one_kernel, dim3(1), dim3(1), 0, s, req);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage(const WorkItem* items, int nitems, int stage, int precision, int dim_max,
+                        size_t lds_bytes, int grid_cap, hipStream_t s)
+{
+    (void)dim_max;
+    if (nitems <= 0) return hipSuccess;
+    int blocks = nitems;
+    if (grid_cap > 0 && blocks > grid_cap) blocks = grid_cap;
+    const int* nd = nullptr;
+    if (precision == SGW_FP64)
+        hipLaunchKernelGGL(stage_kernel<double>, dim3(blocks), dim3(SGW_BLOCK), lds_bytes, s, items, nitems, nd, stage);
+    else
+        hipLaunchKernelGGL(stage_kernel<float>, dim3(blocks), dim3(SGW_BLOCK), lds_bytes, s, items, nitems, nd, stage);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_dev_count(const WorkItem* items, const int* nitems_dev, int blocks, int stage, int precision,
+                                  size_t lds_bytes, hipStream_t s)
+{
+    if (precision == SGW_FP64)
+        hipLaunchKernelGGL(stage_kernel<double>, dim3(blocks), dim3(SGW_BLOCK), lds_bytes, s, items, 0, nitems_dev,
+                           stage);
+    else
+        hipLaunchKernelGGL(stage_kernel<float>, dim3(blocks), dim3(SGW_BLOCK), lds_bytes, s, items, 0, nitems_dev,
+                           stage);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_done(ReqDev* const* reqs, int nreq, int* flags, hipStream_t s)
+{
+    if (nreq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_done_kernel, dim3((nreq + 63) / 64), dim3(64), 0, s, reqs, nreq, flags);
+    return hipGetLastError();
+}

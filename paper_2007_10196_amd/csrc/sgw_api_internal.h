@@ -1,0 +1,63 @@
+// Host-side objects of libsgweno (plans, solvers, batches).
+#pragma once
+
+#include <array>
+#include <vector>
+
+#include "sgw_internal.h"
+
+struct sgw_plan {
+    sgw_problem pb;
+    sgw_config cfg;
+    int G = 0;
+    int N = 0;                                 // finest nodes per direction
+    int64_t fine_nodes = 0;
+    int64_t total_nodes = 0;
+    int64_t nitems = 0;                        // stage boxes over all grids
+    size_t stage_lds = 0;                      // max LDS bytes of a box
+    std::vector<std::array<int, 4>> levels;
+    std::vector<int> coefs;
+    std::vector<int64_t> offsets;              // element offset of each grid in a state copy
+    std::vector<GridDev> grids;                // geometry only (pointers filled by the solver)
+    std::vector<int64_t> coef_off;             // [G][4] offsets into the coefficient tables
+    int fine_T[SGW_MAX_DIM] = {1, 1, 1, 1};
+    size_t pro_buf_elems = 0;
+    uint64_t copy_bytes = 0, state_bytes = 0, scratch_bytes = 0;
+    uint64_t off_grids = 0, off_req = 0, off_items = 0, off_alpha = 0, off_coef = 0, off_coef_off = 0;
+    uint64_t off_pro = 0, off_fine = 0, off_partials = 0, off_result = 0, off_foot = 0;
+};
+
+struct sgw_solver {
+    sgw_plan* plan = nullptr;
+    unsigned char* state = nullptr;
+    unsigned char* scratch = nullptr;
+    hipStream_t stream = nullptr;
+    GridDev* grids_d = nullptr;
+    ReqDev* req_d = nullptr;
+    WorkItem* items_d = nullptr;
+    unsigned long long* alpha_d = nullptr;
+    double* coef_d = nullptr;
+    int64_t* coef_off_d = nullptr;
+    ProDev* pro_d = nullptr;
+    FineDev* fine_d = nullptr;
+    double* partials_d = nullptr;
+    double* result_d = nullptr;
+    double* foot_d = nullptr;
+    std::vector<GridDev> grids_h;
+    std::vector<WorkItem> items_h;
+    std::vector<ProDev> pro_h;
+    FineDev fine_h;
+    ReqDev req_h;
+    ReqDev* req_pinned = nullptr;
+    bool restricted = false;
+    double t_host = 0.0;
+    int occupancy = 1;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_steps = 0;
+    int batch_slot = -1;
+};
+
+sgw_status sgw_fail(sgw_status st, const char* fmt, ...);
+sgw_status sgw_hip_fail(hipError_t e, const char* what);

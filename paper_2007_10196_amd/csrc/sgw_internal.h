@@ -1,0 +1,146 @@
+// Internal definitions of libsgweno shared by its host and device sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sgweno.h"
+
+#define SGW_BLOCK 256     // threads per workgroup of every kernel (4 wave64)
+#define SGW_MAXR 8        // nodes per thread in the stage kernel: box core <= SGW_BLOCK * SGW_MAXR
+#define SGW_NPART 1024    // workgroups of the first norm pass (fixed, so the sum order is fixed)
+
+// Division by a run-time constant d >= 1 for numerators below 2^31:
+// q = (umulhi(x, m) + x) >> s with s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1.
+struct FastDiv {
+    uint32_t d, m, s, pad;
+};
+
+static inline FastDiv make_fastdiv(uint32_t d)
+{
+    FastDiv f;
+    f.d = d;
+    uint32_t s = 0;
+    while ((1ull << s) < d) s++;
+    f.s = s;
+    f.m = (uint32_t)((((1ull << s) - d) << 32) / d + 1);
+    f.pad = 0;
+    return f;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f)
+{
+    return (__umulhi(x, f.m) + x) >> f.s;
+}
+
+struct ReqDev;
+
+// One component grid as seen by the stage kernel.  Box = the tile one
+// workgroup updates; t[k] divides n[k]; a box that does not span its grid in
+// direction k carries 3 halo nodes on each side in that direction.
+struct alignas(64) GridDev {
+    void* u;                         // u^n (also the output of stage 3)
+    void* a;                         // output of stage 1
+    void* b;                         // output of stage 2
+    unsigned long long* alpha;       // [4]: slots 0..2 hold max|u| bits of the input of stage s
+    ReqDev* req;                     // the solve this grid belongs to
+    const double* coef[SGW_MAX_DIM]; // linear flux coefficient per node of direction coef_src[k]
+    int32_t d, flux, dyn_alpha, linear;
+    int32_t nbox, pad_total, core_total, first_item;
+    int32_t n[SGW_MAX_DIM];
+    int32_t stride[SGW_MAX_DIM];
+    int32_t t[SGW_MAX_DIM];
+    int32_t halo[SGW_MAX_DIM];       // 3 or 0
+    int32_t ntile[SGW_MAX_DIM];
+    int32_t P[SGW_MAX_DIM];          // padded box extents t + 2 halo
+    int32_t PS[SGW_MAX_DIM];         // padded strides
+    int32_t CS[SGW_MAX_DIM];         // core strides
+    int32_t I[SGW_MAX_DIM];          // interfaces per line in the box: t + (halo ? 1 : 0)
+    int32_t flux_total[SGW_MAX_DIM]; // interfaces in the box per direction
+    int32_t coef_src[SGW_MAX_DIM];   // direction whose node index selects the coefficient, -1: constant
+    FastDiv fd_P[SGW_MAX_DIM];
+    FastDiv fd_t[SGW_MAX_DIM];
+    FastDiv fd_I[SGW_MAX_DIM];
+    FastDiv fd_CSt[SGW_MAX_DIM];     // CS[k] * t[k]
+    FastDiv fd_n[SGW_MAX_DIM];
+    double lo[SGW_MAX_DIM];
+    double h[SGW_MAX_DIM];
+    double inv_h[SGW_MAX_DIM];
+    double lin_c[SGW_MAX_DIM];       // constant coefficient of a linear flux (advection)
+    double alpha_c[SGW_MAX_DIM];     // constant LF speed max|f_k'| (advection, Vlasov)
+    double eps;
+};
+
+// Per-solve time-stepping record, written only by the device after set-up.
+struct alignas(64) ReqDev {
+    double t, T, dt, cfl, dt_pow53;
+    double hfin[SGW_MAX_DIM];
+    int64_t steps;
+    const GridDev* grids;
+    int32_t ngrids, d, dt_mode, done;
+    int32_t nonfinite, dyn_alpha, active, pad;
+};
+
+struct WorkItem {
+    const GridDev* g;
+    int32_t box;
+    int32_t pad;
+};
+
+// One component grid as seen by the prolongation-combination kernel.
+struct alignas(64) ProDev {
+    const void* u;
+    int32_t coef;
+    int32_t load_total;              // prod c[k]
+    int32_t m[SGW_MAX_DIM];          // refinement exponent N_L - l_k
+    int32_t n[SGW_MAX_DIM];
+    int32_t stride[SGW_MAX_DIM];
+    int32_t c[SGW_MAX_DIM];          // coarse extent loaded per tile (T when m = 0)
+    int32_t outer[SGW_MAX_DIM];      // prod_{j>k} c[j]
+    FastDiv fd_c[SGW_MAX_DIM];
+};
+
+struct alignas(64) FineDev {
+    int32_t d, N, G, lagrange;
+    int32_t T[SGW_MAX_DIM];
+    int32_t ntile[SGW_MAX_DIM];
+    int32_t inner[SGW_MAX_DIM];      // prod_{j<k} T[j]
+    int32_t tile_points, pad0, pad1, pad2;
+    FastDiv fd_T[SGW_MAX_DIM];
+    FastDiv fd_inner[SGW_MAX_DIM];
+    double eps;
+};
+
+// Problem constants the exact-solution kernels need.
+struct ExactDev {
+    int32_t d, flux, ic, N;
+    double lo[SGW_MAX_DIM], h[SGW_MAX_DIM];
+    double fp[SGW_MAX_DIM];
+    double ip[8];
+    double t;
+    const double* foot;              // Vlasov: (X0, V0) per (x node, v node) pair and x direction
+};
+
+// ---------------------------------------------------------------- kernel launchers (kernels_*.hip)
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_coef_init(GridDev* grids_dev, const GridDev* grids_host, int G, double* coef_base,
+                            const int64_t* coef_off_host, const sgw_problem* pb, hipStream_t s);
+hipError_t launch_restrict(const GridDev* grids_dev, const GridDev* grids_host, int G, int precision,
+                           const sgw_problem* pb, hipStream_t s);
+hipError_t launch_req_reset(ReqDev* r, hipStream_t s);
+hipError_t launch_req_set_final(ReqDev* r, double T, hipStream_t s);
+hipError_t launch_dt(ReqDev* const* reqs, int nreq, hipStream_t s);
+hipError_t launch_dt_one(ReqDev* req, hipStream_t s);
+hipError_t launch_stage(const WorkItem* items, int nitems, int stage, int precision, int dim_max,
+                        size_t lds_bytes, int grid_cap, hipStream_t s);
+hipError_t launch_stage_dev_count(const WorkItem* items, const int* nitems_dev, int blocks, int stage, int precision,
+                                  size_t lds_bytes, hipStream_t s);
+hipError_t launch_gather_done(ReqDev* const* reqs, int nreq, int* flags, hipStream_t s);
+size_t stage_lds_bytes(const GridDev& g, int precision);
+int stage_occupancy(int precision, size_t lds_bytes);
+hipError_t launch_prolong(const ProDev* pro_dev, const FineDev* fine_dev, const FineDev& fine_host,
+                          int precision, size_t lds_bytes, double* out, hipStream_t s);
+hipError_t launch_exact(const ExactDev& e, double* out, double* foot_scratch, hipStream_t s);
+hipError_t launch_norms(const double* a, const double* b, int64_t n, double* partials, double* result,
+                        hipStream_t s);

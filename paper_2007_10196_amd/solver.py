@@ -1,0 +1,204 @@
+"""Python front end of libsgweno: one sparse-grid solve on one GPU.
+
+Device memory comes from PyTorch (uint8 tensors sized by sgw_plan_footprint)
+and work is enqueued on the current PyTorch (HIP) stream; the computation is
+the library's.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Tuple
+
+import torch
+
+from . import binding as B
+
+
+class Plan:
+    """Host-only plan: the component grids of the index set, their layout and tiling."""
+
+    def __init__(self, problem, box=None, fine_tile=None, box_target=0):
+        self.problem = problem
+        self._pb, self._cfg = B.make_structs(problem, box, fine_tile, box_target)
+        h = C.c_void_p()
+        B.check(B.lib().sgw_plan_create(C.byref(self._pb), C.byref(self._cfg), C.byref(h)))
+        self.handle = h
+        st, sc, fi = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        B.check(B.lib().sgw_plan_footprint(h, C.byref(st), C.byref(sc), C.byref(fi)))
+        self.state_bytes, self.scratch_bytes, self.fine_bytes = st.value, sc.value, fi.value
+        g, tn, fn = C.c_int32(), C.c_int64(), C.c_int64()
+        B.check(B.lib().sgw_plan_info(h, C.byref(g), C.byref(tn), C.byref(fn)))
+        self.num_grids, self.total_nodes, self.fine_nodes = g.value, tn.value, fn.value
+        self.grids = []
+        for i in range(self.num_grids):
+            lv, sh = (C.c_int32 * 4)(), (C.c_int32 * 4)()
+            cf, off = C.c_int32(), C.c_int64()
+            B.check(B.lib().sgw_plan_grid(h, i, lv, sh, C.byref(cf), C.byref(off)))
+            bx = (C.c_int32 * 4)()
+            B.check(B.lib().sgw_plan_grid_box(h, i, bx))
+            d = problem.d
+            self.grids.append(dict(level=tuple(lv[:d]), shape=tuple(sh[:d]), coef=cf.value, offset=off.value,
+                                   box=tuple(bx[:d])))
+
+    @property
+    def footprint(self) -> int:
+        return self.state_bytes + self.scratch_bytes + self.fine_bytes
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                B.lib().sgw_plan_free(h)
+            except Exception:
+                pass
+            self.handle = C.c_void_p()
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """Bound solve: caller-owned device buffers + a HIP stream."""
+
+    def __init__(self, problem, device: str = "cuda", stream: Optional[torch.cuda.Stream] = None,
+                 box=None, fine_tile=None, plan: Optional[Plan] = None, box_target: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("sgweno needs a ROCm GPU; none is visible")
+        self.problem = problem
+        self.plan = plan or Plan(problem, box, fine_tile, box_target)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # torch's caching allocator returns 512-byte aligned blocks
+        self.state = torch.empty(self.plan.state_bytes, dtype=torch.uint8, device=self.device)
+        self.scratch = torch.empty(self.plan.scratch_bytes, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        B.check(B.lib().sgw_solver_create(self.plan.handle, C.c_void_p(self.state.data_ptr()),
+                                          C.c_void_p(self.scratch.data_ptr()), _stream_handle(self.stream),
+                                          C.byref(h)))
+        self.handle = h
+        self.real = torch.float64 if problem.precision == B.FP64 else torch.float32
+
+    # --- the algorithm
+    def restrict(self):
+        B.check(B.lib().sgw_restrict_initial(self.handle))
+        return self
+
+    def advance(self, t_final: Optional[float] = None, mode: int = B.RUN_GRAPH):
+        B.check(B.lib().sgw_advance(self.handle, self.problem.T if t_final is None else t_final, mode))
+        return self
+
+    def prolongate_combine(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.plan.fine_nodes, dtype=torch.float64, device=self.device)
+        assert out.dtype == torch.float64 and out.numel() >= self.plan.fine_nodes and out.is_contiguous()
+        B.check(B.lib().sgw_prolongate_combine(self.handle, C.c_void_p(out.data_ptr())))
+        return out
+
+    def exact(self, t: float, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.plan.fine_nodes, dtype=torch.float64, device=self.device)
+        B.check(B.lib().sgw_exact(self.handle, float(t), C.c_void_p(out.data_ptr())))
+        return out
+
+    def norms(self, a: torch.Tensor, b: torch.Tensor) -> Tuple[float, float]:
+        assert a.dtype == torch.float64 and b.dtype == torch.float64
+        assert a.numel() >= self.plan.fine_nodes and b.numel() >= self.plan.fine_nodes
+        res = (C.c_double * 2)()
+        B.check(B.lib().sgw_norms(self.handle, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), res))
+        return res[0], res[1]
+
+    def query(self) -> Tuple[float, int]:
+        t, n = C.c_double(), C.c_int64()
+        B.check(B.lib().sgw_query(self.handle, C.byref(t), C.byref(n)))
+        return t.value, n.value
+
+    # --- views of the caller-owned state
+    def state_copy(self, which: int = 0) -> torch.Tensor:
+        """Copy ``which`` (0 = u^n) of every component grid, back to back in plan order."""
+        esz = 8 if self.real == torch.float64 else 4
+        copy_bytes = self.plan.state_bytes // 3
+        raw = self.state[which * copy_bytes: which * copy_bytes + self.plan.total_nodes * esz]
+        return raw.view(self.real)
+
+    def grid(self, g: int) -> torch.Tensor:
+        info = self.plan.grids[g]
+        n = 1
+        for s in info["shape"]:
+            n *= s
+        return self.state_copy()[info["offset"]: info["offset"] + n]
+
+    def solve(self, mode: int = B.RUN_GRAPH, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self.restrict()
+        self.advance(mode=mode)
+        return self.prolongate_combine(out)
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            B.lib().sgw_solver_free(h)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many solves advanced together (sgw_batch_*): one graph launch per step."""
+
+    def __init__(self, max_solvers: int, precision: int, hbm_budget: int, max_items: int = 1 << 20,
+                 device: str = "cuda", stream: Optional[torch.cuda.Stream] = None):
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = B.lib().sgw_batch_scratch_bytes(max_solvers, max_items)
+        self.scratch = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        B.check(B.lib().sgw_batch_create(max_solvers, precision, int(hbm_budget), _stream_handle(self.stream),
+                                         C.c_void_p(self.scratch.data_ptr()), int(nbytes), C.byref(h)))
+        self.handle = h
+        self.max_solvers = max_solvers
+        self.slots = {}
+
+    def admit(self, solver: Solver, t_final: Optional[float] = None) -> int:
+        slot = C.c_int32()
+        B.check(B.lib().sgw_batch_admit(self.handle, solver.handle,
+                                        solver.problem.T if t_final is None else t_final, C.byref(slot)))
+        self.slots[slot.value] = solver
+        return slot.value
+
+    def try_admit(self, solver: Solver, t_final: Optional[float] = None) -> Optional[int]:
+        try:
+            return self.admit(solver, t_final)
+        except B.SgwError as e:
+            if e.status == -3:
+                return None
+            raise
+
+    def step(self, nsteps: int = 1):
+        B.check(B.lib().sgw_batch_step(self.handle, nsteps))
+
+    def poll(self):
+        buf = (C.c_int32 * self.max_solvers)()
+        n = C.c_int32()
+        B.check(B.lib().sgw_batch_poll(self.handle, buf, C.byref(n)))
+        return list(buf[:n.value])
+
+    def release(self, slot: int) -> Solver:
+        B.check(B.lib().sgw_batch_release(self.handle, slot))
+        return self.slots.pop(slot)
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            B.lib().sgw_batch_free(h)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

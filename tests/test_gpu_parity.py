@@ -1,0 +1,243 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+FP64 runs must match the oracle within 1e-11 max-abs on every component grid
+and on the combined solution.  FP32-sweep runs report their L1/Linf error
+against the FP64 oracle and must stay within the stated bound.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import sgw_inputs as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _lib():
+    import torch
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.solver import Solver, Batch
+    return torch, B, Solver, Batch
+
+
+def _announce(what):
+    print(f"\n[gpu] {what}", flush=True)
+
+
+def gpu_solve(pb, mode=2, **kw):
+    torch, B, Solver, _ = _lib()
+    s = Solver(pb, **kw)
+    s.restrict()
+    s.advance(mode=mode)
+    U = s.prolongate_combine()
+    t, steps = s.query()
+    state = s.state_copy().double().cpu().numpy().copy()
+    return s, state, U, t, steps
+
+
+def oracle_solve(pb):
+    st = O.restrict(pb)
+    stats = O.evolve(pb, st)
+    U = O.prolong_combine(pb, st)
+    return st, U, stats
+
+
+def _check_fp64(pb, mode=2, tol=TOL64, **kw):
+    _announce(f"{pb.name} d={pb.d} nr={pb.nr} nl={pb.nl} T={pb.T:.6g} mode={mode} kw={kw}")
+    pb = pb.replace(precision=W.PREC_FP64)
+    s, st_g, U_g, t_g, steps_g = gpu_solve(pb, mode, **kw)
+    st_o, U_o, stats = oracle_solve(pb)
+    assert steps_g == stats["steps"]
+    assert abs(t_g - stats["t"]) < 1e-14
+    assert np.max(np.abs(st_g - st_o)) <= tol
+    U_g = U_g.cpu().numpy()
+    assert np.max(np.abs(U_g - U_o)) <= tol
+    return s, U_g, U_o, stats
+
+
+# --------------------------------------------------------------------------- small, full oracle
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_c1_full_size_all_modes(mode):
+    _check_fp64(W.c1_advection_2d(), mode=mode)
+
+
+SMALL = [
+    ("c2_smooth_nl3", lambda: W.c2_burgers_2d(nl=3, T=0.5 / math.pi ** 2)),
+    ("c2_steep_nl3", lambda: W.c2_burgers_2d(nl=3, T=1.5 / math.pi ** 2)),
+    ("c2_shock_nl3", lambda: W.c2_burgers_2d(nl=3, T=0.30)),
+    ("c3_nl3", lambda: W.c3_advection_3d(nl=3)),
+    ("c3_nr5_ragged", lambda: W.c3_advection_3d(nr=5, nl=2, T=0.3)),
+    ("c3_nr6_burgers", lambda: W.c3_advection_3d(nr=6, nl=2, T=0.2).replace(
+        flux=W.FLUX_BURGERS, flux_params=(), ic_params=(0.3, 0.6, math.pi, 0.4))),
+    ("c4_nl2", lambda: W.c4_vlasov_4d(nl=2, T=0.5)),
+    ("single_grid_3d", lambda: W.c3_advection_3d(nr=16, nl=0, T=0.25)),
+    ("one_dim_burgers", lambda: W.Problem(d=1, lo=(-1.0,), hi=(1.0,), flux=W.FLUX_BURGERS, flux_params=(),
+                                          ic=W.IC_SINE, ic_params=(0.2, 0.8, math.pi, 0.0), nr=12, nl=4,
+                                          T=0.4)),
+    ("linear_lagrange_ex1", lambda: W.paper_example1(40, nr=10, nl=2)),
+    ("pow53_ex3a", lambda: W.paper_example3a(40, nr=10, nl=2)),
+    ("negative_speed", lambda: W.c3_advection_3d(nl=2, T=0.3).replace(flux_params=(-1.0, 0.5, -0.25))),
+]
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+def test_small_configs_fp64(name, make):
+    _check_fp64(make())
+
+
+def test_boxes_smaller_than_the_automatic_choice():
+    # several boxes per grid, halos in every direction, odd box extents
+    _check_fp64(W.c3_advection_3d(nr=6, nl=2, T=0.2), box=[3, 3, 3])
+    _check_fp64(W.c2_burgers_2d(nl=3, T=0.1), box=[4, 4], fine_tile=[8, 4])
+
+
+def test_paper_sparse_weno_row_on_gpu():
+    # Table ex3aweno, sparse grid with WENO prolongation, N_r = 10, N_L = 3 (N_h = 80)
+    pb = W.paper_example3a(80, nr=10, nl=3)
+    s, U_g, U_o, stats = _check_fp64(pb)
+    torch, *_ = _lib()
+    ex = s.exact(stats["t"])
+    l1, li = s.norms(torch.from_numpy(U_g).cuda(), ex)
+    assert l1 == pytest.approx(7.1354e-05, rel=2e-4)
+    assert li == pytest.approx(5.4916e-04, rel=2e-4)
+
+
+def test_exact_and_norms_match_oracle():
+    torch, *_ = _lib()
+    for pb in (W.c2_burgers_2d(nl=3, T=0.1, precision=0), W.c3_advection_3d(nl=2, T=0.4, precision=0),
+               W.c4_vlasov_4d(nl=1, T=0.3, precision=0)):
+        _announce(f"exact {pb.name}")
+        s, st, U, t, steps = gpu_solve(pb)
+        ex_g = s.exact(t)
+        ex_o = O.exact_fine(pb, t)
+        assert np.max(np.abs(ex_g.cpu().numpy() - ex_o)) < 1e-13
+        l1g, lig = s.norms(U, ex_g)
+        l1o, lio = O.norms(U.cpu().numpy(), ex_o)
+        assert l1g == pytest.approx(l1o, rel=1e-12, abs=1e-300)
+        assert lig == pytest.approx(lio, rel=1e-12, abs=1e-300)
+
+
+# --------------------------------------------------------------------------- benchmark workload (2D Burgers)
+
+@pytest.mark.parametrize("T", [0.5 / math.pi ** 2, 1.5 / math.pi ** 2])
+def test_c2_full_size(T):
+    pb = W.c2_burgers_2d(T=T)
+    _check_fp64(pb)
+    # FP32 sweeps, FP64 combination, as benchmarked: error against the FP64 oracle
+    _announce(f"c2 fp32 T={T}")
+    s, st32, U32, t32, steps32 = gpu_solve(pb.replace(precision=W.PREC_FP32))
+    st_o, U_o, stats = oracle_solve(pb.replace(precision=W.PREC_FP64))
+    e = np.abs(U32.cpu().numpy() - U_o)
+    assert e.mean() < 2e-6 and e.max() < 2e-5, (e.mean(), e.max())
+
+
+def test_fp32_errors_are_reported_and_bounded():
+    for pb in (W.c1_advection_2d(), W.c3_advection_3d(nl=3), W.c4_vlasov_4d(nl=2, T=0.5)):
+        _announce(f"fp32 {pb.name}")
+        s, st, U, t, steps = gpu_solve(pb.replace(precision=W.PREC_FP32))
+        st_o, U_o, stats = oracle_solve(pb.replace(precision=W.PREC_FP64))
+        scale = max(1.0, np.max(np.abs(U_o)))
+        e = np.abs(U.cpu().numpy() - U_o)
+        print(f"  {pb.name}: fp32 L1 {e.mean():.3e} Linf {e.max():.3e}")
+        assert e.max() < 5e-5 * scale
+
+
+# --------------------------------------------------------------------------- full sizes, sampled
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"oracle_{name}_full.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name,make", [("c3", lambda: W.c3_advection_3d(precision=0)),
+                                       ("c4", lambda: W.c4_vlasov_4d(precision=0))])
+def test_full_size_sampled(name, make):
+    gd = _golden(name)
+    pb = make()
+    assert gd["eps_flux"] == pb.eps_flux and gd["nl"] == pb.nl and gd["nr"] == pb.nr
+    _announce(f"full {name}")
+    s, st, U, t, steps = gpu_solve(pb)
+    assert steps == gd["steps"]
+    for g in gd["grids"]:
+        vals = st[g["offset"] + np.array(g["idx"])]
+        assert np.max(np.abs(vals - np.array(g["val"]))) <= TOL64
+        n = int(np.prod(g["shape"]))
+        assert abs(st[g["offset"]:g["offset"] + n].sum() - g["sum"]) <= TOL64 * n
+    J = np.array(gd["fine_J"])
+    N = pb.n_fine
+    flat = sum(J[:, k] * N ** k for k in range(pb.d))
+    Ug = U.cpu().numpy()[flat]
+    assert np.max(np.abs(Ug - np.array(gd["fine_val"]))) <= TOL64
+    ex = s.exact(t).cpu().numpy()[flat]
+    assert np.max(np.abs(ex - np.array(gd["fine_exact"]))) < 1e-13
+
+
+# --------------------------------------------------------------------------- batching and determinism
+
+def test_batched_results_equal_solo_results_bitwise():
+    torch, B, Solver, Batch = _lib()
+    rng = np.random.default_rng(5)
+    probs = [W.randomized(f, nl, rng, precision=W.PREC_FP32) for f, nl in
+             [(1, 3), (2, 3), (3, 2), (4, 2), (2, 4), (3, 3)]]
+    probs = [p.replace(T=min(p.T, 0.2)) for p in probs]
+    solo = []
+    for p in probs:
+        _announce(f"solo {p.name} nl={p.nl}")
+        s = Solver(p)
+        solo.append(s.solve(mode=B.RUN_GRAPH).cpu().numpy())
+    _announce("batch")
+    batch = Batch(max_solvers=8, precision=B.FP32_SWEEP, hbm_budget=1 << 34)
+    solvers = []
+    for p in probs:
+        s = Solver(p)
+        s.restrict()
+        batch.admit(s)
+        solvers.append(s)
+    done = set()
+    for _ in range(400):
+        batch.step(8)
+        done |= set(batch.poll())
+        if len(done) == len(probs):
+            break
+    assert len(done) == len(probs)
+    for s, ref in zip(solvers, solo):
+        U = s.prolongate_combine().cpu().numpy()
+        assert np.array_equal(U, ref)
+    for slot in list(batch.slots):
+        batch.release(slot)
+
+
+def test_repeat_runs_are_bitwise_identical():
+    pb = W.c2_burgers_2d(nl=4, T=0.1, precision=W.PREC_FP64)
+    a = gpu_solve(pb)[2].cpu().numpy()
+    b = gpu_solve(pb)[2].cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_non_finite_wave_speed_is_reported():
+    torch, B, Solver, _ = _lib()
+    pb = W.c2_burgers_2d(nl=2, T=0.05).replace(ic_params=(float("nan"), 0.7, math.pi, 0.0))
+    s = Solver(pb)
+    s.restrict()
+    with pytest.raises(B.SgwError) as e:
+        s.advance()
+    assert e.value.status == -4
+
+
+def test_advance_before_restrict_is_refused():
+    torch, B, Solver, _ = _lib()
+    s = Solver(W.c1_advection_2d())
+    with pytest.raises(B.SgwError) as e:
+        s.advance()
+    assert e.value.status == -6

@@ -1,0 +1,110 @@
+"""Host-side checks of libsgweno that need no GPU: exports, planner, validation."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import sgw_inputs as W
+from paper_2007_10196_amd import binding as B
+from paper_2007_10196_amd.solver import Plan
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sgweno.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return set(re.findall(r"\b(sgw_[a-z_0-9]+)\s*\(", src))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 20
+    L = ctypes.CDLL(B.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert not missing, missing
+    assert names == set(B.EXPORTED)
+
+
+@pytest.mark.parametrize("d,nl", [(1, 3), (2, 0), (2, 3), (2, 5), (3, 5), (4, 4), (4, 5)])
+def test_plan_grid_set_matches_oracle(d, nl):
+    if d == 4:
+        pb = W.c4_vlasov_4d(nl=nl)
+    elif d == 3:
+        pb = W.c3_advection_3d(nl=nl)
+    elif d == 2:
+        pb = W.c2_burgers_2d(nl=nl)
+    else:
+        pb = W.Problem(d=1, lo=(0.0,), hi=(1.0,), flux=W.FLUX_ADVECTION, flux_params=(1.0,), ic=W.IC_SINE,
+                       ic_params=(0, 1, 2 * np.pi, 0), nr=8, nl=nl, T=0.1)
+    plan = Plan(pb)
+    lv, cf = O.grid_set(d, nl)
+    assert plan.num_grids == len(lv)
+    off = 0
+    for g, info in enumerate(plan.grids):
+        assert info["level"] == tuple(int(x) for x in lv[g])
+        assert info["coef"] == int(cf[g])
+        assert info["shape"] == tuple(pb.nr << int(x) for x in lv[g])
+        assert info["offset"] == off
+        off += int(np.prod(info["shape"]))
+        for n, t in zip(info["shape"], info["box"]):
+            assert n % t == 0
+        assert int(np.prod(info["box"])) <= 2048
+    assert plan.total_nodes == off == O.total_nodes(pb)
+    assert plan.fine_nodes == pb.n_fine ** d
+    esz = 8 if pb.precision == W.PREC_FP64 else 4
+    assert plan.state_bytes >= 3 * off * esz
+
+
+@pytest.mark.parametrize("nr", [4, 5, 6, 7, 10, 12])
+def test_plan_handles_non_power_of_two_roots(nr):
+    pb = W.c3_advection_3d(nr=nr, nl=3)
+    plan = Plan(pb)
+    for info in plan.grids:
+        for n, t in zip(info["shape"], info["box"]):
+            assert n % t == 0
+
+
+def _expect_status(pb, status, **kw):
+    with pytest.raises(B.SgwError) as e:
+        Plan(pb, **kw)
+    assert e.value.status == status
+
+
+def test_plan_rejects_invalid_arguments():
+    good = W.c1_advection_2d()
+    _expect_status(good.replace(d=5, lo=(0,) * 4, hi=(1,) * 4), -1)
+    _expect_status(good.replace(d=0), -1)
+    _expect_status(good.replace(nr=3), -1)
+    _expect_status(good.replace(nl=13), -1)
+    _expect_status(good.replace(cfl=0.0), -1)
+    _expect_status(good.replace(cfl=2.0), -1)
+    _expect_status(good.replace(eps_flux=0.0), -1)
+    _expect_status(good.replace(hi=(0.0, 2.0)), -1)
+    _expect_status(W.c4_vlasov_4d().replace(d=3, lo=(0,) * 3, hi=(1,) * 3), -1)
+    _expect_status(good, -2, box=[3, 3])          # 3 does not divide 4 << l
+    _expect_status(good, -2, fine_tile=[5, 5])    # 5 does not divide 32
+    _expect_status(good, -1, box_target=32)
+
+
+def test_error_strings():
+    L = B.lib()
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert L.sgw_status_string(s)
+    try:
+        Plan(W.c1_advection_2d().replace(nr=2))
+    except B.SgwError:
+        pass
+    assert b"root_cells" in L.sgw_last_error()
+
+
+def test_footprints_scale_with_precision():
+    p64 = Plan(W.c3_advection_3d(precision=W.PREC_FP64))
+    p32 = Plan(W.c3_advection_3d(precision=W.PREC_FP32))
+    assert p64.total_nodes == p32.total_nodes == 507904
+    assert p64.state_bytes >= 2 * p32.state_bytes - 1024
+    assert p64.fine_bytes == 8 * 256 ** 3
