@@ -1,0 +1,202 @@
+#!/usr/bin/env python
+"""Benchmark of the sparse-grid WENO5 hot path on one MI355X.
+
+One step = the whole method over one batch of synthetic solves of the 2D
+Burgers workload (u_t + (u^2/2)_x + (u^2/2)_y = 0 on [-1,1]^2, u0 = 0.3 + A
+sin(pi(x+y) + phi) with seeded A, phi; root grid 8x8, finest level 5 (256x256),
+CFL 0.5, T = 1.5/pi^2): restriction, the shared-dt TVD-RK3 march of all 11
+component grids of every solve (batched: one graph per time step, one
+persistent stage launch over all boxes), WENO5 prolongation + FP64 combination,
+and the L1/Linf norms against the exact solution.  Sweeps run in FP32, the
+combination and norms in FP64.
+
+Prints one JSON line.  Extra keys: the plain per-grid FP64 method on the same
+workload (equal-L1 comparison), the event-timed stage kernel against its
+roofline, the FP64 oracle timed on the host, and serving latencies.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import sgw_inputs as W  # noqa: E402
+
+METRIC = "sparse-grid WENO5 cell-updates/s vs plain at equal L1 err; p50/p99 solve latency"
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+T_FINAL = 1.5 / math.pi ** 2
+
+
+def flops_per_node_stage(d: int, stage: int) -> int:
+    """Algorithmic flops of one RK stage at one node (counted from the paper's formulas):
+    per direction two WENO5 reconstructions of 70 flops each (3 candidates x 5, 3 smoothness
+    indicators x 12, 3 weights x 3, normalisation 5, combination 5), 6 for the flux and its
+    LF split, 3 for the difference of eq. (2.9); plus the RK combination (2, 5, 5)."""
+    return d * (2 * 70 + 6 + 3) + (2, 5, 5)[stage]
+
+
+def make_problems(n, seed=2007_10196):
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng(seed + 1 + i)
+        p = W.randomized(2, 5, rng, precision=W.PREC_FP32).replace(T=T_FINAL)
+        out.append(p)
+    return out
+
+
+def run_batch_step(torch, batch, solvers, outs, exacts, poll_every=16):
+    for s in solvers:
+        s.restrict()
+    for s in solvers:
+        batch.admit(s)
+    done = set()
+    while len(done) < len(solvers):
+        batch.step(poll_every)
+        done |= set(batch.poll())
+    for s, U in zip(solvers, outs):
+        s.prolongate_combine(U)
+    norms = [s.norms(U, E) for s, U, E in zip(solvers, outs, exacts)]
+    for slot in list(batch.slots):
+        batch.release(slot)
+    return norms
+
+
+def cpu_baseline(budget_s=12.0):
+    import oracle as O
+    probs = make_problems(64)
+    t0 = time.perf_counter()
+    cells = 0
+    n = 0
+    for p in probs:
+        pb = p.replace(precision=W.PREC_FP64)
+        _, _, stats = O.solve(pb)
+        cells += stats["steps"] * O.total_nodes(pb)
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": cells / dt, "unit": "cell-updates/s", "cores": O.max_threads(), "kind": "oracle",
+            "sample": f"{n} solves of the same 2D Burgers workload (FP64, full method incl. prolongation), "
+                      f"{dt:.1f} s wall, OpenMP over component grids"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--solves", type=int, default=256, help="solves per step (batch size)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--stage-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.solver import Batch, Solver
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    probs = make_problems(args.solves)
+    solvers = [Solver(p, device="cuda:0") for p in probs]
+    nodes = solvers[0].plan.total_nodes
+    fine = solvers[0].plan.fine_nodes
+    outs = [torch.empty(fine, dtype=torch.float64, device=dev) for _ in solvers]
+    exacts = [s.exact(T_FINAL) for s in solvers]
+    budget = sum(s.plan.footprint for s in solvers) + (1 << 30)
+    batch = Batch(max_solvers=len(solvers), precision=B.FP32_SWEEP, hbm_budget=budget,
+                  max_items=sum(len(s.plan.grids) * 64 for s in solvers))
+    print(f"[bench] {len(solvers)} solves x {nodes} component nodes, warmup {args.warmup}", file=sys.stderr,
+          flush=True)
+
+    for _ in range(args.warmup):
+        run_batch_step(torch, batch, solvers, outs, exacts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    norms = None
+    for k in range(args.steps):
+        norms = run_batch_step(torch, batch, solvers, outs, exacts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    steps_each = [s.query()[1] for s in solvers]
+    cells_per_step = sum(n * nodes for n in steps_each)
+    ms_per_step = elapsed / args.steps * 1e3
+    value = cells_per_step / (elapsed / args.steps)
+    l1s = np.array([n[0] for n in norms])
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.3e} cell-updates/s",
+          file=sys.stderr, flush=True)
+
+    # ---- the stage kernel alone, same launch shape, HIP events on the batch stream
+    for s in solvers:
+        s.restrict()
+        batch.admit(s)
+    batch.step(1)
+    st = batch.stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    batch.launch_stage(0, 2)
+    ev0.record(st)
+    batch.launch_stage(0, args.stage_reps)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    stage_ms = ev0.elapsed_time(ev1) / args.stage_reps
+    info = batch.info()
+    for slot in list(batch.slots):
+        batch.release(slot)
+    stage_flops = info["nodes"] * flops_per_node_stage(2, 0)
+    achieved = stage_flops / (stage_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "kernel": "stage_kernel<float> (RK stage 1)", "avg_launch_us": stage_ms * 1e3,
+                "flops_per_launch": stage_flops, "boxes_per_launch": info["boxes"],
+                "algorithmic_bytes_per_launch": info["nodes"] * 4 * 2,
+                "achieved_algorithmic_GBs": info["nodes"] * 4 * 2 / (stage_ms * 1e-3) / 1e9}
+
+    # ---- plain per-grid FP64 method on the first solve: the equal-L1 reference
+    plain = None
+    if not args.no_plain:
+        p64 = probs[0].replace(precision=W.PREC_FP64)
+        sp = Solver(p64, device="cuda:0")
+        Up = torch.empty(fine, dtype=torch.float64, device=dev)
+        Ep = sp.exact(T_FINAL)
+        for rep in range(2):
+            torch.cuda.synchronize()
+            tp = time.perf_counter()
+            sp.restrict()
+            sp.advance(mode=B.RUN_PLAIN)
+            sp.prolongate_combine(Up)
+            l1p, lip = sp.norms(Up, Ep)
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - tp
+        stp = sp.query()[1]
+        plain = {"value": stp * nodes / tp, "unit": "cell-updates/s", "mode": "plain: one launch per grid per "
+                 "RK stage, no graph, FP64", "ms_per_solve": tp * 1e3, "l1": l1p, "linf": lip,
+                 "speedup_of_value": value / (stp * nodes / tp),
+                 "equal_l1": abs(l1s[0] - l1p) <= 0.01 * l1p, "l1_batched_fp32_same_solve": float(l1s[0])}
+
+    cpu = None if args.no_cpu else cpu_baseline()
+
+    out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "2D Burgers u0=0.3+A sin(pi(x+y)+phi), [-1,1]^2 periodic, root 8x8, finest "
+                                  "level 5 (256x256), 11 component grids, CFL 0.5, T=1.5/pi^2; FP32 sweeps, FP64 "
+                                  "combination", "solves_per_step": len(solvers), "component_nodes": nodes,
+                      "mode": "batched: one HIP graph per time step, persistent fused WENO5+RK3 stage launch"},
+           "l1_mean": float(l1s.mean()), "l1_max": float(l1s.max()),
+           "roofline": roofline, "cpu_baseline": cpu, "plain": plain}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -196,6 +196,14 @@ sgw_status sgw_batch_step(sgw_batch_t* batch, int32_t nsteps);
 sgw_status sgw_batch_poll(sgw_batch_t* batch, int32_t* done_slots, int32_t* n_done);
 /* Remove a solver from the batch; its budget and slot become free. */
 sgw_status sgw_batch_release(sgw_batch_t* batch, int32_t slot);
+/* Measurement hook: enqueue reps launches of RK stage `stage` (0..2) over the
+ * batch's boxes, outside any graph, with the same launch shape as a step
+ * (callers time them with events on the batch stream).  Stage 0 writes only the
+ * first stage buffer, so repeating it leaves u^n unchanged; the solves' wave
+ * speed slots are disturbed, so re-restrict before trusting later results. */
+sgw_status sgw_batch_launch_stage(sgw_batch_t* batch, int32_t stage, int32_t reps);
+/* Number of stage boxes currently in the batch. */
+sgw_status sgw_batch_info(const sgw_batch_t* batch, int32_t* active_solvers, int64_t* boxes, int64_t* nodes);
 
 /* ---------------------------------------------------------------- errors */
 const char* sgw_status_string(sgw_status status);

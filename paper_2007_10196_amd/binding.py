@@ -72,6 +72,8 @@ _SIGS = {
     "sgw_batch_step": (C.c_int32, [C.c_void_p, C.c_int32]),
     "sgw_batch_poll": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "sgw_batch_release": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "sgw_batch_launch_stage": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
+    "sgw_batch_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "sgw_status_string": (C.c_char_p, [C.c_int32]),
     "sgw_last_error": (C.c_char_p, []),
 }

@@ -235,6 +235,36 @@ extern "C" sgw_status sgw_batch_poll(sgw_batch_t* b, int32_t* done_slots, int32_
     return SGW_OK;
 }
 
+extern "C" sgw_status sgw_batch_launch_stage(sgw_batch_t* b, int32_t stage, int32_t reps)
+{
+    if (!b) return sgw_fail(SGW_ERR_INVALID_ARG, "null batch");
+    if (stage < 0 || stage > 2 || reps < 0) return sgw_fail(SGW_ERR_INVALID_ARG, "stage %d reps %d", stage, reps);
+    sgw_status rc = batch_sync(b);
+    if (rc != SGW_OK) return rc;
+    for (int i = 0; i < reps; i++) {
+        hipError_t e = launch_stage_dev_count(b->items_d, b->nitems_d, b->blocks, stage, b->precision, b->lds, b->stream);
+        if (e != hipSuccess) return sgw_hip_fail(e, "stage launch");
+    }
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_batch_info(const sgw_batch_t* b, int32_t* active, int64_t* boxes, int64_t* nodes)
+{
+    if (!b) return sgw_fail(SGW_ERR_INVALID_ARG, "null batch");
+    int n = 0;
+    int64_t bx = 0, nd = 0;
+    for (auto* s : b->slots)
+        if (s) {
+            n++;
+            bx += (int64_t)s->items_h.size();
+            nd += s->plan->total_nodes;
+        }
+    if (active) *active = n;
+    if (boxes) *boxes = bx;
+    if (nodes) *nodes = nd;
+    return SGW_OK;
+}
+
 extern "C" sgw_status sgw_batch_release(sgw_batch_t* b, int32_t slot)
 {
     if (!b) return sgw_fail(SGW_ERR_INVALID_ARG, "null batch");

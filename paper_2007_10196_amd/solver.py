@@ -187,6 +187,14 @@ class Batch:
         B.check(B.lib().sgw_batch_poll(self.handle, buf, C.byref(n)))
         return list(buf[:n.value])
 
+    def launch_stage(self, stage: int, reps: int = 1):
+        B.check(B.lib().sgw_batch_launch_stage(self.handle, stage, reps))
+
+    def info(self):
+        a, b, n = C.c_int32(), C.c_int64(), C.c_int64()
+        B.check(B.lib().sgw_batch_info(self.handle, C.byref(a), C.byref(b), C.byref(n)))
+        return dict(active=a.value, boxes=b.value, nodes=n.value)
+
     def release(self, slot: int) -> Solver:
         B.check(B.lib().sgw_batch_release(self.handle, slot))
         return self.slots.pop(slot)
