@@ -82,33 +82,39 @@ static int64_t binom(int n, int k)
 static void fill_box_geometry(GridDev& g, int precision)
 {
     (void)precision;
-    int core = 1, pad = 1;
+    int core = 1;
     for (int k = 0; k < SGW_MAX_DIM; k++) {
         if (k >= g.d) {
             g.t[k] = 1;
             g.halo[k] = 0;
             g.ntile[k] = 1;
-            g.P[k] = 1;
             continue;
         }
         g.halo[k] = (g.t[k] < g.n[k]) ? 3 : 0;
         g.ntile[k] = g.n[k] / g.t[k];
-        g.P[k] = g.t[k] + 2 * g.halo[k];
     }
     for (int k = 0; k < SGW_MAX_DIM; k++) {
         g.CS[k] = core;
-        g.PS[k] = pad;
         core *= g.t[k];
-        pad *= g.P[k];
     }
     g.core_total = core;
+    int pad = core;
+    for (int k = 0; k < SGW_MAX_DIM; k++) {
+        g.slab_lo[k] = g.slab_hi[k] = 0;
+        if (k < g.d && g.halo[k]) {
+            g.slab_lo[k] = pad;
+            pad += 3 * (core / g.t[k]);
+            g.slab_hi[k] = pad;
+            pad += 3 * (core / g.t[k]);
+        }
+    }
     g.pad_total = pad;
     g.nbox = 1;
     for (int k = 0; k < g.d; k++) g.nbox *= g.ntile[k];
     for (int k = 0; k < SGW_MAX_DIM; k++) {
         g.I[k] = g.t[k] + (g.halo[k] ? 1 : 0);
         g.flux_total[k] = (k < g.d) ? core / g.t[k] * g.I[k] : 0;
-        g.fd_P[k] = make_fastdiv((uint32_t)g.P[k]);
+        g.fd_CS[k] = make_fastdiv((uint32_t)g.CS[k]);
         g.fd_t[k] = make_fastdiv((uint32_t)g.t[k]);
         g.fd_I[k] = make_fastdiv((uint32_t)g.I[k]);
         g.fd_CSt[k] = make_fastdiv((uint32_t)(g.CS[k] * g.t[k]));
@@ -151,7 +157,7 @@ static void choose_box(GridDev& g, int precision, int target, size_t lds_cap)
                     if (stage_lds_bytes(g, precision) > lds_cap) continue;
                     double flux = 0.0;
                     for (int k = 0; k < g.d; k++) flux += (double)g.flux_total[k];
-                    const double row_bytes = g.P[0] * rs;
+                    const double row_bytes = g.t[0] * rs;
                     const double load = g.pad_total * (row_bytes < 64.0 ? 64.0 / row_bytes : 1.0);
                     const double cost = (load + 25.0 * flux) / (double)core + 2000.0 / (double)core;
                     if (cost < best - 1e-12) {

@@ -97,24 +97,49 @@ __device__ __forceinline__ void stage_box(const GridDev* __restrict__ g, int box
     // the wave-speed slot the next stage reads is cleared by the stage before it
     if (g->dyn_alpha && box == 0 && tid == 0) g->alpha[(stage + 2) % 3] = 0ull;
 
-    // ---- stage the padded box (cross-shaped: at most one direction in the halo)
+    // ---- stage the core box, then the halo slabs (periodic wrap on the global index)
+    const int core_total = g->core_total;
     const int pad_total = g->pad_total;
     for (int e = tid; e < pad_total; e += SGW_BLOCK) {
-        uint32_t r = (uint32_t)e;
-        int gi = 0, outside = 0;
+        // region: -1 core, else (direction, side) of the slab that holds e
+        int kk = -1, side = 0, local = e;
+        if (e >= core_total) {
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+                if (g->halo[k]) {
+                    if (e >= g->slab_lo[k] && e < g->slab_hi[k]) {
+                        kk = k;
+                        side = 0;
+                        local = e - g->slab_lo[k];
+                    } else if (e >= g->slab_hi[k] && e < g->slab_hi[k] + (g->slab_hi[k] - g->slab_lo[k])) {
+                        kk = k;
+                        side = 1;
+                        local = e - g->slab_hi[k];
+                    }
+                }
+            }
+        }
+        uint32_t r = (uint32_t)local;
+        int gi = 0;
 #pragma unroll
         for (int k = 0; k < D; k++) {
-            const uint32_t q = fdiv(r, g->fd_P[k]);
-            const int c = (int)(r - q * (uint32_t)g->P[k]);
-            r = q;
-            const int hk = g->halo[k];
-            int x = o[k] + c - hk;
+            int x;
+            if (k == kk) {
+                const uint32_t q = r / 3u;
+                const int c = (int)(r - 3u * q);
+                r = q;
+                x = side ? o[k] + g->t[k] + c : o[k] - 3 + c;
+            } else {
+                const uint32_t q = fdiv(r, g->fd_t[k]);
+                const int c = (int)(r - q * (uint32_t)g->t[k]);
+                r = q;
+                x = o[k] + c;
+            }
             x += (x < 0) ? g->n[k] : 0;
             x -= (x >= g->n[k]) ? g->n[k] : 0;
-            outside += (c < hk) | (c >= hk + g->t[k]);
             gi += x * g->stride[k];
         }
-        if (outside <= 1) su[e] = in[gi];
+        su[e] = in[gi];
     }
     __syncthreads();
 
@@ -124,7 +149,6 @@ __device__ __forceinline__ void stage_box(const GridDev* __restrict__ g, int box
 
     const Real eps = (Real)g->eps;
     const int linear = g->linear;
-    const int core_total = g->core_total;
     Real dyn_alpha = Real(0);
     if (g->dyn_alpha) dyn_alpha = (Real)__longlong_as_double((long long)g->alpha[stage]);
 
@@ -132,38 +156,42 @@ __device__ __forceinline__ void stage_box(const GridDev* __restrict__ g, int box
     for (int k = 0; k < D; k++) {
         const int hf = g->halo[k] ? 1 : 0;
         const int tk = g->t[k];
-        const int PSk = g->PS[k];
+        const int CSk = g->CS[k];
+        const int Ik = g->I[k];
+        const int slo = g->slab_lo[k], shi = g->slab_hi[k];
         const Real alpha = g->dyn_alpha ? dyn_alpha : (Real)g->alpha_c[k];
         const double* __restrict__ ctab = g->coef[k];
         const int csrc = g->coef_src[k];
         const Real cconst = (Real)g->lin_c[k];
-        // ---- interface fluxes of the box in direction k -> sf
+        // ---- interface fluxes of the box in direction k -> sf; interface index
+        //      f = inner + (i + hf) CS_k + outer CS_k I_k, inner over directions < k
         const int ftot = g->flux_total[k];
         for (int f = tid; f < ftot; f += SGW_BLOCK) {
-            uint32_t r = (uint32_t)f;
-            int base = 0, ck = 0, csrc_coord = 0;
-#pragma unroll
-            for (int j = 0; j < D; j++) {
-                const FastDiv& fd = (j == k) ? g->fd_I[j] : g->fd_t[j];
-                const uint32_t q = fdiv(r, fd);
-                const int c = (int)(r - q * fd.d);
-                r = q;
-                if (j == k) ck = c;
-                else base += (c + g->halo[j]) * g->PS[j];
-                if (j == csrc) csrc_coord = o[j] + c;
-            }
-            const int i = ck - hf; // the flux is at x_{i+1/2}
+            const uint32_t r1 = fdiv((uint32_t)f, g->fd_CS[k]);
+            const int inner = f - (int)r1 * CSk;
+            const uint32_t outer = fdiv(r1, g->fd_I[k]);
+            const int i = (int)(r1 - outer * (uint32_t)Ik) - hf; // the flux is at x_{i+1/2}
+            const int base_core = inner + (int)outer * CSk * tk;   // node with c_k = 0 on this line
+            const int base_slab = inner + (int)outer * 3 * CSk;
             Real v[6];
 #pragma unroll
             for (int m = 0; m < 6; m++) {
                 int p = i + m - 2;
+                int idx;
                 if (hf) {
-                    p += 3;
+                    idx = (p < 0) ? slo + base_slab + (p + 3) * CSk
+                                  : (p >= tk) ? shi + base_slab + (p - tk) * CSk : base_core + p * CSk;
                 } else {
                     p += (p < 0) ? tk : 0;
                     p -= (p >= tk) ? tk : 0;
+                    idx = base_core + p * CSk;
                 }
-                v[m] = su[base + p * PSk];
+                v[m] = su[idx];
+            }
+            int csrc_coord = 0;
+            if (csrc >= 0) {
+                const uint32_t q = fdiv((uint32_t)base_core, g->fd_CS[csrc]);
+                csrc_coord = o[csrc] + (int)(q - fdiv(q, g->fd_t[csrc]) * (uint32_t)g->t[csrc]);
             }
             Real pl[6], mi[6];
             if (g->flux == SGW_FLUX_BURGERS) {
@@ -189,8 +217,6 @@ __device__ __forceinline__ void stage_box(const GridDev* __restrict__ g, int box
         __syncthreads();
         // ---- flux differences of eq. (2.9) for the nodes this thread owns
         const Real ih = (Real)g->inv_h[k];
-        const int CSk = g->CS[k];
-        const int Ik = g->I[k];
 #pragma unroll
         for (int r = 0; r < SGW_MAXR; r++) {
             const int e = tid + r * SGW_BLOCK;
@@ -212,16 +238,15 @@ __device__ __forceinline__ void stage_box(const GridDev* __restrict__ g, int box
         const int e = tid + r * SGW_BLOCK;
         if (e < core_total) {
             uint32_t rr = (uint32_t)e;
-            int pidx = 0, gi = 0;
+            int gi = 0;
 #pragma unroll
             for (int k = 0; k < D; k++) {
                 const uint32_t q = fdiv(rr, g->fd_t[k]);
                 const int c = (int)(rr - q * (uint32_t)g->t[k]);
                 rr = q;
-                pidx += (c + g->halo[k]) * g->PS[k];
                 gi += (o[k] + c) * g->stride[k];
             }
-            const Real val = su[pidx] + dtr * acc[r];
+            const Real val = su[e] + dtr * acc[r];
             Real res;
             if (stage == 0) res = val;
             else if (stage == 1) res = Real(0.75) * u0[gi] + Real(0.25) * val;

@@ -38,7 +38,9 @@ struct ReqDev;
 
 // One component grid as seen by the stage kernel.  Box = the tile one
 // workgroup updates; t[k] divides n[k]; a box that does not span its grid in
-// direction k carries 3 halo nodes on each side in that direction.
+// direction k carries 3 halo nodes on each side in that direction.  LDS holds
+// the core box (row-major, strides CS) followed, for every such direction, by
+// a low and a high slab: the core box with extent 3 in direction k.
 struct alignas(64) GridDev {
     void* u;                         // u^n (also the output of stage 3)
     void* a;                         // output of stage 1
@@ -53,13 +55,13 @@ struct alignas(64) GridDev {
     int32_t t[SGW_MAX_DIM];
     int32_t halo[SGW_MAX_DIM];       // 3 or 0
     int32_t ntile[SGW_MAX_DIM];
-    int32_t P[SGW_MAX_DIM];          // padded box extents t + 2 halo
-    int32_t PS[SGW_MAX_DIM];         // padded strides
+    int32_t slab_lo[SGW_MAX_DIM];    // LDS offset of the low / high halo slab of direction k
+    int32_t slab_hi[SGW_MAX_DIM];
     int32_t CS[SGW_MAX_DIM];         // core strides
     int32_t I[SGW_MAX_DIM];          // interfaces per line in the box: t + (halo ? 1 : 0)
     int32_t flux_total[SGW_MAX_DIM]; // interfaces in the box per direction
     int32_t coef_src[SGW_MAX_DIM];   // direction whose node index selects the coefficient, -1: constant
-    FastDiv fd_P[SGW_MAX_DIM];
+    FastDiv fd_CS[SGW_MAX_DIM];
     FastDiv fd_t[SGW_MAX_DIM];
     FastDiv fd_I[SGW_MAX_DIM];
     FastDiv fd_CSt[SGW_MAX_DIM];     // CS[k] * t[k]
