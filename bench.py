@@ -117,6 +117,52 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes_per_copy": x.numel() * 4, "copies": 3}), flush=True)
 
 
+SERVING_N = 128
+
+
+def serving_run(capacity, box_target, n=None, load=0.7):
+    """Seeded Poisson stream mixing the 2D advection, 2D Burgers, 3D advection and 4D Vlasov
+    workloads at finest levels 2..5 (4D capped at 4), FP32 sweeps; the arrival rate is set so the
+    offered cell-updates/s are `load` x the measured batched capacity."""
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.serving import ServingLoop, latency_summary
+    from paper_2007_10196_amd.solver import Plan
+    n = n or SERVING_N
+    probe = W.serving_stream(n=n, rate_hz=1.0, max_level_by_family={4: 4})
+    work = []
+    for r in probe:
+        p = Plan(r.problem)
+        work.append(step_estimate_any(r.problem) * p.total_nodes)
+    rate = load * capacity / (sum(work) / len(work))
+    reqs = W.serving_stream(n=n, rate_hz=rate, max_level_by_family={4: 4})
+    loop = ServingLoop(precision=B.FP32_SWEEP, max_active=64, hbm_budget=96 << 30, steps_per_tick=8,
+                       box_target=box_target)
+    t0 = time.perf_counter()
+    res = loop.run(reqs)
+    wall = time.perf_counter() - t0
+    loop.close()
+    out = latency_summary(res)
+    out.update({"arrival_rate_hz": rate, "offered_load_of_capacity": load, "wall_s": wall,
+                "mix": "families 2D advection / 2D Burgers / 3D advection / 4D Vlasov, levels 2-5 (4D <= 4), "
+                       "seeded phases and amplitudes, FP32 sweeps + FP64 combination"})
+    print(f"[bench] serving {n} requests: p50 {out['p50_ms']:.1f} ms p99 {out['p99_ms']:.1f} ms",
+          file=sys.stderr, flush=True)
+    return out
+
+
+def step_estimate_any(pb):
+    """Steps of the shared-dt loop for any workload family (wave-speed bound at t = 0)."""
+    if pb.flux == W.FLUX_BURGERS:
+        return step_estimate(pb)
+    if pb.flux == W.FLUX_ADVECTION:
+        A = [abs(a) for a in pb.flux_params[:pb.d]]
+    else:
+        m = pb.d // 2
+        A = [max(abs(pb.lo[m + k]), abs(pb.hi[m + k])) for k in range(m)] + [abs(pb.flux_params[0])] * m
+    denom = sum(A[k] / ((pb.hi[k] - pb.lo[k]) / pb.n_fine) for k in range(pb.d))
+    return int(math.ceil(pb.T / (pb.cfl / denom)))
+
+
 def cpu_baseline(budget_s=15.0):
     import oracle as O
     probs = make_problems(512)
@@ -145,6 +191,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=20)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 1 GiB copy used to scale the HBM byte counters")
     args = ap.parse_args()
@@ -162,7 +210,13 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     probs = make_problems(args.solves)
-    solvers = [Solver(p, device="cuda:0") for p in probs]
+    # box shape for this batch (untimed): fastest of the candidate targets, cached in JSON
+    from paper_2007_10196_amd.autotune import tune_box_target
+    tune = tune_box_target(probs, B.FP32_SWEEP, reps=5)
+    box_target = int(tune["best"])
+    print(f"[bench] autotuned box target {box_target} ({'cached' if tune['cached'] else 'measured'})",
+          file=sys.stderr, flush=True)
+    solvers = [Solver(p, device="cuda:0", box_target=box_target) for p in probs]
     nodes = solvers[0].plan.total_nodes
     fine = solvers[0].plan.fine_nodes
     outs = [torch.empty(fine, dtype=torch.float64, device=dev) for _ in solvers]
@@ -237,6 +291,8 @@ def main():
                  "speedup_of_value": value / (stp * nodes / tp),
                  "equal_l1": bool(abs(l1s[0] - l1p) <= 0.01 * l1p), "l1_batched_fp32_same_solve": float(l1s[0])}
 
+    serving = None if args.no_serving else serving_run(value, box_target)
+
     cpu = None if args.no_cpu else cpu_baseline()
 
     out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -247,7 +303,8 @@ def main():
                                   "combination", "solves_per_step": len(solvers), "component_nodes": nodes,
                       "mode": "batched: one HIP graph per time step, persistent fused WENO5+RK3 stage launch"},
            "l1_mean": float(l1s.mean()), "l1_max": float(l1s.max()),
-           "roofline": roofline, "cpu_baseline": cpu, "plain": plain}
+           "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "latency": serving,
+           "autotune": {"box_target": box_target, "stage_us_by_target": tune["us"]}}
     print(json.dumps(out), flush=True)
 
 

@@ -1,0 +1,93 @@
+"""Box-shape tuner for the stage kernel.
+
+For a set of problems (one batch), every candidate box target (the largest box,
+in nodes, the planner's box search may pick for each component grid) is tried:
+the batch is restricted and admitted, one step is taken, and a few standalone
+stage launches are timed with HIP events on the batch stream.  The fastest
+target is returned and cached in a JSON file keyed by the batch's grid shapes
+and precision.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from typing import Dict, Iterable, Optional, Sequence
+
+import torch
+
+from .solver import Batch, Plan, Solver
+
+CANDIDATES = (256, 512, 1024, 2048)
+
+
+def default_cache_path() -> str:
+    return os.environ.get("SGW_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "sgweno", "tune.json"))
+
+
+def workload_key(problems: Sequence, precision: int) -> str:
+    shapes = sorted({(p.d, p.nr, p.nl, p.flux) for p in problems})
+    raw = json.dumps({"shapes": shapes, "n": len(problems), "precision": precision})
+    return hashlib.sha256(raw.encode()).hexdigest()[:16]
+
+
+def _load(path: str) -> Dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def time_stage(problems: Sequence, precision: int, box_target: int, reps: int = 10) -> float:
+    """Average microseconds of one stage launch over the whole batch."""
+    stream = torch.cuda.current_stream()
+    solvers = [Solver(p, box_target=box_target) for p in problems]
+    batch = Batch(max_solvers=len(solvers), precision=precision, hbm_budget=1 << 50,
+                  max_items=sum(s.plan.total_nodes // 64 + len(s.plan.grids) for s in solvers) + 16)
+    for s in solvers:
+        s.restrict()
+        batch.admit(s)
+    batch.step(1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    batch.launch_stage(0, 2)
+    e0.record(stream)
+    batch.launch_stage(0, reps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / reps * 1e3
+    for slot in list(batch.slots):
+        batch.release(slot)
+    batch.close()
+    for s in solvers:
+        s.close()
+    return us
+
+
+def tune_box_target(problems: Sequence, precision: int, candidates: Iterable[int] = CANDIDATES,
+                    cache_path: Optional[str] = None, reps: int = 10, force: bool = False) -> Dict:
+    """Pick the fastest box target for this batch; returns {"best": t, "us": {t: us}, "cached": bool}."""
+    path = cache_path or default_cache_path()
+    key = workload_key(problems, precision)
+    cache = _load(path)
+    if not force and key in cache:
+        rec = dict(cache[key])
+        rec["cached"] = True
+        return rec
+    times = {}
+    for t in candidates:
+        try:
+            times[int(t)] = time_stage(problems, precision, int(t), reps)
+        except Exception as e:  # a target no box satisfies for some grid
+            times[int(t)] = float("inf")
+            print(f"[autotune] target {t}: {e}", flush=True)
+    best = min(times, key=times.get)
+    rec = {"best": best, "us": times}
+    cache[key] = rec
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    with open(path + ".tmp", "w") as f:
+        json.dump(cache, f, indent=1)
+    os.replace(path + ".tmp", path)
+    out = dict(rec)
+    out["cached"] = False
+    return out

@@ -98,28 +98,57 @@ static void fill_box_geometry(GridDev& g, int precision)
         core *= g.t[k];
     }
     g.core_total = core;
-    int pad = core;
+    // LDS: core rows of t_0 values at an odd stride RS (columns hit distinct banks), then a low
+    // and a high slab per halo direction (direction 0: rows of 3; others: the core layout with
+    // extent 3 in that direction)
+    g.lines = core / g.t[0];
+    g.RS = g.t[0] + ((g.t[0] % 2 == 0 && g.lines > 1) ? 1 : 0);
+    g.whole = 1;
+    for (int k = 0; k < g.d; k++) g.whole &= (g.t[k] == g.n[k]) ? 1 : 0;
+    {
+        int ls = 1;
+        for (int k = 0; k < SGW_MAX_DIM; k++) {
+            g.LS[k] = ls;
+            ls *= (k == 0) ? g.RS : g.t[k];
+        }
+    }
+    int pad = g.RS * g.lines;
     for (int k = 0; k < SGW_MAX_DIM; k++) {
         g.slab_lo[k] = g.slab_hi[k] = 0;
+        g.slab_n[k] = 0;
         if (k < g.d && g.halo[k]) {
+            g.slab_n[k] = 3 * (core / g.t[k]);
+            const int lds = (k == 0) ? 3 * g.lines : 3 * g.RS * (g.lines / g.t[k]);
             g.slab_lo[k] = pad;
-            pad += 3 * (core / g.t[k]);
+            pad += lds;
             g.slab_hi[k] = pad;
-            pad += 3 * (core / g.t[k]);
+            pad += lds;
         }
     }
     g.pad_total = pad;
+    g.fd_lines = make_fastdiv((uint32_t)g.lines);
+    g.pad1_ = 0;
     g.nbox = 1;
     for (int k = 0; k < g.d; k++) g.nbox *= g.ntile[k];
     for (int k = 0; k < SGW_MAX_DIM; k++) {
         g.I[k] = g.t[k] + (g.halo[k] ? 1 : 0);
         g.flux_total[k] = (k < g.d) ? core / g.t[k] * g.I[k] : 0;
+        g.nseg[k] = (g.I[k] + SGW_SEG - 1) / SGW_SEG;
+        g.seg_total[k] = (k < g.d) ? core / g.t[k] * g.nseg[k] : 0;
+        g.fd_nseg[k] = make_fastdiv((uint32_t)g.nseg[k]);
+        if (k == 0) {
+            g.F0S = g.I[0] + ((g.I[0] % 2 == 0 && g.lines > 1) ? 1 : 0);
+            g.flux_total[0] = g.F0S * g.lines; // direction 0 keeps its interface rows at an odd stride
+        }
         g.fd_CS[k] = make_fastdiv((uint32_t)g.CS[k]);
         g.fd_t[k] = make_fastdiv((uint32_t)g.t[k]);
         g.fd_I[k] = make_fastdiv((uint32_t)g.I[k]);
         g.fd_CSt[k] = make_fastdiv((uint32_t)(g.CS[k] * g.t[k]));
         g.fd_n[k] = make_fastdiv((uint32_t)(k < g.d ? g.n[k] : 1));
     }
+    int fm = 0;
+    for (int k = 0; k < g.d; k++) fm = g.flux_total[k] > fm ? g.flux_total[k] : fm;
+    g.sf_elems = (fm + 1) / 2 * 2;
 }
 
 // Box search: every combination of divisors t_k | n_k with a core of at most
@@ -273,7 +302,7 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     p->grids.resize(p->G);
     int64_t tot = 0;
     const size_t lds_cap = 64 * 1024;
-    int target = cfg->precision == SGW_FP64 ? 1024 : 2048;
+    int target = 1024;
     if (cfg->box_target) {
         if (cfg->box_target < 64 || cfg->box_target > SGW_BLOCK * SGW_MAXR) {
             delete p;

@@ -18,33 +18,89 @@
 
 namespace {
 
+// descriptors live in the constant address space for the duration of a launch
+#define SGW_CONST __attribute__((address_space(4)))
+typedef const SGW_CONST GridDev* GridC;
+// LDS indices stay below 2^16: the full-rate 24-bit multiply is exact for them
+#define M24(a, b) __mul24((a), (b))
+
 __device__ __forceinline__ float rdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double rdiv(double a, double b) { return a / b; }
 
-// WENO5 flux from the positive-wind big stencil (a..e) = (f_{i-2} .. f_{i+2}).
-// Nonlinear weights alpha_r = d_r / (eps + beta_r)^2 normalised by their sum;
-// written with one division: multiply numerator and denominator by
-// prod_r (eps + beta_r)^2.
+// WENO5 flux (eqs. 2.7, 2.7.1, 2.6, 2.7.2) of the positive-wind big stencil
+// (a..e) = (f_{i-2} .. f_{i+2}), written in differences so that neighbouring
+// interfaces share them: c = f_i, D0..D3 = b-a, c-b, d-c, e-d, and
+// S0..S2 = 13/12 (a-2b+c)^2, 13/12 (b-2c+d)^2, 13/12 (c-2d+e)^2.  Then
+//   q_r - c = (5 D1 - 2 D0)/6, (D1 + 2 D2)/6, (4 D2 - D3)/6,
+//   beta_r  = S_r + (3 D1 - D0)^2/4, S_1 + (D1 + D2)^2/4, S_2 + (D3 - 3 D2)^2/4,
+// and the normalised weights d_r/(eps+beta_r)^2 are formed with one division
+// (numerator and denominator multiplied by prod_r (eps+beta_r)^2).
 template <typename Real>
-__device__ __forceinline__ Real weno5(Real a, Real b, Real c, Real d, Real e, Real eps, int linear)
+__device__ __forceinline__ Real weno5d(Real c, Real D0, Real D1, Real D2, Real D3, Real S0, Real S1, Real S2, Real eps,
+                                       int linear)
 {
-    const Real q0 = a * Real(1.0 / 3.0) - b * Real(7.0 / 6.0) + c * Real(11.0 / 6.0);
-    const Real q1 = -b * Real(1.0 / 6.0) + c * Real(5.0 / 6.0) + d * Real(1.0 / 3.0);
-    const Real q2 = c * Real(1.0 / 3.0) + d * Real(5.0 / 6.0) - e * Real(1.0 / 6.0);
-    if (linear) return Real(0.1) * q0 + Real(0.6) * q1 + Real(0.3) * q2;
-    const Real t0 = a - Real(2) * b + c, s0 = a - Real(4) * b + Real(3) * c;
-    const Real t1 = b - Real(2) * c + d, s1 = b - d;
-    const Real t2 = c - Real(2) * d + e, s2 = Real(3) * c - Real(4) * d + e;
-    Real e0 = eps + (Real(13.0 / 12.0) * t0 * t0 + Real(0.25) * s0 * s0);
-    Real e1 = eps + (Real(13.0 / 12.0) * t1 * t1 + Real(0.25) * s1 * s1);
-    Real e2 = eps + (Real(13.0 / 12.0) * t2 * t2 + Real(0.25) * s2 * s2);
+    const Real Q0 = Real(5) * D1 - Real(2) * D0;
+    const Real Q1 = D1 + Real(2) * D2;
+    const Real Q2 = Real(4) * D2 - D3;
+    if (linear) return c + (Real(0.1) * Q0 + Real(0.6) * Q1 + Real(0.3) * Q2) * Real(1.0 / 6.0);
+    const Real g0 = Real(3) * D1 - D0, g1 = D1 + D2, g2 = D3 - Real(3) * D2;
+    Real e0 = eps + (S0 + Real(0.25) * g0 * g0);
+    Real e1 = eps + (S1 + Real(0.25) * g1 * g1);
+    Real e2 = eps + (S2 + Real(0.25) * g2 * g2);
     e0 *= e0;
     e1 *= e1;
     e2 *= e2;
-    const Real w0 = Real(0.1) * (e1 * e2);
-    const Real w1 = Real(0.6) * (e0 * e2);
-    const Real w2 = Real(0.3) * (e0 * e1);
-    return rdiv(w0 * q0 + w1 * q1 + w2 * q2, w0 + w1 + w2);
+    const Real A0 = Real(0.1) * (e1 * e2), A1 = Real(0.6) * (e0 * e2), A2 = Real(0.3) * (e0 * e1);
+    return c + rdiv(A0 * Q0 + A1 * Q1 + A2 * Q2, Real(6) * (A0 + A1 + A2));
+}
+
+// NI consecutive interface fluxes F_{i+1/2}, i = i0..i0+NI-1, from the NI+5 values
+// u_{i0-2} .. u_{i0+NI+2} of one line: LF split f^+- (eq. LFflux), the positive-wind
+// reconstruction of f^+ on i-2..i+2 plus the mirrored one of f^- on i+3..i-1.  A
+// split part that is identically zero (c = -+alpha for a linear flux) contributes
+// exactly zero and is skipped.
+template <typename Real, int NI>
+__device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real cp, Real cm, Real alpha, Real eps,
+                                              int linear, Real* F)
+{
+    Real pv[NI + 5], mv[NI + 5];
+#pragma unroll
+    for (int q = 0; q < NI + 5; q++) {
+        if (burgers) {
+            const Real hu = Real(0.25) * v[q], ha = Real(0.5) * alpha;
+            pv[q] = v[q] * (hu + ha);
+            mv[q] = v[q] * (hu - ha);
+        } else {
+            pv[q] = cp * v[q];
+            mv[q] = cm * v[q];
+        }
+    }
+    const bool use_p = burgers || cp != Real(0);
+    const bool use_m = burgers || cm != Real(0);
+    Real dp[NI + 4], dm[NI + 4], sp[NI + 4], sm[NI + 4];
+#pragma unroll
+    for (int q = 0; q < NI + 4; q++) {
+        dp[q] = pv[q + 1] - pv[q];
+        dm[q] = mv[q + 1] - mv[q];
+    }
+    sp[0] = sm[0] = Real(0);
+#pragma unroll
+    for (int q = 1; q < NI + 4; q++) {
+        const Real tp = dp[q] - dp[q - 1], tm = dm[q] - dm[q - 1];
+        sp[q] = Real(13.0 / 12.0) * tp * tp;
+        sm[q] = Real(13.0 / 12.0) * tm * tm;
+    }
+#pragma unroll
+    for (int s = 0; s < NI; s++) {
+        Real f = Real(0);
+        if (use_p)
+            f = weno5d<Real>(pv[s + 2], dp[s], dp[s + 1], dp[s + 2], dp[s + 3], sp[s + 1], sp[s + 2], sp[s + 3], eps,
+                             linear);
+        if (use_m)
+            f += weno5d<Real>(mv[s + 3], -dm[s + 4], -dm[s + 3], -dm[s + 2], -dm[s + 1], sm[s + 4], sm[s + 3],
+                              sm[s + 2], eps, linear);
+        F[s] = f;
+    }
 }
 
 // max that keeps a NaN (a NaN wave speed must reach the time-step check)
@@ -72,13 +128,27 @@ __device__ __forceinline__ void block_atomic_max(double v, unsigned long long* d
     }
 }
 
+// Global index of core node e (logical row-major index inside the box).
+template <int D>
+__device__ __forceinline__ int core_global_index(GridC g, const int* o, int e)
+{
+    uint32_t r = (uint32_t)e;
+    int gi = 0;
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        const uint32_t q = FDIV(r, g->fd_t[k]);
+        gi += (o[k] + (int)(r - q * (uint32_t)g->t[k])) * g->stride[k];
+        r = q;
+    }
+    return gi;
+}
+
 template <typename Real, int D>
-__device__ __forceinline__ void stage_box(const GridDev* __restrict__ g, int box, int stage, Real* su, Real* sf,
+__device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su, Real* sf,
                                           double* red)
 {
     const int tid = threadIdx.x;
-    const ReqDev* req = g->req;
-    const double dt = req->dt;
+    const double dt = ((const SGW_CONST ReqDev*)g->req)->dt;
     const Real dtr = (Real)dt;
 
     int o[D];
@@ -97,49 +167,49 @@ __device__ __forceinline__ void stage_box(const GridDev* __restrict__ g, int box
     // the wave-speed slot the next stage reads is cleared by the stage before it
     if (g->dyn_alpha && box == 0 && tid == 0) g->alpha[(stage + 2) % 3] = 0ull;
 
-    // ---- stage the core box, then the halo slabs (periodic wrap on the global index)
     const int core_total = g->core_total;
-    const int pad_total = g->pad_total;
-    for (int e = tid; e < pad_total; e += SGW_BLOCK) {
-        // region: -1 core, else (direction, side) of the slab that holds e
-        int kk = -1, side = 0, local = e;
-        if (e >= core_total) {
+    const int t0 = g->t[0];
+    const int RS = g->RS;         // LDS row stride of the core box (odd: conflict-free columns)
+    const bool whole = g->whole;  // the box is the whole grid: global index = core index
+
+    // ---- core box -> LDS
+    for (int e = tid; e < core_total; e += SGW_BLOCK) {
+        const uint32_t line = FDIV((uint32_t)e, g->fd_t[0]);
+        const int c0 = e - M24((int)line, t0);
+        su[c0 + M24(RS, (int)line)] = in[whole ? e : core_global_index<D>(g, o, e)];
+    }
+    // ---- halo slabs: the core box with extent 3 in direction k, periodic wrap on the global index
 #pragma unroll
-            for (int k = 0; k < D; k++) {
-                if (g->halo[k]) {
-                    if (e >= g->slab_lo[k] && e < g->slab_hi[k]) {
-                        kk = k;
-                        side = 0;
-                        local = e - g->slab_lo[k];
-                    } else if (e >= g->slab_hi[k] && e < g->slab_hi[k] + (g->slab_hi[k] - g->slab_lo[k])) {
-                        kk = k;
-                        side = 1;
-                        local = e - g->slab_hi[k];
-                    }
+    for (int k = 0; k < D; k++) {
+        if (!g->halo[k]) continue;
+        const int sn = g->slab_n[k];
+        const int w0 = k == 0 ? 3 : RS;
+        for (int e = tid; e < 2 * sn; e += SGW_BLOCK) {
+            const int side = e >= sn ? 1 : 0;
+            uint32_t r = (uint32_t)(e - side * sn);
+            int gi = 0, li = 0, mul = 1;
+#pragma unroll
+            for (int j = 0; j < D; j++) {
+                int c, x;
+                if (j == k) {
+                    const uint32_t q = r / 3u;
+                    c = (int)(r - 3u * q);
+                    r = q;
+                    x = side ? o[j] + g->t[j] + c : o[j] - 3 + c;
+                } else {
+                    const uint32_t q = FDIV(r, g->fd_t[j]);
+                    c = (int)(r - q * (uint32_t)g->t[j]);
+                    r = q;
+                    x = o[j] + c;
                 }
+                x += (x < 0) ? g->n[j] : 0;
+                x -= (x >= g->n[j]) ? g->n[j] : 0;
+                gi += x * g->stride[j];
+                li += c * mul;
+                mul *= (j == 0) ? w0 : (j == k ? 3 : g->t[j]);
             }
+            su[(side ? g->slab_hi[k] : g->slab_lo[k]) + li] = in[gi];
         }
-        uint32_t r = (uint32_t)local;
-        int gi = 0;
-#pragma unroll
-        for (int k = 0; k < D; k++) {
-            int x;
-            if (k == kk) {
-                const uint32_t q = r / 3u;
-                const int c = (int)(r - 3u * q);
-                r = q;
-                x = side ? o[k] + g->t[k] + c : o[k] - 3 + c;
-            } else {
-                const uint32_t q = fdiv(r, g->fd_t[k]);
-                const int c = (int)(r - q * (uint32_t)g->t[k]);
-                r = q;
-                x = o[k] + c;
-            }
-            x += (x < 0) ? g->n[k] : 0;
-            x -= (x >= g->n[k]) ? g->n[k] : 0;
-            gi += x * g->stride[k];
-        }
-        su[e] = in[gi];
     }
     __syncthreads();
 
@@ -149,6 +219,7 @@ __device__ __forceinline__ void stage_box(const GridDev* __restrict__ g, int box
 
     const Real eps = (Real)g->eps;
     const int linear = g->linear;
+    const bool burgers = g->flux == SGW_FLUX_BURGERS;
     Real dyn_alpha = Real(0);
     if (g->dyn_alpha) dyn_alpha = (Real)__longlong_as_double((long long)g->alpha[stage]);
 
@@ -157,62 +228,80 @@ __device__ __forceinline__ void stage_box(const GridDev* __restrict__ g, int box
         const int hf = g->halo[k] ? 1 : 0;
         const int tk = g->t[k];
         const int CSk = g->CS[k];
+        const int LSk = g->LS[k];
         const int Ik = g->I[k];
         const int slo = g->slab_lo[k], shi = g->slab_hi[k];
         const Real alpha = g->dyn_alpha ? dyn_alpha : (Real)g->alpha_c[k];
         const double* __restrict__ ctab = g->coef[k];
         const int csrc = g->coef_src[k];
         const Real cconst = (Real)g->lin_c[k];
-        // ---- interface fluxes of the box in direction k -> sf; interface index
-        //      f = inner + (i + hf) CS_k + outer CS_k I_k, inner over directions < k
-        const int ftot = g->flux_total[k];
-        for (int f = tid; f < ftot; f += SGW_BLOCK) {
-            const uint32_t r1 = fdiv((uint32_t)f, g->fd_CS[k]);
-            const int inner = f - (int)r1 * CSk;
-            const uint32_t outer = fdiv(r1, g->fd_I[k]);
-            const int i = (int)(r1 - outer * (uint32_t)Ik) - hf; // the flux is at x_{i+1/2}
-            const int base_core = inner + (int)outer * CSk * tk;   // node with c_k = 0 on this line
-            const int base_slab = inner + (int)outer * 3 * CSk;
-            Real v[6];
+        // directions alternate between two flux buffers: one barrier per direction
+        Real* __restrict__ sfk = (k & 1) ? sf + g->sf_elems : sf;
+        // ---- interface fluxes F_{i+1/2} of the box in direction k -> sf.  Each thread takes
+        //      SGW_SEG consecutive interfaces of one line from a window of SGW_SEG + 5 values;
+        //      consecutive lanes take neighbouring lines (stride 1, or RS for direction 1).
+        const int stot = g->seg_total[k];
+        const int nseg = g->nseg[k];
+        for (int w = tid; w < stot; w += SGW_BLOCK) {
+            int seg, base_core, base_slab, lbase, fbase, fstride;
+            if (k == 0) {
+                const uint32_t sq = FDIV((uint32_t)w, g->fd_lines);
+                const int line = w - (int)sq * g->lines;
+                seg = (int)sq;
+                base_core = M24(line, RS);
+                base_slab = M24(line, 3);
+                lbase = M24(line, t0);
+                fbase = M24(line, g->F0S);
+                fstride = 1;
+            } else {
+                const uint32_t r1 = FDIV((uint32_t)w, g->fd_CS[k]);
+                const int inner = w - (int)r1 * CSk;
+                const uint32_t outer = FDIV(r1, g->fd_nseg[k]);
+                seg = (int)r1 - (int)outer * nseg;
+                int inner_lds = inner;
+                if (k >= 2) inner_lds += M24(RS - t0, (int)FDIV((uint32_t)inner, g->fd_t[0]));
+                base_core = inner_lds + M24((int)outer, LSk * tk);
+                base_slab = inner_lds + M24((int)outer, 3 * LSk);
+                lbase = inner + M24((int)outer, CSk * tk);
+                fbase = inner + M24((int)outer, CSk * Ik);
+                fstride = CSk;
+            }
+            const int i0 = seg * SGW_SEG - hf; // first interface: x_{i0+1/2}
+            Real v[SGW_SEG + 5];
 #pragma unroll
-            for (int m = 0; m < 6; m++) {
-                int p = i + m - 2;
+            for (int q = 0; q < SGW_SEG + 5; q++) {
+                int p = i0 + q - 2;
                 int idx;
                 if (hf) {
-                    idx = (p < 0) ? slo + base_slab + (p + 3) * CSk
-                                  : (p >= tk) ? shi + base_slab + (p - tk) * CSk : base_core + p * CSk;
+                    p = p > tk + 2 ? tk + 2 : p; // past the last interface: valid data, result unused
+                    idx = (p < 0) ? slo + base_slab + M24(p + 3, LSk)
+                                  : (p >= tk) ? shi + base_slab + M24(p - tk, LSk) : base_core + M24(p, LSk);
                 } else {
                     p += (p < 0) ? tk : 0;
                     p -= (p >= tk) ? tk : 0;
-                    idx = base_core + p * CSk;
+                    p -= (p >= tk) ? tk : 0;
+                    idx = base_core + M24(p, LSk);
                 }
-                v[m] = su[idx];
+                v[q] = su[idx];
             }
-            int csrc_coord = 0;
-            if (csrc >= 0) {
-                const uint32_t q = fdiv((uint32_t)base_core, g->fd_CS[csrc]);
-                csrc_coord = o[csrc] + (int)(q - fdiv(q, g->fd_t[csrc]) * (uint32_t)g->t[csrc]);
+            Real cp = Real(0), cm = Real(0);
+            if (!burgers) {
+                // f_k = c u along the line (advection, Vlasov): f^+- = (c +- alpha)/2 u
+                Real c = cconst;
+                if (csrc >= 0) {
+                    const uint32_t q = FDIV((uint32_t)lbase, g->fd_CS[csrc]);
+                    c = (Real)ctab[o[csrc] + (int)(q - FDIV(q, g->fd_t[csrc]) * (uint32_t)g->t[csrc])];
+                }
+                cp = Real(0.5) * (c + alpha);
+                cm = Real(0.5) * (c - alpha);
             }
-            Real pl[6], mi[6];
-            if (g->flux == SGW_FLUX_BURGERS) {
+            Real F[SGW_SEG];
+            window_fluxes<Real, SGW_SEG>(v, burgers, cp, cm, alpha, eps, linear, F);
 #pragma unroll
-                for (int m = 0; m < 6; m++) {
-                    const Real hu = Real(0.25) * v[m];
-                    pl[m] = v[m] * (hu + Real(0.5) * alpha);
-                    mi[m] = v[m] * (hu - Real(0.5) * alpha);
-                }
-            } else {
-                const Real c = (csrc >= 0) ? (Real)ctab[csrc_coord] : cconst;
-                const Real cp = Real(0.5) * (c + alpha), cm = Real(0.5) * (c - alpha);
-#pragma unroll
-                for (int m = 0; m < 6; m++) {
-                    pl[m] = cp * v[m];
-                    mi[m] = cm * v[m];
-                }
+            for (int s = 0; s < SGW_SEG; s++) {
+                const int ip = seg * SGW_SEG + s; // i + hf
+                if (ip < Ik) sfk[fbase + M24(ip, fstride)] = F[s];
             }
-            const Real F = weno5<Real>(pl[0], pl[1], pl[2], pl[3], pl[4], eps, linear) +
-                           weno5<Real>(mi[5], mi[4], mi[3], mi[2], mi[1], eps, linear);
-            sf[f] = F;
         }
         __syncthreads();
         // ---- flux differences of eq. (2.9) for the nodes this thread owns
@@ -221,14 +310,21 @@ __device__ __forceinline__ void stage_box(const GridDev* __restrict__ g, int box
         for (int r = 0; r < SGW_MAXR; r++) {
             const int e = tid + r * SGW_BLOCK;
             if (e < core_total) {
-                const uint32_t hi = fdiv((uint32_t)e, g->fd_CSt[k]);
-                const int lo = e - (int)hi * (int)g->fd_CSt[k].d;
-                const int fhi = lo + hf * CSk + (int)hi * CSk * Ik;
-                const int flo = (hf || lo >= CSk) ? fhi - CSk : fhi + (tk - 1) * CSk;
-                acc[r] -= (sf[fhi] - sf[flo]) * ih;
+                int fhi, flo;
+                if (k == 0) {
+                    const uint32_t line = FDIV((uint32_t)e, g->fd_t[0]);
+                    const int c0 = e - M24((int)line, t0);
+                    fhi = c0 + hf + M24((int)line, g->F0S);
+                    flo = (hf || c0 > 0) ? fhi - 1 : fhi + t0 - 1;
+                } else {
+                    const uint32_t hi = FDIV((uint32_t)e, g->fd_CSt[k]);
+                    const int lo = e - M24((int)hi, (int)g->fd_CSt[k].d);
+                    fhi = lo + hf * CSk + M24((int)hi, CSk * Ik);
+                    flo = (hf || lo >= CSk) ? fhi - CSk : fhi + (tk - 1) * CSk;
+                }
+                acc[r] -= (sfk[fhi] - sfk[flo]) * ih;
             }
         }
-        __syncthreads();
     }
 
     // ---- TVD-RK3 stage: u1 = u + dt L(u); u2 = 3/4 u + 1/4 (u1 + dt L(u1)); u = 1/3 u + 2/3 (u2 + dt L(u2))
@@ -237,23 +333,16 @@ __device__ __forceinline__ void stage_box(const GridDev* __restrict__ g, int box
     for (int r = 0; r < SGW_MAXR; r++) {
         const int e = tid + r * SGW_BLOCK;
         if (e < core_total) {
-            uint32_t rr = (uint32_t)e;
-            int gi = 0;
-#pragma unroll
-            for (int k = 0; k < D; k++) {
-                const uint32_t q = fdiv(rr, g->fd_t[k]);
-                const int c = (int)(rr - q * (uint32_t)g->t[k]);
-                rr = q;
-                gi += (o[k] + c) * g->stride[k];
-            }
-            const Real val = su[e] + dtr * acc[r];
+            const uint32_t line = FDIV((uint32_t)e, g->fd_t[0]);
+            const int c0 = e - M24((int)line, t0);
+            const int gi = whole ? e : core_global_index<D>(g, o, e);
+            const Real val = su[c0 + M24(RS, (int)line)] + dtr * acc[r];
             Real res;
             if (stage == 0) res = val;
             else if (stage == 1) res = Real(0.75) * u0[gi] + Real(0.25) * val;
             else res = Real(1.0 / 3.0) * u0[gi] + Real(2.0 / 3.0) * val;
             out[gi] = res;
-            const double ar = fabs((double)res);
-            amax = nanmax(amax, ar);
+            amax = nanmax(amax, fabs((double)res));
         }
     }
     if (g->dyn_alpha) block_atomic_max(amax, g->alpha + (stage + 1) % 3, red);
@@ -272,17 +361,20 @@ __global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __rest
     int nb = gridDim.x, bid = blockIdx.x;
     if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
     for (int w = bid; w < nitems; w += nb) {
-        const WorkItem it = items[w];
-        const GridDev* g = it.g;
-        if (g->req->done) continue;
+        // descriptors are read-only during the launch: read them through the constant
+        // address space so the compiler keeps them in scalar registers
+        const SGW_CONST WorkItem* it = (const SGW_CONST WorkItem*)items + w;
+        GridC g = (GridC)it->g;
+        const int ibox = it->box;
+        if (((const SGW_CONST ReqDev*)g->req)->done) continue;
         const size_t su_elems = (size_t)g->pad_total;
         Real* su = (Real*)smem;
         Real* sf = su + ((su_elems + 1) & ~(size_t)1);
         switch (g->d) {
-        case 1: stage_box<Real, 1>(g, it.box, stage, su, sf, red); break;
-        case 2: stage_box<Real, 2>(g, it.box, stage, su, sf, red); break;
-        case 3: stage_box<Real, 3>(g, it.box, stage, su, sf, red); break;
-        default: stage_box<Real, 4>(g, it.box, stage, su, sf, red); break;
+        case 1: stage_box<Real, 1>(g, ibox, stage, su, sf, red); break;
+        case 2: stage_box<Real, 2>(g, ibox, stage, su, sf, red); break;
+        case 3: stage_box<Real, 3>(g, ibox, stage, su, sf, red); break;
+        default: stage_box<Real, 4>(g, ibox, stage, su, sf, red); break;
         }
         __syncthreads();
     }
@@ -346,7 +438,7 @@ __global__ void restrict_kernel(const GridDev* grids, RestrictArgs a)
         uint32_t r = (uint32_t)idx;
         double x[SGW_MAX_DIM] = {0.0, 0.0, 0.0, 0.0};
         for (int k = 0; k < g->d; k++) {
-            const uint32_t q = fdiv(r, g->fd_n[k]);
+            const uint32_t q = FDIV(r, g->fd_n[k]);
             const int j = (int)(r - q * (uint32_t)g->n[k]);
             r = q;
             x[k] = g->lo[k] + j * g->h[k];
@@ -455,7 +547,7 @@ size_t stage_lds_bytes(const GridDev& g, int precision)
     const size_t rs = precision == SGW_FP64 ? 8 : 4;
     int fmax_ = 0;
     for (int k = 0; k < g.d; k++) fmax_ = g.flux_total[k] > fmax_ ? g.flux_total[k] : fmax_;
-    return rs * (((size_t)g.pad_total + 1) / 2 * 2 + (size_t)fmax_);
+    return rs * (((size_t)g.pad_total + 1) / 2 * 2 + 2 * (((size_t)fmax_ + 1) / 2 * 2));
 }
 
 int stage_occupancy(int precision, size_t lds_bytes)

@@ -10,6 +10,7 @@
 #define SGW_BLOCK 256     // threads per workgroup of every kernel (4 wave64)
 #define SGW_MAXR 8        // nodes per thread in the stage kernel: box core <= SGW_BLOCK * SGW_MAXR
 #define SGW_NPART 1024    // workgroups of the first norm pass (fixed, so the sum order is fixed)
+#define SGW_SEG 4         // interfaces per thread along directions 2..d (sliding window)
 
 // Division by a run-time constant d >= 1 for numerators below 2^31:
 // q = (umulhi(x, m) + x) >> s with s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1.
@@ -29,10 +30,18 @@ static inline FastDiv make_fastdiv(uint32_t d)
     return f;
 }
 
-__device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f)
+__device__ __forceinline__ uint32_t fdiv(uint32_t x, FastDiv f)
 {
     return (__umulhi(x, f.m) + x) >> f.s;
 }
+
+__device__ __forceinline__ uint32_t fdiv_ms(uint32_t x, uint32_t m, uint32_t s)
+{
+    return (__umulhi(x, m) + x) >> s;
+}
+
+// the same through a descriptor field of any address space
+#define FDIV(x, f) fdiv_ms((uint32_t)(x), (f).m, (f).s)
 
 struct ReqDev;
 
@@ -61,6 +70,14 @@ struct alignas(64) GridDev {
     int32_t I[SGW_MAX_DIM];          // interfaces per line in the box: t + (halo ? 1 : 0)
     int32_t flux_total[SGW_MAX_DIM]; // interfaces in the box per direction
     int32_t coef_src[SGW_MAX_DIM];   // direction whose node index selects the coefficient, -1: constant
+    int32_t nseg[SGW_MAX_DIM];       // segments of SGW_SEG interfaces per line
+    int32_t seg_total[SGW_MAX_DIM];  // work items of the segment loop: lines * nseg[k]
+    int32_t LS[SGW_MAX_DIM];         // LDS strides of the core box (row stride RS)
+    int32_t slab_n[SGW_MAX_DIM];     // values per halo slab (3 core / t_k)
+    int32_t RS, lines, F0S, whole;   // odd LDS row stride, rows (core / t_0), odd flux row stride, box = grid
+    int32_t sf_elems, pad1_;         // elements of one interface-flux buffer (two alternate in LDS)
+    FastDiv fd_lines;
+    FastDiv fd_nseg[SGW_MAX_DIM];
     FastDiv fd_CS[SGW_MAX_DIM];
     FastDiv fd_t[SGW_MAX_DIM];
     FastDiv fd_I[SGW_MAX_DIM];

@@ -1,0 +1,134 @@
+"""Continuous-batching serving loop over the batch runtime (sgw_batch_*).
+
+Requests arrive over time (each with a problem and an arrival time on the host
+monotonic clock).  The loop admits queued requests in arrival order while a
+batch slot is free and the request's device footprint (state + scratch +
+finest-grid output) fits the HBM budget, so a request that arrives while others
+are on the GPU joins the next time step of the running batch.  Each tick
+advances every admitted solve by a few time steps, one graph launch per step on
+the batch stream.  A finished solve leaves the batch and is prolongated and
+combined on a second stream while the batch keeps stepping; its latency is
+finish - arrival.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Dict, List, Optional
+
+import torch
+
+from . import binding as B
+from .solver import Batch, Plan, Solver
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival_s: float
+    admit_s: float
+    finish_s: float
+    steps: int
+    cell_updates: int
+    out: Optional[torch.Tensor]
+
+    @property
+    def latency_s(self) -> float:
+        return self.finish_s - self.arrival_s
+
+
+class ServingLoop:
+    def __init__(self, precision: int = B.FP32_SWEEP, max_active: int = 64, hbm_budget: int = 64 << 30,
+                 steps_per_tick: int = 8, keep_outputs: bool = False, box_target: int = 0,
+                 device: str = "cuda"):
+        self.precision = precision
+        self.max_active = max_active
+        self.budget = int(hbm_budget)
+        self.steps_per_tick = steps_per_tick
+        self.keep_outputs = keep_outputs
+        self.box_target = box_target
+        self.device = torch.device(device)
+        self.main = torch.cuda.current_stream(self.device)
+        self.side = torch.cuda.Stream(device=self.device)
+        self.batch = Batch(max_solvers=max_active, precision=precision, hbm_budget=self.budget,
+                           max_items=1 << 22, device=device, stream=self.main)
+
+    def run(self, requests: List, clock=time.perf_counter) -> List[Result]:
+        """Serve ``requests`` (objects with rid, arrival_s, problem) against the wall clock."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival_s))
+        queue = collections.deque()
+        active: Dict[int, tuple] = {}
+        finishing: List[tuple] = []
+        used = 0
+        results: List[Result] = []
+        plans: Dict[int, Plan] = {}
+        t0 = clock()
+        while pending or queue or active or finishing:
+            now = clock() - t0
+            while pending and pending[0].arrival_s <= now:
+                queue.append(pending.popleft())
+            # admission in arrival order, by slot and device footprint
+            while queue and len(active) < self.max_active:
+                req = queue[0]
+                plan = plans.get(req.rid)
+                if plan is None:
+                    plan = plans[req.rid] = Plan(req.problem, box_target=self.box_target)
+                if used + plan.footprint > self.budget:
+                    if not active and not finishing:
+                        raise MemoryError(f"request {req.rid} needs {plan.footprint} B, budget {self.budget} B")
+                    break
+                with torch.cuda.stream(self.side):
+                    solver = Solver(req.problem, device=str(self.device), stream=self.side, plan=plan)
+                    solver.restrict()
+                slot = self.batch.admit(solver)  # orders the restriction before the batch's next step
+                queue.popleft()
+                used += plan.footprint
+                active[slot] = (req, solver, clock() - t0, plan.footprint)
+            # solves whose combination has completed
+            still = []
+            for req, solver, admit_s, fp, ev, U in finishing:
+                if ev.query():
+                    t, steps = solver.query()
+                    results.append(Result(rid=req.rid, arrival_s=req.arrival_s, admit_s=admit_s,
+                                          finish_s=clock() - t0, steps=steps,
+                                          cell_updates=steps * solver.plan.total_nodes,
+                                          out=U if self.keep_outputs else None))
+                    used -= fp
+                    plans.pop(req.rid, None)
+                    solver.close()
+                else:
+                    still.append((req, solver, admit_s, fp, ev, U))
+            finishing = still
+            if not active:
+                if finishing:
+                    time.sleep(0.0002)
+                elif pending:
+                    wait = pending[0].arrival_s - (clock() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 0.005))
+                continue
+            self.batch.step(self.steps_per_tick)
+            for slot in self.batch.poll():
+                req, solver, admit_s, fp = active.pop(slot)
+                self.batch.release(slot)
+                with torch.cuda.stream(self.side):
+                    U = solver.prolongate_combine()
+                    ev = torch.cuda.Event()
+                    ev.record(self.side)
+                finishing.append((req, solver, admit_s, fp, ev, U))
+        return results
+
+    def close(self):
+        self.batch.close()
+
+
+def latency_summary(results: List[Result]) -> dict:
+    import numpy as np
+    lat = np.array([r.latency_s for r in results]) * 1e3
+    span = max(r.finish_s for r in results) - min(r.arrival_s for r in results)
+    cells = sum(r.cell_updates for r in results)
+    return {"requests": len(results), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "max_ms": float(lat.max()),
+            "throughput_cell_updates_per_s": cells / span if span > 0 else None, "span_s": span}

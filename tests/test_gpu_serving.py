@@ -1,0 +1,101 @@
+"""Serving loop and autotuner on the GPU.
+
+Each request's combined solution must be bit-for-bit the one the same solve
+produces alone (same kernels, per-solve time stepping), whatever else shares
+the batch; requests are admitted by device footprint as memory frees up.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import sgw_inputs as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _mixed_stream(n=12, rate=400.0, seed=77, levels=(2, 3)):
+    reqs = W.serving_stream(n=n, rate_hz=rate, seed=seed, levels=levels, precision=W.PREC_FP32)
+    for r in reqs:  # keep the GPU time of the test small
+        r.problem = r.problem.replace(T=min(r.problem.T, 0.15))
+    return reqs
+
+
+def test_serving_results_equal_solo_results():
+    import torch
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.serving import ServingLoop, latency_summary
+    from paper_2007_10196_amd.solver import Solver
+    reqs = _mixed_stream()
+    assert len({r.family for r in reqs}) >= 3
+    loop = ServingLoop(precision=B.FP32_SWEEP, max_active=5, hbm_budget=8 << 30, steps_per_tick=4,
+                       keep_outputs=True)
+    res = loop.run(reqs)
+    torch.cuda.synchronize()
+    assert sorted(r.rid for r in res) == [r.rid for r in reqs]
+    summ = latency_summary(res)
+    print("\n[gpu] serving", summ, flush=True)
+    assert summ["p99_ms"] >= summ["p50_ms"] > 0
+    by_id = {r.rid: r for r in reqs}
+    for r in res:
+        pb = by_id[r.rid].problem
+        solo = Solver(pb).solve(mode=B.RUN_GRAPH).cpu().numpy()
+        assert np.array_equal(r.out.cpu().numpy(), solo), r.rid
+        assert r.steps > 0 and r.finish_s >= r.admit_s >= r.arrival_s - 1e-3
+    loop.close()
+
+
+def test_serving_fp32_results_close_to_fp64_oracle():
+    import torch
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.serving import ServingLoop
+    reqs = _mixed_stream(n=6, seed=5, levels=(2,))
+    loop = ServingLoop(precision=B.FP32_SWEEP, max_active=8, hbm_budget=8 << 30, keep_outputs=True)
+    res = loop.run(reqs)
+    by_id = {r.rid: r for r in reqs}
+    for r in res:
+        pb = by_id[r.rid].problem.replace(precision=W.PREC_FP64)
+        U, _, _ = O.solve(pb)
+        err = np.abs(r.out.cpu().numpy() - U)
+        print(f"  request {r.rid} {pb.name} nl={pb.nl}: fp32 L1 {err.mean():.2e} Linf {err.max():.2e}")
+        assert err.max() < 5e-5 * max(1.0, np.abs(U).max())
+    loop.close()
+
+
+def test_admission_waits_for_memory_and_rejects_oversize():
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.serving import ServingLoop
+    from paper_2007_10196_amd.solver import Plan
+    reqs = _mixed_stream(n=8, seed=9, levels=(3,))
+    fps = [Plan(r.problem).footprint for r in reqs]
+    budget = int(max(fps) * 2.2)  # at most about two solves fit at a time
+    loop = ServingLoop(precision=B.FP32_SWEEP, max_active=8, hbm_budget=budget)
+    res = loop.run(reqs)
+    assert len(res) == len(reqs)
+    # resident footprints never exceeded the budget (from the admit / finish stamps)
+    fp_of = {q.rid: f for q, f in zip(reqs, fps)}
+    events = sorted([(r.admit_s, 1, fp_of[r.rid]) for r in res] + [(r.finish_s, -1, fp_of[r.rid]) for r in res])
+    resident, peak = 0, 0
+    for _, kind, f in events:
+        resident += kind * f
+        peak = max(peak, resident)
+    assert peak <= budget
+    assert peak < sum(fps)  # they did not all run at once
+    loop.close()
+    tiny = ServingLoop(precision=B.FP32_SWEEP, max_active=2, hbm_budget=min(fps) // 2)
+    with pytest.raises(MemoryError):
+        tiny.run(reqs[:1])
+    tiny.close()
+
+
+def test_autotuner_picks_and_caches(tmp_path):
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.autotune import tune_box_target
+    probs = [W.c2_burgers_2d(nl=4, precision=W.PREC_FP32).replace(ic_params=(0.3, 0.7, math.pi, 0.1 * i))
+             for i in range(16)]
+    path = str(tmp_path / "tune.json")
+    rec = tune_box_target(probs, B.FP32_SWEEP, candidates=(256, 1024), cache_path=path, reps=3)
+    assert rec["best"] in (256, 1024) and not rec["cached"]
+    again = tune_box_target(probs, B.FP32_SWEEP, candidates=(256, 1024), cache_path=path, reps=3)
+    assert again["cached"] and again["best"] == rec["best"]
