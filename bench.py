@@ -60,7 +60,8 @@ def step_estimate(pb):
     return int(math.ceil(pb.T / (pb.cfl / denom)))
 
 
-def run_batch_step(torch, batch, solvers, outs, exacts):
+def run_batch_step(torch, batch, solvers, outs, exacts, res):
+    from paper_2007_10196_amd.solver import prolongate_combine_many
     for s in solvers:
         s.restrict()
     for s in solvers:
@@ -74,12 +75,13 @@ def run_batch_step(torch, batch, solvers, outs, exacts):
         if len(done) == len(solvers):
             break
         batch.step(2)
-    for s, U in zip(solvers, outs):
-        s.prolongate_combine(U)
-    norms = [s.norms(U, E) for s, U, E in zip(solvers, outs, exacts)]
     for slot in list(batch.slots):
         batch.release(slot)
-    return norms
+    # Alg. Step 3 for every solve in one launch, then the norms, one synchronisation
+    prolongate_combine_many(solvers, outs, stream=batch.stream)
+    for i, (s, U, E) in enumerate(zip(solvers, outs, exacts)):
+        s.norms_async(U, E, res[i])
+    return res.cpu().numpy()
 
 
 STAGE_SRC = os.path.join(ROOT, "paper_2007_10196_amd", "csrc", "kernels_stage.hip")
@@ -129,10 +131,11 @@ def serving_run(capacity, box_target, n=None, load=0.7):
     from paper_2007_10196_amd.solver import Plan
     n = n or SERVING_N
     probe = W.serving_stream(n=n, rate_hz=1.0, max_level_by_family={4: 4})
+    # offered work in 2D-equivalent cell-updates (a stage costs ~d/2 times a 2D stage per node)
     work = []
     for r in probe:
         p = Plan(r.problem)
-        work.append(step_estimate_any(r.problem) * p.total_nodes)
+        work.append(step_estimate_any(r.problem) * p.total_nodes * r.problem.d / 2.0)
     rate = load * capacity / (sum(work) / len(work))
     reqs = W.serving_stream(n=n, rate_hz=rate, max_level_by_family={4: 4})
     loop = ServingLoop(precision=B.FP32_SWEEP, max_active=64, hbm_budget=96 << 30, steps_per_tick=8,
@@ -192,6 +195,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=20)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--box-target", type=int, default=0, help="0: autotune the stage box target")
     ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 1 GiB copy used to scale the HBM byte counters")
@@ -212,7 +216,10 @@ def main():
     probs = make_problems(args.solves)
     # box shape for this batch (untimed): fastest of the candidate targets, cached in JSON
     from paper_2007_10196_amd.autotune import tune_box_target
-    tune = tune_box_target(probs, B.FP32_SWEEP, reps=5)
+    if args.box_target:
+        tune = {"best": args.box_target, "us": None, "cached": True}
+    else:
+        tune = tune_box_target(probs, B.FP32_SWEEP, reps=5)
     box_target = int(tune["best"])
     print(f"[bench] autotuned box target {box_target} ({'cached' if tune['cached'] else 'measured'})",
           file=sys.stderr, flush=True)
@@ -221,6 +228,7 @@ def main():
     fine = solvers[0].plan.fine_nodes
     outs = [torch.empty(fine, dtype=torch.float64, device=dev) for _ in solvers]
     exacts = [s.exact(T_FINAL) for s in solvers]
+    res = torch.zeros((len(solvers), 2), dtype=torch.float64, device=dev)
     budget = sum(s.plan.footprint for s in solvers) + (1 << 30)
     batch = Batch(max_solvers=len(solvers), precision=B.FP32_SWEEP, hbm_budget=budget,
                   max_items=sum(len(s.plan.grids) * 64 for s in solvers))
@@ -228,19 +236,19 @@ def main():
           flush=True)
 
     for _ in range(args.warmup):
-        run_batch_step(torch, batch, solvers, outs, exacts)
+        run_batch_step(torch, batch, solvers, outs, exacts, res)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     norms = None
     for k in range(args.steps):
-        norms = run_batch_step(torch, batch, solvers, outs, exacts)
+        norms = run_batch_step(torch, batch, solvers, outs, exacts, res)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     steps_each = [s.query()[1] for s in solvers]
     cells_per_step = sum(n * nodes for n in steps_each)
     ms_per_step = elapsed / args.steps * 1e3
     value = cells_per_step / (elapsed / args.steps)
-    l1s = np.array([n[0] for n in norms])
+    l1s = norms[:, 0]
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.3e} cell-updates/s",
           file=sys.stderr, flush=True)
 

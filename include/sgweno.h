@@ -171,6 +171,19 @@ sgw_status sgw_exact(sgw_solver_t* solver, double t, double* out_dev);
  * fixed order (bitwise repeatable).  Writes result_host[0..1]; synchronises. */
 sgw_status sgw_norms(sgw_solver_t* solver, const double* a_dev, const double* b_dev, double* result_host);
 
+/* sgw_norms without the synchronisation: writes L1, Linf to result_dev[0..1]
+ * (device memory) in stream order. */
+sgw_status sgw_norms_async(sgw_solver_t* solver, const double* a_dev, const double* b_dev, double* result_dev);
+
+/* Alg. Step 3 for many solves in one launch (one workgroup per finest-grid tile
+ * of every solve; all solves share dimension and precision); outs[i] receives
+ * solve i's combined solution.  scratch_dev (device, 256-byte aligned) holds
+ * the tile list, sgw_prolongate_many_scratch_bytes(solvers, n) bytes.  Runs on
+ * hip_stream after waiting for each solver's own stream; synchronises. */
+sgw_status sgw_prolongate_combine_many(sgw_solver_t* const* solvers, double* const* outs, int32_t n,
+                                       void* scratch_dev, uint64_t scratch_bytes, void* hip_stream);
+uint64_t sgw_prolongate_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n);
+
 /* Current time and number of steps taken; synchronises.  Returns
  * SGW_ERR_NONFINITE if a wave speed or dt became NaN/Inf. */
 sgw_status sgw_query(sgw_solver_t* solver, double* t, int64_t* steps);

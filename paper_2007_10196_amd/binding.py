@@ -64,6 +64,10 @@ _SIGS = {
     "sgw_exact": (C.c_int32, [C.c_void_p, C.c_double, C.c_void_p]),
     "sgw_norms": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "sgw_query": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "sgw_norms_async": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sgw_prolongate_combine_many": (C.c_int32, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32,
+                                                C.c_void_p, C.c_uint64, C.c_void_p]),
+    "sgw_prolongate_many_scratch_bytes": (C.c_uint64, [C.POINTER(C.c_void_p), C.c_int32]),
     "sgw_batch_create": (C.c_int32, [C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p, C.c_uint64,
                                      C.POINTER(C.c_void_p)]),
     "sgw_batch_free": (None, [C.c_void_p]),

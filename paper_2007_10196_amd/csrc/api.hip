@@ -846,3 +846,62 @@ extern "C" sgw_status sgw_query(sgw_solver_t* s, double* t, int64_t* steps)
     if (s->req_pinned->nonfinite) return sgw_fail(SGW_ERR_NONFINITE, "non-finite wave speed or time step");
     return SGW_OK;
 }
+
+extern "C" sgw_status sgw_norms_async(sgw_solver_t* s, const double* a, const double* b, double* result_dev)
+{
+    if (!s || !a || !b || !result_dev) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    HIPCHK(launch_norms(a, b, s->plan->fine_nodes, s->partials_d, result_dev, s->stream), "norms");
+    return SGW_OK;
+}
+
+static int64_t fine_tiles(const sgw_solver* s)
+{
+    int64_t t = 1;
+    for (int k = 0; k < s->fine_h.d; k++) t *= s->fine_h.ntile[k];
+    return t;
+}
+
+extern "C" uint64_t sgw_prolongate_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n)
+{
+    if (!solvers || n <= 0) return 0;
+    int64_t tiles = 0;
+    for (int i = 0; i < n; i++)
+        if (solvers[i]) tiles += fine_tiles(solvers[i]);
+    return align256((uint64_t)tiles * sizeof(ProItem));
+}
+
+extern "C" sgw_status sgw_prolongate_combine_many(sgw_solver_t* const* solvers, double* const* outs, int32_t n,
+                                                  void* scratch_dev, uint64_t scratch_bytes, void* hip_stream)
+{
+    if (!solvers || !outs || n <= 0 || !scratch_dev) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    if ((uintptr_t)scratch_dev & 255) return sgw_fail(SGW_ERR_INVALID_ARG, "scratch must be 256-byte aligned");
+    const int d = solvers[0] ? solvers[0]->plan->pb.dim : 0;
+    const int prec = solvers[0] ? solvers[0]->plan->cfg.precision : 0;
+    size_t lds = 0;
+    std::vector<ProItem> items;
+    for (int i = 0; i < n; i++) {
+        sgw_solver* s = solvers[i];
+        if (!s || !outs[i]) return sgw_fail(SGW_ERR_INVALID_ARG, "null solver or output %d", i);
+        if (!s->restricted) return sgw_fail(SGW_ERR_STATE, "prolongate before restrict (solver %d)", i);
+        if (s->plan->pb.dim != d || s->plan->cfg.precision != prec)
+            return sgw_fail(SGW_ERR_INVALID_ARG, "solvers of one call must share dimension and precision");
+        const size_t l = 2 * (prec == SGW_FP64 ? 8 : 4) * s->plan->pro_buf_elems;
+        lds = l > lds ? l : lds;
+        const int64_t t = fine_tiles(s);
+        for (int64_t k = 0; k < t; k++) items.push_back(ProItem{s->pro_d, s->fine_d, outs[i], (int32_t)k, 0});
+    }
+    if ((uint64_t)items.size() * sizeof(ProItem) > scratch_bytes)
+        return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "scratch holds %llu items, %zu needed",
+                        (unsigned long long)(scratch_bytes / sizeof(ProItem)), items.size());
+    if (items.size() > 0x7fffffff) return sgw_fail(SGW_ERR_UNSUPPORTED, "too many tiles");
+    hipStream_t st = (hipStream_t)hip_stream;
+    // every solver's own stream has finished the state the tiles read
+    for (int i = 0; i < n; i++)
+        if (solvers[i]->stream != st) HIPCHK(hipStreamSynchronize(solvers[i]->stream), "synchronise solver stream");
+    HIPCHK(hipMemcpyAsync(scratch_dev, items.data(), items.size() * sizeof(ProItem), hipMemcpyHostToDevice, st),
+           "upload tile list");
+    HIPCHK(launch_prolong_many((const ProItem*)scratch_dev, (int)items.size(), d, prec, lds, st), "prolongate many");
+    // the host list must outlive the copy
+    HIPCHK(hipStreamSynchronize(st), "synchronise");
+    return SGW_OK;
+}

@@ -20,6 +20,11 @@
 
 namespace {
 
+// descriptors live in the constant address space for the duration of a launch
+#define SGW_CONST __attribute__((address_space(4)))
+typedef const SGW_CONST ProDev* ProC;
+typedef const SGW_CONST FineDev* FineC;
+
 __device__ __forceinline__ float rdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double rdiv(double a, double b) { return a / b; }
 
@@ -50,51 +55,49 @@ __device__ __forceinline__ Real interp5(Real a, Real b, Real c, Real d, Real e, 
 }
 
 template <typename Real, int D>
-__global__ void __launch_bounds__(SGW_BLOCK) prolong_kernel(const ProDev* __restrict__ pro,
-                                                            const FineDev* __restrict__ fdv, double* __restrict__ out)
+__device__ __forceinline__ void prolong_tile(ProC pro, FineC F, double* __restrict__ out, int tile)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
-    const FineDev& F = *fdv;
     int J0[D];
     {
-        int r = blockIdx.x;
+        int r = tile;
         for (int k = 0; k < D; k++) {
-            const int q = r / F.ntile[k];
-            J0[k] = (r - q * F.ntile[k]) * F.T[k];
+            const int q = r / F->ntile[k];
+            J0[k] = (r - q * F->ntile[k]) * F->T[k];
             r = q;
         }
     }
-    const int tile_points = F.tile_points;
-    const Real eps = (Real)F.eps;
-    const int lagrange = F.lagrange;
+    const int tile_points = F->tile_points;
+    const Real eps = (Real)F->eps;
+    const int lagrange = F->lagrange;
     double acc[SGW_MAXRP];
 #pragma unroll
     for (int r = 0; r < SGW_MAXRP; r++) acc[r] = 0.0;
     Real* bufA = (Real*)smem;
-    Real* bufB = bufA + F.pad0; // pad0 holds the per-buffer element count (even)
+    Real* bufB = bufA + F->pad0; // pad0 holds the per-buffer element count (even)
 
-    for (int gidx = 0; gidx < F.G; gidx++) {
-        const ProDev& p = pro[gidx];
-        const Real* __restrict__ u = (const Real*)p.u;
+    for (int gidx = 0; gidx < F->G; gidx++) {
+        ProC p = pro + gidx;
+        const Real* __restrict__ u = (const Real*)p->u;
         int cl[D];
 #pragma unroll
         for (int k = 0; k < D; k++) {
-            const int m = p.m[k];
+            const int m = p->m[k];
             cl[k] = (m == 0) ? J0[k] : (((2 * J0[k] + (1 << m)) >> (m + 1)) - 2);
         }
         // ---- coarse block this tile depends on (periodic wrap)
-        for (int e = tid; e < p.load_total; e += SGW_BLOCK) {
+        for (int e = tid; e < p->load_total; e += SGW_BLOCK) {
             uint32_t r = (uint32_t)e;
             int gi = 0;
 #pragma unroll
             for (int k = 0; k < D; k++) {
-                const uint32_t q = fdiv(r, p.fd_c[k]);
-                const int c = (int)(r - q * (uint32_t)p.c[k]);
+                const uint32_t q = FDIV(r, p->fd_c[k]);
+                const int c = (int)(r - q * (uint32_t)p->c[k]);
                 r = q;
-                int x = cl[k] + c + 2 * p.n[k]; // >= 0
-                x = x % p.n[k];
-                gi += x * p.stride[k];
+                int x = cl[k] + c + 2 * p->n[k]; // >= 0
+                x = x % p->n[k];
+                gi += x * p->stride[k];
             }
             bufA[e] = u[gi];
         }
@@ -103,18 +106,18 @@ __global__ void __launch_bounds__(SGW_BLOCK) prolong_kernel(const ProDev* __rest
         Real* dst = bufB;
 #pragma unroll
         for (int k = 0; k < D; k++) {
-            const int m = p.m[k];
+            const int m = p->m[k];
             if (m == 0) continue;
-            const int Tk = F.T[k];
-            const int ck = p.c[k];
-            const int inner = F.inner[k];
-            const int total = inner * Tk * p.outer[k];
+            const int Tk = F->T[k];
+            const int ck = p->c[k];
+            const int inner = F->inner[k];
+            const int total = inner * Tk * p->outer[k];
             const int R = 1 << m;
             const Real invR = Real(1) / Real(R);
             for (int o = tid; o < total; o += SGW_BLOCK) {
-                const uint32_t r1 = fdiv((uint32_t)o, F.fd_inner[k]);
+                const uint32_t r1 = FDIV((uint32_t)o, F->fd_inner[k]);
                 const int a = o - (int)r1 * inner;
-                const uint32_t bq = fdiv(r1, F.fd_T[k]);
+                const uint32_t bq = FDIV(r1, F->fd_T[k]);
                 const int jl = (int)r1 - (int)bq * Tk;
                 const int J = J0[k] + jl;
                 const int i = (2 * J + R) >> (m + 1);
@@ -129,7 +132,7 @@ __global__ void __launch_bounds__(SGW_BLOCK) prolong_kernel(const ProDev* __rest
             src = dst;
             dst = t;
         }
-        const double cg = (double)p.coef;
+        const double cg = (double)p->coef;
 #pragma unroll
         for (int r = 0; r < SGW_MAXRP; r++) {
             const int e = tid + r * SGW_BLOCK;
@@ -146,15 +149,29 @@ __global__ void __launch_bounds__(SGW_BLOCK) prolong_kernel(const ProDev* __rest
             int64_t gi = 0, st = 1;
 #pragma unroll
             for (int k = 0; k < D; k++) {
-                const uint32_t q = fdiv(rr, F.fd_T[k]);
-                const int c = (int)(rr - q * (uint32_t)F.T[k]);
+                const uint32_t q = FDIV(rr, F->fd_T[k]);
+                const int c = (int)(rr - q * (uint32_t)F->T[k]);
                 rr = q;
                 gi += (int64_t)(J0[k] + c) * st;
-                st *= F.N;
+                st *= F->N;
             }
             out[gi] = acc[r];
         }
     }
+}
+
+template <typename Real, int D>
+__global__ void __launch_bounds__(SGW_BLOCK) prolong_kernel(const ProDev* pro, const FineDev* fine, double* out)
+{
+    prolong_tile<Real, D>((ProC)pro, (FineC)fine, out, blockIdx.x);
+}
+
+// one workgroup per (solve, tile) over many solves of one dimension and precision
+template <typename Real, int D>
+__global__ void __launch_bounds__(SGW_BLOCK) prolong_many_kernel(const ProItem* items)
+{
+    const SGW_CONST ProItem* it = (const SGW_CONST ProItem*)items + blockIdx.x;
+    prolong_tile<Real, D>((ProC)it->pro, (FineC)it->fine, it->out, it->tile);
 }
 
 // ---------------------------------------------------------------- exact solutions
@@ -334,6 +351,31 @@ hipError_t launch_prolong(const ProDev* pro_dev, const FineDev* fine_dev, const 
         }
     }
 #undef SGW_PRO
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_many(const ProItem* items, int nitems, int d, int precision, size_t lds_bytes,
+                               hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+#define SGW_PROM(R, DD) \
+    hipLaunchKernelGGL((prolong_many_kernel<R, DD>), dim3(nitems), dim3(SGW_BLOCK), lds_bytes, s, items)
+    if (precision == SGW_FP64) {
+        switch (d) {
+        case 1: SGW_PROM(double, 1); break;
+        case 2: SGW_PROM(double, 2); break;
+        case 3: SGW_PROM(double, 3); break;
+        default: SGW_PROM(double, 4); break;
+        }
+    } else {
+        switch (d) {
+        case 1: SGW_PROM(float, 1); break;
+        case 2: SGW_PROM(float, 2); break;
+        case 3: SGW_PROM(float, 3); break;
+        default: SGW_PROM(float, 4); break;
+        }
+    }
+#undef SGW_PROM
     return hipGetLastError();
 }
 

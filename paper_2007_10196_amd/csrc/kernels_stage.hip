@@ -482,18 +482,22 @@ __global__ void req_set_final_kernel(ReqDev* r, double T)
 
 // The shared time step (Sec. 3): dt = cfl / sum_k (A_k / h_k^fine), A_k the
 // largest LF speed over all component grids of the solve at u^n, clipped so the
-// last step lands on T.  One thread per solve.
-__device__ void dt_one(ReqDev* r)
+// last step lands on T.  One wavefront per solve: lanes over grids, then a
+// wave-wide max (exact, so the result does not depend on the order).
+__device__ void dt_wave(ReqDev* r)
 {
+    const int lane = threadIdx.x & 63;
     if (!r->active || r->done) {
-        r->dt = 0.0;
+        if (lane == 0) r->dt = 0.0;
         return;
     }
     const double rem = r->T - r->t;
     const double tol = 1e-12 * (r->T > 1.0 ? r->T : 1.0);
     if (!(rem > tol)) {
-        r->done = 1;
-        r->dt = 0.0;
+        if (lane == 0) {
+            r->done = 1;
+            r->dt = 0.0;
+        }
         return;
     }
     double dt;
@@ -503,32 +507,39 @@ __device__ void dt_one(ReqDev* r)
         double denom = 0.0;
         for (int k = 0; k < r->d; k++) {
             double A = 0.0;
-            for (int g = 0; g < r->ngrids; g++) {
+            for (int g = lane; g < r->ngrids; g += 64) {
                 const GridDev* gd = r->grids + g;
                 const double a = gd->dyn_alpha ? __longlong_as_double((long long)gd->alpha[0]) : gd->alpha_c[k];
-                A = (a > A || a != a) ? a : A;
+                A = nanmax(A, a);
             }
+            A = wave_max(A);
             denom += A / r->hfin[k];
         }
         if (denom != denom || denom > 1.7e308) {
-            r->nonfinite = 1;
-            r->done = 1;
-            r->dt = 0.0;
+            if (lane == 0) {
+                r->nonfinite = 1;
+                r->done = 1;
+                r->dt = 0.0;
+            }
             return;
         }
         dt = denom > 0.0 ? r->cfl / denom : rem;
     }
     if (dt > rem) dt = rem;
-    r->dt = dt;
-    r->t += dt;
-    r->steps += 1;
+    if (lane == 0) {
+        r->dt = dt;
+        r->t += dt;
+        r->steps += 1;
+    }
 }
 
-__global__ void dt_kernel(ReqDev* const* reqs, int nreq)
+__global__ void __launch_bounds__(64) dt_kernel(ReqDev* const* reqs, int nreq)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nreq && reqs[i]) dt_one(reqs[i]);
+    const int i = blockIdx.x;
+    if (i < nreq && reqs[i]) dt_wave(reqs[i]);
 }
+
+__global__ void __launch_bounds__(64) dt_one_kernel(ReqDev* r) { dt_wave(r); }
 
 __global__ void gather_done_kernel(ReqDev* const* reqs, int nreq, int* flags)
 {
@@ -536,7 +547,6 @@ __global__ void gather_done_kernel(ReqDev* const* reqs, int nreq, int* flags)
     if (i < nreq) flags[i] = reqs[i] ? (reqs[i]->done ? 1 : 0) | (reqs[i]->nonfinite ? 2 : 0) : 0;
 }
 
-__global__ void dt_one_kernel(ReqDev* r) { dt_one(r); }
 
 } // namespace
 
@@ -618,13 +628,13 @@ hipError_t launch_req_set_final(ReqDev* r, double T, hipStream_t s)
 hipError_t launch_dt(ReqDev* const* reqs, int nreq, hipStream_t s)
 {
     if (nreq <= 0) return hipSuccess;
-    hipLaunchKernelGGL(dt_kernel, dim3((nreq + 63) / 64), dim3(64), 0, s, reqs, nreq);
+    hipLaunchKernelGGL(dt_kernel, dim3(nreq), dim3(64), 0, s, reqs, nreq);
     return hipGetLastError();
 }
 
 hipError_t launch_dt_one(ReqDev* req, hipStream_t s)
 {
-    hipLaunchKernelGGL(dt_one_kernel, dim3(1), dim3(1), 0, s, req);
+    hipLaunchKernelGGL(dt_one_kernel, dim3(1), dim3(64), 0, s, req);
     return hipGetLastError();
 }
 

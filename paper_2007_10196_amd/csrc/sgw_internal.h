@@ -131,6 +131,14 @@ struct alignas(64) FineDev {
     double eps;
 };
 
+// One (solve, finest-grid tile) of a batched prolongation launch.
+struct ProItem {
+    const ProDev* pro;
+    const FineDev* fine;
+    double* out;
+    int32_t tile, pad;
+};
+
 // Problem constants the exact-solution kernels need.
 struct ExactDev {
     int32_t d, flux, ic, N;
@@ -160,6 +168,8 @@ size_t stage_lds_bytes(const GridDev& g, int precision);
 int stage_occupancy(int precision, size_t lds_bytes);
 hipError_t launch_prolong(const ProDev* pro_dev, const FineDev* fine_dev, const FineDev& fine_host,
                           int precision, size_t lds_bytes, double* out, hipStream_t s);
+hipError_t launch_prolong_many(const ProItem* items, int nitems, int d, int precision, size_t lds_bytes,
+                               hipStream_t s);
 hipError_t launch_exact(const ExactDev& e, double* out, double* foot_scratch, hipStream_t s);
 hipError_t launch_norms(const double* a, const double* b, int64_t n, double* partials, double* result,
                         hipStream_t s);

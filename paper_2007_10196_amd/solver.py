@@ -109,6 +109,12 @@ class Solver:
         B.check(B.lib().sgw_norms(self.handle, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), res))
         return res[0], res[1]
 
+    def norms_async(self, a: torch.Tensor, b: torch.Tensor, result: torch.Tensor):
+        """L1, Linf into result[0:2] (device FP64) without synchronising."""
+        assert result.dtype == torch.float64 and result.numel() >= 2 and result.is_cuda
+        B.check(B.lib().sgw_norms_async(self.handle, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
+                                        C.c_void_p(result.data_ptr())))
+
     def query(self) -> Tuple[float, int]:
         t, n = C.c_double(), C.c_int64()
         B.check(B.lib().sgw_query(self.handle, C.byref(t), C.byref(n)))
@@ -210,3 +216,15 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def prolongate_combine_many(solvers, outs, stream: Optional[torch.cuda.Stream] = None):
+    """Combined solutions of many solves (same dimension and precision) in one launch."""
+    n = len(solvers)
+    hs = (C.c_void_p * n)(*[s.handle.value for s in solvers])
+    os_ = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    nbytes = int(B.lib().sgw_prolongate_many_scratch_bytes(hs, n))
+    scratch = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=outs[0].device)
+    B.check(B.lib().sgw_prolongate_combine_many(hs, os_, n, C.c_void_p(scratch.data_ptr()), nbytes,
+                                                _stream_handle(stream)))
+    return outs

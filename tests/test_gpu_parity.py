@@ -241,3 +241,28 @@ def test_advance_before_restrict_is_refused():
     with pytest.raises(B.SgwError) as e:
         s.advance()
     assert e.value.status == -6
+
+
+def test_batched_prolongation_and_async_norms_match_single_calls():
+    torch, B, Solver, _ = _lib()
+    from paper_2007_10196_amd.solver import prolongate_combine_many
+    rng = np.random.default_rng(11)
+    for fam, nl in ((2, 3), (3, 2), (4, 2)):
+        probs = [W.randomized(fam, nl, rng, precision=W.PREC_FP32) for _ in range(3)]
+        probs = [p.replace(T=min(p.T, 0.1)) for p in probs]
+        solvers = [Solver(p) for p in probs]
+        singles = []
+        for s in solvers:
+            s.restrict()
+            s.advance()
+            singles.append(s.prolongate_combine())
+        outs = [torch.empty_like(u) for u in singles]
+        prolongate_combine_many(solvers, outs)
+        res = torch.zeros((len(solvers), 2), dtype=torch.float64, device="cuda")
+        for i, s in enumerate(solvers):
+            assert torch.equal(outs[i], singles[i])
+            ex = s.exact(s.query()[0])
+            s.norms_async(outs[i], ex, res[i])
+            l1, li = s.norms(singles[i], ex)
+            torch.cuda.synchronize()
+            assert res[i, 0].item() == l1 and res[i, 1].item() == li
