@@ -61,9 +61,9 @@ def step_estimate(pb):
 
 
 def run_batch_step(torch, batch, solvers, outs, exacts, res):
-    from paper_2007_10196_amd.solver import prolongate_combine_many
-    for s in solvers:
-        s.restrict()
+    from paper_2007_10196_amd.solver import norms_many, prolongate_combine_many, restrict_many
+    # Alg. Step 1 for every solve in one launch
+    restrict_many(solvers, stream=batch.stream)
     for s in solvers:
         batch.admit(s)
     done = set()
@@ -77,10 +77,9 @@ def run_batch_step(torch, batch, solvers, outs, exacts, res):
         batch.step(2)
     for slot in list(batch.slots):
         batch.release(slot)
-    # Alg. Step 3 for every solve in one launch, then the norms, one synchronisation
+    # Alg. Step 3 for every solve in one launch, then the norms of every solve in one launch
     prolongate_combine_many(solvers, outs, stream=batch.stream)
-    for i, (s, U, E) in enumerate(zip(solvers, outs, exacts)):
-        s.norms_async(U, E, res[i])
+    norms_many(solvers, outs, exacts, res, stream=batch.stream)
     return res.cpu().numpy()
 
 
@@ -253,8 +252,9 @@ def main():
           file=sys.stderr, flush=True)
 
     # ---- the stage kernel alone, same launch shape, HIP events on the batch stream
+    from paper_2007_10196_amd.solver import restrict_many
+    restrict_many(solvers, stream=batch.stream)
     for s in solvers:
-        s.restrict()
         batch.admit(s)
     batch.step(1)
     st = batch.stream

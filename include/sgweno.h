@@ -184,6 +184,26 @@ sgw_status sgw_prolongate_combine_many(sgw_solver_t* const* solvers, double* con
                                        void* scratch_dev, uint64_t scratch_bytes, void* hip_stream);
 uint64_t sgw_prolongate_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n);
 
+/* Alg. Step 1 for many solves in one launch (Sec. 2.2.2): each solve's wave-speed
+ * slots and time-step record are cleared, then every grid of every solve gets
+ * u0 at its nodes, bitwise as sgw_restrict_initial would.  All solves share a
+ * precision.  scratch_dev (device, 256-byte aligned) holds the chunk list,
+ * sgw_restrict_many_scratch_bytes(solvers, n) bytes.  Runs on hip_stream after
+ * waiting for each solver's own stream; synchronises. */
+sgw_status sgw_restrict_initial_many(sgw_solver_t* const* solvers, int32_t n, void* scratch_dev,
+                                     uint64_t scratch_bytes, void* hip_stream);
+uint64_t sgw_restrict_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n);
+
+/* sgw_norms_async for n <= 65535 pairs (a[i], b[i]), each over solve i's finest
+ * grid, in one launch: L1 and Linf of pair i go to result_dev[2i], [2i + 1]
+ * (device FP64), bitwise as sgw_norms gives them.  scratch_dev (device, 256-byte
+ * aligned) holds the pair list and partial sums, sgw_norms_many_scratch_bytes
+ * bytes.  Runs on hip_stream; the caller orders the writes of a and b before
+ * it.  Synchronises. */
+sgw_status sgw_norms_many(sgw_solver_t* const* solvers, const double* const* a_dev, const double* const* b_dev,
+                          int32_t n, double* result_dev, void* scratch_dev, uint64_t scratch_bytes, void* hip_stream);
+uint64_t sgw_norms_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n);
+
 /* Current time and number of steps taken; synchronises.  Returns
  * SGW_ERR_NONFINITE if a wave speed or dt became NaN/Inf. */
 sgw_status sgw_query(sgw_solver_t* solver, double* t, int64_t* steps);

@@ -905,3 +905,135 @@ extern "C" sgw_status sgw_prolongate_combine_many(sgw_solver_t* const* solvers, 
     HIPCHK(hipStreamSynchronize(st), "synchronise");
     return SGW_OK;
 }
+
+// ---------------------------------------------------------------- restriction and norms of many solves
+
+static const int64_t RESTRICT_CHUNK = 8 * SGW_BLOCK;
+
+static int64_t restrict_chunks(const sgw_solver* s)
+{
+    int64_t c = 0;
+    for (const GridDev& g : s->grids_h) {
+        int64_t n = 1;
+        for (int k = 0; k < g.d; k++) n *= g.n[k];
+        c += (n + RESTRICT_CHUNK - 1) / RESTRICT_CHUNK;
+    }
+    return c;
+}
+
+extern "C" uint64_t sgw_restrict_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n)
+{
+    if (!solvers || n <= 0) return 0;
+    int64_t chunks = 0;
+    for (int i = 0; i < n; i++)
+        if (solvers[i]) chunks += restrict_chunks(solvers[i]);
+    return align256((uint64_t)n * sizeof(ResetItem)) + align256((uint64_t)chunks * sizeof(RestrictItem));
+}
+
+extern "C" sgw_status sgw_restrict_initial_many(sgw_solver_t* const* solvers, int32_t n, void* scratch_dev,
+                                                uint64_t scratch_bytes, void* hip_stream)
+{
+    if (!solvers || n <= 0 || !scratch_dev) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    if ((uintptr_t)scratch_dev & 255) return sgw_fail(SGW_ERR_INVALID_ARG, "scratch must be 256-byte aligned");
+    const int prec = solvers[0] ? solvers[0]->plan->cfg.precision : 0;
+    for (int i = 0; i < n; i++) {
+        if (!solvers[i]) return sgw_fail(SGW_ERR_INVALID_ARG, "null solver %d", i);
+        if (solvers[i]->plan->cfg.precision != prec)
+            return sgw_fail(SGW_ERR_INVALID_ARG, "solvers of one call must share their precision");
+    }
+    const uint64_t need = sgw_restrict_many_scratch_bytes(solvers, n);
+    if (need > scratch_bytes)
+        return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "scratch of %llu bytes, %llu needed", (unsigned long long)scratch_bytes,
+                        (unsigned long long)need);
+    const uint64_t off_items = align256((uint64_t)n * sizeof(ResetItem));
+    const int64_t nchunks = (int64_t)((need - off_items) / sizeof(RestrictItem));
+    if (nchunks > 0x7fffffff) return sgw_fail(SGW_ERR_UNSUPPORTED, "too many restriction chunks");
+    std::vector<unsigned char> host(need);
+    ResetItem* resets = (ResetItem*)host.data();
+    RestrictItem* items = (RestrictItem*)(host.data() + off_items);
+    int64_t c = 0;
+    for (int i = 0; i < n; i++) {
+        sgw_solver* s = solvers[i];
+        resets[i] = ResetItem{s->alpha_d, s->req_d, 4 * s->plan->G, 0};
+        for (int g = 0; g < s->plan->G; g++) {
+            const GridDev& gd = s->grids_h[g];
+            int64_t total = 1;
+            for (int k = 0; k < gd.d; k++) total *= gd.n[k];
+            for (int64_t st = 0; st < total; st += RESTRICT_CHUNK) {
+                RestrictItem& it = items[c++];
+                it.g = s->grids_d + g;
+                it.start = st;
+                it.count = (int32_t)(total - st < RESTRICT_CHUNK ? total - st : RESTRICT_CHUNK);
+                it.ic = s->plan->pb.ic;
+                for (int q = 0; q < 8; q++) it.ip[q] = s->plan->pb.ic_params[q];
+            }
+        }
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    // earlier work of each solve on its own stream may still read its state
+    for (int i = 0; i < n; i++)
+        if (solvers[i]->stream != st) HIPCHK(hipStreamSynchronize(solvers[i]->stream), "synchronise solver stream");
+    HIPCHK(hipMemcpyAsync(scratch_dev, host.data(), need, hipMemcpyHostToDevice, st), "upload restriction list");
+    const unsigned char* base = (const unsigned char*)scratch_dev;
+    HIPCHK(launch_restrict_many((const ResetItem*)base, n, (const RestrictItem*)(base + off_items), (int)c, prec, st),
+           "restrict many");
+    // the host list must outlive the copy
+    HIPCHK(hipStreamSynchronize(st), "synchronise");
+    for (int i = 0; i < n; i++) {
+        solvers[i]->restricted = true;
+        solvers[i]->t_host = 0.0;
+    }
+    return SGW_OK;
+}
+
+static int norms_many_max_parts(sgw_solver_t* const* solvers, int32_t n)
+{
+    int mp = 1;
+    for (int i = 0; i < n; i++)
+        if (solvers[i]) {
+            const int p = norms_parts(solvers[i]->plan->fine_nodes);
+            mp = p > mp ? p : mp;
+        }
+    return mp;
+}
+
+extern "C" uint64_t sgw_norms_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n)
+{
+    if (!solvers || n <= 0) return 0;
+    const int mp = norms_many_max_parts(solvers, n);
+    return align256((uint64_t)n * sizeof(NormItem)) + align256((uint64_t)n * 2 * mp * sizeof(double));
+}
+
+extern "C" sgw_status sgw_norms_many(sgw_solver_t* const* solvers, const double* const* a, const double* const* b,
+                                     int32_t n, double* result_dev, void* scratch_dev, uint64_t scratch_bytes,
+                                     void* hip_stream)
+{
+    if (!solvers || !a || !b || n <= 0 || !result_dev || !scratch_dev)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    if (n > 65535) return sgw_fail(SGW_ERR_INVALID_ARG, "at most 65535 pairs per call, %d given", n);
+    if ((uintptr_t)scratch_dev & 255) return sgw_fail(SGW_ERR_INVALID_ARG, "scratch must be 256-byte aligned");
+    for (int i = 0; i < n; i++)
+        if (!solvers[i] || !a[i] || !b[i]) return sgw_fail(SGW_ERR_INVALID_ARG, "null solver or array %d", i);
+    const uint64_t need = sgw_norms_many_scratch_bytes(solvers, n);
+    if (need > scratch_bytes)
+        return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "scratch of %llu bytes, %llu needed", (unsigned long long)scratch_bytes,
+                        (unsigned long long)need);
+    const int mp = norms_many_max_parts(solvers, n);
+    std::vector<NormItem> items(n);
+    for (int i = 0; i < n; i++) {
+        const int64_t cnt = solvers[i]->plan->fine_nodes;
+        items[i] = NormItem{a[i], b[i], cnt, result_dev + 2 * (size_t)i, norms_parts(cnt), 0};
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    for (int i = 0; i < n; i++)
+        if (solvers[i]->stream != st) HIPCHK(hipStreamSynchronize(solvers[i]->stream), "synchronise solver stream");
+    unsigned char* base = (unsigned char*)scratch_dev;
+    HIPCHK(hipMemcpyAsync(base, items.data(), sizeof(NormItem) * (size_t)n, hipMemcpyHostToDevice, st),
+           "upload norm list");
+    HIPCHK(launch_norms_many((const NormItem*)base, n, mp, (double*)(base + align256((uint64_t)n * sizeof(NormItem))),
+                             st),
+           "norms many");
+    // the host list must outlive the copy
+    HIPCHK(hipStreamSynchronize(st), "synchronise");
+    return SGW_OK;
+}

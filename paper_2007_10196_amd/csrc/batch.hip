@@ -4,6 +4,7 @@
 // each a single persistent launch over the boxes of every admitted solve.  The
 // box list and its length live in device memory, so admitting or releasing a
 // solve is a stream-ordered copy and the graph stays valid.
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -21,10 +22,14 @@ struct sgw_batch {
     WorkItem* items_d = nullptr;    // [max_items]
     int* nitems_d = nullptr;
     int* flags_d = nullptr;         // [max_solvers]
+    double* tf_d = nullptr;         // [max_solvers] final times of new slots (NaN: unchanged)
     int* flags_pinned = nullptr;
     std::vector<sgw_solver*> slots;
     std::vector<uint64_t> slot_bytes;
     std::vector<ReqDev*> reqs_h;
+    std::vector<double> tf_h;
+    bool tf_pending = false;
+    bool queued = false;            // step launches may still be in flight on the stream
     std::vector<WorkItem> items_h;
     int nitems_h = 0;
     bool dirty = true;
@@ -41,7 +46,7 @@ extern "C" uint64_t sgw_batch_scratch_bytes(int32_t max_solvers, int64_t max_ite
 {
     if (max_solvers < 1 || max_items < 1) return 0;
     return a256(sizeof(ReqDev*) * (uint64_t)max_solvers) + a256(sizeof(WorkItem) * (uint64_t)max_items) + 256 +
-           a256(sizeof(int) * (uint64_t)max_solvers);
+           a256(sizeof(int) * (uint64_t)max_solvers) + a256(sizeof(double) * (uint64_t)max_solvers);
 }
 
 extern "C" sgw_status sgw_batch_create(int32_t max_solvers, int32_t precision, uint64_t hbm_budget, void* hip_stream,
@@ -71,10 +76,13 @@ extern "C" sgw_status sgw_batch_create(int32_t max_solvers, int32_t precision, u
     off += 256;
     b->flags_d = (int*)(b->scratch + off);
     off += a256(sizeof(int) * (uint64_t)max_solvers);
+    b->tf_d = (double*)(b->scratch + off);
+    off += a256(sizeof(double) * (uint64_t)max_solvers);
     b->items_d = (WorkItem*)(b->scratch + off);
     b->slots.assign(max_solvers, nullptr);
     b->slot_bytes.assign(max_solvers, 0);
     b->reqs_h.assign(max_solvers, nullptr);
+    b->tf_h.assign(max_solvers, NAN);
     hipError_t e = hipHostMalloc((void**)&b->flags_pinned, sizeof(int) * max_solvers, hipHostMallocDefault);
     if (e != hipSuccess) {
         delete b;
@@ -134,9 +142,18 @@ static sgw_status batch_sync(sgw_batch* b)
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->reqs_d, b->reqs_h.data(), sizeof(ReqDev*) * b->max_solvers, hipMemcpyHostToDevice,
                            b->stream);
+    if (e == hipSuccess && b->tf_pending) {
+        e = hipMemcpyAsync(b->tf_d, b->tf_h.data(), sizeof(double) * b->max_solvers, hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = launch_req_set_final_many(b->reqs_d, b->tf_d, b->max_solvers, b->stream);
+    }
     // the host vectors are read by the copies: wait before they can change
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return sgw_hip_fail(e, "upload batch lists");
+    b->queued = false;
+    if (b->tf_pending) {
+        for (double& t : b->tf_h) t = NAN;
+        b->tf_pending = false;
+    }
     if (!b->exec || lds > b->lds) {
         batch_drop_graph(b);
         b->lds = lds;
@@ -187,8 +204,9 @@ extern "C" sgw_status sgw_batch_admit(sgw_batch_t* b, sgw_solver_t* s, double t_
         hipError_t e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) return sgw_hip_fail(e, "synchronise solver stream");
     }
-    hipError_t e = launch_req_set_final(s->req_d, t_final, b->stream);
-    if (e != hipSuccess) return sgw_hip_fail(e, "set final time");
+    // the final time reaches the device with the next upload of the slot table
+    b->tf_h[free_slot] = t_final;
+    b->tf_pending = true;
     b->slots[free_slot] = s;
     b->slot_bytes[free_slot] = need;
     b->reqs_h[free_slot] = s->req_d;
@@ -207,6 +225,7 @@ extern "C" sgw_status sgw_batch_step(sgw_batch_t* b, int32_t nsteps)
     if (rc != SGW_OK) return rc;
     if (!b->nitems_h) return SGW_OK;
     for (int i = 0; i < nsteps; i++) {
+        b->queued = true;
         hipError_t e = hipGraphLaunch(b->exec, b->stream);
         if (e != hipSuccess) return sgw_hip_fail(e, "batch graph launch");
     }
@@ -223,6 +242,7 @@ extern "C" sgw_status sgw_batch_poll(sgw_batch_t* b, int32_t* done_slots, int32_
         e = hipMemcpyAsync(b->flags_pinned, b->flags_d, sizeof(int) * b->max_solvers, hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return sgw_hip_fail(e, "poll batch");
+    b->queued = false;
     int n = 0;
     bool bad = false;
     for (int i = 0; i < b->max_solvers; i++) {
@@ -242,6 +262,7 @@ extern "C" sgw_status sgw_batch_launch_stage(sgw_batch_t* b, int32_t stage, int3
     sgw_status rc = batch_sync(b);
     if (rc != SGW_OK) return rc;
     for (int i = 0; i < reps; i++) {
+        b->queued = true;
         hipError_t e = launch_stage_dev_count(b->items_d, b->nitems_d, b->blocks, stage, b->precision, b->lds, b->stream);
         if (e != hipSuccess) return sgw_hip_fail(e, "stage launch");
     }
@@ -270,9 +291,13 @@ extern "C" sgw_status sgw_batch_release(sgw_batch_t* b, int32_t slot)
     if (!b) return sgw_fail(SGW_ERR_INVALID_ARG, "null batch");
     if (slot < 0 || slot >= b->max_solvers || !b->slots[slot]) return sgw_fail(SGW_ERR_INVALID_ARG, "bad slot %d", slot);
     // the slot's solve may still be referenced by queued graph launches
-    hipError_t e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) return sgw_hip_fail(e, "synchronise batch");
+    if (b->queued) {
+        hipError_t e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return sgw_hip_fail(e, "synchronise batch");
+        b->queued = false;
+    }
     b->slots[slot]->batch_slot = -1;
+    b->tf_h[slot] = NAN;
     b->used -= b->slot_bytes[slot];
     b->slots[slot] = nullptr;
     b->slot_bytes[slot] = 0;

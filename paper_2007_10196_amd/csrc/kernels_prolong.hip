@@ -277,12 +277,14 @@ __global__ void exact_kernel(ExactDev e, double* out)
 
 // ---------------------------------------------------------------- norms (fixed order)
 
-__global__ void norms_partial_kernel(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
-                                     double* partials)
+// First pass: workgroup blk of `parts` reduces its strided share of |a - b|
+// (sum and NaN-keeping max) in a fixed tree order.
+__device__ void norms_partial_block(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                                    int parts, int blk, double* out2)
 {
     __shared__ double ss[SGW_BLOCK], sm[SGW_BLOCK];
     double s = 0.0, mx = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)SGW_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * SGW_BLOCK) {
+    for (int64_t i = blk * (int64_t)SGW_BLOCK + threadIdx.x; i < n; i += (int64_t)parts * SGW_BLOCK) {
         const double d = fabs(a[i] - b[i]);
         s += d;
         mx = (d > mx || d != d) ? d : mx;
@@ -299,12 +301,13 @@ __global__ void norms_partial_kernel(const double* __restrict__ a, const double*
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = ss[0];
-        partials[2 * blockIdx.x + 1] = sm[0];
+        out2[0] = ss[0];
+        out2[1] = sm[0];
     }
 }
 
-__global__ void norms_final_kernel(const double* partials, int np, int64_t n, double* result)
+// Second pass: the np partials, zero-padded to SGW_NPART, in a fixed tree order.
+__device__ void norms_final_block(const double* partials, int np, int64_t n, double* result)
 {
     __shared__ double ss[SGW_NPART], sm[SGW_NPART];
     for (int i = threadIdx.x; i < SGW_NPART; i += blockDim.x) {
@@ -324,6 +327,32 @@ __global__ void norms_final_kernel(const double* partials, int np, int64_t n, do
         result[0] = n > 0 ? ss[0] / (double)n : 0.0;
         result[1] = sm[0];
     }
+}
+
+__global__ void norms_partial_kernel(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                                     double* partials)
+{
+    norms_partial_block(a, b, n, gridDim.x, blockIdx.x, partials + 2 * blockIdx.x);
+}
+
+__global__ void norms_final_kernel(const double* partials, int np, int64_t n, double* result)
+{
+    norms_final_block(partials, np, n, result);
+}
+
+// Many pairs in one launch: blockIdx.y is the pair, the same per-pair order as above.
+__global__ void norms_partial_many_kernel(const NormItem* items, double* partials, int stride)
+{
+    const NormItem* it = items + blockIdx.y;
+    if ((int)blockIdx.x >= it->parts) return;
+    norms_partial_block(it->a, it->b, it->n, it->parts, blockIdx.x,
+                        partials + (size_t)blockIdx.y * stride + 2 * blockIdx.x);
+}
+
+__global__ void norms_final_many_kernel(const NormItem* items, const double* partials, int stride)
+{
+    const NormItem* it = items + blockIdx.x;
+    norms_final_block(partials + (size_t)blockIdx.x * stride, it->parts, it->n, it->result);
 }
 
 } // namespace
@@ -392,11 +421,29 @@ hipError_t launch_exact(const ExactDev& e, double* out, double* foot_scratch, hi
     return hipGetLastError();
 }
 
+int norms_parts(int64_t n)
+{
+    const int64_t p = (n + SGW_BLOCK - 1) / SGW_BLOCK;
+    return p < 1 ? 1 : (p > SGW_NPART ? SGW_NPART : (int)p);
+}
+
 hipError_t launch_norms(const double* a, const double* b, int64_t n, double* partials, double* result, hipStream_t s)
 {
-    hipLaunchKernelGGL(norms_partial_kernel, dim3(SGW_NPART), dim3(SGW_BLOCK), 0, s, a, b, n, partials);
+    const int parts = norms_parts(n);
+    hipLaunchKernelGGL(norms_partial_kernel, dim3(parts), dim3(SGW_BLOCK), 0, s, a, b, n, partials);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(norms_final_kernel, dim3(1), dim3(SGW_BLOCK), 0, s, partials, SGW_NPART, n, result);
+    hipLaunchKernelGGL(norms_final_kernel, dim3(1), dim3(SGW_BLOCK), 0, s, partials, parts, n, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_norms_many(const NormItem* items, int n, int max_parts, double* partials, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(norms_partial_many_kernel, dim3(max_parts, n), dim3(SGW_BLOCK), 0, s, items, partials,
+                       2 * max_parts);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(norms_final_many_kernel, dim3(n), dim3(SGW_BLOCK), 0, s, items, partials, 2 * max_parts);
     return hipGetLastError();
 }

@@ -423,7 +423,33 @@ struct RestrictArgs {
     double ip[8];
 };
 
-// Alg. Step 1: evaluate the initial condition at the nodes x_j = lo + j h.
+// Alg. Step 1: the initial condition at node idx (row-major, direction 1
+// fastest) of grid g, whose coordinates are x_j = lo + j h.
+__device__ __forceinline__ double ic_value(const GridDev* g, int64_t idx, int ic, const double* ip)
+{
+    uint32_t r = (uint32_t)idx;
+    double x[SGW_MAX_DIM] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < g->d; k++) {
+        const uint32_t q = FDIV(r, g->fd_n[k]);
+        const int j = (int)(r - q * (uint32_t)g->n[k]);
+        r = q;
+        x[k] = g->lo[k] + j * g->h[k];
+    }
+    if (ic == SGW_IC_SINE) {
+        double s = 0.0;
+        for (int k = 0; k < g->d; k++) s += x[k];
+        return ip[0] + ip[1] * sin(ip[2] * s + ip[3]);
+    }
+    const int m = g->d / 2;
+    double v2 = 0.0, pert = 1.0, norm = 1.0;
+    for (int k = 0; k < m; k++) {
+        v2 += x[m + k] * x[m + k];
+        pert *= cos(ip[1] * x[k] + ip[2 + k]);
+        norm *= 2.0 * M_PI;
+    }
+    return exp(-0.5 * v2) / sqrt(norm) * (1.0 + ip[0] * pert);
+}
+
 template <typename Real>
 __global__ void restrict_kernel(const GridDev* grids, RestrictArgs a)
 {
@@ -435,37 +461,32 @@ __global__ void restrict_kernel(const GridDev* grids, RestrictArgs a)
     double amax = 0.0;
     for (int64_t idx = blockIdx.x * (int64_t)SGW_BLOCK + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * SGW_BLOCK) {
-        uint32_t r = (uint32_t)idx;
-        double x[SGW_MAX_DIM] = {0.0, 0.0, 0.0, 0.0};
-        for (int k = 0; k < g->d; k++) {
-            const uint32_t q = FDIV(r, g->fd_n[k]);
-            const int j = (int)(r - q * (uint32_t)g->n[k]);
-            r = q;
-            x[k] = g->lo[k] + j * g->h[k];
-        }
-        double v;
-        if (a.ic == SGW_IC_SINE) {
-            double s = 0.0;
-            for (int k = 0; k < g->d; k++) s += x[k];
-            v = a.ip[0] + a.ip[1] * sin(a.ip[2] * s + a.ip[3]);
-        } else {
-            const int m = g->d / 2;
-            double v2 = 0.0, pert = 1.0, norm = 1.0;
-            for (int k = 0; k < m; k++) {
-                v2 += x[m + k] * x[m + k];
-                pert *= cos(a.ip[1] * x[k] + a.ip[2 + k]);
-                norm *= 2.0 * M_PI;
-            }
-            v = exp(-0.5 * v2) / sqrt(norm) * (1.0 + a.ip[0] * pert);
-        }
-        const Real vr = (Real)v;
+        const Real vr = (Real)ic_value(g, idx, a.ic, a.ip);
         u[idx] = vr;
         amax = nanmax(amax, fabs((double)vr));
     }
     if (g->dyn_alpha) block_atomic_max(amax, g->alpha + 0, red);
 }
 
-__global__ void req_reset_kernel(ReqDev* r)
+// Restriction of many solves in one launch: one workgroup per chunk of a grid.
+template <typename Real>
+__global__ void restrict_many_kernel(const RestrictItem* items)
+{
+    __shared__ double red[SGW_BLOCK / 64];
+    const RestrictItem* it = items + blockIdx.x;
+    const GridDev* g = it->g;
+    Real* u = (Real*)g->u;
+    double amax = 0.0;
+    for (int i = threadIdx.x; i < it->count; i += SGW_BLOCK) {
+        const int64_t idx = it->start + i;
+        const Real vr = (Real)ic_value(g, idx, it->ic, it->ip);
+        u[idx] = vr;
+        amax = nanmax(amax, fabs((double)vr));
+    }
+    if (g->dyn_alpha) block_atomic_max(amax, g->alpha + 0, red);
+}
+
+__device__ __forceinline__ void req_reset(ReqDev* r)
 {
     r->t = 0.0;
     r->steps = 0;
@@ -474,8 +495,31 @@ __global__ void req_reset_kernel(ReqDev* r)
     r->dt = 0.0;
 }
 
+// Before a restriction of many solves: clear each solve's wave-speed slots and
+// rewind its time-step record (one workgroup per solve).
+__global__ void reset_many_kernel(const ResetItem* items)
+{
+    const ResetItem* it = items + blockIdx.x;
+    for (int i = threadIdx.x; i < it->nalpha; i += blockDim.x) it->alpha[i] = 0ull;
+    if (threadIdx.x == 0) req_reset(it->req);
+}
+
+__global__ void req_reset_kernel(ReqDev* r) { req_reset(r); }
+
 __global__ void req_set_final_kernel(ReqDev* r, double T)
 {
+    r->T = T;
+    r->done = r->nonfinite ? 1 : 0;
+}
+
+// Final times of newly admitted batch slots; a NaN entry leaves its slot alone.
+__global__ void req_set_final_many_kernel(ReqDev* const* reqs, const double* tf, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ReqDev* r = reqs[i];
+    const double T = tf[i];
+    if (!r || T != T) return;
     r->T = T;
     r->done = r->nonfinite ? 1 : 0;
 }
@@ -622,6 +666,30 @@ hipError_t launch_req_reset(ReqDev* r, hipStream_t s)
 hipError_t launch_req_set_final(ReqDev* r, double T, hipStream_t s)
 {
     hipLaunchKernelGGL(req_set_final_kernel, dim3(1), dim3(1), 0, s, r, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_req_set_final_many(ReqDev* const* reqs, const double* tf, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(req_set_final_many_kernel, dim3((n + SGW_BLOCK - 1) / SGW_BLOCK), dim3(SGW_BLOCK), 0, s, reqs,
+                       tf, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict_many(const ResetItem* resets, int nresets, const RestrictItem* items, int nitems,
+                                int precision, hipStream_t s)
+{
+    if (nresets > 0) {
+        hipLaunchKernelGGL(reset_many_kernel, dim3(nresets), dim3(64), 0, s, resets);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (nitems <= 0) return hipSuccess;
+    if (precision == SGW_FP64)
+        hipLaunchKernelGGL(restrict_many_kernel<double>, dim3(nitems), dim3(SGW_BLOCK), 0, s, items);
+    else
+        hipLaunchKernelGGL(restrict_many_kernel<float>, dim3(nitems), dim3(SGW_BLOCK), 0, s, items);
     return hipGetLastError();
 }
 

@@ -9,7 +9,7 @@
 
 #define SGW_BLOCK 256     // threads per workgroup of every kernel (4 wave64)
 #define SGW_MAXR 8        // nodes per thread in the stage kernel: box core <= SGW_BLOCK * SGW_MAXR
-#define SGW_NPART 1024    // workgroups of the first norm pass (fixed, so the sum order is fixed)
+#define SGW_NPART 1024    // most workgroups of the first norm pass (their count depends on n only)
 #define SGW_SEG 4         // interfaces per thread along directions 2..d (sliding window)
 
 // Division by a run-time constant d >= 1 for numerators below 2^31:
@@ -139,6 +139,31 @@ struct ProItem {
     int32_t tile, pad;
 };
 
+// One chunk of one component grid in a restriction over many solves.
+struct RestrictItem {
+    const GridDev* g;
+    int64_t start;                   // first node of the chunk
+    int32_t count;                   // nodes in the chunk
+    int32_t ic;
+    double ip[8];
+};
+
+// One solve's wave-speed slots and time-step record, cleared before its restriction.
+struct ResetItem {
+    unsigned long long* alpha;
+    ReqDev* req;
+    int32_t nalpha, pad;
+};
+
+// One (computed, reference) pair of a norms launch over many solves.
+struct NormItem {
+    const double* a;
+    const double* b;
+    int64_t n;
+    double* result;                  // L1, Linf
+    int32_t parts, pad;              // first-pass workgroups of this pair
+};
+
 // Problem constants the exact-solution kernels need.
 struct ExactDev {
     int32_t d, flux, ic, N;
@@ -157,6 +182,9 @@ hipError_t launch_restrict(const GridDev* grids_dev, const GridDev* grids_host, 
                            const sgw_problem* pb, hipStream_t s);
 hipError_t launch_req_reset(ReqDev* r, hipStream_t s);
 hipError_t launch_req_set_final(ReqDev* r, double T, hipStream_t s);
+hipError_t launch_req_set_final_many(ReqDev* const* reqs, const double* tf, int n, hipStream_t s);
+hipError_t launch_restrict_many(const ResetItem* resets, int nresets, const RestrictItem* items, int nitems,
+                                int precision, hipStream_t s);
 hipError_t launch_dt(ReqDev* const* reqs, int nreq, hipStream_t s);
 hipError_t launch_dt_one(ReqDev* req, hipStream_t s);
 hipError_t launch_stage(const WorkItem* items, int nitems, int stage, int precision, int dim_max,
@@ -173,3 +201,5 @@ hipError_t launch_prolong_many(const ProItem* items, int nitems, int d, int prec
 hipError_t launch_exact(const ExactDev& e, double* out, double* foot_scratch, hipStream_t s);
 hipError_t launch_norms(const double* a, const double* b, int64_t n, double* partials, double* result,
                         hipStream_t s);
+int norms_parts(int64_t n);
+hipError_t launch_norms_many(const NormItem* items, int n, int max_parts, double* partials, hipStream_t s);

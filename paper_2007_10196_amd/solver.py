@@ -228,3 +228,30 @@ def prolongate_combine_many(solvers, outs, stream: Optional[torch.cuda.Stream] =
     B.check(B.lib().sgw_prolongate_combine_many(hs, os_, n, C.c_void_p(scratch.data_ptr()), nbytes,
                                                 _stream_handle(stream)))
     return outs
+
+
+def restrict_many(solvers, stream: Optional[torch.cuda.Stream] = None):
+    """Initial values of many solves (one precision) in one launch."""
+    n = len(solvers)
+    hs = (C.c_void_p * n)(*[s.handle.value for s in solvers])
+    nbytes = int(B.lib().sgw_restrict_many_scratch_bytes(hs, n))
+    scratch = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=solvers[0].device)
+    B.check(B.lib().sgw_restrict_initial_many(hs, n, C.c_void_p(scratch.data_ptr()), nbytes, _stream_handle(stream)))
+    return solvers
+
+
+def norms_many(solvers, a, b, result: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
+    """L1, Linf of (a[i] - b[i]) over solve i's finest grid into result[i, 0:2] (device FP64)."""
+    n = len(solvers)
+    assert result.dtype == torch.float64 and result.is_cuda and result.is_contiguous() and result.numel() >= 2 * n
+    for x, y, s in zip(a, b, solvers):
+        assert x.dtype == torch.float64 and y.dtype == torch.float64
+        assert x.numel() >= s.plan.fine_nodes and y.numel() >= s.plan.fine_nodes
+    hs = (C.c_void_p * n)(*[s.handle.value for s in solvers])
+    pa = (C.c_void_p * n)(*[x.data_ptr() for x in a])
+    pb = (C.c_void_p * n)(*[y.data_ptr() for y in b])
+    nbytes = int(B.lib().sgw_norms_many_scratch_bytes(hs, n))
+    scratch = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=result.device)
+    B.check(B.lib().sgw_norms_many(hs, pa, pb, n, C.c_void_p(result.data_ptr()), C.c_void_p(scratch.data_ptr()),
+                                   nbytes, _stream_handle(stream)))
+    return result

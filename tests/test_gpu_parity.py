@@ -266,3 +266,51 @@ def test_batched_prolongation_and_async_norms_match_single_calls():
             l1, li = s.norms(singles[i], ex)
             torch.cuda.synchronize()
             assert res[i, 0].item() == l1 and res[i, 1].item() == li
+
+
+def test_restrict_many_and_norms_many_match_single_calls():
+    """One-launch restriction and norms over solves of mixed dimension equal the per-solve calls bitwise;
+    a used solver restricted again starts from t = 0 with cleared wave speeds."""
+    torch, B, Solver, _ = _lib()
+    from paper_2007_10196_amd.solver import norms_many, restrict_many
+    rng = np.random.default_rng(23)
+    for prec in (W.PREC_FP32, W.PREC_FP64):
+        _announce(f"restrict_many / norms_many precision {prec}")
+        probs = [W.randomized(fam, nl, rng, precision=prec) for fam, nl in ((1, 3), (2, 4), (3, 2), (4, 2), (2, 2))]
+        probs = [p.replace(T=min(p.T, 0.05)) for p in probs]
+        single = [Solver(p) for p in probs]
+        many = [Solver(p) for p in probs]
+        for s in many:  # leave state, time and wave speeds behind, to be reset
+            s.restrict()
+            s.advance()
+        outs_s, outs_m = [], []
+        for s in single:
+            s.restrict()
+        restrict_many(many)
+        for a, b in zip(single, many):
+            assert torch.equal(a.state_copy(0), b.state_copy(0))
+            assert b.query() == (0.0, 0)
+        for a, b in zip(single, many):
+            a.advance()
+            b.advance()
+            assert a.query() == b.query()
+            outs_s.append(a.prolongate_combine())
+            outs_m.append(b.prolongate_combine())
+            assert torch.equal(outs_s[-1], outs_m[-1])
+        exacts = [s.exact(s.query()[0]) for s in single]
+        res = torch.full((len(many), 2), -1.0, dtype=torch.float64, device="cuda")
+        norms_many(many, outs_m, exacts, res)
+        for i, s in enumerate(single):
+            l1, li = s.norms(outs_s[i], exacts[i])
+            assert res[i, 0].item() == l1 and res[i, 1].item() == li
+            assert 0.0 < l1 <= li
+
+
+def test_restrict_many_rejects_mixed_precision():
+    torch, B, Solver, _ = _lib()
+    from paper_2007_10196_amd.solver import restrict_many
+    a = Solver(W.c1_advection_2d())
+    b = Solver(W.c1_advection_2d().replace(precision=W.PREC_FP32))
+    with pytest.raises(B.SgwError) as e:
+        restrict_many([a, b])
+    assert e.value.status == -1
