@@ -121,7 +121,7 @@ def copy_calibration():
 SERVING_N = 128
 
 
-def serving_run(capacity, box_target, n=None, load=0.7):
+def serving_run(capacity, box_target, n=None, load=0.7, blocks_per_cu=0):
     """Seeded Poisson stream mixing the 2D advection, 2D Burgers, 3D advection and 4D Vlasov
     workloads at finest levels 2..5 (4D capped at 4), FP32 sweeps; the arrival rate is set so the
     offered cell-updates/s are `load` x the measured batched capacity."""
@@ -138,7 +138,7 @@ def serving_run(capacity, box_target, n=None, load=0.7):
     rate = load * capacity / (sum(work) / len(work))
     reqs = W.serving_stream(n=n, rate_hz=rate, max_level_by_family={4: 4})
     loop = ServingLoop(precision=B.FP32_SWEEP, max_active=64, hbm_budget=96 << 30, steps_per_tick=8,
-                       box_target=box_target)
+                       box_target=box_target, blocks_per_cu=blocks_per_cu)
     t0 = time.perf_counter()
     res = loop.run(reqs)
     wall = time.perf_counter() - t0
@@ -194,7 +194,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=20)
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--box-target", type=int, default=0, help="0: autotune the stage box target")
+    ap.add_argument("--box-target", type=int, default=0,
+                    help="0: autotune the stage box target and the workgroups per compute unit")
+    ap.add_argument("--blocks-per-cu", type=int, default=0, help="with --box-target: stage workgroups per CU")
     ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 1 GiB copy used to scale the HBM byte counters")
@@ -216,11 +218,13 @@ def main():
     # box shape for this batch (untimed): fastest of the candidate targets, cached in JSON
     from paper_2007_10196_amd.autotune import tune_box_target
     if args.box_target:
-        tune = {"best": args.box_target, "us": None, "cached": True}
+        tune = {"best": args.box_target, "blocks_per_cu": args.blocks_per_cu, "us": None, "cached": True}
     else:
         tune = tune_box_target(probs, B.FP32_SWEEP, reps=5)
     box_target = int(tune["best"])
-    print(f"[bench] autotuned box target {box_target} ({'cached' if tune['cached'] else 'measured'})",
+    bpc = int(tune.get("blocks_per_cu", 0))
+    print(f"[bench] launch shape: box target {box_target}, {bpc or 'max'} workgroups per CU "
+          f"({'cached' if tune['cached'] else 'measured'})",
           file=sys.stderr, flush=True)
     solvers = [Solver(p, device="cuda:0", box_target=box_target) for p in probs]
     nodes = solvers[0].plan.total_nodes
@@ -231,6 +235,7 @@ def main():
     budget = sum(s.plan.footprint for s in solvers) + (1 << 30)
     batch = Batch(max_solvers=len(solvers), precision=B.FP32_SWEEP, hbm_budget=budget,
                   max_items=sum(len(s.plan.grids) * 64 for s in solvers))
+    batch.set_blocks_per_cu(bpc)
     print(f"[bench] {len(solvers)} solves x {nodes} component nodes, warmup {args.warmup}", file=sys.stderr,
           flush=True)
 
@@ -299,7 +304,7 @@ def main():
                  "speedup_of_value": value / (stp * nodes / tp),
                  "equal_l1": bool(abs(l1s[0] - l1p) <= 0.01 * l1p), "l1_batched_fp32_same_solve": float(l1s[0])}
 
-    serving = None if args.no_serving else serving_run(value, box_target)
+    serving = None if args.no_serving else serving_run(value, box_target, blocks_per_cu=bpc)
 
     cpu = None if args.no_cpu else cpu_baseline()
 
@@ -312,7 +317,7 @@ def main():
                       "mode": "batched: one HIP graph per time step, persistent fused WENO5+RK3 stage launch"},
            "l1_mean": float(l1s.mean()), "l1_max": float(l1s.max()),
            "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "latency": serving,
-           "autotune": {"box_target": box_target, "stage_us_by_target": tune["us"]}}
+           "autotune": {"box_target": box_target, "blocks_per_cu": bpc, "stage_us_by_target_and_cap": tune["us"]}}
     print(json.dumps(out), flush=True)
 
 

@@ -98,7 +98,8 @@ typedef struct sgw_config {
     int32_t fine_tile[SGW_MAX_DIM];/* 0: automatic; else the prolongation tile per direction       */
     int32_t box_target;            /* 0: automatic; else the largest box (nodes) the automatic
                                       box search may pick, 256..2048                               */
-    int32_t reserved1;             /* must be 0                                                    */
+    int32_t blocks_per_cu;         /* 0: as many resident stage workgroups per compute unit as
+                                      fit; else at most this many (1..64), a tuning knob         */
 } sgw_config;
 
 typedef struct sgw_plan sgw_plan_t;
@@ -235,6 +236,12 @@ sgw_status sgw_batch_release(sgw_batch_t* batch, int32_t slot);
  * first stage buffer, so repeating it leaves u^n unchanged; the solves' wave
  * speed slots are disturbed, so re-restrict before trusting later results. */
 sgw_status sgw_batch_launch_stage(sgw_batch_t* batch, int32_t stage, int32_t reps);
+/* Tuning knob: at most blocks_per_cu resident stage workgroups per compute unit
+ * (0: as many as fit).  The persistent stage launch splits the box list into
+ * equal contiguous ranges over its workgroups, so this trades latency hiding
+ * against the share of the last, partly filled round.  Waits for queued steps;
+ * the step graph is captured again on the next step. */
+sgw_status sgw_batch_set_blocks_per_cu(sgw_batch_t* batch, int32_t blocks_per_cu);
 /* Number of stage boxes currently in the batch. */
 sgw_status sgw_batch_info(const sgw_batch_t* batch, int32_t* active_solvers, int64_t* boxes, int64_t* nodes);
 

@@ -1,11 +1,11 @@
-"""Box-shape tuner for the stage kernel.
+"""Launch-shape tuner for the stage kernel.
 
 For a set of problems (one batch), every candidate box target (the largest box,
-in nodes, the planner's box search may pick for each component grid) is tried:
-the batch is restricted and admitted, one step is taken, and a few standalone
-stage launches are timed with HIP events on the batch stream.  The fastest
-target is returned and cached in a JSON file keyed by the batch's grid shapes
-and precision.
+in nodes, the planner's box search may pick for each component grid) is tried
+with every candidate cap on resident workgroups per compute unit: the batch is
+restricted and admitted, one step is taken, and a few standalone stage launches
+are timed with HIP events on the batch stream.  The fastest pair is returned and
+cached in a JSON file keyed by the batch's grid shapes and precision.
 """
 from __future__ import annotations
 
@@ -18,7 +18,8 @@ import torch
 
 from .solver import Batch, Plan, Solver
 
-CANDIDATES = (256, 512, 1024, 2048)
+CANDIDATES = (512, 1024, 2048)
+BLOCKS_PER_CU = (0, 4, 5, 6, 7)     # 0: as many as fit
 
 
 def default_cache_path() -> str:
@@ -27,7 +28,7 @@ def default_cache_path() -> str:
 
 def workload_key(problems: Sequence, precision: int) -> str:
     shapes = sorted({(p.d, p.nr, p.nl, p.flux) for p in problems})
-    raw = json.dumps({"shapes": shapes, "n": len(problems), "precision": precision})
+    raw = json.dumps({"shapes": shapes, "n": len(problems), "precision": precision, "tuner": 2})
     return hashlib.sha256(raw.encode()).hexdigest()[:16]
 
 
@@ -39,8 +40,9 @@ def _load(path: str) -> Dict:
         return {}
 
 
-def time_stage(problems: Sequence, precision: int, box_target: int, reps: int = 10) -> float:
-    """Average microseconds of one stage launch over the whole batch."""
+def time_stage(problems: Sequence, precision: int, box_target: int, reps: int = 10,
+               blocks_per_cu: Iterable[int] = (0,)) -> Dict[int, float]:
+    """Average microseconds of one stage launch over the whole batch, per workgroup cap."""
     stream = torch.cuda.current_stream()
     solvers = [Solver(p, box_target=box_target) for p in problems]
     batch = Batch(max_solvers=len(solvers), precision=precision, hbm_budget=1 << 50,
@@ -49,24 +51,29 @@ def time_stage(problems: Sequence, precision: int, box_target: int, reps: int = 
         s.restrict()
         batch.admit(s)
     batch.step(1)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    batch.launch_stage(0, 2)
-    e0.record(stream)
-    batch.launch_stage(0, reps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    us = e0.elapsed_time(e1) / reps * 1e3
+    out = {}
+    for bpc in blocks_per_cu:
+        batch.set_blocks_per_cu(int(bpc))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        batch.launch_stage(0, 2)
+        e0.record(stream)
+        batch.launch_stage(0, reps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[int(bpc)] = e0.elapsed_time(e1) / reps * 1e3
     for slot in list(batch.slots):
         batch.release(slot)
     batch.close()
     for s in solvers:
         s.close()
-    return us
+    return out
 
 
 def tune_box_target(problems: Sequence, precision: int, candidates: Iterable[int] = CANDIDATES,
-                    cache_path: Optional[str] = None, reps: int = 10, force: bool = False) -> Dict:
-    """Pick the fastest box target for this batch; returns {"best": t, "us": {t: us}, "cached": bool}."""
+                    cache_path: Optional[str] = None, reps: int = 10, force: bool = False,
+                    blocks_per_cu: Iterable[int] = BLOCKS_PER_CU) -> Dict:
+    """Pick the fastest (box target, workgroups per CU) for this batch; returns
+    {"best": target, "blocks_per_cu": cap, "us": {"target/cap": us}, "cached": bool}."""
     path = cache_path or default_cache_path()
     key = workload_key(problems, precision)
     cache = _load(path)
@@ -77,12 +84,14 @@ def tune_box_target(problems: Sequence, precision: int, candidates: Iterable[int
     times = {}
     for t in candidates:
         try:
-            times[int(t)] = time_stage(problems, precision, int(t), reps)
+            for bpc, us in time_stage(problems, precision, int(t), reps, blocks_per_cu).items():
+                times[f"{int(t)}/{bpc}"] = us
         except Exception as e:  # a target no box satisfies for some grid
-            times[int(t)] = float("inf")
+            times[f"{int(t)}/0"] = float("inf")
             print(f"[autotune] target {t}: {e}", flush=True)
     best = min(times, key=times.get)
-    rec = {"best": best, "us": times}
+    t_best, b_best = (int(x) for x in best.split("/"))
+    rec = {"best": t_best, "blocks_per_cu": b_best, "us": times}
     cache[key] = rec
     os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
     with open(path + ".tmp", "w") as f:

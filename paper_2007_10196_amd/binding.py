@@ -41,7 +41,7 @@ class Config(C.Structure):
                 ("prolong", C.c_int32), ("linear_weights", C.c_int32), ("precision", C.c_int32),
                 ("cfl", C.c_double), ("eps_flux", C.c_double), ("eps_interp", C.c_double),
                 ("box", C.c_int32 * 4), ("fine_tile", C.c_int32 * 4), ("box_target", C.c_int32),
-                ("reserved1", C.c_int32)]
+                ("blocks_per_cu", C.c_int32)]
 
 
 _lib = None
@@ -83,6 +83,7 @@ _SIGS = {
     "sgw_batch_poll": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "sgw_batch_release": (C.c_int32, [C.c_void_p, C.c_int32]),
     "sgw_batch_launch_stage": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
+    "sgw_batch_set_blocks_per_cu": (C.c_int32, [C.c_void_p, C.c_int32]),
     "sgw_batch_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "sgw_status_string": (C.c_char_p, [C.c_int32]),
     "sgw_last_error": (C.c_char_p, []),
@@ -116,7 +117,7 @@ def _pad(v, n, fill=0.0):
     return v + [fill] * (n - len(v))
 
 
-def make_structs(pb, box=None, fine_tile=None, box_target=0):
+def make_structs(pb, box=None, fine_tile=None, box_target=0, blocks_per_cu=0):
     """Problem/Config structs from a problem description with the fields of
     sgw_inputs.Problem (d, lo, hi, flux, flux_params, ic, ic_params, nr, nl, cfl,
     dt_mode, prolong, linear, precision, eps_flux, eps_interp)."""
@@ -142,5 +143,5 @@ def make_structs(pb, box=None, fine_tile=None, box_target=0):
     c.box[:] = _pad(box or [], 4, 0)
     c.fine_tile[:] = _pad(fine_tile or [], 4, 0)
     c.box_target = int(box_target or 0)
-    c.reserved1 = 0
+    c.blocks_per_cu = int(blocks_per_cu or 0)
     return p, c

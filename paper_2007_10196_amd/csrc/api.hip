@@ -102,7 +102,11 @@ static void fill_box_geometry(GridDev& g, int precision)
     // and a high slab per halo direction (direction 0: rows of 3; others: the core layout with
     // extent 3 in that direction)
     g.lines = core / g.t[0];
-    g.RS = g.t[0] + ((g.t[0] % 2 == 0 && g.lines > 1) ? 1 : 0);
+    {
+        // rows hold t_0 values, or the t_0 + 1 interface fluxes of direction 1 with a halo
+        const int i0 = g.t[0] + (g.halo[0] ? 1 : 0);
+        g.RS = i0 + ((i0 % 2 == 0 && g.lines > 1) ? 1 : 0);
+    }
     g.whole = 1;
     for (int k = 0; k < g.d; k++) g.whole &= (g.t[k] == g.n[k]) ? 1 : 0;
     {
@@ -127,7 +131,7 @@ static void fill_box_geometry(GridDev& g, int precision)
     }
     g.pad_total = pad;
     g.fd_lines = make_fastdiv((uint32_t)g.lines);
-    g.pad1_ = 0;
+    g.rline = (SGW_BLOCK % g.t[0] == 0) ? SGW_BLOCK / g.t[0] : 0;
     g.nbox = 1;
     for (int k = 0; k < g.d; k++) g.nbox *= g.ntile[k];
     for (int k = 0; k < SGW_MAX_DIM; k++) {
@@ -136,9 +140,18 @@ static void fill_box_geometry(GridDev& g, int precision)
         g.nseg[k] = (g.I[k] + SGW_SEG - 1) / SGW_SEG;
         g.seg_total[k] = (k < g.d) ? core / g.t[k] * g.nseg[k] : 0;
         g.fd_nseg[k] = make_fastdiv((uint32_t)g.nseg[k]);
+        // segment s reads window positions s*SEG - hf - 2 .. s*SEG - hf + SEG + 2: interior (no
+        // halo, no wrap) for 1 <= s <= (t - 3 - SEG + hf) / SEG
+        g.nlines[k] = core / g.t[k];
+        g.fd_lines_k[k] = make_fastdiv((uint32_t)g.nlines[k]);
+        {
+            const int hf = g.halo[k] ? 1 : 0;
+            const int top = g.t[k] - 3 - SGW_SEG + hf;
+            g.nint[k] = (k < g.d && top >= SGW_SEG) ? top / SGW_SEG : 0;
+        }
         if (k == 0) {
-            g.F0S = g.I[0] + ((g.I[0] % 2 == 0 && g.lines > 1) ? 1 : 0);
-            g.flux_total[0] = g.F0S * g.lines; // direction 0 keeps its interface rows at an odd stride
+            g.F0S = g.RS;
+            g.flux_total[0] = g.F0S * g.lines; // direction 0 keeps its interface rows at the core row stride
         }
         g.fd_CS[k] = make_fastdiv((uint32_t)g.CS[k]);
         g.fd_t[k] = make_fastdiv((uint32_t)g.t[k]);
@@ -303,6 +316,8 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     int64_t tot = 0;
     const size_t lds_cap = 64 * 1024;
     int target = 1024;
+    if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "blocks_per_cu %d outside 0..64", cfg->blocks_per_cu);
     if (cfg->box_target) {
         if (cfg->box_target < 64 || cfg->box_target > SGW_BLOCK * SGW_MAXR) {
             delete p;
@@ -637,7 +652,7 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
         sgw_solver_free(s);
         return rc;
     }
-    s->occupancy = stage_occupancy(p->cfg.precision, p->stage_lds);
+    s->grid = stage_grid(p->cfg.precision, p->stage_lds, p->cfg.blocks_per_cu);
     *out = s;
     return SGW_OK;
 }
@@ -687,7 +702,7 @@ static hipError_t enqueue_step(sgw_solver* s, int mode, hipStream_t st)
     const sgw_plan* p = s->plan;
     hipError_t e = launch_dt_one(s->req_d, st);
     if (e != hipSuccess) return e;
-    const int cap = s->occupancy * 256;
+    const int cap = s->grid;
     for (int stage = 0; stage < 3; stage++) {
         if (mode == SGW_RUN_PLAIN) {
             for (int g = 0; g < p->G; g++) {

@@ -35,6 +35,7 @@ struct sgw_batch {
     bool dirty = true;
     size_t lds = 0;                 // LDS of the captured stage launches
     int blocks = 0;
+    int blocks_per_cu = 0;          // cap on resident stage workgroups per CU (0: occupancy)
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -157,7 +158,7 @@ static sgw_status batch_sync(sgw_batch* b)
     if (!b->exec || lds > b->lds) {
         batch_drop_graph(b);
         b->lds = lds;
-        b->blocks = stage_occupancy(b->precision, lds) * 256;
+        b->blocks = stage_grid(b->precision, lds, b->blocks_per_cu);
         e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
         if (e != hipSuccess) return sgw_hip_fail(e, "capture stream");
         e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
@@ -302,6 +303,24 @@ extern "C" sgw_status sgw_batch_release(sgw_batch_t* b, int32_t slot)
     b->slots[slot] = nullptr;
     b->slot_bytes[slot] = 0;
     b->reqs_h[slot] = nullptr;
+    b->dirty = true;
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_batch_set_blocks_per_cu(sgw_batch_t* b, int32_t blocks_per_cu)
+{
+    if (!b) return sgw_fail(SGW_ERR_INVALID_ARG, "null batch");
+    if (blocks_per_cu < 0 || blocks_per_cu > 64)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "blocks_per_cu %d outside 0..64", blocks_per_cu);
+    if (blocks_per_cu == b->blocks_per_cu) return SGW_OK;
+    // queued launches of the old graph may still run: wait before it is destroyed
+    if (b->queued) {
+        hipError_t e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return sgw_hip_fail(e, "synchronise batch");
+        b->queued = false;
+    }
+    batch_drop_graph(b);
+    b->blocks_per_cu = blocks_per_cu;
     b->dirty = true;
     return SGW_OK;
 }

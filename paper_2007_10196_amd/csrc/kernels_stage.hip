@@ -29,47 +29,55 @@ __device__ __forceinline__ double rdiv(double a, double b) { return a / b; }
 
 // WENO5 flux (eqs. 2.7, 2.7.1, 2.6, 2.7.2) of the positive-wind big stencil
 // (a..e) = (f_{i-2} .. f_{i+2}), written in differences so that neighbouring
-// interfaces share them: c = f_i, D0..D3 = b-a, c-b, d-c, e-d, and
-// S0..S2 = 13/12 (a-2b+c)^2, 13/12 (b-2c+d)^2, 13/12 (c-2d+e)^2.  Then
-//   q_r - c = (5 D1 - 2 D0)/6, (D1 + 2 D2)/6, (4 D2 - D3)/6,
-//   beta_r  = S_r + (3 D1 - D0)^2/4, S_1 + (D1 + D2)^2/4, S_2 + (D3 - 3 D2)^2/4,
-// and the normalised weights d_r/(eps+beta_r)^2 are formed with one division
-// (numerator and denominator multiplied by prod_r (eps+beta_r)^2).
+// interfaces share them: c = f_i, D0..D3 = b-a, c-b, d-c, e-d.  The candidate
+// values are q_r - c = (5 D1 - 2 D0)/6, (D1 + 2 D2)/6, (4 D2 - D3)/6 and the
+// smoothness indicators beta_r = 13/12 s_r^2 + 1/4 g_r^2 with the second
+// differences s_r = a-2b+c, b-2c+d, c-2d+e and g_r = 3 D1 - D0, D1 + D2, D3 - 3 D2.
+// The normalised weights are unchanged when eps and every beta_r are scaled by
+// the same factor, so 12/13 (eps + beta_r) = T_r + 3/13 g_r^2 with
+// T_r = s_r^2 + 12/13 eps is used, and the weights d_r/(...)^2 are normalised
+// with one division (numerator and denominator times the product of the three
+// squares).  R_r = d_r (q_r - c).
 template <typename Real>
-__device__ __forceinline__ Real weno5d(Real c, Real D0, Real D1, Real D2, Real D3, Real S0, Real S1, Real S2, Real eps,
+__device__ __forceinline__ Real weno5s(Real c, Real D0, Real D1, Real D2, Real D3, Real T0, Real T1, Real T2,
                                        int linear)
 {
-    const Real Q0 = Real(5) * D1 - Real(2) * D0;
-    const Real Q1 = D1 + Real(2) * D2;
-    const Real Q2 = Real(4) * D2 - D3;
-    if (linear) return c + (Real(0.1) * Q0 + Real(0.6) * Q1 + Real(0.3) * Q2) * Real(1.0 / 6.0);
+    const Real R0 = Real(0.5 / 6.0) * D1 - Real(0.2 / 6.0) * D0;
+    const Real R1 = Real(0.6 / 6.0) * D1 + Real(1.2 / 6.0) * D2;
+    const Real R2 = Real(1.2 / 6.0) * D2 - Real(0.3 / 6.0) * D3;
+    if (linear) return c + ((R0 + R1) + R2);
     const Real g0 = Real(3) * D1 - D0, g1 = D1 + D2, g2 = D3 - Real(3) * D2;
-    Real e0 = eps + (S0 + Real(0.25) * g0 * g0);
-    Real e1 = eps + (S1 + Real(0.25) * g1 * g1);
-    Real e2 = eps + (S2 + Real(0.25) * g2 * g2);
+    const Real K = Real(3.0 / 13.0);
+    Real e0 = (K * g0) * g0 + T0;
+    Real e1 = (K * g1) * g1 + T1;
+    Real e2 = (K * g2) * g2 + T2;
     e0 *= e0;
     e1 *= e1;
     e2 *= e2;
-    const Real A0 = Real(0.1) * (e1 * e2), A1 = Real(0.6) * (e0 * e2), A2 = Real(0.3) * (e0 * e1);
-    return c + rdiv(A0 * Q0 + A1 * Q1 + A2 * Q2, Real(6) * (A0 + A1 + A2));
+    const Real P12 = e1 * e2, P02 = e0 * e2, P01 = e0 * e1;
+    const Real num = R0 * P12 + R1 * P02 + R2 * P01;
+    const Real den = Real(0.1) * P12 + Real(0.6) * P02 + Real(0.3) * P01;
+    return c + rdiv(num, den);
 }
 
 // NI consecutive interface fluxes F_{i+1/2}, i = i0..i0+NI-1, from the NI+5 values
 // u_{i0-2} .. u_{i0+NI+2} of one line: LF split f^+- (eq. LFflux), the positive-wind
 // reconstruction of f^+ on i-2..i+2 plus the mirrored one of f^- on i+3..i-1.  A
 // split part that is identically zero (c = -+alpha for a linear flux) contributes
-// exactly zero and is skipped.
+// exactly zero and is skipped.  epsT = 12/13 eps.
 template <typename Real, int NI>
-__device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real cp, Real cm, Real alpha, Real eps,
+__device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real cp, Real cm, Real alpha, Real epsT,
                                               int linear, Real* F)
 {
     Real pv[NI + 5], mv[NI + 5];
+    const Real ha = Real(0.5) * alpha;
 #pragma unroll
     for (int q = 0; q < NI + 5; q++) {
         if (burgers) {
-            const Real hu = Real(0.25) * v[q], ha = Real(0.5) * alpha;
-            pv[q] = v[q] * (hu + ha);
-            mv[q] = v[q] * (hu - ha);
+            // f^+- = (u^2/2 +- alpha u)/2
+            const Real f4 = (Real(0.25) * v[q]) * v[q], av = ha * v[q];
+            pv[q] = f4 + av;
+            mv[q] = f4 - av;
         } else {
             pv[q] = cp * v[q];
             mv[q] = cm * v[q];
@@ -77,28 +85,28 @@ __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real 
     }
     const bool use_p = burgers || cp != Real(0);
     const bool use_m = burgers || cm != Real(0);
-    Real dp[NI + 4], dm[NI + 4], sp[NI + 4], sm[NI + 4];
+    Real dp[NI + 4], dm[NI + 4], tp[NI + 4], tm[NI + 4];
 #pragma unroll
     for (int q = 0; q < NI + 4; q++) {
         dp[q] = pv[q + 1] - pv[q];
         dm[q] = mv[q + 1] - mv[q];
     }
-    sp[0] = sm[0] = Real(0);
+    tp[0] = tm[0] = Real(0);
 #pragma unroll
     for (int q = 1; q < NI + 4; q++) {
-        const Real tp = dp[q] - dp[q - 1], tm = dm[q] - dm[q - 1];
-        sp[q] = Real(13.0 / 12.0) * tp * tp;
-        sm[q] = Real(13.0 / 12.0) * tm * tm;
+        const Real sp = dp[q] - dp[q - 1], sm = dm[q] - dm[q - 1];
+        tp[q] = sp * sp + epsT;
+        tm[q] = sm * sm + epsT;
     }
 #pragma unroll
     for (int s = 0; s < NI; s++) {
         Real f = Real(0);
         if (use_p)
-            f = weno5d<Real>(pv[s + 2], dp[s], dp[s + 1], dp[s + 2], dp[s + 3], sp[s + 1], sp[s + 2], sp[s + 3], eps,
+            f = weno5s<Real>(pv[s + 2], dp[s], dp[s + 1], dp[s + 2], dp[s + 3], tp[s + 1], tp[s + 2], tp[s + 3],
                              linear);
         if (use_m)
-            f += weno5d<Real>(mv[s + 3], -dm[s + 4], -dm[s + 3], -dm[s + 2], -dm[s + 1], sm[s + 4], sm[s + 3],
-                              sm[s + 2], eps, linear);
+            f += weno5s<Real>(mv[s + 3], -dm[s + 4], -dm[s + 3], -dm[s + 2], -dm[s + 1], tm[s + 4], tm[s + 3],
+                              tm[s + 2], linear);
         F[s] = f;
     }
 }
@@ -172,11 +180,38 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
     const int RS = g->RS;         // LDS row stride of the core box (odd: conflict-free columns)
     const bool whole = g->whole;  // the box is the whole grid: global index = core index
 
+    // This thread's nodes are e = tid + r * SGW_BLOCK (row-major in the box): row `line` of
+    // t_0 values and column c0.  When t_0 divides the block size all of them share the column
+    // and the row advances by rline per r.
+    const int rline = g->rline;
+    const uint32_t l00 = FDIV((uint32_t)tid, g->fd_t[0]);
+    const int c00 = tid - M24((int)l00, t0);
+    auto node_rc = [&](int r, int& line, int& c0) {
+        if (rline) {
+            line = (int)l00 + r * rline;
+            c0 = c00;
+        } else {
+            const int e = tid + r * SGW_BLOCK;
+            const uint32_t q = FDIV((uint32_t)e, g->fd_t[0]);
+            line = (int)q;
+            c0 = e - M24((int)q, t0);
+        }
+    };
+    auto node_gi = [&](int r, int line, int c0) -> int {
+        if (whole) return tid + r * SGW_BLOCK;
+        if (D == 1) return o[0] + c0;
+        if (D == 2) return (o[0] + c0) + (o[1] + line) * g->stride[1];
+        return core_global_index<D>(g, o, tid + r * SGW_BLOCK);
+    };
+
     // ---- core box -> LDS
-    for (int e = tid; e < core_total; e += SGW_BLOCK) {
-        const uint32_t line = FDIV((uint32_t)e, g->fd_t[0]);
-        const int c0 = e - M24((int)line, t0);
-        su[c0 + M24(RS, (int)line)] = in[whole ? e : core_global_index<D>(g, o, e)];
+#pragma unroll
+    for (int r = 0; r < SGW_MAXR; r++) {
+        if (tid + r * SGW_BLOCK < core_total) {
+            int line, c0;
+            node_rc(r, line, c0);
+            su[c0 + M24(RS, line)] = in[node_gi(r, line, c0)];
+        }
     }
     // ---- halo slabs: the core box with extent 3 in direction k, periodic wrap on the global index
 #pragma unroll
@@ -217,7 +252,7 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
 #pragma unroll
     for (int r = 0; r < SGW_MAXR; r++) acc[r] = Real(0);
 
-    const Real eps = (Real)g->eps;
+    const Real epsT = (Real)(g->eps * (12.0 / 13.0));
     const int linear = g->linear;
     const bool burgers = g->flux == SGW_FLUX_BURGERS;
     Real dyn_alpha = Real(0);
@@ -228,7 +263,7 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
         const int hf = g->halo[k] ? 1 : 0;
         const int tk = g->t[k];
         const int CSk = g->CS[k];
-        const int LSk = g->LS[k];
+        const int LSk = (k == 0) ? 1 : g->LS[k];
         const int Ik = g->I[k];
         const int slo = g->slab_lo[k], shi = g->slab_hi[k];
         const Real alpha = g->dyn_alpha ? dyn_alpha : (Real)g->alpha_c[k];
@@ -241,23 +276,30 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
         //      SGW_SEG consecutive interfaces of one line from a window of SGW_SEG + 5 values;
         //      consecutive lanes take neighbouring lines (stride 1, or RS for direction 1).
         const int stot = g->seg_total[k];
-        const int nseg = g->nseg[k];
+        const int Lk = g->nlines[k];
+        const int nint = g->nint[k];
+        const int int_total = M24(Lk, nint);
         for (int w = tid; w < stot; w += SGW_BLOCK) {
-            int seg, base_core, base_slab, lbase, fbase, fstride;
+            // interior segments (window inside the core, no wrap) first, then the edge ones;
+            // consecutive lanes take neighbouring lines of the same segment
+            const bool interior = w < int_total;
+            // the contiguous fast path for whole wavefronts of interior segments only, so that no
+            // wavefront runs both paths
+            const bool fast = w < (int_total & ~63);
+            const int wl = interior ? w : w - int_total;
+            const uint32_t sq = FDIV((uint32_t)wl, g->fd_lines_k[k]);
+            const int line = wl - M24((int)sq, Lk);
+            const int seg = interior ? 1 + (int)sq : (sq == 0 ? 0 : (int)sq + nint);
+            int base_core, base_slab, lbase, fbase, fstride;
             if (k == 0) {
-                const uint32_t sq = FDIV((uint32_t)w, g->fd_lines);
-                const int line = w - (int)sq * g->lines;
-                seg = (int)sq;
                 base_core = M24(line, RS);
                 base_slab = M24(line, 3);
                 lbase = M24(line, t0);
-                fbase = M24(line, g->F0S);
+                fbase = M24(line, RS);
                 fstride = 1;
             } else {
-                const uint32_t r1 = FDIV((uint32_t)w, g->fd_CS[k]);
-                const int inner = w - (int)r1 * CSk;
-                const uint32_t outer = FDIV(r1, g->fd_nseg[k]);
-                seg = (int)r1 - (int)outer * nseg;
+                const uint32_t outer = FDIV((uint32_t)line, g->fd_CS[k]);
+                const int inner = line - M24((int)outer, CSk);
                 int inner_lds = inner;
                 if (k >= 2) inner_lds += M24(RS - t0, (int)FDIV((uint32_t)inner, g->fd_t[0]));
                 base_core = inner_lds + M24((int)outer, LSk * tk);
@@ -268,21 +310,30 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
             }
             const int i0 = seg * SGW_SEG - hf; // first interface: x_{i0+1/2}
             Real v[SGW_SEG + 5];
+            if (fast) {
+                const int a0 = base_core + M24(i0 - 2, LSk);
 #pragma unroll
-            for (int q = 0; q < SGW_SEG + 5; q++) {
-                int p = i0 + q - 2;
-                int idx;
-                if (hf) {
+                for (int q = 0; q < SGW_SEG + 5; q++) v[q] = su[a0 + (k == 0 ? q : M24(q, LSk))];
+            } else if (hf) {
+                // window position p < 0 lies in the low slab, p >= t in the high one: pick the
+                // base by selects (no divergent branches), then add p times the line stride
+                const int blo = slo + base_slab + 3 * LSk, bhi = shi + base_slab - tk * LSk;
+#pragma unroll
+                for (int q = 0; q < SGW_SEG + 5; q++) {
+                    int p = i0 + q - 2;
                     p = p > tk + 2 ? tk + 2 : p; // past the last interface: valid data, result unused
-                    idx = (p < 0) ? slo + base_slab + M24(p + 3, LSk)
-                                  : (p >= tk) ? shi + base_slab + M24(p - tk, LSk) : base_core + M24(p, LSk);
-                } else {
+                    const int bs = p < 0 ? blo : base_core;
+                    v[q] = su[(p >= tk ? bhi : bs) + M24(p, LSk)];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < SGW_SEG + 5; q++) {
+                    int p = i0 + q - 2;
                     p += (p < 0) ? tk : 0;
                     p -= (p >= tk) ? tk : 0;
                     p -= (p >= tk) ? tk : 0;
-                    idx = base_core + M24(p, LSk);
+                    v[q] = su[base_core + M24(p, LSk)];
                 }
-                v[q] = su[idx];
             }
             Real cp = Real(0), cm = Real(0);
             if (!burgers) {
@@ -296,11 +347,11 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
                 cm = Real(0.5) * (c - alpha);
             }
             Real F[SGW_SEG];
-            window_fluxes<Real, SGW_SEG>(v, burgers, cp, cm, alpha, eps, linear, F);
+            window_fluxes<Real, SGW_SEG>(v, burgers, cp, cm, alpha, epsT, linear, F);
 #pragma unroll
             for (int s = 0; s < SGW_SEG; s++) {
                 const int ip = seg * SGW_SEG + s; // i + hf
-                if (ip < Ik) sfk[fbase + M24(ip, fstride)] = F[s];
+                if (interior || ip < Ik) sfk[fbase + M24(ip, fstride)] = F[s];
             }
         }
         __syncthreads();
@@ -312,14 +363,18 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
             if (e < core_total) {
                 int fhi, flo;
                 if (k == 0) {
-                    const uint32_t line = FDIV((uint32_t)e, g->fd_t[0]);
-                    const int c0 = e - M24((int)line, t0);
-                    fhi = c0 + hf + M24((int)line, g->F0S);
+                    // interface rows share the core row stride RS
+                    int line, c0;
+                    node_rc(r, line, c0);
+                    fhi = c0 + hf + M24(line, RS);
                     flo = (hf || c0 > 0) ? fhi - 1 : fhi + t0 - 1;
                 } else {
-                    const uint32_t hi = FDIV((uint32_t)e, g->fd_CSt[k]);
-                    const int lo = e - M24((int)hi, (int)g->fd_CSt[k].d);
-                    fhi = lo + hf * CSk + M24((int)hi, CSk * Ik);
+                    int hi = 0, lo = e;
+                    if (k < D - 1) {
+                        hi = (int)FDIV((uint32_t)e, g->fd_CSt[k]);
+                        lo = e - M24(hi, (int)g->fd_CSt[k].d);
+                    }
+                    fhi = lo + hf * CSk + M24(hi, CSk * Ik);
                     flo = (hf || lo >= CSk) ? fhi - CSk : fhi + (tk - 1) * CSk;
                 }
                 acc[r] -= (sfk[fhi] - sfk[flo]) * ih;
@@ -328,24 +383,24 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
     }
 
     // ---- TVD-RK3 stage: u1 = u + dt L(u); u2 = 3/4 u + 1/4 (u1 + dt L(u1)); u = 1/3 u + 2/3 (u2 + dt L(u2))
-    double amax = 0.0;
+    Real amax = Real(0);
 #pragma unroll
     for (int r = 0; r < SGW_MAXR; r++) {
-        const int e = tid + r * SGW_BLOCK;
-        if (e < core_total) {
-            const uint32_t line = FDIV((uint32_t)e, g->fd_t[0]);
-            const int c0 = e - M24((int)line, t0);
-            const int gi = whole ? e : core_global_index<D>(g, o, e);
-            const Real val = su[c0 + M24(RS, (int)line)] + dtr * acc[r];
+        if (tid + r * SGW_BLOCK < core_total) {
+            int line, c0;
+            node_rc(r, line, c0);
+            const int gi = node_gi(r, line, c0);
+            const Real val = su[c0 + M24(RS, line)] + dtr * acc[r];
             Real res;
             if (stage == 0) res = val;
             else if (stage == 1) res = Real(0.75) * u0[gi] + Real(0.25) * val;
             else res = Real(1.0 / 3.0) * u0[gi] + Real(2.0 / 3.0) * val;
             out[gi] = res;
-            amax = nanmax(amax, fabs((double)res));
+            const Real ar = fabs(res);
+            amax = (ar > amax || ar != ar) ? ar : amax;
         }
     }
-    if (g->dyn_alpha) block_atomic_max(amax, g->alpha + (stage + 1) % 3, red);
+    if (g->dyn_alpha) block_atomic_max((double)amax, g->alpha + (stage + 1) % 3, red);
 }
 
 template <typename Real>
@@ -357,10 +412,14 @@ __global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __rest
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[SGW_BLOCK / 64];
     // XCD-aware order: consecutive workgroup ids land on different XCDs, so hand
-    // each XCD a contiguous run of boxes (neighbouring boxes share halo lines in L2)
-    int nb = gridDim.x, bid = blockIdx.x;
+    // each XCD a contiguous run of boxes (neighbouring boxes share halo lines in L2).
+    // Each workgroup takes a contiguous range of floor or ceil(nitems / nb) boxes,
+    // so every XCD and every CU gets the same share.
+    const int nb = gridDim.x;
+    int bid = blockIdx.x;
     if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
-    for (int w = bid; w < nitems; w += nb) {
+    const int w_end = (int)(((uint64_t)(bid + 1) * (uint32_t)nitems) / (uint32_t)nb);
+    for (int w = (int)(((uint64_t)bid * (uint32_t)nitems) / (uint32_t)nb); w < w_end; w++) {
         // descriptors are read-only during the launch: read them through the constant
         // address space so the compiler keeps them in scalar registers
         const SGW_CONST WorkItem* it = (const SGW_CONST WorkItem*)items + w;
@@ -602,6 +661,22 @@ size_t stage_lds_bytes(const GridDev& g, int precision)
     int fmax_ = 0;
     for (int k = 0; k < g.d; k++) fmax_ = g.flux_total[k] > fmax_ ? g.flux_total[k] : fmax_;
     return rs * (((size_t)g.pad_total + 1) / 2 * 2 + 2 * (((size_t)fmax_ + 1) / 2 * 2));
+}
+
+int device_cus()
+{
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+        n = 256;
+    return n;
+}
+
+int stage_grid(int precision, size_t lds_bytes, int blocks_per_cu)
+{
+    int occ = stage_occupancy(precision, lds_bytes);
+    if (blocks_per_cu > 0 && blocks_per_cu < occ) occ = blocks_per_cu;
+    return occ * device_cus();
 }
 
 int stage_occupancy(int precision, size_t lds_bytes)

@@ -51,7 +51,7 @@ struct sgw_solver {
     ReqDev* req_pinned = nullptr;
     bool restricted = false;
     double t_host = 0.0;
-    int occupancy = 1;
+    int grid = 1;                              // workgroups of a persistent stage launch
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;

@@ -74,9 +74,14 @@ struct alignas(64) GridDev {
     int32_t seg_total[SGW_MAX_DIM];  // work items of the segment loop: lines * nseg[k]
     int32_t LS[SGW_MAX_DIM];         // LDS strides of the core box (row stride RS)
     int32_t slab_n[SGW_MAX_DIM];     // values per halo slab (3 core / t_k)
-    int32_t RS, lines, F0S, whole;   // odd LDS row stride, rows (core / t_0), odd flux row stride, box = grid
-    int32_t sf_elems, pad1_;         // elements of one interface-flux buffer (two alternate in LDS)
+    int32_t RS, lines, F0S, whole;   // LDS row stride of core and direction-1 fluxes (odd: conflict-free
+                                     // columns), rows (core / t_0), F0S = RS, box = grid
+    int32_t sf_elems, rline;         // elements of one interface-flux buffer (two alternate in LDS);
+                                     // SGW_BLOCK / t_0 when t_0 divides SGW_BLOCK, else 0
+    int32_t nlines[SGW_MAX_DIM];     // lines of the box along direction k: core / t_k
+    int32_t nint[SGW_MAX_DIM];       // interior segments per line (window inside the core, no wrap)
     FastDiv fd_lines;
+    FastDiv fd_lines_k[SGW_MAX_DIM];
     FastDiv fd_nseg[SGW_MAX_DIM];
     FastDiv fd_CS[SGW_MAX_DIM];
     FastDiv fd_t[SGW_MAX_DIM];
@@ -194,6 +199,7 @@ hipError_t launch_stage_dev_count(const WorkItem* items, const int* nitems_dev, 
 hipError_t launch_gather_done(ReqDev* const* reqs, int nreq, int* flags, hipStream_t s);
 size_t stage_lds_bytes(const GridDev& g, int precision);
 int stage_occupancy(int precision, size_t lds_bytes);
+int stage_grid(int precision, size_t lds_bytes, int blocks_per_cu);  // persistent grid: blocks per CU x CUs
 hipError_t launch_prolong(const ProDev* pro_dev, const FineDev* fine_dev, const FineDev& fine_host,
                           int precision, size_t lds_bytes, double* out, hipStream_t s);
 hipError_t launch_prolong_many(const ProItem* items, int nitems, int d, int precision, size_t lds_bytes,

@@ -41,7 +41,7 @@ class Result:
 class ServingLoop:
     def __init__(self, precision: int = B.FP32_SWEEP, max_active: int = 64, hbm_budget: int = 64 << 30,
                  steps_per_tick: int = 8, keep_outputs: bool = False, box_target: int = 0,
-                 device: str = "cuda"):
+                 blocks_per_cu: int = 0, device: str = "cuda"):
         self.precision = precision
         self.max_active = max_active
         self.budget = int(hbm_budget)
@@ -53,6 +53,8 @@ class ServingLoop:
         self.side = torch.cuda.Stream(device=self.device)
         self.batch = Batch(max_solvers=max_active, precision=precision, hbm_budget=self.budget,
                            max_items=1 << 22, device=device, stream=self.main)
+        if blocks_per_cu:
+            self.batch.set_blocks_per_cu(blocks_per_cu)
 
     def run(self, requests: List, clock=time.perf_counter) -> List[Result]:
         """Serve ``requests`` (objects with rid, arrival_s, problem) against the wall clock."""

@@ -17,9 +17,9 @@ from . import binding as B
 class Plan:
     """Host-only plan: the component grids of the index set, their layout and tiling."""
 
-    def __init__(self, problem, box=None, fine_tile=None, box_target=0):
+    def __init__(self, problem, box=None, fine_tile=None, box_target=0, blocks_per_cu=0):
         self.problem = problem
-        self._pb, self._cfg = B.make_structs(problem, box, fine_tile, box_target)
+        self._pb, self._cfg = B.make_structs(problem, box, fine_tile, box_target, blocks_per_cu)
         h = C.c_void_p()
         B.check(B.lib().sgw_plan_create(C.byref(self._pb), C.byref(self._cfg), C.byref(h)))
         self.handle = h
@@ -63,11 +63,12 @@ class Solver:
     """Bound solve: caller-owned device buffers + a HIP stream."""
 
     def __init__(self, problem, device: str = "cuda", stream: Optional[torch.cuda.Stream] = None,
-                 box=None, fine_tile=None, plan: Optional[Plan] = None, box_target: int = 0):
+                 box=None, fine_tile=None, plan: Optional[Plan] = None, box_target: int = 0,
+                 blocks_per_cu: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("sgweno needs a ROCm GPU; none is visible")
         self.problem = problem
-        self.plan = plan or Plan(problem, box, fine_tile, box_target)
+        self.plan = plan or Plan(problem, box, fine_tile, box_target, blocks_per_cu)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         # torch's caching allocator returns 512-byte aligned blocks
@@ -192,6 +193,9 @@ class Batch:
         n = C.c_int32()
         B.check(B.lib().sgw_batch_poll(self.handle, buf, C.byref(n)))
         return list(buf[:n.value])
+
+    def set_blocks_per_cu(self, n: int):
+        B.check(B.lib().sgw_batch_set_blocks_per_cu(self.handle, int(n)))
 
     def launch_stage(self, stage: int, reps: int = 1):
         B.check(B.lib().sgw_batch_launch_stage(self.handle, stage, reps))

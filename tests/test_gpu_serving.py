@@ -95,7 +95,10 @@ def test_autotuner_picks_and_caches(tmp_path):
     probs = [W.c2_burgers_2d(nl=4, precision=W.PREC_FP32).replace(ic_params=(0.3, 0.7, math.pi, 0.1 * i))
              for i in range(16)]
     path = str(tmp_path / "tune.json")
-    rec = tune_box_target(probs, B.FP32_SWEEP, candidates=(256, 1024), cache_path=path, reps=3)
-    assert rec["best"] in (256, 1024) and not rec["cached"]
-    again = tune_box_target(probs, B.FP32_SWEEP, candidates=(256, 1024), cache_path=path, reps=3)
-    assert again["cached"] and again["best"] == rec["best"]
+    rec = tune_box_target(probs, B.FP32_SWEEP, candidates=(256, 1024), cache_path=path, reps=3,
+                          blocks_per_cu=(0, 2))
+    assert rec["best"] in (256, 1024) and rec["blocks_per_cu"] in (0, 2) and not rec["cached"]
+    assert len(rec["us"]) == 4 and all(v > 0 for v in rec["us"].values())
+    again = tune_box_target(probs, B.FP32_SWEEP, candidates=(256, 1024), cache_path=path, reps=3,
+                            blocks_per_cu=(0, 2))
+    assert again["cached"] and again["best"] == rec["best"] and again["blocks_per_cu"] == rec["blocks_per_cu"]
