@@ -64,8 +64,7 @@ def run_batch_step(torch, batch, solvers, outs, exacts, res):
     from paper_2007_10196_amd.solver import norms_many, prolongate_combine_many, restrict_many
     # Alg. Step 1 for every solve in one launch
     restrict_many(solvers, stream=batch.stream)
-    for s in solvers:
-        batch.admit(s)
+    batch.admit_many(solvers)
     done = set()
     # the wave speed only decays before the shock, so the estimate is an upper bound
     # up to WENO overshoot: march most of it blind, then look every two steps
@@ -75,8 +74,7 @@ def run_batch_step(torch, batch, solvers, outs, exacts, res):
         if len(done) == len(solvers):
             break
         batch.step(2)
-    for slot in list(batch.slots):
-        batch.release(slot)
+    batch.release_many(list(batch.slots))
     # Alg. Step 3 for every solve in one launch, then the norms of every solve in one launch
     prolongate_combine_many(solvers, outs, stream=batch.stream)
     norms_many(solvers, outs, exacts, res, stream=batch.stream)
@@ -118,38 +116,51 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes_per_copy": x.numel() * 4, "copies": 3}), flush=True)
 
 
-SERVING_N = 128
+SERVING_N = 512
 
 
-def serving_run(capacity, box_target, n=None, load=0.7, blocks_per_cu=0):
+def serving_run(box_target, n=None, loads=(0.7,), blocks_per_cu=0):
     """Seeded Poisson stream mixing the 2D advection, 2D Burgers, 3D advection and 4D Vlasov
-    workloads at finest levels 2..5 (4D capped at 4), FP32 sweeps; the arrival rate is set so the
-    offered cell-updates/s are `load` x the measured batched capacity."""
+    workloads at finest levels 2..5 (4D capped at 4), FP32 sweeps.  The mix is first served
+    closed-loop (every request queued at t = 0) to measure its saturation throughput; the
+    arrival rate of each open-loop run is then `load` x that throughput."""
+    import dataclasses
     from paper_2007_10196_amd import binding as B
     from paper_2007_10196_amd.serving import ServingLoop, latency_summary
-    from paper_2007_10196_amd.solver import Plan
     n = n or SERVING_N
     probe = W.serving_stream(n=n, rate_hz=1.0, max_level_by_family={4: 4})
-    # offered work in 2D-equivalent cell-updates (a stage costs ~d/2 times a 2D stage per node)
-    work = []
-    for r in probe:
-        p = Plan(r.problem)
-        work.append(step_estimate_any(r.problem) * p.total_nodes * r.problem.d / 2.0)
-    rate = load * capacity / (sum(work) / len(work))
-    reqs = W.serving_stream(n=n, rate_hz=rate, max_level_by_family={4: 4})
-    loop = ServingLoop(precision=B.FP32_SWEEP, max_active=64, hbm_budget=96 << 30, steps_per_tick=8,
-                       box_target=box_target, blocks_per_cu=blocks_per_cu)
-    t0 = time.perf_counter()
-    res = loop.run(reqs)
-    wall = time.perf_counter() - t0
-    loop.close()
-    out = latency_summary(res)
-    out.update({"arrival_rate_hz": rate, "offered_load_of_capacity": load, "wall_s": wall,
-                "mix": "families 2D advection / 2D Burgers / 3D advection / 4D Vlasov, levels 2-5 (4D <= 4), "
-                       "seeded phases and amplitudes, FP32 sweeps + FP64 combination"})
-    print(f"[bench] serving {n} requests: p50 {out['p50_ms']:.1f} ms p99 {out['p99_ms']:.1f} ms",
-          file=sys.stderr, flush=True)
-    return out
+
+    def serve(reqs):
+        loop = ServingLoop(precision=B.FP32_SWEEP, max_active=64, hbm_budget=96 << 30, steps_per_tick=8,
+                           box_target=box_target, blocks_per_cu=blocks_per_cu)
+        t0 = time.perf_counter()
+        res = loop.run(reqs)
+        wall = time.perf_counter() - t0
+        loop.close()
+        return res, wall
+
+    res, wall = serve([dataclasses.replace(r, arrival_s=0.0) for r in probe])
+    cap_hz = n / wall
+    closed = latency_summary(res)
+    print(f"[bench] serving {n} requests closed-loop: {cap_hz:.1f} requests/s, "
+          f"{closed['throughput_cell_updates_per_s']:.3e} cell-updates/s", file=sys.stderr, flush=True)
+    runs = []
+    for load in loads:
+        reqs = W.serving_stream(n=n, rate_hz=load * cap_hz, max_level_by_family={4: 4})
+        res, wall = serve(reqs)
+        out = latency_summary(res)
+        out.update({"arrival_rate_hz": load * cap_hz, "offered_load_of_capacity": load, "wall_s": wall})
+        runs.append(out)
+        print(f"[bench] serving {n} requests at {load:.1f} of capacity: p50 {out['p50_ms']:.1f} ms "
+              f"p99 {out['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    main = dict(runs[0])
+    main.update({"capacity_requests_per_s": cap_hz,
+                 "capacity_cell_updates_per_s": closed["throughput_cell_updates_per_s"],
+                 "other_loads": runs[1:],
+                 "mix": "families 2D advection / 2D Burgers / 3D advection / 4D Vlasov, levels 2-5 (4D <= 4), "
+                        "seeded phases and amplitudes, FP32 sweeps + FP64 combination; capacity measured "
+                        "closed-loop on the same mix"})
+    return main
 
 
 def step_estimate_any(pb):
@@ -197,7 +208,8 @@ def main():
     ap.add_argument("--box-target", type=int, default=0,
                     help="0: autotune the stage box target and the workgroups per compute unit")
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="with --box-target: stage workgroups per CU")
-    ap.add_argument("--serving-requests", type=int, default=128)
+    ap.add_argument("--serving-requests", type=int, default=SERVING_N)
+    ap.add_argument("--serving-loads", default="0.7", help="comma-separated offered loads (first one reported)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 1 GiB copy used to scale the HBM byte counters")
     args = ap.parse_args()
@@ -259,8 +271,7 @@ def main():
     # ---- the stage kernel alone, same launch shape, HIP events on the batch stream
     from paper_2007_10196_amd.solver import restrict_many
     restrict_many(solvers, stream=batch.stream)
-    for s in solvers:
-        batch.admit(s)
+    batch.admit_many(solvers)
     batch.step(1)
     st = batch.stream
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -271,8 +282,7 @@ def main():
     torch.cuda.synchronize()
     stage_ms = ev0.elapsed_time(ev1) / args.stage_reps
     info = batch.info()
-    for slot in list(batch.slots):
-        batch.release(slot)
+    batch.release_many(list(batch.slots))
     stage_flops = info["nodes"] * flops_per_node_stage(2, 0)
     achieved = stage_flops / (stage_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -304,7 +314,9 @@ def main():
                  "speedup_of_value": value / (stp * nodes / tp),
                  "equal_l1": bool(abs(l1s[0] - l1p) <= 0.01 * l1p), "l1_batched_fp32_same_solve": float(l1s[0])}
 
-    serving = None if args.no_serving else serving_run(value, box_target, blocks_per_cu=bpc)
+    serving = None if args.no_serving else serving_run(
+        box_target, n=args.serving_requests, loads=[float(x) for x in args.serving_loads.split(",")],
+        blocks_per_cu=bpc)
 
     cpu = None if args.no_cpu else cpu_baseline()
 

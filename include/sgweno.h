@@ -223,6 +223,11 @@ uint64_t sgw_batch_scratch_bytes(int32_t max_solvers, int64_t max_items);
 /* Admit a restricted solver to advance to t_final.  SGW_ERR_OUT_OF_MEMORY when
  * no slot is free or its footprint does not fit the remaining budget. */
 sgw_status sgw_batch_admit(sgw_batch_t* batch, sgw_solver_t* solver, double t_final, int32_t* slot);
+/* sgw_batch_admit for solvers[0..n) with final times t_final[i]; slots[i]
+ * receives each slot.  Stops at the first solver that is refused and returns
+ * its error; *n_admitted counts the solvers admitted before it. */
+sgw_status sgw_batch_admit_many(sgw_batch_t* batch, sgw_solver_t* const* solvers, int32_t n, const double* t_final,
+                                int32_t* slots, int32_t* n_admitted);
 /* Advance every active solver by up to nsteps steps (finished ones do nothing). */
 sgw_status sgw_batch_step(sgw_batch_t* batch, int32_t nsteps);
 /* Which slots have reached their final time (synchronises).  done_slots has
@@ -230,6 +235,9 @@ sgw_status sgw_batch_step(sgw_batch_t* batch, int32_t nsteps);
 sgw_status sgw_batch_poll(sgw_batch_t* batch, int32_t* done_slots, int32_t* n_done);
 /* Remove a solver from the batch; its budget and slot become free. */
 sgw_status sgw_batch_release(sgw_batch_t* batch, int32_t slot);
+/* sgw_batch_release for n distinct occupied slots (all checked before any is
+ * released); waits for queued steps at most once. */
+sgw_status sgw_batch_release_many(sgw_batch_t* batch, const int32_t* slots, int32_t n);
 /* Measurement hook: enqueue reps launches of RK stage `stage` (0..2) over the
  * batch's boxes, outside any graph, with the same launch shape as a step
  * (callers time them with events on the batch stream).  Stage 0 writes only the

@@ -79,6 +79,9 @@ _SIGS = {
     "sgw_batch_free": (None, [C.c_void_p]),
     "sgw_batch_scratch_bytes": (C.c_uint64, [C.c_int32, C.c_int64]),
     "sgw_batch_admit": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(C.c_int32)]),
+    "sgw_batch_admit_many": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "sgw_batch_release_many": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32]),
     "sgw_batch_step": (C.c_int32, [C.c_void_p, C.c_int32]),
     "sgw_batch_poll": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "sgw_batch_release": (C.c_int32, [C.c_void_p, C.c_int32]),

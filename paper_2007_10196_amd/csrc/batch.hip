@@ -324,3 +324,33 @@ extern "C" sgw_status sgw_batch_set_blocks_per_cu(sgw_batch_t* b, int32_t blocks
     b->dirty = true;
     return SGW_OK;
 }
+
+extern "C" sgw_status sgw_batch_admit_many(sgw_batch_t* b, sgw_solver_t* const* solvers, int32_t n,
+                                           const double* t_final, int32_t* slots, int32_t* n_admitted)
+{
+    if (!b || !solvers || !t_final || !slots || !n_admitted || n < 0)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    *n_admitted = 0;
+    for (int i = 0; i < n; i++) {
+        const sgw_status rc = sgw_batch_admit(b, solvers[i], t_final[i], slots + i);
+        if (rc != SGW_OK) return rc;
+        *n_admitted = i + 1;
+    }
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_batch_release_many(sgw_batch_t* b, const int32_t* slots, int32_t n)
+{
+    if (!b || (!slots && n > 0) || n < 0) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    std::vector<char> seen(b->max_solvers, 0);
+    for (int i = 0; i < n; i++) {
+        if (slots[i] < 0 || slots[i] >= b->max_solvers || !b->slots[slots[i]])
+            return sgw_fail(SGW_ERR_INVALID_ARG, "bad slot %d", slots[i]);
+        if (seen[slots[i]]++) return sgw_fail(SGW_ERR_INVALID_ARG, "slot %d listed twice", slots[i]);
+    }
+    for (int i = 0; i < n; i++) {
+        const sgw_status rc = sgw_batch_release(b, slots[i]);
+        if (rc != SGW_OK) return rc;
+    }
+    return SGW_OK;
+}

@@ -185,6 +185,26 @@ class Batch:
                 return None
             raise
 
+    def admit_many(self, solvers, t_final=None):
+        """Admit solvers in order; raises at the first refused one (those before it stay admitted)."""
+        n = len(solvers)
+        hs = (C.c_void_p * n)(*[s.handle.value for s in solvers])
+        tf = (C.c_double * n)(*[s.problem.T if t_final is None else float(t_final[i]) for i, s in enumerate(solvers)])
+        slots = (C.c_int32 * n)()
+        got = C.c_int32()
+        st = B.lib().sgw_batch_admit_many(self.handle, hs, n, tf, slots, C.byref(got))
+        for i in range(got.value):
+            self.slots[slots[i]] = solvers[i]
+        B.check(st)
+        return list(slots[:n])
+
+    def release_many(self, slots):
+        """Release the given slots; returns their solvers."""
+        n = len(slots)
+        arr = (C.c_int32 * n)(*slots)
+        B.check(B.lib().sgw_batch_release_many(self.handle, arr, n))
+        return [self.slots.pop(s) for s in slots]
+
     def step(self, nsteps: int = 1):
         B.check(B.lib().sgw_batch_step(self.handle, nsteps))
 

@@ -314,3 +314,41 @@ def test_restrict_many_rejects_mixed_precision():
     with pytest.raises(B.SgwError) as e:
         restrict_many([a, b])
     assert e.value.status == -1
+
+
+def test_batch_admit_many_and_release_many():
+    """Many-solver admission equals one-by-one admission (bitwise results); a refused solver stops the
+    list with the earlier ones admitted; release_many rejects a repeated slot before releasing any."""
+    torch, B, Solver, Batch = _lib()
+    from paper_2007_10196_amd.solver import restrict_many
+    rng = np.random.default_rng(5)
+    probs = [W.randomized(2, 3, rng, precision=W.PREC_FP32) for _ in range(6)]
+    ref = []
+    for p in probs:
+        s = Solver(p)
+        s.restrict()
+        s.advance()
+        ref.append(s.prolongate_combine())
+    solvers = [Solver(p) for p in probs]
+    restrict_many(solvers)
+    fp = [s.plan.footprint for s in solvers]
+    batch = Batch(max_solvers=8, precision=B.FP32_SWEEP, hbm_budget=sum(fp[:4]) + fp[4] // 2)
+    with pytest.raises(B.SgwError) as e:
+        batch.admit_many(solvers)
+    assert e.value.status == -3 and len(batch.slots) == 4
+    with pytest.raises(B.SgwError) as e:
+        batch.release_many([0, 0])
+    assert e.value.status == -1 and len(batch.slots) == 4
+    batch.release_many(sorted(batch.slots))
+    assert not batch.slots
+    big = Batch(max_solvers=8, precision=B.FP32_SWEEP, hbm_budget=sum(fp) + (1 << 20))
+    restrict_many(solvers)
+    slots = big.admit_many(solvers)
+    assert sorted(slots) == list(range(6))
+    done = set()
+    while len(done) < 6:
+        big.step(4)
+        done |= set(big.poll())
+    big.release_many(slots)
+    for s, r in zip(solvers, ref):
+        assert torch.equal(s.prolongate_combine(), r)
