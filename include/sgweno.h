@@ -144,6 +144,10 @@ sgw_status sgw_plan_grid_box(const sgw_plan_t* plan, int32_t g, int32_t box[SGW_
 sgw_status sgw_solver_create(sgw_plan_t* plan, void* state_dev, void* scratch_dev, void* hip_stream,
                              sgw_solver_t** out);
 void sgw_solver_free(sgw_solver_t* solver);
+/* Later calls of this solver enqueue on hip_stream.  Work already enqueued on
+ * the previous stream is not waited for: the caller orders it (an event or a
+ * synchronisation).  Refused while the solver is in a batch. */
+sgw_status sgw_solver_set_stream(sgw_solver_t* solver, void* hip_stream);
 
 /* Alg. Step 1: u^0 = u0 at the nodes of every component grid; t = 0. */
 sgw_status sgw_restrict_initial(sgw_solver_t* solver);

@@ -58,6 +58,7 @@ _SIGS = {
     "sgw_plan_grid_box": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32 * 4]),
     "sgw_solver_create": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "sgw_solver_free": (None, [C.c_void_p]),
+    "sgw_solver_set_stream": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "sgw_restrict_initial": (C.c_int32, [C.c_void_p]),
     "sgw_advance": (C.c_int32, [C.c_void_p, C.c_double, C.c_int32]),
     "sgw_prolongate_combine": (C.c_int32, [C.c_void_p, C.c_void_p]),

@@ -676,6 +676,14 @@ extern "C" void sgw_solver_free(sgw_solver_t* s)
     delete s;
 }
 
+extern "C" sgw_status sgw_solver_set_stream(sgw_solver_t* s, void* hip_stream)
+{
+    if (!s) return sgw_fail(SGW_ERR_INVALID_ARG, "null solver");
+    if (s->batch_slot >= 0) return sgw_fail(SGW_ERR_STATE, "solver is in a batch");
+    s->stream = (hipStream_t)hip_stream;
+    return SGW_OK;
+}
+
 extern "C" sgw_status sgw_restrict_initial(sgw_solver_t* s)
 {
     if (!s) return sgw_fail(SGW_ERR_INVALID_ARG, "null solver");

@@ -51,6 +51,11 @@ class ServingLoop:
         self.device = torch.device(device)
         self.main = torch.cuda.current_stream(self.device)
         self.side = torch.cuda.Stream(device=self.device)
+        # solver set-up and restriction: their own stream, so an admission never waits
+        # behind the prolongations queued on the side stream
+        self.setup = torch.cuda.Stream(device=self.device)
+        # host seconds spent per phase of the loop, for tuning
+        self.stats: Dict[str, float] = collections.defaultdict(float)
         self.batch = Batch(max_solvers=max_active, precision=precision, hbm_budget=self.budget,
                            max_items=1 << 22, device=device, stream=self.main)
         if blocks_per_cu:
@@ -75,32 +80,38 @@ class ServingLoop:
                 req = queue[0]
                 plan = plans.get(req.rid)
                 if plan is None:
+                    tp = clock()
                     plan = plans[req.rid] = Plan(req.problem, box_target=self.box_target)
+                    self.stats["plan"] += clock() - tp
                 if used + plan.footprint > self.budget:
                     if not active and not finishing:
                         raise MemoryError(f"request {req.rid} needs {plan.footprint} B, budget {self.budget} B")
                     break
-                with torch.cuda.stream(self.side):
-                    solver = Solver(req.problem, device=str(self.device), stream=self.side, plan=plan)
+                tp = clock()
+                with torch.cuda.stream(self.setup):
+                    solver = Solver(req.problem, device=str(self.device), stream=self.setup, plan=plan)
                     solver.restrict()
                 slot = self.batch.admit(solver)  # orders the restriction before the batch's next step
+                self.stats["admit"] += clock() - tp
                 queue.popleft()
                 used += plan.footprint
                 active[slot] = (req, solver, clock() - t0, plan.footprint)
             # solves whose combination has completed
             still = []
-            for req, solver, admit_s, fp, ev, U in finishing:
+            for req, solver, admit_s, fp, ev, U, steps in finishing:
                 if ev.query():
-                    t, steps = solver.query()
                     results.append(Result(rid=req.rid, arrival_s=req.arrival_s, admit_s=admit_s,
                                           finish_s=clock() - t0, steps=steps,
                                           cell_updates=steps * solver.plan.total_nodes,
                                           out=U if self.keep_outputs else None))
                     used -= fp
                     plans.pop(req.rid, None)
+                    # its combination is done (event above); freeing synchronises the solver's
+                    # stream, so point it at the set-up stream rather than the busy side stream
+                    solver.set_stream(self.setup)
                     solver.close()
                 else:
-                    still.append((req, solver, admit_s, fp, ev, U))
+                    still.append((req, solver, admit_s, fp, ev, U, steps))
             finishing = still
             if not active:
                 if finishing:
@@ -110,15 +121,27 @@ class ServingLoop:
                     if wait > 0:
                         time.sleep(min(wait, 0.005))
                 continue
+            tp = clock()
             self.batch.step(self.steps_per_tick)
-            for slot in self.batch.poll():
+            tq = clock()
+            done = self.batch.poll()
+            tr = clock()
+            self.stats["step_enqueue"] += tq - tp
+            self.stats["poll_wait"] += tr - tq
+            for slot in done:
                 req, solver, admit_s, fp = active.pop(slot)
                 self.batch.release(slot)
+                t, steps = solver.query()  # cheap: the solver's stream is still the set-up stream
+                # the batch stream has finished this solve's steps (poll synchronised it); the
+                # set-up stream's restriction was ordered before its admission
+                solver.set_stream(self.side)
                 with torch.cuda.stream(self.side):
                     U = solver.prolongate_combine()
                     ev = torch.cuda.Event()
                     ev.record(self.side)
-                finishing.append((req, solver, admit_s, fp, ev, U))
+                finishing.append((req, solver, admit_s, fp, ev, U, steps))
+            self.stats["finish"] += clock() - tr
+            self.stats["ticks"] += 1
         return results
 
     def close(self):

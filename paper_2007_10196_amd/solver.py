@@ -81,6 +81,12 @@ class Solver:
         self.handle = h
         self.real = torch.float64 if problem.precision == B.FP64 else torch.float32
 
+    def set_stream(self, stream: torch.cuda.Stream):
+        """Enqueue later calls on `stream` (earlier work is not waited for)."""
+        B.check(B.lib().sgw_solver_set_stream(self.handle, C.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+        return self
+
     # --- the algorithm
     def restrict(self):
         B.check(B.lib().sgw_restrict_initial(self.handle))
