@@ -1,0 +1,319 @@
+// Per-step kernels of libsgweno around the stage kernel: initial restriction
+// (one solve or many), the Vlasov coefficient tables and constant LF speeds,
+// time-step records, the shared time step and the completion flags.
+#include "sgw_internal.h"
+
+namespace {
+
+// ---------------------------------------------------------------- set-up kernels
+
+__global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long long v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Coefficient tables of the fixed-field Vlasov flux and the constant LF speeds:
+// f_{x_k} = v_k u (coefficient indexed by the v_k node), f_{v_k} = E_k(x_k) u.
+// One workgroup per (grid, direction); the max over the table is the LF speed.
+__global__ void coef_init_kernel(GridDev* grids, double* coef_base, const int64_t* coef_off, double amp, double kE)
+{
+    __shared__ double red[SGW_BLOCK / 64];
+    GridDev* g = grids + blockIdx.x;
+    const int k = blockIdx.y;
+    if (k >= g->d) return;
+    const int m = g->d / 2;
+    const int src = g->coef_src[k];
+    double* tab = coef_base + coef_off[blockIdx.x * SGW_MAX_DIM + k];
+    const int n = g->n[src];
+    double amax = 0.0;
+    for (int j = threadIdx.x; j < n; j += SGW_BLOCK) {
+        const double x = g->lo[src] + j * g->h[src];
+        const double c = (k < m) ? x : amp * sin(kE * x);
+        tab[j] = c;
+        amax = fmax(amax, fabs(c));
+    }
+    amax = wave_max(amax);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mm = red[0];
+        for (int w = 1; w < SGW_BLOCK / 64; w++) mm = fmax(mm, red[w]);
+        g->alpha_c[k] = mm;
+    }
+}
+
+struct RestrictArgs {
+    int32_t ic, precision;
+    double ip[8];
+};
+
+// Alg. Step 1: the initial condition at node idx (row-major, direction 1
+// fastest) of grid g, whose coordinates are x_j = lo + j h.
+__device__ __forceinline__ double ic_value(const GridDev* g, int64_t idx, int ic, const double* ip)
+{
+    uint32_t r = (uint32_t)idx;
+    double x[SGW_MAX_DIM] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < g->d; k++) {
+        const uint32_t q = FDIV(r, g->fd_n[k]);
+        const int j = (int)(r - q * (uint32_t)g->n[k]);
+        r = q;
+        x[k] = g->lo[k] + j * g->h[k];
+    }
+    if (ic == SGW_IC_SINE) {
+        double s = 0.0;
+        for (int k = 0; k < g->d; k++) s += x[k];
+        return ip[0] + ip[1] * sin(ip[2] * s + ip[3]);
+    }
+    const int m = g->d / 2;
+    double v2 = 0.0, pert = 1.0, norm = 1.0;
+    for (int k = 0; k < m; k++) {
+        v2 += x[m + k] * x[m + k];
+        pert *= cos(ip[1] * x[k] + ip[2 + k]);
+        norm *= 2.0 * M_PI;
+    }
+    return exp(-0.5 * v2) / sqrt(norm) * (1.0 + ip[0] * pert);
+}
+
+template <typename Real>
+__global__ void restrict_kernel(const GridDev* grids, RestrictArgs a)
+{
+    __shared__ double red[SGW_BLOCK / 64];
+    const GridDev* g = grids + blockIdx.y;
+    int64_t total = 1;
+    for (int k = 0; k < g->d; k++) total *= g->n[k];
+    Real* u = (Real*)g->u;
+    double amax = 0.0;
+    for (int64_t idx = blockIdx.x * (int64_t)SGW_BLOCK + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * SGW_BLOCK) {
+        const Real vr = (Real)ic_value(g, idx, a.ic, a.ip);
+        u[idx] = vr;
+        amax = nanmax(amax, fabs((double)vr));
+    }
+    if (g->dyn_alpha) block_atomic_max(amax, g->alpha + 0, red);
+}
+
+// Restriction of many solves in one launch: one workgroup per chunk of a grid.
+template <typename Real>
+__global__ void restrict_many_kernel(const RestrictItem* items)
+{
+    __shared__ double red[SGW_BLOCK / 64];
+    const RestrictItem* it = items + blockIdx.x;
+    const GridDev* g = it->g;
+    Real* u = (Real*)g->u;
+    double amax = 0.0;
+    for (int i = threadIdx.x; i < it->count; i += SGW_BLOCK) {
+        const int64_t idx = it->start + i;
+        const Real vr = (Real)ic_value(g, idx, it->ic, it->ip);
+        u[idx] = vr;
+        amax = nanmax(amax, fabs((double)vr));
+    }
+    if (g->dyn_alpha) block_atomic_max(amax, g->alpha + 0, red);
+}
+
+__device__ __forceinline__ void req_reset(ReqDev* r)
+{
+    r->t = 0.0;
+    r->steps = 0;
+    r->done = 0;
+    r->nonfinite = 0;
+    r->dt = 0.0;
+}
+
+// Before a restriction of many solves: clear each solve's wave-speed slots and
+// rewind its time-step record (one workgroup per solve).
+__global__ void reset_many_kernel(const ResetItem* items)
+{
+    const ResetItem* it = items + blockIdx.x;
+    for (int i = threadIdx.x; i < it->nalpha; i += blockDim.x) it->alpha[i] = 0ull;
+    if (threadIdx.x == 0) req_reset(it->req);
+}
+
+__global__ void req_reset_kernel(ReqDev* r) { req_reset(r); }
+
+__global__ void req_set_final_kernel(ReqDev* r, double T)
+{
+    r->T = T;
+    r->done = r->nonfinite ? 1 : 0;
+}
+
+// Final times of newly admitted batch slots; a NaN entry leaves its slot alone.
+__global__ void req_set_final_many_kernel(ReqDev* const* reqs, const double* tf, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ReqDev* r = reqs[i];
+    const double T = tf[i];
+    if (!r || T != T) return;
+    r->T = T;
+    r->done = r->nonfinite ? 1 : 0;
+}
+
+// The shared time step (Sec. 3): dt = cfl / sum_k (A_k / h_k^fine), A_k the
+// largest LF speed over all component grids of the solve at u^n, clipped so the
+// last step lands on T.  One wavefront per solve: lanes over grids, then a
+// wave-wide max (exact, so the result does not depend on the order).
+__device__ void dt_wave(ReqDev* r)
+{
+    const int lane = threadIdx.x & 63;
+    if (!r->active || r->done) {
+        if (lane == 0) r->dt = 0.0;
+        return;
+    }
+    const double rem = r->T - r->t;
+    const double tol = 1e-12 * (r->T > 1.0 ? r->T : 1.0);
+    if (!(rem > tol)) {
+        if (lane == 0) {
+            r->done = 1;
+            r->dt = 0.0;
+        }
+        return;
+    }
+    double dt;
+    if (r->dt_mode == SGW_DT_POW53) {
+        dt = r->dt_pow53;
+    } else {
+        double denom = 0.0;
+        for (int k = 0; k < r->d; k++) {
+            double A = 0.0;
+            for (int g = lane; g < r->ngrids; g += 64) {
+                const GridDev* gd = r->grids + g;
+                const double a = gd->dyn_alpha ? __longlong_as_double((long long)gd->alpha[0]) : gd->alpha_c[k];
+                A = nanmax(A, a);
+            }
+            A = wave_max(A);
+            denom += A / r->hfin[k];
+        }
+        if (denom != denom || denom > 1.7e308) {
+            if (lane == 0) {
+                r->nonfinite = 1;
+                r->done = 1;
+                r->dt = 0.0;
+            }
+            return;
+        }
+        dt = denom > 0.0 ? r->cfl / denom : rem;
+    }
+    if (dt > rem) dt = rem;
+    if (lane == 0) {
+        r->dt = dt;
+        r->t += dt;
+        r->steps += 1;
+    }
+}
+
+__global__ void __launch_bounds__(64) dt_kernel(ReqDev* const* reqs, int nreq)
+{
+    const int i = blockIdx.x;
+    if (i < nreq && reqs[i]) dt_wave(reqs[i]);
+}
+
+__global__ void __launch_bounds__(64) dt_one_kernel(ReqDev* r) { dt_wave(r); }
+
+__global__ void gather_done_kernel(ReqDev* const* reqs, int nreq, int* flags)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nreq) flags[i] = reqs[i] ? (reqs[i]->done ? 1 : 0) | (reqs[i]->nonfinite ? 2 : 0) : 0;
+}
+
+
+} // namespace
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)((n + SGW_BLOCK - 1) / SGW_BLOCK);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks), dim3(SGW_BLOCK), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_coef_init(GridDev* grids_dev, const GridDev* grids_host, int G, double* coef_base,
+                            const int64_t* coef_off_dev, const sgw_problem* pb, hipStream_t s)
+{
+    (void)grids_host;
+    if (G <= 0) return hipSuccess;
+    hipLaunchKernelGGL(coef_init_kernel, dim3(G, SGW_MAX_DIM), dim3(SGW_BLOCK), 0, s, grids_dev, coef_base,
+                       coef_off_dev, pb->flux_params[0], pb->flux_params[1]);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict(const GridDev* grids_dev, const GridDev* grids_host, int G, int precision,
+                           const sgw_problem* pb, hipStream_t s)
+{
+    int64_t maxn = 1;
+    for (int g = 0; g < G; g++) {
+        int64_t n = 1;
+        for (int k = 0; k < grids_host[g].d; k++) n *= grids_host[g].n[k];
+        maxn = n > maxn ? n : maxn;
+    }
+    int bx = (int)((maxn + SGW_BLOCK - 1) / SGW_BLOCK);
+    if (bx > 256) bx = 256;
+    RestrictArgs a;
+    a.ic = pb->ic;
+    a.precision = precision;
+    for (int i = 0; i < 8; i++) a.ip[i] = pb->ic_params[i];
+    if (precision == SGW_FP64)
+        hipLaunchKernelGGL(restrict_kernel<double>, dim3(bx, G), dim3(SGW_BLOCK), 0, s, grids_dev, a);
+    else
+        hipLaunchKernelGGL(restrict_kernel<float>, dim3(bx, G), dim3(SGW_BLOCK), 0, s, grids_dev, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_req_reset(ReqDev* r, hipStream_t s)
+{
+    hipLaunchKernelGGL(req_reset_kernel, dim3(1), dim3(1), 0, s, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_req_set_final(ReqDev* r, double T, hipStream_t s)
+{
+    hipLaunchKernelGGL(req_set_final_kernel, dim3(1), dim3(1), 0, s, r, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_req_set_final_many(ReqDev* const* reqs, const double* tf, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(req_set_final_many_kernel, dim3((n + SGW_BLOCK - 1) / SGW_BLOCK), dim3(SGW_BLOCK), 0, s, reqs,
+                       tf, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict_many(const ResetItem* resets, int nresets, const RestrictItem* items, int nitems,
+                                int precision, hipStream_t s)
+{
+    if (nresets > 0) {
+        hipLaunchKernelGGL(reset_many_kernel, dim3(nresets), dim3(64), 0, s, resets);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (nitems <= 0) return hipSuccess;
+    if (precision == SGW_FP64)
+        hipLaunchKernelGGL(restrict_many_kernel<double>, dim3(nitems), dim3(SGW_BLOCK), 0, s, items);
+    else
+        hipLaunchKernelGGL(restrict_many_kernel<float>, dim3(nitems), dim3(SGW_BLOCK), 0, s, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt(ReqDev* const* reqs, int nreq, hipStream_t s)
+{
+    if (nreq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dt_kernel, dim3(nreq), dim3(64), 0, s, reqs, nreq);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt_one(ReqDev* req, hipStream_t s)
+{
+    hipLaunchKernelGGL(dt_one_kernel, dim3(1), dim3(64), 0, s, req);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_done(ReqDev* const* reqs, int nreq, int* flags, hipStream_t s)
+{
+    if (nreq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_done_kernel, dim3((nreq + 63) / 64), dim3(64), 0, s, reqs, nreq, flags);
+    return hipGetLastError();
+}

@@ -45,6 +45,31 @@ __device__ __forceinline__ uint32_t fdiv_ms(uint32_t x, uint32_t m, uint32_t s)
 
 struct ReqDev;
 
+// max that keeps a NaN (a NaN wave speed must reach the time-step check)
+__device__ __forceinline__ double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Max over the workgroup, then one atomic max on the bit pattern (non-negative
+// doubles order like their unsigned bit patterns; NaN sorts above everything).
+__device__ __forceinline__ void block_atomic_max(double v, unsigned long long* dst, double* red)
+{
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < SGW_BLOCK / 64; w++) m = nanmax(m, red[w]);
+        atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
 // One component grid as seen by the stage kernel.  Box = the tile one
 // workgroup updates; t[k] divides n[k]; a box that does not span its grid in
 // direction k carries 3 halo nodes on each side in that direction.  LDS holds
