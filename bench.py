@@ -163,6 +163,34 @@ def serving_run(box_target, n=None, loads=(0.7,), blocks_per_cu=0):
     return main
 
 
+def full_grid_run(torch, probs, box_target, bpc, steps=2):
+    """The paper's comparison (Sec. 3 tables): the same solves on one full grid of the finest
+    resolution (root 256, finest level 0), batched the same way; time per step of all solves and
+    the L1 error against the exact solution."""
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.solver import Batch, Solver
+    full = [p.replace(nr=p.n_fine, nl=0) for p in probs]
+    solvers = [Solver(p, device="cuda:0", box_target=box_target) for p in full]
+    fine = solvers[0].plan.fine_nodes
+    outs = [torch.empty(fine, dtype=torch.float64, device="cuda:0") for _ in solvers]
+    exacts = [s.exact(T_FINAL) for s in solvers]
+    res = torch.zeros((len(solvers), 2), dtype=torch.float64, device="cuda:0")
+    batch = Batch(max_solvers=len(solvers), precision=B.FP32_SWEEP,
+                  hbm_budget=sum(s.plan.footprint for s in solvers) + (1 << 30),
+                  max_items=sum(s.plan.total_nodes // 32 + 64 for s in solvers))
+    batch.set_blocks_per_cu(bpc)
+    run_batch_step(torch, batch, solvers, outs, exacts, res)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        norms = run_batch_step(torch, batch, solvers, outs, exacts, res)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    batch.close()
+    return {"ms_per_step": ms, "l1_mean": float(norms[:, 0].mean()), "nodes_per_solve": solvers[0].plan.total_nodes,
+            "time_steps": solvers[0].query()[1]}
+
+
 def step_estimate_any(pb):
     """Steps of the shared-dt loop for any workload family (wave-speed bound at t = 0)."""
     if pb.flux == W.FLUX_BURGERS:
@@ -205,6 +233,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=20)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-full", action="store_true", help="skip the single full-grid comparison")
     ap.add_argument("--box-target", type=int, default=0,
                     help="0: autotune the stage box target and the workgroups per compute unit")
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="with --box-target: stage workgroups per CU")
@@ -314,6 +343,19 @@ def main():
                  "speedup_of_value": value / (stp * nodes / tp),
                  "equal_l1": bool(abs(l1s[0] - l1p) <= 0.01 * l1p), "l1_batched_fp32_same_solve": float(l1s[0])}
 
+    full = None
+    if not args.no_full:
+        f = full_grid_run(torch, probs, box_target, bpc)
+        full = {"full_grid": "one 256x256 grid (root 256, finest level 0), same solves, same batched FP32 path",
+                "full_ms_per_step": f["ms_per_step"], "sparse_ms_per_step": ms_per_step,
+                "time_ratio_sparse_over_full": ms_per_step / f["ms_per_step"],
+                "l1_full": f["l1_mean"], "l1_sparse": float(l1s.mean()),
+                "nodes_full": f["nodes_per_solve"], "nodes_sparse": nodes, "time_steps_full": f["time_steps"],
+                "paper_cpu_time_ratio": "2D WENO sparse/single 0.72-0.68 (Table ex3aweno: 0.414/0.572 s at "
+                                        "N_h = 80 to 781.990/1149.946 s at 640), 2.3 GHz workstation"}
+        print(f"[bench] full grid: {f['ms_per_step']:.2f} ms/step, L1 {f['l1_mean']:.3e} "
+              f"(sparse {ms_per_step:.2f} ms/step, L1 {float(l1s.mean()):.3e})", file=sys.stderr, flush=True)
+
     serving = None if args.no_serving else serving_run(
         box_target, n=args.serving_requests, loads=[float(x) for x in args.serving_loads.split(",")],
         blocks_per_cu=bpc)
@@ -328,7 +370,7 @@ def main():
                                   "combination", "solves_per_step": len(solvers), "component_nodes": nodes,
                       "mode": "batched: one HIP graph per time step, persistent fused WENO5+RK3 stage launch"},
            "l1_mean": float(l1s.mean()), "l1_max": float(l1s.max()),
-           "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "latency": serving,
+           "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "latency": serving, "sparse_vs_full": full,
            "autotune": {"box_target": box_target, "blocks_per_cu": bpc, "stage_us_by_target_and_cap": tune["us"]}}
     print(json.dumps(out), flush=True)
 

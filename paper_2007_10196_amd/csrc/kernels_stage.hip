@@ -25,8 +25,9 @@ typedef const SGW_CONST GridDev* GridC;
 // LDS indices stay below 2^16: the full-rate 24-bit multiply is exact for them
 #define M24(a, b) __mul24((a), (b))
 
-__device__ __forceinline__ float rdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ double rdiv(double a, double b) { return a / b; }
+// c + num / den: one reciprocal and an fma in FP32, a division in FP64
+__device__ __forceinline__ float wsum(float c, float num, float den) { return fmaf(num, __builtin_amdgcn_rcpf(den), c); }
+__device__ __forceinline__ double wsum(double c, double num, double den) { return c + num / den; }
 
 // WENO5 flux (eqs. 2.7, 2.7.1, 2.6, 2.7.2) of the positive-wind big stencil
 // (a..e) = (f_{i-2} .. f_{i+2}), written in differences so that neighbouring
@@ -43,22 +44,25 @@ template <typename Real>
 __device__ __forceinline__ Real weno5s(Real c, Real D0, Real D1, Real D2, Real D3, Real T0, Real T1, Real T2,
                                        int linear)
 {
-    const Real R0 = Real(0.5 / 6.0) * D1 - Real(0.2 / 6.0) * D0;
-    const Real R1 = Real(0.6 / 6.0) * D1 + Real(1.2 / 6.0) * D2;
-    const Real R2 = Real(1.2 / 6.0) * D2 - Real(0.3 / 6.0) * D3;
+    // every multiply-add is an explicit fma: a flux then rounds the same wherever it sits in a
+    // window, so results do not depend on the box decomposition
+    const Real d2 = Real(1.2 / 6.0) * D2;
+    const Real R0 = fma(Real(0.5 / 6.0), D1, Real(-0.2 / 6.0) * D0);
+    const Real R1 = fma(Real(0.6 / 6.0), D1, d2);
+    const Real R2 = fma(Real(-0.3 / 6.0), D3, d2);
     if (linear) return c + ((R0 + R1) + R2);
-    const Real g0 = Real(3) * D1 - D0, g1 = D1 + D2, g2 = D3 - Real(3) * D2;
+    const Real g0 = fma(Real(3), D1, -D0), g1 = D1 + D2, g2 = fma(Real(-3), D2, D3);
     const Real K = Real(3.0 / 13.0);
-    Real e0 = (K * g0) * g0 + T0;
-    Real e1 = (K * g1) * g1 + T1;
-    Real e2 = (K * g2) * g2 + T2;
+    Real e0 = fma(K * g0, g0, T0);
+    Real e1 = fma(K * g1, g1, T1);
+    Real e2 = fma(K * g2, g2, T2);
     e0 *= e0;
     e1 *= e1;
     e2 *= e2;
     const Real P12 = e1 * e2, P02 = e0 * e2, P01 = e0 * e1;
-    const Real num = R0 * P12 + R1 * P02 + R2 * P01;
-    const Real den = Real(0.1) * P12 + Real(0.6) * P02 + Real(0.3) * P01;
-    return c + rdiv(num, den);
+    const Real num = fma(R2, P01, fma(R1, P02, R0 * P12));
+    const Real den = fma(Real(0.3), P01, fma(Real(0.6), P02, Real(0.1) * P12));
+    return wsum(c, num, den);
 }
 
 // NI consecutive interface fluxes F_{i+1/2}, i = i0..i0+NI-1, from the NI+5 values
@@ -76,9 +80,9 @@ __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real 
     for (int q = 0; q < NI + 5; q++) {
         if (burgers) {
             // f^+- = (u^2/2 +- alpha u)/2
-            const Real f4 = (Real(0.25) * v[q]) * v[q], av = ha * v[q];
-            pv[q] = f4 + av;
-            mv[q] = f4 - av;
+            const Real f4 = (Real(0.25) * v[q]) * v[q];
+            pv[q] = fma(ha, v[q], f4);
+            mv[q] = fma(-ha, v[q], f4);
         } else {
             pv[q] = cp * v[q];
             mv[q] = cm * v[q];
@@ -96,8 +100,8 @@ __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real 
 #pragma unroll
     for (int q = 1; q < NI + 4; q++) {
         const Real sp = dp[q] - dp[q - 1], sm = dm[q] - dm[q - 1];
-        tp[q] = sp * sp + epsT;
-        tm[q] = sm * sm + epsT;
+        tp[q] = fma(sp, sp, epsT);
+        tm[q] = fma(sm, sm, epsT);
     }
 #pragma unroll
     for (int s = 0; s < NI; s++) {
@@ -353,7 +357,7 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
                     fhi = lo + hf * CSk + M24(hi, CSk * Ik);
                     flo = (hf || lo >= CSk) ? fhi - CSk : fhi + (tk - 1) * CSk;
                 }
-                acc[r] -= (sfk[fhi] - sfk[flo]) * ih;
+                acc[r] = fma(sfk[flo] - sfk[fhi], ih, acc[r]);
             }
         }
     }
@@ -366,11 +370,11 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
             int line, c0;
             node_rc(r, line, c0);
             const int gi = node_gi(r, line, c0);
-            const Real val = su[c0 + M24(RS, line)] + dtr * acc[r];
+            const Real val = fma(dtr, acc[r], su[c0 + M24(RS, line)]);
             Real res;
             if (stage == 0) res = val;
-            else if (stage == 1) res = Real(0.75) * u0[gi] + Real(0.25) * val;
-            else res = Real(1.0 / 3.0) * u0[gi] + Real(2.0 / 3.0) * val;
+            else if (stage == 1) res = fma(Real(0.75), u0[gi], Real(0.25) * val);
+            else res = fma(Real(1.0 / 3.0), u0[gi], Real(2.0 / 3.0) * val);
             out[gi] = res;
             const Real ar = fabs(res);
             amax = (ar > amax || ar != ar) ? ar : amax;

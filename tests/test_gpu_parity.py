@@ -352,3 +352,34 @@ def test_batch_admit_many_and_release_many():
     big.release_many(slots)
     for s, r in zip(solvers, ref):
         assert torch.equal(s.prolongate_combine(), r)
+
+
+@pytest.mark.parametrize("prec", [W.PREC_FP32, W.PREC_FP64])
+def test_launch_shape_does_not_change_results(prec):
+    """Box target (box decomposition) and workgroups per CU change only who computes each interface
+    flux, not the arithmetic: batched results are bitwise identical across launch shapes."""
+    torch, B, Solver, Batch = _lib()
+    from paper_2007_10196_amd.solver import restrict_many
+    rng = np.random.default_rng(31)
+    probs = [W.randomized(fam, nl, rng, precision=prec) for fam, nl in ((2, 4), (3, 3), (4, 2), (1, 4))]
+    probs = [p.replace(T=min(p.T, 0.05)) for p in probs]
+    outs = []
+    for target, bpc in ((256, 0), (1024, 3), (2048, 7)):
+        _announce(f"launch shape target {target} bpc {bpc} prec {prec}")
+        solvers = [Solver(p, box_target=target) for p in probs]
+        batch = Batch(max_solvers=8, precision=prec, hbm_budget=1 << 40)
+        batch.set_blocks_per_cu(bpc)
+        restrict_many(solvers)
+        batch.admit_many(solvers)
+        done = set()
+        while len(done) < len(solvers):
+            batch.step(4)
+            done |= set(batch.poll())
+        batch.release_many(sorted(batch.slots))
+        outs.append([s.prolongate_combine() for s in solvers])
+    bad = []
+    for j, other in enumerate(outs[1:], 1):
+        for i, (a, b) in enumerate(zip(outs[0], other)):
+            if not torch.equal(a, b):
+                bad.append((j, probs[i].name, probs[i].nl, float((a - b).abs().max()), int((a != b).sum())))
+    assert not bad, bad
