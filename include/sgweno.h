@@ -134,6 +134,9 @@ sgw_status sgw_plan_info(const sgw_plan_t* plan, int32_t* num_grids, int64_t* to
 sgw_status sgw_plan_grid(const sgw_plan_t* plan, int32_t g, int32_t level[SGW_MAX_DIM],
                          int32_t shape[SGW_MAX_DIM], int32_t* coef, int64_t* offset);
 
+/* Finest-grid tile the prolongation kernel uses (one workgroup per tile). */
+sgw_status sgw_plan_fine_tile(const sgw_plan_t* plan, int32_t tile[SGW_MAX_DIM]);
+
 /* Box extents the stage kernel uses for grid g (one workgroup per box). */
 sgw_status sgw_plan_grid_box(const sgw_plan_t* plan, int32_t g, int32_t box[SGW_MAX_DIM]);
 

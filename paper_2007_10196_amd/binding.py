@@ -55,6 +55,7 @@ _SIGS = {
     "sgw_plan_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "sgw_plan_grid": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32 * 4, C.c_int32 * 4, C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int64)]),
+    "sgw_plan_fine_tile": (C.c_int32, [C.c_void_p, C.c_int32 * 4]),
     "sgw_plan_grid_box": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32 * 4]),
     "sgw_solver_create": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "sgw_solver_free": (None, [C.c_void_p]),

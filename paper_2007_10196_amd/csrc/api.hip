@@ -44,13 +44,6 @@ extern "C" const char* sgw_status_string(sgw_status s)
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 
-static int smallest_factor(int n)
-{
-    for (int p = 2; p * p <= n; p++)
-        if (n % p == 0) return p;
-    return n;
-}
-
 // ---------------------------------------------------------------- index set
 // All l in Z_{>=0}^d with |l| = s, lexicographic in (l_1..l_d): the first
 // component counts up from 0 and the rest are filled recursively.
@@ -232,6 +225,39 @@ static size_t prolong_buffer_elems(const sgw_plan& p, const int* T)
     return (best + 1) / 2 * 2;
 }
 
+// Interpolations and staged coarse values of one finest-grid tile T, summed
+// over the grids.  Directions are refined in order 1..d, so the pass of
+// direction k covers the tile in directions <= k and the coarse block (stencil
+// halo included) in the directions after k: a small T early and a large T late
+// keeps the halo work of the early passes small.
+static void prolong_tile_work(const sgw_plan& p, const int* T, double* interp, double* load)
+{
+    const int d = p.pb.dim;
+    *interp = 0.0;
+    *load = 0.0;
+    for (int g = 0; g < p.G; g++) {
+        int c[SGW_MAX_DIM];
+        for (int k = 0; k < d; k++) {
+            const int m = p.cfg.finest_level - p.levels[g][k];
+            c[k] = m == 0 ? T[k] : (T[k] - 1) / (1 << m) + 6;
+        }
+        double l = 1.0;
+        for (int k = 0; k < d; k++) l *= c[k];
+        *load += l;
+        for (int k = 0; k < d; k++) {
+            if (p.cfg.finest_level - p.levels[g][k] == 0) continue;
+            double out = 1.0;
+            for (int j = 0; j < d; j++) out *= (j <= k) ? T[j] : c[j];
+            *interp += out;
+        }
+    }
+}
+
+// Tile search: every combination of divisors T_k | N with at most 8 (2D) or 16
+// points per thread and two LDS buffers within 64 KB; the cost per finest node
+// counts interpolations (~50 operations each), staged coarse values (~10), a
+// fixed cost per grid and tile (barriers, set-up: ~2000) and the FP64 write of
+// the node (more when tile rows along direction 1 are short).
 static void choose_fine_tile(sgw_plan& p)
 {
     const int d = p.pb.dim;
@@ -242,19 +268,40 @@ static void choose_fine_tile(sgw_plan& p)
         T[k] = p.cfg.fine_tile[k] > 0 ? p.cfg.fine_tile[k] : p.N;
         manual |= p.cfg.fine_tile[k] > 0;
     }
-    const int target = d <= 2 ? 1024 : 2048;
     if (!manual) {
+        std::vector<int> divs;
+        for (int v = 1; v <= p.N; v++)
+            if (p.N % v == 0) divs.push_back(v);
+        const int cap = d <= 2 ? SGW_BLOCK * 8 : SGW_BLOCK * 16;
+        const int nd = (int)divs.size();
+        double best = 1e300;
+        int bt[SGW_MAX_DIM] = {1, 1, 1, 1};
+        int idx[SGW_MAX_DIM] = {0, 0, 0, 0};
         for (;;) {
-            int pts = 1;
-            for (int k = 0; k < d; k++) pts *= T[k];
-            const size_t lds = 2 * rs * prolong_buffer_elems(p, T);
-            if (pts <= target && lds <= 64 * 1024) break;
-            int kk = -1;
-            for (int k = d - 1; k >= 0; k--)
-                if (T[k] > 1 && (kk < 0 || T[k] > T[kk])) kk = k;
-            if (kk < 0) break;
-            T[kk] /= smallest_factor(T[kk]);
+            int t[SGW_MAX_DIM] = {1, 1, 1, 1};
+            int64_t pts = 1;
+            for (int k = 0; k < d; k++) {
+                t[k] = divs[idx[k]];
+                pts *= t[k];
+            }
+            if (pts <= cap && pts >= SGW_BLOCK / 4 && 2 * rs * prolong_buffer_elems(p, t) <= 64 * 1024) {
+                double interp, load;
+                prolong_tile_work(p, t, &interp, &load);
+                // the tile's FP64 rows along direction 1 are written to HBM: rows shorter than
+                // 8 values (64 bytes) waste most of each write transaction
+                const double write = 40.0 * (t[0] >= 8 ? 1.0 : 8.0 / t[0]);
+                const double cost = (50.0 * interp + 10.0 * load + 2000.0 * p.G) / (double)pts + write;
+                if (cost < best - 1e-9) {
+                    best = cost;
+                    for (int k = 0; k < SGW_MAX_DIM; k++) bt[k] = t[k];
+                }
+            }
+            int k = 0;
+            while (k < d && ++idx[k] == nd) idx[k++] = 0;
+            if (k == d) break;
         }
+        if (best < 1e300)
+            for (int k = 0; k < d; k++) T[k] = bt[k];
     }
     for (int k = 0; k < SGW_MAX_DIM; k++) p.fine_T[k] = k < d ? T[k] : 1;
     p.pro_buf_elems = prolong_buffer_elems(p, p.fine_T);
@@ -467,6 +514,13 @@ extern "C" sgw_status sgw_plan_grid(const sgw_plan_t* p, int32_t g, int32_t leve
 }
 
 // Box extents chosen for grid g (for tests and the tuner).
+extern "C" sgw_status sgw_plan_fine_tile(const sgw_plan_t* p, int32_t tile[SGW_MAX_DIM])
+{
+    if (!p || !tile) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    for (int k = 0; k < SGW_MAX_DIM; k++) tile[k] = p->fine_T[k];
+    return SGW_OK;
+}
+
 extern "C" sgw_status sgw_plan_grid_box(const sgw_plan_t* p, int32_t g, int32_t box[SGW_MAX_DIM])
 {
     if (!p || g < 0 || g >= p->G || !box) return sgw_fail(SGW_ERR_INVALID_ARG, "bad grid");

@@ -29,6 +29,9 @@ class Plan:
         g, tn, fn = C.c_int32(), C.c_int64(), C.c_int64()
         B.check(B.lib().sgw_plan_info(h, C.byref(g), C.byref(tn), C.byref(fn)))
         self.num_grids, self.total_nodes, self.fine_nodes = g.value, tn.value, fn.value
+        ft = (C.c_int32 * 4)()
+        B.check(B.lib().sgw_plan_fine_tile(h, ft))
+        self.fine_tile = tuple(ft[:problem.d])
         self.grids = []
         for i in range(self.num_grids):
             lv, sh = (C.c_int32 * 4)(), (C.c_int32 * 4)()
