@@ -257,7 +257,8 @@ static void prolong_tile_work(const sgw_plan& p, const int* T, double* interp, d
 // points per thread and two LDS buffers within 64 KB; the cost per finest node
 // counts interpolations (~50 operations each), staged coarse values (~10), a
 // fixed cost per grid and tile (barriers, set-up: ~2000) and the FP64 write of
-// the node (more when tile rows along direction 1 are short).
+// the node (more when tile rows along direction 1 are short), scaled up when the
+// LDS of two buffers leaves fewer than 4 workgroups per compute unit.
 static void choose_fine_tile(sgw_plan& p)
 {
     const int d = p.pb.dim;
@@ -284,13 +285,18 @@ static void choose_fine_tile(sgw_plan& p)
                 t[k] = divs[idx[k]];
                 pts *= t[k];
             }
-            if (pts <= cap && pts >= SGW_BLOCK / 4 && 2 * rs * prolong_buffer_elems(p, t) <= 64 * 1024) {
+            const size_t lds = 2 * rs * prolong_buffer_elems(p, t);
+            if (pts <= cap && pts >= SGW_BLOCK / 4 && lds <= 64 * 1024) {
                 double interp, load;
                 prolong_tile_work(p, t, &interp, &load);
+                // fewer than 4 resident workgroups per CU (160 KB of LDS each) leave the
+                // kernel latency-bound: charge the missing occupancy
+                const double occ = (double)(163840 / lds);
+                const double slow = occ >= 4.0 ? 1.0 : 4.0 / occ;
                 // the tile's FP64 rows along direction 1 are written to HBM: rows shorter than
                 // 8 values (64 bytes) waste most of each write transaction
                 const double write = 40.0 * (t[0] >= 8 ? 1.0 : 8.0 / t[0]);
-                const double cost = (50.0 * interp + 10.0 * load + 2000.0 * p.G) / (double)pts + write;
+                const double cost = slow * ((50.0 * interp + 10.0 * load + 2000.0 * p.G) / (double)pts + write);
                 if (cost < best - 1e-9) {
                     best = cost;
                     for (int k = 0; k < SGW_MAX_DIM; k++) bt[k] = t[k];
