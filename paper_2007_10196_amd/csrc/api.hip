@@ -155,6 +155,20 @@ static void fill_box_geometry(GridDev& g, int precision)
     int fm = 0;
     for (int k = 0; k < g.d; k++) fm = g.flux_total[k] > fm ? g.flux_total[k] : fm;
     g.sf_elems = (fm + 1) / 2 * 2;
+    // 3D/4D boxes that do not span their grid keep the global offset of every core row and
+    // halo-slab row in LDS
+    int rt = 0;
+    for (int k = 0; k < SGW_MAX_DIM; k++) g.rt_off[k] = 0;
+    if (g.d >= 3 && !g.whole) {
+        rt = g.lines;
+        for (int k = 1; k < g.d; k++)
+            if (g.halo[k]) {
+                g.rt_off[k] = rt;
+                rt += 2 * (g.slab_n[k] / g.t[0]);
+            }
+    }
+    g.rt_total = rt;
+    g.pad2_ = 0;
 }
 
 // Box search: every combination of divisors t_k | n_k with a core of at most

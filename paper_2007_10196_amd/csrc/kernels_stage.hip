@@ -177,11 +177,58 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
             c0 = e - M24((int)q, t0);
         }
     };
+    // 3D/4D: global offsets of the box rows (and of the halo slab rows) go to an LDS table
+    // once per box, so a staged value costs one table read instead of a division per direction
+    int* __restrict__ rt = (int*)(sf + 2 * g->sf_elems);
+    if constexpr (D >= 3) {
+        if (!whole) {
+            for (int ln = tid; ln < g->lines; ln += SGW_BLOCK) {
+                uint32_t r = (uint32_t)ln;
+                int gi = o[0];
+#pragma unroll
+                for (int j = 1; j < D; j++) {
+                    const uint32_t q = FDIV(r, g->fd_t[j]);
+                    gi += (o[j] + (int)(r - q * (uint32_t)g->t[j])) * g->stride[j];
+                    r = q;
+                }
+                rt[ln] = gi;
+            }
+#pragma unroll
+            for (int k = 1; k < D; k++) {
+                if (!g->halo[k]) continue;
+                const int nr = g->slab_n[k] / t0; // slab rows per side
+                for (int e = tid; e < 2 * nr; e += SGW_BLOCK) {
+                    const int side = e >= nr ? 1 : 0;
+                    uint32_t r = (uint32_t)(e - side * nr);
+                    int gi = o[0];
+#pragma unroll
+                    for (int j = 1; j < D; j++) {
+                        int x;
+                        if (j == k) {
+                            const uint32_t q = r / 3u;
+                            const int c = (int)(r - 3u * q);
+                            r = q;
+                            x = side ? o[j] + g->t[j] + c : o[j] - 3 + c;
+                            x += (x < 0) ? g->n[j] : 0;
+                            x -= (x >= g->n[j]) ? g->n[j] : 0;
+                        } else {
+                            const uint32_t q = FDIV(r, g->fd_t[j]);
+                            x = o[j] + (int)(r - q * (uint32_t)g->t[j]);
+                            r = q;
+                        }
+                        gi += x * g->stride[j];
+                    }
+                    rt[g->rt_off[k] + e] = gi;
+                }
+            }
+            __syncthreads();
+        }
+    }
     auto node_gi = [&](int r, int line, int c0) -> int {
         if (whole) return tid + r * SGW_BLOCK;
         if constexpr (D == 1) return o[0] + c0;
         else if constexpr (D == 2) return (o[0] + c0) + (o[1] + line) * g->stride[1];
-        else return core_global_index<D>(g, o, tid + r * SGW_BLOCK);
+        else return rt[line] + c0;
     };
 
     // ---- core box -> LDS
@@ -197,6 +244,32 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
 #pragma unroll
     for (int k = 0; k < D; k++) {
         if (!g->halo[k]) continue;
+        if constexpr (D >= 3) {
+            // rows of the slab from the tables: direction 1 slabs are 3 values at each core row,
+            // the others rows of t_1 values
+            const int sn = g->slab_n[k];
+            for (int e = tid; e < 2 * sn; e += SGW_BLOCK) {
+                const int side = e >= sn ? 1 : 0;
+                const int r = e - side * sn;
+                int gi, li;
+                if (k == 0) {
+                    const int ln = (int)((uint32_t)r / 3u);
+                    const int c = r - 3 * ln;
+                    int x = side ? o[0] + t0 + c : o[0] - 3 + c;
+                    x += (x < 0) ? g->n[0] : 0;
+                    x -= (x >= g->n[0]) ? g->n[0] : 0;
+                    gi = rt[ln] - o[0] + x;
+                    li = r;
+                } else {
+                    const int rho = (int)FDIV((uint32_t)r, g->fd_t[0]);
+                    const int c0 = r - M24(rho, t0);
+                    gi = rt[g->rt_off[k] + side * (sn / t0) + rho] + c0;
+                    li = c0 + M24(RS, rho);
+                }
+                su[(side ? g->slab_hi[k] : g->slab_lo[k]) + li] = in[gi];
+            }
+            continue;
+        }
         const int sn = g->slab_n[k];
         const int w0 = k == 0 ? 3 : RS;
         for (int e = tid; e < 2 * sn; e += SGW_BLOCK) {
@@ -428,7 +501,8 @@ size_t stage_lds_bytes(const GridDev& g, int precision)
     const size_t rs = precision == SGW_FP64 ? 8 : 4;
     int fmax_ = 0;
     for (int k = 0; k < g.d; k++) fmax_ = g.flux_total[k] > fmax_ ? g.flux_total[k] : fmax_;
-    return rs * (((size_t)g.pad_total + 1) / 2 * 2 + 2 * (((size_t)fmax_ + 1) / 2 * 2));
+    // staged values, two flux buffers, then (3D/4D) the row tables of 32-bit offsets
+    return rs * (((size_t)g.pad_total + 1) / 2 * 2 + 2 * (((size_t)fmax_ + 1) / 2 * 2)) + 4 * (size_t)g.rt_total;
 }
 
 int device_cus()

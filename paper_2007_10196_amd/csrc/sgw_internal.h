@@ -104,6 +104,8 @@ struct alignas(64) GridDev {
     int32_t sf_elems, rline;         // elements of one interface-flux buffer (two alternate in LDS);
                                      // SGW_BLOCK / t_0 when t_0 divides SGW_BLOCK, else 0
     int32_t nlines[SGW_MAX_DIM];     // lines of the box along direction k: core / t_k
+    int32_t rt_off[SGW_MAX_DIM];     // 3D/4D: offset of the slab-row table of direction k in the row tables
+    int32_t rt_total, pad2_;         // 3D/4D: ints of the row tables (core rows, then slab rows)
     int32_t nint[SGW_MAX_DIM];       // interior segments per line (window inside the core, no wrap)
     FastDiv fd_lines;
     FastDiv fd_lines_k[SGW_MAX_DIM];
