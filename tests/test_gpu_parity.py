@@ -183,6 +183,27 @@ def test_full_size_sampled(name, make):
     assert np.max(np.abs(ex - np.array(gd["fine_exact"]))) < 1e-13
 
 
+@pytest.mark.parametrize("name,make", [("c3", lambda: W.c3_advection_3d(precision=1)),
+                                       ("c4", lambda: W.c4_vlasov_4d(precision=1))])
+def test_full_size_fp32_against_fp64_oracle_samples(name, make):
+    """FP32 sweeps + FP64 combination at the full sizes: the sampled finest-grid values stay within
+    a stated bound of the FP64 oracle (the error is reported)."""
+    gd = _golden(name)
+    pb = make()
+    _announce(f"full {name} fp32")
+    s, st, U, t, steps = gpu_solve(pb)
+    J = np.array(gd["fine_J"])
+    N = pb.n_fine
+    flat = sum(J[:, k] * N ** k for k in range(pb.d))
+    ref = np.array(gd["fine_val"])
+    e = np.abs(U.cpu().numpy()[flat] - ref)
+    scale = max(1e-300, np.max(np.abs(ref)))
+    print(f"  {name} fp32 vs fp64 oracle on {len(ref)} samples: L1 {e.mean():.3e} Linf {e.max():.3e} "
+          f"(max |u| {scale:.3e})")
+    assert abs(steps - gd["steps"]) <= 1
+    assert e.max() <= 1e-4 * scale
+
+
 # --------------------------------------------------------------------------- batching and determinism
 
 def test_batched_results_equal_solo_results_bitwise():
