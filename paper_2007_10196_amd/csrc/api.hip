@@ -661,6 +661,7 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
             }
             load *= pd.c[k];
             pd.fd_c[k] = make_fastdiv((uint32_t)pd.c[k]);
+            pd.fd_n[k] = make_fastdiv((uint32_t)pd.n[k]);
         }
         pd.load_total = load;
         for (int k = 0; k < SGW_MAX_DIM; k++) {

@@ -95,8 +95,9 @@ __device__ __forceinline__ void prolong_tile(ProC pro, FineC F, double* __restri
                 const uint32_t q = FDIV(r, p->fd_c[k]);
                 const int c = (int)(r - q * (uint32_t)p->c[k]);
                 r = q;
-                int x = cl[k] + c + 2 * p->n[k]; // >= 0
-                x = x % p->n[k];
+                // periodic wrap: cl + c + 2n is >= 0, its remainder by n by the fast division
+                const uint32_t xw = (uint32_t)(cl[k] + c + 2 * p->n[k]);
+                const int x = (int)(xw - FDIV(xw, p->fd_n[k]) * (uint32_t)p->n[k]);
                 gi += x * p->stride[k];
             }
             bufA[e] = u[gi];

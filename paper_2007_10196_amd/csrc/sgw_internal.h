@@ -150,6 +150,7 @@ struct alignas(64) ProDev {
     int32_t c[SGW_MAX_DIM];          // coarse extent loaded per tile (T when m = 0)
     int32_t outer[SGW_MAX_DIM];      // prod_{j>k} c[j]
     FastDiv fd_c[SGW_MAX_DIM];
+    FastDiv fd_n[SGW_MAX_DIM];
 };
 
 struct alignas(64) FineDev {
