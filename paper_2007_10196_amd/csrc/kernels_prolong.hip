@@ -24,6 +24,7 @@ namespace {
 #define SGW_CONST __attribute__((address_space(4)))
 typedef const SGW_CONST ProDev* ProC;
 typedef const SGW_CONST FineDev* FineC;
+#define M24(a, b) __mul24((a), (b))
 
 __device__ __forceinline__ float rdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double rdiv(double a, double b) { return a / b; }
@@ -116,17 +117,19 @@ __device__ __forceinline__ void prolong_tile(ProC pro, FineC F, double* __restri
             const int R = 1 << m;
             const Real invR = Real(1) / Real(R);
             for (int o = tid; o < total; o += SGW_BLOCK) {
+                // LDS indices stay below 2^24: 24-bit multiplies and 32-bit offsets
                 const uint32_t r1 = FDIV((uint32_t)o, F->fd_inner[k]);
-                const int a = o - (int)r1 * inner;
+                const int a = o - M24((int)r1, inner);
                 const uint32_t bq = FDIV(r1, F->fd_T[k]);
-                const int jl = (int)r1 - (int)bq * Tk;
+                const int jl = (int)r1 - M24((int)bq, Tk);
                 const int J = J0[k] + jl;
                 const int i = (2 * J + R) >> (m + 1);
                 const Real s = (Real)(J - i * R) * invR;
                 const int li = i - cl[k];
-                const int base = a + inner * ((li - 2) + ck * (int)bq);
-                dst[o] = interp5<Real>(src[base], src[base + inner], src[base + 2 * inner], src[base + 3 * inner],
-                                       src[base + 4 * inner], s, eps, lagrange);
+                const uint32_t base = (uint32_t)(a + M24(inner, (li - 2) + M24(ck, (int)bq)));
+                const uint32_t st = (uint32_t)inner;
+                dst[o] = interp5<Real>(src[base], src[base + st], src[base + 2 * st], src[base + 3 * st],
+                                       src[base + 4 * st], s, eps, lagrange);
             }
             __syncthreads();
             Real* t = src;
