@@ -136,6 +136,7 @@ def test_c2_full_size(T):
     s, st32, U32, t32, steps32 = gpu_solve(pb.replace(precision=W.PREC_FP32))
     st_o, U_o, stats = oracle_solve(pb.replace(precision=W.PREC_FP64))
     e = np.abs(U32.cpu().numpy() - U_o)
+    print(f"  c2 T={T:.4f}: fp32 L1 {e.mean():.3e} Linf {e.max():.3e} against the fp64 oracle")
     assert e.mean() < 2e-6 and e.max() < 2e-5, (e.mean(), e.max())
 
 
