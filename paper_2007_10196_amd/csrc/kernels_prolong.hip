@@ -27,7 +27,14 @@ typedef const SGW_CONST FineDev* FineC;
 #define M24(a, b) __mul24((a), (b))
 
 __device__ __forceinline__ float rdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ double rdiv(double a, double b) { return a / b; }
+// a / b for b > 0: hardware reciprocal, one Newton step, one residual correction
+__device__ __forceinline__ double rdiv(double a, double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(fma(-b, r, 1.0), r, r);
+    const double q = a * r;
+    return fma(fma(-b, q, a), r, q);
+}
 
 // P_r written about x_i: P_r(s) = c + s g_r + s^2 k_r with g_r, k_r the first and
 // second differences of substencil r; the integral of eq. (si) then equals

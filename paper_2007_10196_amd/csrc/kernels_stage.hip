@@ -25,9 +25,17 @@ typedef const SGW_CONST GridDev* GridC;
 // LDS indices stay below 2^16: the full-rate 24-bit multiply is exact for them
 #define M24(a, b) __mul24((a), (b))
 
-// c + num / den: one reciprocal and an fma in FP32, a division in FP64
+// c + num / den: one reciprocal and an fma in FP32; in FP64 the hardware
+// reciprocal, one Newton step and a residual correction of the quotient (den > 0)
 __device__ __forceinline__ float wsum(float c, float num, float den) { return fmaf(num, __builtin_amdgcn_rcpf(den), c); }
-__device__ __forceinline__ double wsum(double c, double num, double den) { return c + num / den; }
+__device__ __forceinline__ double wsum(double c, double num, double den)
+{
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(fma(-den, r, 1.0), r, r);
+    double q = num * r;
+    q = fma(fma(-den, q, num), r, q);
+    return c + q;
+}
 
 // WENO5 flux (eqs. 2.7, 2.7.1, 2.6, 2.7.2) of the positive-wind big stencil
 // (a..e) = (f_{i-2} .. f_{i+2}), written in differences so that neighbouring
