@@ -216,6 +216,23 @@ uint64_t sgw_norms_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n);
  * SGW_ERR_NONFINITE if a wave speed or dt became NaN/Inf. */
 sgw_status sgw_query(sgw_solver_t* solver, double* t, int64_t* steps);
 
+/* Alg. Step 1 with values the caller samples itself (Sec. 2.2.2): copies the
+ * nodes of grid g (solver precision, row-major with direction 1 fastest, the
+ * shape sgw_plan_grid reports) from src_dev (device) into u^n, recomputes that
+ * grid's wave speed and rewinds the solve to t = 0.  Call it for every grid
+ * before sgw_advance; a grid not set keeps its previous values.  Stream-ordered;
+ * refused while the solver is in a batch. */
+sgw_status sgw_set_grid(sgw_solver_t* solver, int32_t g, const void* src_dev);
+
+/* Checkpoint of a running solve: u^n of every grid, the wave-speed slots and the
+ * time record (t, steps, last dt, flags), sgw_snapshot_bytes(solver) bytes of
+ * device memory, written or read in stream order.  sgw_restore resumes a solver
+ * of the same plan from it (the final time stays the solver's own); refused
+ * while the solver is in a batch. */
+uint64_t sgw_snapshot_bytes(const sgw_solver_t* solver);
+sgw_status sgw_snapshot(sgw_solver_t* solver, void* dst_dev);
+sgw_status sgw_restore(sgw_solver_t* solver, const void* src_dev);
+
 /* ---------------------------------------------------------------- batches
  * A batch advances the component grids of many solvers together: one fused
  * stage launch per RK stage over the grids of every active solver, each solver

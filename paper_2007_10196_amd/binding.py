@@ -66,6 +66,10 @@ _SIGS = {
     "sgw_exact": (C.c_int32, [C.c_void_p, C.c_double, C.c_void_p]),
     "sgw_norms": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "sgw_query": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "sgw_set_grid": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "sgw_snapshot_bytes": (C.c_uint64, [C.c_void_p]),
+    "sgw_snapshot": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "sgw_restore": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "sgw_norms_async": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sgw_prolongate_combine_many": (C.c_int32, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32,
                                                 C.c_void_p, C.c_uint64, C.c_void_p]),

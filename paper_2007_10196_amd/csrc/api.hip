@@ -771,6 +771,64 @@ extern "C" sgw_status sgw_restrict_initial(sgw_solver_t* s)
     return SGW_OK;
 }
 
+extern "C" sgw_status sgw_set_grid(sgw_solver_t* s, int32_t g, const void* src_dev)
+{
+    if (!s || !src_dev) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    const sgw_plan* p = s->plan;
+    if (g < 0 || g >= p->G) return sgw_fail(SGW_ERR_INVALID_ARG, "grid %d outside 0..%d", g, p->G - 1);
+    if (s->batch_slot >= 0) return sgw_fail(SGW_ERR_STATE, "solver is in a batch");
+    const GridDev& gd = s->grids_h[g];
+    int64_t n = 1;
+    for (int k = 0; k < gd.d; k++) n *= gd.n[k];
+    const size_t rs = p->cfg.precision == SGW_FP64 ? 8 : 4;
+    HIPCHK(hipMemcpyAsync(gd.u, src_dev, (size_t)n * rs, hipMemcpyDeviceToDevice, s->stream), "copy grid values");
+    HIPCHK(launch_fill_u64(s->alpha_d + 4 * g, 4, 0ull, s->stream), "clear wave speeds");
+    if (gd.dyn_alpha) HIPCHK(launch_grid_absmax(s->grids_d + g, n, p->cfg.precision, s->stream), "wave speed");
+    HIPCHK(launch_req_reset(s->req_d, s->stream), "reset time");
+    s->restricted = true;
+    s->t_host = 0.0;
+    return SGW_OK;
+}
+
+static uint64_t snap_alpha_off(const sgw_plan* p) { return align256(p->copy_bytes); }
+static uint64_t snap_req_off(const sgw_plan* p) { return snap_alpha_off(p) + align256(sizeof(unsigned long long) * 4 * p->G); }
+
+extern "C" uint64_t sgw_snapshot_bytes(const sgw_solver_t* s)
+{
+    if (!s) return 0;
+    return snap_req_off(s->plan) + align256(sizeof(ReqDev));
+}
+
+extern "C" sgw_status sgw_snapshot(sgw_solver_t* s, void* dst_dev)
+{
+    if (!s || !dst_dev) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    if (!s->restricted) return sgw_fail(SGW_ERR_STATE, "snapshot before restrict");
+    const sgw_plan* p = s->plan;
+    unsigned char* d = (unsigned char*)dst_dev;
+    HIPCHK(hipMemcpyAsync(d, s->state, p->copy_bytes, hipMemcpyDeviceToDevice, s->stream), "snapshot state");
+    HIPCHK(hipMemcpyAsync(d + snap_alpha_off(p), s->alpha_d, sizeof(unsigned long long) * 4 * p->G,
+                          hipMemcpyDeviceToDevice, s->stream),
+           "snapshot wave speeds");
+    HIPCHK(hipMemcpyAsync(d + snap_req_off(p), s->req_d, sizeof(ReqDev), hipMemcpyDeviceToDevice, s->stream),
+           "snapshot time");
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_restore(sgw_solver_t* s, const void* src_dev)
+{
+    if (!s || !src_dev) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    if (s->batch_slot >= 0) return sgw_fail(SGW_ERR_STATE, "solver is in a batch");
+    const sgw_plan* p = s->plan;
+    const unsigned char* d = (const unsigned char*)src_dev;
+    HIPCHK(hipMemcpyAsync(s->state, d, p->copy_bytes, hipMemcpyDeviceToDevice, s->stream), "restore state");
+    HIPCHK(hipMemcpyAsync(s->alpha_d, d + snap_alpha_off(p), sizeof(unsigned long long) * 4 * p->G,
+                          hipMemcpyDeviceToDevice, s->stream),
+           "restore wave speeds");
+    HIPCHK(launch_req_restore(s->req_d, (const ReqDev*)(d + snap_req_off(p)), s->stream), "restore time");
+    s->restricted = true;
+    return SGW_OK;
+}
+
 static sgw_status read_req(sgw_solver* s)
 {
     HIPCHK(hipMemcpyAsync(s->req_pinned, s->req_d, sizeof(ReqDev), hipMemcpyDeviceToHost, s->stream), "read time");

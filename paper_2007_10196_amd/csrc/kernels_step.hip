@@ -217,6 +217,30 @@ __global__ void gather_done_kernel(ReqDev* const* reqs, int nreq, int* flags)
 }
 
 
+// Largest |u| over one grid into its wave-speed slot 0 (caller-set initial data).
+template <typename Real>
+__global__ void grid_absmax_kernel(GridDev* g)
+{
+    __shared__ double red[SGW_BLOCK / 64];
+    int64_t total = 1;
+    for (int k = 0; k < g->d; k++) total *= g->n[k];
+    const Real* u = (const Real*)g->u;
+    double amax = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)SGW_BLOCK + threadIdx.x; i < total; i += (int64_t)gridDim.x * SGW_BLOCK)
+        amax = nanmax(amax, fabs((double)u[i]));
+    block_atomic_max(amax, g->alpha + 0, red);
+}
+
+// The time fields of a snapshot record (t, steps, dt, completion flags) into a solve's record.
+__global__ void req_restore_kernel(ReqDev* dst, const ReqDev* src)
+{
+    dst->t = src->t;
+    dst->steps = src->steps;
+    dst->dt = src->dt;
+    dst->done = src->done;
+    dst->nonfinite = src->nonfinite;
+}
+
 } // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -315,5 +339,23 @@ hipError_t launch_gather_done(ReqDev* const* reqs, int nreq, int* flags, hipStre
 {
     if (nreq <= 0) return hipSuccess;
     hipLaunchKernelGGL(gather_done_kernel, dim3((nreq + 63) / 64), dim3(64), 0, s, reqs, nreq, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_absmax(GridDev* g_dev, int64_t n, int precision, hipStream_t s)
+{
+    int blocks = (int)((n + SGW_BLOCK - 1) / SGW_BLOCK);
+    if (blocks > 256) blocks = 256;
+    if (blocks < 1) blocks = 1;
+    if (precision == SGW_FP64)
+        hipLaunchKernelGGL(grid_absmax_kernel<double>, dim3(blocks), dim3(SGW_BLOCK), 0, s, g_dev);
+    else
+        hipLaunchKernelGGL(grid_absmax_kernel<float>, dim3(blocks), dim3(SGW_BLOCK), 0, s, g_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_req_restore(ReqDev* dst, const ReqDev* src, hipStream_t s)
+{
+    hipLaunchKernelGGL(req_restore_kernel, dim3(1), dim3(1), 0, s, dst, src);
     return hipGetLastError();
 }

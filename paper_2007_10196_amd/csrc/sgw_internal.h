@@ -215,6 +215,8 @@ hipError_t launch_restrict(const GridDev* grids_dev, const GridDev* grids_host, 
                            const sgw_problem* pb, hipStream_t s);
 hipError_t launch_req_reset(ReqDev* r, hipStream_t s);
 hipError_t launch_req_set_final(ReqDev* r, double T, hipStream_t s);
+hipError_t launch_grid_absmax(GridDev* g_dev, int64_t n, int precision, hipStream_t s);
+hipError_t launch_req_restore(ReqDev* dst, const ReqDev* src, hipStream_t s);
 hipError_t launch_req_set_final_many(ReqDev* const* reqs, const double* tf, int n, hipStream_t s);
 hipError_t launch_restrict_many(const ResetItem* resets, int nresets, const RestrictItem* items, int nitems,
                                 int precision, hipStream_t s);

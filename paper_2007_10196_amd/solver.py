@@ -125,6 +125,31 @@ class Solver:
         B.check(B.lib().sgw_norms_async(self.handle, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
                                         C.c_void_p(result.data_ptr())))
 
+    def set_grid(self, g: int, values: torch.Tensor):
+        """Initial values of grid g sampled by the caller (solver precision, plan shape)."""
+        info = self.plan.grids[g]
+        n = 1
+        for x in info["shape"]:
+            n *= x
+        assert values.dtype == self.real and values.is_cuda and values.is_contiguous() and values.numel() == n
+        B.check(B.lib().sgw_set_grid(self.handle, int(g), C.c_void_p(values.data_ptr())))
+        return self
+
+    def snapshot(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Checkpoint (device bytes) of u^n, wave speeds and time record."""
+        nbytes = int(B.lib().sgw_snapshot_bytes(self.handle))
+        if out is None:
+            out = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        assert out.dtype == torch.uint8 and out.numel() >= nbytes and out.is_contiguous()
+        B.check(B.lib().sgw_snapshot(self.handle, C.c_void_p(out.data_ptr())))
+        return out
+
+    def restore(self, snap: torch.Tensor):
+        """Resume from a snapshot of a solver with the same plan."""
+        assert snap.dtype == torch.uint8 and snap.numel() >= int(B.lib().sgw_snapshot_bytes(self.handle))
+        B.check(B.lib().sgw_restore(self.handle, C.c_void_p(snap.data_ptr())))
+        return self
+
     def query(self) -> Tuple[float, int]:
         t, n = C.c_double(), C.c_int64()
         B.check(B.lib().sgw_query(self.handle, C.byref(t), C.byref(n)))

@@ -405,3 +405,38 @@ def test_launch_shape_does_not_change_results(prec):
             if not torch.equal(a, b):
                 bad.append((j, probs[i].name, probs[i].nl, float((a - b).abs().max()), int((a != b).sum())))
     assert not bad, bad
+
+
+def test_set_grid_equals_restriction_bitwise():
+    """Caller-sampled initial values through sgw_set_grid give the same solve as sgw_restrict_initial."""
+    torch, B, Solver, _ = _lib()
+    for pb in (W.c2_burgers_2d(nl=3, T=0.05, precision=W.PREC_FP64), W.c4_vlasov_4d(nl=2, T=0.1)):
+        _announce(f"set_grid {pb.name}")
+        a = Solver(pb).restrict()
+        b = Solver(pb)
+        init = a.state_copy(0).clone()
+        for g, info in enumerate(b.plan.grids):
+            n = int(np.prod(info["shape"]))
+            b.set_grid(g, init[info["offset"]: info["offset"] + n].clone())
+        a.advance()
+        b.advance()
+        assert a.query() == b.query()
+        assert torch.equal(a.prolongate_combine(), b.prolongate_combine())
+
+
+def test_snapshot_restore_resumes_bitwise():
+    """A solve stopped at T/2 and checkpointed, then resumed in another solver, ends bitwise where the
+    original solver ends when it simply continues (stopping at T/2 itself adds a clipped step)."""
+    torch, B, Solver, _ = _lib()
+    for pb in (W.c2_burgers_2d(nl=3, T=0.1, precision=W.PREC_FP32), W.c3_advection_3d(nl=2, T=0.2)):
+        _announce(f"snapshot {pb.name}")
+        a = Solver(pb).restrict().advance(t_final=pb.T / 2)
+        snap = a.snapshot()
+        t_half, steps_half = a.query()
+        a.advance()
+        b = Solver(pb).restore(snap)
+        assert b.query() == (t_half, steps_half)
+        b.advance()
+        assert a.query() == b.query()
+        assert a.query()[0] == pb.T
+        assert torch.equal(a.prolongate_combine(), b.prolongate_combine())
