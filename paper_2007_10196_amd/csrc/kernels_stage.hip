@@ -140,8 +140,7 @@ __device__ __forceinline__ int core_global_index(GridC g, const int* o, int e)
 }
 
 template <typename Real, int D>
-__device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su, Real* sf,
-                                          double* red)
+__device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su, Real* sf)
 {
     const int tid = threadIdx.x;
     const double dt = ((const SGW_CONST ReqDev*)g->req)->dt;
@@ -461,7 +460,11 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
             amax = (ar > amax || ar != ar) ? ar : amax;
         }
     }
-    if (g->dyn_alpha) block_atomic_max((double)amax, g->alpha + (stage + 1) % 3, red);
+    // one atomic max per wavefront on the bit pattern (order-free, no barrier)
+    if (g->dyn_alpha) {
+        const double m = wave_max((double)amax);
+        if ((tid & 63) == 0) atomicMax(g->alpha + (stage + 1) % 3, (unsigned long long)__double_as_longlong(m));
+    }
 }
 
 template <typename Real>
@@ -471,7 +474,6 @@ __global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __rest
     // a batch keeps its box count in device memory so a captured graph stays valid as solves come and go
     if (nitems_dev) nitems = *nitems_dev;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[SGW_BLOCK / 64];
     // XCD-aware order: consecutive workgroup ids land on different XCDs, so hand
     // each XCD a contiguous run of boxes (neighbouring boxes share halo lines in L2).
     // Each workgroup takes a contiguous range of floor or ceil(nitems / nb) boxes,
@@ -491,10 +493,10 @@ __global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __rest
         Real* su = (Real*)smem;
         Real* sf = su + ((su_elems + 1) & ~(size_t)1);
         switch (g->d) {
-        case 1: stage_box<Real, 1>(g, ibox, stage, su, sf, red); break;
-        case 2: stage_box<Real, 2>(g, ibox, stage, su, sf, red); break;
-        case 3: stage_box<Real, 3>(g, ibox, stage, su, sf, red); break;
-        default: stage_box<Real, 4>(g, ibox, stage, su, sf, red); break;
+        case 1: stage_box<Real, 1>(g, ibox, stage, su, sf); break;
+        case 2: stage_box<Real, 2>(g, ibox, stage, su, sf); break;
+        case 3: stage_box<Real, 3>(g, ibox, stage, su, sf); break;
+        default: stage_box<Real, 4>(g, ibox, stage, su, sf); break;
         }
         __syncthreads();
     }
