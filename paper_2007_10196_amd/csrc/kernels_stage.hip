@@ -82,45 +82,56 @@ template <typename Real, int NI>
 __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real cp, Real cm, Real alpha, Real epsT,
                                               int linear, Real* F)
 {
+    // the flux type and the wind sides are uniform: branch once per window, not per value
     Real pv[NI + 5], mv[NI + 5];
-    const Real ha = Real(0.5) * alpha;
+    if (burgers) {
+        const Real ha = Real(0.5) * alpha;
 #pragma unroll
-    for (int q = 0; q < NI + 5; q++) {
-        if (burgers) {
+        for (int q = 0; q < NI + 5; q++) {
             // f^+- = (u^2/2 +- alpha u)/2
             const Real f4 = (Real(0.25) * v[q]) * v[q];
             pv[q] = fma(ha, v[q], f4);
             mv[q] = fma(-ha, v[q], f4);
-        } else {
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NI + 5; q++) {
             pv[q] = cp * v[q];
             mv[q] = cm * v[q];
         }
     }
-    const bool use_p = burgers || cp != Real(0);
-    const bool use_m = burgers || cm != Real(0);
-    Real dp[NI + 4], dm[NI + 4], tp[NI + 4], tm[NI + 4];
+    if (burgers || cp != Real(0)) {
+        Real dp[NI + 4], tp[NI + 4];
 #pragma unroll
-    for (int q = 0; q < NI + 4; q++) {
-        dp[q] = pv[q + 1] - pv[q];
-        dm[q] = mv[q + 1] - mv[q];
+        for (int q = 0; q < NI + 4; q++) dp[q] = pv[q + 1] - pv[q];
+        tp[0] = Real(0);
+#pragma unroll
+        for (int q = 1; q < NI + 4; q++) {
+            const Real sp = dp[q] - dp[q - 1];
+            tp[q] = fma(sp, sp, epsT);
+        }
+#pragma unroll
+        for (int s = 0; s < NI; s++)
+            F[s] = weno5s<Real>(pv[s + 2], dp[s], dp[s + 1], dp[s + 2], dp[s + 3], tp[s + 1], tp[s + 2], tp[s + 3],
+                                linear);
+    } else {
+#pragma unroll
+        for (int s = 0; s < NI; s++) F[s] = Real(0);
     }
-    tp[0] = tm[0] = Real(0);
+    if (burgers || cm != Real(0)) {
+        Real dm[NI + 4], tm[NI + 4];
 #pragma unroll
-    for (int q = 1; q < NI + 4; q++) {
-        const Real sp = dp[q] - dp[q - 1], sm = dm[q] - dm[q - 1];
-        tp[q] = fma(sp, sp, epsT);
-        tm[q] = fma(sm, sm, epsT);
-    }
+        for (int q = 0; q < NI + 4; q++) dm[q] = mv[q + 1] - mv[q];
+        tm[0] = Real(0);
 #pragma unroll
-    for (int s = 0; s < NI; s++) {
-        Real f = Real(0);
-        if (use_p)
-            f = weno5s<Real>(pv[s + 2], dp[s], dp[s + 1], dp[s + 2], dp[s + 3], tp[s + 1], tp[s + 2], tp[s + 3],
-                             linear);
-        if (use_m)
-            f += weno5s<Real>(mv[s + 3], -dm[s + 4], -dm[s + 3], -dm[s + 2], -dm[s + 1], tm[s + 4], tm[s + 3],
-                              tm[s + 2], linear);
-        F[s] = f;
+        for (int q = 1; q < NI + 4; q++) {
+            const Real sm = dm[q] - dm[q - 1];
+            tm[q] = fma(sm, sm, epsT);
+        }
+#pragma unroll
+        for (int s = 0; s < NI; s++)
+            F[s] += weno5s<Real>(mv[s + 3], -dm[s + 4], -dm[s + 3], -dm[s + 2], -dm[s + 1], tm[s + 4], tm[s + 3],
+                                 tm[s + 2], linear);
     }
 }
 
