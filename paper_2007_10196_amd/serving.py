@@ -32,6 +32,7 @@ class Result:
     steps: int
     cell_updates: int
     out: Optional[torch.Tensor]
+    kind: str = ""                 # "<dimension>D N_L=<finest level>"
 
     @property
     def latency_s(self) -> float:
@@ -103,7 +104,8 @@ class ServingLoop:
                     results.append(Result(rid=req.rid, arrival_s=req.arrival_s, admit_s=admit_s,
                                           finish_s=clock() - t0, steps=steps,
                                           cell_updates=steps * solver.plan.total_nodes,
-                                          out=U if self.keep_outputs else None))
+                                          out=U if self.keep_outputs else None,
+                                          kind=f"{req.problem.d}D N_L={req.problem.nl}"))
                     used -= fp
                     plans.pop(req.rid, None)
                     # its combination is done (event above); freeing synchronises the solver's
@@ -153,7 +155,13 @@ def latency_summary(results: List[Result]) -> dict:
     lat = np.array([r.latency_s for r in results]) * 1e3
     span = max(r.finish_s for r in results) - min(r.arrival_s for r in results)
     cells = sum(r.cell_updates for r in results)
+    by_kind = {}
+    for kind in sorted({r.kind for r in results}):
+        lk = np.array([r.latency_s for r in results if r.kind == kind]) * 1e3
+        by_kind[kind] = {"requests": int(lk.size), "p50_ms": float(np.percentile(lk, 50)),
+                         "p99_ms": float(np.percentile(lk, 99))}
     return {"requests": len(results), "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
             "max_ms": float(lat.max()),
-            "throughput_cell_updates_per_s": cells / span if span > 0 else None, "span_s": span}
+            "throughput_cell_updates_per_s": cells / span if span > 0 else None, "span_s": span,
+            "by_kind": by_kind}
