@@ -108,3 +108,50 @@ def test_footprints_scale_with_precision():
     assert p64.total_nodes == p32.total_nodes == 507904
     assert p64.state_bytes >= 2 * p32.state_bytes - 1024
     assert p64.fine_bytes == 8 * 256 ** 3
+
+
+def _coarse_extent(pb, level, T):
+    """Coarse values a tile row of extent T needs per direction: T without refinement, else the
+    (T-1)/R + 1 intervals it spans plus the 5-point stencil (Sec. 2.2.1)."""
+    out = []
+    for k in range(pb.d):
+        m = pb.nl - level[k]
+        out.append(T[k] if m == 0 else (T[k] - 1) // (1 << m) + 6)
+    return out
+
+
+@pytest.mark.parametrize("make", [lambda: W.c1_advection_2d(), lambda: W.c2_burgers_2d(),
+                                  lambda: W.c3_advection_3d(), lambda: W.c3_advection_3d(precision=1),
+                                  lambda: W.c4_vlasov_4d(), lambda: W.c4_vlasov_4d(precision=0),
+                                  lambda: W.c2_burgers_2d(nr=10, nl=3)])
+def test_prolongation_tile_fits_and_divides(make):
+    """The searched finest-grid tile divides N in every direction, holds at most 16 nodes per thread,
+    and its two LDS buffers (largest coarse block or pass output) stay within 64 KB."""
+    pb = make()
+    plan = Plan(pb)
+    T = plan.fine_tile
+    N = pb.n_fine
+    assert len(T) == pb.d and all(N % t == 0 for t in T)
+    assert int(np.prod(T)) <= 256 * 16
+    esz = 8 if pb.precision == W.PREC_FP64 else 4
+    biggest = 0
+    for info in plan.grids:
+        c = _coarse_extent(pb, info["level"], T)
+        biggest = max(biggest, int(np.prod(c)))
+        for k in range(pb.d):
+            biggest = max(biggest, int(np.prod([T[j] if j <= k else c[j] for j in range(pb.d)])))
+    assert 2 * esz * biggest <= 64 * 1024
+
+
+def test_prolongation_tile_prefers_late_directions():
+    """Directions are refined in increasing order, so halo work of early passes is multiplied by the
+    coarse extents of the later directions: the search makes the last extent at least the first."""
+    for pb in (W.c3_advection_3d(precision=1), W.c4_vlasov_4d()):
+        T = Plan(pb).fine_tile
+        assert T[-1] >= T[0], T
+
+
+def test_blocks_per_cu_is_validated():
+    _expect_status(W.c1_advection_2d(), -1, blocks_per_cu=65)
+    _expect_status(W.c1_advection_2d(), -1, blocks_per_cu=-1)
+    Plan(W.c1_advection_2d(), blocks_per_cu=6)  # accepted
