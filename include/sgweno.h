@@ -8,8 +8,10 @@
  *   Step 1  restrict the initial condition to the component grids   -> sgw_restrict_initial
  *   Step 2  march every component grid to T with WENO5 + TVD-RK3     -> sgw_advance
  *   Step 3  prolongate every grid to the finest grid and combine    -> sgw_prolongate_combine
- * plus the error norms of Sec. 3 (sgw_exact, sgw_norms) and a batched
- * runtime that advances many solves together (sgw_batch_*).
+ * plus the error norms of Sec. 3 (sgw_exact, sgw_norms), one-launch forms of
+ * these steps over many solves (*_many), checkpoints (sgw_snapshot,
+ * sgw_restore) and a batched runtime that advances many solves together
+ * (sgw_batch_*).
  *
  * Conventions
  *   - Every call returns sgw_status: SGW_OK (0) or a negative error code; the
@@ -96,8 +98,8 @@ typedef struct sgw_config {
     int32_t box[SGW_MAX_DIM];      /* 0: automatic; else the stage-kernel box extent per direction
                                       (must divide every grid's extent in that direction)         */
     int32_t fine_tile[SGW_MAX_DIM];/* 0: automatic; else the prolongation tile per direction       */
-    int32_t box_target;            /* 0: automatic; else the largest box (nodes) the automatic
-                                      box search may pick, 256..2048                               */
+    int32_t box_target;            /* 0: automatic (1024); else the largest box (nodes) the
+                                      automatic box search may pick, 64..2048                      */
     int32_t blocks_per_cu;         /* 0: as many resident stage workgroups per compute unit as
                                       fit; else at most this many (1..64), a tuning knob         */
 } sgw_config;
@@ -113,8 +115,11 @@ typedef struct sgw_batch sgw_batch_t;
  * (l_1..l_dim), with combination coefficient (-1)^q C(dim-1, q).  Grid l has
  * N_r 2^{l_k} nodes in direction k.  Errors: SGW_ERR_INVALID_ARG for dim
  * outside 1..4, N_r < 4, N_L outside 0..12, cfl outside (0, 1.5], eps <= 0,
- * a Vlasov flux with odd dim, or a finest grid with more than 2^40 nodes;
- * SGW_ERR_UNSUPPORTED for a box or tile that does not divide the extents. */
+ * a Vlasov flux with odd dim, a finest grid with more than 2^40 nodes, box_target
+ * outside 64..2048 or blocks_per_cu outside 0..64; SGW_ERR_UNSUPPORTED for a box
+ * or tile that does not divide the extents or does not fit one workgroup.  With
+ * fine_tile 0 the prolongation tile is searched over divisors of the finest
+ * extent (interpolations, staging, writes and LDS occupancy weighed). */
 sgw_status sgw_plan_create(const sgw_problem* problem, const sgw_config* config, sgw_plan_t** out);
 void sgw_plan_free(sgw_plan_t* plan);
 

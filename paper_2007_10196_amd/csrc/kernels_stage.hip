@@ -135,21 +135,6 @@ __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real 
     }
 }
 
-// Global index of core node e (logical row-major index inside the box).
-template <int D>
-__device__ __forceinline__ int core_global_index(GridC g, const int* o, int e)
-{
-    uint32_t r = (uint32_t)e;
-    int gi = 0;
-#pragma unroll
-    for (int k = 0; k < D; k++) {
-        const uint32_t q = FDIV(r, g->fd_t[k]);
-        gi += (o[k] + (int)(r - q * (uint32_t)g->t[k])) * g->stride[k];
-        r = q;
-    }
-    return gi;
-}
-
 template <typename Real, int D>
 __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su, Real* sf)
 {
