@@ -514,6 +514,8 @@ int orc_evolve(const orc_problem *p, const orc_config *c, double T, double *stat
         if (hfin[k] < hmin) hmin = hfin[k];
     }
 #ifdef _OPENMP
+    /* the thread count applies to this call only */
+    const int prev_threads = omp_get_max_threads();
     if (c->nthreads > 0) omp_set_num_threads(c->nthreads);
 #endif
     double t = 0.0;
@@ -564,6 +566,9 @@ int orc_evolve(const orc_problem *p, const orc_config *c, double T, double *stat
         st->max_dt = maxdt;
     }
     orc_set_free(&s);
+#ifdef _OPENMP
+    omp_set_num_threads(prev_threads);
+#endif
     return 0;
 }
 
