@@ -130,7 +130,8 @@ static void fill_box_geometry(GridDev& g, int precision)
     for (int k = 0; k < SGW_MAX_DIM; k++) {
         g.I[k] = g.t[k] + (g.halo[k] ? 1 : 0);
         g.flux_total[k] = (k < g.d) ? core / g.t[k] * g.I[k] : 0;
-        g.nseg[k] = (g.I[k] + SGW_SEG - 1) / SGW_SEG;
+        const int SEG = sgw_seg(g.d);
+        g.nseg[k] = (g.I[k] + SEG - 1) / SEG;
         g.seg_total[k] = (k < g.d) ? core / g.t[k] * g.nseg[k] : 0;
         g.fd_nseg[k] = make_fastdiv((uint32_t)g.nseg[k]);
         // segment s reads window positions s*SEG - hf - 2 .. s*SEG - hf + SEG + 2: interior (no
@@ -139,8 +140,8 @@ static void fill_box_geometry(GridDev& g, int precision)
         g.fd_lines_k[k] = make_fastdiv((uint32_t)g.nlines[k]);
         {
             const int hf = g.halo[k] ? 1 : 0;
-            const int top = g.t[k] - 3 - SGW_SEG + hf;
-            g.nint[k] = (k < g.d && top >= SGW_SEG) ? top / SGW_SEG : 0;
+            const int top = g.t[k] - 3 - SEG + hf;
+            g.nint[k] = (k < g.d && top >= SEG) ? top / SEG : 0;
         }
         if (k == 0) {
             g.F0S = g.RS;
@@ -727,7 +728,7 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
         sgw_solver_free(s);
         return rc;
     }
-    s->grid = stage_grid(p->cfg.precision, p->stage_lds, p->cfg.blocks_per_cu);
+    s->grid = stage_grid(p->cfg.precision, p->pb.dim, p->stage_lds, p->cfg.blocks_per_cu);
     *out = s;
     return SGW_OK;
 }

@@ -1,9 +1,10 @@
 // Batched runtime of libsgweno: many solves (any dimension, level and final
 // time, one precision) advance together.  Each time step is one captured HIP
 // graph: the time-step kernel for every slot, then the three TVD-RK3 stages,
-// each a single persistent launch over the boxes of every admitted solve.  The
-// box list and its length live in device memory, so admitting or releasing a
-// solve is a stream-ordered copy and the graph stays valid.
+// each one persistent launch per dimension present over the boxes of every
+// admitted solve of that dimension.  The box list, grouped by dimension, and
+// each dimension's range of it live in device memory, so admitting or releasing
+// a solve is a stream-ordered copy and the graph stays valid.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -19,8 +20,8 @@ struct sgw_batch {
     uint64_t scratch_bytes = 0;
     int64_t max_items = 0;
     ReqDev** reqs_d = nullptr;      // [max_solvers], null for a free slot
-    WorkItem* items_d = nullptr;    // [max_items]
-    int* nitems_d = nullptr;
+    WorkItem* items_d = nullptr;    // [max_items], grouped by dimension
+    int* ranges_d = nullptr;        // [8]: (offset, count) in items_d of the boxes of dimension 1..4
     int* flags_d = nullptr;         // [max_solvers]
     double* tf_d = nullptr;         // [max_solvers] final times of new slots (NaN: unchanged)
     int* flags_pinned = nullptr;
@@ -32,9 +33,10 @@ struct sgw_batch {
     bool queued = false;            // step launches may still be in flight on the stream
     std::vector<WorkItem> items_h;
     int nitems_h = 0;
+    int ranges_h[8] = {};
     bool dirty = true;
-    size_t lds = 0;                 // LDS of the captured stage launches
-    int blocks = 0;
+    size_t lds[4] = {};             // LDS of the captured stage launch of each dimension (0: not captured)
+    int blocks[4] = {};
     int blocks_per_cu = 0;          // cap on resident stage workgroups per CU (0: occupancy)
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -73,7 +75,7 @@ extern "C" sgw_status sgw_batch_create(int32_t max_solvers, int32_t precision, u
     uint64_t off = 0;
     b->reqs_d = (ReqDev**)(b->scratch + off);
     off += a256(sizeof(ReqDev*) * (uint64_t)max_solvers);
-    b->nitems_d = (int*)(b->scratch + off);
+    b->ranges_d = (int*)(b->scratch + off);
     off += 256;
     b->flags_d = (int*)(b->scratch + off);
     off += a256(sizeof(int) * (uint64_t)max_solvers);
@@ -120,26 +122,33 @@ static uint64_t solver_bytes(const sgw_solver* s)
 }
 
 // Re-upload the box list and the slot table; recapture the step graph only when
-// an admitted grid needs more LDS than the captured launches provide.
+// a solve of a dimension not yet captured arrives, or an admitted grid needs more
+// LDS than the captured launch of its dimension provides.  Captured dimensions
+// stay in the graph (an empty range costs one launch whose workgroups exit).
 static sgw_status batch_sync(sgw_batch* b)
 {
     if (!b->dirty) return SGW_OK;
     b->items_h.clear();
-    size_t lds = 0;
-    for (int i = 0; i < b->max_solvers; i++) {
-        sgw_solver* s = b->slots[i];
-        if (!s) continue;
-        b->items_h.insert(b->items_h.end(), s->items_h.begin(), s->items_h.end());
-        lds = s->plan->stage_lds > lds ? s->plan->stage_lds : lds;
+    size_t lds[4] = {};
+    for (int d = 1; d <= 4; d++) {
+        b->ranges_h[2 * (d - 1)] = (int)b->items_h.size();
+        for (int i = 0; i < b->max_solvers; i++) {
+            sgw_solver* s = b->slots[i];
+            if (!s || s->plan->pb.dim != d) continue;
+            if ((int64_t)(b->items_h.size() + s->items_h.size()) > b->max_items)
+                return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "batch box list full");
+            b->items_h.insert(b->items_h.end(), s->items_h.begin(), s->items_h.end());
+            lds[d - 1] = s->plan->stage_lds > lds[d - 1] ? s->plan->stage_lds : lds[d - 1];
+        }
+        b->ranges_h[2 * (d - 1) + 1] = (int)b->items_h.size() - b->ranges_h[2 * (d - 1)];
     }
-    if ((int64_t)b->items_h.size() > b->max_items) return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "batch box list full");
     b->nitems_h = (int)b->items_h.size();
     hipError_t e = hipSuccess;
     if (b->nitems_h)
         e = hipMemcpyAsync(b->items_d, b->items_h.data(), sizeof(WorkItem) * b->items_h.size(), hipMemcpyHostToDevice,
                            b->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b->nitems_d, &b->nitems_h, sizeof(int), hipMemcpyHostToDevice, b->stream);
+        e = hipMemcpyAsync(b->ranges_d, b->ranges_h, sizeof(b->ranges_h), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->reqs_d, b->reqs_h.data(), sizeof(ReqDev*) * b->max_solvers, hipMemcpyHostToDevice,
                            b->stream);
@@ -155,17 +164,24 @@ static sgw_status batch_sync(sgw_batch* b)
         for (double& t : b->tf_h) t = NAN;
         b->tf_pending = false;
     }
-    if (!b->exec || lds > b->lds) {
+    bool recapture = !b->exec;
+    for (int d = 0; d < 4; d++) recapture |= lds[d] > b->lds[d];
+    if (recapture) {
         batch_drop_graph(b);
-        b->lds = lds;
-        b->blocks = stage_grid(b->precision, lds, b->blocks_per_cu);
+        for (int d = 0; d < 4; d++) {
+            b->lds[d] = lds[d] > b->lds[d] ? lds[d] : b->lds[d];
+            b->blocks[d] = b->lds[d] ? stage_grid(b->precision, d + 1, b->lds[d], b->blocks_per_cu) : 0;
+        }
         e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
         if (e != hipSuccess) return sgw_hip_fail(e, "capture stream");
         e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return sgw_hip_fail(e, "begin capture");
         hipError_t el = launch_dt(b->reqs_d, b->max_solvers, b->cap);
         for (int st = 0; st < 3 && el == hipSuccess; st++)
-            el = launch_stage_dev_count(b->items_d, b->nitems_d, b->blocks, st, b->precision, b->lds, b->cap);
+            for (int d = 0; d < 4 && el == hipSuccess; d++)
+                if (b->lds[d])
+                    el = launch_stage_range(b->items_d, b->ranges_d + 2 * d, b->blocks[d], st, b->precision, d + 1,
+                                            b->lds[d], b->cap);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap, &g);
         if (el != hipSuccess) return sgw_hip_fail(el, "capture batch step");
@@ -262,11 +278,14 @@ extern "C" sgw_status sgw_batch_launch_stage(sgw_batch_t* b, int32_t stage, int3
     if (stage < 0 || stage > 2 || reps < 0) return sgw_fail(SGW_ERR_INVALID_ARG, "stage %d reps %d", stage, reps);
     sgw_status rc = batch_sync(b);
     if (rc != SGW_OK) return rc;
-    for (int i = 0; i < reps; i++) {
-        b->queued = true;
-        hipError_t e = launch_stage_dev_count(b->items_d, b->nitems_d, b->blocks, stage, b->precision, b->lds, b->stream);
-        if (e != hipSuccess) return sgw_hip_fail(e, "stage launch");
-    }
+    for (int i = 0; i < reps; i++)
+        for (int d = 0; d < 4; d++) {
+            if (!b->ranges_h[2 * d + 1]) continue;
+            b->queued = true;
+            hipError_t e = launch_stage_range(b->items_d, b->ranges_d + 2 * d, b->blocks[d], stage, b->precision, d + 1,
+                                              b->lds[d], b->stream);
+            if (e != hipSuccess) return sgw_hip_fail(e, "stage launch");
+        }
     return SGW_OK;
 }
 
@@ -320,6 +339,7 @@ extern "C" sgw_status sgw_batch_set_blocks_per_cu(sgw_batch_t* b, int32_t blocks
         b->queued = false;
     }
     batch_drop_graph(b);
+    for (int d = 0; d < 4; d++) b->lds[d] = 0;
     b->blocks_per_cu = blocks_per_cu;
     b->dirty = true;
     return SGW_OK;

@@ -138,6 +138,7 @@ __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real 
 template <typename Real, int D>
 __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su, Real* sf)
 {
+    constexpr int SEG = sgw_seg(D);
     const int tid = threadIdx.x;
     const double dt = ((const SGW_CONST ReqDev*)g->req)->dt;
     const Real dtr = (Real)dt;
@@ -329,7 +330,7 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
         // directions alternate between two flux buffers: one barrier per direction
         Real* __restrict__ sfk = (k & 1) ? sf + g->sf_elems : sf;
         // ---- interface fluxes F_{i+1/2} of the box in direction k -> sf.  Each thread takes
-        //      SGW_SEG consecutive interfaces of one line from a window of SGW_SEG + 5 values;
+        //      SEG consecutive interfaces of one line from a window of SEG + 5 values;
         //      consecutive lanes take neighbouring lines (stride 1, or RS for direction 1).
         const int stot = g->seg_total[k];
         const int Lk = g->nlines[k];
@@ -364,18 +365,18 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
                 fbase = inner + M24((int)outer, CSk * Ik);
                 fstride = CSk;
             }
-            const int i0 = seg * SGW_SEG - hf; // first interface: x_{i0+1/2}
-            Real v[SGW_SEG + 5];
+            const int i0 = seg * SEG - hf; // first interface: x_{i0+1/2}
+            Real v[SEG + 5];
             if (fast) {
                 const int a0 = base_core + M24(i0 - 2, LSk);
 #pragma unroll
-                for (int q = 0; q < SGW_SEG + 5; q++) v[q] = su[a0 + (k == 0 ? q : M24(q, LSk))];
+                for (int q = 0; q < SEG + 5; q++) v[q] = su[a0 + (k == 0 ? q : M24(q, LSk))];
             } else if (hf) {
                 // window position p < 0 lies in the low slab, p >= t in the high one: pick the
                 // base by selects (no divergent branches), then add p times the line stride
                 const int blo = slo + base_slab + 3 * LSk, bhi = shi + base_slab - tk * LSk;
 #pragma unroll
-                for (int q = 0; q < SGW_SEG + 5; q++) {
+                for (int q = 0; q < SEG + 5; q++) {
                     int p = i0 + q - 2;
                     p = p > tk + 2 ? tk + 2 : p; // past the last interface: valid data, result unused
                     const int bs = p < 0 ? blo : base_core;
@@ -383,7 +384,7 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
                 }
             } else {
 #pragma unroll
-                for (int q = 0; q < SGW_SEG + 5; q++) {
+                for (int q = 0; q < SEG + 5; q++) {
                     int p = i0 + q - 2;
                     p += (p < 0) ? tk : 0;
                     p -= (p >= tk) ? tk : 0;
@@ -402,11 +403,11 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
                 cp = Real(0.5) * (c + alpha);
                 cm = Real(0.5) * (c - alpha);
             }
-            Real F[SGW_SEG];
-            window_fluxes<Real, SGW_SEG>(v, burgers, cp, cm, alpha, epsT, linear, F);
+            Real F[SEG];
+            window_fluxes<Real, SEG>(v, burgers, cp, cm, alpha, epsT, linear, F);
 #pragma unroll
-            for (int s = 0; s < SGW_SEG; s++) {
-                const int ip = seg * SGW_SEG + s; // i + hf
+            for (int s = 0; s < SEG; s++) {
+                const int ip = seg * SEG + s; // i + hf
                 if (interior || ip < Ik) sfk[fbase + M24(ip, fstride)] = F[s];
             }
         }
@@ -463,12 +464,17 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
     }
 }
 
-template <typename Real>
+// One kernel per precision and dimension, so each gets its own registers and code size.
+template <typename Real, int D>
 __global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __restrict__ items, int nitems,
-                                                          const int* __restrict__ nitems_dev, int stage)
+                                                          const int* __restrict__ range_dev, int stage)
 {
-    // a batch keeps its box count in device memory so a captured graph stays valid as solves come and go
-    if (nitems_dev) nitems = *nitems_dev;
+    // a batch keeps this dimension's range of its box list (offset, count) in device memory,
+    // so a captured graph stays valid as solves come and go
+    if (range_dev) {
+        items += range_dev[0];
+        nitems = range_dev[1];
+    }
     extern __shared__ __align__(16) unsigned char smem[];
     // XCD-aware order: consecutive workgroup ids land on different XCDs, so hand
     // each XCD a contiguous run of boxes (neighbouring boxes share halo lines in L2).
@@ -488,13 +494,50 @@ __global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __rest
         const size_t su_elems = (size_t)g->pad_total;
         Real* su = (Real*)smem;
         Real* sf = su + ((su_elems + 1) & ~(size_t)1);
-        switch (g->d) {
-        case 1: stage_box<Real, 1>(g, ibox, stage, su, sf); break;
-        case 2: stage_box<Real, 2>(g, ibox, stage, su, sf); break;
-        case 3: stage_box<Real, 3>(g, ibox, stage, su, sf); break;
-        default: stage_box<Real, 4>(g, ibox, stage, su, sf); break;
-        }
+        stage_box<Real, D>(g, ibox, stage, su, sf);
         __syncthreads();
+    }
+}
+
+template <typename Real, int D>
+int occupancy_d(size_t lds_bytes)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_kernel<Real, D>, SGW_BLOCK, lds_bytes) != hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb;
+}
+
+template <typename Real>
+int occupancy_r(int dim, size_t lds_bytes)
+{
+    switch (dim) {
+    case 1: return occupancy_d<Real, 1>(lds_bytes);
+    case 2: return occupancy_d<Real, 2>(lds_bytes);
+    case 3: return occupancy_d<Real, 3>(lds_bytes);
+    default: return occupancy_d<Real, 4>(lds_bytes);
+    }
+}
+
+template <typename Real, int D>
+hipError_t launch_d(const WorkItem* items, int nitems, const int* range_dev, int blocks, int stage, size_t lds,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL((stage_kernel<Real, D>), dim3(blocks), dim3(SGW_BLOCK), lds, s, items, nitems, range_dev,
+                       stage);
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_r(int dim, const WorkItem* items, int nitems, const int* range_dev, int blocks, int stage,
+                    size_t lds, hipStream_t s)
+{
+    switch (dim) {
+    case 1: return launch_d<Real, 1>(items, nitems, range_dev, blocks, stage, lds, s);
+    case 2: return launch_d<Real, 2>(items, nitems, range_dev, blocks, stage, lds, s);
+    case 3: return launch_d<Real, 3>(items, nitems, range_dev, blocks, stage, lds, s);
+    default: return launch_d<Real, 4>(items, nitems, range_dev, blocks, stage, lds, s);
     }
 }
 
@@ -520,49 +563,31 @@ int device_cus()
     return n;
 }
 
-int stage_grid(int precision, size_t lds_bytes, int blocks_per_cu)
+int stage_grid(int precision, int dim, size_t lds_bytes, int blocks_per_cu)
 {
-    int occ = stage_occupancy(precision, lds_bytes);
+    int occ = stage_occupancy(precision, dim, lds_bytes);
     if (blocks_per_cu > 0 && blocks_per_cu < occ) occ = blocks_per_cu;
     return occ * device_cus();
 }
 
-int stage_occupancy(int precision, size_t lds_bytes)
+int stage_occupancy(int precision, int dim, size_t lds_bytes)
 {
-    int nb = 0;
-    hipError_t e;
-    if (precision == SGW_FP64)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_kernel<double>, SGW_BLOCK, lds_bytes);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_kernel<float>, SGW_BLOCK, lds_bytes);
-    if (e != hipSuccess || nb < 1) nb = 1;
-    return nb;
+    return precision == SGW_FP64 ? occupancy_r<double>(dim, lds_bytes) : occupancy_r<float>(dim, lds_bytes);
 }
 
-
-hipError_t launch_stage(const WorkItem* items, int nitems, int stage, int precision, int dim_max,
-                        size_t lds_bytes, int grid_cap, hipStream_t s)
+hipError_t launch_stage(const WorkItem* items, int nitems, int stage, int precision, int dim, size_t lds_bytes,
+                        int grid_cap, hipStream_t s)
 {
-    (void)dim_max;
     if (nitems <= 0) return hipSuccess;
     int blocks = nitems;
     if (grid_cap > 0 && blocks > grid_cap) blocks = grid_cap;
-    const int* nd = nullptr;
-    if (precision == SGW_FP64)
-        hipLaunchKernelGGL(stage_kernel<double>, dim3(blocks), dim3(SGW_BLOCK), lds_bytes, s, items, nitems, nd, stage);
-    else
-        hipLaunchKernelGGL(stage_kernel<float>, dim3(blocks), dim3(SGW_BLOCK), lds_bytes, s, items, nitems, nd, stage);
-    return hipGetLastError();
+    if (precision == SGW_FP64) return launch_r<double>(dim, items, nitems, nullptr, blocks, stage, lds_bytes, s);
+    return launch_r<float>(dim, items, nitems, nullptr, blocks, stage, lds_bytes, s);
 }
 
-hipError_t launch_stage_dev_count(const WorkItem* items, const int* nitems_dev, int blocks, int stage, int precision,
-                                  size_t lds_bytes, hipStream_t s)
+hipError_t launch_stage_range(const WorkItem* items, const int* range_dev, int blocks, int stage, int precision,
+                              int dim, size_t lds_bytes, hipStream_t s)
 {
-    if (precision == SGW_FP64)
-        hipLaunchKernelGGL(stage_kernel<double>, dim3(blocks), dim3(SGW_BLOCK), lds_bytes, s, items, 0, nitems_dev,
-                           stage);
-    else
-        hipLaunchKernelGGL(stage_kernel<float>, dim3(blocks), dim3(SGW_BLOCK), lds_bytes, s, items, 0, nitems_dev,
-                           stage);
-    return hipGetLastError();
+    if (precision == SGW_FP64) return launch_r<double>(dim, items, 0, range_dev, blocks, stage, lds_bytes, s);
+    return launch_r<float>(dim, items, 0, range_dev, blocks, stage, lds_bytes, s);
 }

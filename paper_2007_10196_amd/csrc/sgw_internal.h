@@ -10,7 +10,13 @@
 #define SGW_BLOCK 256     // threads per workgroup of every kernel (4 wave64)
 #define SGW_MAXR 8        // nodes per thread in the stage kernel: box core <= SGW_BLOCK * SGW_MAXR
 #define SGW_NPART 1024    // most workgroups of the first norm pass (their count depends on n only)
-#define SGW_SEG 4         // interfaces per thread along directions 2..d (sliding window)
+#define SGW_SEG 4         // interfaces per thread of the flux sweep (sliding window), d <= 3
+
+// Interfaces per thread of the flux sweep of a d-dimensional grid.  4D boxes are short
+// (4 or 8 nodes) in most directions, so 4 + 1 interfaces fill one segment of 5.  A box that
+// spans its grid has t = n >= 4 nodes, which keeps every window position of the periodic
+// wrap within two subtractions of t for both lengths.
+__host__ __device__ constexpr int sgw_seg(int d) { return d == 4 ? 5 : SGW_SEG; }
 
 // Division by a run-time constant d >= 1 for numerators below 2^31:
 // q = (umulhi(x, m) + x) >> s with s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1.
@@ -95,7 +101,7 @@ struct alignas(64) GridDev {
     int32_t I[SGW_MAX_DIM];          // interfaces per line in the box: t + (halo ? 1 : 0)
     int32_t flux_total[SGW_MAX_DIM]; // interfaces in the box per direction
     int32_t coef_src[SGW_MAX_DIM];   // direction whose node index selects the coefficient, -1: constant
-    int32_t nseg[SGW_MAX_DIM];       // segments of SGW_SEG interfaces per line
+    int32_t nseg[SGW_MAX_DIM];       // segments of sgw_seg(d) interfaces per line
     int32_t seg_total[SGW_MAX_DIM];  // work items of the segment loop: lines * nseg[k]
     int32_t LS[SGW_MAX_DIM];         // LDS strides of the core box (row stride RS)
     int32_t slab_n[SGW_MAX_DIM];     // values per halo slab (3 core / t_k)
@@ -222,14 +228,16 @@ hipError_t launch_restrict_many(const ResetItem* resets, int nresets, const Rest
                                 int precision, hipStream_t s);
 hipError_t launch_dt(ReqDev* const* reqs, int nreq, hipStream_t s);
 hipError_t launch_dt_one(ReqDev* req, hipStream_t s);
-hipError_t launch_stage(const WorkItem* items, int nitems, int stage, int precision, int dim_max,
-                        size_t lds_bytes, int grid_cap, hipStream_t s);
-hipError_t launch_stage_dev_count(const WorkItem* items, const int* nitems_dev, int blocks, int stage, int precision,
-                                  size_t lds_bytes, hipStream_t s);
+// stage kernel of dimension dim over items[0..nitems); grid_cap caps the persistent grid
+hipError_t launch_stage(const WorkItem* items, int nitems, int stage, int precision, int dim, size_t lds_bytes,
+                        int grid_cap, hipStream_t s);
+// the same over items[range_dev[0] .. + range_dev[1]) read on the device (batches, graphs)
+hipError_t launch_stage_range(const WorkItem* items, const int* range_dev, int blocks, int stage, int precision,
+                              int dim, size_t lds_bytes, hipStream_t s);
 hipError_t launch_gather_done(ReqDev* const* reqs, int nreq, int* flags, hipStream_t s);
 size_t stage_lds_bytes(const GridDev& g, int precision);
-int stage_occupancy(int precision, size_t lds_bytes);
-int stage_grid(int precision, size_t lds_bytes, int blocks_per_cu);  // persistent grid: blocks per CU x CUs
+int stage_occupancy(int precision, int dim, size_t lds_bytes);
+int stage_grid(int precision, int dim, size_t lds_bytes, int blocks_per_cu);  // persistent grid: blocks per CU x CUs
 hipError_t launch_prolong(const ProDev* pro_dev, const FineDev* fine_dev, const FineDev& fine_host,
                           int precision, size_t lds_bytes, double* out, hipStream_t s);
 hipError_t launch_prolong_many(const ProItem* items, int nitems, int d, int precision, size_t lds_bytes,
