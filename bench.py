@@ -339,7 +339,7 @@ def main():
     achieved = stage_flops / (stage_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
-                "kernel": "stage_kernel<float> (RK stage 1)", "avg_launch_us": stage_ms * 1e3,
+                "kernel": "stage_kernel<float, 2> (RK stage 1)", "avg_launch_us": stage_ms * 1e3,
                 "flops_per_launch": stage_flops, "boxes_per_launch": info["boxes"],
                 "algorithmic_bytes_per_launch": info["nodes"] * 4 * 2,
                 "achieved_algorithmic_GBs": info["nodes"] * 4 * 2 / (stage_ms * 1e-3) / 1e9}
