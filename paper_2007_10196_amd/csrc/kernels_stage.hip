@@ -48,9 +48,8 @@ __device__ __forceinline__ double wsum(double c, double num, double den)
 // T_r = s_r^2 + 12/13 eps is used, and the weights d_r/(...)^2 are normalised
 // with one division (numerator and denominator times the product of the three
 // squares).  R_r = d_r (q_r - c).
-template <typename Real>
-__device__ __forceinline__ Real weno5s(Real c, Real D0, Real D1, Real D2, Real D3, Real T0, Real T1, Real T2,
-                                       int linear)
+template <typename Real, bool LINEAR>
+__device__ __forceinline__ Real weno5s(Real c, Real D0, Real D1, Real D2, Real D3, Real T0, Real T1, Real T2)
 {
     // every multiply-add is an explicit fma: a flux then rounds the same wherever it sits in a
     // window, so results do not depend on the box decomposition
@@ -58,7 +57,7 @@ __device__ __forceinline__ Real weno5s(Real c, Real D0, Real D1, Real D2, Real D
     const Real R0 = fma(Real(0.5 / 6.0), D1, Real(-0.2 / 6.0) * D0);
     const Real R1 = fma(Real(0.6 / 6.0), D1, d2);
     const Real R2 = fma(Real(-0.3 / 6.0), D3, d2);
-    if (linear) return c + ((R0 + R1) + R2);
+    if (LINEAR) return c + ((R0 + R1) + R2);
     const Real g0 = fma(Real(3), D1, -D0), g1 = D1 + D2, g2 = fma(Real(-3), D2, D3);
     const Real K = Real(3.0 / 13.0);
     Real e0 = fma(K * g0, g0, T0);
@@ -77,10 +76,10 @@ __device__ __forceinline__ Real weno5s(Real c, Real D0, Real D1, Real D2, Real D
 // u_{i0-2} .. u_{i0+NI+2} of one line: LF split f^+- (eq. LFflux), the positive-wind
 // reconstruction of f^+ on i-2..i+2 plus the mirrored one of f^- on i+3..i-1.  A
 // split part that is identically zero (c = -+alpha for a linear flux) contributes
-// exactly zero and is skipped.  epsT = 12/13 eps.
-template <typename Real, int NI>
+// exactly zero and is skipped.  epsT = 12/13 eps.  LINEAR: the linear weights d_r.
+template <typename Real, int NI, bool LINEAR>
 __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real cp, Real cm, Real alpha, Real epsT,
-                                              int linear, Real* F)
+                                              Real* F)
 {
     // the flux type and the wind sides are uniform: branch once per window, not per value
     Real pv[NI + 5], mv[NI + 5];
@@ -112,8 +111,8 @@ __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real 
         }
 #pragma unroll
         for (int s = 0; s < NI; s++)
-            F[s] = weno5s<Real>(pv[s + 2], dp[s], dp[s + 1], dp[s + 2], dp[s + 3], tp[s + 1], tp[s + 2], tp[s + 3],
-                                linear);
+            F[s] = weno5s<Real, LINEAR>(pv[s + 2], dp[s], dp[s + 1], dp[s + 2], dp[s + 3], tp[s + 1], tp[s + 2],
+                                        tp[s + 3]);
     } else {
 #pragma unroll
         for (int s = 0; s < NI; s++) F[s] = Real(0);
@@ -130,8 +129,8 @@ __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real 
         }
 #pragma unroll
         for (int s = 0; s < NI; s++)
-            F[s] += weno5s<Real>(mv[s + 3], -dm[s + 4], -dm[s + 3], -dm[s + 2], -dm[s + 1], tm[s + 4], tm[s + 3],
-                                 tm[s + 2], linear);
+            F[s] += weno5s<Real, LINEAR>(mv[s + 3], -dm[s + 4], -dm[s + 3], -dm[s + 2], -dm[s + 1], tm[s + 4],
+                                         tm[s + 3], tm[s + 2]);
     }
 }
 
@@ -404,7 +403,11 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
                 cm = Real(0.5) * (c - alpha);
             }
             Real F[SEG];
-            window_fluxes<Real, SEG>(v, burgers, cp, cm, alpha, epsT, linear, F);
+            // the weight type is uniform over the launch's grids: one branch per window
+            if (linear)
+                window_fluxes<Real, SEG, true>(v, burgers, cp, cm, alpha, epsT, F);
+            else
+                window_fluxes<Real, SEG, false>(v, burgers, cp, cm, alpha, epsT, F);
 #pragma unroll
             for (int s = 0; s < SEG; s++) {
                 const int ip = seg * SEG + s; // i + hf
