@@ -69,11 +69,15 @@ def run_batch_step(torch, batch, solvers, outs, exacts, res):
     # the wave speed only decays before the shock, so the estimate is an upper bound
     # up to WENO overshoot: march most of it blind, then look every two steps
     batch.step(max(1, step_estimate(solvers[0].problem) - 4))
+    # the flags of each poll travel while the next two steps run (a step of solves
+    # that are done does no work)
+    batch.poll_begin()
     while True:
-        done |= set(batch.poll())
+        batch.step(2)
+        done |= set(batch.poll_end())
         if len(done) == len(solvers):
             break
-        batch.step(2)
+        batch.poll_begin()
     batch.release_many(list(batch.slots))
     # Alg. Step 3 for every solve in one launch, then the norms of every solve in one launch
     prolongate_combine_many(solvers, outs, stream=batch.stream)

@@ -192,7 +192,9 @@ sgw_status sgw_norms_async(sgw_solver_t* solver, const double* a_dev, const doub
  * of every solve; all solves share dimension and precision); outs[i] receives
  * solve i's combined solution.  scratch_dev (device, 256-byte aligned) holds
  * the tile list, sgw_prolongate_many_scratch_bytes(solvers, n) bytes.  Runs on
- * hip_stream after waiting for each solver's own stream; synchronises. */
+ * hip_stream after waiting for each solver's own stream that differs from it;
+ * returns without waiting for the device (scratch_dev stays in use until the
+ * launch has run in stream order). */
 sgw_status sgw_prolongate_combine_many(sgw_solver_t* const* solvers, double* const* outs, int32_t n,
                                        void* scratch_dev, uint64_t scratch_bytes, void* hip_stream);
 uint64_t sgw_prolongate_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n);
@@ -202,7 +204,8 @@ uint64_t sgw_prolongate_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t
  * u0 at its nodes, bitwise as sgw_restrict_initial would.  All solves share a
  * precision.  scratch_dev (device, 256-byte aligned) holds the chunk list,
  * sgw_restrict_many_scratch_bytes(solvers, n) bytes.  Runs on hip_stream after
- * waiting for each solver's own stream; synchronises. */
+ * waiting for each solver's own stream that differs from it; returns without
+ * waiting for the device (scratch_dev stays in use until the launch has run). */
 sgw_status sgw_restrict_initial_many(sgw_solver_t* const* solvers, int32_t n, void* scratch_dev,
                                      uint64_t scratch_bytes, void* hip_stream);
 uint64_t sgw_restrict_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n);
@@ -212,7 +215,8 @@ uint64_t sgw_restrict_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n
  * (device FP64), bitwise as sgw_norms gives them.  scratch_dev (device, 256-byte
  * aligned) holds the pair list and partial sums, sgw_norms_many_scratch_bytes
  * bytes.  Runs on hip_stream; the caller orders the writes of a and b before
- * it.  Synchronises. */
+ * it.  Returns without waiting for the device (scratch_dev stays in use until
+ * the launches have run). */
 sgw_status sgw_norms_many(sgw_solver_t* const* solvers, const double* const* a_dev, const double* const* b_dev,
                           int32_t n, double* result_dev, void* scratch_dev, uint64_t scratch_bytes, void* hip_stream);
 uint64_t sgw_norms_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n);
@@ -257,12 +261,23 @@ sgw_status sgw_batch_admit(sgw_batch_t* batch, sgw_solver_t* solver, double t_fi
  * its error; *n_admitted counts the solvers admitted before it. */
 sgw_status sgw_batch_admit_many(sgw_batch_t* batch, sgw_solver_t* const* solvers, int32_t n, const double* t_final,
                                 int32_t* slots, int32_t* n_admitted);
-/* Advance every active solver by up to nsteps steps (finished ones do nothing). */
+/* Advance every active solver by up to nsteps steps (finished ones do nothing).
+ * Enqueues graph launches on the batch stream and returns; runs of 8 steps go
+ * in one launch of an 8-step graph. */
 sgw_status sgw_batch_step(sgw_batch_t* batch, int32_t nsteps);
 /* Which slots have reached their final time (synchronises).  done_slots has
  * room for max_solvers entries. */
 sgw_status sgw_batch_poll(sgw_batch_t* batch, int32_t* done_slots, int32_t* n_done);
-/* Remove a solver from the batch; its budget and slot become free. */
+/* sgw_batch_poll in two halves, so that steps can be queued while the flags
+ * travel: _begin enqueues the gathering of the completion flags at this point of
+ * the stream; _end waits for them and reports the slots that were done there.
+ * One poll may be in flight (SGW_ERR_STATE otherwise); a slot released or
+ * refilled in between is not reported. */
+sgw_status sgw_batch_poll_begin(sgw_batch_t* batch);
+sgw_status sgw_batch_poll_end(sgw_batch_t* batch, int32_t* done_slots, int32_t* n_done);
+/* Remove a solver from the batch; its budget and slot become free.  Returns
+ * without waiting for queued steps: a solver whose own stream differs from the
+ * batch stream has that stream wait for them (stream-ordered). */
 sgw_status sgw_batch_release(sgw_batch_t* batch, int32_t slot);
 /* sgw_batch_release for n distinct occupied slots (all checked before any is
  * released); waits for queued steps at most once. */

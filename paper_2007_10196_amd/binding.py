@@ -90,6 +90,8 @@ _SIGS = {
     "sgw_batch_release_many": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32]),
     "sgw_batch_step": (C.c_int32, [C.c_void_p, C.c_int32]),
     "sgw_batch_poll": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "sgw_batch_poll_begin": (C.c_int32, [C.c_void_p]),
+    "sgw_batch_poll_end": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "sgw_batch_release": (C.c_int32, [C.c_void_p, C.c_int32]),
     "sgw_batch_launch_stage": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
     "sgw_batch_set_blocks_per_cu": (C.c_int32, [C.c_void_p, C.c_int32]),

@@ -1035,7 +1035,7 @@ extern "C" sgw_status sgw_prolongate_combine_many(sgw_solver_t* const* solvers, 
     const int d = solvers[0] ? solvers[0]->plan->pb.dim : 0;
     const int prec = solvers[0] ? solvers[0]->plan->cfg.precision : 0;
     size_t lds = 0;
-    std::vector<ProItem> items;
+    uint64_t nitems = 0;
     for (int i = 0; i < n; i++) {
         sgw_solver* s = solvers[i];
         if (!s || !outs[i]) return sgw_fail(SGW_ERR_INVALID_ARG, "null solver or output %d", i);
@@ -1044,22 +1044,27 @@ extern "C" sgw_status sgw_prolongate_combine_many(sgw_solver_t* const* solvers, 
             return sgw_fail(SGW_ERR_INVALID_ARG, "solvers of one call must share dimension and precision");
         const size_t l = 2 * (prec == SGW_FP64 ? 8 : 4) * s->plan->pro_buf_elems;
         lds = l > lds ? l : lds;
-        const int64_t t = fine_tiles(s);
-        for (int64_t k = 0; k < t; k++) items.push_back(ProItem{s->pro_d, s->fine_d, outs[i], (int32_t)k, 0});
+        nitems += (uint64_t)fine_tiles(s);
     }
-    if ((uint64_t)items.size() * sizeof(ProItem) > scratch_bytes)
-        return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "scratch holds %llu items, %zu needed",
-                        (unsigned long long)(scratch_bytes / sizeof(ProItem)), items.size());
-    if (items.size() > 0x7fffffff) return sgw_fail(SGW_ERR_UNSUPPORTED, "too many tiles");
+    if (nitems * sizeof(ProItem) > scratch_bytes)
+        return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "scratch holds %llu items, %llu needed",
+                        (unsigned long long)(scratch_bytes / sizeof(ProItem)), (unsigned long long)nitems);
+    if (nitems > 0x7fffffff) return sgw_fail(SGW_ERR_UNSUPPORTED, "too many tiles");
+    Staging stg(nitems * sizeof(ProItem));
+    HIPCHK(stg.err, "staging buffer");
+    ProItem* items = (ProItem*)stg.host;
+    uint64_t c = 0;
+    for (int i = 0; i < n; i++) {
+        sgw_solver* s = solvers[i];
+        const int64_t t = fine_tiles(s);
+        for (int64_t k = 0; k < t; k++) items[c++] = ProItem{s->pro_d, s->fine_d, outs[i], (int32_t)k, 0};
+    }
     hipStream_t st = (hipStream_t)hip_stream;
     // every solver's own stream has finished the state the tiles read
     for (int i = 0; i < n; i++)
         if (solvers[i]->stream != st) HIPCHK(hipStreamSynchronize(solvers[i]->stream), "synchronise solver stream");
-    HIPCHK(hipMemcpyAsync(scratch_dev, items.data(), items.size() * sizeof(ProItem), hipMemcpyHostToDevice, st),
-           "upload tile list");
-    HIPCHK(launch_prolong_many((const ProItem*)scratch_dev, (int)items.size(), d, prec, lds, st), "prolongate many");
-    // the host list must outlive the copy
-    HIPCHK(hipStreamSynchronize(st), "synchronise");
+    HIPCHK(stg.upload(0, scratch_dev, nitems * sizeof(ProItem), st), "upload tile list");
+    HIPCHK(launch_prolong_many((const ProItem*)scratch_dev, (int)nitems, d, prec, lds, st), "prolongate many");
     return SGW_OK;
 }
 
@@ -1105,9 +1110,10 @@ extern "C" sgw_status sgw_restrict_initial_many(sgw_solver_t* const* solvers, in
     const uint64_t off_items = align256((uint64_t)n * sizeof(ResetItem));
     const int64_t nchunks = (int64_t)((need - off_items) / sizeof(RestrictItem));
     if (nchunks > 0x7fffffff) return sgw_fail(SGW_ERR_UNSUPPORTED, "too many restriction chunks");
-    std::vector<unsigned char> host(need);
-    ResetItem* resets = (ResetItem*)host.data();
-    RestrictItem* items = (RestrictItem*)(host.data() + off_items);
+    Staging stg(need);
+    HIPCHK(stg.err, "staging buffer");
+    ResetItem* resets = (ResetItem*)stg.host;
+    RestrictItem* items = (RestrictItem*)(stg.host + off_items);
     int64_t c = 0;
     for (int i = 0; i < n; i++) {
         sgw_solver* s = solvers[i];
@@ -1130,12 +1136,10 @@ extern "C" sgw_status sgw_restrict_initial_many(sgw_solver_t* const* solvers, in
     // earlier work of each solve on its own stream may still read its state
     for (int i = 0; i < n; i++)
         if (solvers[i]->stream != st) HIPCHK(hipStreamSynchronize(solvers[i]->stream), "synchronise solver stream");
-    HIPCHK(hipMemcpyAsync(scratch_dev, host.data(), need, hipMemcpyHostToDevice, st), "upload restriction list");
+    HIPCHK(stg.upload(0, scratch_dev, need, st), "upload restriction list");
     const unsigned char* base = (const unsigned char*)scratch_dev;
     HIPCHK(launch_restrict_many((const ResetItem*)base, n, (const RestrictItem*)(base + off_items), (int)c, prec, st),
            "restrict many");
-    // the host list must outlive the copy
-    HIPCHK(hipStreamSynchronize(st), "synchronise");
     for (int i = 0; i < n; i++) {
         solvers[i]->restricted = true;
         solvers[i]->t_host = 0.0;
@@ -1176,7 +1180,9 @@ extern "C" sgw_status sgw_norms_many(sgw_solver_t* const* solvers, const double*
         return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "scratch of %llu bytes, %llu needed", (unsigned long long)scratch_bytes,
                         (unsigned long long)need);
     const int mp = norms_many_max_parts(solvers, n);
-    std::vector<NormItem> items(n);
+    Staging stg(sizeof(NormItem) * (size_t)n);
+    HIPCHK(stg.err, "staging buffer");
+    NormItem* items = (NormItem*)stg.host;
     for (int i = 0; i < n; i++) {
         const int64_t cnt = solvers[i]->plan->fine_nodes;
         items[i] = NormItem{a[i], b[i], cnt, result_dev + 2 * (size_t)i, norms_parts(cnt), 0};
@@ -1185,12 +1191,9 @@ extern "C" sgw_status sgw_norms_many(sgw_solver_t* const* solvers, const double*
     for (int i = 0; i < n; i++)
         if (solvers[i]->stream != st) HIPCHK(hipStreamSynchronize(solvers[i]->stream), "synchronise solver stream");
     unsigned char* base = (unsigned char*)scratch_dev;
-    HIPCHK(hipMemcpyAsync(base, items.data(), sizeof(NormItem) * (size_t)n, hipMemcpyHostToDevice, st),
-           "upload norm list");
+    HIPCHK(stg.upload(0, base, sizeof(NormItem) * (size_t)n, st), "upload norm list");
     HIPCHK(launch_norms_many((const NormItem*)base, n, mp, (double*)(base + align256((uint64_t)n * sizeof(NormItem))),
                              st),
            "norms many");
-    // the host list must outlive the copy
-    HIPCHK(hipStreamSynchronize(st), "synchronise");
     return SGW_OK;
 }

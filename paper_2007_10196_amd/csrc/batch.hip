@@ -1,10 +1,12 @@
 // Batched runtime of libsgweno: many solves (any dimension, level and final
-// time, one precision) advance together.  Each time step is one captured HIP
-// graph: the time-step kernel for every slot, then the three TVD-RK3 stages,
+// time, one precision) advance together.  A time step is the time-step kernel
+// for every slot, then the three TVD-RK3 stages,
 // each one persistent launch per dimension present over the boxes of every
 // admitted solve of that dimension.  The box list, grouped by dimension, and
 // each dimension's range of it live in device memory, so admitting or releasing
-// a solve is a stream-ordered copy and the graph stays valid.
+// a solve is a stream-ordered copy and the graph stays valid.  Two graphs are
+// captured: one step, and SGW_GRAPH_STEPS steps in a row (each graph launch
+// costs the device a gap of several microseconds, as long as a small stage).
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -25,6 +27,10 @@ struct sgw_batch {
     int* flags_d = nullptr;         // [max_solvers]
     double* tf_d = nullptr;         // [max_solvers] final times of new slots (NaN: unchanged)
     int* flags_pinned = nullptr;
+    hipEvent_t ev_order = nullptr;  // orders a released solver's own stream after the batch's steps
+    hipEvent_t ev_poll = nullptr;   // behind the copy of the completion flags
+    bool poll_inflight = false;
+    std::vector<sgw_solver*> poll_slots; // occupants of the slots when the flags were gathered
     std::vector<sgw_solver*> slots;
     std::vector<uint64_t> slot_bytes;
     std::vector<ReqDev*> reqs_h;
@@ -40,8 +46,12 @@ struct sgw_batch {
     int blocks_per_cu = 0;          // cap on resident stage workgroups per CU (0: occupancy)
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraphExec_t exec = nullptr;      // one step
+    hipGraph_t graph_n = nullptr;
+    hipGraphExec_t exec_n = nullptr;    // SGW_GRAPH_STEPS steps
 };
+
+#define SGW_GRAPH_STEPS 8
 
 static uint64_t a256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 
@@ -87,9 +97,11 @@ extern "C" sgw_status sgw_batch_create(int32_t max_solvers, int32_t precision, u
     b->reqs_h.assign(max_solvers, nullptr);
     b->tf_h.assign(max_solvers, NAN);
     hipError_t e = hipHostMalloc((void**)&b->flags_pinned, sizeof(int) * max_solvers, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_order, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_poll, hipEventDisableTiming);
     if (e != hipSuccess) {
-        delete b;
-        return sgw_hip_fail(e, "pinned flags");
+        sgw_batch_free(b);
+        return sgw_hip_fail(e, "batch set-up");
     }
     *out = b;
     return SGW_OK;
@@ -99,6 +111,10 @@ static void batch_drop_graph(sgw_batch* b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->exec_n) (void)hipGraphExecDestroy(b->exec_n);
+    if (b->graph_n) (void)hipGraphDestroy(b->graph_n);
+    b->exec_n = nullptr;
+    b->graph_n = nullptr;
     if (b->cap) (void)hipStreamDestroy(b->cap);
     b->exec = nullptr;
     b->graph = nullptr;
@@ -113,6 +129,8 @@ extern "C" void sgw_batch_free(sgw_batch_t* b)
     for (auto* s : b->slots)
         if (s) s->batch_slot = -1;
     if (b->flags_pinned) (void)hipHostFree(b->flags_pinned);
+    if (b->ev_order) (void)hipEventDestroy(b->ev_order);
+    if (b->ev_poll) (void)hipEventDestroy(b->ev_poll);
     delete b;
 }
 
@@ -143,30 +161,40 @@ static sgw_status batch_sync(sgw_batch* b)
         b->ranges_h[2 * (d - 1) + 1] = (int)b->items_h.size() - b->ranges_h[2 * (d - 1)];
     }
     b->nitems_h = (int)b->items_h.size();
-    hipError_t e = hipSuccess;
-    if (b->nitems_h)
-        e = hipMemcpyAsync(b->items_d, b->items_h.data(), sizeof(WorkItem) * b->items_h.size(), hipMemcpyHostToDevice,
-                           b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->ranges_d, b->ranges_h, sizeof(b->ranges_h), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->reqs_d, b->reqs_h.data(), sizeof(ReqDev*) * b->max_solvers, hipMemcpyHostToDevice,
-                           b->stream);
+    // the lists go through a pinned staging buffer: the uploads are stream-ordered
+    // and the host does not wait for the device
+    const size_t n_items = sizeof(WorkItem) * b->items_h.size(), n_ranges = sizeof(b->ranges_h);
+    const size_t n_reqs = sizeof(ReqDev*) * b->max_solvers, n_tf = sizeof(double) * b->max_solvers;
+    Staging stg(n_items + n_ranges + n_reqs + n_tf);
+    hipError_t e = stg.err;
+    if (e == hipSuccess) {
+        unsigned char* h = stg.host;
+        if (n_items) std::memcpy(h, b->items_h.data(), n_items);
+        std::memcpy(h + n_items, b->ranges_h, n_ranges);
+        std::memcpy(h + n_items + n_ranges, b->reqs_h.data(), n_reqs);
+        std::memcpy(h + n_items + n_ranges + n_reqs, b->tf_h.data(), n_tf);
+        e = stg.upload(0, b->items_d, n_items, b->stream);
+    }
+    if (e == hipSuccess) e = stg.upload(n_items, b->ranges_d, n_ranges, b->stream);
+    if (e == hipSuccess) e = stg.upload(n_items + n_ranges, b->reqs_d, n_reqs, b->stream);
     if (e == hipSuccess && b->tf_pending) {
-        e = hipMemcpyAsync(b->tf_d, b->tf_h.data(), sizeof(double) * b->max_solvers, hipMemcpyHostToDevice, b->stream);
+        e = stg.upload(n_items + n_ranges + n_reqs, b->tf_d, n_tf, b->stream);
         if (e == hipSuccess) e = launch_req_set_final_many(b->reqs_d, b->tf_d, b->max_solvers, b->stream);
     }
-    // the host vectors are read by the copies: wait before they can change
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return sgw_hip_fail(e, "upload batch lists");
-    b->queued = false;
     if (b->tf_pending) {
         for (double& t : b->tf_h) t = NAN;
         b->tf_pending = false;
     }
-    bool recapture = !b->exec;
+    bool recapture = !b->exec || !b->exec_n;
     for (int d = 0; d < 4; d++) recapture |= lds[d] > b->lds[d];
     if (recapture) {
+        // queued launches of the old graphs may still run: wait before they are destroyed
+        if (b->queued) {
+            e = hipStreamSynchronize(b->stream);
+            if (e != hipSuccess) return sgw_hip_fail(e, "synchronise batch");
+            b->queued = false;
+        }
         batch_drop_graph(b);
         for (int d = 0; d < 4; d++) {
             b->lds[d] = lds[d] > b->lds[d] ? lds[d] : b->lds[d];
@@ -174,21 +202,32 @@ static sgw_status batch_sync(sgw_batch* b)
         }
         e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
         if (e != hipSuccess) return sgw_hip_fail(e, "capture stream");
-        e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return sgw_hip_fail(e, "begin capture");
-        hipError_t el = launch_dt(b->reqs_d, b->max_solvers, b->cap);
-        for (int st = 0; st < 3 && el == hipSuccess; st++)
-            for (int d = 0; d < 4 && el == hipSuccess; d++)
-                if (b->lds[d])
-                    el = launch_stage_range(b->items_d, b->ranges_d + 2 * d, b->blocks[d], st, b->precision, d + 1,
-                                            b->lds[d], b->cap);
-        hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(b->cap, &g);
-        if (el != hipSuccess) return sgw_hip_fail(el, "capture batch step");
-        if (e != hipSuccess) return sgw_hip_fail(e, "end capture");
-        b->graph = g;
-        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-        if (e != hipSuccess) return sgw_hip_fail(e, "instantiate batch graph");
+        for (int which = 0; which < 2; which++) {
+            const int nsteps = which ? SGW_GRAPH_STEPS : 1;
+            e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return sgw_hip_fail(e, "begin capture");
+            hipError_t el = hipSuccess;
+            for (int step = 0; step < nsteps && el == hipSuccess; step++) {
+                el = launch_dt(b->reqs_d, b->max_solvers, b->cap);
+                for (int st = 0; st < 3 && el == hipSuccess; st++)
+                    for (int d = 0; d < 4 && el == hipSuccess; d++)
+                        if (b->lds[d])
+                            el = launch_stage_range(b->items_d, b->ranges_d + 2 * d, b->blocks[d], st, b->precision,
+                                                    d + 1, b->lds[d], b->cap);
+            }
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(b->cap, &g);
+            if (el != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return sgw_hip_fail(el, "capture batch step");
+            }
+            if (e != hipSuccess) return sgw_hip_fail(e, "end capture");
+            hipGraphExec_t x = nullptr;
+            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            (which ? b->graph_n : b->graph) = g;
+            if (e != hipSuccess) return sgw_hip_fail(e, "instantiate batch graph");
+            (which ? b->exec_n : b->exec) = x;
+        }
     }
     b->dirty = false;
     return SGW_OK;
@@ -241,35 +280,61 @@ extern "C" sgw_status sgw_batch_step(sgw_batch_t* b, int32_t nsteps)
     sgw_status rc = batch_sync(b);
     if (rc != SGW_OK) return rc;
     if (!b->nitems_h) return SGW_OK;
-    for (int i = 0; i < nsteps; i++) {
+    for (int i = 0; i < nsteps;) {
+        const bool many = nsteps - i >= SGW_GRAPH_STEPS;
         b->queued = true;
-        hipError_t e = hipGraphLaunch(b->exec, b->stream);
+        hipError_t e = hipGraphLaunch(many ? b->exec_n : b->exec, b->stream);
         if (e != hipSuccess) return sgw_hip_fail(e, "batch graph launch");
+        i += many ? SGW_GRAPH_STEPS : 1;
     }
     return SGW_OK;
 }
 
-extern "C" sgw_status sgw_batch_poll(sgw_batch_t* b, int32_t* done_slots, int32_t* n_done)
+extern "C" sgw_status sgw_batch_poll_begin(sgw_batch_t* b)
 {
-    if (!b || !done_slots || !n_done) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    if (!b) return sgw_fail(SGW_ERR_INVALID_ARG, "null batch");
+    if (b->poll_inflight) return sgw_fail(SGW_ERR_STATE, "a poll is already in flight");
     sgw_status rc = batch_sync(b);
     if (rc != SGW_OK) return rc;
     hipError_t e = launch_gather_done(b->reqs_d, b->max_solvers, b->flags_d, b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->flags_pinned, b->flags_d, sizeof(int) * b->max_solvers, hipMemcpyDeviceToHost, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_poll, b->stream);
     if (e != hipSuccess) return sgw_hip_fail(e, "poll batch");
-    b->queued = false;
+    b->poll_slots = b->slots;
+    b->poll_inflight = true;
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_batch_poll_end(sgw_batch_t* b, int32_t* done_slots, int32_t* n_done)
+{
+    if (!b || !done_slots || !n_done) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    if (!b->poll_inflight) return sgw_fail(SGW_ERR_STATE, "no poll in flight");
+    b->poll_inflight = false;
+    hipError_t e = hipEventSynchronize(b->ev_poll);
+    if (e != hipSuccess) return sgw_hip_fail(e, "poll batch");
     int n = 0;
     bool bad = false;
     for (int i = 0; i < b->max_solvers; i++) {
-        if (!b->slots[i]) continue;
+        // a slot released or refilled since the flags were gathered is not reported
+        if (!b->slots[i] || b->slots[i] != b->poll_slots[i]) continue;
         if (b->flags_pinned[i] & 1) done_slots[n++] = i;
         bad |= (b->flags_pinned[i] & 2) != 0;
     }
     *n_done = n;
     if (bad) return sgw_fail(SGW_ERR_NONFINITE, "a solve in the batch hit a non-finite wave speed");
     return SGW_OK;
+}
+
+extern "C" sgw_status sgw_batch_poll(sgw_batch_t* b, int32_t* done_slots, int32_t* n_done)
+{
+    if (!b || !done_slots || !n_done) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    sgw_status rc = sgw_batch_poll_begin(b);
+    if (rc != SGW_OK) return rc;
+    rc = sgw_batch_poll_end(b, done_slots, n_done);
+    // nothing is queued behind the flags: every step launched so far has run
+    if (rc == SGW_OK || rc == SGW_ERR_NONFINITE) b->queued = false;
+    return rc;
 }
 
 extern "C" sgw_status sgw_batch_launch_stage(sgw_batch_t* b, int32_t stage, int32_t reps)
@@ -310,13 +375,14 @@ extern "C" sgw_status sgw_batch_release(sgw_batch_t* b, int32_t slot)
 {
     if (!b) return sgw_fail(SGW_ERR_INVALID_ARG, "null batch");
     if (slot < 0 || slot >= b->max_solvers || !b->slots[slot]) return sgw_fail(SGW_ERR_INVALID_ARG, "bad slot %d", slot);
-    // the slot's solve may still be referenced by queued graph launches
-    if (b->queued) {
-        hipError_t e = hipStreamSynchronize(b->stream);
-        if (e != hipSuccess) return sgw_hip_fail(e, "synchronise batch");
-        b->queued = false;
+    // queued steps may still work on the solve: its own stream waits for them
+    sgw_solver* s = b->slots[slot];
+    if (b->queued && s->stream != b->stream) {
+        hipError_t e = hipEventRecord(b->ev_order, b->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, b->ev_order, 0);
+        if (e != hipSuccess) return sgw_hip_fail(e, "order solver stream after batch");
     }
-    b->slots[slot]->batch_slot = -1;
+    s->batch_slot = -1;
     b->tf_h[slot] = NAN;
     b->used -= b->slot_bytes[slot];
     b->slots[slot] = nullptr;

@@ -61,3 +61,44 @@ struct sgw_solver {
 
 sgw_status sgw_fail(sgw_status st, const char* fmt, ...);
 sgw_status sgw_hip_fail(hipError_t e, const char* what);
+
+// Pinned staging buffers for host-to-device list uploads (staging.hip): acquire a
+// buffer of at least `bytes`, fill it, upload parts of it in stream order, then
+// release it behind the copies (an event, no host wait).
+hipError_t staging_acquire(size_t bytes, int* handle, void** host);
+hipError_t staging_upload(int handle, size_t offset, void* dst_dev, size_t bytes, hipStream_t s);
+hipError_t staging_release(int handle, hipStream_t s);
+void staging_cancel(int handle);  // nothing was uploaded from it
+
+struct Staging {
+    int handle = -1;
+    unsigned char* host = nullptr;
+    hipError_t err = hipSuccess;
+    hipStream_t stream = nullptr;
+    bool uploaded = false;
+    explicit Staging(size_t bytes)
+    {
+        void* p = nullptr;
+        err = staging_acquire(bytes ? bytes : 1, &handle, &p);
+        host = (unsigned char*)p;
+        if (err != hipSuccess) handle = -1;
+    }
+    hipError_t upload(size_t offset, void* dst_dev, size_t bytes, hipStream_t s)
+    {
+        stream = s;
+        uploaded = true;
+        return staging_upload(handle, offset, dst_dev, bytes, s);
+    }
+    // the buffer returns to the pool once the copies enqueued so far have run
+    ~Staging()
+    {
+        if (handle < 0) return;
+        if (uploaded)
+            (void)staging_release(handle, stream);
+        else
+            staging_cancel(handle);
+    }
+    Staging(const Staging&) = delete;
+    Staging& operator=(const Staging&) = delete;
+};
+

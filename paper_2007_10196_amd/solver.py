@@ -248,6 +248,16 @@ class Batch:
         B.check(B.lib().sgw_batch_poll(self.handle, buf, C.byref(n)))
         return list(buf[:n.value])
 
+    def poll_begin(self):
+        """Enqueue the gathering of the completion flags; poll_end() reads them."""
+        B.check(B.lib().sgw_batch_poll_begin(self.handle))
+
+    def poll_end(self):
+        buf = (C.c_int32 * self.max_solvers)()
+        n = C.c_int32()
+        B.check(B.lib().sgw_batch_poll_end(self.handle, buf, C.byref(n)))
+        return list(buf[:n.value])
+
     def set_blocks_per_cu(self, n: int):
         B.check(B.lib().sgw_batch_set_blocks_per_cu(self.handle, int(n)))
 
@@ -276,13 +286,22 @@ class Batch:
             pass
 
 
+def _call_scratch(nbytes: int, device, stream: Optional[torch.cuda.Stream]) -> torch.Tensor:
+    """Device scratch for one many-solve call.  The call returns before its kernels
+    run, so the allocator is told the scratch is in use on the call's stream."""
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    if stream is not None and stream != torch.cuda.current_stream(t.device):
+        t.record_stream(stream)
+    return t
+
+
 def prolongate_combine_many(solvers, outs, stream: Optional[torch.cuda.Stream] = None):
     """Combined solutions of many solves (same dimension and precision) in one launch."""
     n = len(solvers)
     hs = (C.c_void_p * n)(*[s.handle.value for s in solvers])
     os_ = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
     nbytes = int(B.lib().sgw_prolongate_many_scratch_bytes(hs, n))
-    scratch = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=outs[0].device)
+    scratch = _call_scratch(nbytes, outs[0].device, stream)
     B.check(B.lib().sgw_prolongate_combine_many(hs, os_, n, C.c_void_p(scratch.data_ptr()), nbytes,
                                                 _stream_handle(stream)))
     return outs
@@ -293,7 +312,7 @@ def restrict_many(solvers, stream: Optional[torch.cuda.Stream] = None):
     n = len(solvers)
     hs = (C.c_void_p * n)(*[s.handle.value for s in solvers])
     nbytes = int(B.lib().sgw_restrict_many_scratch_bytes(hs, n))
-    scratch = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=solvers[0].device)
+    scratch = _call_scratch(nbytes, solvers[0].device, stream)
     B.check(B.lib().sgw_restrict_initial_many(hs, n, C.c_void_p(scratch.data_ptr()), nbytes, _stream_handle(stream)))
     return solvers
 
@@ -309,7 +328,7 @@ def norms_many(solvers, a, b, result: torch.Tensor, stream: Optional[torch.cuda.
     pa = (C.c_void_p * n)(*[x.data_ptr() for x in a])
     pb = (C.c_void_p * n)(*[y.data_ptr() for y in b])
     nbytes = int(B.lib().sgw_norms_many_scratch_bytes(hs, n))
-    scratch = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=result.device)
+    scratch = _call_scratch(nbytes, result.device, stream)
     B.check(B.lib().sgw_norms_many(hs, pa, pb, n, C.c_void_p(result.data_ptr()), C.c_void_p(scratch.data_ptr()),
                                    nbytes, _stream_handle(stream)))
     return result

@@ -240,6 +240,55 @@ def test_batched_results_equal_solo_results_bitwise():
         batch.release(slot)
 
 
+def test_pipelined_polls_and_multi_step_graphs_match_single_steps():
+    """Steps queued in runs (8-step graphs plus single ones) with the completion flags
+    polled while the next steps run give the same solutions as one step per poll."""
+    torch, B, Solver, Batch = _lib()
+    rng = np.random.default_rng(11)
+    probs = [W.randomized(f, nl, rng, precision=W.PREC_FP64) for f, nl in [(1, 3), (2, 3), (3, 2)]]
+    probs = [p.replace(T=min(p.T, 0.15)) for p in probs]
+
+    def run(pipelined):
+        _announce(f"batch pipelined={pipelined}")
+        batch = Batch(max_solvers=4, precision=B.FP64, hbm_budget=1 << 34)
+        solvers = []
+        for p in probs:
+            s = Solver(p)
+            s.restrict()
+            batch.admit(s)
+            solvers.append(s)
+        done = set()
+        if pipelined:
+            with pytest.raises(B.SgwError):
+                batch.poll_end()  # nothing in flight
+            batch.step(13)
+            batch.poll_begin()
+            with pytest.raises(B.SgwError):
+                batch.poll_begin()  # one poll at a time
+            for _ in range(400):
+                batch.step(3)
+                done |= set(batch.poll_end())
+                if len(done) == len(probs):
+                    break
+                batch.poll_begin()
+        else:
+            for _ in range(4000):
+                batch.step(1)
+                done |= set(batch.poll())
+                if len(done) == len(probs):
+                    break
+        assert len(done) == len(probs)
+        out = [(s.query()[1], s.prolongate_combine().cpu().numpy()) for s in solvers]
+        batch.release_many(list(batch.slots))
+        batch.close()
+        return out
+
+    a, b = run(False), run(True)
+    for (sa, ua), (sb, ub) in zip(a, b):
+        assert sa == sb
+        assert np.array_equal(ua, ub)
+
+
 def test_repeat_runs_are_bitwise_identical():
     pb = W.c2_burgers_2d(nl=4, T=0.1, precision=W.PREC_FP64)
     a = gpu_solve(pb)[2].cpu().numpy()
