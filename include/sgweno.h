@@ -71,7 +71,8 @@ typedef int32_t sgw_status;
                                       sum and the norms in FP64                                          */
 
 #define SGW_RUN_PLAIN 0            /* one launch per component grid per RK stage, no graph              */
-#define SGW_RUN_FUSED 1            /* one launch per RK stage over all component grids                  */
+#define SGW_RUN_FUSED 1            /* one launch per RK stage over all component grids; grids that are  */
+                                   /* one stage box take all three stages in one launch                 */
 #define SGW_RUN_GRAPH 2            /* SGW_RUN_FUSED with each time step captured in a HIP graph         */
 
 typedef struct sgw_problem {
@@ -282,11 +283,14 @@ sgw_status sgw_batch_release(sgw_batch_t* batch, int32_t slot);
 /* sgw_batch_release for n distinct occupied slots (all checked before any is
  * released); waits for queued steps at most once. */
 sgw_status sgw_batch_release_many(sgw_batch_t* batch, const int32_t* slots, int32_t n);
-/* Measurement hook: enqueue reps launches of RK stage `stage` (0..2) over the
- * batch's boxes, outside any graph, with the same launch shape as a step
- * (callers time them with events on the batch stream).  Stage 0 writes only the
- * first stage buffer, so repeating it leaves u^n unchanged; the solves' wave
- * speed slots are disturbed, so re-restrict before trusting later results. */
+/* Measurement hook, outside any graph (callers time it with events on the batch
+ * stream).  stage 0..2: reps launches of that RK stage, one stage at a time,
+ * over all of the batch's boxes; stage 0 writes only the first stage buffer, so
+ * repeating it leaves u^n unchanged.  stage 3: reps times the stage launches of
+ * one step as the step graph runs them (all three stages of the grids that are
+ * one box in one launch, the other grids stage by stage); this advances u^n
+ * without advancing t.  Either way the solves' wave-speed slots are disturbed,
+ * so re-restrict before trusting later results. */
 sgw_status sgw_batch_launch_stage(sgw_batch_t* batch, int32_t stage, int32_t reps);
 /* Tuning knob: at most blocks_per_cu resident stage workgroups per compute unit
  * (0: as many as fit).  The persistent stage launch splits the box list into

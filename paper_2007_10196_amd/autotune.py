@@ -3,8 +3,9 @@
 For a set of problems (one batch), every candidate box target (the largest box,
 in nodes, the planner's box search may pick for each component grid) is tried
 with every candidate cap on resident workgroups per compute unit: the batch is
-restricted and admitted, one step is taken, and a few standalone stage launches
-are timed with HIP events on the batch stream.  The fastest pair is returned and
+restricted and admitted, one step is taken, and the stage launches of a few steps
+(the three-stage launch of the grids that are one box, the per-stage launches of
+the others) are timed with HIP events on the batch stream.  The fastest pair is returned and
 cached in a JSON file keyed by the batch's grid shapes and precision.
 """
 from __future__ import annotations
@@ -19,6 +20,7 @@ import torch
 from .solver import Batch, Plan, Solver
 
 CANDIDATES = (512, 1024, 2048)
+STEP_STAGES = 3                     # sgw_batch_launch_stage: the stage launches of one step
 BLOCKS_PER_CU = (0, 4, 5, 6, 7)     # 0: as many as fit
 
 
@@ -28,7 +30,7 @@ def default_cache_path() -> str:
 
 def workload_key(problems: Sequence, precision: int) -> str:
     shapes = sorted({(p.d, p.nr, p.nl, p.flux) for p in problems})
-    raw = json.dumps({"shapes": shapes, "n": len(problems), "precision": precision, "tuner": 2})
+    raw = json.dumps({"shapes": shapes, "n": len(problems), "precision": precision, "tuner": 3})
     return hashlib.sha256(raw.encode()).hexdigest()[:16]
 
 
@@ -42,7 +44,8 @@ def _load(path: str) -> Dict:
 
 def time_stage(problems: Sequence, precision: int, box_target: int, reps: int = 10,
                blocks_per_cu: Iterable[int] = (0,)) -> Dict[int, float]:
-    """Average microseconds of one stage launch over the whole batch, per workgroup cap."""
+    """Average microseconds of the stage launches of one step (all three RK stages) over the
+    whole batch, per workgroup cap."""
     stream = torch.cuda.current_stream()
     solvers = [Solver(p, box_target=box_target) for p in problems]
     batch = Batch(max_solvers=len(solvers), precision=precision, hbm_budget=1 << 50,
@@ -55,9 +58,9 @@ def time_stage(problems: Sequence, precision: int, box_target: int, reps: int = 
     for bpc in blocks_per_cu:
         batch.set_blocks_per_cu(int(bpc))
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        batch.launch_stage(0, 2)
+        batch.launch_stage(STEP_STAGES, 2)
         e0.record(stream)
-        batch.launch_stage(0, reps)
+        batch.launch_stage(STEP_STAGES, reps)
         e1.record(stream)
         torch.cuda.synchronize()
         out[int(bpc)] = e0.elapsed_time(e1) / reps * 1e3

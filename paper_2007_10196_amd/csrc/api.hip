@@ -436,14 +436,23 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     }
     p->offsets[p->G] = tot;
     p->total_nodes = tot;
+    // the box list holds the grids that are one box first (their three stages run in one
+    // launch), then the boxes of the others, grid by grid
     p->nitems = 0;
-    p->stage_lds = 0;
-    for (int g = 0; g < p->G; g++) {
-        p->grids[g].first_item = (int32_t)p->nitems;
-        p->nitems += p->grids[g].nbox;
-        const size_t l = stage_lds_bytes(p->grids[g], cfg->precision);
-        p->stage_lds = l > p->stage_lds ? l : p->stage_lds;
-    }
+    p->nitems_whole = 0;
+    p->stage_lds = p->lds_whole = p->lds_boxed = 0;
+    for (int pass = 0; pass < 2; pass++)
+        for (int g = 0; g < p->G; g++) {
+            const bool one = p->grids[g].nbox == 1;
+            if (one != (pass == 0)) continue;
+            p->grids[g].first_item = (int32_t)p->nitems;
+            p->nitems += p->grids[g].nbox;
+            if (one) p->nitems_whole = p->nitems;
+            const size_t l = stage_lds_bytes(p->grids[g], cfg->precision);
+            p->stage_lds = l > p->stage_lds ? l : p->stage_lds;
+            size_t& m = one ? p->lds_whole : p->lds_boxed;
+            m = l > m ? l : m;
+        }
     for (int k = 0; k < d; k++)
         if (cfg->fine_tile[k] > 0 && N % cfg->fine_tile[k]) {
             delete p;
@@ -728,7 +737,8 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
         sgw_solver_free(s);
         return rc;
     }
-    s->grid = stage_grid(p->cfg.precision, p->pb.dim, p->stage_lds, p->cfg.blocks_per_cu);
+    s->grid = p->lds_boxed ? stage_grid(p->cfg.precision, p->pb.dim, p->lds_boxed, p->cfg.blocks_per_cu) : 1;
+    s->grid_whole = p->lds_whole ? stage_grid(p->cfg.precision, p->pb.dim, p->lds_whole, p->cfg.blocks_per_cu, true) : 1;
     *out = s;
     return SGW_OK;
 }
@@ -844,18 +854,24 @@ static hipError_t enqueue_step(sgw_solver* s, int mode, hipStream_t st)
     const sgw_plan* p = s->plan;
     hipError_t e = launch_dt_one(s->req_d, st);
     if (e != hipSuccess) return e;
-    const int cap = s->grid;
-    for (int stage = 0; stage < 3; stage++) {
-        if (mode == SGW_RUN_PLAIN) {
+    if (mode == SGW_RUN_PLAIN) {
+        for (int stage = 0; stage < 3; stage++)
             for (int g = 0; g < p->G; g++) {
                 e = launch_stage(s->items_d + p->grids[g].first_item, p->grids[g].nbox, stage, p->cfg.precision,
                                  p->pb.dim, stage_lds_bytes(p->grids[g], p->cfg.precision), 0, st);
                 if (e != hipSuccess) return e;
             }
-        } else {
-            e = launch_stage(s->items_d, (int)p->nitems, stage, p->cfg.precision, p->pb.dim, p->stage_lds, cap, st);
-            if (e != hipSuccess) return e;
-        }
+        return hipSuccess;
+    }
+    // grids that are one box: all three stages in one launch; the others stage by stage
+    const int nw = (int)p->nitems_whole, nbx = (int)(p->nitems - p->nitems_whole);
+    if (nw) {
+        e = launch_stage(s->items_d, nw, SGW_STAGE_FUSED, p->cfg.precision, p->pb.dim, p->lds_whole, s->grid_whole, st);
+        if (e != hipSuccess) return e;
+    }
+    for (int stage = 0; stage < 3 && nbx; stage++) {
+        e = launch_stage(s->items_d + nw, nbx, stage, p->cfg.precision, p->pb.dim, p->lds_boxed, s->grid, st);
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }

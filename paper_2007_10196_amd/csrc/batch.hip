@@ -1,10 +1,11 @@
 // Batched runtime of libsgweno: many solves (any dimension, level and final
 // time, one precision) advance together.  A time step is the time-step kernel
-// for every slot, then the three TVD-RK3 stages,
-// each one persistent launch per dimension present over the boxes of every
-// admitted solve of that dimension.  The box list, grouped by dimension, and
-// each dimension's range of it live in device memory, so admitting or releasing
-// a solve is a stream-ordered copy and the graph stays valid.  Two graphs are
+// for every slot, then per dimension present one persistent launch that runs
+// all three TVD-RK3 stages of the grids that are one stage box, and three
+// persistent launches, one per stage, over the boxes of the other grids.  The
+// box list, grouped by dimension and kind, and the ranges of it live in device
+// memory, so admitting or releasing a solve is a stream-ordered copy and the
+// graph stays valid.  Two graphs are
 // captured: one step, and SGW_GRAPH_STEPS steps in a row (each graph launch
 // costs the device a gap of several microseconds, as long as a small stage).
 #include <cmath>
@@ -23,7 +24,7 @@ struct sgw_batch {
     int64_t max_items = 0;
     ReqDev** reqs_d = nullptr;      // [max_solvers], null for a free slot
     WorkItem* items_d = nullptr;    // [max_items], grouped by dimension
-    int* ranges_d = nullptr;        // [8]: (offset, count) in items_d of the boxes of dimension 1..4
+    int* ranges_d = nullptr;        // ranges_h on the device
     int* flags_d = nullptr;         // [max_solvers]
     double* tf_d = nullptr;         // [max_solvers] final times of new slots (NaN: unchanged)
     int* flags_pinned = nullptr;
@@ -39,10 +40,12 @@ struct sgw_batch {
     bool queued = false;            // step launches may still be in flight on the stream
     std::vector<WorkItem> items_h;
     int nitems_h = 0;
-    int ranges_h[8] = {};
+    // (offset, count) in the box list, [kind][dimension - 1]: kind 0 the grids that are one
+    // box (three-stage launch), 1 the boxes of the other grids, 2 both (contiguous)
+    int ranges_h[3][4][2] = {};
     bool dirty = true;
-    size_t lds[4] = {};             // LDS of the captured stage launch of each dimension (0: not captured)
-    int blocks[4] = {};
+    size_t lds[2][4] = {};          // LDS of the captured launches, [kind][dimension - 1] (0: not captured)
+    int blocks[2][4] = {};
     int blocks_per_cu = 0;          // cap on resident stage workgroups per CU (0: occupancy)
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -139,26 +142,70 @@ static uint64_t solver_bytes(const sgw_solver* s)
     return s->plan->state_bytes + s->plan->scratch_bytes + (uint64_t)s->plan->fine_nodes * sizeof(double);
 }
 
-// Re-upload the box list and the slot table; recapture the step graph only when
-// a solve of a dimension not yet captured arrives, or an admitted grid needs more
-// LDS than the captured launch of its dimension provides.  Captured dimensions
-// stay in the graph (an empty range costs one launch whose workgroups exit).
+// The stage launches of one step (stage < 0): for every captured dimension, the three-stage
+// launch over its one-box grids, then stage by stage the launches over the boxes of the
+// other grids.  stage 0..2: that stage alone over all boxes (the split kernel, every box);
+// SGW_STAGE_FUSED: the launches of a step over the current lists, captured or not.
+static hipError_t enqueue_stages(sgw_batch* b, int stage, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    const bool step = stage < 0 || stage == SGW_STAGE_FUSED;
+    if (!step) {
+        for (int d = 0; d < 4 && e == hipSuccess; d++) {
+            if (!b->ranges_h[2][d][1]) continue;
+            const size_t l = b->lds[0][d] > b->lds[1][d] ? b->lds[0][d] : b->lds[1][d];
+            e = launch_stage_range(b->items_d, b->ranges_d + (2 * 4 + d) * 2,
+                                   stage_grid(b->precision, d + 1, l, b->blocks_per_cu), stage, b->precision, d + 1, l,
+                                   st);
+        }
+        return e;
+    }
+    // a captured graph keeps every launch it was built with; a direct call skips empty ranges
+    const bool all = stage < 0;
+    for (int d = 0; d < 4 && e == hipSuccess; d++)
+        if (b->lds[0][d] && (all || b->ranges_h[0][d][1]))
+            e = launch_stage_range(b->items_d, b->ranges_d + d * 2, b->blocks[0][d], SGW_STAGE_FUSED, b->precision,
+                                   d + 1, b->lds[0][d], st);
+    for (int s = 0; s < 3 && e == hipSuccess; s++)
+        for (int d = 0; d < 4 && e == hipSuccess; d++)
+            if (b->lds[1][d] && (all || b->ranges_h[1][d][1]))
+                e = launch_stage_range(b->items_d, b->ranges_d + (4 + d) * 2, b->blocks[1][d], s, b->precision, d + 1,
+                                       b->lds[1][d], st);
+    return e;
+}
+
+// Re-upload the box list and the slot table; recapture the step graphs only when
+// a solve of a kind of launch (dimension; one-box grids or not) not yet captured
+// arrives, or an admitted grid needs more LDS than the captured launch provides.
+// Captured launches stay in the graph (an empty range costs one launch whose
+// workgroups exit).
 static sgw_status batch_sync(sgw_batch* b)
 {
     if (!b->dirty) return SGW_OK;
     b->items_h.clear();
-    size_t lds[4] = {};
+    size_t lds[2][4] = {};
     for (int d = 1; d <= 4; d++) {
-        b->ranges_h[2 * (d - 1)] = (int)b->items_h.size();
-        for (int i = 0; i < b->max_solvers; i++) {
-            sgw_solver* s = b->slots[i];
-            if (!s || s->plan->pb.dim != d) continue;
-            if ((int64_t)(b->items_h.size() + s->items_h.size()) > b->max_items)
-                return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "batch box list full");
-            b->items_h.insert(b->items_h.end(), s->items_h.begin(), s->items_h.end());
-            lds[d - 1] = s->plan->stage_lds > lds[d - 1] ? s->plan->stage_lds : lds[d - 1];
+        const size_t d_begin = b->items_h.size();
+        for (int kind = 0; kind < 2; kind++) {
+            b->ranges_h[kind][d - 1][0] = (int)b->items_h.size();
+            for (int i = 0; i < b->max_solvers; i++) {
+                sgw_solver* s = b->slots[i];
+                if (!s || s->plan->pb.dim != d) continue;
+                const sgw_plan* p = s->plan;
+                // a solver's list holds its one-box grids first
+                const size_t lo = kind == 0 ? 0 : (size_t)p->nitems_whole;
+                const size_t hi = kind == 0 ? (size_t)p->nitems_whole : (size_t)p->nitems;
+                if (hi == lo) continue;
+                if ((int64_t)(b->items_h.size() + (hi - lo)) > b->max_items)
+                    return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "batch box list full");
+                b->items_h.insert(b->items_h.end(), s->items_h.begin() + lo, s->items_h.begin() + hi);
+                const size_t l = kind == 0 ? p->lds_whole : p->lds_boxed;
+                lds[kind][d - 1] = l > lds[kind][d - 1] ? l : lds[kind][d - 1];
+            }
+            b->ranges_h[kind][d - 1][1] = (int)b->items_h.size() - b->ranges_h[kind][d - 1][0];
         }
-        b->ranges_h[2 * (d - 1) + 1] = (int)b->items_h.size() - b->ranges_h[2 * (d - 1)];
+        b->ranges_h[2][d - 1][0] = (int)d_begin;
+        b->ranges_h[2][d - 1][1] = (int)(b->items_h.size() - d_begin);
     }
     b->nitems_h = (int)b->items_h.size();
     // the lists go through a pinned staging buffer: the uploads are stream-ordered
@@ -187,7 +234,8 @@ static sgw_status batch_sync(sgw_batch* b)
         b->tf_pending = false;
     }
     bool recapture = !b->exec || !b->exec_n;
-    for (int d = 0; d < 4; d++) recapture |= lds[d] > b->lds[d];
+    for (int k = 0; k < 2; k++)
+        for (int d = 0; d < 4; d++) recapture |= lds[k][d] > b->lds[k][d];
     if (recapture) {
         // queued launches of the old graphs may still run: wait before they are destroyed
         if (b->queued) {
@@ -196,10 +244,12 @@ static sgw_status batch_sync(sgw_batch* b)
             b->queued = false;
         }
         batch_drop_graph(b);
-        for (int d = 0; d < 4; d++) {
-            b->lds[d] = lds[d] > b->lds[d] ? lds[d] : b->lds[d];
-            b->blocks[d] = b->lds[d] ? stage_grid(b->precision, d + 1, b->lds[d], b->blocks_per_cu) : 0;
-        }
+        for (int k = 0; k < 2; k++)
+            for (int d = 0; d < 4; d++) {
+                b->lds[k][d] = lds[k][d] > b->lds[k][d] ? lds[k][d] : b->lds[k][d];
+                b->blocks[k][d] =
+                    b->lds[k][d] ? stage_grid(b->precision, d + 1, b->lds[k][d], b->blocks_per_cu, k == 0) : 0;
+            }
         e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
         if (e != hipSuccess) return sgw_hip_fail(e, "capture stream");
         for (int which = 0; which < 2; which++) {
@@ -209,11 +259,7 @@ static sgw_status batch_sync(sgw_batch* b)
             hipError_t el = hipSuccess;
             for (int step = 0; step < nsteps && el == hipSuccess; step++) {
                 el = launch_dt(b->reqs_d, b->max_solvers, b->cap);
-                for (int st = 0; st < 3 && el == hipSuccess; st++)
-                    for (int d = 0; d < 4 && el == hipSuccess; d++)
-                        if (b->lds[d])
-                            el = launch_stage_range(b->items_d, b->ranges_d + 2 * d, b->blocks[d], st, b->precision,
-                                                    d + 1, b->lds[d], b->cap);
+                if (el == hipSuccess) el = enqueue_stages(b, -1, b->cap);
             }
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(b->cap, &g);
@@ -340,17 +386,15 @@ extern "C" sgw_status sgw_batch_poll(sgw_batch_t* b, int32_t* done_slots, int32_
 extern "C" sgw_status sgw_batch_launch_stage(sgw_batch_t* b, int32_t stage, int32_t reps)
 {
     if (!b) return sgw_fail(SGW_ERR_INVALID_ARG, "null batch");
-    if (stage < 0 || stage > 2 || reps < 0) return sgw_fail(SGW_ERR_INVALID_ARG, "stage %d reps %d", stage, reps);
+    if (stage < 0 || stage > SGW_STAGE_FUSED || reps < 0)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "stage %d reps %d", stage, reps);
     sgw_status rc = batch_sync(b);
     if (rc != SGW_OK) return rc;
-    for (int i = 0; i < reps; i++)
-        for (int d = 0; d < 4; d++) {
-            if (!b->ranges_h[2 * d + 1]) continue;
-            b->queued = true;
-            hipError_t e = launch_stage_range(b->items_d, b->ranges_d + 2 * d, b->blocks[d], stage, b->precision, d + 1,
-                                              b->lds[d], b->stream);
-            if (e != hipSuccess) return sgw_hip_fail(e, "stage launch");
-        }
+    for (int i = 0; i < reps; i++) {
+        b->queued = true;
+        hipError_t e = enqueue_stages(b, stage, b->stream);
+        if (e != hipSuccess) return sgw_hip_fail(e, "stage launch");
+    }
     return SGW_OK;
 }
 
@@ -405,7 +449,8 @@ extern "C" sgw_status sgw_batch_set_blocks_per_cu(sgw_batch_t* b, int32_t blocks
         b->queued = false;
     }
     batch_drop_graph(b);
-    for (int d = 0; d < 4; d++) b->lds[d] = 0;
+    for (int k = 0; k < 2; k++)
+        for (int d = 0; d < 4; d++) b->lds[k][d] = 0;
     b->blocks_per_cu = blocks_per_cu;
     b->dirty = true;
     return SGW_OK;

@@ -134,11 +134,15 @@ __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real 
     }
 }
 
-template <typename Real, int D>
-__device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su, Real* sf)
+// One RK stage of one box (FUSED = false), or all three stages of a box that is its
+// whole grid (FUSED = true): the stage results stay in LDS, u^n is read once and u^{n+1}
+// written once, and the wave speed of each stage input is a workgroup maximum.  red holds
+// one double per wavefront.
+template <typename Real, int D, bool FUSED>
+__device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su, Real* sf, double* red)
 {
     constexpr int SEG = sgw_seg(D);
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
     const double dt = ((const SGW_CONST ReqDev*)g->req)->dt;
     const Real dtr = (Real)dt;
 
@@ -151,12 +155,12 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
             r = q;
         }
     }
-    const Real* __restrict__ in = (const Real*)(stage == 0 ? g->u : stage == 1 ? g->a : g->b);
-    Real* __restrict__ out = (Real*)(stage == 0 ? g->a : stage == 1 ? g->b : g->u);
+    const Real* __restrict__ in = (const Real*)(FUSED || stage == 0 ? g->u : stage == 1 ? g->a : g->b);
+    Real* __restrict__ out = (Real*)(FUSED || stage == 2 ? g->u : stage == 0 ? g->a : g->b);
     const Real* __restrict__ u0 = (const Real*)g->u;
 
     // the wave-speed slot the next stage reads is cleared by the stage before it
-    if (g->dyn_alpha && box == 0 && tid == 0) g->alpha[(stage + 2) % 3] = 0ull;
+    if (!FUSED && g->dyn_alpha && box == 0 && tid == 0) g->alpha[(stage + 2) % 3] = 0ull;
 
     const int core_total = g->core_total;
     const int t0 = g->t[0];
@@ -167,8 +171,8 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
     // t_0 values and column c0.  When t_0 divides the block size all of them share the column
     // and the row advances by rline per r.
     const int rline = g->rline;
-    const uint32_t l00 = FDIV((uint32_t)tid, g->fd_t[0]);
-    const int c00 = tid - M24((int)l00, t0);
+    uint32_t l00 = FDIV((uint32_t)tid, g->fd_t[0]);
+    int c00 = tid - M24((int)l00, t0);
     auto node_rc = [&](int r, int& line, int& c0) {
         if (rline) {
             line = (int)l00 + r * rline;
@@ -304,15 +308,29 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
     }
     __syncthreads();
 
-    Real acc[SGW_MAXR];
-#pragma unroll
-    for (int r = 0; r < SGW_MAXR; r++) acc[r] = Real(0);
-
     const Real epsT = (Real)(g->eps * (12.0 / 13.0));
     const int linear = g->linear;
     const bool burgers = g->flux == SGW_FLUX_BURGERS;
     Real dyn_alpha = Real(0);
-    if (g->dyn_alpha) dyn_alpha = (Real)__longlong_as_double((long long)g->alpha[stage]);
+    if (g->dyn_alpha) dyn_alpha = (Real)__longlong_as_double((long long)g->alpha[FUSED ? 0 : stage]);
+    // the fused launch keeps the split stages' invariant between steps: slot 0 holds
+    // max |u^n|, slots 1 and 2 are zero
+    if (FUSED && g->dyn_alpha && tid == 0) {
+        g->alpha[1] = 0ull;
+        g->alpha[2] = 0ull;
+    }
+
+    const int s_first = FUSED ? 0 : stage, s_last = FUSED ? 2 : stage;
+#pragma unroll 1
+    for (int s = s_first; s <= s_last; s++) {
+    if (FUSED) {
+        // the node indices are recomputed in every stage rather than kept live across the
+        // three (an empty asm hides their invariance from the compiler)
+        asm volatile("" : "+v"(tid), "+v"(l00), "+v"(c00));
+    }
+    Real acc[SGW_MAXR];
+#pragma unroll
+    for (int r = 0; r < SGW_MAXR; r++) acc[r] = Real(0);
 
 #pragma unroll
     for (int k = 0; k < D; k++) {
@@ -450,35 +468,67 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
             int line, c0;
             node_rc(r, line, c0);
             const int gi = node_gi(r, line, c0);
-            const Real val = fma(dtr, acc[r], su[c0 + M24(RS, line)]);
+            const int li = c0 + M24(RS, line);
+            const Real val = fma(dtr, acc[r], su[li]);
             Real res;
-            if (stage == 0) res = val;
-            else if (stage == 1) res = fma(Real(0.75), u0[gi], Real(0.25) * val);
+            if (s == 0) res = val;
+            else if (s == 1) res = fma(Real(0.75), u0[gi], Real(0.25) * val);
             else res = fma(Real(1.0 / 3.0), u0[gi], Real(2.0 / 3.0) * val);
-            out[gi] = res;
+            // the fused launch keeps the first two stage results in LDS (each thread
+            // rewrites its own nodes; every flux read of this stage is behind a barrier)
+            if (FUSED && s < 2)
+                su[li] = res;
+            else
+                out[gi] = res;
             const Real ar = fabs(res);
             amax = (ar > amax || ar != ar) ? ar : amax;
         }
     }
-    // one atomic max per wavefront on the bit pattern (order-free, no barrier)
-    if (g->dyn_alpha) {
+    if (!FUSED) {
+        // one atomic max per wavefront on the bit pattern (order-free, no barrier)
+        if (g->dyn_alpha) {
+            const double m = wave_max((double)amax);
+            if ((tid & 63) == 0) atomicMax(g->alpha + (stage + 1) % 3, (unsigned long long)__double_as_longlong(m));
+        }
+    } else if (g->dyn_alpha) {
+        // the box is the grid: the wave speed of the next stage is the workgroup maximum
+        // (the same value the split stages reach with atomics)
         const double m = wave_max((double)amax);
-        if ((tid & 63) == 0) atomicMax(g->alpha + (stage + 1) % 3, (unsigned long long)__double_as_longlong(m));
+        if ((tid & 63) == 0) red[tid >> 6] = m;
+        __syncthreads();
+        double mall = red[0];
+#pragma unroll
+        for (int w = 1; w < SGW_BLOCK / 64; w++) mall = nanmax(mall, red[w]);
+        // the same in every lane: keep it in scalar registers
+        const long long mb = __double_as_longlong(mall);
+        mall = __longlong_as_double(
+            (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(mb >> 32)) << 32) |
+                        (unsigned)__builtin_amdgcn_readfirstlane((int)mb)));
+        if (s < 2)
+            dyn_alpha = (Real)mall;
+        else if (tid == 0)
+            g->alpha[0] = (unsigned long long)__double_as_longlong(mall);
+    } else if (s < 2) {
+        __syncthreads();
+    }
     }
 }
 
-// One kernel per precision and dimension, so each gets its own registers and code size.
-template <typename Real, int D>
-__global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __restrict__ items, int nitems,
+// One kernel per precision and dimension, so each gets its own registers and code size;
+// FUSED: the three RK stages of whole-grid boxes in one launch.
+template <typename Real, int D, bool FUSED>
+__global__ void __launch_bounds__(SGW_BLOCK)
+stage_kernel(const WorkItem* __restrict__ items, int nitems,
                                                           const int* __restrict__ range_dev, int stage)
 {
-    // a batch keeps this dimension's range of its box list (offset, count) in device memory,
-    // so a captured graph stays valid as solves come and go
+    // a batch keeps its box list ranges (offset, count) in device memory, so a captured
+    // graph stays valid as solves come and go
     if (range_dev) {
         items += range_dev[0];
         nitems = range_dev[1];
     }
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[SGW_BLOCK / 64];
     // XCD-aware order: consecutive workgroup ids land on different XCDs, so hand
     // each XCD a contiguous run of boxes (neighbouring boxes share halo lines in L2).
     // Each workgroup takes a contiguous range of floor or ceil(nitems / nb) boxes,
@@ -497,51 +547,60 @@ __global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __rest
         const size_t su_elems = (size_t)g->pad_total;
         Real* su = (Real*)smem;
         Real* sf = su + ((su_elems + 1) & ~(size_t)1);
-        stage_box<Real, D>(g, ibox, stage, su, sf);
+        stage_box<Real, D, FUSED>(g, ibox, stage, su, sf, red);
         __syncthreads();
     }
 }
 
-template <typename Real, int D>
+template <typename Real, int D, bool FUSED>
 int occupancy_d(size_t lds_bytes)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_kernel<Real, D>, SGW_BLOCK, lds_bytes) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_kernel<Real, D, FUSED>, SGW_BLOCK, lds_bytes) !=
+            hipSuccess ||
         nb < 1)
         nb = 1;
     return nb;
 }
 
-template <typename Real>
+template <typename Real, bool FUSED>
 int occupancy_r(int dim, size_t lds_bytes)
 {
     switch (dim) {
-    case 1: return occupancy_d<Real, 1>(lds_bytes);
-    case 2: return occupancy_d<Real, 2>(lds_bytes);
-    case 3: return occupancy_d<Real, 3>(lds_bytes);
-    default: return occupancy_d<Real, 4>(lds_bytes);
+    case 1: return occupancy_d<Real, 1, FUSED>(lds_bytes);
+    case 2: return occupancy_d<Real, 2, FUSED>(lds_bytes);
+    case 3: return occupancy_d<Real, 3, FUSED>(lds_bytes);
+    default: return occupancy_d<Real, 4, FUSED>(lds_bytes);
     }
 }
 
-template <typename Real, int D>
+template <typename Real, int D, bool FUSED>
 hipError_t launch_d(const WorkItem* items, int nitems, const int* range_dev, int blocks, int stage, size_t lds,
                     hipStream_t s)
 {
-    hipLaunchKernelGGL((stage_kernel<Real, D>), dim3(blocks), dim3(SGW_BLOCK), lds, s, items, nitems, range_dev,
-                       stage);
+    hipLaunchKernelGGL((stage_kernel<Real, D, FUSED>), dim3(blocks), dim3(SGW_BLOCK), lds, s, items, nitems,
+                       range_dev, stage);
     return hipGetLastError();
+}
+
+template <typename Real, bool FUSED>
+hipError_t launch_f(int dim, const WorkItem* items, int nitems, const int* range_dev, int blocks, int stage,
+                    size_t lds, hipStream_t s)
+{
+    switch (dim) {
+    case 1: return launch_d<Real, 1, FUSED>(items, nitems, range_dev, blocks, stage, lds, s);
+    case 2: return launch_d<Real, 2, FUSED>(items, nitems, range_dev, blocks, stage, lds, s);
+    case 3: return launch_d<Real, 3, FUSED>(items, nitems, range_dev, blocks, stage, lds, s);
+    default: return launch_d<Real, 4, FUSED>(items, nitems, range_dev, blocks, stage, lds, s);
+    }
 }
 
 template <typename Real>
 hipError_t launch_r(int dim, const WorkItem* items, int nitems, const int* range_dev, int blocks, int stage,
                     size_t lds, hipStream_t s)
 {
-    switch (dim) {
-    case 1: return launch_d<Real, 1>(items, nitems, range_dev, blocks, stage, lds, s);
-    case 2: return launch_d<Real, 2>(items, nitems, range_dev, blocks, stage, lds, s);
-    case 3: return launch_d<Real, 3>(items, nitems, range_dev, blocks, stage, lds, s);
-    default: return launch_d<Real, 4>(items, nitems, range_dev, blocks, stage, lds, s);
-    }
+    if (stage == SGW_STAGE_FUSED) return launch_f<Real, true>(dim, items, nitems, range_dev, blocks, stage, lds, s);
+    return launch_f<Real, false>(dim, items, nitems, range_dev, blocks, stage, lds, s);
 }
 
 } // namespace
@@ -566,16 +625,19 @@ int device_cus()
     return n;
 }
 
-int stage_grid(int precision, int dim, size_t lds_bytes, int blocks_per_cu)
+int stage_grid(int precision, int dim, size_t lds_bytes, int blocks_per_cu, bool fused)
 {
-    int occ = stage_occupancy(precision, dim, lds_bytes);
+    int occ = stage_occupancy(precision, dim, lds_bytes, fused);
     if (blocks_per_cu > 0 && blocks_per_cu < occ) occ = blocks_per_cu;
     return occ * device_cus();
 }
 
-int stage_occupancy(int precision, int dim, size_t lds_bytes)
+int stage_occupancy(int precision, int dim, size_t lds_bytes, bool fused)
 {
-    return precision == SGW_FP64 ? occupancy_r<double>(dim, lds_bytes) : occupancy_r<float>(dim, lds_bytes);
+    if (fused)
+        return precision == SGW_FP64 ? occupancy_r<double, true>(dim, lds_bytes)
+                                     : occupancy_r<float, true>(dim, lds_bytes);
+    return precision == SGW_FP64 ? occupancy_r<double, false>(dim, lds_bytes) : occupancy_r<float, false>(dim, lds_bytes);
 }
 
 hipError_t launch_stage(const WorkItem* items, int nitems, int stage, int precision, int dim, size_t lds_bytes,

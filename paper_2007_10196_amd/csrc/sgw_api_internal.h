@@ -14,7 +14,9 @@ struct sgw_plan {
     int64_t fine_nodes = 0;
     int64_t total_nodes = 0;
     int64_t nitems = 0;                        // stage boxes over all grids
+    int64_t nitems_whole = 0;                  // the first boxes of the list: grids that are one box
     size_t stage_lds = 0;                      // max LDS bytes of a box
+    size_t lds_whole = 0, lds_boxed = 0;       // the same over the one-box grids and over the others
     std::vector<std::array<int, 4>> levels;
     std::vector<int> coefs;
     std::vector<int64_t> offsets;              // element offset of each grid in a state copy
@@ -52,6 +54,7 @@ struct sgw_solver {
     bool restricted = false;
     double t_host = 0.0;
     int grid = 1;                              // workgroups of a persistent stage launch
+    int grid_whole = 1;                        // the same for the three-stage launch of one-box grids
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;

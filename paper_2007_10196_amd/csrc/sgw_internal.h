@@ -10,6 +10,7 @@
 #define SGW_BLOCK 256     // threads per workgroup of every kernel (4 wave64)
 #define SGW_MAXR 8        // nodes per thread in the stage kernel: box core <= SGW_BLOCK * SGW_MAXR
 #define SGW_NPART 1024    // most workgroups of the first norm pass (their count depends on n only)
+#define SGW_STAGE_FUSED 3 // stage index of the launch that runs all three stages of whole-grid boxes
 #define SGW_SEG 4         // interfaces per thread of the flux sweep (sliding window), d <= 3
 
 // Interfaces per thread of the flux sweep of a d-dimensional grid.  4D boxes are short
@@ -228,7 +229,8 @@ hipError_t launch_restrict_many(const ResetItem* resets, int nresets, const Rest
                                 int precision, hipStream_t s);
 hipError_t launch_dt(ReqDev* const* reqs, int nreq, hipStream_t s);
 hipError_t launch_dt_one(ReqDev* req, hipStream_t s);
-// stage kernel of dimension dim over items[0..nitems); grid_cap caps the persistent grid
+// stage kernel of dimension dim over items[0..nitems); grid_cap caps the persistent grid.
+// stage SGW_STAGE_FUSED: the three stages of whole-grid boxes in one launch.
 hipError_t launch_stage(const WorkItem* items, int nitems, int stage, int precision, int dim, size_t lds_bytes,
                         int grid_cap, hipStream_t s);
 // the same over items[range_dev[0] .. + range_dev[1]) read on the device (batches, graphs)
@@ -236,8 +238,9 @@ hipError_t launch_stage_range(const WorkItem* items, const int* range_dev, int b
                               int dim, size_t lds_bytes, hipStream_t s);
 hipError_t launch_gather_done(ReqDev* const* reqs, int nreq, int* flags, hipStream_t s);
 size_t stage_lds_bytes(const GridDev& g, int precision);
-int stage_occupancy(int precision, int dim, size_t lds_bytes);
-int stage_grid(int precision, int dim, size_t lds_bytes, int blocks_per_cu);  // persistent grid: blocks per CU x CUs
+int stage_occupancy(int precision, int dim, size_t lds_bytes, bool fused = false);
+// persistent grid: blocks per CU x CUs
+int stage_grid(int precision, int dim, size_t lds_bytes, int blocks_per_cu, bool fused = false);
 hipError_t launch_prolong(const ProDev* pro_dev, const FineDev* fine_dev, const FineDev& fine_host,
                           int precision, size_t lds_bytes, double* out, hipStream_t s);
 hipError_t launch_prolong_many(const ProItem* items, int nitems, int d, int precision, size_t lds_bytes,

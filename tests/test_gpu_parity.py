@@ -456,6 +456,28 @@ def test_launch_shape_does_not_change_results(prec):
     assert not bad, bad
 
 
+@pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_FP32])
+def test_three_stage_launch_equals_split_stages_bitwise(prec):
+    """Grids that are one stage box run all three RK stages in one launch (results kept in
+    LDS, wave speeds as workgroup maxima); the per-grid split launches of the plain mode give
+    the same bits, with and without state-dependent wave speeds, and with a mix of one-box
+    and many-box grids in one solve."""
+    cases = [W.c2_burgers_2d(nl=4, T=0.05), W.c1_advection_2d(nl=4).replace(T=0.05),
+             W.c3_advection_3d(nr=6, nl=2, T=0.05).replace(flux=W.FLUX_BURGERS, flux_params=(),
+                                                          ic_params=(0.3, 0.6, math.pi, 0.4)),
+             W.c4_vlasov_4d(nr=4, nl=2, T=0.05)]
+    for pb in cases:
+        pb = pb.replace(precision=prec)
+        for target in (512, 2048):
+            _announce(f"three-stage vs split {pb.name} d={pb.d} prec={prec} target={target}")
+            s_plain, _, u_plain, _, n_plain = gpu_solve(pb, mode=0, box_target=target)
+            s_graph, _, u_graph, _, n_graph = gpu_solve(pb, mode=2, box_target=target)
+            assert n_plain == n_graph
+            assert bool((u_plain == u_graph).all()), (pb.name, target)
+            for s in (s_plain, s_graph):
+                s.close()
+
+
 def test_set_grid_equals_restriction_bitwise():
     """Caller-sampled initial values through sgw_set_grid give the same solve as sgw_restrict_initial."""
     torch, B, Solver, _ = _lib()
