@@ -336,6 +336,7 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
     for (int k = 0; k < D; k++) {
         const int hf = g->halo[k] ? 1 : 0;
         const int tk = g->t[k];
+        const bool pow2 = (tk & (tk - 1)) == 0;
         const int CSk = g->CS[k];
         const int LSk = (k == 0) ? 1 : g->LS[k];
         const int Ik = g->I[k];
@@ -399,6 +400,11 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
                     const int bs = p < 0 ? blo : base_core;
                     v[q] = su[(p >= tk ? bhi : bs) + M24(p, LSk)];
                 }
+            } else if (pow2) {
+                // the box spans the grid and t is a power of two: the periodic wrap is a mask
+                // (window positions run from -2 up, two's complement wraps them)
+#pragma unroll
+                for (int q = 0; q < SEG + 5; q++) v[q] = su[base_core + M24((i0 + q - 2) & (tk - 1), LSk)];
             } else {
 #pragma unroll
                 for (int q = 0; q < SEG + 5; q++) {
@@ -517,8 +523,7 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
 // One kernel per precision and dimension, so each gets its own registers and code size;
 // FUSED: the three RK stages of whole-grid boxes in one launch.
 template <typename Real, int D, bool FUSED>
-__global__ void __launch_bounds__(SGW_BLOCK)
-stage_kernel(const WorkItem* __restrict__ items, int nitems,
+__global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __restrict__ items, int nitems,
                                                           const int* __restrict__ range_dev, int stage)
 {
     // a batch keeps its box list ranges (offset, count) in device memory, so a captured
