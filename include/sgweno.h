@@ -190,9 +190,9 @@ sgw_status sgw_norms(sgw_solver_t* solver, const double* a_dev, const double* b_
 sgw_status sgw_norms_async(sgw_solver_t* solver, const double* a_dev, const double* b_dev, double* result_dev);
 
 /* Alg. Step 3 for many solves in one launch (one workgroup per finest-grid tile
- * of every solve; all solves share dimension and precision); outs[i] receives
- * solve i's combined solution.  scratch_dev (device, 256-byte aligned) holds
- * the tile list, sgw_prolongate_many_scratch_bytes(solvers, n) bytes.  Runs on
+ * of every solve; all solves share dimension and precision; n <= 65535); outs[i]
+ * receives solve i's combined solution.  scratch_dev (device, 256-byte aligned)
+ * holds the solve list, sgw_prolongate_many_scratch_bytes(solvers, n) bytes.  Runs on
  * hip_stream after waiting for each solver's own stream that differs from it;
  * returns without waiting for the device (scratch_dev stays in use until the
  * launch has run in stream order). */

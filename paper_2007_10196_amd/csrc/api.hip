@@ -1037,10 +1037,7 @@ static int64_t fine_tiles(const sgw_solver* s)
 extern "C" uint64_t sgw_prolongate_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n)
 {
     if (!solvers || n <= 0) return 0;
-    int64_t tiles = 0;
-    for (int i = 0; i < n; i++)
-        if (solvers[i]) tiles += fine_tiles(solvers[i]);
-    return align256((uint64_t)tiles * sizeof(ProItem));
+    return align256((uint64_t)n * sizeof(ProItem));
 }
 
 extern "C" sgw_status sgw_prolongate_combine_many(sgw_solver_t* const* solvers, double* const* outs, int32_t n,
@@ -1050,8 +1047,9 @@ extern "C" sgw_status sgw_prolongate_combine_many(sgw_solver_t* const* solvers, 
     if ((uintptr_t)scratch_dev & 255) return sgw_fail(SGW_ERR_INVALID_ARG, "scratch must be 256-byte aligned");
     const int d = solvers[0] ? solvers[0]->plan->pb.dim : 0;
     const int prec = solvers[0] ? solvers[0]->plan->cfg.precision : 0;
+    if (n > 65535) return sgw_fail(SGW_ERR_INVALID_ARG, "at most 65535 solves per call, %d given", n);
     size_t lds = 0;
-    uint64_t nitems = 0;
+    int64_t max_tiles = 0;
     for (int i = 0; i < n; i++) {
         sgw_solver* s = solvers[i];
         if (!s || !outs[i]) return sgw_fail(SGW_ERR_INVALID_ARG, "null solver or output %d", i);
@@ -1060,27 +1058,24 @@ extern "C" sgw_status sgw_prolongate_combine_many(sgw_solver_t* const* solvers, 
             return sgw_fail(SGW_ERR_INVALID_ARG, "solvers of one call must share dimension and precision");
         const size_t l = 2 * (prec == SGW_FP64 ? 8 : 4) * s->plan->pro_buf_elems;
         lds = l > lds ? l : lds;
-        nitems += (uint64_t)fine_tiles(s);
+        const int64_t t = fine_tiles(s);
+        max_tiles = t > max_tiles ? t : max_tiles;
     }
-    if (nitems * sizeof(ProItem) > scratch_bytes)
-        return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "scratch holds %llu items, %llu needed",
-                        (unsigned long long)(scratch_bytes / sizeof(ProItem)), (unsigned long long)nitems);
-    if (nitems > 0x7fffffff) return sgw_fail(SGW_ERR_UNSUPPORTED, "too many tiles");
-    Staging stg(nitems * sizeof(ProItem));
+    if ((uint64_t)n * sizeof(ProItem) > scratch_bytes)
+        return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "scratch of %llu bytes, %llu needed", (unsigned long long)scratch_bytes,
+                        (unsigned long long)((uint64_t)n * sizeof(ProItem)));
+    if (max_tiles > 0x7fffffff) return sgw_fail(SGW_ERR_UNSUPPORTED, "too many tiles");
+    Staging stg((size_t)n * sizeof(ProItem));
     HIPCHK(stg.err, "staging buffer");
     ProItem* items = (ProItem*)stg.host;
-    uint64_t c = 0;
-    for (int i = 0; i < n; i++) {
-        sgw_solver* s = solvers[i];
-        const int64_t t = fine_tiles(s);
-        for (int64_t k = 0; k < t; k++) items[c++] = ProItem{s->pro_d, s->fine_d, outs[i], (int32_t)k, 0};
-    }
+    for (int i = 0; i < n; i++)
+        items[i] = ProItem{solvers[i]->pro_d, solvers[i]->fine_d, outs[i], (int32_t)fine_tiles(solvers[i]), 0};
     hipStream_t st = (hipStream_t)hip_stream;
     // every solver's own stream has finished the state the tiles read
     for (int i = 0; i < n; i++)
         if (solvers[i]->stream != st) HIPCHK(hipStreamSynchronize(solvers[i]->stream), "synchronise solver stream");
-    HIPCHK(stg.upload(0, scratch_dev, nitems * sizeof(ProItem), st), "upload tile list");
-    HIPCHK(launch_prolong_many((const ProItem*)scratch_dev, (int)nitems, d, prec, lds, st), "prolongate many");
+    HIPCHK(stg.upload(0, scratch_dev, (size_t)n * sizeof(ProItem), st), "upload solve list");
+    HIPCHK(launch_prolong_many((const ProItem*)scratch_dev, n, (int)max_tiles, d, prec, lds, st), "prolongate many");
     return SGW_OK;
 }
 

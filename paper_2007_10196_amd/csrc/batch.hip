@@ -33,6 +33,8 @@ struct sgw_batch {
     bool poll_inflight = false;
     std::vector<sgw_solver*> poll_slots; // occupants of the slots when the flags were gathered
     std::vector<sgw_solver*> slots;
+    int free_hint = 0;              // no free slot below this index
+    int64_t items_admitted = 0;     // boxes of the admitted solves
     std::vector<uint64_t> slot_bytes;
     std::vector<ReqDev*> reqs_h;
     std::vector<double> tf_h;
@@ -291,16 +293,15 @@ extern "C" sgw_status sgw_batch_admit(sgw_batch_t* b, sgw_solver_t* s, double t_
         return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "footprint %llu exceeds remaining budget %llu",
                         (unsigned long long)need, (unsigned long long)(b->budget - b->used));
     int free_slot = -1;
-    for (int i = 0; i < b->max_solvers; i++)
+    for (int i = b->free_hint; i < b->max_solvers; i++)
         if (!b->slots[i]) {
             free_slot = i;
             break;
         }
     if (free_slot < 0) return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "no free slot");
-    int64_t items = 0;
-    for (auto* o : b->slots)
-        if (o) items += (int64_t)o->items_h.size();
-    if (items + (int64_t)s->items_h.size() > b->max_items) return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "box list full");
+    b->free_hint = free_slot;
+    if (b->items_admitted + (int64_t)s->items_h.size() > b->max_items)
+        return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "box list full");
     // the solve's own work (restriction) is ordered before the batch's
     if (s->stream != b->stream) {
         hipError_t e = hipStreamSynchronize(s->stream);
@@ -310,6 +311,7 @@ extern "C" sgw_status sgw_batch_admit(sgw_batch_t* b, sgw_solver_t* s, double t_
     b->tf_h[free_slot] = t_final;
     b->tf_pending = true;
     b->slots[free_slot] = s;
+    b->items_admitted += (int64_t)s->items_h.size();
     b->slot_bytes[free_slot] = need;
     b->reqs_h[free_slot] = s->req_d;
     b->used += need;
@@ -427,6 +429,8 @@ extern "C" sgw_status sgw_batch_release(sgw_batch_t* b, int32_t slot)
         if (e != hipSuccess) return sgw_hip_fail(e, "order solver stream after batch");
     }
     s->batch_slot = -1;
+    b->items_admitted -= (int64_t)s->items_h.size();
+    if (slot < b->free_hint) b->free_hint = slot;
     b->tf_h[slot] = NAN;
     b->used -= b->slot_bytes[slot];
     b->slots[slot] = nullptr;

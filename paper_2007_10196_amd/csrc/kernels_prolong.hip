@@ -181,8 +181,9 @@ __global__ void __launch_bounds__(SGW_BLOCK) prolong_kernel(const ProDev* pro, c
 template <typename Real, int D>
 __global__ void __launch_bounds__(SGW_BLOCK) prolong_many_kernel(const ProItem* items)
 {
-    const SGW_CONST ProItem* it = (const SGW_CONST ProItem*)items + blockIdx.x;
-    prolong_tile<Real, D>((ProC)it->pro, (FineC)it->fine, it->out, it->tile);
+    const SGW_CONST ProItem* it = (const SGW_CONST ProItem*)items + blockIdx.y;
+    if ((int)blockIdx.x >= it->ntiles) return;
+    prolong_tile<Real, D>((ProC)it->pro, (FineC)it->fine, it->out, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------- exact solutions
@@ -394,12 +395,12 @@ hipError_t launch_prolong(const ProDev* pro_dev, const FineDev* fine_dev, const 
     return hipGetLastError();
 }
 
-hipError_t launch_prolong_many(const ProItem* items, int nitems, int d, int precision, size_t lds_bytes,
-                               hipStream_t s)
+hipError_t launch_prolong_many(const ProItem* items, int nitems, int max_tiles, int d, int precision,
+                               size_t lds_bytes, hipStream_t s)
 {
-    if (nitems <= 0) return hipSuccess;
+    if (nitems <= 0 || max_tiles <= 0) return hipSuccess;
 #define SGW_PROM(R, DD) \
-    hipLaunchKernelGGL((prolong_many_kernel<R, DD>), dim3(nitems), dim3(SGW_BLOCK), lds_bytes, s, items)
+    hipLaunchKernelGGL((prolong_many_kernel<R, DD>), dim3(max_tiles, nitems), dim3(SGW_BLOCK), lds_bytes, s, items)
     if (precision == SGW_FP64) {
         switch (d) {
         case 1: SGW_PROM(double, 1); break;

@@ -172,11 +172,13 @@ struct alignas(64) FineDev {
 };
 
 // One (solve, finest-grid tile) of a batched prolongation launch.
+// One solve of a prolongation over many solves: workgroup (x, y) takes finest-grid
+// tile x of solve y (x < ntiles).
 struct ProItem {
     const ProDev* pro;
     const FineDev* fine;
     double* out;
-    int32_t tile, pad;
+    int32_t ntiles, pad;
 };
 
 // One chunk of one component grid in a restriction over many solves.
@@ -243,8 +245,9 @@ int stage_occupancy(int precision, int dim, size_t lds_bytes, bool fused = false
 int stage_grid(int precision, int dim, size_t lds_bytes, int blocks_per_cu, bool fused = false);
 hipError_t launch_prolong(const ProDev* pro_dev, const FineDev* fine_dev, const FineDev& fine_host,
                           int precision, size_t lds_bytes, double* out, hipStream_t s);
-hipError_t launch_prolong_many(const ProItem* items, int nitems, int d, int precision, size_t lds_bytes,
-                               hipStream_t s);
+// items: one per solve (n <= 65535); max_tiles: the largest ntiles
+hipError_t launch_prolong_many(const ProItem* items, int nitems, int max_tiles, int d, int precision,
+                               size_t lds_bytes, hipStream_t s);
 hipError_t launch_exact(const ExactDev& e, double* out, double* foot_scratch, hipStream_t s);
 hipError_t launch_norms(const double* a, const double* b, int64_t n, double* partials, double* result,
                         hipStream_t s);
