@@ -263,8 +263,9 @@ sgw_status sgw_batch_admit(sgw_batch_t* batch, sgw_solver_t* solver, double t_fi
 sgw_status sgw_batch_admit_many(sgw_batch_t* batch, sgw_solver_t* const* solvers, int32_t n, const double* t_final,
                                 int32_t* slots, int32_t* n_admitted);
 /* Advance every active solver by up to nsteps steps (finished ones do nothing).
- * Enqueues graph launches on the batch stream and returns; runs of 8 steps go
- * in one launch of an 8-step graph. */
+ * Enqueues graph launches on the batch stream and returns: graphs of 1, 2, 4,
+ * ..., 32 steps are captured, and nsteps is launched as its binary
+ * decomposition. */
 sgw_status sgw_batch_step(sgw_batch_t* batch, int32_t nsteps);
 /* Which slots have reached their final time (synchronises).  done_slots has
  * room for max_solvers entries. */

@@ -5,9 +5,10 @@
 // persistent launches, one per stage, over the boxes of the other grids.  The
 // box list, grouped by dimension and kind, and the ranges of it live in device
 // memory, so admitting or releasing a solve is a stream-ordered copy and the
-// graph stays valid.  Two graphs are
-// captured: one step, and SGW_GRAPH_STEPS steps in a row (each graph launch
-// costs the device a gap of several microseconds, as long as a small stage).
+// graph stays valid.  Graphs of 1, 2, 4, ..., 2^(SGW_GRAPH_LEVELS-1) steps are
+// captured, and a request for n steps launches the binary decomposition of n
+// (each graph launch costs the device a gap of several microseconds, as long as
+// a small stage).
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -50,13 +51,11 @@ struct sgw_batch {
     int blocks[2][4] = {};
     int blocks_per_cu = 0;          // cap on resident stage workgroups per CU (0: occupancy)
     hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;      // one step
-    hipGraph_t graph_n = nullptr;
-    hipGraphExec_t exec_n = nullptr;    // SGW_GRAPH_STEPS steps
+    hipGraph_t graph[6] = {};           // graph[j]: 2^j steps
+    hipGraphExec_t exec[6] = {};
 };
 
-#define SGW_GRAPH_STEPS 8
+#define SGW_GRAPH_LEVELS 6
 
 static uint64_t a256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 
@@ -114,15 +113,13 @@ extern "C" sgw_status sgw_batch_create(int32_t max_solvers, int32_t precision, u
 
 static void batch_drop_graph(sgw_batch* b)
 {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    if (b->exec_n) (void)hipGraphExecDestroy(b->exec_n);
-    if (b->graph_n) (void)hipGraphDestroy(b->graph_n);
-    b->exec_n = nullptr;
-    b->graph_n = nullptr;
+    for (int j = 0; j < SGW_GRAPH_LEVELS; j++) {
+        if (b->exec[j]) (void)hipGraphExecDestroy(b->exec[j]);
+        if (b->graph[j]) (void)hipGraphDestroy(b->graph[j]);
+        b->exec[j] = nullptr;
+        b->graph[j] = nullptr;
+    }
     if (b->cap) (void)hipStreamDestroy(b->cap);
-    b->exec = nullptr;
-    b->graph = nullptr;
     b->cap = nullptr;
 }
 
@@ -235,7 +232,8 @@ static sgw_status batch_sync(sgw_batch* b)
         for (double& t : b->tf_h) t = NAN;
         b->tf_pending = false;
     }
-    bool recapture = !b->exec || !b->exec_n;
+    bool recapture = false;
+    for (int j = 0; j < SGW_GRAPH_LEVELS; j++) recapture |= !b->exec[j];
     for (int k = 0; k < 2; k++)
         for (int d = 0; d < 4; d++) recapture |= lds[k][d] > b->lds[k][d];
     if (recapture) {
@@ -254,8 +252,8 @@ static sgw_status batch_sync(sgw_batch* b)
             }
         e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
         if (e != hipSuccess) return sgw_hip_fail(e, "capture stream");
-        for (int which = 0; which < 2; which++) {
-            const int nsteps = which ? SGW_GRAPH_STEPS : 1;
+        for (int which = 0; which < SGW_GRAPH_LEVELS; which++) {
+            const int nsteps = 1 << which;
             e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return sgw_hip_fail(e, "begin capture");
             hipError_t el = hipSuccess;
@@ -272,9 +270,9 @@ static sgw_status batch_sync(sgw_batch* b)
             if (e != hipSuccess) return sgw_hip_fail(e, "end capture");
             hipGraphExec_t x = nullptr;
             e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-            (which ? b->graph_n : b->graph) = g;
+            b->graph[which] = g;
             if (e != hipSuccess) return sgw_hip_fail(e, "instantiate batch graph");
-            (which ? b->exec_n : b->exec) = x;
+            b->exec[which] = x;
         }
     }
     b->dirty = false;
@@ -328,12 +326,13 @@ extern "C" sgw_status sgw_batch_step(sgw_batch_t* b, int32_t nsteps)
     sgw_status rc = batch_sync(b);
     if (rc != SGW_OK) return rc;
     if (!b->nitems_h) return SGW_OK;
-    for (int i = 0; i < nsteps;) {
-        const bool many = nsteps - i >= SGW_GRAPH_STEPS;
+    for (int left = nsteps; left > 0;) {
+        int j = SGW_GRAPH_LEVELS - 1;
+        while ((1 << j) > left) j--;
         b->queued = true;
-        hipError_t e = hipGraphLaunch(many ? b->exec_n : b->exec, b->stream);
+        hipError_t e = hipGraphLaunch(b->exec[j], b->stream);
         if (e != hipSuccess) return sgw_hip_fail(e, "batch graph launch");
-        i += many ? SGW_GRAPH_STEPS : 1;
+        left -= 1 << j;
     }
     return SGW_OK;
 }

@@ -174,15 +174,21 @@ __device__ void dt_wave(ReqDev* r)
         dt = r->dt_pow53;
     } else {
         double denom = 0.0;
-        for (int k = 0; k < r->d; k++) {
+        if (r->grids[0].dyn_alpha) {
+            // every grid of a solve has the same flux: one maximum of the state-dependent
+            // speeds serves all directions
             double A = 0.0;
-            for (int g = lane; g < r->ngrids; g += 64) {
-                const GridDev* gd = r->grids + g;
-                const double a = gd->dyn_alpha ? __longlong_as_double((long long)gd->alpha[0]) : gd->alpha_c[k];
-                A = nanmax(A, a);
-            }
+            for (int g = lane; g < r->ngrids; g += 64)
+                A = nanmax(A, __longlong_as_double((long long)r->grids[g].alpha[0]));
             A = wave_max(A);
-            denom += A / r->hfin[k];
+            for (int k = 0; k < r->d; k++) denom += A / r->hfin[k];
+        } else {
+            for (int k = 0; k < r->d; k++) {
+                double A = 0.0;
+                for (int g = lane; g < r->ngrids; g += 64) A = nanmax(A, r->grids[g].alpha_c[k]);
+                A = wave_max(A);
+                denom += A / r->hfin[k];
+            }
         }
         if (denom != denom || denom > 1.7e308) {
             if (lane == 0) {
