@@ -138,7 +138,9 @@ __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real 
 // whole grid (FUSED = true): the stage results stay in LDS, u^n is read once and u^{n+1}
 // written once, and the wave speed of each stage input is a workgroup maximum.  red holds
 // one double per wavefront.
-template <typename Real, int D, bool FUSED>
+// ROWS: t_1 divides the block size, so a thread's nodes share one column and step through
+// the rows by a fixed count (one variant per case, chosen once per box).
+template <typename Real, int D, bool FUSED, bool ROWS>
 __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su, Real* sf, double* red)
 {
     constexpr int SEG = sgw_seg(D);
@@ -174,7 +176,7 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
     uint32_t l00 = FDIV((uint32_t)tid, g->fd_t[0]);
     int c00 = tid - M24((int)l00, t0);
     auto node_rc = [&](int r, int& line, int& c0) {
-        if (rline) {
+        if (ROWS) {
             line = (int)l00 + r * rline;
             c0 = c00;
         } else {
@@ -552,7 +554,10 @@ __global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __rest
         const size_t su_elems = (size_t)g->pad_total;
         Real* su = (Real*)smem;
         Real* sf = su + ((su_elems + 1) & ~(size_t)1);
-        stage_box<Real, D, FUSED>(g, ibox, stage, su, sf, red);
+        if (g->rline)
+            stage_box<Real, D, FUSED, true>(g, ibox, stage, su, sf, red);
+        else
+            stage_box<Real, D, FUSED, false>(g, ibox, stage, su, sf, red);
         __syncthreads();
     }
 }
