@@ -633,6 +633,7 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
     s->req_h.d = d;
     s->req_h.dt_mode = p->cfg.dt_mode;
     s->req_h.grids = s->grids_d;
+    s->req_h.alpha = s->alpha_d;
     s->req_h.ngrids = p->G;
     s->req_h.dyn_alpha = dyn ? 1 : 0;
     s->req_h.active = 1;

@@ -174,12 +174,11 @@ __device__ void dt_wave(ReqDev* r)
         dt = r->dt_pow53;
     } else {
         double denom = 0.0;
-        if (r->grids[0].dyn_alpha) {
+        if (r->dyn_alpha) {
             // every grid of a solve has the same flux: one maximum of the state-dependent
             // speeds serves all directions
             double A = 0.0;
-            for (int g = lane; g < r->ngrids; g += 64)
-                A = nanmax(A, __longlong_as_double((long long)r->grids[g].alpha[0]));
+            for (int g = lane; g < r->ngrids; g += 64) A = nanmax(A, __longlong_as_double((long long)r->alpha[4 * g]));
             A = wave_max(A);
             for (int k = 0; k < r->d; k++) denom += A / r->hfin[k];
         } else {

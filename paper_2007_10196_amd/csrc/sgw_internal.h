@@ -136,6 +136,7 @@ struct alignas(64) ReqDev {
     double hfin[SGW_MAX_DIM];
     int64_t steps;
     const GridDev* grids;
+    const unsigned long long* alpha; // the solve's wave-speed slots, 4 per grid (slot 0: max |u^n|)
     int32_t ngrids, d, dt_mode, done;
     int32_t nonfinite, dyn_alpha, active, pad;
 };
