@@ -36,25 +36,29 @@ __device__ __forceinline__ double rdiv(double a, double b)
     return fma(fma(-b, q, a), r, q);
 }
 
-// P_r written about x_i: P_r(s) = c + s g_r + s^2 k_r with g_r, k_r the first and
-// second differences of substencil r; the integral of eq. (si) then equals
-// g_r^2 + (13/3) k_r^2, the Jiang-Shu quadratic forms of eq. (2.7.2).
+// P_r written about x_i: P_r(s) = c + s g_r + s^2 k_r, where 2 g_r is the (one-sided or
+// central) first difference of substencil r at x_i and 2 k_r its second difference; the
+// integral of eq. (si) then equals g_r^2 + (13/3) k_r^2, the Jiang-Shu quadratic forms of
+// eq. (2.7.2).  The code keeps G_r = 2 g_r and K_r = 2 k_r: P_r = c + (s/2)(G_r + s K_r),
+// and eps + beta_r = (eps4 + G_r^2 + 13/3 K_r^2) / 4 with eps4 = 4 eps, a factor common
+// to the three weights that their normalisation cancels.
 template <typename Real>
-__device__ __forceinline__ Real interp5(Real a, Real b, Real c, Real d, Real e, Real s, Real eps, int lagrange)
+__device__ __forceinline__ Real interp5(Real a, Real b, Real c, Real d, Real e, Real s, Real eps4, int lagrange)
 {
-    const Real g0 = Real(0.5) * (a - Real(4) * b + Real(3) * c), k0 = Real(0.5) * (a - Real(2) * b + c);
-    const Real g1 = Real(0.5) * (d - b), k1 = Real(0.5) * (b - Real(2) * c + d);
-    const Real g2 = Real(0.5) * (Real(-3) * c + Real(4) * d - e), k2 = Real(0.5) * (c - Real(2) * d + e);
-    const Real P0 = c + s * (g0 + s * k0);
-    const Real P1 = c + s * (g1 + s * k1);
-    const Real P2 = c + s * (g2 + s * k2);
+    const Real G0 = a - Real(4) * b + Real(3) * c, K0 = a - Real(2) * b + c;
+    const Real G1 = d - b, K1 = b - Real(2) * c + d;
+    const Real G2 = Real(-3) * c + Real(4) * d - e, K2 = c - Real(2) * d + e;
+    const Real h = Real(0.5) * s;
+    const Real P0 = c + h * (G0 + s * K0);
+    const Real P1 = c + h * (G1 + s * K1);
+    const Real P2 = c + h * (G2 + s * K2);
     const Real C0 = (s - Real(1)) * (s - Real(2)) * Real(1.0 / 12.0);
     const Real C1 = (Real(4) - s * s) * Real(1.0 / 6.0);
     const Real C2 = (s + Real(1)) * (s + Real(2)) * Real(1.0 / 12.0);
     if (lagrange) return C0 * P0 + C1 * P1 + C2 * P2;
-    Real e0 = eps + (g0 * g0 + Real(13.0 / 3.0) * k0 * k0);
-    Real e1 = eps + (g1 * g1 + Real(13.0 / 3.0) * k1 * k1);
-    Real e2 = eps + (g2 * g2 + Real(13.0 / 3.0) * k2 * k2);
+    Real e0 = eps4 + (G0 * G0 + Real(13.0 / 3.0) * K0 * K0);
+    Real e1 = eps4 + (G1 * G1 + Real(13.0 / 3.0) * K1 * K1);
+    Real e2 = eps4 + (G2 * G2 + Real(13.0 / 3.0) * K2 * K2);
     e0 *= e0;
     e1 *= e1;
     e2 *= e2;
@@ -77,7 +81,7 @@ __device__ __forceinline__ void prolong_tile(ProC pro, FineC F, double* __restri
         }
     }
     const int tile_points = F->tile_points;
-    const Real eps = (Real)F->eps;
+    const Real eps4 = (Real)(4.0 * F->eps);
     const int lagrange = F->lagrange;
     double acc[SGW_MAXRP];
 #pragma unroll
@@ -136,7 +140,7 @@ __device__ __forceinline__ void prolong_tile(ProC pro, FineC F, double* __restri
                 const uint32_t base = (uint32_t)(a + M24(inner, (li - 2) + M24(ck, (int)bq)));
                 const uint32_t st = (uint32_t)inner;
                 dst[o] = interp5<Real>(src[base], src[base + st], src[base + 2 * st], src[base + 3 * st],
-                                       src[base + 4 * st], s, eps, lagrange);
+                                       src[base + 4 * st], s, eps4, lagrange);
             }
             __syncthreads();
             Real* t = src;
