@@ -8,13 +8,17 @@
 // x_{i+1/2} is the WENO5 reconstruction of f^+ from (i-2..i+2) plus the mirror
 // reconstruction of f^- from (i+3..i-1) (eqs. 2.7, 2.7.1, 2.6, 2.7.2), and the
 // operator is the conservative difference of eq. (2.9), summed over k.  The
-// TVD-RK3 (Shu-Osher) stage combination is applied in the same pass.
+// TVD-RK3 (Shu-Osher) stage combination is applied in the same pass; a box that
+// is its whole grid runs all three stages in one launch.
 //
 // Layout: one workgroup owns a box of one component grid.  The box and a
 // 3-node halo in every direction where the box does not span the grid are
-// staged in LDS (periodic wrap applied while loading), one direction at a
-// time the interface fluxes of the box go to a second LDS array, and each
-// thread accumulates the flux differences of its nodes in registers.
+// staged in LDS (periodic wrap of the halo applied while loading; within a box
+// that spans its grid the wrap is resolved on the LDS indices), one direction at
+// a time the interface fluxes of the box go to one of two alternating LDS
+// arrays, and each thread accumulates the flux differences of its nodes in
+// registers.  Launches are persistent: a workgroup takes a contiguous range of a
+// box list that covers many grids of many solves.
 #include "sgw_internal.h"
 
 namespace {
