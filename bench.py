@@ -350,8 +350,12 @@ def main():
     achieved = step_flops / (step_ms * 1e-3) / 1e12
     # algorithmic bytes of a step: u^n read once, u^{n+1} written once (FP32)
     step_bytes = info["nodes"] * 4 * 2
+    traffic = measured_traffic()
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                # the HBM side of the same launch: counter bytes (when current) over the event time
+                "hbm_GBs": traffic / (step_ms * 1e-3) / 1e9 if traffic else None,
+                "hbm_frac": traffic / (step_ms * 1e-3) / 1e9 / PEAK_HBM_GBS if traffic else None,
                 "kernel": "stage_kernel<float, 2, fused> (three RK stages of every one-box grid)",
                 "avg_launch_us": step_ms * 1e3,
                 "flops_per_launch": step_flops, "boxes_per_launch": info["boxes"],
