@@ -41,6 +41,18 @@ __device__ __forceinline__ double wsum(double c, double num, double den)
     return c + q;
 }
 
+// max(m, |x|) for m >= 0 that keeps a NaN: the bit patterns of non-negative floats
+// order as unsigned integers, with every NaN above infinity
+__device__ __forceinline__ float absmax(float m, float x)
+{
+    return __uint_as_float(max(__float_as_uint(m), __float_as_uint(x) & 0x7fffffffu));
+}
+__device__ __forceinline__ double absmax(double m, double x)
+{
+    const double a = fabs(x);
+    return (a > m || a != a) ? a : m;
+}
+
 // WENO5 flux (eqs. 2.7, 2.7.1, 2.6, 2.7.2) of the positive-wind big stencil
 // (a..e) = (f_{i-2} .. f_{i+2}), written in differences so that neighbouring
 // interfaces share them: c = f_i, D0..D3 = b-a, c-b, d-c, e-d.  The candidate
@@ -48,10 +60,11 @@ __device__ __forceinline__ double wsum(double c, double num, double den)
 // smoothness indicators beta_r = 13/12 s_r^2 + 1/4 g_r^2 with the second
 // differences s_r = a-2b+c, b-2c+d, c-2d+e and g_r = 3 D1 - D0, D1 + D2, D3 - 3 D2.
 // The normalised weights are unchanged when eps and every beta_r are scaled by
-// the same factor, so 12/13 (eps + beta_r) = T_r + 3/13 g_r^2 with
-// T_r = s_r^2 + 12/13 eps is used, and the weights d_r/(...)^2 are normalised
-// with one division (numerator and denominator times the product of the three
-// squares).  R_r = d_r (q_r - c).
+// the same factor, so 4 (eps + beta_r) = T_r + g_r^2 with
+// T_r = 13/3 s_r^2 + 4 eps is used (T_r belongs to a second difference, which
+// three neighbouring interfaces share), and the weights d_r/(...)^2 are
+// normalised with one division (numerator and denominator times the product of
+// the three squares).  R_r = d_r (q_r - c).
 template <typename Real, bool LINEAR>
 __device__ __forceinline__ Real weno5s(Real c, Real D0, Real D1, Real D2, Real D3, Real T0, Real T1, Real T2)
 {
@@ -63,10 +76,9 @@ __device__ __forceinline__ Real weno5s(Real c, Real D0, Real D1, Real D2, Real D
     const Real R2 = fma(Real(-0.3 / 6.0), D3, d2);
     if (LINEAR) return c + ((R0 + R1) + R2);
     const Real g0 = fma(Real(3), D1, -D0), g1 = D1 + D2, g2 = fma(Real(-3), D2, D3);
-    const Real K = Real(3.0 / 13.0);
-    Real e0 = fma(K * g0, g0, T0);
-    Real e1 = fma(K * g1, g1, T1);
-    Real e2 = fma(K * g2, g2, T2);
+    Real e0 = fma(g0, g0, T0);
+    Real e1 = fma(g1, g1, T1);
+    Real e2 = fma(g2, g2, T2);
     e0 *= e0;
     e1 *= e1;
     e2 *= e2;
@@ -80,7 +92,7 @@ __device__ __forceinline__ Real weno5s(Real c, Real D0, Real D1, Real D2, Real D
 // u_{i0-2} .. u_{i0+NI+2} of one line: LF split f^+- (eq. LFflux), the positive-wind
 // reconstruction of f^+ on i-2..i+2 plus the mirrored one of f^- on i+3..i-1.  A
 // split part that is identically zero (c = -+alpha for a linear flux) contributes
-// exactly zero and is skipped.  epsT = 12/13 eps.  LINEAR: the linear weights d_r.
+// exactly zero and is skipped.  epsT = 4 eps.  LINEAR: the linear weights d_r.
 template <typename Real, int NI, bool LINEAR>
 __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real cp, Real cm, Real alpha, Real epsT,
                                               Real* F)
@@ -111,7 +123,7 @@ __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real 
 #pragma unroll
         for (int q = 1; q < NI + 4; q++) {
             const Real sp = dp[q] - dp[q - 1];
-            tp[q] = fma(sp, sp, epsT);
+            tp[q] = fma(Real(13.0 / 3.0) * sp, sp, epsT);
         }
 #pragma unroll
         for (int s = 0; s < NI; s++)
@@ -129,7 +141,7 @@ __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real 
 #pragma unroll
         for (int q = 1; q < NI + 4; q++) {
             const Real sm = dm[q] - dm[q - 1];
-            tm[q] = fma(sm, sm, epsT);
+            tm[q] = fma(Real(13.0 / 3.0) * sm, sm, epsT);
         }
 #pragma unroll
         for (int s = 0; s < NI; s++)
@@ -314,7 +326,7 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
     }
     __syncthreads();
 
-    const Real epsT = (Real)(g->eps * (12.0 / 13.0));
+    const Real epsT = (Real)(g->eps * 4.0);
     const int linear = g->linear;
     const bool burgers = g->flux == SGW_FLUX_BURGERS;
     Real dyn_alpha = Real(0);
@@ -360,6 +372,7 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
         const int Lk = g->nlines[k];
         const int nint = g->nint[k];
         const int int_total = M24(Lk, nint);
+        const bool seg_exact = Ik % SEG == 0;
         for (int w = tid; w < stot; w += SGW_BLOCK) {
             // interior segments (window inside the core, no wrap) first, then the edge ones;
             // consecutive lanes take neighbouring lines of the same segment
@@ -410,7 +423,10 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
                 // the box spans the grid and t is a power of two: the periodic wrap is a mask
                 // (window positions run from -2 up, two's complement wraps them)
 #pragma unroll
-                for (int q = 0; q < SEG + 5; q++) v[q] = su[base_core + M24((i0 + q - 2) & (tk - 1), LSk)];
+                for (int q = 0; q < SEG + 5; q++) {
+                    const int p = (i0 + q - 2) & (tk - 1);
+                    v[q] = su[base_core + (k == 0 ? p : M24(p, LSk))];
+                }
             } else {
 #pragma unroll
                 for (int q = 0; q < SEG + 5; q++) {
@@ -438,21 +454,38 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
                 window_fluxes<Real, SEG, true>(v, burgers, cp, cm, alpha, epsT, F);
             else
                 window_fluxes<Real, SEG, false>(v, burgers, cp, cm, alpha, epsT, F);
+            Real* __restrict__ fp = sfk + fbase + M24(seg * SEG, fstride);
+            if (seg_exact) {
+                // the segments tile the interfaces of the line: no store to skip
 #pragma unroll
-            for (int s = 0; s < SEG; s++) {
-                const int ip = seg * SEG + s; // i + hf
-                if (interior || ip < Ik) sfk[fbase + M24(ip, fstride)] = F[s];
+                for (int s = 0; s < SEG; s++) fp[k == 0 ? s : M24(s, fstride)] = F[s];
+            } else {
+#pragma unroll
+                for (int s = 0; s < SEG; s++) {
+                    const int ip = seg * SEG + s; // i + hf
+                    if (interior || ip < Ik) fp[k == 0 ? s : M24(s, fstride)] = F[s];
+                }
             }
         }
         __syncthreads();
         // ---- flux differences of eq. (2.9) for the nodes this thread owns
         const Real ih = (Real)g->inv_h[k];
+        // ROWS: a thread's nodes share one column, so along direction 0 the lower interface
+        // sits at the same offset from the upper one in every row
+        const int fhi0 = c00 + hf + M24((int)l00, RS);
+        const int dlo0 = (hf || c00 > 0) ? -1 : t0 - 1;
+        int fstep0 = M24(rline, RS);
+        // kept opaque: otherwise the row offsets are refactored into a full 32-bit multiply per row
+        asm volatile("" : "+s"(fstep0));
 #pragma unroll
         for (int r = 0; r < SGW_MAXR; r++) {
             const int e = tid + r * SGW_BLOCK;
             if (e < core_total) {
                 int fhi, flo;
-                if (k == 0) {
+                if (k == 0 && ROWS) {
+                    fhi = fhi0 + r * fstep0;
+                    flo = fhi + dlo0;
+                } else if (k == 0) {
                     // interface rows share the core row stride RS
                     int line, c0;
                     node_rc(r, line, c0);
@@ -492,8 +525,7 @@ __device__ __forceinline__ void stage_box(GridC g, int box, int stage, Real* su,
                 su[li] = res;
             else
                 out[gi] = res;
-            const Real ar = fabs(res);
-            amax = (ar > amax || ar != ar) ? ar : amax;
+            amax = absmax(amax, res);
         }
     }
     if (!FUSED) {
