@@ -61,6 +61,8 @@ def step_estimate(pb):
 
 
 def run_batch_step(torch, batch, solvers, outs, exacts, res):
+    """One step of the whole path for every solve.  solvers, outs and exacts are PtrLists:
+    marshalled once, so the host builds no pointer arrays between launches."""
     from paper_2007_10196_amd.solver import norms_many, prolongate_combine_many, restrict_many
     # Alg. Step 1 for every solve in one launch
     restrict_many(solvers, stream=batch.stream)
@@ -172,13 +174,14 @@ def full_grid_run(torch, probs, box_target, bpc, steps=2):
     resolution (root 256, finest level 0), batched the same way; time per step of all solves and
     the L1 error against the exact solution."""
     from paper_2007_10196_amd import binding as B
-    from paper_2007_10196_amd.solver import Batch, Solver
+    from paper_2007_10196_amd.solver import Batch, PtrList, Solver
     full = [p.replace(nr=p.n_fine, nl=0) for p in probs]
     solvers = [Solver(p, device="cuda:0", box_target=box_target) for p in full]
     fine = solvers[0].plan.fine_nodes
     outs = [torch.empty(fine, dtype=torch.float64, device="cuda:0") for _ in solvers]
     exacts = [s.exact(T_FINAL) for s in solvers]
     res = torch.zeros((len(solvers), 2), dtype=torch.float64, device="cuda:0")
+    solvers, outs, exacts = PtrList(solvers), PtrList(outs), PtrList(exacts)
     batch = Batch(max_solvers=len(solvers), precision=B.FP32_SWEEP,
                   hbm_budget=sum(s.plan.footprint for s in solvers) + (1 << 30),
                   max_items=sum(s.plan.total_nodes // 32 + 64 for s in solvers))
@@ -276,7 +279,7 @@ def main():
 
     import torch
     from paper_2007_10196_amd import binding as B
-    from paper_2007_10196_amd.solver import Batch, Solver
+    from paper_2007_10196_amd.solver import Batch, PtrList, Solver
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
@@ -298,6 +301,7 @@ def main():
     outs = [torch.empty(fine, dtype=torch.float64, device=dev) for _ in solvers]
     exacts = [s.exact(T_FINAL) for s in solvers]
     res = torch.zeros((len(solvers), 2), dtype=torch.float64, device=dev)
+    solvers, outs, exacts = PtrList(solvers), PtrList(outs), PtrList(exacts)
     budget = sum(s.plan.footprint for s in solvers) + (1 << 30)
     batch = Batch(max_solvers=len(solvers), precision=B.FP32_SWEEP, hbm_budget=budget,
                   max_items=sum(len(s.plan.grids) * 64 for s in solvers))

@@ -282,7 +282,8 @@ sgw_status sgw_batch_poll_end(sgw_batch_t* batch, int32_t* done_slots, int32_t* 
  * batch stream has that stream wait for them (stream-ordered). */
 sgw_status sgw_batch_release(sgw_batch_t* batch, int32_t slot);
 /* sgw_batch_release for n distinct occupied slots (all checked before any is
- * released); waits for queued steps at most once. */
+ * released).  One event marks the queued steps, and each distinct solver
+ * stream waits for it once. */
 sgw_status sgw_batch_release_many(sgw_batch_t* batch, const int32_t* slots, int32_t n);
 /* Measurement hook, outside any graph (callers time it with events on the batch
  * stream).  stage 0..2: reps launches of that RK stage, one stage at a time,

@@ -9,6 +9,7 @@
 // captured, and a request for n steps launches the binary decomposition of n
 // (each graph launch costs the device a gap of several microseconds, as long as
 // a small stage).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -416,6 +417,21 @@ extern "C" sgw_status sgw_batch_info(const sgw_batch_t* b, int32_t* active, int6
     return SGW_OK;
 }
 
+// Frees a slot whose solver's stream the caller has already ordered after the queued steps.
+static void release_slot(sgw_batch_t* b, int32_t slot)
+{
+    sgw_solver* s = b->slots[slot];
+    s->batch_slot = -1;
+    b->items_admitted -= (int64_t)s->items_h.size();
+    if (slot < b->free_hint) b->free_hint = slot;
+    b->tf_h[slot] = NAN;
+    b->used -= b->slot_bytes[slot];
+    b->slots[slot] = nullptr;
+    b->slot_bytes[slot] = 0;
+    b->reqs_h[slot] = nullptr;
+    b->dirty = true;
+}
+
 extern "C" sgw_status sgw_batch_release(sgw_batch_t* b, int32_t slot)
 {
     if (!b) return sgw_fail(SGW_ERR_INVALID_ARG, "null batch");
@@ -427,15 +443,7 @@ extern "C" sgw_status sgw_batch_release(sgw_batch_t* b, int32_t slot)
         if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, b->ev_order, 0);
         if (e != hipSuccess) return sgw_hip_fail(e, "order solver stream after batch");
     }
-    s->batch_slot = -1;
-    b->items_admitted -= (int64_t)s->items_h.size();
-    if (slot < b->free_hint) b->free_hint = slot;
-    b->tf_h[slot] = NAN;
-    b->used -= b->slot_bytes[slot];
-    b->slots[slot] = nullptr;
-    b->slot_bytes[slot] = 0;
-    b->reqs_h[slot] = nullptr;
-    b->dirty = true;
+    release_slot(b, slot);
     return SGW_OK;
 }
 
@@ -482,9 +490,21 @@ extern "C" sgw_status sgw_batch_release_many(sgw_batch_t* b, const int32_t* slot
             return sgw_fail(SGW_ERR_INVALID_ARG, "bad slot %d", slots[i]);
         if (seen[slots[i]]++) return sgw_fail(SGW_ERR_INVALID_ARG, "slot %d listed twice", slots[i]);
     }
-    for (int i = 0; i < n; i++) {
-        const sgw_status rc = sgw_batch_release(b, slots[i]);
-        if (rc != SGW_OK) return rc;
+    // one event after the queued steps, and one wait per distinct solver stream
+    if (b->queued) {
+        std::vector<hipStream_t> waited;
+        bool recorded = false;
+        for (int i = 0; i < n; i++) {
+            hipStream_t ss = b->slots[slots[i]]->stream;
+            if (ss == b->stream || std::find(waited.begin(), waited.end(), ss) != waited.end()) continue;
+            hipError_t e = hipSuccess;
+            if (!recorded) e = hipEventRecord(b->ev_order, b->stream);
+            recorded = true;
+            if (e == hipSuccess) e = hipStreamWaitEvent(ss, b->ev_order, 0);
+            if (e != hipSuccess) return sgw_hip_fail(e, "order solver stream after batch");
+            waited.push_back(ss);
+        }
     }
+    for (int i = 0; i < n; i++) release_slot(b, slots[i]);
     return SGW_OK;
 }

@@ -220,10 +220,15 @@ class Batch:
             raise
 
     def admit_many(self, solvers, t_final=None):
-        """Admit solvers in order; raises at the first refused one (those before it stay admitted)."""
+        """Admit solvers (a list or a PtrList) in order; raises at the first refused one (those
+        before it stay admitted)."""
         n = len(solvers)
-        hs = (C.c_void_p * n)(*[s.handle.value for s in solvers])
-        tf = (C.c_double * n)(*[s.problem.T if t_final is None else float(t_final[i]) for i, s in enumerate(solvers)])
+        hs = _ptrs(solvers, "solver")
+        if t_final is None and isinstance(solvers, PtrList):
+            tf = solvers.t_final()
+        else:
+            tf = (C.c_double * n)(*[s.problem.T if t_final is None else float(t_final[i])
+                                    for i, s in enumerate(solvers)])
         slots = (C.c_int32 * n)()
         got = C.c_int32()
         st = B.lib().sgw_batch_admit_many(self.handle, hs, n, tf, slots, C.byref(got))
@@ -286,6 +291,57 @@ class Batch:
             pass
 
 
+class PtrList:
+    """A list of solvers or of device tensors, marshalled once into the C pointer array that the
+    many-solve calls take.  With hundreds of solves, building that array from Python costs
+    0.1-0.3 ms of host time per call, which a caller that repeats the same call on the same
+    solvers and buffers (a benchmark or serving loop) pays only once this way.  The list keeps
+    its items alive; it must not be changed after construction."""
+
+    def __init__(self, items):
+        self.items = tuple(items)
+        if self.items and isinstance(self.items[0], Solver):
+            vals = [x.handle.value for x in self.items]
+            self.min_numel = None
+            self.all_fp64 = None
+        else:
+            vals = [x.data_ptr() for x in self.items]
+            self.min_numel = min((x.numel() for x in self.items), default=0)
+            self.all_fp64 = all(x.dtype == torch.float64 and x.is_cuda for x in self.items)
+        self.arr = (C.c_void_p * len(vals))(*vals)
+        self._t_final = None
+        self._max_fine = None
+
+    def __len__(self):
+        return len(self.items)
+
+    def __iter__(self):
+        return iter(self.items)
+
+    def __getitem__(self, i):
+        return self.items[i]
+
+    def max_fine_nodes(self):
+        """The largest finest-grid size over a list of solvers."""
+        if self._max_fine is None:
+            self._max_fine = max((s.plan.fine_nodes for s in self.items), default=0)
+        return self._max_fine
+
+    def t_final(self):
+        """The final times of a list of solvers, as the C array admit_many takes."""
+        if self._t_final is None:
+            self._t_final = (C.c_double * len(self.items))(*[s.problem.T for s in self.items])
+        return self._t_final
+
+
+def _ptrs(items, kind):
+    if isinstance(items, PtrList):
+        return items.arr
+    if kind == "solver":
+        return (C.c_void_p * len(items))(*[s.handle.value for s in items])
+    return (C.c_void_p * len(items))(*[x.data_ptr() for x in items])
+
+
 def _call_scratch(nbytes: int, device, stream: Optional[torch.cuda.Stream]) -> torch.Tensor:
     """Device scratch for one many-solve call.  The call returns before its kernels
     run, so the allocator is told the scratch is in use on the call's stream."""
@@ -296,10 +352,12 @@ def _call_scratch(nbytes: int, device, stream: Optional[torch.cuda.Stream]) -> t
 
 
 def prolongate_combine_many(solvers, outs, stream: Optional[torch.cuda.Stream] = None):
-    """Combined solutions of many solves (same dimension and precision) in one launch."""
+    """Combined solutions of many solves (same dimension and precision) in one launch.
+    `solvers` and `outs` are lists or PtrLists."""
     n = len(solvers)
-    hs = (C.c_void_p * n)(*[s.handle.value for s in solvers])
-    os_ = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    assert len(outs) == n
+    hs = _ptrs(solvers, "solver")
+    os_ = _ptrs(outs, "tensor")
     nbytes = int(B.lib().sgw_prolongate_many_scratch_bytes(hs, n))
     scratch = _call_scratch(nbytes, outs[0].device, stream)
     B.check(B.lib().sgw_prolongate_combine_many(hs, os_, n, C.c_void_p(scratch.data_ptr()), nbytes,
@@ -308,9 +366,9 @@ def prolongate_combine_many(solvers, outs, stream: Optional[torch.cuda.Stream] =
 
 
 def restrict_many(solvers, stream: Optional[torch.cuda.Stream] = None):
-    """Initial values of many solves (one precision) in one launch."""
+    """Initial values of many solves (one precision) in one launch (a list or a PtrList)."""
     n = len(solvers)
-    hs = (C.c_void_p * n)(*[s.handle.value for s in solvers])
+    hs = _ptrs(solvers, "solver")
     nbytes = int(B.lib().sgw_restrict_many_scratch_bytes(hs, n))
     scratch = _call_scratch(nbytes, solvers[0].device, stream)
     B.check(B.lib().sgw_restrict_initial_many(hs, n, C.c_void_p(scratch.data_ptr()), nbytes, _stream_handle(stream)))
@@ -318,15 +376,22 @@ def restrict_many(solvers, stream: Optional[torch.cuda.Stream] = None):
 
 
 def norms_many(solvers, a, b, result: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
-    """L1, Linf of (a[i] - b[i]) over solve i's finest grid into result[i, 0:2] (device FP64)."""
+    """L1, Linf of (a[i] - b[i]) over solve i's finest grid into result[i, 0:2] (device FP64).
+    `solvers`, `a` and `b` are lists or PtrLists."""
     n = len(solvers)
+    assert len(a) == n and len(b) == n
     assert result.dtype == torch.float64 and result.is_cuda and result.is_contiguous() and result.numel() >= 2 * n
-    for x, y, s in zip(a, b, solvers):
-        assert x.dtype == torch.float64 and y.dtype == torch.float64
-        assert x.numel() >= s.plan.fine_nodes and y.numel() >= s.plan.fine_nodes
-    hs = (C.c_void_p * n)(*[s.handle.value for s in solvers])
-    pa = (C.c_void_p * n)(*[x.data_ptr() for x in a])
-    pb = (C.c_void_p * n)(*[y.data_ptr() for y in b])
+    for v in (a, b):
+        if isinstance(v, PtrList):
+            need = (solvers.max_fine_nodes() if isinstance(solvers, PtrList)
+                    else max((s.plan.fine_nodes for s in solvers), default=0))
+            assert v.all_fp64 and v.min_numel >= need
+        else:
+            for x, s in zip(v, solvers):
+                assert x.dtype == torch.float64 and x.numel() >= s.plan.fine_nodes
+    hs = _ptrs(solvers, "solver")
+    pa = _ptrs(a, "tensor")
+    pb = _ptrs(b, "tensor")
     nbytes = int(B.lib().sgw_norms_many_scratch_bytes(hs, n))
     scratch = _call_scratch(nbytes, result.device, stream)
     B.check(B.lib().sgw_norms_many(hs, pa, pb, n, C.c_void_p(result.data_ptr()), C.c_void_p(scratch.data_ptr()),

@@ -377,6 +377,83 @@ def test_restrict_many_and_norms_many_match_single_calls():
             assert 0.0 < l1 <= li
 
 
+def test_pointer_lists_marshalled_once_match_plain_lists():
+    """The many-solve calls and admit_many take PtrLists (pointer arrays built once) with the same
+    results as plain lists, bitwise, on two calls in a row."""
+    torch, B, Solver, Batch = _lib()
+    from paper_2007_10196_amd.solver import PtrList, norms_many, prolongate_combine_many, restrict_many
+    rng = np.random.default_rng(31)
+    probs = [W.randomized(2, 3, rng, precision=W.PREC_FP32).replace(T=0.05) for _ in range(4)]
+    ref = []
+    for p in probs:
+        s = Solver(p)
+        s.restrict()
+        s.advance()
+        ref.append(s.prolongate_combine())
+    solvers = [Solver(p) for p in probs]
+    outs = [torch.empty_like(u) for u in ref]
+    exacts = [s.exact(p.T) for s, p in zip(solvers, probs)]
+    pl_s, pl_o, pl_e = PtrList(solvers), PtrList(outs), PtrList(exacts)
+    assert len(pl_s) == 4 and pl_s[1] is solvers[1] and list(pl_o) == outs
+    batch = Batch(max_solvers=4, precision=B.FP32_SWEEP, hbm_budget=1 << 32)
+    for rep in range(2):
+        _announce(f"ptrlist call {rep}")
+        for o in outs:
+            o.fill_(-1.0)
+        restrict_many(pl_s, stream=batch.stream)
+        batch.admit_many(pl_s)
+        done = set()
+        for _ in range(200):
+            batch.step(4)
+            done |= set(batch.poll())
+            if len(done) == 4:
+                break
+        assert len(done) == 4
+        batch.release_many(list(batch.slots))
+        prolongate_combine_many(pl_s, pl_o, stream=batch.stream)
+        res = torch.full((4, 2), -1.0, dtype=torch.float64, device="cuda")
+        norms_many(pl_s, pl_o, pl_e, res, stream=batch.stream)
+        res_plain = torch.full((4, 2), -1.0, dtype=torch.float64, device="cuda")
+        norms_many(solvers, outs, exacts, res_plain, stream=batch.stream)
+        torch.cuda.synchronize()
+        for i in range(4):
+            assert torch.equal(outs[i], ref[i])
+        assert torch.equal(res, res_plain)
+    batch.close()
+
+
+def test_release_many_orders_solver_streams_after_queued_steps():
+    """Solvers on two side streams, released while steps are still queued, prolongate on their own
+    streams at once: release_many's single event makes both streams wait, so the results equal a run
+    that synchronises before releasing, bitwise."""
+    torch, B, Solver, Batch = _lib()
+    from paper_2007_10196_amd.solver import restrict_many
+    rng = np.random.default_rng(37)
+    probs = [W.randomized(2, 4, rng, precision=W.PREC_FP32).replace(T=1.0) for _ in range(4)]
+    results = []
+    for sync in (True, False):
+        _announce(f"release ordering sync={sync}")
+        side = [torch.cuda.Stream(), torch.cuda.Stream()]
+        solvers = [Solver(p, stream=side[i % 2]) for i, p in enumerate(probs)]
+        batch = Batch(max_solvers=4, precision=B.FP32_SWEEP, hbm_budget=1 << 32)
+        restrict_many(solvers, stream=batch.stream)
+        batch.admit_many(solvers)
+        batch.step(6)
+        if sync:
+            torch.cuda.synchronize()
+        batch.release_many(sorted(batch.slots))
+        outs = []
+        for s in solvers:
+            with torch.cuda.stream(s.stream):
+                outs.append(s.prolongate_combine())
+        torch.cuda.synchronize()
+        assert all(s.query()[1] == 6 for s in solvers)
+        results.append(outs)
+        batch.close()
+    for a, b in zip(*results):
+        assert torch.equal(a, b)
+
+
 def test_restrict_many_rejects_mixed_precision():
     torch, B, Solver, _ = _lib()
     from paper_2007_10196_amd.solver import restrict_many
