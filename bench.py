@@ -60,9 +60,34 @@ def step_estimate(pb):
     return int(math.ceil(pb.T / (pb.cfl / denom)))
 
 
-def run_batch_step(torch, batch, solvers, outs, exacts, res):
+class StepNorms:
+    """The norms of every solve of one step travel to pinned host memory behind the step's
+    kernels; the host reads them once the next step is queued (or at the end)."""
+
+    def __init__(self, torch, res):
+        self.host = torch.empty(tuple(res.shape), dtype=res.dtype, pin_memory=True)
+        self.event = None
+
+    def send(self, torch, res, stream):
+        with torch.cuda.stream(stream):
+            self.host.copy_(res, non_blocking=True)
+        self.event = torch.cuda.Event()
+        self.event.record(stream)
+
+    def take(self):
+        """The norms sent last (waits for them), or None."""
+        if self.event is None:
+            return None
+        self.event.synchronize()
+        self.event = None
+        return self.host.numpy().copy()
+
+
+def run_batch_step(torch, batch, solvers, outs, exacts, res, sent):
     """One step of the whole path for every solve.  solvers, outs and exacts are PtrLists:
-    marshalled once, so the host builds no pointer arrays between launches."""
+    marshalled once, so the host builds no pointer arrays between launches.  Returns the
+    norms of the previous step (None for the first): they are read only after this step's
+    march is queued, so the device never waits for the host between steps."""
     from paper_2007_10196_amd.solver import norms_many, prolongate_combine_many, restrict_many
     # Alg. Step 1 for every solve in one launch
     restrict_many(solvers, stream=batch.stream)
@@ -71,6 +96,7 @@ def run_batch_step(torch, batch, solvers, outs, exacts, res):
     # the wave speed only decays before the shock, so the estimate is an upper bound
     # up to WENO overshoot: march most of it blind, then look every two steps
     batch.step(max(1, step_estimate(solvers[0].problem) - 4))
+    prev = sent.take()
     # the flags of each poll travel while the next two steps run (a step of solves
     # that are done does no work)
     batch.poll_begin()
@@ -84,7 +110,8 @@ def run_batch_step(torch, batch, solvers, outs, exacts, res):
     # Alg. Step 3 for every solve in one launch, then the norms of every solve in one launch
     prolongate_combine_many(solvers, outs, stream=batch.stream)
     norms_many(solvers, outs, exacts, res, stream=batch.stream)
-    return res.cpu().numpy()
+    sent.send(torch, res, batch.stream)
+    return prev
 
 
 STAGE_SRC = os.path.join(ROOT, "paper_2007_10196_amd", "csrc", "kernels_stage.hip")
@@ -182,15 +209,18 @@ def full_grid_run(torch, probs, box_target, bpc, steps=2):
     exacts = [s.exact(T_FINAL) for s in solvers]
     res = torch.zeros((len(solvers), 2), dtype=torch.float64, device="cuda:0")
     solvers, outs, exacts = PtrList(solvers), PtrList(outs), PtrList(exacts)
+    sent = StepNorms(torch, res)
     batch = Batch(max_solvers=len(solvers), precision=B.FP32_SWEEP,
                   hbm_budget=sum(s.plan.footprint for s in solvers) + (1 << 30),
                   max_items=sum(s.plan.total_nodes // 32 + 64 for s in solvers))
     batch.set_blocks_per_cu(bpc)
-    run_batch_step(torch, batch, solvers, outs, exacts, res)
+    run_batch_step(torch, batch, solvers, outs, exacts, res, sent)
+    sent.take()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        norms = run_batch_step(torch, batch, solvers, outs, exacts, res)
+        run_batch_step(torch, batch, solvers, outs, exacts, res, sent)
+    norms = sent.take()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / steps * 1e3
     batch.close()
@@ -302,6 +332,7 @@ def main():
     exacts = [s.exact(T_FINAL) for s in solvers]
     res = torch.zeros((len(solvers), 2), dtype=torch.float64, device=dev)
     solvers, outs, exacts = PtrList(solvers), PtrList(outs), PtrList(exacts)
+    sent = StepNorms(torch, res)
     budget = sum(s.plan.footprint for s in solvers) + (1 << 30)
     batch = Batch(max_solvers=len(solvers), precision=B.FP32_SWEEP, hbm_budget=budget,
                   max_items=sum(len(s.plan.grids) * 64 for s in solvers))
@@ -310,12 +341,14 @@ def main():
           flush=True)
 
     for _ in range(args.warmup):
-        run_batch_step(torch, batch, solvers, outs, exacts, res)
+        run_batch_step(torch, batch, solvers, outs, exacts, res, sent)
+    sent.take()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     norms = None
     for k in range(args.steps):
-        norms = run_batch_step(torch, batch, solvers, outs, exacts, res)
+        run_batch_step(torch, batch, solvers, outs, exacts, res, sent)
+    norms = sent.take()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     steps_each = [s.query()[1] for s in solvers]
