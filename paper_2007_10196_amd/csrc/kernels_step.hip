@@ -156,12 +156,26 @@ __global__ void req_set_final_many_kernel(ReqDev* const* reqs, const double* tf,
 __device__ void dt_wave(ReqDev* r)
 {
     const int lane = threadIdx.x & 63;
-    if (!r->active || r->done) {
+    // The record is read once through the constant address space (scalar loads, several in
+    // flight together, instead of one dependent vector load per field).  This kernel writes
+    // the record only after the last read.
+    typedef const __attribute__((address_space(4))) ReqDev* ReqC;
+    const ReqC rc = (ReqC)r;
+    const int active = rc->active, done = rc->done, dt_mode = rc->dt_mode, dyn = rc->dyn_alpha;
+    const int ngrids = rc->ngrids, d = rc->d;
+    const double t = rc->t, T = rc->T, cfl = rc->cfl, dt_pow53 = rc->dt_pow53;
+    const int64_t steps = rc->steps;
+    const unsigned long long* alpha = rc->alpha;
+    const GridDev* grids = rc->grids;
+    double hfin[SGW_MAX_DIM];
+#pragma unroll
+    for (int k = 0; k < SGW_MAX_DIM; k++) hfin[k] = rc->hfin[k];
+    if (!active || done) {
         if (lane == 0) r->dt = 0.0;
         return;
     }
-    const double rem = r->T - r->t;
-    const double tol = 1e-12 * (r->T > 1.0 ? r->T : 1.0);
+    const double rem = T - t;
+    const double tol = 1e-12 * (T > 1.0 ? T : 1.0);
     if (!(rem > tol)) {
         if (lane == 0) {
             r->done = 1;
@@ -170,23 +184,23 @@ __device__ void dt_wave(ReqDev* r)
         return;
     }
     double dt;
-    if (r->dt_mode == SGW_DT_POW53) {
-        dt = r->dt_pow53;
+    if (dt_mode == SGW_DT_POW53) {
+        dt = dt_pow53;
     } else {
         double denom = 0.0;
-        if (r->dyn_alpha) {
+        if (dyn) {
             // every grid of a solve has the same flux: one maximum of the state-dependent
             // speeds serves all directions
             double A = 0.0;
-            for (int g = lane; g < r->ngrids; g += 64) A = nanmax(A, __longlong_as_double((long long)r->alpha[4 * g]));
+            for (int g = lane; g < ngrids; g += 64) A = nanmax(A, __longlong_as_double((long long)alpha[4 * g]));
             A = wave_max(A);
-            for (int k = 0; k < r->d; k++) denom += A / r->hfin[k];
+            for (int k = 0; k < d; k++) denom += A / hfin[k];
         } else {
-            for (int k = 0; k < r->d; k++) {
+            for (int k = 0; k < d; k++) {
                 double A = 0.0;
-                for (int g = lane; g < r->ngrids; g += 64) A = nanmax(A, r->grids[g].alpha_c[k]);
+                for (int g = lane; g < ngrids; g += 64) A = nanmax(A, grids[g].alpha_c[k]);
                 A = wave_max(A);
-                denom += A / r->hfin[k];
+                denom += A / hfin[k];
             }
         }
         if (denom != denom || denom > 1.7e308) {
@@ -197,13 +211,13 @@ __device__ void dt_wave(ReqDev* r)
             }
             return;
         }
-        dt = denom > 0.0 ? r->cfl / denom : rem;
+        dt = denom > 0.0 ? cfl / denom : rem;
     }
     if (dt > rem) dt = rem;
     if (lane == 0) {
         r->dt = dt;
-        r->t += dt;
-        r->steps += 1;
+        r->t = t + dt;
+        r->steps = steps + 1;
     }
 }
 
