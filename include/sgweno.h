@@ -255,11 +255,14 @@ void sgw_batch_free(sgw_batch_t* batch);
 /* Scratch bytes a batch of max_solvers needs for at most max_items stage boxes. */
 uint64_t sgw_batch_scratch_bytes(int32_t max_solvers, int64_t max_items);
 /* Admit a restricted solver to advance to t_final.  SGW_ERR_OUT_OF_MEMORY when
- * no slot is free or its footprint does not fit the remaining budget. */
+ * no slot is free or its footprint does not fit the remaining budget.  Returns
+ * without waiting: when the solver's stream differs from the batch stream, the
+ * batch stream waits (an event) for the work already enqueued on it. */
 sgw_status sgw_batch_admit(sgw_batch_t* batch, sgw_solver_t* solver, double t_final, int32_t* slot);
 /* sgw_batch_admit for solvers[0..n) with final times t_final[i]; slots[i]
  * receives each slot.  Stops at the first solver that is refused and returns
- * its error; *n_admitted counts the solvers admitted before it. */
+ * its error; *n_admitted counts the solvers admitted before it.  The batch
+ * stream waits once per distinct solver stream. */
 sgw_status sgw_batch_admit_many(sgw_batch_t* batch, sgw_solver_t* const* solvers, int32_t n, const double* t_final,
                                 int32_t* slots, int32_t* n_admitted);
 /* Advance every active solver by up to nsteps steps (finished ones do nothing).

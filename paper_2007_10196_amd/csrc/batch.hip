@@ -31,9 +31,11 @@ struct sgw_batch {
     double* tf_d = nullptr;         // [max_solvers] final times of new slots (NaN: unchanged)
     int* flags_pinned = nullptr;
     hipEvent_t ev_order = nullptr;  // orders a released solver's own stream after the batch's steps
+    hipEvent_t ev_admit = nullptr;  // orders the batch stream after an admitted solver's own work
     hipEvent_t ev_poll = nullptr;   // behind the copy of the completion flags
     bool poll_inflight = false;
-    std::vector<sgw_solver*> poll_slots; // occupants of the slots when the flags were gathered
+    std::vector<uint64_t> slot_gen;   // bumped by every admission and release of the slot
+    std::vector<uint64_t> poll_gen;   // slot_gen when the flags in flight were gathered
     std::vector<sgw_solver*> slots;
     int free_hint = 0;              // no free slot below this index
     int64_t items_admitted = 0;     // boxes of the admitted solves
@@ -98,11 +100,14 @@ extern "C" sgw_status sgw_batch_create(int32_t max_solvers, int32_t precision, u
     off += a256(sizeof(double) * (uint64_t)max_solvers);
     b->items_d = (WorkItem*)(b->scratch + off);
     b->slots.assign(max_solvers, nullptr);
+    b->slot_gen.assign(max_solvers, 0);
+    b->poll_gen.assign(max_solvers, 0);
     b->slot_bytes.assign(max_solvers, 0);
     b->reqs_h.assign(max_solvers, nullptr);
     b->tf_h.assign(max_solvers, NAN);
     hipError_t e = hipHostMalloc((void**)&b->flags_pinned, sizeof(int) * max_solvers, hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_order, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_admit, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_poll, hipEventDisableTiming);
     if (e != hipSuccess) {
         sgw_batch_free(b);
@@ -133,6 +138,7 @@ extern "C" void sgw_batch_free(sgw_batch_t* b)
         if (s) s->batch_slot = -1;
     if (b->flags_pinned) (void)hipHostFree(b->flags_pinned);
     if (b->ev_order) (void)hipEventDestroy(b->ev_order);
+    if (b->ev_admit) (void)hipEventDestroy(b->ev_admit);
     if (b->ev_poll) (void)hipEventDestroy(b->ev_poll);
     delete b;
 }
@@ -280,7 +286,19 @@ static sgw_status batch_sync(sgw_batch* b)
     return SGW_OK;
 }
 
-extern "C" sgw_status sgw_batch_admit(sgw_batch_t* b, sgw_solver_t* s, double t_final, int32_t* slot)
+// The batch stream waits (an event, no host wait) for the work already enqueued on a
+// solver's own stream, such as its restriction.
+static sgw_status order_after_solver_stream(sgw_batch_t* b, hipStream_t ss)
+{
+    if (ss == b->stream) return SGW_OK;
+    hipError_t e = hipEventRecord(b->ev_admit, ss);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_admit, 0);
+    if (e != hipSuccess) return sgw_hip_fail(e, "order batch after solver stream");
+    return SGW_OK;
+}
+
+// ordered: the caller has already ordered the batch stream after the solver's stream
+static sgw_status admit_one(sgw_batch_t* b, sgw_solver_t* s, double t_final, int32_t* slot, bool ordered)
 {
     if (!b || !s || !slot) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
     if (!s->restricted) return sgw_fail(SGW_ERR_STATE, "admit before restrict");
@@ -302,14 +320,15 @@ extern "C" sgw_status sgw_batch_admit(sgw_batch_t* b, sgw_solver_t* s, double t_
     if (b->items_admitted + (int64_t)s->items_h.size() > b->max_items)
         return sgw_fail(SGW_ERR_OUT_OF_MEMORY, "box list full");
     // the solve's own work (restriction) is ordered before the batch's
-    if (s->stream != b->stream) {
-        hipError_t e = hipStreamSynchronize(s->stream);
-        if (e != hipSuccess) return sgw_hip_fail(e, "synchronise solver stream");
+    if (!ordered) {
+        const sgw_status rc = order_after_solver_stream(b, s->stream);
+        if (rc != SGW_OK) return rc;
     }
     // the final time reaches the device with the next upload of the slot table
     b->tf_h[free_slot] = t_final;
     b->tf_pending = true;
     b->slots[free_slot] = s;
+    b->slot_gen[free_slot]++;
     b->items_admitted += (int64_t)s->items_h.size();
     b->slot_bytes[free_slot] = need;
     b->reqs_h[free_slot] = s->req_d;
@@ -318,6 +337,11 @@ extern "C" sgw_status sgw_batch_admit(sgw_batch_t* b, sgw_solver_t* s, double t_
     b->dirty = true;
     *slot = free_slot;
     return SGW_OK;
+}
+
+extern "C" sgw_status sgw_batch_admit(sgw_batch_t* b, sgw_solver_t* s, double t_final, int32_t* slot)
+{
+    return admit_one(b, s, t_final, slot, false);
 }
 
 extern "C" sgw_status sgw_batch_step(sgw_batch_t* b, int32_t nsteps)
@@ -349,7 +373,7 @@ extern "C" sgw_status sgw_batch_poll_begin(sgw_batch_t* b)
         e = hipMemcpyAsync(b->flags_pinned, b->flags_d, sizeof(int) * b->max_solvers, hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipEventRecord(b->ev_poll, b->stream);
     if (e != hipSuccess) return sgw_hip_fail(e, "poll batch");
-    b->poll_slots = b->slots;
+    b->poll_gen = b->slot_gen;
     b->poll_inflight = true;
     return SGW_OK;
 }
@@ -364,8 +388,9 @@ extern "C" sgw_status sgw_batch_poll_end(sgw_batch_t* b, int32_t* done_slots, in
     int n = 0;
     bool bad = false;
     for (int i = 0; i < b->max_solvers; i++) {
-        // a slot released or refilled since the flags were gathered is not reported
-        if (!b->slots[i] || b->slots[i] != b->poll_slots[i]) continue;
+        // a slot released or refilled since the flags were gathered is not reported (also
+        // when the same solver was admitted again)
+        if (!b->slots[i] || b->slot_gen[i] != b->poll_gen[i]) continue;
         if (b->flags_pinned[i] & 1) done_slots[n++] = i;
         bad |= (b->flags_pinned[i] & 2) != 0;
     }
@@ -427,6 +452,7 @@ static void release_slot(sgw_batch_t* b, int32_t slot)
     b->tf_h[slot] = NAN;
     b->used -= b->slot_bytes[slot];
     b->slots[slot] = nullptr;
+    b->slot_gen[slot]++;
     b->slot_bytes[slot] = 0;
     b->reqs_h[slot] = nullptr;
     b->dirty = true;
@@ -473,8 +499,18 @@ extern "C" sgw_status sgw_batch_admit_many(sgw_batch_t* b, sgw_solver_t* const* 
     if (!b || !solvers || !t_final || !slots || !n_admitted || n < 0)
         return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
     *n_admitted = 0;
+    // one ordering per distinct solver stream, not one per solver
+    std::vector<hipStream_t> ordered;
     for (int i = 0; i < n; i++) {
-        const sgw_status rc = sgw_batch_admit(b, solvers[i], t_final[i], slots + i);
+        if (!solvers[i]) return sgw_fail(SGW_ERR_INVALID_ARG, "null solver %d", i);
+        hipStream_t ss = solvers[i]->stream;
+        if (std::find(ordered.begin(), ordered.end(), ss) != ordered.end()) continue;
+        const sgw_status rc = order_after_solver_stream(b, ss);
+        if (rc != SGW_OK) return rc;
+        ordered.push_back(ss);
+    }
+    for (int i = 0; i < n; i++) {
+        const sgw_status rc = admit_one(b, solvers[i], t_final[i], slots + i, true);
         if (rc != SGW_OK) return rc;
         *n_admitted = i + 1;
     }

@@ -86,8 +86,11 @@ struct Staging {
         host = (unsigned char*)p;
         if (err != hipSuccess) handle = -1;
     }
+    // every upload from one buffer goes to one stream: the release event is recorded there
     hipError_t upload(size_t offset, void* dst_dev, size_t bytes, hipStream_t s)
     {
+        if (handle < 0) return err != hipSuccess ? err : hipErrorInvalidValue;
+        if (uploaded && s != stream) return hipErrorInvalidValue;
         stream = s;
         uploaded = true;
         return staging_upload(handle, offset, dst_dev, bytes, s);

@@ -454,6 +454,50 @@ def test_release_many_orders_solver_streams_after_queued_steps():
         assert torch.equal(a, b)
 
 
+def test_poll_in_flight_skips_a_slot_refilled_by_the_same_solver():
+    """Flags gathered before a slot is released and refilled, even by the same solver, are not
+    reported for it; the refilled solve then runs to the same result as a solo solve.  The solver
+    sits on its own stream, so admission orders the batch after its restriction by an event."""
+    torch, B, Solver, Batch = _lib()
+    rng = np.random.default_rng(41)
+    p = W.randomized(2, 3, rng, precision=W.PREC_FP32).replace(T=0.05)
+    solo = Solver(p)
+    solo.restrict()
+    solo.advance()
+    ref = solo.prolongate_combine()
+    side = torch.cuda.Stream()
+    s = Solver(p, stream=side)
+    batch = Batch(max_solvers=2, precision=B.FP32_SWEEP, hbm_budget=1 << 32)
+    s.restrict()
+    slot = batch.admit(s)
+    done = []
+    for _ in range(400):
+        batch.step(4)
+        done = batch.poll()
+        if done:
+            break
+    assert done == [slot]
+    _announce("poll in flight across release and re-admission")
+    batch.poll_begin()
+    batch.release(slot)
+    s.restrict()
+    assert batch.admit(s) == slot
+    assert batch.poll_end() == []
+    done = []
+    for _ in range(400):
+        batch.step(4)
+        done = batch.poll()
+        if done:
+            break
+    assert done == [slot]
+    batch.release(slot)
+    with torch.cuda.stream(side):
+        out = s.prolongate_combine()
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    batch.close()
+
+
 def test_restrict_many_rejects_mixed_precision():
     torch, B, Solver, _ = _lib()
     from paper_2007_10196_amd.solver import restrict_many
