@@ -193,9 +193,10 @@ sgw_status sgw_norms_async(sgw_solver_t* solver, const double* a_dev, const doub
  * of every solve; all solves share dimension and precision; n <= 65535); outs[i]
  * receives solve i's combined solution.  scratch_dev (device, 256-byte aligned)
  * holds the solve list, sgw_prolongate_many_scratch_bytes(solvers, n) bytes.  Runs on
- * hip_stream after waiting for each solver's own stream that differs from it;
- * returns without waiting for the device (scratch_dev stays in use until the
- * launch has run in stream order). */
+ * hip_stream after the work already enqueued on each solver's own stream that
+ * differs from it, and each such stream then waits for the launch (events, no
+ * host wait).  Returns without waiting for the device (scratch_dev stays in use
+ * until the launch has run in stream order). */
 sgw_status sgw_prolongate_combine_many(sgw_solver_t* const* solvers, double* const* outs, int32_t n,
                                        void* scratch_dev, uint64_t scratch_bytes, void* hip_stream);
 uint64_t sgw_prolongate_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n);
@@ -205,8 +206,10 @@ uint64_t sgw_prolongate_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t
  * u0 at its nodes, bitwise as sgw_restrict_initial would.  All solves share a
  * precision.  scratch_dev (device, 256-byte aligned) holds the chunk list,
  * sgw_restrict_many_scratch_bytes(solvers, n) bytes.  Runs on hip_stream after
- * waiting for each solver's own stream that differs from it; returns without
- * waiting for the device (scratch_dev stays in use until the launch has run). */
+ * the work already enqueued on each solver's own stream that differs from it,
+ * and each such stream then waits for the launch (events, no host wait).
+ * Returns without waiting for the device (scratch_dev stays in use until the
+ * launch has run). */
 sgw_status sgw_restrict_initial_many(sgw_solver_t* const* solvers, int32_t n, void* scratch_dev,
                                      uint64_t scratch_bytes, void* hip_stream);
 uint64_t sgw_restrict_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n);
@@ -215,9 +218,10 @@ uint64_t sgw_restrict_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n
  * grid, in one launch: L1 and Linf of pair i go to result_dev[2i], [2i + 1]
  * (device FP64), bitwise as sgw_norms gives them.  scratch_dev (device, 256-byte
  * aligned) holds the pair list and partial sums, sgw_norms_many_scratch_bytes
- * bytes.  Runs on hip_stream; the caller orders the writes of a and b before
- * it.  Returns without waiting for the device (scratch_dev stays in use until
- * the launches have run). */
+ * bytes.  Runs on hip_stream after the work already enqueued on each solver's
+ * own stream that differs from it (an event); the caller orders other writes of
+ * a and b before it.  Returns without waiting for the device (scratch_dev stays
+ * in use until the launches have run). */
 sgw_status sgw_norms_many(sgw_solver_t* const* solvers, const double* const* a_dev, const double* const* b_dev,
                           int32_t n, double* result_dev, void* scratch_dev, uint64_t scratch_bytes, void* hip_stream);
 uint64_t sgw_norms_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n);

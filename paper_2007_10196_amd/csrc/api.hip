@@ -1,5 +1,6 @@
 // Host side of libsgweno: plans (grid enumeration, layout, tiling), solvers
 // bound to caller memory, the time loop and the C entry points of sgweno.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1041,6 +1042,35 @@ extern "C" uint64_t sgw_prolongate_many_scratch_bytes(sgw_solver_t* const* solve
     return align256((uint64_t)n * sizeof(ProItem));
 }
 
+// `later` waits (an event, no host wait) for the work already enqueued on `earlier`.
+static hipError_t stream_wait(hipStream_t later, hipStream_t earlier)
+{
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ev, earlier);
+    if (e == hipSuccess) e = hipStreamWaitEvent(later, ev, 0);
+    // an event may be destroyed once the wait is enqueued
+    (void)hipEventDestroy(ev);
+    return e;
+}
+
+// A many-solve call on stream st and the solvers' own streams: before the call st waits for
+// each distinct solver stream that differs from it (after = false); after the call each such
+// stream waits for st (after = true), so the solver's later calls follow the launch.
+static hipError_t order_solver_streams(hipStream_t st, sgw_solver_t* const* solvers, int n, bool after)
+{
+    std::vector<hipStream_t> done;
+    for (int i = 0; i < n; i++) {
+        hipStream_t ss = solvers[i]->stream;
+        if (ss == st || std::find(done.begin(), done.end(), ss) != done.end()) continue;
+        const hipError_t e = after ? stream_wait(ss, st) : stream_wait(st, ss);
+        if (e != hipSuccess) return e;
+        done.push_back(ss);
+    }
+    return hipSuccess;
+}
+
 extern "C" sgw_status sgw_prolongate_combine_many(sgw_solver_t* const* solvers, double* const* outs, int32_t n,
                                                   void* scratch_dev, uint64_t scratch_bytes, void* hip_stream)
 {
@@ -1072,11 +1102,11 @@ extern "C" sgw_status sgw_prolongate_combine_many(sgw_solver_t* const* solvers, 
     for (int i = 0; i < n; i++)
         items[i] = ProItem{solvers[i]->pro_d, solvers[i]->fine_d, outs[i], (int32_t)fine_tiles(solvers[i]), 0};
     hipStream_t st = (hipStream_t)hip_stream;
-    // every solver's own stream has finished the state the tiles read
-    for (int i = 0; i < n; i++)
-        if (solvers[i]->stream != st) HIPCHK(hipStreamSynchronize(solvers[i]->stream), "synchronise solver stream");
+    // the tiles read each solve's state after the work enqueued on its own stream
+    HIPCHK(order_solver_streams(st, solvers, n, false), "order after solver streams");
     HIPCHK(stg.upload(0, scratch_dev, (size_t)n * sizeof(ProItem), st), "upload solve list");
     HIPCHK(launch_prolong_many((const ProItem*)scratch_dev, n, (int)max_tiles, d, prec, lds, st), "prolongate many");
+    HIPCHK(order_solver_streams(st, solvers, n, true), "order solver streams after the launch");
     return SGW_OK;
 }
 
@@ -1146,12 +1176,12 @@ extern "C" sgw_status sgw_restrict_initial_many(sgw_solver_t* const* solvers, in
     }
     hipStream_t st = (hipStream_t)hip_stream;
     // earlier work of each solve on its own stream may still read its state
-    for (int i = 0; i < n; i++)
-        if (solvers[i]->stream != st) HIPCHK(hipStreamSynchronize(solvers[i]->stream), "synchronise solver stream");
+    HIPCHK(order_solver_streams(st, solvers, n, false), "order after solver streams");
     HIPCHK(stg.upload(0, scratch_dev, need, st), "upload restriction list");
     const unsigned char* base = (const unsigned char*)scratch_dev;
     HIPCHK(launch_restrict_many((const ResetItem*)base, n, (const RestrictItem*)(base + off_items), (int)c, prec, st),
            "restrict many");
+    HIPCHK(order_solver_streams(st, solvers, n, true), "order solver streams after the launch");
     for (int i = 0; i < n; i++) {
         solvers[i]->restricted = true;
         solvers[i]->t_host = 0.0;
@@ -1200,8 +1230,7 @@ extern "C" sgw_status sgw_norms_many(sgw_solver_t* const* solvers, const double*
         items[i] = NormItem{a[i], b[i], cnt, result_dev + 2 * (size_t)i, norms_parts(cnt), 0};
     }
     hipStream_t st = (hipStream_t)hip_stream;
-    for (int i = 0; i < n; i++)
-        if (solvers[i]->stream != st) HIPCHK(hipStreamSynchronize(solvers[i]->stream), "synchronise solver stream");
+    HIPCHK(order_solver_streams(st, solvers, n, false), "order after solver streams");
     unsigned char* base = (unsigned char*)scratch_dev;
     HIPCHK(stg.upload(0, base, sizeof(NormItem) * (size_t)n, st), "upload norm list");
     HIPCHK(launch_norms_many((const NormItem*)base, n, mp, (double*)(base + align256((uint64_t)n * sizeof(NormItem))),

@@ -498,6 +498,36 @@ def test_poll_in_flight_skips_a_slot_refilled_by_the_same_solver():
     batch.close()
 
 
+def test_many_solve_calls_order_solver_streams_both_ways():
+    """restrict_many and prolongate_combine_many on a third stream, with no host synchronisation:
+    the solvers' own streams (two side streams) run their advance after the restriction, and a
+    restriction enqueued on them right after the prolongation does not disturb it."""
+    torch, B, Solver, _ = _lib()
+    from paper_2007_10196_amd.solver import prolongate_combine_many, restrict_many
+    rng = np.random.default_rng(43)
+    probs = [W.randomized(2, 4, rng, precision=W.PREC_FP32).replace(T=0.05) for _ in range(4)]
+    ref = []
+    for p in probs:
+        s = Solver(p)
+        s.restrict()
+        s.advance()
+        ref.append(s.prolongate_combine())
+    side = [torch.cuda.Stream(), torch.cuda.Stream()]
+    call = torch.cuda.Stream()
+    solvers = [Solver(p, stream=side[i % 2]) for i, p in enumerate(probs)]
+    outs = [torch.empty_like(u) for u in ref]
+    _announce("many-solve calls across three streams")
+    restrict_many(solvers, stream=call)
+    for s in solvers:
+        s.advance()
+    prolongate_combine_many(solvers, outs, stream=call)
+    for s in solvers:
+        s.restrict()
+    torch.cuda.synchronize()
+    for a, b in zip(outs, ref):
+        assert torch.equal(a, b)
+
+
 def test_restrict_many_rejects_mixed_precision():
     torch, B, Solver, _ = _lib()
     from paper_2007_10196_amd.solver import restrict_many
