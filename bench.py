@@ -280,6 +280,72 @@ def cpu_baseline(budget_s=15.0, single_budget_s=5.0):
             "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
+def path_workload(name, precision, box_target, bpc, reps):
+    """One solve of the 3D advection workload (root 8, finest level 5, 46 grids) or the 4D Vlasov
+    workload (root 8, finest level 4, 69 grids) through the whole path on one GPU, each part
+    timed with HIP events: the stage launches of one time step in the batch's launch shape
+    (`reps` repetitions), the march to T as a solver runs it (step graphs), and the WENO5
+    prolongation with the signed combination.  Prints one JSON line."""
+    import torch
+    from paper_2007_10196_amd.solver import Batch, Solver
+    torch.cuda.set_device(0)
+    make = {"c3": W.c3_advection_3d, "c4": W.c4_vlasov_4d}[name]
+    prec = W.PREC_FP64 if precision == "fp64" else W.PREC_FP32
+    pb = make(precision=prec)
+    if not box_target:
+        # the launch shape the autotuner picks for this solve (cached in JSON)
+        from paper_2007_10196_amd.autotune import tune_box_target
+        tune = tune_box_target([pb], prec, reps=5)
+        box_target, bpc = int(tune["best"]), int(tune.get("blocks_per_cu", 0))
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    s = Solver(pb, device="cuda:0", box_target=box_target, blocks_per_cu=bpc)
+    batch = Batch(max_solvers=1, precision=prec, hbm_budget=1 << 40, max_items=1 << 20)
+    if bpc:
+        batch.set_blocks_per_cu(bpc)
+    s.restrict()
+    slot = batch.admit(s)
+    batch.step(1)
+    st = batch.stream
+    e0, e1 = ev(), ev()
+    batch.launch_stage(3, 2)
+    e0.record(st)
+    batch.launch_stage(3, reps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    stage_us = e0.elapsed_time(e1) / reps * 1e3
+    info = batch.info()
+    batch.release(slot)
+    batch.close()
+    # the march and the prolongation as one solver runs them; the second of two runs is timed
+    # (the first loads the kernels' code)
+    s = Solver(pb, device="cuda:0", box_target=box_target, blocks_per_cu=bpc)
+    out = torch.empty(s.plan.fine_nodes, dtype=torch.float64, device="cuda:0")
+    for _ in range(2):
+        s.restrict()
+        torch.cuda.synchronize()
+        e0, e1, e2, e3 = ev(), ev(), ev(), ev()
+        e0.record(s.stream)
+        s.advance()
+        e1.record(s.stream)
+        t, steps = s.query()
+        e2.record(s.stream)
+        s.prolongate_combine(out)
+        e3.record(s.stream)
+        torch.cuda.synchronize()
+    march_ms = e0.elapsed_time(e1)
+    print(json.dumps({
+        "workload": f"{pb.name}: d={pb.d}, root {pb.nr}, finest level {pb.nl}, {len(s.plan.grids)} component grids, "
+                    f"{s.plan.total_nodes} nodes, finest grid {s.plan.fine_nodes} nodes, T={pb.T}",
+        "precision": precision, "boxes": info["boxes"], "box_target": box_target, "blocks_per_cu": bpc,
+        "stage_launches_per_step_us": stage_us, "steps": steps, "t": t, "march_ms": march_ms,
+        "march_ms_per_step": march_ms / max(steps, 1),
+        "march_cell_updates_per_s": steps * s.plan.total_nodes / (march_ms * 1e-3),
+        "prolong_combine_ms": e2.elapsed_time(e3)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,12 +365,18 @@ def main():
                     help="comma-separated offered loads (the first one is the reported latency)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 1 GiB copy used to scale the HBM byte counters")
+    ap.add_argument("--path-workload", choices=("c3", "c4"),
+                    help="only run one 3D (c3) or 4D (c4) solve through the path, each part timed")
+    ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32", help="with --path-workload")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.path_workload:
+        path_workload(args.path_workload, args.precision, args.box_target, args.blocks_per_cu, args.stage_reps)
         return
 
     import torch
