@@ -6,7 +6,8 @@
 // host round trip.  Lists are therefore written into pinned buffers, uploaded
 // with hipMemcpyAsync and an event recorded behind the copy; a buffer is handed
 // out again only once its event has completed, so calls return without waiting
-// for the device.
+// for the device.  The pool grows to the number of uploads in flight at once
+// (64 KiB and up per buffer) and keeps its buffers until the process ends.
 #include <mutex>
 #include <vector>
 

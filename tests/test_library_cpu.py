@@ -155,3 +155,20 @@ def test_blocks_per_cu_is_validated():
     _expect_status(W.c1_advection_2d(), -1, blocks_per_cu=65)
     _expect_status(W.c1_advection_2d(), -1, blocks_per_cu=-1)
     Plan(W.c1_advection_2d(), blocks_per_cu=6)  # accepted
+
+
+def test_pointer_list_marshals_once_and_validates_lazily():
+    """PtrList (binding side, no GPU): the pointer array holds each tensor's data pointer in order,
+    it behaves as the sequence it was built from, and records what the norm call checks."""
+    import torch
+    from paper_2007_10196_amd.solver import PtrList, _ptrs
+    xs = [torch.zeros(n, dtype=torch.float64) for n in (5, 3, 7)]
+    pl = PtrList(xs)
+    assert len(pl) == 3 and pl[1] is xs[1] and list(pl) == xs
+    assert [pl.arr[i] for i in range(3)] == [x.data_ptr() for x in xs]
+    assert pl.min_numel == 3
+    assert pl.all_fp64 is False  # host tensors: the norm call would refuse them
+    assert _ptrs(pl, "tensor") is pl.arr
+    plain = _ptrs(xs, "tensor")
+    assert [plain[i] for i in range(3)] == [x.data_ptr() for x in xs]
+    assert len(PtrList([])) == 0
