@@ -21,6 +21,11 @@
 // box list that covers many grids of many solves.
 #include "sgw_internal.h"
 
+// Only the explicit fma calls fuse: with contraction left to the compiler, a product that
+// feeds an addition could fuse in one kernel instantiation and not in another, and the
+// fused and split kernels would round differently.
+#pragma clang fp contract(off)
+
 namespace {
 
 // descriptors live in the constant address space for the duration of a launch
@@ -103,10 +108,9 @@ __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real 
         const Real ha = Real(0.5) * alpha;
 #pragma unroll
         for (int q = 0; q < NI + 5; q++) {
-            // f^+- = (u^2/2 +- alpha u)/2
-            const Real f4 = (Real(0.25) * v[q]) * v[q];
-            pv[q] = fma(ha, v[q], f4);
-            mv[q] = fma(-ha, v[q], f4);
+            // f^+ = (u^2/2 + alpha u)/2 = u (u/4 + alpha/2), f^- = f^+ - alpha u
+            pv[q] = v[q] * fma(Real(0.25), v[q], ha);
+            mv[q] = fma(-alpha, v[q], pv[q]);
         }
     } else {
 #pragma unroll
