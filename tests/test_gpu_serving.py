@@ -63,6 +63,30 @@ def test_serving_fp32_results_close_to_fp64_oracle():
     loop.close()
 
 
+def test_serving_fp64_results_match_fp64_oracle():
+    """Served FP64 solves of mixed dimension and level, admitted while others run: each combined
+    solution matches the FP64 oracle within 1e-11 max-abs."""
+    import torch
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.serving import ServingLoop
+    reqs = W.serving_stream(n=6, rate_hz=400.0, seed=9, levels=(2,), precision=W.PREC_FP64)
+    for r in reqs:
+        r.problem = r.problem.replace(T=min(r.problem.T, 0.1))
+    assert len({r.problem.d for r in reqs}) >= 2
+    loop = ServingLoop(precision=B.FP64, max_active=3, hbm_budget=8 << 30, steps_per_tick=4, keep_outputs=True)
+    res = loop.run(reqs)
+    torch.cuda.synchronize()
+    assert sorted(r.rid for r in res) == [r.rid for r in reqs]
+    by_id = {r.rid: r for r in reqs}
+    for r in res:
+        pb = by_id[r.rid].problem
+        U, _, _ = O.solve(pb)
+        err = np.abs(r.out.cpu().numpy() - U).max()
+        print(f"  request {r.rid} {pb.name} d={pb.d} nl={pb.nl}: fp64 max-abs {err:.2e}")
+        assert err <= 1e-11, (r.rid, err)
+    loop.close()
+
+
 def test_admission_waits_for_memory_and_rejects_oversize():
     from paper_2007_10196_amd import binding as B
     from paper_2007_10196_amd.serving import ServingLoop
