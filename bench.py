@@ -200,17 +200,21 @@ def full_grid_run(torch, probs, box_target, bpc, steps=2):
     """The paper's comparison (Sec. 3 tables): the same solves on one full grid of the finest
     resolution (root 256, finest level 0), batched the same way; time per step of all solves and
     the L1 error against the exact solution."""
-    from paper_2007_10196_amd import binding as B
+    return batch_run(torch, [p.replace(nr=p.n_fine, nl=0) for p in probs], box_target, bpc, steps)
+
+
+def batch_run(torch, probs, box_target, bpc, steps=2):
+    """The batched step of run_batch_step over `probs` (one precision), after one untimed step:
+    time per step of all solves and the mean L1 error against the exact solution."""
     from paper_2007_10196_amd.solver import Batch, PtrList, Solver
-    full = [p.replace(nr=p.n_fine, nl=0) for p in probs]
-    solvers = [Solver(p, device="cuda:0", box_target=box_target) for p in full]
+    solvers = [Solver(p, device="cuda:0", box_target=box_target) for p in probs]
     fine = solvers[0].plan.fine_nodes
     outs = [torch.empty(fine, dtype=torch.float64, device="cuda:0") for _ in solvers]
     exacts = [s.exact(T_FINAL) for s in solvers]
     res = torch.zeros((len(solvers), 2), dtype=torch.float64, device="cuda:0")
     solvers, outs, exacts = PtrList(solvers), PtrList(outs), PtrList(exacts)
     sent = StepNorms(torch, res)
-    batch = Batch(max_solvers=len(solvers), precision=B.FP32_SWEEP,
+    batch = Batch(max_solvers=len(solvers), precision=probs[0].precision,
                   hbm_budget=sum(s.plan.footprint for s in solvers) + (1 << 30),
                   max_items=sum(s.plan.total_nodes // 32 + 64 for s in solvers))
     batch.set_blocks_per_cu(bpc)
@@ -225,7 +229,8 @@ def full_grid_run(torch, probs, box_target, bpc, steps=2):
     ms = (time.perf_counter() - t0) / steps * 1e3
     batch.close()
     return {"ms_per_step": ms, "l1_mean": float(norms[:, 0].mean()), "nodes_per_solve": solvers[0].plan.total_nodes,
-            "time_steps": solvers[0].query()[1]}
+            "time_steps": solvers[0].query()[1],
+            "cell_updates_per_step": sum(s.query()[1] * s.plan.total_nodes for s in solvers)}
 
 
 def step_estimate_any(pb):
@@ -357,6 +362,7 @@ def main():
     ap.add_argument("--stage-reps", type=int, default=20)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-full", action="store_true", help="skip the single full-grid comparison")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 batched run of the same solves")
     ap.add_argument("--box-target", type=int, default=0,
                     help="0: autotune the stage box target and the workgroups per compute unit")
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="with --box-target: stage workgroups per CU")
@@ -507,6 +513,16 @@ def main():
         print(f"[bench] full grid: {f['ms_per_step']:.2f} ms/step, L1 {f['l1_mean']:.3e} "
               f"(sparse {ms_per_step:.2f} ms/step, L1 {float(l1s.mean()):.3e})", file=sys.stderr, flush=True)
 
+    batched_fp64 = None
+    if not args.no_fp64:
+        f = batch_run(torch, [p.replace(precision=W.PREC_FP64) for p in probs], box_target, bpc, steps=args.steps)
+        v64 = f["cell_updates_per_step"] / (f["ms_per_step"] * 1e-3)
+        batched_fp64 = {"value": v64, "unit": "cell-updates/s", "ms_per_step": f["ms_per_step"],
+                        "mode": "the same 256 solves and batched path with FP64 sweeps (launch shape of the FP32 run)",
+                        "l1_mean": f["l1_mean"], "fp32_speedup": value / v64}
+        print(f"[bench] FP64 batched: {f['ms_per_step']:.2f} ms/step, {v64:.3e} cell-updates/s, L1 {f['l1_mean']:.3e}",
+              file=sys.stderr, flush=True)
+
     serving = None if args.no_serving else serving_run(
         box_target, n=args.serving_requests, loads=[float(x) for x in args.serving_loads.split(",")],
         blocks_per_cu=bpc)
@@ -523,6 +539,7 @@ def main():
            "l1_mean": float(l1s.mean()), "l1_max": float(l1s.max()),
            "finest_equivalent_cell_updates_per_s": finest_equiv,
            "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "latency": serving, "sparse_vs_full": full,
+           "batched_fp64": batched_fp64,
            "autotune": {"box_target": box_target, "blocks_per_cu": bpc, "step_stage_us_by_target_and_cap": tune["us"]}}
     print(json.dumps(out), flush=True)
 
