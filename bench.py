@@ -12,7 +12,11 @@ combination and norms in FP64.
 
 Prints one JSON line.  Extra keys: the plain per-grid FP64 method on the same
 workload (equal-L1 comparison), the event-timed stage kernel against its
-roofline, the FP64 oracle timed on the host, and serving latencies.
+roofline, the FP64 oracle timed on the host, serving latencies, the same solves
+on one full grid, and the same batched path with FP64 sweeps.
+
+--path-workload c3|c4 instead times one 3D advection or 4D Vlasov solve through
+the path (stage launches of a step, march, prolongation) and prints its own line.
 """
 import argparse
 import json
