@@ -355,6 +355,32 @@ def path_workload(name, precision, box_target, bpc, reps):
         "prolong_combine_ms": e2.elapsed_time(e3)}), flush=True)
 
 
+def valu_calibration():
+    """Cycles one SIMD spends per wave64 instruction of each class (FP32 FMA, multiply, add;
+    INT32 add/xor; FP64 FMA), from event-timed launches of the library's calibration kernels
+    over 16 workgroups per compute unit, at the 2.4 GHz peak clock."""
+    import ctypes as C
+    import torch
+    from paper_2007_10196_amd import binding as B
+    torch.cuda.set_device(0)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks = 16 * cus
+    out = torch.empty(blocks * 256 * 8, dtype=torch.uint8, device="cuda:0")
+    st = torch.cuda.current_stream()
+    res = {}
+    for op, name in enumerate(("fp32_fma", "fp32_mul", "fp32_add", "int32_add_xor", "fp64_fma")):
+        n = C.c_double()
+        for rep in range(3):  # the last of three launches is kept
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            B.check(B.lib().sgw_calibrate_valu(op, blocks, C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream),
+                                               C.byref(n)))
+            e1.record(st)
+            torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) * 1e-3 * 2.4e9 / n.value
+    print(json.dumps({"valu_cycles_per_wave64_instruction": res, "clock_GHz": 2.4, "compute_units": cus}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -375,6 +401,8 @@ def main():
                     help="comma-separated offered loads (the first one is the reported latency)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 1 GiB copy used to scale the HBM byte counters")
+    ap.add_argument("--valu-calibration", action="store_true",
+                    help="only time the VALU issue-rate calibration kernels")
     ap.add_argument("--path-workload", choices=("c3", "c4"),
                     help="only run one 3D (c3) or 4D (c4) solve through the path, each part timed")
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32", help="with --path-workload")
@@ -384,6 +412,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.valu_calibration:
+        valu_calibration()
         return
     if args.path_workload:
         path_workload(args.path_workload, args.precision, args.box_target, args.blocks_per_cu, args.stage_reps)

@@ -301,6 +301,17 @@ sgw_status sgw_batch_release_many(sgw_batch_t* batch, const int32_t* slots, int3
  * without advancing t.  Either way the solves' wave-speed slots are disturbed,
  * so re-restrict before trusting later results. */
 sgw_status sgw_batch_launch_stage(sgw_batch_t* batch, int32_t stage, int32_t reps);
+/* Measurement hook for the VALU issue rates that price kernel issue floors (not
+ * part of the method): enqueues on hip_stream one launch of `blocks` workgroups
+ * of 256 threads running long chains of independent instructions of one class,
+ * op 0 FP32 FMA, 1 FP32 multiply, 2 FP32 add, 3 INT32 add + xor, 4 FP64 FMA.
+ * out_dev (device) receives one value per thread: blocks * 256 * 8 bytes.
+ * *instructions_per_simd receives the wave64 instructions of the class each SIMD
+ * issues (host, written before return); the caller times the launch with events,
+ * so cycles per instruction = seconds * clock / *instructions_per_simd.  Returns
+ * without waiting for the device. */
+sgw_status sgw_calibrate_valu(int32_t op, int32_t blocks, void* out_dev, void* hip_stream,
+                              double* instructions_per_simd);
 /* Tuning knob: at most blocks_per_cu resident stage workgroups per compute unit
  * (0: as many as fit).  The persistent stage launch splits the box list into
  * equal contiguous ranges over its workgroups, so this trades latency hiding

@@ -94,6 +94,7 @@ _SIGS = {
     "sgw_batch_poll_end": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "sgw_batch_release": (C.c_int32, [C.c_void_p, C.c_int32]),
     "sgw_batch_launch_stage": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
+    "sgw_calibrate_valu": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "sgw_batch_set_blocks_per_cu": (C.c_int32, [C.c_void_p, C.c_int32]),
     "sgw_batch_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "sgw_status_string": (C.c_char_p, [C.c_int32]),

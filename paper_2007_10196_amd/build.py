@@ -14,7 +14,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsgweno.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "batch.hip", "staging.hip", "kernels_stage.hip", "kernels_step.hip", "kernels_prolong.hip"]
+SOURCES = ["api.hip", "batch.hip", "staging.hip", "kernels_stage.hip", "kernels_step.hip", "kernels_prolong.hip",
+           "calibrate.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SGW_OFFLOAD_ARCH", "gfx950")

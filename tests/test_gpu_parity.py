@@ -528,6 +528,20 @@ def test_many_solve_calls_order_solver_streams_both_ways():
         assert torch.equal(a, b)
 
 
+def test_valu_calibration_hook_runs_every_class():
+    """The issue-rate measurement hook launches each instruction class and reports the wave64
+    instructions per SIMD that its timing is divided by."""
+    import ctypes as C
+    torch, B, _, _ = _lib()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = torch.empty(cus * 256 * 8, dtype=torch.uint8, device="cuda")
+    for op in range(5):
+        n = C.c_double()
+        B.check(B.lib().sgw_calibrate_valu(op, cus, C.c_void_p(out.data_ptr()), None, C.byref(n)))
+        torch.cuda.synchronize()
+        assert n.value == cus * 4 * 4096 * (16 if op == 3 else 8) / (4.0 * cus)
+
+
 def test_restrict_many_rejects_mixed_precision():
     torch, B, Solver, _ = _lib()
     from paper_2007_10196_amd.solver import restrict_many

@@ -172,3 +172,12 @@ def test_pointer_list_marshals_once_and_validates_lazily():
     plain = _ptrs(xs, "tensor")
     assert [plain[i] for i in range(3)] == [x.data_ptr() for x in xs]
     assert len(PtrList([])) == 0
+
+
+def test_valu_calibration_hook_validates_before_launching():
+    """sgw_calibrate_valu refuses an unknown instruction class or a bad size before any GPU call."""
+    import ctypes as C
+    n = C.c_double()
+    for op, blocks, out in ((5, 1, 1), (-1, 1, 1), (0, 0, 1), (0, 1, None)):
+        st = B.lib().sgw_calibrate_valu(op, blocks, C.c_void_p(out), None, C.byref(n))
+        assert st == -1  # SGW_ERR_INVALID_ARG
