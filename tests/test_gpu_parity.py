@@ -528,6 +528,43 @@ def test_many_solve_calls_order_solver_streams_both_ways():
         assert torch.equal(a, b)
 
 
+def test_bench_configuration_against_fp64_oracle_samples():
+    """The benchmark's own step (256 batched 2D Burgers solves, FP32 sweeps, box target 2048 and
+    7 workgroups per CU, as bench.py times it): four of the 256 combined solutions, spread over the
+    batch, are within the FP32 bounds of the FP64 oracle, and the device norms equal the norms of
+    the returned solutions."""
+    torch, B, Solver, Batch = _lib()
+    import bench
+    from paper_2007_10196_amd.solver import PtrList
+    probs = bench.make_problems(256)
+    solvers = [Solver(p, device="cuda:0", box_target=2048) for p in probs]
+    fine = solvers[0].plan.fine_nodes
+    outs = [torch.empty(fine, dtype=torch.float64, device="cuda:0") for _ in solvers]
+    exacts = [s.exact(bench.T_FINAL) for s in solvers]
+    res = torch.zeros((256, 2), dtype=torch.float64, device="cuda:0")
+    S, O_, E = PtrList(solvers), PtrList(outs), PtrList(exacts)
+    sent = bench.StepNorms(torch, res)
+    batch = Batch(max_solvers=256, precision=B.FP32_SWEEP, hbm_budget=sum(s.plan.footprint for s in solvers) + (1 << 30),
+                  max_items=sum(len(s.plan.grids) * 64 for s in solvers))
+    batch.set_blocks_per_cu(7)
+    _announce("bench step, 256 solves")
+    bench.run_batch_step(torch, batch, S, O_, E, res, sent)
+    norms = sent.take()
+    torch.cuda.synchronize()
+    for i in (0, 85, 170, 255):
+        _announce(f"oracle solve {i}")
+        st_o, U_o, stats = oracle_solve(probs[i].replace(precision=W.PREC_FP64))
+        U = outs[i].cpu().numpy()
+        e = np.abs(U - U_o)
+        print(f"  solve {i}: fp32 L1 {e.mean():.3e} Linf {e.max():.3e} against the fp64 oracle")
+        assert e.mean() < 2e-6 and e.max() < 2e-5, (i, e.mean(), e.max())
+        ex = exacts[i].cpu().numpy()
+        assert abs(norms[i, 0] - np.abs(U - ex).mean()) <= 1e-12 * max(1.0, norms[i, 0])
+        assert norms[i, 1] == np.abs(U - ex).max()
+    batch.release_many(list(batch.slots))
+    batch.close()
+
+
 def test_valu_calibration_hook_runs_every_class():
     """The issue-rate measurement hook launches each instruction class and reports the wave64
     instructions per SIMD that its timing is divided by."""
