@@ -25,7 +25,11 @@
  *
  * Readings of points the paper leaves open (all of them listed in the design
  * notes of the repository):
- *   - epsilon = 1e-6 in both the flux weights and the interpolation weights;
+ *   - epsilon = 1e-3 in both the flux weights of eq. (2.6) and the interpolation
+ *     weights of eq. (eqnlnwe) (the paper only calls it small and positive; the
+ *     single-grid and sparse-grid WENO rows of Tables ex3aweno and ex3-baweno
+ *     reproduce to their printed digits with 1e-3 and not with 1e-6).  The value
+ *     is an argument (orc_config.eps_flux, .eps_interp) supplied by the caller;
  *   - the LF speed alpha is global per component grid, per direction and per
  *     Runge-Kutta stage, taken over the stage input;
  *   - CFL time step dt = CFL / sum_k (A_k / h_k^fine), A_k the maximum wave

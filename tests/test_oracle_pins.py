@@ -368,3 +368,105 @@ def test_sparse_grid_burgers_converges():
     # sparse-grid WENO errors fall quickly with the root grid (Table ex3aweno trend)
     e = [O.solve_errors(W.paper_example3a(nr * 8, nr=nr, nl=3))[0] for nr in (5, 10)]
     assert e[1] < e[0] / 10
+
+
+# --------------------------------------------------------------------------- 4D Vlasov branch (Sec. 3.4 setting)
+
+def _vlasov_single(n, T=0.5, amp=0.01):
+    """The 4D phase-space workload on one full grid of n^4 nodes (finest level 0)."""
+    return W.c4_vlasov_4d(nr=n, nl=0, precision=W.PREC_FP64, T=T).replace(flux_params=(amp, 0.5))
+
+
+def _foot_by_scipy(x, t, amp, kE):
+    """Foot of the characteristic through x at time t: x_k' = v_k, v_k' = amp sin(kE x_k), integrated
+    back to 0 by a library ODE solver (DOP853), independently of the oracle's own integrator."""
+    from scipy.integrate import solve_ivp
+    y = np.array(x, dtype=float)
+    m = len(x) // 2
+    for k in range(m):
+        sol = solve_ivp(lambda s, z: [z[1], amp * math.sin(kE * z[0])], (t, 0.0), [x[k], x[m + k]],
+                        method="DOP853", rtol=1e-13, atol=1e-14)
+        y[k], y[m + k] = sol.y[0, -1], sol.y[1, -1]
+    return y
+
+
+def _maxwell_cos(pb, y):
+    """f0 of the 4D workload written out: exp(-|v|^2/2)/(2 pi) (1 + a cos(k x1 + p1) cos(k x2 + p2))."""
+    a, k, p1, p2 = pb.ic_params[:4]
+    return math.exp(-0.5 * (y[2] ** 2 + y[3] ** 2)) / (2 * math.pi) * (
+        1 + a * math.cos(k * y[0] + p1) * math.cos(k * y[1] + p2))
+
+
+@pytest.mark.parametrize("amp", [0.01, 0.3, -0.3])
+def test_vlasov_exact_solution_matches_an_independent_characteristic_solve(amp):
+    # f is constant along x' = v, v' = E(x): the oracle's exact value is f0 at the foot.  The foot
+    # here comes from scipy's DOP853 and f0 is written out; a flipped field sign, swapped x/v
+    # roles or a wrong Maxwellian normalisation in the oracle's exact solution fails this.
+    pb = W.c4_vlasov_4d(precision=W.PREC_FP64).replace(flux_params=(amp, 0.5), ic_params=(0.05, 0.5, 0.3, 1.1))
+    rng = np.random.default_rng(20)
+    for _ in range(6):
+        x = rng.uniform([0, 0, -4, -4], [4 * math.pi, 4 * math.pi, 4, 4])
+        for t in (0.4, 1.0):
+            ref = _maxwell_cos(pb, _foot_by_scipy(x, t, amp, 0.5))
+            assert O.exact(pb, x, t) == pytest.approx(ref, rel=1e-11, abs=1e-15)
+
+
+def test_vlasov_characteristics_conserve_the_pendulum_energy():
+    # Each (x_k, v_k) pair is a pendulum x'' = amp sin(kE x): H = v^2/2 + (amp/kE) cos(kE x) is
+    # constant along it.  Read the foot back through f0 = exp(-|v|^2/2)(...) with the x perturbation
+    # switched off and one velocity zero, so f0 = exp(-v_1^2/2)/(2 pi) fixes |v_1| at the foot.
+    amp, kE = 0.3, 0.5
+    pb = W.c4_vlasov_4d(precision=W.PREC_FP64).replace(flux_params=(amp, kE), ic_params=(0.0, 0.5, 0.0, 0.0))
+    rng = np.random.default_rng(21)
+    for _ in range(10):
+        x1, v1 = rng.uniform(0, 4 * math.pi), rng.uniform(-2, 2)
+        t = 1.0
+        f = O.exact(pb, np.array([x1, 0.0, v1, 0.0]), t)
+        v_foot_sq = -2.0 * math.log(f * 2 * math.pi)
+        # x_2 = 0, v_2 = 0 is a fixed point of the second pendulum (sin 0 = 0), so only pair 1 moves
+        x_foot = _foot_by_scipy([x1, 0.0, v1, 0.0], t, amp, kE)[0]
+        H_now = 0.5 * v1 * v1 + amp / kE * math.cos(kE * x1)
+        H_foot = 0.5 * v_foot_sq + amp / kE * math.cos(kE * x_foot)
+        assert H_foot == pytest.approx(H_now, abs=1e-10)
+
+
+def test_vlasov_maxwellian_has_unit_velocity_integral():
+    # the Maxwellian exp(-|v|^2/2)/(2 pi) integrates to 1 over v in R^2; the periodic node sum over
+    # [-6, 6) misses the tail beyond |v_k| = 6 and the node v_k = 6 (together 7e-9); the perturbation
+    # 1 + a cos(x1/2) cos(x2/2) averages to 1 over the x period 4 pi
+    n = 24
+    pb = W.c4_vlasov_4d(nr=n, nl=0, precision=W.PREC_FP64).replace(ic_params=(0.3, 0.5, 0.7, 0.2))
+    f = O.restrict(pb).reshape(n, n, n, n)           # axes (v2, v1, x2, x1)
+    hx, hv = 4 * math.pi / n, 12.0 / n
+    rho = f.sum(axis=(0, 1)) * hv * hv               # density at every x node
+    a, k, p1, p2 = pb.ic_params
+    xs = np.arange(n) * hx
+    pert = 1 + a * np.cos(k * xs[None, :] + p1) * np.cos(k * xs[:, None] + p2)
+    assert np.max(np.abs(rho - pert)) < 1e-8
+    assert rho.sum() * hx * hx == pytest.approx((4 * math.pi) ** 2, rel=1e-8)
+
+
+def test_vlasov_solve_converges_to_the_characteristic_solution():
+    # The oracle's march (flux v_k f in x_k, E_k(x_k) f in v_k, eq. (1) in phase space) on full
+    # grids n^4 at T = 0.5 against the exact solution: errors fall with n (observed 1.0e-5, 4.4e-6,
+    # 1.5e-6 at n = 8, 12, 16; pre-asymptotic on these coarse grids, local order > 3 at the end).
+    errs = []
+    for n in (8, 12, 16):
+        l1, _, st = O.solve_errors(_vlasov_single(n))
+        errs.append(l1)
+    assert errs[0] < 2e-5 and errs[2] < 2e-6, errs
+    order = math.log(errs[1] / errs[2]) / math.log(16 / 12)
+    assert order > 3.0, (errs, order)
+
+
+@pytest.mark.parametrize("amp", [0.01, 0.3])
+def test_vlasov_solve_follows_the_field_sign(amp):
+    # the same solve measured against the exact solution of the opposite field is far worse: a sign
+    # error in E_k f (or a field in the wrong direction) would swap these two errors
+    n = 16 if amp == 0.01 else 12
+    pb = _vlasov_single(n, amp=amp)
+    U, _, st = O.solve(pb)
+    l1 = O.norms(U, O.exact_fine(pb, st["t"]))[0]
+    l1_flip = O.norms(U, O.exact_fine(pb.replace(flux_params=(-amp, 0.5)), st["t"]))[0]
+    l1_free = O.norms(U, O.exact_fine(pb.replace(flux_params=(0.0, 0.5)), st["t"]))[0]
+    assert l1_flip > 8 * l1 and l1_free > 4 * l1, (l1, l1_flip, l1_free)
