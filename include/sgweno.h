@@ -27,7 +27,9 @@
  *   - Arrays on component grids and on the finest grid are row-major with
  *     direction 1 fastest: index = j_1 + n_1 (j_2 + n_2 (j_3 + n_3 j_4)).
  *     Node j of direction k sits at x = lo_k + j h_k, h_k = (hi_k - lo_k)/n_k,
- *     periodic (node n_k is node 0).
+ *     periodic (node n_k is node 0; sgw_problem.bc).
+ *   - Measurement hooks that are not part of the method (stage-launch timing,
+ *     VALU issue-rate calibration) are declared in sgweno_measure.h.
  */
 #ifndef SGWENO_H
 #define SGWENO_H
@@ -75,12 +77,20 @@ typedef int32_t sgw_status;
                                    /* one stage box take all three stages in one launch                 */
 #define SGW_RUN_GRAPH 2            /* SGW_RUN_FUSED with each time step captured in a HIP graph         */
 
+/* Boundary condition per direction (the examples of Sec. 3 are periodic; the
+ * phase-space examples of Sec. 3.4 set the ghost values outside the velocity
+ * domain to zero).  SGW_BC_ZERO is reserved: plans that ask for it are refused
+ * with SGW_ERR_UNSUPPORTED. */
+#define SGW_BC_PERIODIC 0          /* node n_k is node 0                                              */
+#define SGW_BC_ZERO 1              /* the three ghost values beyond either end are 0 (reserved)       */
+
 typedef struct sgw_problem {
     int32_t dim;                   /* 1..4                                                   */
     int32_t flux;                  /* SGW_FLUX_*                                              */
     int32_t ic;                    /* SGW_IC_*                                                */
     int32_t reserved0;             /* must be 0                                               */
-    double lo[SGW_MAX_DIM];        /* domain [lo_k, hi_k), periodic in every direction        */
+    int32_t bc[SGW_MAX_DIM];       /* SGW_BC_* per direction; entries beyond dim are ignored  */
+    double lo[SGW_MAX_DIM];        /* domain [lo_k, hi_k)                                     */
     double hi[SGW_MAX_DIM];
     double flux_params[SGW_MAX_DIM];
     double ic_params[8];
@@ -117,8 +127,9 @@ typedef struct sgw_batch sgw_batch_t;
  * N_r 2^{l_k} nodes in direction k.  Errors: SGW_ERR_INVALID_ARG for dim
  * outside 1..4, N_r < 4, N_L outside 0..12, cfl outside (0, 1.5], eps <= 0,
  * a Vlasov flux with odd dim, a finest grid with more than 2^40 nodes, box_target
- * outside 64..2048 or blocks_per_cu outside 0..64; SGW_ERR_UNSUPPORTED for a box
- * or tile that does not divide the extents or does not fit one workgroup.  With
+ * outside 64..2048, blocks_per_cu outside 0..64, reserved0 not 0 or an unknown
+ * boundary condition; SGW_ERR_UNSUPPORTED for a box or tile that does not divide
+ * the extents or does not fit one workgroup, and for SGW_BC_ZERO.  With
  * fine_tile 0 the prolongation tile is searched over divisors of the finest
  * extent (interpolations, staging, writes and LDS occupancy weighed). */
 sgw_status sgw_plan_create(const sgw_problem* problem, const sgw_config* config, sgw_plan_t** out);
@@ -241,8 +252,9 @@ sgw_status sgw_set_grid(sgw_solver_t* solver, int32_t g, const void* src_dev);
 /* Checkpoint of a running solve: u^n of every grid, the wave-speed slots and the
  * time record (t, steps, last dt, flags), sgw_snapshot_bytes(solver) bytes of
  * device memory, written or read in stream order.  sgw_restore resumes a solver
- * of the same plan from it (the final time stays the solver's own); refused
- * while the solver is in a batch. */
+ * of the same plan from it (the final time stays the solver's own).  Both are
+ * refused (SGW_ERR_STATE) while the solver is in a batch: the batch advances it
+ * on the batch stream, so a copy on the solver stream could mix two steps. */
 uint64_t sgw_snapshot_bytes(const sgw_solver_t* solver);
 sgw_status sgw_snapshot(sgw_solver_t* solver, void* dst_dev);
 sgw_status sgw_restore(sgw_solver_t* solver, const void* src_dev);
@@ -292,26 +304,6 @@ sgw_status sgw_batch_release(sgw_batch_t* batch, int32_t slot);
  * released).  One event marks the queued steps, and each distinct solver
  * stream waits for it once. */
 sgw_status sgw_batch_release_many(sgw_batch_t* batch, const int32_t* slots, int32_t n);
-/* Measurement hook, outside any graph (callers time it with events on the batch
- * stream).  stage 0..2: reps launches of that RK stage, one stage at a time,
- * over all of the batch's boxes; stage 0 writes only the first stage buffer, so
- * repeating it leaves u^n unchanged.  stage 3: reps times the stage launches of
- * one step as the step graph runs them (all three stages of the grids that are
- * one box in one launch, the other grids stage by stage); this advances u^n
- * without advancing t.  Either way the solves' wave-speed slots are disturbed,
- * so re-restrict before trusting later results. */
-sgw_status sgw_batch_launch_stage(sgw_batch_t* batch, int32_t stage, int32_t reps);
-/* Measurement hook for the VALU issue rates that price kernel issue floors (not
- * part of the method): enqueues on hip_stream one launch of `blocks` workgroups
- * of 256 threads running long chains of independent instructions of one class,
- * op 0 FP32 FMA, 1 FP32 multiply, 2 FP32 add, 3 INT32 add + xor, 4 FP64 FMA.
- * out_dev (device) receives one value per thread: blocks * 256 * 8 bytes.
- * *instructions_per_simd receives the wave64 instructions of the class each SIMD
- * issues (host, written before return); the caller times the launch with events,
- * so cycles per instruction = seconds * clock / *instructions_per_simd.  Returns
- * without waiting for the device. */
-sgw_status sgw_calibrate_valu(int32_t op, int32_t blocks, void* out_dev, void* hip_stream,
-                              double* instructions_per_simd);
 /* Tuning knob: at most blocks_per_cu resident stage workgroups per compute unit
  * (0: as many as fit).  The persistent stage launch splits the box list into
  * equal contiguous ranges over its workgroups, so this trades latency hiding

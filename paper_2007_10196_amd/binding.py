@@ -21,6 +21,7 @@ IC_SINE, IC_MAXWELL_COS = 0, 1
 DT_CFL, DT_POW53 = 0, 1
 PROLONG_WENO5, PROLONG_LAGRANGE5 = 0, 1
 FP64, FP32_SWEEP = 0, 1
+BC_PERIODIC, BC_ZERO = 0, 1
 RUN_PLAIN, RUN_FUSED, RUN_GRAPH = 0, 1, 2
 
 
@@ -32,7 +33,7 @@ class SgwError(RuntimeError):
 
 class Problem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("flux", C.c_int32), ("ic", C.c_int32), ("reserved0", C.c_int32),
-                ("lo", C.c_double * 4), ("hi", C.c_double * 4), ("flux_params", C.c_double * 4),
+                ("bc", C.c_int32 * 4), ("lo", C.c_double * 4), ("hi", C.c_double * 4), ("flux_params", C.c_double * 4),
                 ("ic_params", C.c_double * 8)]
 
 
@@ -132,12 +133,13 @@ def _pad(v, n, fill=0.0):
 def make_structs(pb, box=None, fine_tile=None, box_target=0, blocks_per_cu=0):
     """Problem/Config structs from a problem description with the fields of
     sgw_inputs.Problem (d, lo, hi, flux, flux_params, ic, ic_params, nr, nl, cfl,
-    dt_mode, prolong, linear, precision, eps_flux, eps_interp)."""
+    dt_mode, prolong, linear, precision, eps_flux, eps_interp, bc)."""
     p = Problem()
     p.dim = pb.d
     p.flux = pb.flux
     p.ic = pb.ic
     p.reserved0 = 0
+    p.bc[:] = _pad(getattr(pb, "bc", ()) or (), 4, BC_PERIODIC)
     p.lo[:] = _pad(pb.lo, 4)
     p.hi[:] = _pad(pb.hi, 4)
     p.flux_params[:] = _pad(pb.flux_params, 4)

@@ -345,6 +345,13 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
         return sgw_fail(SGW_ERR_INVALID_ARG, "epsilon must be positive");
     if (pb->flux < 0 || pb->flux > 2) return sgw_fail(SGW_ERR_INVALID_ARG, "unknown flux %d", pb->flux);
     if (pb->ic < 0 || pb->ic > 1) return sgw_fail(SGW_ERR_INVALID_ARG, "unknown initial condition %d", pb->ic);
+    if (pb->reserved0 != 0) return sgw_fail(SGW_ERR_INVALID_ARG, "reserved0 must be 0");
+    for (int k = 0; k < d; k++) {
+        if (pb->bc[k] != SGW_BC_PERIODIC && pb->bc[k] != SGW_BC_ZERO)
+            return sgw_fail(SGW_ERR_INVALID_ARG, "unknown boundary condition %d in direction %d", pb->bc[k], k);
+        if (pb->bc[k] != SGW_BC_PERIODIC)
+            return sgw_fail(SGW_ERR_UNSUPPORTED, "boundary condition %d in direction %d (only periodic)", pb->bc[k], k);
+    }
     if ((pb->flux == SGW_FLUX_VLASOV_FIXED_E || pb->ic == SGW_IC_MAXWELL_COS) && (d % 2))
         return sgw_fail(SGW_ERR_INVALID_ARG, "phase-space problems need an even dim");
     if (cfg->dt_mode != SGW_DT_CFL && cfg->dt_mode != SGW_DT_POW53)
@@ -816,6 +823,8 @@ extern "C" sgw_status sgw_snapshot(sgw_solver_t* s, void* dst_dev)
 {
     if (!s || !dst_dev) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
     if (!s->restricted) return sgw_fail(SGW_ERR_STATE, "snapshot before restrict");
+    // a batch advances the solver on the batch stream: a copy on the solver stream could tear
+    if (s->batch_slot >= 0) return sgw_fail(SGW_ERR_STATE, "solver is in a batch");
     const sgw_plan* p = s->plan;
     unsigned char* d = (unsigned char*)dst_dev;
     HIPCHK(hipMemcpyAsync(d, s->state, p->copy_bytes, hipMemcpyDeviceToDevice, s->stream), "snapshot state");

@@ -6,6 +6,7 @@
 #include <cstdint>
 
 #include "sgweno.h"
+#include "sgweno_measure.h"
 
 #define SGW_BLOCK 256     // threads per workgroup of every kernel (4 wave64)
 #define SGW_MAXR 8        // nodes per thread in the stage kernel: box core <= SGW_BLOCK * SGW_MAXR

@@ -42,6 +42,9 @@ PROLONG_LAGRANGE5 = 1
 PREC_FP64 = 0
 PREC_FP32 = 1
 
+BC_PERIODIC = 0
+BC_ZERO = 1
+
 
 @dataclasses.dataclass
 class Problem:
@@ -66,6 +69,8 @@ class Problem:
     eps_flux: float = 1e-3
     eps_interp: float = 1e-3
     name: str = ""
+    # boundary condition per direction: 0 periodic (every workload here), 1 zero ghost values
+    bc: Tuple[int, ...] = ()
 
     def replace(self, **kw) -> "Problem":
         return dataclasses.replace(self, **kw)

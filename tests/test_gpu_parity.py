@@ -697,6 +697,26 @@ def test_set_grid_equals_restriction_bitwise():
         assert torch.equal(a.prolongate_combine(), b.prolongate_combine())
 
 
+def test_snapshot_and_restore_are_refused_while_in_a_batch():
+    """A batch advances its solvers on the batch stream, so a checkpoint copy on the solver's own
+    stream could mix two steps: both calls are refused until the solver is released."""
+    torch, B, Solver, Batch = _lib()
+    pb = W.c2_burgers_2d(nl=2, T=0.05, precision=W.PREC_FP32)
+    _announce("snapshot refused in a batch")
+    s = Solver(pb).restrict()
+    snap = s.snapshot()
+    batch = Batch(4, pb.precision, 1 << 30)
+    slot = batch.admit(s)
+    for call in (lambda: s.snapshot(), lambda: s.restore(snap)):
+        with pytest.raises(B.SgwError) as e:
+            call()
+        assert e.value.status == -6
+    batch.step(4)
+    batch.release(slot)
+    s.snapshot()
+    torch.cuda.synchronize()
+
+
 def test_snapshot_restore_resumes_bitwise():
     """A solve stopped at T/2 and checkpointed, then resumed in another solver, ends bitwise where the
     original solver ends when it simply continues (stopping at T/2 itself adds a clipped step)."""

@@ -12,13 +12,18 @@ from paper_2007_10196_amd import binding as B
 from paper_2007_10196_amd.solver import Plan
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "sgweno.h")
+INCLUDE = os.path.join(ROOT, "include")
 
 
 def _declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return set(re.findall(r"\b(sgw_[a-z_0-9]+)\s*\(", src))
+    names = set()
+    for h in sorted(os.listdir(INCLUDE)):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(INCLUDE, h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(sgw_[a-z_0-9]+)\s*\(", src))
+    return names
 
 
 def test_library_exports_every_declared_symbol():
@@ -89,6 +94,9 @@ def test_plan_rejects_invalid_arguments():
     _expect_status(good, -2, box=[3, 3])          # 3 does not divide 4 << l
     _expect_status(good, -2, fine_tile=[5, 5])    # 5 does not divide 32
     _expect_status(good, -1, box_target=32)
+    _expect_status(good.replace(bc=(0, 2)), -1)     # unknown boundary condition
+    _expect_status(good.replace(bc=(0, 1)), -2)     # zero ghost values: reserved, refused
+    Plan(good.replace(bc=(0, 0, 1, 1)))            # entries beyond dim are ignored
 
 
 def test_error_strings():
