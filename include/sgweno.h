@@ -237,6 +237,21 @@ sgw_status sgw_norms_many(sgw_solver_t* const* solvers, const double* const* a_d
                           int32_t n, double* result_dev, void* scratch_dev, uint64_t scratch_bytes, void* hip_stream);
 uint64_t sgw_norms_many_scratch_bytes(sgw_solver_t* const* solvers, int32_t n);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): sgw_norms_many for n <= 32 pairs with
+ * no scratch argument and no allocation of any kind.  The pair list and partial
+ * sums live in a library-owned device array of sgw_norms_many_static_max_bytes()
+ * bytes (about 514 KiB), one per device, held until the process ends.  Results
+ * are bitwise those of sgw_norms_many.  Runs on hip_stream only: unlike
+ * sgw_norms_many it makes no stream wait on the solvers' own streams, so the
+ * caller orders the writes of a and b before it.  Calls on one device share the
+ * array: two calls whose launches overlap on one device (different streams, no
+ * ordering between them) race and give wrong results.  n above 32 is refused
+ * with SGW_ERR_INVALID_ARG.  Returns without waiting for the device. */
+sgw_status sgw_norms_many_static(sgw_solver_t* const* solvers, const double* const* a_dev,
+                                 const double* const* b_dev, int32_t n, double* result_dev, void* hip_stream);
+uint64_t sgw_norms_many_static_max_bytes(void);
+
 /* Current time and number of steps taken; synchronises.  Returns
  * SGW_ERR_NONFINITE if a wave speed or dt became NaN/Inf. */
 sgw_status sgw_query(sgw_solver_t* solver, double* t, int64_t* steps);

@@ -81,6 +81,9 @@ _SIGS = {
     "sgw_norms_many": (C.c_int32, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32,
                                    C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p]),
     "sgw_norms_many_scratch_bytes": (C.c_uint64, [C.POINTER(C.c_void_p), C.c_int32]),
+    "sgw_norms_many_static": (C.c_int32, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                          C.c_int32, C.c_void_p, C.c_void_p]),
+    "sgw_norms_many_static_max_bytes": (C.c_uint64, []),
     "sgw_batch_create": (C.c_int32, [C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p, C.c_uint64,
                                      C.POINTER(C.c_void_p)]),
     "sgw_batch_free": (None, [C.c_void_p]),

@@ -397,3 +397,18 @@ def norms_many(solvers, a, b, result: torch.Tensor, stream: Optional[torch.cuda.
     B.check(B.lib().sgw_norms_many(hs, pa, pb, n, C.c_void_p(result.data_ptr()), C.c_void_p(scratch.data_ptr()),
                                    nbytes, _stream_handle(stream)))
     return result
+
+
+def norms_many_static(solvers, a, b, result: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
+    """norms_many for at most 32 pairs without any allocation: the library keeps the pair list
+    and partial sums in its own device array.  Runs on `stream` (default: the current stream)
+    only, so the caller orders the writes of a and b before it."""
+    n = len(solvers)
+    assert len(a) == n and len(b) == n
+    assert result.dtype == torch.float64 and result.is_cuda and result.is_contiguous() and result.numel() >= 2 * n
+    for x, y, s in zip(a, b, solvers):
+        assert x.dtype == torch.float64 and x.numel() >= s.plan.fine_nodes
+        assert y.dtype == torch.float64 and y.numel() >= s.plan.fine_nodes
+    B.check(B.lib().sgw_norms_many_static(_ptrs(solvers, "solver"), _ptrs(a, "tensor"), _ptrs(b, "tensor"), n,
+                                          C.c_void_p(result.data_ptr()), _stream_handle(stream)))
+    return result
