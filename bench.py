@@ -1,19 +1,21 @@
 #!/usr/bin/env python
 """Benchmark of the sparse-grid WENO5 hot path on one MI355X.
 
-One step = the whole method over one batch of synthetic solves of the 2D
-Burgers workload (u_t + (u^2/2)_x + (u^2/2)_y = 0 on [-1,1]^2, u0 = 0.3 + A
-sin(pi(x+y) + phi) with seeded A, phi; root grid 8x8, finest level 5 (256x256),
-CFL 0.5, T = 1.5/pi^2): restriction, the shared-dt TVD-RK3 march of all 11
-component grids of every solve (batched: one graph per time step, one
-persistent stage launch over all boxes), WENO5 prolongation + FP64 combination,
-and the L1/Linf norms against the exact solution.  Sweeps run in FP32, the
-combination and norms in FP64.
+One step = the whole method for one solve of the 4D Vlasov workload at FP64
+(f_t + v.grad_x f + E(x).grad_v f = 0, x in [0,4pi]^2, v in [-6,6]^2, periodic,
+E = 0.01 (sin(x1/2), sin(x2/2)), f0 = Maxwellian x (1 + 0.01 cos(x1/2) cos(x2/2));
+root grid 8^4, finest level 4 (128^4 finest nodes), 69 component grids,
+CFL 0.4, T = 1, 307 time steps): restriction, the shared-dt TVD-RK3 march of
+every component grid (step graphs, one persistent stage launch per RK stage over
+all boxes), WENO5 prolongation + FP64 combination onto the finest grid, and the
+L1/Linf norms against the exact solution (computed once, before timing).
 
-Prints one JSON line.  Extra keys: the plain per-grid FP64 method on the same
-workload (equal-L1 comparison), the event-timed stage kernel against its
-roofline, the FP64 oracle timed on the host, serving latencies, the same solves
-on one full grid, and the same batched path with FP64 sweeps.
+Prints one JSON line.  `value` is component-grid cell-updates per second of
+that solve.  Extra keys: the same solve with FP32 sweeps, the plain per-grid
+FP64 method on the same solve (equal-L1 comparison), the stage and
+prolongation kernels against their rooflines (HIP events), the FP64 oracle on
+the host (a bounded sample), the batched 2D Burgers workload (256 solves per
+step, FP32 and FP64), the same 2D solves on one full grid, and serving latencies.
 
 --path-workload c3|c4 instead times one 3D advection or 4D Vlasov solve through
 the path (stage launches of a step, march, prolongation) and prints its own line.
@@ -39,12 +41,39 @@ PEAK_HBM_GBS = 8000.0
 T_FINAL = 1.5 / math.pi ** 2
 
 
-def flops_per_node_stage(d: int, stage: int) -> int:
-    """Algorithmic flops of one RK stage at one node (counted from the paper's formulas):
-    per direction two WENO5 reconstructions of 70 flops each (3 candidates x 5, 3 smoothness
-    indicators x 12, 3 weights x 3, normalisation 5, combination 5), 6 for the flux and its
-    LF split, 3 for the difference of eq. (2.9); plus the RK combination (2, 5, 5)."""
-    return d * (2 * 70 + 6 + 3) + (2, 5, 5)[stage]
+def flops_per_node_stage(d: int) -> int:
+    """Algorithmic flops of one RK stage at one node: per direction two WENO5 reconstructions
+    (about 65 flops each: 3 candidate stencils, 3 smoothness indicators, 3 nonlinear weights and
+    their normalisation) plus the flux, its Lax-Friedrichs split and the flux difference of
+    eq. (2.9), 140 in all; plus 5 for the Runge-Kutta combination."""
+    return 140 * d + 5
+
+
+def flops_per_cell_update(d: int) -> int:
+    """One component node advanced one full TVD-RK3 step: three stages."""
+    return 3 * flops_per_node_stage(d)
+
+
+INTERP_FLOPS = 30  # per interpolated point, the smoothness indicators shared by the R points of a coarse interval
+
+
+def interpolation_count(plan) -> int:
+    """Interpolated points of the direction-by-direction prolongation of every component grid
+    over whole arrays: the pass along direction k (k = 1..d, refined only where the grid is
+    coarser than the finest grid) produces N^k x prod_{k' > k} n_k' points."""
+    N = plan.problem.n_fine
+    total = 0
+    for g in plan.grids:
+        n = list(g["shape"])
+        for k in range(len(n)):
+            if n[k] == N:
+                continue
+            n[k] = N
+            pts = 1
+            for x in n:
+                pts *= x
+            total += pts
+    return total
 
 
 def make_problems(n, seed=2007_10196):
@@ -118,25 +147,30 @@ def run_batch_step(torch, batch, solvers, outs, exacts, res, sent):
     return prev
 
 
-STAGE_SRC = os.path.join(ROOT, "paper_2007_10196_amd", "csrc", "kernels_stage.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_c2_batch256_traffic.json")
+CSRC = os.path.join(ROOT, "paper_2007_10196_amd", "csrc")
+# HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs, keyed to the hash of
+# the kernel's source file: (summary file under profiles/, source file)
+TRAFFIC = {"stage_c2_fp32": ("stage_kernel_c2_batch256_traffic.json", "kernels_stage.hip"),
+           "stage_c4_fp64": ("stage_kernel_c4_vlasov_4d_fp64_traffic.json", "kernels_stage.hip"),
+           "prolong_c4_fp64": ("prolong_kernel_c4_vlasov_4d_fp64_traffic.json", "kernels_prolong.hip")}
 
 
-def stage_source_hash():
+def source_hash(name):
     import hashlib
-    with open(STAGE_SRC, "rb") as f:
+    with open(os.path.join(CSRC, name), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs,
-    or None when the stage kernel source changed since they were taken."""
+def measured_traffic(key):
+    """HBM bytes per launch of a kernel from its committed counter summary, or None when the
+    kernel's source changed since the counters were taken (or none were taken)."""
+    fname, src = TRAFFIC[key]
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(ROOT, "profiles", fname)) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256_16") != stage_source_hash():
+    if rec.get("kernel_source_sha256_16") != source_hash(src):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -261,31 +295,48 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(budget_s=15.0, single_budget_s=5.0):
-    """The oracle on the host: all OpenMP threads for about budget_s, then one thread (the paper's
-    setting) for about single_budget_s, on the same solves."""
+def cpu_baseline(march_steps=12, single_steps=1):
+    """The FP64 oracle on the host for the 4D Vlasov solve of the headline, on a bounded sample:
+    `march_steps` time steps on all OpenMP threads (and `single_steps` on one thread, the paper's
+    setting), plus the oracle's prolongation + combination of the same workload at finest level 2
+    (32^4), scaled to the full solve by the interpolation count.  The estimated solve time is
+    307 x (seconds per step) + (seconds per interpolation) x (interpolations of the full solve)."""
     import oracle as O
-    probs = make_problems(512)
+    from paper_2007_10196_amd.solver import Plan
+    pb = W.c4_vlasov_4d(precision=W.PREC_FP64)
+    nodes = O.total_nodes(pb)
+    steps_full = step_estimate_any(pb)
+    interp_full = interpolation_count(Plan(pb))
+    st = O.restrict(pb)
+    dt = pb.T / steps_full
 
-    def run(budget, nthreads):
+    def march(nsteps, nthreads):
         t0 = time.perf_counter()
-        cells = n = 0
-        for p in probs:
-            pb = p.replace(precision=W.PREC_FP64)
-            _, _, stats = O.solve(pb, nthreads=nthreads)
-            cells += stats["steps"] * O.total_nodes(pb)
-            n += 1
-            if time.perf_counter() - t0 > budget:
-                break
-        return cells / (time.perf_counter() - t0), n, time.perf_counter() - t0
+        stats = O.evolve(pb, st, T=(nsteps - 0.5) * dt, nthreads=nthreads)
+        return (time.perf_counter() - t0) / stats["steps"], stats["steps"]
 
-    cores = O.max_threads()
-    v, n, dt = run(budget_s, 0)
-    v1, n1, dt1 = run(single_budget_s, 1)
-    return {"value": v, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} solves of the same 2D Burgers workload (FP64, full method incl. prolongation), "
-                      f"{dt:.1f} s wall, OpenMP over component grids",
-            "single_thread_value": v1, "single_thread_sample": f"{n1} solves in {dt1:.1f} s on one thread",
+    sec_step, n_all = march(march_steps, 0)
+    sec_step1, n_one = march(single_steps, 1)
+    small = pb.replace(nl=2)
+    st_small = O.restrict(small)
+    t0 = time.perf_counter()
+    O.prolong_combine(small, st_small)
+    t_pro_small = time.perf_counter() - t0
+    interp_small = interpolation_count(Plan(small))
+    sec_interp = t_pro_small / interp_small
+    solve_s = steps_full * sec_step + sec_interp * interp_full
+    solve_s1 = steps_full * sec_step1 + sec_interp * interp_full
+    cells = steps_full * nodes
+    return {"value": cells / solve_s, "unit": "cell-updates/s", "cores": O.max_threads(), "kind": "oracle",
+            "sample": f"4D Vlasov solve (FP64, root 8, finest level 4, 69 grids): {n_all} time steps on all "
+                      f"threads ({sec_step:.3f} s per step) + the prolongation and combination of the same "
+                      f"workload at finest level 2 ({interp_small} interpolations in {t_pro_small:.2f} s, one "
+                      f"thread), scaled to {steps_full} steps and {interp_full:.3e} interpolations: "
+                      f"{solve_s:.0f} s per solve",
+            "estimated_solve_s": solve_s, "march_s_per_step": sec_step, "prolong_s_per_interpolation": sec_interp,
+            "single_thread_value": cells / solve_s1,
+            "single_thread_sample": f"{n_one} time step(s) on one thread ({sec_step1:.2f} s per step), the same "
+                                    f"prolongation figure",
             "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
@@ -381,18 +432,311 @@ def valu_calibration():
     print(json.dumps({"valu_cycles_per_wave64_instruction": res, "clock_GHz": 2.4, "compute_units": cus}), flush=True)
 
 
+def ev(torch):
+    return torch.cuda.Event(enable_timing=True)
+
+
+def stage_launch_us(torch, pb, box_target, bpc, reps):
+    """Average duration of one stage-kernel launch over all boxes of the solve, in the launch
+    shape the step graphs use: HIP events on the batch stream around `reps` repetitions of the
+    stage launches of one step (the measurement hook), divided by the launches of a step.
+    Returns (microseconds per launch, launches per step, batch info)."""
+    from paper_2007_10196_amd.solver import Batch, Solver
+    s = Solver(pb, device="cuda:0", box_target=box_target, blocks_per_cu=bpc)
+    # grids that are one stage box take their three stages in one launch; the others one per stage
+    whole = [g["box"] == g["shape"] for g in s.plan.grids]
+    launches = (1 if any(whole) else 0) + (3 if not all(whole) else 0)
+    batch = Batch(max_solvers=1, precision=pb.precision, hbm_budget=1 << 40, max_items=1 << 20)
+    if bpc:
+        batch.set_blocks_per_cu(bpc)
+    s.restrict()
+    slot = batch.admit(s)
+    batch.step(1)
+    st = batch.stream
+    e0, e1 = ev(torch), ev(torch)
+    batch.launch_stage(3, 2)
+    e0.record(st)
+    batch.launch_stage(3, reps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    info = batch.info()
+    batch.release(slot)
+    batch.close()
+    return e0.elapsed_time(e1) * 1e3 / reps / launches, launches, info
+
+
+def solve_run(torch, pb, steps, warmup, box_target, bpc):
+    """`warmup` untimed and `steps` timed solves of pb through the whole path on one stream
+    (restriction, march, prolongation + combination, norms against the exact solution, which is
+    computed once before timing), then one more solve with each part event-timed."""
+    from paper_2007_10196_amd.solver import Solver
+    s = Solver(pb, device="cuda:0", box_target=box_target, blocks_per_cu=bpc)
+    out = torch.empty(s.plan.fine_nodes, dtype=torch.float64, device="cuda:0")
+    exact = s.exact(pb.T)
+    res = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+
+    def one():
+        s.restrict()
+        s.advance()
+        s.prolongate_combine(out)
+        s.norms_async(out, exact, res)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        one()
+        print(f"[bench] {pb.name} solve {k + 1}/{steps} queued", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    l1, linf = res.tolist()
+    t, nsteps = s.query()
+    # one more solve, each part between HIP events on the solver stream
+    e = [ev(torch) for _ in range(5)]
+    e[0].record(s.stream)
+    s.restrict()
+    e[1].record(s.stream)
+    s.advance()
+    e[2].record(s.stream)
+    s.prolongate_combine(out)
+    e[3].record(s.stream)
+    s.norms_async(out, exact, res)
+    e[4].record(s.stream)
+    torch.cuda.synchronize()
+    parts = {name: e[i].elapsed_time(e[i + 1]) for i, name in
+             enumerate(("restrict_ms", "march_ms", "prolong_combine_ms", "norms_ms"))}
+    return {"solver": s, "out": out, "exact": exact, "ms_per_solve": elapsed / steps * 1e3, "l1": l1, "linf": linf,
+            "t": t, "time_steps": nsteps, "parts": parts}
+
+
+def kernel_roofline(kernel, launch_us, flops, peak, traffic, extra):
+    ach = flops / (launch_us * 1e-6) / 1e12
+    out = {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+           "traffic": traffic, "kernel": kernel, "avg_launch_us": launch_us, "flops_per_launch": flops,
+           "hbm_GBs": traffic / (launch_us * 1e-6) / 1e9 if traffic else None,
+           "hbm_frac": traffic / (launch_us * 1e-6) / 1e9 / PEAK_HBM_GBS if traffic else None}
+    out.update(extra)
+    return out
+
+
+def c4_headline(args, torch):
+    """The 4D Vlasov solve at FP64 (value), its kernels against their rooflines, the same solve with
+    FP32 sweeps and the plain per-grid FP64 method on it."""
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.autotune import tune_box_target
+    from paper_2007_10196_amd.solver import Solver
+    pb = W.c4_vlasov_4d(precision=W.PREC_FP64)
+    if args.box_target:
+        tune = {"best": args.box_target, "blocks_per_cu": args.blocks_per_cu, "us": None, "cached": True}
+    else:
+        tune = tune_box_target([pb], pb.precision, reps=5)
+    bt, bpc = int(tune["best"]), int(tune.get("blocks_per_cu", 0))
+    print(f"[bench] 4D Vlasov FP64: box target {bt}, {bpc or 'max'} workgroups per CU "
+          f"({'cached' if tune['cached'] else 'measured'})", file=sys.stderr, flush=True)
+    r = solve_run(torch, pb, args.steps, args.warmup, bt, bpc)
+    s = r["solver"]
+    nodes, fine = s.plan.total_nodes, s.plan.fine_nodes
+    cells = r["time_steps"] * nodes
+    value = cells / (r["ms_per_solve"] * 1e-3)
+    print(f"[bench] 4D Vlasov FP64: {r['ms_per_solve']:.1f} ms per solve, {value:.3e} cell-updates/s, "
+          f"L1 {r['l1']:.3e}", file=sys.stderr, flush=True)
+
+    # ---- the two kernels that take the solve's time, against their rooflines
+    st_us, launches, info = stage_launch_us(torch, pb, bt, bpc, args.stage_reps)
+    stage_flops = nodes * flops_per_node_stage(pb.d)
+    stage = kernel_roofline(
+        "stage_kernel<double, 4, false> (one WENO5-LF + TVD-RK3 stage over every box of the solve)", st_us,
+        stage_flops, PEAK_FP64_TFLOPS, measured_traffic("stage_c4_fp64"),
+        {"launches_per_time_step": launches, "boxes_per_launch": info["boxes"], "nodes_per_launch": nodes,
+         "flops_per_node_stage": flops_per_node_stage(pb.d),
+         # u read and the stage output written (stage 1), plus u^n read (stages 2, 3): 8/3 words a launch
+         "algorithmic_bytes_per_launch": nodes * 8 * 8 // 3,
+         "time_per_solve_ms": st_us * launches * r["time_steps"] * 1e-3})
+    pro_us = r["parts"]["prolong_combine_ms"] * 1e3
+    interps = interpolation_count(s.plan)
+    prolong = kernel_roofline(
+        "prolong_kernel<double, 4> (WENO5 prolongation of the 69 grids and FP64 combination, one launch)",
+        pro_us, interps * INTERP_FLOPS, PEAK_FP64_TFLOPS, measured_traffic("prolong_c4_fp64"),
+        {"interpolations_per_launch": interps, "flops_per_interpolation": INTERP_FLOPS,
+         "algorithmic_bytes_per_launch": fine * 8 + nodes * 8,
+         "achieved_write_GBs": fine * 8 / (pro_us * 1e-6) / 1e9, "time_per_solve_ms": pro_us * 1e-3})
+    by_time = sorted((stage, prolong), key=lambda k: -k["time_per_solve_ms"])
+
+    # ---- the same solve with FP32 sweeps (FP64 combination and norms)
+    fp32 = None
+    if not args.no_fp32:
+        p32 = pb.replace(precision=W.PREC_FP32)
+        t32 = tune_box_target([p32], p32.precision, reps=5)
+        r32 = solve_run(torch, p32, args.steps, 1, int(t32["best"]), int(t32.get("blocks_per_cu", 0)))
+        d = (r32["out"] - r["out"]).abs()
+        fp32 = {"value": r32["time_steps"] * nodes / (r32["ms_per_solve"] * 1e-3), "unit": "cell-updates/s",
+                "ms_per_solve": r32["ms_per_solve"], "parts": r32["parts"], "l1": r32["l1"], "linf": r32["linf"],
+                "l1_vs_fp64_solution": float(d.mean()), "linf_vs_fp64_solution": float(d.max()),
+                "box_target": int(t32["best"]), "blocks_per_cu": int(t32.get("blocks_per_cu", 0))}
+        print(f"[bench] 4D Vlasov FP32 sweeps: {r32['ms_per_solve']:.1f} ms per solve, L1 {r32['l1']:.3e}",
+              file=sys.stderr, flush=True)
+        del r32, d
+
+    # ---- plain per-grid FP64 method (one launch per grid per RK stage, no graph) on the same solve
+    plain = None
+    if not args.no_plain:
+        sp = Solver(pb, device="cuda:0")
+        Up = torch.empty(fine, dtype=torch.float64, device="cuda:0")
+        for _ in range(2):
+            torch.cuda.synchronize()
+            tp = time.perf_counter()
+            sp.restrict()
+            sp.advance(mode=B.RUN_PLAIN)
+            sp.prolongate_combine(Up)
+            l1p, lip = sp.norms(Up, r["exact"])
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - tp
+        stp = sp.query()[1]
+        plain = {"value": stp * nodes / tp, "unit": "cell-updates/s",
+                 "mode": "plain: one launch per grid per RK stage, no graph, FP64", "ms_per_solve": tp * 1e3,
+                 "l1": l1p, "linf": lip, "speedup_of_value": value / (stp * nodes / tp),
+                 "equal_l1": bool(abs(r["l1"] - l1p) <= 0.01 * l1p)}
+        print(f"[bench] plain per-grid FP64: {tp * 1e3:.1f} ms per solve", file=sys.stderr, flush=True)
+        del sp, Up
+
+    head = {"value": value, "ms_per_solve": r["ms_per_solve"], "l1": r["l1"], "linf": r["linf"],
+            "time_steps": r["time_steps"], "t": r["t"], "nodes": nodes, "fine": fine, "parts": r["parts"],
+            "finest_equivalent_cell_updates_per_s": r["time_steps"] * fine / (r["ms_per_solve"] * 1e-3),
+            "roofline": by_time[0], "roofline_other": by_time[1], "fp32": fp32, "plain": plain,
+            "autotune": {"box_target": bt, "blocks_per_cu": bpc, "stage_us_by_target_and_cap": tune["us"]}}
+    del r
+    return head
+
+
+def c2_batched(args, torch):
+    """The batched 2D Burgers workload: 256 solves per step, FP32 sweeps (and FP64), the plain
+    per-grid method on one of them, and the same solves on one full 256x256 grid."""
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.autotune import tune_box_target
+    from paper_2007_10196_amd.solver import Batch, PtrList, Solver
+    dev = torch.device("cuda:0")
+    probs = make_problems(args.solves)
+    tune = tune_box_target(probs, B.FP32_SWEEP, reps=5)
+    box_target, bpc = int(tune["best"]), int(tune.get("blocks_per_cu", 0))
+    solvers = [Solver(p, device="cuda:0", box_target=box_target) for p in probs]
+    nodes = solvers[0].plan.total_nodes
+    fine = solvers[0].plan.fine_nodes
+    outs = [torch.empty(fine, dtype=torch.float64, device=dev) for _ in solvers]
+    exacts = [s.exact(T_FINAL) for s in solvers]
+    res = torch.zeros((len(solvers), 2), dtype=torch.float64, device=dev)
+    solvers, outs, exacts = PtrList(solvers), PtrList(outs), PtrList(exacts)
+    sent = StepNorms(torch, res)
+    budget = sum(s.plan.footprint for s in solvers) + (1 << 30)
+    batch = Batch(max_solvers=len(solvers), precision=B.FP32_SWEEP, hbm_budget=budget,
+                  max_items=sum(len(s.plan.grids) * 64 for s in solvers))
+    batch.set_blocks_per_cu(bpc)
+    run_batch_step(torch, batch, solvers, outs, exacts, res, sent)
+    sent.take()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run_batch_step(torch, batch, solvers, outs, exacts, res, sent)
+    norms = sent.take()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    steps_each = [s.query()[1] for s in solvers]
+    ms_per_step = elapsed / args.steps * 1e3
+    value = sum(n * nodes for n in steps_each) / (elapsed / args.steps)
+    l1s = norms[:, 0]
+    print(f"[bench] 2D Burgers x {len(probs)}: {ms_per_step:.2f} ms per step, {value:.3e} cell-updates/s",
+          file=sys.stderr, flush=True)
+
+    # the three-stage kernel alone (every grid of this workload is one stage box), HIP events on the
+    # batch stream, and the split kernel's stage 1 beside it
+    from paper_2007_10196_amd.solver import restrict_many
+    restrict_many(solvers, stream=batch.stream)
+    batch.admit_many(solvers)
+    batch.step(1)
+    st = batch.stream
+
+    def timed(stage, reps):
+        e0, e1 = ev(torch), ev(torch)
+        batch.launch_stage(stage, 2)
+        e0.record(st)
+        batch.launch_stage(stage, reps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    step_ms = timed(3, args.stage_reps)
+    split_ms = timed(0, args.stage_reps)
+    info = batch.info()
+    batch.release_many(list(batch.slots))
+    batch.close()
+    roof = kernel_roofline("stage_kernel<float, 2, fused> (three RK stages of every one-box grid)", step_ms * 1e3,
+                           info["nodes"] * flops_per_cell_update(2), PEAK_FP32_TFLOPS,
+                           measured_traffic("stage_c2_fp32"),
+                           {"boxes_per_launch": info["boxes"], "algorithmic_bytes_per_launch": info["nodes"] * 8,
+                            "split_stage_kernel_stage1_us": split_ms * 1e3})
+
+    plain = None
+    if not args.no_plain:
+        p64 = probs[0].replace(precision=W.PREC_FP64)
+        sp = Solver(p64, device="cuda:0")
+        Up = torch.empty(fine, dtype=torch.float64, device=dev)
+        Ep = sp.exact(T_FINAL)
+        for _ in range(2):
+            torch.cuda.synchronize()
+            tp = time.perf_counter()
+            sp.restrict()
+            sp.advance(mode=B.RUN_PLAIN)
+            sp.prolongate_combine(Up)
+            l1p, lip = sp.norms(Up, Ep)
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - tp
+        stp = sp.query()[1]
+        plain = {"value": stp * nodes / tp, "ms_per_solve": tp * 1e3, "l1": l1p, "linf": lip,
+                 "speedup_of_value": value / (stp * nodes / tp),
+                 "equal_l1": bool(abs(l1s[0] - l1p) <= 0.01 * l1p), "l1_batched_fp32_same_solve": float(l1s[0])}
+
+    batched_fp64 = None
+    if not args.no_fp64:
+        f = batch_run(torch, [p.replace(precision=W.PREC_FP64) for p in probs], box_target, bpc, steps=args.steps)
+        v64 = f["cell_updates_per_step"] / (f["ms_per_step"] * 1e-3)
+        batched_fp64 = {"value": v64, "ms_per_step": f["ms_per_step"], "l1_mean": f["l1_mean"],
+                        "fp32_speedup": value / v64,
+                        "plain_fp64_speedup": v64 / plain["value"] if plain else None}
+        print(f"[bench] 2D Burgers FP64 batched: {f['ms_per_step']:.2f} ms per step, {v64:.3e} cell-updates/s",
+              file=sys.stderr, flush=True)
+
+    full = None
+    if not args.no_full:
+        f = full_grid_run(torch, probs, box_target, bpc)
+        full = {"full_grid": "one 256x256 grid (root 256, finest level 0), same solves, same batched FP32 path",
+                "full_ms_per_step": f["ms_per_step"], "sparse_ms_per_step": ms_per_step,
+                "time_ratio_sparse_over_full": ms_per_step / f["ms_per_step"],
+                "l1_full": f["l1_mean"], "l1_sparse": float(l1s.mean()),
+                "nodes_full": f["nodes_per_solve"], "nodes_sparse": nodes, "time_steps_full": f["time_steps"]}
+
+    return {"workload": "2D Burgers u0=0.3+A sin(pi(x+y)+phi), [-1,1]^2 periodic, root 8x8, finest level 5 "
+                        "(256x256), 11 component grids, CFL 0.5, T=1.5/pi^2; FP32 sweeps, FP64 combination",
+            "solves_per_step": len(probs), "value": value, "unit": "cell-updates/s", "ms_per_step": ms_per_step,
+            "l1_mean": float(l1s.mean()), "l1_max": float(l1s.max()),
+            "mode": "batched: step graphs of 1..32 time steps, persistent fused WENO5+RK3 stage launch",
+            "roofline": roof, "plain_fp64_one_solve": plain, "batched_fp64": batched_fp64, "sparse_vs_full": full,
+            "autotune": {"box_target": box_target, "blocks_per_cu": bpc, "step_stage_us_by_target_and_cap": tune["us"]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=5, help="timed solves of the 4D workload (and timed 2D batch steps)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--solves", type=int, default=256, help="solves per step (batch size)")
+    ap.add_argument("--solves", type=int, default=256, help="2D solves per batched step")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-sweep run of the 4D solve")
+    ap.add_argument("--no-c2", action="store_true", help="skip the batched 2D Burgers workload")
     ap.add_argument("--stage-reps", type=int, default=20)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-full", action="store_true", help="skip the single full-grid comparison")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 batched run of the same solves")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 batched run of the 2D solves")
     ap.add_argument("--box-target", type=int, default=0,
                     help="0: autotune the stage box target and the workgroups per compute unit")
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="with --box-target: stage workgroups per CU")
@@ -421,161 +765,28 @@ def main():
         return
 
     import torch
-    from paper_2007_10196_amd import binding as B
-    from paper_2007_10196_amd.solver import Batch, PtrList, Solver
-
     torch.cuda.set_device(0)
-    dev = torch.device("cuda:0")
-    probs = make_problems(args.solves)
-    # box shape for this batch (untimed): fastest of the candidate targets, cached in JSON
-    from paper_2007_10196_amd.autotune import tune_box_target
-    if args.box_target:
-        tune = {"best": args.box_target, "blocks_per_cu": args.blocks_per_cu, "us": None, "cached": True}
-    else:
-        tune = tune_box_target(probs, B.FP32_SWEEP, reps=5)
-    box_target = int(tune["best"])
-    bpc = int(tune.get("blocks_per_cu", 0))
-    print(f"[bench] launch shape: box target {box_target}, {bpc or 'max'} workgroups per CU "
-          f"({'cached' if tune['cached'] else 'measured'})",
-          file=sys.stderr, flush=True)
-    solvers = [Solver(p, device="cuda:0", box_target=box_target) for p in probs]
-    nodes = solvers[0].plan.total_nodes
-    fine = solvers[0].plan.fine_nodes
-    outs = [torch.empty(fine, dtype=torch.float64, device=dev) for _ in solvers]
-    exacts = [s.exact(T_FINAL) for s in solvers]
-    res = torch.zeros((len(solvers), 2), dtype=torch.float64, device=dev)
-    solvers, outs, exacts = PtrList(solvers), PtrList(outs), PtrList(exacts)
-    sent = StepNorms(torch, res)
-    budget = sum(s.plan.footprint for s in solvers) + (1 << 30)
-    batch = Batch(max_solvers=len(solvers), precision=B.FP32_SWEEP, hbm_budget=budget,
-                  max_items=sum(len(s.plan.grids) * 64 for s in solvers))
-    batch.set_blocks_per_cu(bpc)
-    print(f"[bench] {len(solvers)} solves x {nodes} component nodes, warmup {args.warmup}", file=sys.stderr,
-          flush=True)
-
-    for _ in range(args.warmup):
-        run_batch_step(torch, batch, solvers, outs, exacts, res, sent)
-    sent.take()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    norms = None
-    for k in range(args.steps):
-        run_batch_step(torch, batch, solvers, outs, exacts, res, sent)
-    norms = sent.take()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    steps_each = [s.query()[1] for s in solvers]
-    cells_per_step = sum(n * nodes for n in steps_each)
-    ms_per_step = elapsed / args.steps * 1e3
-    value = cells_per_step / (elapsed / args.steps)
-    # the paper's savings view: finest-grid nodes advanced per second
-    finest_equiv = sum(n * solvers[0].plan.fine_nodes for n in steps_each) / (elapsed / args.steps)
-    l1s = norms[:, 0]
-    print(f"[bench] timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.3e} cell-updates/s",
-          file=sys.stderr, flush=True)
-
-    # ---- the dominant kernel alone, same launch shape, HIP events on the batch stream.  Every
-    # component grid of this workload is one stage box, so the stage work of a step is one
-    # launch of the three-stage kernel; the split kernel's stage 1 is timed beside it.
-    from paper_2007_10196_amd.solver import restrict_many
-    restrict_many(solvers, stream=batch.stream)
-    batch.admit_many(solvers)
-    batch.step(1)
-    st = batch.stream
-
-    def timed(stage, reps):
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        batch.launch_stage(stage, 2)
-        ev0.record(st)
-        batch.launch_stage(stage, reps)
-        ev1.record(st)
-        torch.cuda.synchronize()
-        return ev0.elapsed_time(ev1) / reps
-
-    step_ms = timed(3, args.stage_reps)
-    split_ms = timed(0, args.stage_reps)
-    info = batch.info()
-    batch.release_many(list(batch.slots))
-    step_flops = info["nodes"] * sum(flops_per_node_stage(2, s) for s in range(3))
-    achieved = step_flops / (step_ms * 1e-3) / 1e12
-    # algorithmic bytes of a step: u^n read once, u^{n+1} written once (FP32)
-    step_bytes = info["nodes"] * 4 * 2
-    traffic = measured_traffic()
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                # the HBM side of the same launch: counter bytes (when current) over the event time
-                "hbm_GBs": traffic / (step_ms * 1e-3) / 1e9 if traffic else None,
-                "hbm_frac": traffic / (step_ms * 1e-3) / 1e9 / PEAK_HBM_GBS if traffic else None,
-                "kernel": "stage_kernel<float, 2, fused> (three RK stages of every one-box grid)",
-                "avg_launch_us": step_ms * 1e3,
-                "flops_per_launch": step_flops, "boxes_per_launch": info["boxes"],
-                "algorithmic_bytes_per_launch": step_bytes,
-                "achieved_algorithmic_GBs": step_bytes / (step_ms * 1e-3) / 1e9,
-                "split_stage_kernel_stage1_us": split_ms * 1e3}
-
-    # ---- plain per-grid FP64 method on the first solve: the equal-L1 reference
-    plain = None
-    if not args.no_plain:
-        p64 = probs[0].replace(precision=W.PREC_FP64)
-        sp = Solver(p64, device="cuda:0")
-        Up = torch.empty(fine, dtype=torch.float64, device=dev)
-        Ep = sp.exact(T_FINAL)
-        for rep in range(2):
-            torch.cuda.synchronize()
-            tp = time.perf_counter()
-            sp.restrict()
-            sp.advance(mode=B.RUN_PLAIN)
-            sp.prolongate_combine(Up)
-            l1p, lip = sp.norms(Up, Ep)
-            torch.cuda.synchronize()
-            tp = time.perf_counter() - tp
-        stp = sp.query()[1]
-        plain = {"value": stp * nodes / tp, "unit": "cell-updates/s", "mode": "plain: one launch per grid per "
-                 "RK stage, no graph, FP64", "ms_per_solve": tp * 1e3, "l1": l1p, "linf": lip,
-                 "speedup_of_value": value / (stp * nodes / tp),
-                 "equal_l1": bool(abs(l1s[0] - l1p) <= 0.01 * l1p), "l1_batched_fp32_same_solve": float(l1s[0])}
-
-    full = None
-    if not args.no_full:
-        f = full_grid_run(torch, probs, box_target, bpc)
-        full = {"full_grid": "one 256x256 grid (root 256, finest level 0), same solves, same batched FP32 path",
-                "full_ms_per_step": f["ms_per_step"], "sparse_ms_per_step": ms_per_step,
-                "time_ratio_sparse_over_full": ms_per_step / f["ms_per_step"],
-                "l1_full": f["l1_mean"], "l1_sparse": float(l1s.mean()),
-                "nodes_full": f["nodes_per_solve"], "nodes_sparse": nodes, "time_steps_full": f["time_steps"],
-                "paper_cpu_time_ratio": "2D WENO sparse/single 0.72-0.68 (Table ex3aweno: 0.414/0.572 s at "
-                                        "N_h = 80 to 781.990/1149.946 s at 640), 2.3 GHz workstation"}
-        print(f"[bench] full grid: {f['ms_per_step']:.2f} ms/step, L1 {f['l1_mean']:.3e} "
-              f"(sparse {ms_per_step:.2f} ms/step, L1 {float(l1s.mean()):.3e})", file=sys.stderr, flush=True)
-
-    batched_fp64 = None
-    if not args.no_fp64:
-        f = batch_run(torch, [p.replace(precision=W.PREC_FP64) for p in probs], box_target, bpc, steps=args.steps)
-        v64 = f["cell_updates_per_step"] / (f["ms_per_step"] * 1e-3)
-        batched_fp64 = {"value": v64, "unit": "cell-updates/s", "ms_per_step": f["ms_per_step"],
-                        "mode": "the same 256 solves and batched path with FP64 sweeps (launch shape of the FP32 run)",
-                        "l1_mean": f["l1_mean"], "fp32_speedup": value / v64}
-        print(f"[bench] FP64 batched: {f['ms_per_step']:.2f} ms/step, {v64:.3e} cell-updates/s, L1 {f['l1_mean']:.3e}",
-              file=sys.stderr, flush=True)
-
+    head = c4_headline(args, torch)
+    c2 = None if args.no_c2 else c2_batched(args, torch)
     serving = None if args.no_serving else serving_run(
-        box_target, n=args.serving_requests, loads=[float(x) for x in args.serving_loads.split(",")],
-        blocks_per_cu=bpc)
-
+        0, n=args.serving_requests, loads=[float(x) for x in args.serving_loads.split(",")])
     cpu = None if args.no_cpu else cpu_baseline()
-
-    out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "2D Burgers u0=0.3+A sin(pi(x+y)+phi), [-1,1]^2 periodic, root 8x8, finest "
-                                  "level 5 (256x256), 11 component grids, CFL 0.5, T=1.5/pi^2; FP32 sweeps, FP64 "
-                                  "combination", "solves_per_step": len(solvers), "component_nodes": nodes,
-                      "mode": "batched: one HIP graph per time step, persistent fused WENO5+RK3 stage launch"},
-           "l1_mean": float(l1s.mean()), "l1_max": float(l1s.max()),
-           "finest_equivalent_cell_updates_per_s": finest_equiv,
-           "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "latency": serving, "sparse_vs_full": full,
-           "batched_fp64": batched_fp64,
-           "autotune": {"box_target": box_target, "blocks_per_cu": bpc, "step_stage_us_by_target_and_cap": tune["us"]}}
+    out = {"metric": METRIC, "value": head["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "4D Vlasov with fixed field, f_t + v.grad_x f + E(x).grad_v f = 0, x in [0,4pi]^2, "
+                                  "v in [-6,6]^2 periodic, E = 0.01 (sin(x1/2), sin(x2/2)), f0 = Maxwellian x "
+                                  "(1 + 0.01 cos(x1/2) cos(x2/2)); root 8^4, finest level 4 (128^4), 69 component "
+                                  "grids, CFL 0.4, T = 1; FP64 throughout; one solve per step",
+                      "component_nodes": head["nodes"], "finest_nodes": head["fine"],
+                      "time_steps": head["time_steps"],
+                      "mode": "step graphs, one persistent WENO5-LF + TVD-RK3 stage launch per RK stage over all "
+                              "boxes, gather-fused WENO5 prolongation with FP64 combination"},
+           "l1": head["l1"], "linf": head["linf"], "parts_ms": head["parts"],
+           "finest_equivalent_cell_updates_per_s": head["finest_equivalent_cell_updates_per_s"],
+           "roofline": head["roofline"], "roofline_other": head["roofline_other"], "cpu_baseline": cpu,
+           "fp32_sweeps": head["fp32"], "plain": head["plain"], "latency": serving, "batched_2d_burgers": c2,
+           "autotune": head["autotune"]}
     print(json.dumps(out), flush=True)
 
 
