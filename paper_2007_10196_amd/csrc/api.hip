@@ -220,25 +220,49 @@ static void choose_box(GridDev& g, int precision, int target, size_t lds_cap)
     fill_box_geometry(g, precision);
 }
 
-static size_t prolong_buffer_elems(const sgw_plan& p, const int* T)
+// Coarse extent staged per tile in direction k: the tile's fine nodes T fall in at most
+// (T - 1) / R + 2 coarse intervals, each centre with two stencil nodes on either side.
+static int coarse_extent(int T, int m) { return m == 0 ? T : (T - 1) / (1 << m) + 6; }
+
+static int last_refined(const sgw_plan& p, int g)
 {
-    size_t best = 0;
+    int kl = -1;
+    for (int k = 0; k < p.pb.dim; k++)
+        if (p.cfg.finest_level - p.levels[g][k] > 0) kl = k;
+    return kl;
+}
+
+// LDS elements of one buffer: the largest staged coarse block or pass output.  In the line form
+// the last refined direction's pass goes to registers, so its output needs no buffer.
+static size_t prolong_buffer_elems(const sgw_plan& p, const int* T, bool lines, size_t* rows_max)
+{
+    size_t best = 0, rows = 0;
     for (int g = 0; g < p.G; g++) {
         int c[SGW_MAX_DIM];
-        for (int k = 0; k < p.pb.dim; k++) {
-            const int m = p.cfg.finest_level - p.levels[g][k];
-            c[k] = m == 0 ? T[k] : (T[k] - 1) / (1 << m) + 6;
-        }
+        for (int k = 0; k < p.pb.dim; k++) c[k] = coarse_extent(T[k], p.cfg.finest_level - p.levels[g][k]);
         size_t load = 1;
         for (int k = 0; k < p.pb.dim; k++) load *= (size_t)c[k];
         best = load > best ? load : best;
+        const size_t r = load / (size_t)c[0];
+        rows = r > rows ? r : rows;
+        const int kl = last_refined(p, g);
         for (int k = 0; k < p.pb.dim; k++) {
+            if (lines && k >= kl) break;
             size_t sz = 1;
             for (int j = 0; j < p.pb.dim; j++) sz *= (size_t)(j <= k ? T[j] : c[j]);
             best = sz > best ? sz : best;
         }
     }
+    if (rows_max) *rows_max = lines ? rows : 0;
     return (best + 1) / 2 * 2;
+}
+
+static size_t prolong_lds_bytes(const sgw_plan& p, const int* T, bool lines)
+{
+    const size_t rs = p.cfg.precision == SGW_FP64 ? 8 : 4;
+    size_t rows = 0;
+    const size_t buf = prolong_buffer_elems(p, T, lines, &rows);
+    return 2 * rs * buf + (lines ? 4 * rows : 0);
 }
 
 // Interpolations and staged coarse values of one finest-grid tile T, summed
@@ -253,10 +277,7 @@ static void prolong_tile_work(const sgw_plan& p, const int* T, double* interp, d
     *load = 0.0;
     for (int g = 0; g < p.G; g++) {
         int c[SGW_MAX_DIM];
-        for (int k = 0; k < d; k++) {
-            const int m = p.cfg.finest_level - p.levels[g][k];
-            c[k] = m == 0 ? T[k] : (T[k] - 1) / (1 << m) + 6;
-        }
+        for (int k = 0; k < d; k++) c[k] = coarse_extent(T[k], p.cfg.finest_level - p.levels[g][k]);
         double l = 1.0;
         for (int k = 0; k < d; k++) l *= c[k];
         *load += l;
@@ -269,12 +290,60 @@ static void prolong_tile_work(const sgw_plan& p, const int* T, double* interp, d
     }
 }
 
-// Tile search: every combination of divisors T_k | N with at most 8 (2D) or 16
-// points per thread and two LDS buffers within 64 KB; the cost per finest node
-// counts interpolations (~50 operations each), staged coarse values (~10), a
-// fixed cost per grid and tile (barriers, set-up: ~2000) and the FP64 write of
-// the node (more when tile rows along direction 1 are short), scaled up when the
-// LDS of two buffers leaves fewer than 4 workgroups per compute unit.
+// Estimated VALU lane-operations of one tile in the line form: a lane per line, rounds of
+// SGW_BLOCK lines, only the wavefronts that hold a line issue.  Per staged value ~16, per
+// row offset ~12 per direction, per line ~12, per coarse centre ~30, per fine node ~16 (FP32)
+// or ~22 (FP64: the division's Newton steps), per accumulated node 2, and a node-by-node
+// final pass (~60 per node) for the grid whose last direction is not refined.
+static double prolong_lines_cost(const sgw_plan& p, const int* T)
+{
+    const int d = p.pb.dim;
+    const double pt = p.cfg.precision == SGW_FP64 ? 22.0 : 16.0;
+    double cost = 0.0;
+    for (int g = 0; g < p.G; g++) {
+        int c[SGW_MAX_DIM], m[SGW_MAX_DIM];
+        for (int k = 0; k < d; k++) {
+            m[k] = p.cfg.finest_level - p.levels[g][k];
+            c[k] = coarse_extent(T[k], m[k]);
+        }
+        double load = 1.0;
+        for (int k = 0; k < d; k++) load *= c[k];
+        const double rows = load / c[0];
+        cost += std::ceil(load / SGW_BLOCK) * SGW_BLOCK * 16.0 + std::ceil(rows / SGW_BLOCK) * SGW_BLOCK * 12.0 * (d - 1);
+        const int kl = last_refined(p, g);
+        for (int k = 0; k < d && k <= kl; k++) {
+            if (m[k] == 0) continue;
+            const int R = 1 << m[k];
+            const double cen = (T[k] >= R ? (T[k] - 1) / R + 2 : 2);
+            double inner = 1.0, outer = 1.0;
+            for (int j = 0; j < k; j++) inner *= T[j];
+            for (int j = k + 1; j < d; j++) outer *= c[j];
+            const double per_line = 12.0 + 30.0 * cen + pt * T[k];
+            if (k == d - 1) {
+                cost += SGW_BLOCK * (per_line + 2.0 * T[k]);
+            } else if (k == kl) {
+                cost += SGW_BLOCK * 60.0 * T[d - 1];
+            } else {
+                const double lines = inner * outer;
+                for (double done = 0.0; done < lines; done += SGW_BLOCK) {
+                    const double act = std::min((double)SGW_BLOCK, lines - done);
+                    cost += std::ceil(act / 64.0) * 64.0 * per_line;
+                }
+            }
+        }
+        cost += 2000.0; // barriers and set-up per grid and tile
+    }
+    return cost;
+}
+
+// Tile search.  3D/4D: the line form, tiles with prod_{k<d-1} T_k = SGW_BLOCK and at most 16
+// nodes per line along the last direction, LDS within 64 KB, cost by prolong_lines_cost per
+// finest node plus the FP64 write (more when tile rows along direction 1 are short), scaled up
+// when fewer than 4 workgroups per compute unit fit in LDS.  Otherwise (1D/2D, a manual tile or
+// no such tile): every combination of divisors T_k | N with at most 8 (2D) or 16 points per
+// thread and two LDS buffers within 64 KB; the cost per finest node counts interpolations (~50
+// operations each), staged coarse values (~10), a fixed cost per grid and tile (barriers, set-up:
+// ~2000) and the FP64 write of the node, scaled the same way.
 static void choose_fine_tile(sgw_plan& p)
 {
     const int d = p.pb.dim;
@@ -285,12 +354,49 @@ static void choose_fine_tile(sgw_plan& p)
         T[k] = p.cfg.fine_tile[k] > 0 ? p.cfg.fine_tile[k] : p.N;
         manual |= p.cfg.fine_tile[k] > 0;
     }
-    if (!manual) {
-        std::vector<int> divs;
-        for (int v = 1; v <= p.N; v++)
-            if (p.N % v == 0) divs.push_back(v);
+    std::vector<int> divs;
+    for (int v = 1; v <= p.N; v++)
+        if (p.N % v == 0) divs.push_back(v);
+    const int nd = (int)divs.size();
+    auto occupancy_slow = [](size_t lds) {
+        const double occ = (double)(163840 / (lds ? lds : 1));
+        return occ >= 4.0 ? 1.0 : 4.0 / occ;
+    };
+    bool lines = false;
+    if (!manual && d >= 3) {
+        double best = 1e300;
+        int bt[SGW_MAX_DIM] = {1, 1, 1, 1};
+        int idx[SGW_MAX_DIM] = {0, 0, 0, 0};
+        for (;;) {
+            int t[SGW_MAX_DIM] = {1, 1, 1, 1};
+            int64_t inner = 1;
+            for (int k = 0; k < d; k++) {
+                t[k] = divs[idx[k]];
+                if (k < d - 1) inner *= t[k];
+            }
+            if (inner == SGW_BLOCK && t[d - 1] <= 16) {
+                const size_t lds = prolong_lds_bytes(p, t, true);
+                if (lds <= 64 * 1024) {
+                    const double pts = (double)inner * t[d - 1];
+                    const double write = 40.0 * (t[0] >= 8 ? 1.0 : 8.0 / t[0]);
+                    const double cost = occupancy_slow(lds) * (prolong_lines_cost(p, t) / pts + write);
+                    if (cost < best - 1e-9) {
+                        best = cost;
+                        for (int k = 0; k < SGW_MAX_DIM; k++) bt[k] = t[k];
+                    }
+                }
+            }
+            int k = 0;
+            while (k < d && ++idx[k] == nd) idx[k++] = 0;
+            if (k == d) break;
+        }
+        if (best < 1e300) {
+            lines = true;
+            for (int k = 0; k < d; k++) T[k] = bt[k];
+        }
+    }
+    if (!manual && !lines) {
         const int cap = d <= 2 ? SGW_BLOCK * 8 : SGW_BLOCK * 16;
-        const int nd = (int)divs.size();
         double best = 1e300;
         int bt[SGW_MAX_DIM] = {1, 1, 1, 1};
         int idx[SGW_MAX_DIM] = {0, 0, 0, 0};
@@ -301,18 +407,15 @@ static void choose_fine_tile(sgw_plan& p)
                 t[k] = divs[idx[k]];
                 pts *= t[k];
             }
-            const size_t lds = 2 * rs * prolong_buffer_elems(p, t);
+            const size_t lds = prolong_lds_bytes(p, t, false);
             if (pts <= cap && pts >= SGW_BLOCK / 4 && lds <= 64 * 1024) {
                 double interp, load;
                 prolong_tile_work(p, t, &interp, &load);
-                // fewer than 4 resident workgroups per CU (160 KB of LDS each) leave the
-                // kernel latency-bound: charge the missing occupancy
-                const double occ = (double)(163840 / lds);
-                const double slow = occ >= 4.0 ? 1.0 : 4.0 / occ;
                 // the tile's FP64 rows along direction 1 are written to HBM: rows shorter than
                 // 8 values (64 bytes) waste most of each write transaction
                 const double write = 40.0 * (t[0] >= 8 ? 1.0 : 8.0 / t[0]);
-                const double cost = slow * ((50.0 * interp + 10.0 * load + 2000.0 * p.G) / (double)pts + write);
+                const double cost =
+                    occupancy_slow(lds) * ((50.0 * interp + 10.0 * load + 2000.0 * p.G) / (double)pts + write);
                 if (cost < best - 1e-9) {
                     best = cost;
                     for (int k = 0; k < SGW_MAX_DIM; k++) bt[k] = t[k];
@@ -326,7 +429,9 @@ static void choose_fine_tile(sgw_plan& p)
             for (int k = 0; k < d; k++) T[k] = bt[k];
     }
     for (int k = 0; k < SGW_MAX_DIM; k++) p.fine_T[k] = k < d ? T[k] : 1;
-    p.pro_buf_elems = prolong_buffer_elems(p, p.fine_T);
+    p.fine_lines = lines;
+    p.pro_buf_elems = prolong_buffer_elems(p, p.fine_T, lines, &p.pro_rows_max);
+    p.pro_lds = prolong_lds_bytes(p, p.fine_T, lines);
 }
 
 // ---------------------------------------------------------------- plans
@@ -470,8 +575,7 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     {
         int pts = 1;
         for (int k = 0; k < d; k++) pts *= p->fine_T[k];
-        const size_t rs = cfg->precision == SGW_FP64 ? 8 : 4;
-        if (pts > SGW_BLOCK * 16 || 2 * rs * p->pro_buf_elems > 64 * 1024) {
+        if (pts > SGW_BLOCK * 16 || p->pro_lds > 64 * 1024) {
             delete p;
             return sgw_fail(SGW_ERR_UNSUPPORTED, "prolongation tile too large for one workgroup");
         }
@@ -505,6 +609,8 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     p->off_coef_off = take(sizeof(int64_t) * p->coef_off.size());
     p->off_pro = take(sizeof(ProDev) * p->G);
     p->off_fine = take(sizeof(FineDev));
+    // per-point prolongation coefficients, entries for R = 2, 4, ..., 2^N_L
+    p->off_stab = take(8 * rs * (((uint64_t)2 << cfg->finest_level) - 1));
     p->off_partials = take(sizeof(double) * 2 * SGW_NPART);
     p->off_result = take(sizeof(double) * 2);
     uint64_t foot = 0;
@@ -673,7 +779,7 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
             pd.stride[k] = s->grids_h[g].stride[k];
             if (k < d) {
                 pd.m[k] = p->cfg.finest_level - p->levels[g][k];
-                pd.c[k] = pd.m[k] == 0 ? p->fine_T[k] : (p->fine_T[k] - 1) / (1 << pd.m[k]) + 6;
+                pd.c[k] = coarse_extent(p->fine_T[k], pd.m[k]);
             } else {
                 pd.m[k] = 0;
                 pd.c[k] = 1;
@@ -683,6 +789,8 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
             pd.fd_n[k] = make_fastdiv((uint32_t)pd.n[k]);
         }
         pd.load_total = load;
+        pd.rows = load / pd.c[0];
+        pd.klast = last_refined(*p, g);
         for (int k = 0; k < SGW_MAX_DIM; k++) {
             int o = 1;
             for (int j = k + 1; j < SGW_MAX_DIM; j++) o *= pd.c[j];
@@ -706,6 +814,32 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
         pts *= p->fine_T[k];
     }
     s->fine_h.tile_points = pts;
+    s->fine_h.lines = p->fine_lines ? 1 : 0;
+    s->fine_h.rows_max = (int32_t)p->pro_rows_max;
+    s->fine_h.stab = s->scratch + p->off_stab;
+    // per-point coefficient table: entry (R - 2) + q of R = 2^m holds s = (q - R/2)/R, s/2, s^2/2
+    // and the linear weights C_r(s) = ((s-1)(s-2)/12, (4-s^2)/6, (s+1)(s+2)/12) of eq. (lwlag)
+    std::vector<double> stab_h((size_t)8 * (((size_t)2 << p->cfg.finest_level) - 1), 0.0);
+    for (int m = 1; m <= p->cfg.finest_level; m++) {
+        const int R = 1 << m;
+        for (int q = 0; q < R; q++) {
+            const double sv = (double)(q - R / 2) / (double)R;
+            double* e = &stab_h[(size_t)8 * (R - 2 + q)];
+            e[0] = 0.5 * sv;
+            e[1] = 0.5 * sv * sv;
+            e[2] = (sv - 1.0) * (sv - 2.0) / 12.0;
+            e[3] = (4.0 - sv * sv) / 6.0;
+            e[4] = (sv + 1.0) * (sv + 2.0) / 12.0;
+        }
+    }
+    if (p->cfg.precision == SGW_FP64) {
+        s->stab_h.resize(sizeof(double) * stab_h.size());
+        std::memcpy(s->stab_h.data(), stab_h.data(), s->stab_h.size());
+    } else {
+        std::vector<float> f(stab_h.begin(), stab_h.end());
+        s->stab_h.resize(sizeof(float) * f.size());
+        std::memcpy(s->stab_h.data(), f.data(), s->stab_h.size());
+    }
 
     hipStream_t st = s->stream;
     sgw_status rc = SGW_OK;
@@ -720,6 +854,7 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
     cp(s->coef_off_d, p->coef_off.data(), sizeof(int64_t) * p->coef_off.size());
     cp(s->pro_d, s->pro_h.data(), sizeof(ProDev) * p->G);
     cp(s->fine_d, &s->fine_h, sizeof(FineDev));
+    cp(s->scratch + p->off_stab, s->stab_h.data(), s->stab_h.size());
     if (rc == SGW_OK && p->pb.flux == SGW_FLUX_VLASOV_FIXED_E) {
         hipError_t e = launch_coef_init(s->grids_d, s->grids_h.data(), p->G, s->coef_d, s->coef_off_d, &p->pb, st);
         if (e != hipSuccess) rc = sgw_hip_fail(e, "coefficient tables");
@@ -980,7 +1115,7 @@ extern "C" sgw_status sgw_prolongate_combine(sgw_solver_t* s, double* out_dev)
     if (!s || !out_dev) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
     if (!s->restricted) return sgw_fail(SGW_ERR_STATE, "prolongate before restrict");
     const sgw_plan* p = s->plan;
-    const size_t lds = 2 * (p->cfg.precision == SGW_FP64 ? 8 : 4) * p->pro_buf_elems;
+    const size_t lds = p->pro_lds;
     HIPCHK(launch_prolong(s->pro_d, s->fine_d, s->fine_h, p->cfg.precision, lds, out_dev, s->stream), "prolongate");
     return SGW_OK;
 }
@@ -1096,7 +1231,7 @@ extern "C" sgw_status sgw_prolongate_combine_many(sgw_solver_t* const* solvers, 
         if (!s->restricted) return sgw_fail(SGW_ERR_STATE, "prolongate before restrict (solver %d)", i);
         if (s->plan->pb.dim != d || s->plan->cfg.precision != prec)
             return sgw_fail(SGW_ERR_INVALID_ARG, "solvers of one call must share dimension and precision");
-        const size_t l = 2 * (prec == SGW_FP64 ? 8 : 4) * s->plan->pro_buf_elems;
+        const size_t l = s->plan->pro_lds;
         lds = l > lds ? l : lds;
         const int64_t t = fine_tiles(s);
         max_tiles = t > max_tiles ? t : max_tiles;

@@ -175,10 +175,270 @@ __device__ __forceinline__ void prolong_tile(ProC pro, FineC F, double* __restri
     }
 }
 
+// ---------------------------------------------------------------- line form (3D, 4D)
+//
+// The same interpolation, organised so that the work depending only on a coarse stencil is
+// done once for the R fine nodes it serves.  One lane refines one line of a pass: for each
+// coarse centre i on the line it forms the differences G_r, K_r of the three substencils, the
+// squared weight denominators e_r = (eps4 + G_r^2 + 13/3 K_r^2)^2 and the products
+// E_r = e_r' e_r'' (the common factor of eq. (nlweno) after clearing denominators), and the
+// centre's A_r = E_r c, B_r = E_r G_r, D_r = E_r K_r.  Each fine node at offset s then costs
+// E_r P_r(s) = A_r + h B_r + hs D_r, the sums num = sum C_r E_r P_r and den = sum C_r E_r and
+// one division, with h, hs and C_r(s) read from a table whose index is the same for every
+// lane (scalar loads).  A node at s = 0 takes the centre's value: every P_r(0) = u_i.
+
+template <typename Real>
+struct Centre {
+    Real c, A0, A1, A2, B0, B1, B2, D0, D1, D2, E0, E1, E2;
+};
+
+template <typename Real>
+__device__ __forceinline__ void centre_setup(Centre<Real>& z, Real a, Real b, Real c, Real d, Real e, Real eps4,
+                                             int lagrange)
+{
+    const Real K0 = a - Real(2) * b + c, K1 = b - Real(2) * c + d, K2 = c - Real(2) * d + e;
+    const Real G0 = K0 + Real(2) * (c - b), G1 = d - b, G2 = Real(2) * (d - c) - K2;
+    z.c = c;
+    if (lagrange) {
+        z.A0 = z.A1 = z.A2 = c;
+        z.B0 = G0, z.B1 = G1, z.B2 = G2;
+        z.D0 = K0, z.D1 = K1, z.D2 = K2;
+        z.E0 = z.E1 = z.E2 = Real(1);
+        return;
+    }
+    Real e0 = eps4 + (G0 * G0 + Real(13.0 / 3.0) * K0 * K0);
+    Real e1 = eps4 + (G1 * G1 + Real(13.0 / 3.0) * K1 * K1);
+    Real e2 = eps4 + (G2 * G2 + Real(13.0 / 3.0) * K2 * K2);
+    e0 *= e0;
+    e1 *= e1;
+    e2 *= e2;
+    z.E0 = e1 * e2;
+    z.E1 = e0 * e2;
+    z.E2 = e0 * e1;
+    z.A0 = z.E0 * c, z.A1 = z.E1 * c, z.A2 = z.E2 * c;
+    z.B0 = z.E0 * G0, z.B1 = z.E1 * G1, z.B2 = z.E2 * G2;
+    z.D0 = z.E0 * K0, z.D1 = z.E1 * K1, z.D2 = z.E2 * K2;
+}
+
+template <typename Real>
+__device__ __forceinline__ Real centre_value(const Centre<Real>& z, const SGW_CONST STab<Real>& t, int copy,
+                                             int lagrange)
+{
+    if (copy) return z.c;
+    const Real Q0 = z.A0 + t.h * z.B0 + t.hs * z.D0;
+    const Real Q1 = z.A1 + t.h * z.B1 + t.hs * z.D1;
+    const Real Q2 = z.A2 + t.h * z.B2 + t.hs * z.D2;
+    const Real num = t.c0 * Q0 + t.c1 * Q1 + t.c2 * Q2;
+    if (lagrange) return num;
+    return rdiv(num, t.c0 * z.E0 + t.c1 * z.E1 + t.c2 * z.E2);
+}
+
+template <typename Real, int D>
+__device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __restrict__ out, int tile)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x;
+    int J0[D];
+    {
+        int r = tile;
+        for (int k = 0; k < D; k++) {
+            const int q = r / F->ntile[k];
+            J0[k] = (r - q * F->ntile[k]) * F->T[k];
+            r = q;
+        }
+    }
+    const Real eps4 = (Real)(4.0 * F->eps);
+    const int lagrange = F->lagrange;
+    const int Tlast = F->T[D - 1];
+    typedef const SGW_CONST STab<Real>* TabC;
+    const TabC stab = (TabC)F->stab;
+    double acc[SGW_MAXRP];
+#pragma unroll
+    for (int r = 0; r < SGW_MAXRP; r++) acc[r] = 0.0;
+    Real* bufA = (Real*)smem;
+    Real* bufB = bufA + F->pad0;
+    int* rowoff = (int*)(bufB + F->pad0);
+
+    for (int gidx = 0; gidx < F->G; gidx++) {
+        ProC p = pro + gidx;
+        const Real* __restrict__ u = (const Real*)p->u;
+        int cl[D];
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            const int m = p->m[k];
+            cl[k] = (m == 0) ? J0[k] : (((2 * J0[k] + (1 << m)) >> (m + 1)) - 2);
+        }
+        // ---- coarse block (periodic wrap): element offsets of its rows along direction 1, then
+        // the rows; a wrapped index cl + c + 2n >= 0 takes its remainder by n with the fast division
+        const int rows = p->rows;
+        for (int r = tid; r < rows; r += SGW_BLOCK) {
+            uint32_t rr = (uint32_t)r;
+            int gi = 0;
+#pragma unroll
+            for (int k = 1; k < D; k++) {
+                const uint32_t q = FDIV(rr, p->fd_c[k]);
+                const int c = (int)(rr - q * (uint32_t)p->c[k]);
+                rr = q;
+                const uint32_t xw = (uint32_t)(cl[k] + c + 2 * p->n[k]);
+                gi += (int)(xw - FDIV(xw, p->fd_n[k]) * (uint32_t)p->n[k]) * p->stride[k];
+            }
+            rowoff[r] = gi;
+        }
+        __syncthreads();
+        {
+            const int c0 = p->c[0], n0 = p->n[0];
+            for (int e = tid; e < p->load_total; e += SGW_BLOCK) {
+                const uint32_t row = FDIV((uint32_t)e, p->fd_c[0]);
+                const int x0 = e - (int)row * c0;
+                const uint32_t xw = (uint32_t)(cl[0] + x0 + 2 * n0);
+                const int x = (int)(xw - FDIV(xw, p->fd_n[0]) * (uint32_t)n0);
+                bufA[e] = u[rowoff[row] + x];
+            }
+        }
+        __syncthreads();
+        Real* src = bufA;
+        Real* dst = bufB;
+        const int kl = p->klast;
+        // ---- passes before the last refined direction: one lane per line, into LDS
+#pragma unroll
+        for (int k = 0; k < D - 1; k++) {
+            const int m = p->m[k];
+            if (m == 0 || k >= kl) continue;
+            const int Tk = F->T[k], ck = p->c[k], inner = F->inner[k];
+            const int lines = inner * p->outer[k];
+            const int R = 1 << m, half = R >> 1, Jk = J0[k];
+            const int ifirst = (2 * Jk + R) >> (m + 1);
+            const TabC tb = stab + (R - 2);
+            for (int L = tid; L < lines; L += SGW_BLOCK) {
+                const int b = (int)FDIV((uint32_t)L, F->fd_inner[k]);
+                const int a = L - b * inner;
+                const Real* sp = src + a + inner * (ck * b);
+                Real* dp = dst + a + inner * (Tk * b);
+                Real w0 = sp[0], w1 = sp[inner], w2 = sp[2 * inner], w3 = sp[3 * inner], w4 = sp[4 * inner];
+                const Real* nx = sp + 5 * inner;
+                Centre<Real> z;
+                centre_setup(z, w0, w1, w2, w3, w4, eps4, lagrange);
+                int next = ifirst * R + half - Jk; // first node of the next centre
+                for (int t = 0; t < Tk; t++) {
+                    if (t == next) {
+                        w0 = w1, w1 = w2, w2 = w3, w3 = w4, w4 = *nx;
+                        nx += inner;
+                        centre_setup(z, w0, w1, w2, w3, w4, eps4, lagrange);
+                        next += R;
+                    }
+                    const int q = (Jk + t + half) & (R - 1);
+                    dp[t * inner] = centre_value(z, tb[q], q == half, lagrange);
+                }
+            }
+            __syncthreads();
+            Real* sw = src;
+            src = dst;
+            dst = sw;
+        }
+        const double cg = (double)p->coef;
+        if (kl == D - 1) {
+            // ---- last direction: the tile has SGW_BLOCK lines along it, lane tid takes line tid
+            // and adds its nodes straight into its accumulators (node tid + SGW_BLOCK t)
+            const int m = p->m[D - 1];
+            const int R = 1 << m, half = R >> 1, Jk = J0[D - 1];
+            const int ifirst = (2 * Jk + R) >> (m + 1);
+            const TabC tb = stab + (R - 2);
+            const Real* sp = src + tid;
+            Real w0 = sp[0], w1 = sp[SGW_BLOCK], w2 = sp[2 * SGW_BLOCK], w3 = sp[3 * SGW_BLOCK],
+                 w4 = sp[4 * SGW_BLOCK];
+            const Real* nx = sp + 5 * SGW_BLOCK;
+            Centre<Real> z;
+            centre_setup(z, w0, w1, w2, w3, w4, eps4, lagrange);
+            int next = ifirst * R + half - Jk;
+#pragma unroll
+            for (int t = 0; t < SGW_MAXRP; t++) {
+                if (t < Tlast) {
+                    if (t == next) {
+                        w0 = w1, w1 = w2, w2 = w3, w3 = w4, w4 = *nx;
+                        nx += SGW_BLOCK;
+                        centre_setup(z, w0, w1, w2, w3, w4, eps4, lagrange);
+                        next += R;
+                    }
+                    const int q = (Jk + t + half) & (R - 1);
+                    acc[t] += cg * (double)centre_value(z, tb[q], q == half, lagrange);
+                }
+            }
+        } else if (kl >= 0) {
+            // ---- the grid whose last direction is not refined: its last pass (direction kl,
+            // every later direction at tile extent) node by node, lane tid taking node
+            // (a, t) of each of the Tlast slices
+            int Jk = J0[0], clk = cl[0];
+#pragma unroll
+            for (int k = 1; k < D; k++)
+                if (k == kl) Jk = J0[k], clk = cl[k];
+            const int m = p->m[kl];
+            const int R = 1 << m;
+            const int inner = F->inner[kl], ck = p->c[kl];
+            const int t = (int)FDIV((uint32_t)tid, F->fd_inner[kl]);
+            const int a = tid - t * inner;
+            const int J = Jk + t;
+            const int i = (2 * J + R) >> (m + 1);
+            const Real sv = (Real)(J - i * R) * (Real(1) / Real(R));
+            const Real* sp = src + a + inner * (i - clk - 2);
+            const int slice = inner * ck;
+#pragma unroll
+            for (int bq = 0; bq < SGW_MAXRP; bq++) {
+                if (bq < Tlast) {
+                    const Real* q = sp + bq * slice;
+                    acc[bq] += cg * (double)interp5<Real>(q[0], q[inner], q[2 * inner], q[3 * inner], q[4 * inner], sv,
+                                                          eps4, lagrange);
+                }
+            }
+        } else {
+            // ---- no direction refined: the coarse block is the tile
+#pragma unroll
+            for (int r = 0; r < SGW_MAXRP; r++)
+                if (r < Tlast) acc[r] += cg * (double)src[tid + r * SGW_BLOCK];
+        }
+        __syncthreads();
+    }
+    // ---- write the tile: node tid + SGW_BLOCK t of the tile lies at offset t along the last
+    // direction
+    int64_t gi = 0, st = 1;
+    {
+        uint32_t rr = (uint32_t)tid;
+#pragma unroll
+        for (int k = 0; k < D - 1; k++) {
+            const uint32_t q = FDIV(rr, F->fd_T[k]);
+            const int c = (int)(rr - q * (uint32_t)F->T[k]);
+            rr = q;
+            gi += (int64_t)(J0[k] + c) * st;
+            st *= F->N;
+        }
+        gi += (int64_t)J0[D - 1] * st;
+    }
+#pragma unroll
+    for (int r = 0; r < SGW_MAXRP; r++)
+        if (r < Tlast) out[gi + (int64_t)r * st] = acc[r];
+}
+
+template <typename Real, int D>
+__device__ __forceinline__ void prolong_any(ProC pro, FineC F, double* out, int tile)
+{
+    if constexpr (D >= 3) {
+        if (F->lines) {
+            prolong_tile_lines<Real, D>(pro, F, out, tile);
+            return;
+        }
+    }
+    prolong_tile<Real, D>(pro, F, out, tile);
+}
+
 template <typename Real, int D>
 __global__ void __launch_bounds__(SGW_BLOCK) prolong_kernel(const ProDev* pro, const FineDev* fine, double* out)
 {
-    prolong_tile<Real, D>((ProC)pro, (FineC)fine, out, blockIdx.x);
+    // XCD-aware order: workgroups go to the 8 XCDs in turn, so XCD x takes the contiguous tile
+    // range [x n/8, (x+1) n/8) and neighbouring tiles share its L2 (coarse blocks, partly written
+    // output lines)
+    int b = blockIdx.x;
+    const int nt = gridDim.x;
+    if ((nt & 7) == 0) b = (b & 7) * (nt >> 3) + (b >> 3);
+    prolong_any<Real, D>((ProC)pro, (FineC)fine, out, b);
 }
 
 // one workgroup per (solve, tile) over many solves of one dimension and precision
@@ -187,7 +447,10 @@ __global__ void __launch_bounds__(SGW_BLOCK) prolong_many_kernel(const ProItem* 
 {
     const SGW_CONST ProItem* it = (const SGW_CONST ProItem*)items + blockIdx.y;
     if ((int)blockIdx.x >= it->ntiles) return;
-    prolong_tile<Real, D>((ProC)it->pro, (FineC)it->fine, it->out, (int)blockIdx.x);
+    int b = blockIdx.x;
+    const int nt = gridDim.x;
+    if ((nt & 7) == 0 && it->ntiles == nt) b = (b & 7) * (nt >> 3) + (b >> 3);
+    prolong_any<Real, D>((ProC)it->pro, (FineC)it->fine, it->out, b);
 }
 
 // ---------------------------------------------------------------- exact solutions

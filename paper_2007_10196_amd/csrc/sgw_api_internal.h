@@ -24,9 +24,12 @@ struct sgw_plan {
     std::vector<int64_t> coef_off;             // [G][4] offsets into the coefficient tables
     int fine_T[SGW_MAX_DIM] = {1, 1, 1, 1};
     size_t pro_buf_elems = 0;
+    bool fine_lines = false;                   // 3D/4D line form of the prolongation
+    size_t pro_rows_max = 0;                   // its LDS row-offset table entries
+    size_t pro_lds = 0;                        // LDS bytes of a prolongation workgroup
     uint64_t copy_bytes = 0, state_bytes = 0, scratch_bytes = 0;
     uint64_t off_grids = 0, off_req = 0, off_items = 0, off_alpha = 0, off_coef = 0, off_coef_off = 0;
-    uint64_t off_pro = 0, off_fine = 0, off_partials = 0, off_result = 0, off_foot = 0;
+    uint64_t off_pro = 0, off_fine = 0, off_partials = 0, off_result = 0, off_foot = 0, off_stab = 0;
 };
 
 struct sgw_solver {
@@ -49,6 +52,7 @@ struct sgw_solver {
     std::vector<WorkItem> items_h;
     std::vector<ProDev> pro_h;
     FineDev fine_h;
+    std::vector<unsigned char> stab_h;         // prolongation coefficient table (host copy of the upload)
     ReqDev req_h;
     ReqDev* req_pinned = nullptr;
     bool restricted = false;

@@ -160,6 +160,8 @@ struct alignas(64) ProDev {
     int32_t outer[SGW_MAX_DIM];      // prod_{j>k} c[j]
     FastDiv fd_c[SGW_MAX_DIM];
     FastDiv fd_n[SGW_MAX_DIM];
+    int32_t klast;                   // last refined direction (-1: none)
+    int32_t rows;                    // prod_{k>0} c[k]: rows of the coarse block along direction 1
 };
 
 struct alignas(64) FineDev {
@@ -171,6 +173,20 @@ struct alignas(64) FineDev {
     FastDiv fd_T[SGW_MAX_DIM];
     FastDiv fd_inner[SGW_MAX_DIM];
     double eps;
+    // 3D/4D tiles with prod_{k<d-1} T_k = SGW_BLOCK run the line form of the passes (lines = 1):
+    // one lane per line, the stencil work shared by the fine points of a coarse interval, the
+    // per-point coefficients read from stab (STab entries of the solver's precision, the
+    // entries of R = 2^m from index R - 2 on), the last pass accumulated in registers
+    const void* stab;
+    int32_t lines, rows_max;         // rows_max: LDS row-offset table entries (line form)
+};
+
+// Per-point coefficients of WENO5 prolongation: fine offset q = 0..R-1 inside a coarse
+// interval of R fine nodes, s = (q - R/2) / R; P_r(s) = c + h G_r + hs K_r with h = s / 2,
+// hs = s^2 / 2, and the linear weights C_r(s) of eq. (lwlag).
+template <typename Real>
+struct alignas(8 * sizeof(Real)) STab {
+    Real h, hs, c0, c1, c2, pad0, pad1, pad2;
 };
 
 // One (solve, finest-grid tile) of a batched prolongation launch.
