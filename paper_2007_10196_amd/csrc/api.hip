@@ -220,9 +220,22 @@ static void choose_box(GridDev& g, int precision, int target, size_t lds_cap)
     fill_box_geometry(g, precision);
 }
 
-// Coarse extent staged per tile in direction k: the tile's fine nodes T fall in at most
-// (T - 1) / R + 2 coarse intervals, each centre with two stencil nodes on either side.
-static int coarse_extent(int T, int m) { return m == 0 ? T : (T - 1) / (1 << m) + 6; }
+// Coarse extent staged per tile in direction k.
+static int coarse_extent(int T, int m, int N)
+{
+    if (m == 0) return T;
+    // centres spanned by the tile's nodes J0..J0+T-1 (J0 a multiple of T), the most over the
+    // tile positions, plus two stencil nodes on either side
+    // tile positions (J0 a multiple of T): with x = (J0 + R/2) mod R the nodes span
+    // floor((x + T - 1) / R) + 1 centres; x takes every value R/2 + j gcd(T, R) mod R (N is a
+    // multiple of T and R), the largest R - gcd(T, R), or R/2 when R divides T
+    (void)N;
+    const int R = 1 << m;
+    int g = R;
+    while (T % g) g >>= 1;
+    const int x = (g == R) ? R / 2 : R - g;
+    return (x + T - 1) / R + 1 + 4;
+}
 
 static int last_refined(const sgw_plan& p, int g)
 {
@@ -232,37 +245,50 @@ static int last_refined(const sgw_plan& p, int g)
     return kl;
 }
 
-// LDS elements of one buffer: the largest staged coarse block or pass output.  In the line form
-// the last refined direction's pass goes to registers, so its output needs no buffer.
-static size_t prolong_buffer_elems(const sgw_plan& p, const int* T, bool lines, size_t* rows_max)
+// LDS elements of the two buffers.  The staged coarse block goes to buffer A and the passes
+// write B, A, B, ... in turn.  The old form gives both buffers the largest staged block or pass
+// output.  In the line form the last refined direction's pass goes to registers (its output
+// needs no buffer), a grid refined along direction 1 reads its coarse rows from global memory
+// (no staged block), and each buffer takes the largest output that lands in it.
+static void prolong_buffer_elems(const sgw_plan& p, const int* T, bool lines, size_t* a_elems, size_t* b_elems,
+                                 size_t* rows_max)
 {
-    size_t best = 0, rows = 0;
+    size_t amax = 0, bmax = 0, rows = 0;
     for (int g = 0; g < p.G; g++) {
         int c[SGW_MAX_DIM];
-        for (int k = 0; k < p.pb.dim; k++) c[k] = coarse_extent(T[k], p.cfg.finest_level - p.levels[g][k]);
+        for (int k = 0; k < p.pb.dim; k++) c[k] = coarse_extent(T[k], p.cfg.finest_level - p.levels[g][k], p.N);
         size_t load = 1;
         for (int k = 0; k < p.pb.dim; k++) load *= (size_t)c[k];
-        best = load > best ? load : best;
-        const size_t r = load / (size_t)c[0];
-        rows = r > rows ? r : rows;
         const int kl = last_refined(p, g);
+        const bool direct = lines && p.cfg.finest_level - p.levels[g][0] > 0 && kl > 0;
+        if (!direct) {
+            amax = load > amax ? load : amax;
+            const size_t r = load / (size_t)c[0];
+            rows = r > rows ? r : rows;
+        }
+        int j = 0;
         for (int k = 0; k < p.pb.dim; k++) {
             if (lines && k >= kl) break;
+            if (p.cfg.finest_level - p.levels[g][k] == 0) continue;
             size_t sz = 1;
-            for (int j = 0; j < p.pb.dim; j++) sz *= (size_t)(j <= k ? T[j] : c[j]);
-            best = sz > best ? sz : best;
+            for (int i = 0; i < p.pb.dim; i++) sz *= (size_t)(i <= k ? T[i] : c[i]);
+            size_t& m = (j % 2 == 0) ? bmax : amax;
+            m = sz > m ? sz : m;
+            j++;
         }
     }
+    if (!lines) amax = bmax = amax > bmax ? amax : bmax;
+    *a_elems = (amax + 1) / 2 * 2;
+    *b_elems = (bmax + 1) / 2 * 2;
     if (rows_max) *rows_max = lines ? rows : 0;
-    return (best + 1) / 2 * 2;
 }
 
 static size_t prolong_lds_bytes(const sgw_plan& p, const int* T, bool lines)
 {
     const size_t rs = p.cfg.precision == SGW_FP64 ? 8 : 4;
-    size_t rows = 0;
-    const size_t buf = prolong_buffer_elems(p, T, lines, &rows);
-    return 2 * rs * buf + (lines ? 4 * rows : 0);
+    size_t a = 0, b = 0, rows = 0;
+    prolong_buffer_elems(p, T, lines, &a, &b, &rows);
+    return rs * (a + b) + (lines ? 4 * rows : 0);
 }
 
 // Interpolations and staged coarse values of one finest-grid tile T, summed
@@ -277,7 +303,7 @@ static void prolong_tile_work(const sgw_plan& p, const int* T, double* interp, d
     *load = 0.0;
     for (int g = 0; g < p.G; g++) {
         int c[SGW_MAX_DIM];
-        for (int k = 0; k < d; k++) c[k] = coarse_extent(T[k], p.cfg.finest_level - p.levels[g][k]);
+        for (int k = 0; k < d; k++) c[k] = coarse_extent(T[k], p.cfg.finest_level - p.levels[g][k], p.N);
         double l = 1.0;
         for (int k = 0; k < d; k++) l *= c[k];
         *load += l;
@@ -304,13 +330,17 @@ static double prolong_lines_cost(const sgw_plan& p, const int* T)
         int c[SGW_MAX_DIM], m[SGW_MAX_DIM];
         for (int k = 0; k < d; k++) {
             m[k] = p.cfg.finest_level - p.levels[g][k];
-            c[k] = coarse_extent(T[k], m[k]);
+            c[k] = coarse_extent(T[k], m[k], p.N);
         }
         double load = 1.0;
         for (int k = 0; k < d; k++) load *= c[k];
         const double rows = load / c[0];
-        cost += std::ceil(load / SGW_BLOCK) * SGW_BLOCK * 16.0 + std::ceil(rows / SGW_BLOCK) * SGW_BLOCK * 12.0 * (d - 1);
         const int kl = last_refined(p, g);
+        if (m[0] > 0 && kl > 0)
+            cost += std::ceil(rows / SGW_BLOCK) * SGW_BLOCK * (12.0 * (d - 1) + 2.0 * c[0]); // rows read directly
+        else
+            cost += std::ceil(load / SGW_BLOCK) * SGW_BLOCK * 16.0 +
+                    std::ceil(rows / SGW_BLOCK) * SGW_BLOCK * 12.0 * (d - 1);
         for (int k = 0; k < d && k <= kl; k++) {
             if (m[k] == 0) continue;
             const int R = 1 << m[k];
@@ -363,6 +393,12 @@ static void choose_fine_tile(sgw_plan& p)
         return occ >= 4.0 ? 1.0 : 4.0 / occ;
     };
     bool lines = false;
+    if (manual && d >= 3) {
+        // a manual tile takes the line form when it has its shape
+        int64_t inner = 1;
+        for (int k = 0; k < d - 1; k++) inner *= T[k];
+        lines = inner == SGW_BLOCK && T[d - 1] <= 16 && prolong_lds_bytes(p, T, true) <= 64 * 1024;
+    }
     if (!manual && d >= 3) {
         double best = 1e300;
         int bt[SGW_MAX_DIM] = {1, 1, 1, 1};
@@ -430,7 +466,7 @@ static void choose_fine_tile(sgw_plan& p)
     }
     for (int k = 0; k < SGW_MAX_DIM; k++) p.fine_T[k] = k < d ? T[k] : 1;
     p.fine_lines = lines;
-    p.pro_buf_elems = prolong_buffer_elems(p, p.fine_T, lines, &p.pro_rows_max);
+    prolong_buffer_elems(p, p.fine_T, lines, &p.pro_buf_elems, &p.pro_bufb_elems, &p.pro_rows_max);
     p.pro_lds = prolong_lds_bytes(p, p.fine_T, lines);
 }
 
@@ -779,7 +815,7 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
             pd.stride[k] = s->grids_h[g].stride[k];
             if (k < d) {
                 pd.m[k] = p->cfg.finest_level - p->levels[g][k];
-                pd.c[k] = coarse_extent(p->fine_T[k], pd.m[k]);
+                pd.c[k] = coarse_extent(p->fine_T[k], pd.m[k], p->N);
             } else {
                 pd.m[k] = 0;
                 pd.c[k] = 1;
@@ -804,6 +840,7 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
     s->fine_h.lagrange = p->cfg.prolong == SGW_PROLONG_LAGRANGE5;
     s->fine_h.eps = p->cfg.eps_interp;
     s->fine_h.pad0 = (int32_t)p->pro_buf_elems;
+    s->fine_h.pad1 = (int32_t)p->pro_bufb_elems;
     int pts = 1;
     for (int k = 0; k < SGW_MAX_DIM; k++) {
         s->fine_h.T[k] = p->fine_T[k];

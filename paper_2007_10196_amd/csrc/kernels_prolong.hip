@@ -187,53 +187,97 @@ __device__ __forceinline__ void prolong_tile(ProC pro, FineC F, double* __restri
 // one division, with h, hs and C_r(s) read from a table whose index is the same for every
 // lane (scalar loads).  A node at s = 0 takes the centre's value: every P_r(0) = u_i.
 
+// Sliding state of the stencil along a line: for centre i it holds u_i, u_{i+1}, u_{i+2},
+// the first differences D1(i) = u_i - u_{i-1}, D1(i+1), the second differences
+// K_r = D2(i-1+r), D2(j) = u_{j-1} - 2 u_j + u_{j+1}, and kk_r = eps4 + 13/3 K_r^2.  Moving to
+// centre i+1 takes one new value and one new difference of each order.
+template <typename Real>
+struct Slide {
+    Real c, d, e, D1a, D1b, K0, K1, K2, kk0, kk1, kk2;
+};
+
+template <typename Real, bool LAG>
+__device__ __forceinline__ void slide_init(Slide<Real>& w, Real a, Real b, Real c, Real d, Real e, Real eps4)
+{
+#pragma clang fp contract(off)
+    w.c = c, w.d = d, w.e = e;
+    w.D1a = c - b;
+    w.D1b = d - c;
+    w.K0 = fma(Real(-2), b, a) + c;
+    w.K1 = fma(Real(-2), c, b) + d;
+    w.K2 = fma(Real(-2), d, c) + e;
+    if (!LAG) {
+        w.kk0 = fma(Real(13.0 / 3.0) * w.K0, w.K0, eps4);
+        w.kk1 = fma(Real(13.0 / 3.0) * w.K1, w.K1, eps4);
+        w.kk2 = fma(Real(13.0 / 3.0) * w.K2, w.K2, eps4);
+    }
+}
+
+template <typename Real, bool LAG>
+__device__ __forceinline__ void slide_next(Slide<Real>& w, Real f, Real eps4)
+{
+#pragma clang fp contract(off)
+    w.D1a = w.D1b;
+    w.D1b = w.e - w.d;
+    w.K0 = w.K1;
+    w.K1 = w.K2;
+    w.K2 = fma(Real(-2), w.e, w.d) + f;
+    if (!LAG) {
+        w.kk0 = w.kk1;
+        w.kk1 = w.kk2;
+        w.kk2 = fma(Real(13.0 / 3.0) * w.K2, w.K2, eps4);
+    }
+    w.c = w.d, w.d = w.e, w.e = f;
+}
+
+// What the fine nodes of one centre share: with G_r the first-derivative differences of the
+// substencils (G0 = K0 + 2 D1(i), G1 = D1(i) + D1(i+1), G2 = 2 D1(i+1) - K2), the squared
+// weight denominators e_r = (kk_r + G_r^2)^2, E_r = e_r' e_r'' and A_r = E_r u_i, B_r = E_r G_r,
+// D_r = E_r K_r (Lagrange: E_r = 1).
 template <typename Real>
 struct Centre {
     Real c, A0, A1, A2, B0, B1, B2, D0, D1, D2, E0, E1, E2;
 };
 
-template <typename Real>
-__device__ __forceinline__ void centre_setup(Centre<Real>& z, Real a, Real b, Real c, Real d, Real e, Real eps4,
-                                             int lagrange)
+template <typename Real, bool LAG>
+__device__ __forceinline__ void centre_setup(Centre<Real>& z, const Slide<Real>& w)
 {
-    const Real K0 = a - Real(2) * b + c, K1 = b - Real(2) * c + d, K2 = c - Real(2) * d + e;
-    const Real G0 = K0 + Real(2) * (c - b), G1 = d - b, G2 = Real(2) * (d - c) - K2;
-    z.c = c;
-    if (lagrange) {
-        z.A0 = z.A1 = z.A2 = c;
+#pragma clang fp contract(off)
+    const Real G0 = fma(Real(2), w.D1a, w.K0), G1 = w.D1a + w.D1b, G2 = fma(Real(2), w.D1b, -w.K2);
+    z.c = w.c;
+    if (LAG) {
+        z.A0 = z.A1 = z.A2 = w.c;
         z.B0 = G0, z.B1 = G1, z.B2 = G2;
-        z.D0 = K0, z.D1 = K1, z.D2 = K2;
+        z.D0 = w.K0, z.D1 = w.K1, z.D2 = w.K2;
         z.E0 = z.E1 = z.E2 = Real(1);
         return;
     }
-    Real e0 = eps4 + (G0 * G0 + Real(13.0 / 3.0) * K0 * K0);
-    Real e1 = eps4 + (G1 * G1 + Real(13.0 / 3.0) * K1 * K1);
-    Real e2 = eps4 + (G2 * G2 + Real(13.0 / 3.0) * K2 * K2);
+    Real e0 = fma(G0, G0, w.kk0), e1 = fma(G1, G1, w.kk1), e2 = fma(G2, G2, w.kk2);
     e0 *= e0;
     e1 *= e1;
     e2 *= e2;
     z.E0 = e1 * e2;
     z.E1 = e0 * e2;
     z.E2 = e0 * e1;
-    z.A0 = z.E0 * c, z.A1 = z.E1 * c, z.A2 = z.E2 * c;
+    z.A0 = z.E0 * w.c, z.A1 = z.E1 * w.c, z.A2 = z.E2 * w.c;
     z.B0 = z.E0 * G0, z.B1 = z.E1 * G1, z.B2 = z.E2 * G2;
-    z.D0 = z.E0 * K0, z.D1 = z.E1 * K1, z.D2 = z.E2 * K2;
+    z.D0 = z.E0 * w.K0, z.D1 = z.E1 * w.K1, z.D2 = z.E2 * w.K2;
 }
 
-template <typename Real>
-__device__ __forceinline__ Real centre_value(const Centre<Real>& z, const SGW_CONST STab<Real>& t, int copy,
-                                             int lagrange)
+template <typename Real, bool LAG>
+__device__ __forceinline__ Real centre_value(const Centre<Real>& z, const SGW_CONST STab<Real>& t, int copy)
 {
+#pragma clang fp contract(off)
     if (copy) return z.c;
-    const Real Q0 = z.A0 + t.h * z.B0 + t.hs * z.D0;
-    const Real Q1 = z.A1 + t.h * z.B1 + t.hs * z.D1;
-    const Real Q2 = z.A2 + t.h * z.B2 + t.hs * z.D2;
-    const Real num = t.c0 * Q0 + t.c1 * Q1 + t.c2 * Q2;
-    if (lagrange) return num;
-    return rdiv(num, t.c0 * z.E0 + t.c1 * z.E1 + t.c2 * z.E2);
+    const Real Q0 = fma(t.hs, z.D0, fma(t.h, z.B0, z.A0));
+    const Real Q1 = fma(t.hs, z.D1, fma(t.h, z.B1, z.A1));
+    const Real Q2 = fma(t.hs, z.D2, fma(t.h, z.B2, z.A2));
+    const Real num = fma(t.c2, Q2, fma(t.c1, Q1, t.c0 * Q0));
+    if (LAG) return num;
+    return rdiv(num, fma(t.c2, z.E2, fma(t.c1, z.E1, t.c0 * z.E0)));
 }
 
-template <typename Real, int D>
+template <typename Real, int D, bool LAG>
 __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __restrict__ out, int tile)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -248,7 +292,7 @@ __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __
         }
     }
     const Real eps4 = (Real)(4.0 * F->eps);
-    const int lagrange = F->lagrange;
+    const int lagrange = LAG ? 1 : 0;
     const int Tlast = F->T[D - 1];
     typedef const SGW_CONST STab<Real>* TabC;
     const TabC stab = (TabC)F->stab;
@@ -257,7 +301,7 @@ __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __
     for (int r = 0; r < SGW_MAXRP; r++) acc[r] = 0.0;
     Real* bufA = (Real*)smem;
     Real* bufB = bufA + F->pad0;
-    int* rowoff = (int*)(bufB + F->pad0);
+    int* rowoff = (int*)(bufB + F->pad1);
 
     for (int gidx = 0; gidx < F->G; gidx++) {
         ProC p = pro + gidx;
@@ -268,10 +312,10 @@ __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __
             const int m = p->m[k];
             cl[k] = (m == 0) ? J0[k] : (((2 * J0[k] + (1 << m)) >> (m + 1)) - 2);
         }
-        // ---- coarse block (periodic wrap): element offsets of its rows along direction 1, then
-        // the rows; a wrapped index cl + c + 2n >= 0 takes its remainder by n with the fast division
-        const int rows = p->rows;
-        for (int r = tid; r < rows; r += SGW_BLOCK) {
+        const int kl = p->klast;
+        // element offset of row r of the coarse block (its position along directions 2..d,
+        // periodic wrap: cl + c + 2n >= 0 takes its remainder by n with the fast division)
+        auto row_offset = [&](int r) {
             uint32_t rr = (uint32_t)r;
             int gi = 0;
 #pragma unroll
@@ -282,11 +326,23 @@ __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __
                 const uint32_t xw = (uint32_t)(cl[k] + c + 2 * p->n[k]);
                 gi += (int)(xw - FDIV(xw, p->fd_n[k]) * (uint32_t)p->n[k]) * p->stride[k];
             }
-            rowoff[r] = gi;
-        }
-        __syncthreads();
-        {
-            const int c0 = p->c[0], n0 = p->n[0];
+            return gi;
+        };
+        // wrapped position along direction 1 of coarse index cl_1 + l: the same for every lane
+        const int c0 = p->c[0], n0 = p->n[0];
+        auto wrap0 = [&](int l) {
+            const uint32_t xw = (uint32_t)(cl[0] + l + 2 * n0);
+            return (int)(xw - FDIV(xw, p->fd_n[0]) * (uint32_t)n0);
+        };
+        // a grid refined along direction 1 reads its coarse rows from global memory in the first
+        // pass; the others stage the coarse block in LDS first
+        const bool direct = p->m[0] > 0 && kl > 0;
+        Real* src = bufA;
+        Real* dst = bufB;
+        if (!direct) {
+            const int rows = p->rows;
+            for (int r = tid; r < rows; r += SGW_BLOCK) rowoff[r] = row_offset(r);
+            __syncthreads();
             for (int e = tid; e < p->load_total; e += SGW_BLOCK) {
                 const uint32_t row = FDIV((uint32_t)e, p->fd_c[0]);
                 const int x0 = e - (int)row * c0;
@@ -294,16 +350,43 @@ __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __
                 const int x = (int)(xw - FDIV(xw, p->fd_n[0]) * (uint32_t)n0);
                 bufA[e] = u[rowoff[row] + x];
             }
+            __syncthreads();
+        } else {
+            // ---- first pass from global memory: lane L refines coarse row L along direction 1
+            const int m = p->m[0];
+            const int T0 = F->T[0], lines = p->rows;
+            const int R = 1 << m, half = R >> 1, Jk = J0[0];
+            const int ifirst = (2 * Jk + R) >> (m + 1);
+            const TabC tb = stab + (R - 2);
+            for (int L = tid; L < lines; L += SGW_BLOCK) {
+                const Real* __restrict__ up = u + row_offset(L);
+                Real* dp = bufB + L * T0;
+                Slide<Real> w;
+                slide_init<Real, LAG>(w, up[wrap0(0)], up[wrap0(1)], up[wrap0(2)], up[wrap0(3)], up[wrap0(4)], eps4);
+                int li = 5;
+                Centre<Real> z;
+                centre_setup<Real, LAG>(z, w);
+                int next = ifirst * R + half - Jk;
+                for (int t = 0; t < T0; t++) {
+                    if (t == next) {
+                        slide_next<Real, LAG>(w, up[wrap0(li)], eps4);
+                        li++;
+                        centre_setup<Real, LAG>(z, w);
+                        next += R;
+                    }
+                    const int q = (Jk + t + half) & (R - 1);
+                    dp[t] = centre_value<Real, LAG>(z, tb[q], q == half);
+                }
+            }
+            __syncthreads();
+            src = bufB;
+            dst = bufA;
         }
-        __syncthreads();
-        Real* src = bufA;
-        Real* dst = bufB;
-        const int kl = p->klast;
         // ---- passes before the last refined direction: one lane per line, into LDS
 #pragma unroll
         for (int k = 0; k < D - 1; k++) {
             const int m = p->m[k];
-            if (m == 0 || k >= kl) continue;
+            if (m == 0 || k >= kl || (k == 0 && direct)) continue;
             const int Tk = F->T[k], ck = p->c[k], inner = F->inner[k];
             const int lines = inner * p->outer[k];
             const int R = 1 << m, half = R >> 1, Jk = J0[k];
@@ -314,20 +397,21 @@ __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __
                 const int a = L - b * inner;
                 const Real* sp = src + a + inner * (ck * b);
                 Real* dp = dst + a + inner * (Tk * b);
-                Real w0 = sp[0], w1 = sp[inner], w2 = sp[2 * inner], w3 = sp[3 * inner], w4 = sp[4 * inner];
+                Slide<Real> w;
+                slide_init<Real, LAG>(w, sp[0], sp[inner], sp[2 * inner], sp[3 * inner], sp[4 * inner], eps4);
                 const Real* nx = sp + 5 * inner;
                 Centre<Real> z;
-                centre_setup(z, w0, w1, w2, w3, w4, eps4, lagrange);
+                centre_setup<Real, LAG>(z, w);
                 int next = ifirst * R + half - Jk; // first node of the next centre
                 for (int t = 0; t < Tk; t++) {
                     if (t == next) {
-                        w0 = w1, w1 = w2, w2 = w3, w3 = w4, w4 = *nx;
+                        slide_next<Real, LAG>(w, *nx, eps4);
                         nx += inner;
-                        centre_setup(z, w0, w1, w2, w3, w4, eps4, lagrange);
+                        centre_setup<Real, LAG>(z, w);
                         next += R;
                     }
                     const int q = (Jk + t + half) & (R - 1);
-                    dp[t * inner] = centre_value(z, tb[q], q == half, lagrange);
+                    dp[t * inner] = centre_value<Real, LAG>(z, tb[q], q == half);
                 }
             }
             __syncthreads();
@@ -344,23 +428,24 @@ __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __
             const int ifirst = (2 * Jk + R) >> (m + 1);
             const TabC tb = stab + (R - 2);
             const Real* sp = src + tid;
-            Real w0 = sp[0], w1 = sp[SGW_BLOCK], w2 = sp[2 * SGW_BLOCK], w3 = sp[3 * SGW_BLOCK],
-                 w4 = sp[4 * SGW_BLOCK];
+            Slide<Real> w;
+            slide_init<Real, LAG>(w, sp[0], sp[SGW_BLOCK], sp[2 * SGW_BLOCK], sp[3 * SGW_BLOCK], sp[4 * SGW_BLOCK],
+                                  eps4);
             const Real* nx = sp + 5 * SGW_BLOCK;
             Centre<Real> z;
-            centre_setup(z, w0, w1, w2, w3, w4, eps4, lagrange);
+            centre_setup<Real, LAG>(z, w);
             int next = ifirst * R + half - Jk;
 #pragma unroll
             for (int t = 0; t < SGW_MAXRP; t++) {
                 if (t < Tlast) {
                     if (t == next) {
-                        w0 = w1, w1 = w2, w2 = w3, w3 = w4, w4 = *nx;
+                        slide_next<Real, LAG>(w, *nx, eps4);
                         nx += SGW_BLOCK;
-                        centre_setup(z, w0, w1, w2, w3, w4, eps4, lagrange);
+                        centre_setup<Real, LAG>(z, w);
                         next += R;
                     }
                     const int q = (Jk + t + half) & (R - 1);
-                    acc[t] += cg * (double)centre_value(z, tb[q], q == half, lagrange);
+                    acc[t] = fma(cg, (double)centre_value<Real, LAG>(z, tb[q], q == half), acc[t]);
                 }
             }
         } else if (kl >= 0) {
@@ -385,15 +470,16 @@ __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __
             for (int bq = 0; bq < SGW_MAXRP; bq++) {
                 if (bq < Tlast) {
                     const Real* q = sp + bq * slice;
-                    acc[bq] += cg * (double)interp5<Real>(q[0], q[inner], q[2 * inner], q[3 * inner], q[4 * inner], sv,
-                                                          eps4, lagrange);
+                    acc[bq] = fma(cg, (double)interp5<Real>(q[0], q[inner], q[2 * inner], q[3 * inner], q[4 * inner],
+                                                            sv, eps4, lagrange),
+                                  acc[bq]);
                 }
             }
         } else {
             // ---- no direction refined: the coarse block is the tile
 #pragma unroll
             for (int r = 0; r < SGW_MAXRP; r++)
-                if (r < Tlast) acc[r] += cg * (double)src[tid + r * SGW_BLOCK];
+                if (r < Tlast) acc[r] = fma(cg, (double)src[tid + r * SGW_BLOCK], acc[r]);
         }
         __syncthreads();
     }
@@ -422,7 +508,10 @@ __device__ __forceinline__ void prolong_any(ProC pro, FineC F, double* out, int 
 {
     if constexpr (D >= 3) {
         if (F->lines) {
-            prolong_tile_lines<Real, D>(pro, F, out, tile);
+            if (F->lagrange)
+                prolong_tile_lines<Real, D, true>(pro, F, out, tile);
+            else
+                prolong_tile_lines<Real, D, false>(pro, F, out, tile);
             return;
         }
     }

@@ -23,7 +23,8 @@ struct sgw_plan {
     std::vector<GridDev> grids;                // geometry only (pointers filled by the solver)
     std::vector<int64_t> coef_off;             // [G][4] offsets into the coefficient tables
     int fine_T[SGW_MAX_DIM] = {1, 1, 1, 1};
-    size_t pro_buf_elems = 0;
+    size_t pro_buf_elems = 0;                  // prolongation LDS buffer A (and B in the old form)
+    size_t pro_bufb_elems = 0;                 // buffer B
     bool fine_lines = false;                   // 3D/4D line form of the prolongation
     size_t pro_rows_max = 0;                   // its LDS row-offset table entries
     size_t pro_lds = 0;                        // LDS bytes of a prolongation workgroup

@@ -169,7 +169,7 @@ struct alignas(64) FineDev {
     int32_t T[SGW_MAX_DIM];
     int32_t ntile[SGW_MAX_DIM];
     int32_t inner[SGW_MAX_DIM];      // prod_{j<k} T[j]
-    int32_t tile_points, pad0, pad1, pad2;
+    int32_t tile_points, pad0, pad1, pad2; // pad0, pad1: LDS elements of prolongation buffers A, B
     FastDiv fd_T[SGW_MAX_DIM];
     FastDiv fd_inner[SGW_MAX_DIM];
     double eps;

@@ -120,11 +120,18 @@ def test_footprints_scale_with_precision():
 
 def _coarse_extent(pb, level, T):
     """Coarse values a tile row of extent T needs per direction: T without refinement, else the
-    (T-1)/R + 1 intervals it spans plus the 5-point stencil (Sec. 2.2.1)."""
+    most coarse centres its nodes J0..J0+T-1 reach over the tile positions (node J has centre
+    floor(J/R + 1/2), Sec. 2.2.1) plus the two stencil nodes on either side, by brute force."""
     out = []
+    N = pb.n_fine
     for k in range(pb.d):
         m = pb.nl - level[k]
-        out.append(T[k] if m == 0 else (T[k] - 1) // (1 << m) + 6)
+        if m == 0:
+            out.append(T[k])
+            continue
+        R = 1 << m
+        centre = lambda J: (2 * J + R) >> (m + 1)
+        out.append(max(centre(J0 + T[k] - 1) - centre(J0) + 1 for J0 in range(0, N, T[k])) + 4)
     return out
 
 
