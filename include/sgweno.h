@@ -154,7 +154,9 @@ sgw_status sgw_plan_grid(const sgw_plan_t* plan, int32_t g, int32_t level[SGW_MA
 /* Finest-grid tile the prolongation kernel uses (one workgroup per tile). */
 sgw_status sgw_plan_fine_tile(const sgw_plan_t* plan, int32_t tile[SGW_MAX_DIM]);
 
-/* Box extents the stage kernel uses for grid g (one workgroup per box). */
+/* Box extents the stage kernel uses for grid g (one workgroup per box).  4D grids
+ * without manual boxes march as line sweeps (one launch per direction, a lane per
+ * segment of a grid line, no boxes) and report all-zero extents. */
 sgw_status sgw_plan_grid_box(const sgw_plan_t* plan, int32_t g, int32_t box[SGW_MAX_DIM]);
 
 /* ---------------------------------------------------------------- solvers

@@ -73,6 +73,32 @@ static int64_t binom(int n, int k)
 
 // ---------------------------------------------------------------- tiling
 
+// The line sweep divides segment and line indices with the fast divisions of its descriptor:
+// check each against plain division at the ends of its range (0, d - 1, d, the largest index)
+// before any kernel relies on it.
+static bool line_divisions_ok(const GridDev& g)
+{
+    auto ok = [](const FastDiv& f, uint32_t d, uint32_t xmax) {
+        if (f.d != d || d == 0) return false;
+        const uint32_t xs[] = {0u, d - 1, d, xmax, xmax > 0 ? xmax - 1 : 0};
+        for (uint32_t x : xs) {
+            if (x > xmax) continue;
+            const uint32_t q = (uint32_t)((((uint64_t)x * f.m) >> 32) + x) >> f.s;
+            if (q != x / d) return false;
+        }
+        return true;
+    };
+    uint32_t size = 1;
+    for (int k = 0; k < g.d; k++) size *= (uint32_t)g.n[k];
+    for (int k = 0; k < g.d; k++) {
+        const uint32_t segs = (uint32_t)g.lsegl[k] * (uint32_t)g.ltrans[k];
+        if (!ok(g.fd_n[k], (uint32_t)g.n[k], size) || !ok(g.fd_lsegl[k], (uint32_t)g.lsegl[k], segs) ||
+            !ok(g.fd_ltrans[k], (uint32_t)g.ltrans[k], segs))
+            return false;
+    }
+    return true;
+}
+
 static void fill_box_geometry(GridDev& g, int precision)
 {
     (void)precision;
@@ -560,6 +586,29 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
         tot += n;
         bool manual = false;
         for (int k = 0; k < d; k++) manual |= cfg->box[k] > 0;
+        if (d == 4 && !manual) {
+            // 4D: the line sweep (no stage boxes); a work item is SGW_LWAVE segments of
+            // SGW_LSEG nodes, enough items for the direction with the most segments
+            gd.line_mode = 1;
+            int64_t most = 0;
+            for (int k = 0; k < SGW_MAX_DIM; k++) gd.fd_n[k] = make_fastdiv((uint32_t)gd.n[k]);
+            for (int k = 0; k < d; k++) {
+                gd.lsegl[k] = (gd.n[k] + SGW_LSEG - 1) / SGW_LSEG;
+                gd.ltrans[k] = (int32_t)(n / gd.n[k]);
+                gd.fd_lsegl[k] = make_fastdiv((uint32_t)gd.lsegl[k]);
+                gd.fd_ltrans[k] = make_fastdiv((uint32_t)gd.ltrans[k]);
+                if ((gd.n[k] & (gd.n[k] - 1)) == 0) gd.pow2_mask |= 1 << k;
+                const int64_t segs = (int64_t)gd.lsegl[k] * gd.ltrans[k];
+                most = segs > most ? segs : most;
+            }
+            gd.nbox = (int32_t)((most + SGW_LWAVE - 1) / SGW_LWAVE);
+            p->line_mode = true;
+            if (!line_divisions_ok(gd)) {
+                delete p;
+                return sgw_fail(SGW_ERR_UNSUPPORTED, "line sweep index division fails for grid %d", g);
+            }
+            continue;
+        }
         if (manual) {
             for (int k = 0; k < SGW_MAX_DIM; k++) {
                 gd.t[k] = (k < d && cfg->box[k] > 0) ? (cfg->box[k] < gd.n[k] ? cfg->box[k] : gd.n[k])
@@ -592,7 +641,7 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     p->stage_lds = p->lds_whole = p->lds_boxed = 0;
     for (int pass = 0; pass < 2; pass++)
         for (int g = 0; g < p->G; g++) {
-            const bool one = p->grids[g].nbox == 1;
+            const bool one = p->grids[g].nbox == 1 && !p->grids[g].line_mode;
             if (one != (pass == 0)) continue;
             p->grids[g].first_item = (int32_t)p->nitems;
             p->nitems += p->grids[g].nbox;
@@ -1041,7 +1090,8 @@ static hipError_t enqueue_step(sgw_solver* s, int mode, hipStream_t st)
         for (int stage = 0; stage < 3; stage++)
             for (int g = 0; g < p->G; g++) {
                 e = launch_stage(s->items_d + p->grids[g].first_item, p->grids[g].nbox, stage, p->cfg.precision,
-                                 p->pb.dim, stage_lds_bytes(p->grids[g], p->cfg.precision), 0, st);
+                                 p->pb.dim, stage_lds_bytes(p->grids[g], p->cfg.precision), 0, st,
+                                 p->grids[g].line_mode != 0);
                 if (e != hipSuccess) return e;
             }
         return hipSuccess;
@@ -1053,7 +1103,8 @@ static hipError_t enqueue_step(sgw_solver* s, int mode, hipStream_t st)
         if (e != hipSuccess) return e;
     }
     for (int stage = 0; stage < 3 && nbx; stage++) {
-        e = launch_stage(s->items_d + nw, nbx, stage, p->cfg.precision, p->pb.dim, p->lds_boxed, s->grid, st);
+        e = launch_stage(s->items_d + nw, nbx, stage, p->cfg.precision, p->pb.dim, p->lds_boxed, s->grid, st,
+                         p->line_mode);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

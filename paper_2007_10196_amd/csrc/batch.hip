@@ -162,7 +162,7 @@ static hipError_t enqueue_stages(sgw_batch* b, int stage, hipStream_t st)
             const size_t l = b->lds[0][d] > b->lds[1][d] ? b->lds[0][d] : b->lds[1][d];
             e = launch_stage_range(b->items_d, b->ranges_d + (2 * 4 + d) * 2,
                                    stage_grid(b->precision, d + 1, l, b->blocks_per_cu), stage, b->precision, d + 1, l,
-                                   st);
+                                   st, d == 3);
         }
         return e;
     }
@@ -176,7 +176,7 @@ static hipError_t enqueue_stages(sgw_batch* b, int stage, hipStream_t st)
         for (int d = 0; d < 4 && e == hipSuccess; d++)
             if (b->lds[1][d] && (all || b->ranges_h[1][d][1]))
                 e = launch_stage_range(b->items_d, b->ranges_d + (4 + d) * 2, b->blocks[1][d], s, b->precision, d + 1,
-                                       b->lds[1][d], st);
+                                       b->lds[1][d], st, d == 3);
     return e;
 }
 
@@ -304,6 +304,9 @@ static sgw_status admit_one(sgw_batch_t* b, sgw_solver_t* s, double t_final, int
     if (!s->restricted) return sgw_fail(SGW_ERR_STATE, "admit before restrict");
     if (s->batch_slot >= 0) return sgw_fail(SGW_ERR_STATE, "solver already in a batch");
     if (s->plan->cfg.precision != b->precision) return sgw_fail(SGW_ERR_INVALID_ARG, "precision differs from batch");
+    // a batch runs its 4D grids as line sweeps
+    if (s->plan->pb.dim == 4 && !s->plan->line_mode)
+        return sgw_fail(SGW_ERR_UNSUPPORTED, "4D solvers with manual stage boxes run alone, not in a batch");
     if (!(t_final >= 0.0)) return sgw_fail(SGW_ERR_INVALID_ARG, "bad final time");
     const uint64_t need = solver_bytes(s);
     if (b->used + need > b->budget)

@@ -602,6 +602,171 @@ __global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __rest
     }
 }
 
+// ---------------------------------------------------------------- line sweep (4D)
+//
+// The same stage with one launch per direction k and no halo: a lane takes a segment of
+// SGW_LSEG nodes of one grid line along k, reads the SGW_LSEG + 6 values its interface fluxes
+// need (periodic wrap along the line) straight from memory, forms the SGW_LSEG + 1 fluxes
+// with window_fluxes (the box kernel's arithmetic, so the same bits) and adds
+// (F_{i-1/2} - F_{i+1/2}) / h_k of its nodes to the sum of the earlier directions.  That
+// partial sum waits in a state copy the stage does not read: the stage output for stages 1
+// and 2, the stage-1 buffer in stage 3.  The last direction applies the Runge-Kutta
+// combination, writes the stage output and reduces the next wave speed.
+template <typename Real, int D, int k, bool LIN>
+__device__ __forceinline__ void line_segment(GridC g, int blk, int stage, Real alpha, Real& amax)
+{
+    const int lane = threadIdx.x;
+    const int n = g->n[k], segl = g->lsegl[k], trans = g->ltrans[k];
+    const int sid = blk * SGW_LWAVE + lane;
+    if (sid >= segl * trans) return;
+    int q, t;
+    if constexpr (k == 0) {
+        // the segments of one row on neighbouring lanes: each lane streams its piece of the row
+        const uint32_t a = FDIV((uint32_t)sid, g->fd_lsegl[0]);
+        t = (int)a;
+        q = sid - (int)a * segl;
+    } else {
+        // neighbouring lines (direction 1 fastest) on neighbouring lanes: coalesced
+        const uint32_t a = FDIV((uint32_t)sid, g->fd_ltrans[k]);
+        q = (int)a;
+        t = sid - (int)a * trans;
+    }
+    // the line's position: t over the directions other than k, direction 1 fastest
+    const int csrc = g->coef_src[k];
+    int base = 0, xc = 0;
+    {
+        uint32_t r = (uint32_t)t;
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            if (j == k) continue;
+            const uint32_t qq = FDIV(r, g->fd_n[j]);
+            const int x = (int)(r - qq * (uint32_t)g->n[j]);
+            r = qq;
+            base += x * g->stride[j];
+            if (j == csrc) xc = x;
+        }
+    }
+    const int stride = g->stride[k];
+    const int i0 = q * SGW_LSEG;
+    const Real* __restrict__ in = (const Real*)(stage == 0 ? g->u : stage == 1 ? g->a : g->b);
+    Real v[SGW_LSEG + 6]; // u_{i0-3} .. u_{i0+SGW_LSEG+2}
+    if ((g->pow2_mask >> k) & 1) {
+#pragma unroll
+        for (int c = 0; c < SGW_LSEG + 6; c++) v[c] = in[base + ((i0 - 3 + c) & (n - 1)) * stride];
+    } else {
+        // n >= 4: positions -3 .. n + 9 need at most one addition or three subtractions
+#pragma unroll
+        for (int c = 0; c < SGW_LSEG + 6; c++) {
+            int p = i0 - 3 + c;
+            p += p < 0 ? n : 0;
+            p -= p >= n ? n : 0;
+            p -= p >= n ? n : 0;
+            p -= p >= n ? n : 0;
+            v[c] = in[base + p * stride];
+        }
+    }
+    // the sum of the earlier directions and (last direction, stages 2 and 3) u^n of the
+    // segment's nodes are loaded with the window, so their latency overlaps it
+    constexpr bool last = k == D - 1;
+    Real* __restrict__ part = (Real*)(stage == 1 ? g->b : g->a);
+    const Real* __restrict__ u0 = (const Real*)g->u;
+    Real pin[SGW_LSEG], un[SGW_LSEG];
+#pragma unroll
+    for (int i = 0; i < SGW_LSEG; i++) {
+        const bool in_line = i0 + i < n;
+        const int gi = base + (i0 + i) * stride;
+        pin[i] = (k > 0 && in_line) ? part[gi] : Real(0);
+        un[i] = (last && stage > 0 && in_line) ? u0[gi] : Real(0);
+    }
+    const bool burgers = g->flux == SGW_FLUX_BURGERS;
+    Real cp = Real(0), cm = Real(0);
+    if (!burgers) {
+        // f_k = c u along the line (advection, Vlasov): f^+- = (c +- alpha)/2 u
+        Real c = (Real)g->lin_c[k];
+        if (csrc >= 0) c = (Real)g->coef[k][xc];
+        cp = Real(0.5) * (c + alpha);
+        cm = Real(0.5) * (c - alpha);
+    }
+    Real F[SGW_LSEG + 1]; // F_{i0-1/2} .. F_{i0+SGW_LSEG-1/2}
+    window_fluxes<Real, SGW_LSEG + 1, LIN>(v, burgers, cp, cm, alpha, (Real)(g->eps * 4.0), F);
+    const Real ih = (Real)g->inv_h[k];
+    if constexpr (!last) {
+#pragma unroll
+        for (int i = 0; i < SGW_LSEG; i++)
+            if (i0 + i < n) part[base + (i0 + i) * stride] = fma(F[i] - F[i + 1], ih, pin[i]);
+        return;
+    }
+    // ---- last direction: TVD-RK3 stage u1 = u + dt L(u); u2 = 3/4 u + 1/4 (u1 + dt L(u1));
+    //      u = 1/3 u + 2/3 (u2 + dt L(u2))
+    const Real dtr = (Real)((const SGW_CONST ReqDev*)g->req)->dt;
+    Real* __restrict__ out = (Real*)(stage == 0 ? g->a : stage == 1 ? g->b : g->u);
+#pragma unroll
+    for (int i = 0; i < SGW_LSEG; i++)
+        if (i0 + i < n) {
+            const Real acc = fma(F[i] - F[i + 1], ih, pin[i]);
+            const Real val = fma(dtr, acc, v[i + 3]);
+            Real res;
+            if (stage == 0) res = val;
+            else if (stage == 1) res = fma(Real(0.75), un[i], Real(0.25) * val);
+            else res = fma(Real(1.0 / 3.0), un[i], Real(2.0 / 3.0) * val);
+            out[base + (i0 + i) * stride] = res;
+            amax = absmax(amax, res);
+        }
+}
+
+// One wavefront per workgroup, persistent over a contiguous range of the work items
+// (grid, block of SGW_LWAVE segments).
+template <typename Real, int D, int k>
+__global__ void __launch_bounds__(SGW_LWAVE) line_kernel(const WorkItem* __restrict__ items, int nitems,
+                                                         const int* __restrict__ range_dev, int stage)
+{
+    if (range_dev) {
+        items += range_dev[0];
+        nitems = range_dev[1];
+    }
+    // XCD-aware order, as in the box kernel: neighbouring items (neighbouring lines of one
+    // grid) on one XCD share its L2
+    const int nb = gridDim.x;
+    int bid = blockIdx.x;
+    if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+    const int w_end = (int)(((uint64_t)(bid + 1) * (uint32_t)nitems) / (uint32_t)nb);
+    for (int w = (int)(((uint64_t)bid * (uint32_t)nitems) / (uint32_t)nb); w < w_end; w++) {
+        const SGW_CONST WorkItem* it = (const SGW_CONST WorkItem*)items + w;
+        GridC g = (GridC)it->g;
+        if (((const SGW_CONST ReqDev*)g->req)->done) continue;
+        // the wave-speed slot the next stage reads is cleared by the stage before it
+        if (k == 0 && g->dyn_alpha && it->box == 0 && threadIdx.x == 0) g->alpha[(stage + 2) % 3] = 0ull;
+        const Real alpha =
+            g->dyn_alpha ? (Real)__longlong_as_double((long long)g->alpha[stage]) : (Real)g->alpha_c[k];
+        Real amax = Real(0);
+        if (g->linear)
+            line_segment<Real, D, k, true>(g, it->box, stage, alpha, amax);
+        else
+            line_segment<Real, D, k, false>(g, it->box, stage, alpha, amax);
+        if (k == D - 1 && g->dyn_alpha) {
+            // one atomic max per wavefront on the bit pattern (order-free)
+            const double m = wave_max((double)amax);
+            if (threadIdx.x == 0) atomicMax(g->alpha + (stage + 1) % 3, (unsigned long long)__double_as_longlong(m));
+        }
+    }
+}
+
+template <typename Real>
+hipError_t launch_lines(const WorkItem* items, int nitems, const int* range_dev, int blocks, int stage, int dim,
+                        hipStream_t s)
+{
+    if (dim != 4) return hipErrorInvalidValue;
+#define SGW_LINE(K)                                                                                                   \
+    hipLaunchKernelGGL((line_kernel<Real, 4, K>), dim3(blocks), dim3(SGW_LWAVE), 0, s, items, nitems, range_dev, stage); \
+    if (hipGetLastError() != hipSuccess) return hipGetLastError();
+    SGW_LINE(0)
+    SGW_LINE(1)
+    SGW_LINE(2)
+    SGW_LINE(3)
+#undef SGW_LINE
+    return hipSuccess;
+}
+
 template <typename Real, int D, bool FUSED>
 int occupancy_d(size_t lds_bytes)
 {
@@ -659,6 +824,7 @@ hipError_t launch_r(int dim, const WorkItem* items, int nitems, const int* range
 
 size_t stage_lds_bytes(const GridDev& g, int precision)
 {
+    if (g.line_mode) return 16; // the line sweep uses no LDS; a nominal size keeps its launches in the lists
     const size_t rs = precision == SGW_FP64 ? 8 : 4;
     int fmax_ = 0;
     for (int k = 0; k < g.d; k++) fmax_ = g.flux_total[k] > fmax_ ? g.flux_total[k] : fmax_;
@@ -690,10 +856,21 @@ int stage_occupancy(int precision, int dim, size_t lds_bytes, bool fused)
     return precision == SGW_FP64 ? occupancy_r<double, false>(dim, lds_bytes) : occupancy_r<float, false>(dim, lds_bytes);
 }
 
+// persistent one-wavefront workgroups of the line sweep: 16 per compute unit
+#ifndef SGW_LINE_WAVES_PER_CU
+#define SGW_LINE_WAVES_PER_CU 24
+#endif
+int line_grid() { return SGW_LINE_WAVES_PER_CU * device_cus(); }
+
 hipError_t launch_stage(const WorkItem* items, int nitems, int stage, int precision, int dim, size_t lds_bytes,
-                        int grid_cap, hipStream_t s)
+                        int grid_cap, hipStream_t s, bool lines)
 {
     if (nitems <= 0) return hipSuccess;
+    if (lines) {
+        int blocks = nitems < line_grid() ? nitems : line_grid();
+        if (precision == SGW_FP64) return launch_lines<double>(items, nitems, nullptr, blocks, stage, dim, s);
+        return launch_lines<float>(items, nitems, nullptr, blocks, stage, dim, s);
+    }
     int blocks = nitems;
     if (grid_cap > 0 && blocks > grid_cap) blocks = grid_cap;
     if (precision == SGW_FP64) return launch_r<double>(dim, items, nitems, nullptr, blocks, stage, lds_bytes, s);
@@ -701,8 +878,12 @@ hipError_t launch_stage(const WorkItem* items, int nitems, int stage, int precis
 }
 
 hipError_t launch_stage_range(const WorkItem* items, const int* range_dev, int blocks, int stage, int precision,
-                              int dim, size_t lds_bytes, hipStream_t s)
+                              int dim, size_t lds_bytes, hipStream_t s, bool lines)
 {
+    if (lines) {
+        if (precision == SGW_FP64) return launch_lines<double>(items, 0, range_dev, line_grid(), stage, dim, s);
+        return launch_lines<float>(items, 0, range_dev, line_grid(), stage, dim, s);
+    }
     if (precision == SGW_FP64) return launch_r<double>(dim, items, 0, range_dev, blocks, stage, lds_bytes, s);
     return launch_r<float>(dim, items, 0, range_dev, blocks, stage, lds_bytes, s);
 }

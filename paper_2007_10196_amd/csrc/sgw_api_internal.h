@@ -26,6 +26,7 @@ struct sgw_plan {
     size_t pro_buf_elems = 0;                  // prolongation LDS buffer A (and B in the old form)
     size_t pro_bufb_elems = 0;                 // buffer B
     bool fine_lines = false;                   // 3D/4D line form of the prolongation
+    bool line_mode = false;                    // 4D: the stage runs as line sweeps (no boxes)
     size_t pro_rows_max = 0;                   // its LDS row-offset table entries
     size_t pro_lds = 0;                        // LDS bytes of a prolongation workgroup
     uint64_t copy_bytes = 0, state_bytes = 0, scratch_bytes = 0;

@@ -129,7 +129,20 @@ struct alignas(64) GridDev {
     double lin_c[SGW_MAX_DIM];       // constant coefficient of a linear flux (advection)
     double alpha_c[SGW_MAX_DIM];     // constant LF speed max|f_k'| (advection, Vlasov)
     double eps;
+    // line sweep (4D grids): one launch per direction k, a lane per segment of SGW_LSEG nodes
+    // of a grid line along k, SGW_LWAVE segments per work item
+    int32_t line_mode;
+    int32_t pow2_mask;               // bit k: n[k] is a power of two (periodic wrap by a mask)
+    int32_t lsegl[SGW_MAX_DIM];      // segments per line along k: ceil(n[k] / SGW_LSEG)
+    int32_t ltrans[SGW_MAX_DIM];     // lines along k: prod_{j != k} n[j]
+    FastDiv fd_lsegl[SGW_MAX_DIM];
+    FastDiv fd_ltrans[SGW_MAX_DIM];
 };
+
+#ifndef SGW_LSEG
+#define SGW_LSEG 8    // nodes per segment of the line sweep
+#endif
+#define SGW_LWAVE 64  // segments (lanes) per work item of the line sweep: one wavefront
 
 // Per-solve time-stepping record, written only by the device after set-up.
 struct alignas(64) ReqDev {
@@ -250,12 +263,13 @@ hipError_t launch_restrict_many(const ResetItem* resets, int nresets, const Rest
 hipError_t launch_dt(ReqDev* const* reqs, int nreq, hipStream_t s);
 hipError_t launch_dt_one(ReqDev* req, hipStream_t s);
 // stage kernel of dimension dim over items[0..nitems); grid_cap caps the persistent grid.
-// stage SGW_STAGE_FUSED: the three stages of whole-grid boxes in one launch.
+// stage SGW_STAGE_FUSED: the three stages of whole-grid boxes in one launch.  lines: the
+// items are line-sweep items (4D), one launch per direction.
 hipError_t launch_stage(const WorkItem* items, int nitems, int stage, int precision, int dim, size_t lds_bytes,
-                        int grid_cap, hipStream_t s);
+                        int grid_cap, hipStream_t s, bool lines = false);
 // the same over items[range_dev[0] .. + range_dev[1]) read on the device (batches, graphs)
 hipError_t launch_stage_range(const WorkItem* items, const int* range_dev, int blocks, int stage, int precision,
-                              int dim, size_t lds_bytes, hipStream_t s);
+                              int dim, size_t lds_bytes, hipStream_t s, bool lines = false);
 hipError_t launch_gather_done(ReqDev* const* reqs, int nreq, int* flags, hipStream_t s);
 size_t stage_lds_bytes(const GridDev& g, int precision);
 int stage_occupancy(int precision, int dim, size_t lds_bytes, bool fused = false);

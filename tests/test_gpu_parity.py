@@ -99,6 +99,36 @@ def test_boxes_smaller_than_the_automatic_choice():
     _check_fp64(W.c2_burgers_2d(nl=3, T=0.1), box=[4, 4], fine_tile=[8, 4])
 
 
+def _four_d_cases(prec):
+    """4D workloads with each kind of flux: the Vlasov one (coefficients per line), advection with
+    unequal speeds of both signs (constant coefficients) and Burgers (state-dependent wave speed)."""
+    adv = W.Problem(d=4, lo=(0.0,) * 4, hi=(2.0,) * 4, flux=W.FLUX_ADVECTION, flux_params=(1.0, -0.5, 0.75, 0.25),
+                    ic=W.IC_SINE, ic_params=(0.1, 1.0, math.pi, 0.3), nr=8, nl=2, T=0.05, cfl=0.5,
+                    precision=prec, name="advection_4d")
+    burg = adv.replace(flux=W.FLUX_BURGERS, flux_params=(), ic_params=(0.3, 0.7, math.pi, 0.0), name="burgers_4d")
+    return [W.c4_vlasov_4d(nl=2, T=0.1, precision=prec), adv, burg, adv.replace(nr=5, nl=1, name="advection_4d_nr5")]
+
+
+def test_4d_line_sweep_equals_box_kernel_bitwise():
+    """4D grids march as line sweeps (one launch per direction, no halo, partial sums in a free state
+    copy); manual stage boxes select the box kernel, which stages halo slabs in LDS.  Both give the
+    same bits on every component grid and on the combined solution, FP64 and FP32, and the FP64
+    line sweep matches the oracle."""
+    for prec in (W.PREC_FP64, W.PREC_FP32):
+        for pb in _four_d_cases(prec):
+            _announce(f"4D line sweep vs boxes {pb.name} nr={pb.nr} nl={pb.nl} precision={prec}")
+            s_l, st_l, U_l, t_l, n_l = gpu_solve(pb)
+            s_b, st_b, U_b, t_b, n_b = gpu_solve(pb, box=[4, 4, 4, 2] if pb.nr % 4 == 0 else [5, 5, 5, 5])
+            assert n_l == n_b and t_l == t_b
+            assert np.array_equal(st_l, st_b)
+            assert bool((U_l == U_b).all())
+            if prec == W.PREC_FP64 and pb.name != "advection_4d_nr5":
+                st_o, U_o, stats = oracle_solve(pb)
+                assert n_l == stats["steps"]
+                assert np.max(np.abs(st_l - st_o)) <= TOL64
+                assert np.max(np.abs(U_l.cpu().numpy() - U_o)) <= TOL64
+
+
 def test_paper_sparse_weno_row_on_gpu():
     # Table ex3aweno, sparse grid with WENO prolongation, N_r = 10, N_L = 3 (N_h = 80)
     pb = W.paper_example3a(80, nr=10, nl=3)
