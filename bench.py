@@ -443,9 +443,13 @@ def stage_launch_us(torch, pb, box_target, bpc, reps):
     Returns (microseconds per launch, launches per step, batch info)."""
     from paper_2007_10196_amd.solver import Batch, Solver
     s = Solver(pb, device="cuda:0", box_target=box_target, blocks_per_cu=bpc)
-    # grids that are one stage box take their three stages in one launch; the others one per stage
-    whole = [g["box"] == g["shape"] for g in s.plan.grids]
-    launches = (1 if any(whole) else 0) + (3 if not all(whole) else 0)
+    if all(not any(g["box"]) for g in s.plan.grids):
+        # line sweeps (4D): one launch per direction and RK stage
+        launches = 3 * pb.d
+    else:
+        # grids that are one stage box take their three stages in one launch; the others one per stage
+        whole = [g["box"] == g["shape"] for g in s.plan.grids]
+        launches = (1 if any(whole) else 0) + (3 if not all(whole) else 0)
     batch = Batch(max_solvers=1, precision=pb.precision, hbm_budget=1 << 40, max_items=1 << 20)
     if bpc:
         batch.set_blocks_per_cu(bpc)
@@ -544,14 +548,18 @@ def c4_headline(args, torch):
 
     # ---- the two kernels that take the solve's time, against their rooflines
     st_us, launches, info = stage_launch_us(torch, pb, bt, bpc, args.stage_reps)
-    stage_flops = nodes * flops_per_node_stage(pb.d)
+    # a time step is 3 RK stages of 140 d + 5 flops per node, spread over its launches
+    stage_flops = nodes * 3 * flops_per_node_stage(pb.d) / launches
     stage = kernel_roofline(
-        "stage_kernel<double, 4, false> (one WENO5-LF + TVD-RK3 stage over every box of the solve)", st_us,
+        "line_kernel<double, 4, k> (one direction of one WENO5-LF + TVD-RK3 stage over every grid line of the "
+        "solve; 4 launches per stage)", st_us,
         stage_flops, PEAK_FP64_TFLOPS, measured_traffic("stage_c4_fp64"),
-        {"launches_per_time_step": launches, "boxes_per_launch": info["boxes"], "nodes_per_launch": nodes,
+        {"launches_per_time_step": launches, "work_items_per_launch": info["boxes"], "nodes_per_launch": nodes,
          "flops_per_node_stage": flops_per_node_stage(pb.d),
-         # u read and the stage output written (stage 1), plus u^n read (stages 2, 3): 8/3 words a launch
-         "algorithmic_bytes_per_launch": nodes * 8 * 8 // 3,
+         # a stage reads its input once per direction, writes and reads back the partial sum
+         # between directions (d - 1 times each), writes the output and (stages 2, 3) reads u^n:
+         # 3d - 1/3 words per node over the three stages, spread over the d launches of a stage
+         "algorithmic_bytes_per_launch": nodes * 8 * (3 * pb.d - 1.0 / 3.0) / pb.d,
          "time_per_solve_ms": st_us * launches * r["time_steps"] * 1e-3})
     pro_us = r["parts"]["prolong_combine_ms"] * 1e3
     interps = interpolation_count(s.plan)
