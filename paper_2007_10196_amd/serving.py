@@ -5,8 +5,9 @@ monotonic clock).  The loop admits queued requests in arrival order while a
 batch slot is free and the request's device footprint (state + scratch +
 finest-grid output) fits the HBM budget, so a request that arrives while others
 are on the GPU joins the next time step of the running batch.  Each tick
-advances every admitted solve by a few time steps, one graph launch per step on
-the batch stream.  A finished solve leaves the batch and is prolongated and
+advances every admitted solve by a few time steps (graph launches on the batch
+stream) and reads the completion flags gathered after the previous tick, whose
+copy overlapped this tick's steps.  A finished solve leaves the batch and is prolongated and
 combined on a second stream while the batch keeps stepping; its latency is
 finish - arrival.
 """
@@ -72,6 +73,7 @@ class ServingLoop:
         results: List[Result] = []
         plans: Dict[int, Plan] = {}
         t0 = clock()
+        polling = False  # a poll_begin whose flags have not been read yet
         while pending or queue or active or finishing:
             now = clock() - t0
             while pending and pending[0].arrival_s <= now:
@@ -116,6 +118,10 @@ class ServingLoop:
                     still.append((req, solver, admit_s, fp, ev, U, steps))
             finishing = still
             if not active:
+                if polling:
+                    # nothing left to report: a released slot is never reported
+                    self.batch.poll_end()
+                    polling = False
                 if finishing:
                     time.sleep(0.0002)
                 elif pending:
@@ -126,7 +132,10 @@ class ServingLoop:
             tp = clock()
             self.batch.step(self.steps_per_tick)
             tq = clock()
-            done = self.batch.poll()
+            # the flags gathered after the previous tick travel while this tick's steps run
+            done = self.batch.poll_end() if polling else []
+            self.batch.poll_begin()
+            polling = True
             tr = clock()
             self.stats["step_enqueue"] += tq - tp
             self.stats["poll_wait"] += tr - tq
@@ -144,6 +153,8 @@ class ServingLoop:
                 finishing.append((req, solver, admit_s, fp, ev, U, steps))
             self.stats["finish"] += clock() - tr
             self.stats["ticks"] += 1
+        if polling:
+            self.batch.poll_end()
         return results
 
     def close(self):

@@ -127,3 +127,74 @@ def test_autotuner_picks_and_caches(tmp_path):
     again = tune_box_target(probs, B.FP32_SWEEP, candidates=(256, 1024), cache_path=path, reps=3,
                             blocks_per_cu=(0, 2))
     assert again["cached"] and again["best"] == rec["best"] and again["blocks_per_cu"] == rec["blocks_per_cu"]
+
+
+def test_serving_mix_with_a_4d_level5_request_equals_solo_bitwise():
+    """A short FP32 stream with one 4D Vlasov request at finest level 5 (121 grids, a 256^4 FP64 finest
+    grid of 34.4 GB that admission counts) among 2D/3D/4D requests at levels 2-3, full final times:
+    every served solution equals the same solve run alone, bit for bit."""
+    import torch
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.serving import ServingLoop, latency_summary
+    from paper_2007_10196_amd.solver import Plan, Solver
+    reqs = W.serving_stream(n=6, rate_hz=200.0, seed=31, levels=(2, 3), precision=W.PREC_FP32)
+    big = W.randomized(4, 5, np.random.default_rng(2007_10196 + 999), precision=W.PREC_FP32)
+    reqs.append(W.Request(rid=6, arrival_s=reqs[2].arrival_s, problem=big, family=4))
+    fp_big = Plan(big).footprint
+    assert fp_big >= 256 ** 4 * 8  # the FP64 finest grid is counted
+    loop = ServingLoop(precision=B.FP32_SWEEP, max_active=8, hbm_budget=fp_big + (8 << 30), steps_per_tick=8,
+                       keep_outputs=True)
+    print(f"\n[gpu] serving 7 requests incl. 4D N_L=5 ({fp_big / 1e9:.1f} GB footprint)", flush=True)
+    res = loop.run(reqs)
+    torch.cuda.synchronize()
+    assert sorted(r.rid for r in res) == list(range(7))
+    print("[gpu] serving", latency_summary(res), flush=True)
+    by_id = {r.rid: r for r in reqs}
+    for r in sorted(res, key=lambda x: x.rid):
+        pb = by_id[r.rid].problem
+        solo = Solver(pb).solve(mode=B.RUN_GRAPH)
+        same = bool(torch.equal(r.out, solo))
+        print(f"  request {r.rid} {pb.d}D N_L={pb.nl}: served == alone: {same}", flush=True)
+        assert same, r.rid
+        del solo
+        r.out = None
+        torch.cuda.empty_cache()
+    loop.close()
+
+
+def test_served_stream_at_full_final_time_fp64():
+    """24 seeded requests at their full final times and levels 2-5 (one 4D N_L = 5), FP64, served with
+    admissions while others run: members whose oracle solve is quick (2D, 3D up to N_L = 3, 4D up to
+    N_L = 2) match the FP64 oracle within 1e-11 max-abs; every member equals its solve run alone, bit
+    for bit."""
+    import torch
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.serving import ServingLoop, latency_summary
+    from paper_2007_10196_amd.solver import Solver
+    reqs = W.serving_stream(n=24, rate_hz=50.0, seed=119, precision=W.PREC_FP64)
+    mix = [(r.problem.d, r.problem.nl) for r in reqs]
+    assert (4, 5) in mix and (3, 5) in mix and len({r.family for r in reqs}) == 4
+    loop = ServingLoop(precision=B.FP64, max_active=12, hbm_budget=64 << 30, steps_per_tick=8, keep_outputs=True)
+    print(f"\n[gpu] serving 24 FP64 requests at full T: {sorted(mix)}", flush=True)
+    res = loop.run(reqs)
+    torch.cuda.synchronize()
+    assert sorted(r.rid for r in res) == list(range(24))
+    print("[gpu] serving", latency_summary(res), flush=True)
+    by_id = {r.rid: r for r in reqs}
+    checked = 0
+    for r in sorted(res, key=lambda x: x.rid):
+        pb = by_id[r.rid].problem
+        if pb.d == 2 or (pb.d == 3 and pb.nl <= 3) or (pb.d == 4 and pb.nl <= 2):
+            U, _, stats = O.solve(pb)
+            assert r.steps == stats["steps"]
+            err = float(np.abs(r.out.cpu().numpy() - U).max())
+            print(f"  request {r.rid} {pb.d}D N_L={pb.nl}: max-abs vs oracle {err:.2e}", flush=True)
+            assert err <= 1e-11, (r.rid, err)
+            checked += 1
+        solo = Solver(pb).solve(mode=B.RUN_GRAPH)
+        assert bool(torch.equal(r.out, solo)), r.rid
+        del solo
+        r.out = None
+        torch.cuda.empty_cache()
+    assert checked >= 16
+    loop.close()
