@@ -734,6 +734,141 @@ def c2_batched(args, torch):
             "autotune": {"box_target": box_target, "blocks_per_cu": bpc, "step_stage_us_by_target_and_cap": tune["us"]}}
 
 
+# The paper's own comparison (Sec. 3): CPU seconds of the sparse grid with WENO prolongation and of the
+# single grid at equal finest resolution N_h, with their L1 errors, on a 2.3 GHz workstation.
+PAPER_SWEEPS = {
+    "ex3a_2d_burgers": {"table": "Table ex3aweno", "nl": 3, "n_h": (80, 160, 320, 640),
+                        "cpu_sparse_s": (0.414, 4.976, 61.510, 781.990),
+                        "cpu_single_s": (0.572, 7.156, 92.854, 1149.946),
+                        "l1_sparse": (7.1354e-05, 2.7404e-07, 1.3265e-09, 4.0784e-11),
+                        "l1_single": (1.3362e-06, 4.2306e-08, 1.3119e-09, 4.0883e-11)},
+    "ex3b_3d_burgers": {"table": "Table ex3-baweno", "nl": 3, "n_h": (80, 160, 320, 640),
+                        "cpu_sparse_s": (15.106, 223.450, 4144.632, 96962.960),
+                        "cpu_single_s": (26.706, 691.410, 16868.220, 444972.000),
+                        "l1_sparse": (1.3225e-04, 7.6655e-07, 2.4830e-09, 6.4883e-11),
+                        "l1_single": (2.0866e-06, 6.6687e-08, 2.0836e-09, 6.5107e-11)},
+}
+
+
+def timed_solve(torch, pb, reps=2):
+    """Restriction, march, prolongation + combination of one FP64 solve on one stream, the last of
+    `reps` runs timed with HIP events; L1 / Linf against the exact solution at T."""
+    from paper_2007_10196_amd.solver import Solver
+    s = Solver(pb, device="cuda:0")
+    out = torch.empty(s.plan.fine_nodes, dtype=torch.float64, device="cuda:0")
+    for _ in range(reps):
+        e0, e1 = ev(torch), ev(torch)
+        e0.record(s.stream)
+        s.restrict()
+        s.advance()
+        s.prolongate_combine(out)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+    t, steps = s.query()
+    exact = s.exact(t)
+    l1, linf = s.norms(out, exact)
+    res = {"ms": e0.elapsed_time(e1), "l1": l1, "linf": linf, "time_steps": steps, "nodes": s.plan.total_nodes}
+    del s, out, exact
+    torch.cuda.empty_cache()
+    return res
+
+
+def paper_sweep(torch):
+    """Sparse grid against single grid on the GPU at the paper's N_h (Tables ex3aweno and ex3-baweno
+    settings, FP64, dt = dx^(5/3)), the 4D Vlasov workload at root 10, level 3 (80^4, the resolution
+    of Table tb:ex5bcpu) against its single grid, and the 2D Burgers workload's single grid at the
+    resolution whose L1 matches the sparse grid's (equal error), with FP32 sweeps as in the batched leg."""
+    out = {}
+    for name, spec in PAPER_SWEEPS.items():
+        make = W.paper_example3a if name.startswith("ex3a") else W.paper_example3b
+        rows = []
+        for i, nh in enumerate(spec["n_h"]):
+            sp = timed_solve(torch, make(nh, nl=spec["nl"]))
+            si = timed_solve(torch, make(nh, nl=0))
+            rows.append({"n_h": nh, "sparse_ms": sp["ms"], "single_ms": si["ms"], "gpu_ratio": sp["ms"] / si["ms"],
+                         "l1_sparse": sp["l1"], "l1_single": si["l1"], "time_steps": sp["time_steps"],
+                         "paper_l1_sparse": spec["l1_sparse"][i], "paper_l1_single": spec["l1_single"][i],
+                         "paper_cpu_ratio": spec["cpu_sparse_s"][i] / spec["cpu_single_s"][i],
+                         "nodes_sparse": sp["nodes"], "nodes_single": si["nodes"]})
+            print(f"[bench] {name} N_h {nh}: sparse {sp['ms']:.1f} ms L1 {sp['l1']:.4e}, single {si['ms']:.1f} ms "
+                  f"L1 {si['l1']:.4e}", file=sys.stderr, flush=True)
+        out[name] = {"table": spec["table"], "rows": rows}
+    v4 = []
+    for nl in (3, 0):
+        pb = W.c4_vlasov_4d(nr=10 << (3 - nl), nl=nl, precision=W.PREC_FP64)
+        v4.append(timed_solve(torch, pb, reps=1 if nl == 0 else 2))
+    out["vlasov_4d_80"] = {"setting": "4D Vlasov workload (fixed field, periodic), N_h = 80: sparse root 10, "
+                                      "level 3 against one 80^4 grid, FP64, CFL 0.4, T = 1",
+                           "sparse_ms": v4[0]["ms"], "single_ms": v4[1]["ms"], "gpu_ratio": v4[0]["ms"] / v4[1]["ms"],
+                           "l1_sparse": v4[0]["l1"], "l1_single": v4[1]["l1"],
+                           "nodes_sparse": v4[0]["nodes"], "nodes_single": v4[1]["nodes"],
+                           "paper_cpu_ratio": "0.064-0.070 (Table tb:ex5bcpu: 4D Vlasov-Boltzmann, zero boundary, "
+                                              "t = 0.5 to 3)"}
+    print(f"[bench] 4D N_h 80: sparse {v4[0]['ms']:.1f} ms, single {v4[1]['ms']:.1f} ms", file=sys.stderr, flush=True)
+    # equal error, 2D Burgers workload, 256 solves per step (FP32 sweeps)
+    probs = make_problems(256)
+    sparse = batch_run(torch, probs, 0, 0, steps=2)
+    fulls = []
+    for nh in (32, 48, 64, 96, 128):
+        f = batch_run(torch, [p.replace(nr=nh, nl=0) for p in probs], 0, 0, steps=2)
+        fulls.append({"n_h": nh, "ms_per_step": f["ms_per_step"], "l1_mean": f["l1_mean"]})
+        print(f"[bench] 2D Burgers single {nh}^2: {f['ms_per_step']:.2f} ms/step L1 {f['l1_mean']:.3e}",
+              file=sys.stderr, flush=True)
+    match = next((f for f in fulls if f["l1_mean"] <= sparse["l1_mean"]), None)
+    out["equal_error_2d_burgers"] = {
+        "sparse": {"n_h": 256, "ms_per_step": sparse["ms_per_step"], "l1_mean": sparse["l1_mean"]},
+        "single_grids": fulls, "single_at_equal_error": match,
+        "sparse_over_single_time_at_equal_error": sparse["ms_per_step"] / match["ms_per_step"] if match else None}
+    return out
+
+
+def large_roofline(torch, reps=10):
+    """Stage launches of one time step on the scaled cases whose state exceeds the 256 MB MALL: 3D
+    advection at root 32 (32.5 M nodes, box kernel) and the 4D Vlasov workload at root 16 (50.3 M
+    nodes, line sweep), FP64 and FP32, event-timed through the batch measurement hook."""
+    from paper_2007_10196_amd.solver import Batch, Solver
+    out = []
+    for name, make in (("c3_large", lambda p: W.c3_advection_3d(nr=32, precision=p)),
+                       ("c4_large", lambda p: W.c4_vlasov_4d(nr=16, precision=p))):
+        for prec in (W.PREC_FP64, W.PREC_FP32):
+            pb = make(prec)
+            s = Solver(pb, device="cuda:0")
+            batch = Batch(max_solvers=1, precision=prec, hbm_budget=1 << 40, max_items=1 << 24)
+            s.restrict()
+            slot = batch.admit(s)
+            batch.step(1)
+            st = batch.stream
+            e0, e1 = ev(torch), ev(torch)
+            batch.launch_stage(3, 2)
+            e0.record(st)
+            batch.launch_stage(3, reps)
+            e1.record(st)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) / reps * 1e3
+            nodes = s.plan.total_nodes
+            esz = 8 if prec == W.PREC_FP64 else 4
+            flops = nodes * flops_per_cell_update(pb.d)
+            # fused 3-stage minimum: stage 1 reads u and writes u1, stages 2 and 3 also read u^n (8 words);
+            # the 4D line sweep also moves its partial sums: 3 (3d - 1/3) words per step
+            words = 8.0 if pb.d == 3 else 3 * (3 * pb.d - 1.0 / 3.0)
+            peak = PEAK_FP64_TFLOPS if prec == W.PREC_FP64 else PEAK_FP32_TFLOPS
+            row = {"case": name, "precision": "fp64" if prec == W.PREC_FP64 else "fp32", "nodes": nodes,
+                   "state_MB": 3 * nodes * esz / 1e6, "step_stage_us": us,
+                   "cell_updates_per_s": nodes / (us * 1e-6), "tflops": flops / (us * 1e-6) / 1e12,
+                   "valu_frac_of_peak": flops / (us * 1e-6) / 1e12 / peak,
+                   "algorithmic_bytes_per_cell_update": words * esz,
+                   "algorithmic_GBs": nodes * words * esz / (us * 1e-6) / 1e9,
+                   "algorithmic_hbm_frac": nodes * words * esz / (us * 1e-6) / 1e9 / PEAK_HBM_GBS}
+            out.append(row)
+            print(f"[bench] {name} {row['precision']}: {us:.1f} us per step, {row['algorithmic_GBs']:.0f} GB/s "
+                  f"algorithmic, {row['tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
+            batch.release(slot)
+            batch.close()
+            del s
+            torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -761,6 +896,10 @@ def main():
     ap.add_argument("--path-workload", choices=("c3", "c4"),
                     help="only run one 3D (c3) or 4D (c4) solve through the path, each part timed")
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32", help="with --path-workload")
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="only run sparse against single grid at the paper's resolutions (and equal error)")
+    ap.add_argument("--large-roofline", action="store_true",
+                    help="only time the stage launches of the scaled 3D/4D cases that exceed the MALL")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -773,6 +912,12 @@ def main():
         return
     if args.path_workload:
         path_workload(args.path_workload, args.precision, args.box_target, args.blocks_per_cu, args.stage_reps)
+        return
+    if args.paper_sweep or args.large_roofline:
+        import torch
+        torch.cuda.set_device(0)
+        res = {"paper_sweep": paper_sweep(torch)} if args.paper_sweep else {"large_roofline": large_roofline(torch)}
+        print(json.dumps(res), flush=True)
         return
 
     import torch

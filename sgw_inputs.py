@@ -195,3 +195,9 @@ def serving_stream(n: int = 512, rate_hz: float = 100.0, seed: int = 2007_10196,
         out.append(Request(rid=i, arrival_s=t, problem=randomized(fam, nl, r, precision), family=fam))
     return out
 
+
+
+def component_noise(total_nodes: int, seed: int = 2007_10196) -> np.ndarray:
+    """Seeded uniform values in [0, 1) for every component-grid node (grids back to back in plan
+    order): caller-set data that stresses the nonlinear interpolation weights."""
+    return np.random.default_rng(seed).random(total_nodes)

@@ -214,6 +214,42 @@ def test_full_size_sampled(name, make):
     assert np.max(np.abs(ex - np.array(gd["fine_exact"]))) < 1e-13
 
 
+@pytest.mark.parametrize("name,make", [("c3", lambda: W.c3_advection_3d(precision=0)),
+                                       ("c4", lambda: W.c4_vlasov_4d(precision=0))])
+def test_full_size_prolongation_whole_tiles(name, make):
+    """The prolongation and combination at full size, in the finest-grid tile shape the planner picks
+    for the bench: every component grid holds seeded noise (set through sgw_set_grid), and whole
+    tiles of the output -- the corner tile (periodic wrap in every direction), the far-corner tile
+    and two interior ones, their corners and edges included -- match the oracle's pointwise
+    prolongation of the same values within 1e-11."""
+    torch, B, Solver, _ = _lib()
+    pb = make()
+    s = Solver(pb)
+    noise = W.component_noise(s.plan.total_nodes, seed=2007_10196 + 17)
+    dev = torch.from_numpy(noise).cuda()
+    for g, info in enumerate(s.plan.grids):
+        n = int(np.prod(info["shape"]))
+        s.set_grid(g, dev[info["offset"]: info["offset"] + n].clone())
+    U = s.prolongate_combine()
+    torch.cuda.synchronize()
+    T = s.plan.fine_tile
+    N = pb.n_fine
+    ntile = [N // t for t in T]
+    rng = np.random.default_rng(2007_10196 + 18)
+    picks = [[0] * pb.d, [n - 1 for n in ntile], [int(rng.integers(1, n - 1)) for n in ntile],
+             [int(rng.integers(1, n - 1)) for n in ntile]]
+    local = np.stack(np.meshgrid(*[np.arange(t) for t in T], indexing="ij"), -1).reshape(-1, pb.d)
+    for tile in picks:
+        J = (local + np.array(tile) * np.array(T)).astype(np.int32)
+        _announce(f"full {name} tile {tile} of shape {T}: {len(J)} nodes")
+        flat = torch.from_numpy(sum(J[:, k].astype(np.int64) * N ** k for k in range(pb.d))).cuda()
+        got = U[flat].cpu().numpy()
+        ref = O.prolong_combine_points(pb, noise, J)
+        err = float(np.max(np.abs(got - ref)))
+        print(f"  max-abs {err:.2e}", flush=True)
+        assert err <= TOL64, (tile, err)
+
+
 @pytest.mark.parametrize("name,make", [("c3", lambda: W.c3_advection_3d(precision=1)),
                                        ("c4", lambda: W.c4_vlasov_4d(precision=1))])
 def test_full_size_fp32_against_fp64_oracle_samples(name, make):
