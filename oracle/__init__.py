@@ -22,7 +22,8 @@ _lib = None
 class _Problem(C.Structure):
     _fields_ = [("d", C.c_int32), ("flux", C.c_int32), ("ic", C.c_int32), ("pad_", C.c_int32),
                 ("lo", C.c_double * 4), ("hi", C.c_double * 4), ("fp", C.c_double * 4),
-                ("ip", C.c_double * 8)]
+                ("ip", C.c_double * 8), ("bc", C.c_int32 * 4), ("relax_tau", C.c_double),
+                ("relax_theta", C.c_double)]
 
 
 class _Config(C.Structure):
@@ -72,6 +73,8 @@ def lib():
         L.orc_exact_fine.argtypes = [C.POINTER(_Problem), C.POINTER(_Config), C.c_double, _dp]
         L.orc_norms.argtypes = [_dp, _dp, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_max_threads.restype = C.c_int
+        L.orc_entropies.argtypes = [C.POINTER(_Problem), C.POINTER(_Config), _dp, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -90,6 +93,9 @@ def _structs(pb, nthreads: int = 0):
     p.hi[:] = _pad(pb.hi, 4)
     p.fp[:] = _pad(pb.flux_params, 4)
     p.ip[:] = _pad(pb.ic_params, 8)
+    p.bc[:] = [int(b) for b in _pad(getattr(pb, "bc", ()) or (), 4, 0)]
+    p.relax_tau = float(getattr(pb, "relax_tau", 0.0))
+    p.relax_theta = float(getattr(pb, "relax_theta", 1.0))
     c = _Config()
     c.nr = pb.nr
     c.nl = pb.nl
@@ -229,6 +235,16 @@ def norms(a: np.ndarray, b: np.ndarray) -> Tuple[float, float]:
     l1, li = C.c_double(), C.c_double()
     lib().orc_norms(a, b, a.size, C.byref(l1), C.byref(li))
     return l1.value, li.value
+
+
+def entropies(pb, fine: np.ndarray) -> Tuple[float, float]:
+    """(H_2, H_log) of a finest-grid solution relative to the stationary state (Sec. 3.4, Example 5)."""
+    p, c = _structs(pb)
+    fine = np.ascontiguousarray(fine, dtype=np.float64).ravel()
+    assert fine.size == pb.n_fine ** pb.d
+    h2, hl = C.c_double(), C.c_double()
+    lib().orc_entropies(C.byref(p), C.byref(c), fine, C.byref(h2), C.byref(hl))
+    return h2.value, hl.value
 
 
 def max_threads() -> int:

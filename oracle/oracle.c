@@ -22,6 +22,12 @@
  *   - Sec. 2.2.1, eqs. (lwlag), (eqnlnwe), (si), (nlweno) : WENO5 interpolation with
  *                                    the positive linear weights C_k(x)
  *   - Sec. 2.2.2 and eq. (genformusgc) : the algorithm summary and the combination formula
+ *   - Sec. 3.4, Example 5          : the Vlasov-Boltzmann transport equation: the field
+ *                                    E = -grad Phi with Phi = |x|^2/2, the linear relaxation
+ *                                    operator (mu_inf(v) rho(t,x) - f)/tau with the absolute
+ *                                    Maxwellian mu_inf and the density rho = int f dv, zero
+ *                                    boundary conditions, and the entropy functionals H_2, H_log
+ *                                    relative to the stationary state M(x, v)
  *
  * Readings of points the paper leaves open (all of them listed in the design
  * notes of the repository):
@@ -38,7 +44,14 @@
  *   - fine node J refines to coarse node i = floor(J/R + 1/2), offset s = J/R - i,
  *     s in [-1/2, 1/2) (the half-open interval of Sec. 2.2.1);
  *   - prolongation runs over the directions in increasing order;
- *   - L1 error = mean absolute error over the finest nodes, Linf = maximum.
+ *   - L1 error = mean absolute error over the finest nodes, Linf = maximum;
+ *   - zero boundary condition: the same nodes lo + j h, j = 0..n-1, with every value beyond
+ *     either end taken as 0 (the WENO stencils of the sweep and of the prolongation read zeros
+ *     there; the node at hi is one of them);
+ *   - the density rho(x) = int f dv is the sum over the velocity nodes of the grid times the
+ *     velocity cell volume; the relaxation source is added to the spatial operator of every
+ *     Runge-Kutta stage, with rho taken from the stage input;
+ *   - the entropy H log H is taken as 0 where f <= 0.
  *
  * Compiled with -O2 -ffp-contract=off (no fused multiply-add, no fast math).
  */
@@ -52,10 +65,12 @@
 
 #define ORC_MAXD 4
 
-/* flux families of eq. (1) used by the examples of Sec. 3 */
-enum { ORC_FLUX_ADVECTION = 0, ORC_FLUX_BURGERS = 1, ORC_FLUX_VLASOV = 2 };
+/* flux families of eq. (1) used by the examples of Sec. 3; VLASOV_HARMONIC is the transport of
+   Example 5 with E = -x */
+enum { ORC_FLUX_ADVECTION = 0, ORC_FLUX_BURGERS = 1, ORC_FLUX_VLASOV = 2, ORC_FLUX_VLASOV_HARMONIC = 3 };
 /* initial conditions */
-enum { ORC_IC_SINE = 0, ORC_IC_MAXWELL_COS = 1 };
+enum { ORC_IC_SINE = 0, ORC_IC_MAXWELL_COS = 1, ORC_IC_VB = 2 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_ZERO = 1 };
 enum { ORC_DT_CFL = 0, ORC_DT_POW53 = 1 };
 enum { ORC_PROLONG_WENO5 = 0, ORC_PROLONG_LAGRANGE5 = 1 };
 
@@ -70,8 +85,15 @@ typedef struct {
        fp[1] = field wavenumber; directions 0..d/2-1 are x, d/2..d-1 are v. */
     double fp[ORC_MAXD];
     /* sine:        u0 = ip[0] + ip[1] * sin(ip[2] * sum_k x_k + ip[3])
-       maxwell_cos: f0 = M(v) * (1 + ip[0] * prod_k cos(ip[1] * x_k + ip[2+k])) */
+       maxwell_cos: f0 = M(v) * (1 + ip[0] * prod_k cos(ip[1] * x_k + ip[2+k]))
+       vb:          f0 = ip[0] * sin(x_1^2/2)^2 [* cos(x_2^2/2)^2] * exp(-(|x|^2 + |v|^2)/2),
+                    ip[0] = 1/s, the normalisation of Example 5 */
     double ip[8];
+    int32_t bc[ORC_MAXD];   /* ORC_BC_* per direction */
+    /* relaxation source (mu_inf(v) rho(x) - f) / tau of Example 5, off when tau <= 0; the first
+       d/2 directions are x, the others v; theta is the kinetic temperature of mu_inf */
+    double relax_tau;
+    double relax_theta;
 } orc_problem;
 
 typedef struct {
@@ -229,6 +251,7 @@ static void orc_flux(const orc_problem *p, int k, double u, const double *x, dou
         int dx = p->d / 2;
         double c;
         if (k < dx) c = x[dx + k];
+        else if (p->flux == ORC_FLUX_VLASOV_HARMONIC) c = -x[k - dx]; /* E = -grad |x|^2/2 */
         else c = p->fp[0] * sin(p->fp[1] * x[k - dx]);
         *f = c * u;
         *fp = c;
@@ -244,8 +267,18 @@ static double orc_u0(const orc_problem *p, const double *x)
         for (int k = 0; k < p->d; k++) s += x[k];
         return p->ip[0] + p->ip[1] * sin(p->ip[2] * s + p->ip[3]);
     }
-    /* Maxwellian in v times a cosine perturbation in x */
     int dx = p->d / 2;
+    if (p->ic == ORC_IC_VB) {
+        /* Example 5: sin(x_1^2/2)^2 (and cos(x_2^2/2)^2 in 4D) times a Gaussian in (x, v) */
+        double shape = 1.0, r2 = 0.0;
+        for (int k = 0; k < dx; k++) {
+            double q = (k == 0) ? sin(0.5 * x[k] * x[k]) : cos(0.5 * x[k] * x[k]);
+            shape *= q * q;
+        }
+        for (int k = 0; k < p->d; k++) r2 += x[k] * x[k];
+        return p->ip[0] * shape * exp(-0.5 * r2);
+    }
+    /* Maxwellian in v times a cosine perturbation in x */
     double v2 = 0.0, pert = 1.0;
     for (int k = 0; k < dx; k++) {
         v2 += x[dx + k] * x[dx + k];
@@ -318,6 +351,53 @@ static double orc_alpha(const orc_problem *p, const orc_grid *g, const double *u
     return a;
 }
 
+/* a[j] of a line of n values, j in -3..n+2: wrapped, or 0 beyond the ends (zero boundary) */
+static double orc_ghost(const double *a, int j, int n, int zero)
+{
+    if (j >= 0 && j < n) return a[j];
+    if (zero) return 0.0;
+    return a[((j % n) + n) % n];
+}
+
+/* The absolute Maxwellian of Example 5, mu_inf(v) = exp(-|v|^2/(2 theta)) / (2 pi theta)^(m/2),
+   m = d/2 velocity directions. */
+static double orc_mu_inf(const orc_problem *p, const double *x)
+{
+    int dx = p->d / 2;
+    double v2 = 0.0;
+    for (int k = dx; k < p->d; k++) v2 += x[k] * x[k];
+    return exp(-v2 / (2.0 * p->relax_theta)) / pow(2.0 * M_PI * p->relax_theta, 0.5 * dx);
+}
+
+/* L += (mu_inf(v) rho(x) - u) / tau, the linear relaxation operator of Example 5, with
+   rho(x) = int u dv as the sum over this grid's velocity nodes times their cell volume. */
+static void orc_relax_add(const orc_problem *p, const orc_grid *g, const double *u, double *L)
+{
+    int dx = p->d / 2;
+    int64_t nx = 1, nv = 1;
+    double hv = 1.0;
+    for (int k = 0; k < dx; k++) nx *= g->n[k];
+    for (int k = dx; k < p->d; k++) {
+        nv *= g->n[k];
+        hv *= g->h[k];
+    }
+    /* direction 1 is fastest, so node (x, v) sits at ix + nx * iv */
+    double *rho = malloc(sizeof(double) * nx);
+    for (int64_t ix = 0; ix < nx; ix++) {
+        double s = 0.0;
+        for (int64_t iv = 0; iv < nv; iv++) s += u[ix + nx * iv];
+        rho[ix] = s * hv;
+    }
+    for (int64_t idx = 0; idx < g->size; idx++) {
+        int j[ORC_MAXD];
+        double x[ORC_MAXD] = {0, 0, 0, 0};
+        orc_index_to_coords(g, idx, j);
+        for (int k = 0; k < p->d; k++) x[k] = orc_coord(p, k, j[k], g->n[k]);
+        L[idx] += (orc_mu_inf(p, x) * rho[idx % nx] - u[idx]) / p->relax_tau;
+    }
+    free(rho);
+}
+
 /* Spatial operator L(u) = -sum_k (F_{i+1/2} - F_{i-1/2}) / h_k, eq. (2.9), with the
    LF-split WENO5 fluxes F = F^+ + F^- of Sec. 2.1. */
 static void orc_rhs_grid(const orc_problem *p, const orc_config *c, const orc_grid *g,
@@ -329,7 +409,7 @@ static void orc_rhs_grid(const orc_problem *p, const orc_config *c, const orc_gr
         if (g->n[k] > nmax) nmax = g->n[k];
     double *pl = malloc(sizeof(double) * nmax);
     double *mi = malloc(sizeof(double) * nmax);
-    double *F = malloc(sizeof(double) * nmax);
+    double *F = malloc(sizeof(double) * (nmax + 1));
     for (int k = 0; k < g->d; k++) {
         int n = g->n[k];
         int64_t st = g->stride[k];
@@ -349,24 +429,25 @@ static void orc_rhs_grid(const orc_problem *p, const orc_config *c, const orc_gr
                 pl[i] = 0.5 * (f + alpha * u[idx]); /* f^+ */
                 mi[i] = 0.5 * (f - alpha * u[idx]); /* f^- */
             }
-            /* F[i] is the numerical flux at x_{i+1/2}; periodic indices */
-            for (int i = 0; i < n; i++) {
-#define W(j) (((j) % n + n) % n)
-                double fplus = orc_weno5(pl[W(i - 2)], pl[W(i - 1)], pl[W(i)], pl[W(i + 1)], pl[W(i + 2)],
-                                         c->eps_flux, c->linear);
-                double fminus = orc_weno5(mi[W(i + 3)], mi[W(i + 2)], mi[W(i + 1)], mi[W(i)], mi[W(i - 1)],
-                                          c->eps_flux, c->linear);
-                F[i] = fplus + fminus;
+            /* F[i + 1] is the numerical flux at x_{i+1/2}, i = -1..n-1; values beyond the ends
+               wrap (periodic) or are 0 (zero boundary) */
+            int zero = p->bc[k] == ORC_BC_ZERO;
+            for (int i = -1; i < n; i++) {
+#define PL(j) orc_ghost(pl, (j), n, zero)
+#define MI(j) orc_ghost(mi, (j), n, zero)
+                double fplus = orc_weno5(PL(i - 2), PL(i - 1), PL(i), PL(i + 1), PL(i + 2), c->eps_flux, c->linear);
+                double fminus = orc_weno5(MI(i + 3), MI(i + 2), MI(i + 1), MI(i), MI(i - 1), c->eps_flux, c->linear);
+#undef PL
+#undef MI
+                F[i + 1] = fplus + fminus;
             }
-            for (int i = 0; i < n; i++) {
-                L[base + i * st] -= (F[i] - F[W(i - 1)]) / g->h[k];
-#undef W
-            }
+            for (int i = 0; i < n; i++) L[base + i * st] -= (F[i + 1] - F[i]) / g->h[k];
         }
     }
     free(pl);
     free(mi);
     free(F);
+    if (p->relax_tau > 0.0) orc_relax_add(p, g, u, L);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -404,7 +485,8 @@ double orc_interp(const double *u, double s, double eps, int lagrange)
 }
 
 /* Refine direction k of an array of shape n[] from n[k] to n[k] * R nodes. */
-static void orc_refine_dim(const int *n, int k, int R, const double *src, double *dst, double eps, int lagrange)
+static void orc_refine_dim(const int *n, int k, int R, const double *src, double *dst, double eps, int lagrange,
+                           int zero)
 {
     int64_t inner = 1, outer = 1;
     for (int kk = 0; kk < k; kk++) inner *= n[kk];
@@ -418,7 +500,12 @@ static void orc_refine_dim(const int *n, int k, int R, const double *src, double
                 double s = (double)(J - i * R) / R;          /* in [-1/2, 1/2) */
                 double st[5];
                 for (int m = 0; m < 5; m++) {
-                    int64_t ii = ((i + m - 2) % nc + nc) % nc;
+                    int64_t ii = i + m - 2;
+                    if (zero && (ii < 0 || ii >= nc)) {
+                        st[m] = 0.0; /* zero boundary: values beyond either end are 0 */
+                        continue;
+                    }
+                    ii = (ii % nc + nc) % nc;
                     st[m] = src[(o * nc + ii) * inner + a];
                 }
                 dst[(o * nf + J) * inner + a] = orc_interp(st, s, eps, lagrange);
@@ -593,7 +680,8 @@ void orc_prolong(const orc_problem *p, const orc_config *c, const int *level, co
     for (int k = 0; k < p->d; k++) {
         int m = c->nl - level[k];
         if (m == 0) continue;
-        orc_refine_dim(n, k, 1 << m, a, b, c->eps_interp, c->prolong == ORC_PROLONG_LAGRANGE5);
+        orc_refine_dim(n, k, 1 << m, a, b, c->eps_interp, c->prolong == ORC_PROLONG_LAGRANGE5,
+                       p->bc[k] == ORC_BC_ZERO);
         n[k] = nfin;
         double *t = a;
         a = b;
@@ -625,8 +713,8 @@ void orc_prolong_combine(const orc_problem *p, const orc_config *c, const double
 
 /* The same value at one fine node J[] only: the dimension-by-dimension
    prolongation restricted to the coarse lines that fine node depends on. */
-static double orc_prolong_point_grid(const orc_config *c, const orc_grid *g, const int *level, const double *u,
-                                     const int *J, int d)
+static double orc_prolong_point_grid(const orc_problem *p, const orc_config *c, const orc_grid *g,
+                                     const int *level, const double *u, const int *J, int d)
 {
     /* per direction: either a copy (m = 0) or a 5-point stencil with offset s */
     int64_t ci[ORC_MAXD][5];
@@ -643,7 +731,11 @@ static double orc_prolong_point_grid(const orc_config *c, const orc_grid *g, con
             int64_t R = (int64_t)1 << m;
             int64_t i = (2 * (int64_t)J[k] + R) / (2 * R);
             s[k] = (double)(J[k] - i * R) / R;
-            for (int q = 0; q < 5; q++) ci[k][q] = ((i + q - 2) % nc + nc) % nc;
+            for (int q = 0; q < 5; q++) {
+                int64_t ii = i + q - 2;
+                /* -1 marks a value beyond the end of a zero-boundary direction */
+                ci[k][q] = (p->bc[k] == ORC_BC_ZERO && (ii < 0 || ii >= nc)) ? -1 : (ii % nc + nc) % nc;
+            }
             npts[k] = 5;
         }
     }
@@ -654,12 +746,14 @@ static double orc_prolong_point_grid(const orc_config *c, const orc_grid *g, con
     for (int e = 0; e < tot; e++) {
         int r = e;
         int64_t idx = 0;
+        int outside = 0;
         for (int k = 0; k < d; k++) {
             int q = r % npts[k];
             r /= npts[k];
+            if (ci[k][q] < 0) outside = 1;
             idx += ci[k][q] * g->stride[k];
         }
-        vals[e] = u[idx];
+        vals[e] = outside ? 0.0 : u[idx];
     }
     int cur = tot;
     for (int k = 0; k < d; k++) {
@@ -686,7 +780,7 @@ void orc_prolong_combine_points(const orc_problem *p, const orc_config *c, const
     for (int64_t q = 0; q < npts; q++) {
         double acc = 0.0;
         for (int g = 0; g < s.G; g++)
-            acc += s.coefs[g] * orc_prolong_point_grid(c, &s.grids[g], s.levels + g * ORC_MAXD,
+            acc += s.coefs[g] * orc_prolong_point_grid(p, c, &s.grids[g], s.levels + g * ORC_MAXD,
                                                        state + s.offsets[g], J + q * ORC_MAXD, p->d);
         out[q] = acc;
     }
@@ -745,6 +839,8 @@ double orc_exact(const orc_problem *p, const double *x, double t)
         return orc_u0(p, y);
     case ORC_FLUX_BURGERS:
         return orc_burgers_exact(p, x, t);
+    case ORC_FLUX_VLASOV_HARMONIC:
+        return NAN; /* Example 5 has no closed-form solution */
     default: {
         int dx = p->d / 2;
         for (int k = 0; k < p->d; k++) y[k] = x[k];
@@ -783,6 +879,42 @@ void orc_norms(const double *a, const double *b, int64_t n, double *l1, double *
     }
     *l1 = n ? s / n : 0.0;
     *linf = m;
+}
+
+/* Entropy functionals of Example 5 on the finest grid (N = N_r 2^N_L nodes per direction):
+   H_2 = int H^2 M and H_log = int H log(H) M over the domain, H = f / M, with the stationary
+   state M(x, v) = exp(-(|v|^2/2 + |x|^2/2)/theta) / ((2 pi theta)^(m/2) int_x exp(-|x|^2/(2 theta)) dx),
+   every integral a sum over the nodes times the cell volume. */
+void orc_entropies(const orc_problem *p, const orc_config *c, const double *f, double *h2, double *hlog)
+{
+    int nfin = c->nr << c->nl;
+    int dx = p->d / 2;
+    double th = p->relax_theta;
+    /* int_x exp(-|x|^2/(2 theta)) dx over the x domain, a product of one-dimensional integrals */
+    double zx = 1.0, cell = 1.0;
+    for (int k = 0; k < dx; k++) {
+        double a = p->lo[k], b = p->hi[k];
+        zx *= sqrt(0.5 * M_PI * th) * 2.0 * 0.5 * (erf(b / sqrt(2.0 * th)) - erf(a / sqrt(2.0 * th)));
+    }
+    for (int k = 0; k < p->d; k++) cell *= (p->hi[k] - p->lo[k]) / nfin;
+    int64_t ftot = 1;
+    for (int k = 0; k < p->d; k++) ftot *= nfin;
+    double s2 = 0.0, sl = 0.0;
+    for (int64_t idx = 0; idx < ftot; idx++) {
+        int64_t r = idx;
+        double r2 = 0.0;
+        for (int k = 0; k < p->d; k++) {
+            double x = orc_coord(p, k, (int)(r % nfin), nfin);
+            r /= nfin;
+            r2 += x * x;
+        }
+        double M = exp(-0.5 * r2 / th) / (pow(2.0 * M_PI * th, 0.5 * dx) * zx);
+        double H = f[idx] / M;
+        s2 += H * H * M;
+        if (H > 0.0) sl += H * log(H) * M;
+    }
+    *h2 = s2 * cell;
+    *hlog = sl * cell;
 }
 
 int orc_max_threads(void)

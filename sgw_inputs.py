@@ -29,9 +29,11 @@ import numpy as np
 FLUX_ADVECTION = 0
 FLUX_BURGERS = 1
 FLUX_VLASOV = 2
+FLUX_VLASOV_HARMONIC = 3
 
 IC_SINE = 0
 IC_MAXWELL_COS = 1
+IC_VB = 2
 
 DT_CFL = 0
 DT_POW53 = 1
@@ -69,8 +71,12 @@ class Problem:
     eps_flux: float = 1e-3
     eps_interp: float = 1e-3
     name: str = ""
-    # boundary condition per direction: 0 periodic (every workload here), 1 zero ghost values
+    # boundary condition per direction: 0 periodic, 1 zero values beyond both ends
     bc: Tuple[int, ...] = ()
+    # relaxation source (mu_inf(v) rho(x) - f) / tau of the Vlasov-Boltzmann model (off at tau 0)
+    # and the kinetic temperature theta of mu_inf
+    relax_tau: float = 0.0
+    relax_theta: float = 1.0
 
     def replace(self, **kw) -> "Problem":
         return dataclasses.replace(self, **kw)
@@ -141,6 +147,37 @@ def paper_example3b(n_h: int, nr: Optional[int] = None, nl: int = 0, linear: boo
     return Problem(d=3, lo=(0.0,) * 3, hi=(two_pi,) * 3, flux=FLUX_BURGERS, flux_params=(),
                    ic=IC_SINE, ic_params=(1.0, 0.5, 1.0, 0.0), nr=nr, nl=nl, T=0.1, dt_mode=DT_POW53,
                    linear=linear, prolong=prolong, name="paper_example3b")
+
+
+def _simpson(f, a: float, b: float, n: int = 1 << 20) -> float:
+    x = np.linspace(a, b, n + 1)
+    w = np.ones(n + 1)
+    w[1:-1:2] = 4.0
+    w[2:-1:2] = 2.0
+    return float((b - a) / (3.0 * n) * np.dot(w, f(x)))
+
+
+def vb_normalisation(d: int, lo: float = -5.0, hi: float = 5.0) -> float:
+    """The constant s of the Vlasov-Boltzmann initial condition: the integral over the domain of
+    sin(x_1^2/2)^2 [cos(x_2^2/2)^2] exp(-(|x|^2+|v|^2)/2), a product of one-dimensional integrals
+    taken by composite Simpson on 2^20 intervals."""
+    ix1 = _simpson(lambda x: np.sin(0.5 * x * x) ** 2 * np.exp(-0.5 * x * x), lo, hi)
+    ix2 = _simpson(lambda x: np.cos(0.5 * x * x) ** 2 * np.exp(-0.5 * x * x), lo, hi)
+    iv = math.sqrt(2.0 * math.pi) * math.erf(hi / math.sqrt(2.0))
+    return ix1 * iv if d == 2 else ix1 * ix2 * iv * iv
+
+
+def paper_example5(d: int = 2, nr: Optional[int] = None, nl: int = 3, T: float = 0.5,
+                   precision: int = PREC_FP64) -> Problem:
+    """Example 5 of Sec. 3.4, the Vlasov-Boltzmann transport equation with E = -x and the linear
+    relaxation source, theta = tau = 1, on [-5,5]^d with zero boundary values, CFL 0.4:
+    (a) d = 2 on a 40^2 root grid, (b) d = 4 on a 10^4 root grid, finest level 3."""
+    if nr is None:
+        nr = 40 if d == 2 else 10
+    return Problem(d=d, lo=(-5.0,) * d, hi=(5.0,) * d, flux=FLUX_VLASOV_HARMONIC, flux_params=(),
+                   ic=IC_VB, ic_params=(1.0 / vb_normalisation(d),), nr=nr, nl=nl, T=T, cfl=0.4,
+                   precision=precision, bc=(BC_ZERO,) * d, relax_tau=1.0, relax_theta=1.0,
+                   name=f"paper_example5_{d}d")
 
 
 FAMILIES = {
