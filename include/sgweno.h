@@ -27,7 +27,8 @@
  *   - Arrays on component grids and on the finest grid are row-major with
  *     direction 1 fastest: index = j_1 + n_1 (j_2 + n_2 (j_3 + n_3 j_4)).
  *     Node j of direction k sits at x = lo_k + j h_k, h_k = (hi_k - lo_k)/n_k,
- *     periodic (node n_k is node 0; sgw_problem.bc).
+ *     j = 0..n_k-1; beyond either end the values wrap (periodic) or are 0
+ *     (sgw_problem.bc).
  *   - Measurement hooks that are not part of the method (stage-launch timing,
  *     VALU issue-rate calibration) are declared in sgweno_measure.h.
  */
@@ -57,10 +58,14 @@ typedef int32_t sgw_status;
 #define SGW_FLUX_VLASOV_FIXED_E 2  /* dim = 2 m: directions 1..m are x, m+1..2m are v;
                                       f_{x_k} = v_k u, f_{v_k} = E_k(x_k) u with
                                       E_k = flux_params[0] sin(flux_params[1] x_k)                     */
+#define SGW_FLUX_VLASOV_HARMONIC 3 /* the same transport with E = -grad |x|^2/2 = -x, the field of the
+                                      Vlasov-Boltzmann model (Sec. 3.4, Example 5)                      */
 
 /* Initial conditions */
 #define SGW_IC_SINE 0              /* u0 = p0 + p1 sin(p2 sum_k x_k + p3)                               */
 #define SGW_IC_MAXWELL_COS 1       /* f0 = exp(-|v|^2/2) / (2 pi)^(m/2) (1 + p0 prod_k cos(p1 x_k + p_{2+k})) */
+#define SGW_IC_VLASOV_BOLTZMANN 2  /* f0 = p0 sin(x_1^2/2)^2 [cos(x_2^2/2)^2] exp(-(|x|^2 + |v|^2)/2), m = 1
+                                      [m = 2]; p0 = 1/s normalises the integral (Sec. 3.4, Example 5)   */
 
 #define SGW_DT_CFL 0               /* dt = cfl / sum_k (A_k / h_k^fine), A_k = max wave speed (Sec. 3) */
 #define SGW_DT_POW53 1             /* dt = (min_k h_k^fine)^(5/3), the accuracy-test rule of Sec. 3     */
@@ -77,12 +82,13 @@ typedef int32_t sgw_status;
                                    /* one stage box take all three stages in one launch                 */
 #define SGW_RUN_GRAPH 2            /* SGW_RUN_FUSED with each time step captured in a HIP graph         */
 
-/* Boundary condition per direction (the examples of Sec. 3 are periodic; the
- * phase-space examples of Sec. 3.4 set the ghost values outside the velocity
- * domain to zero).  SGW_BC_ZERO is reserved: plans that ask for it are refused
- * with SGW_ERR_UNSUPPORTED. */
+/* Boundary condition per direction (the examples of Secs. 3.1-3.3 are periodic;
+ * the Vlasov-Boltzmann model of Sec. 3.4, Example 5, prescribes zero boundary
+ * values).  Plans with a zero boundary run the stage as line sweeps in every
+ * dimension; the prolongation reads 0 beyond the ends as well. */
 #define SGW_BC_PERIODIC 0          /* node n_k is node 0                                              */
-#define SGW_BC_ZERO 1              /* the three ghost values beyond either end are 0 (reserved)       */
+#define SGW_BC_ZERO 1              /* every value beyond either end (the stencils' ghosts) is 0;
+                                      the node at hi_k is one of them                                 */
 
 typedef struct sgw_problem {
     int32_t dim;                   /* 1..4                                                   */
@@ -94,6 +100,14 @@ typedef struct sgw_problem {
     double hi[SGW_MAX_DIM];
     double flux_params[SGW_MAX_DIM];
     double ic_params[8];
+    /* Linear relaxation source L(f) = (mu_inf(v) rho(x) - f) / tau of the Vlasov-Boltzmann
+       model (Sec. 3.4, Example 5), added to the spatial operator of every Runge-Kutta stage;
+       dim = 2 m with directions 1..m = x, m+1..2m = v.  mu_inf(v) = exp(-|v|^2/(2 theta)) /
+       (2 pi theta)^(m/2) and rho(x) = int f dv, the sum over the grid's velocity nodes times
+       their cell volume, taken from each stage's input.  relax_tau = 0 switches it off; else
+       relax_tau > 0 and relax_theta > 0. */
+    double relax_tau;
+    double relax_theta;
 } sgw_problem;
 
 typedef struct sgw_config {
@@ -126,10 +140,12 @@ typedef struct sgw_batch sgw_batch_t;
  * (l_1..l_dim), with combination coefficient (-1)^q C(dim-1, q).  Grid l has
  * N_r 2^{l_k} nodes in direction k.  Errors: SGW_ERR_INVALID_ARG for dim
  * outside 1..4, N_r < 4, N_L outside 0..12, cfl outside (0, 1.5], eps <= 0,
- * a Vlasov flux with odd dim, a finest grid with more than 2^40 nodes, box_target
- * outside 64..2048, blocks_per_cu outside 0..64, reserved0 not 0 or an unknown
- * boundary condition; SGW_ERR_UNSUPPORTED for a box or tile that does not divide
- * the extents or does not fit one workgroup, and for SGW_BC_ZERO.  With
+ * a Vlasov flux, initial condition or relaxation with odd dim, a negative or
+ * non-finite relax_tau, relax_theta <= 0 with relaxation on, a finest grid with more
+ * than 2^40 nodes, box_target outside 64..2048, blocks_per_cu outside 0..64,
+ * reserved0 not 0 or an unknown boundary condition; SGW_ERR_UNSUPPORTED for a box or
+ * tile that does not divide the extents or does not fit one workgroup, and for manual
+ * stage boxes with a zero boundary or relaxation (those run as line sweeps).  With
  * fine_tile 0 the prolongation tile is searched over divisors of the finest
  * extent (interpolations, staging, writes and LDS occupancy weighed). */
 sgw_status sgw_plan_create(const sgw_problem* problem, const sgw_config* config, sgw_plan_t** out);
@@ -155,8 +171,9 @@ sgw_status sgw_plan_grid(const sgw_plan_t* plan, int32_t g, int32_t level[SGW_MA
 sgw_status sgw_plan_fine_tile(const sgw_plan_t* plan, int32_t tile[SGW_MAX_DIM]);
 
 /* Box extents the stage kernel uses for grid g (one workgroup per box).  4D grids
- * without manual boxes march as line sweeps (one launch per direction, a lane per
- * segment of a grid line, no boxes) and report all-zero extents. */
+ * without manual boxes, and every grid of a plan with a zero boundary or relaxation,
+ * march as line sweeps (one launch per direction, a lane per segment of a grid line,
+ * no boxes) and report all-zero extents. */
 sgw_status sgw_plan_grid_box(const sgw_plan_t* plan, int32_t g, int32_t box[SGW_MAX_DIM]);
 
 /* ---------------------------------------------------------------- solvers
@@ -191,8 +208,20 @@ sgw_status sgw_prolongate_combine(sgw_solver_t* solver, double* out_dev);
 /* Exact solution at time t on the finest grid (FP64), for the error norms:
  * advection: u0(x - a t); Burgers with a sine: characteristics solved by
  * Newton's method (valid before the shock); Vlasov: f0 at the foot of the
- * characteristic, classical RK4 with steps of at most 1e-3. */
+ * characteristic, classical RK4 with steps of at most 1e-3.  SGW_ERR_UNSUPPORTED
+ * for the Vlasov-Boltzmann model (no closed form). */
 sgw_status sgw_exact(sgw_solver_t* solver, double t, double* out_dev);
+
+/* Entropy functionals of the Vlasov-Boltzmann model (Sec. 3.4, Example 5) of a
+ * finest-grid solution f_dev (FP64, the layout sgw_prolongate_combine writes):
+ * H_2 = int H^2 M and H_log = int H log(H) M over the domain, H = f / M, with the
+ * stationary state M(x, v) = exp(-(|v|^2/2 + |x|^2/2)/theta) / ((2 pi theta)^(m/2)
+ * int_x exp(-|x|^2/(2 theta)) dx), the x integral over the x domain in closed form,
+ * the others sums over the finest nodes times the cell volume; H log H is 0 where
+ * f <= 0.  theta = relax_theta.  Writes result_host[0] = H_2, [1] = H_log in a fixed
+ * order (bitwise repeatable); synchronises.  SGW_ERR_INVALID_ARG for odd dim or
+ * relax_theta <= 0. */
+sgw_status sgw_entropies(sgw_solver_t* solver, const double* f_dev, double* result_host);
 
 /* L1 = mean |a - b|, Linf = max |a - b| over the finest grid, in FP64 and in a
  * fixed order (bitwise repeatable).  Writes result_host[0..1]; synchronises. */

@@ -16,8 +16,8 @@ SGW_OK = 0
 ERRORS = {-1: "invalid argument", -2: "unsupported", -3: "out of memory", -4: "non-finite",
           -5: "HIP error", -6: "call out of order"}
 
-FLUX_ADVECTION, FLUX_BURGERS, FLUX_VLASOV_FIXED_E = 0, 1, 2
-IC_SINE, IC_MAXWELL_COS = 0, 1
+FLUX_ADVECTION, FLUX_BURGERS, FLUX_VLASOV_FIXED_E, FLUX_VLASOV_HARMONIC = 0, 1, 2, 3
+IC_SINE, IC_MAXWELL_COS, IC_VLASOV_BOLTZMANN = 0, 1, 2
 DT_CFL, DT_POW53 = 0, 1
 PROLONG_WENO5, PROLONG_LAGRANGE5 = 0, 1
 FP64, FP32_SWEEP = 0, 1
@@ -34,7 +34,7 @@ class SgwError(RuntimeError):
 class Problem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("flux", C.c_int32), ("ic", C.c_int32), ("reserved0", C.c_int32),
                 ("bc", C.c_int32 * 4), ("lo", C.c_double * 4), ("hi", C.c_double * 4), ("flux_params", C.c_double * 4),
-                ("ic_params", C.c_double * 8)]
+                ("ic_params", C.c_double * 8), ("relax_tau", C.c_double), ("relax_theta", C.c_double)]
 
 
 class Config(C.Structure):
@@ -66,6 +66,7 @@ _SIGS = {
     "sgw_prolongate_combine": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "sgw_exact": (C.c_int32, [C.c_void_p, C.c_double, C.c_void_p]),
     "sgw_norms": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "sgw_entropies": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "sgw_query": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "sgw_set_grid": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
     "sgw_snapshot_bytes": (C.c_uint64, [C.c_void_p]),
@@ -136,7 +137,7 @@ def _pad(v, n, fill=0.0):
 def make_structs(pb, box=None, fine_tile=None, box_target=0, blocks_per_cu=0):
     """Problem/Config structs from a problem description with the fields of
     sgw_inputs.Problem (d, lo, hi, flux, flux_params, ic, ic_params, nr, nl, cfl,
-    dt_mode, prolong, linear, precision, eps_flux, eps_interp, bc)."""
+    dt_mode, prolong, linear, precision, eps_flux, eps_interp, bc, relax_tau, relax_theta)."""
     p = Problem()
     p.dim = pb.d
     p.flux = pb.flux
@@ -147,6 +148,8 @@ def make_structs(pb, box=None, fine_tile=None, box_target=0, blocks_per_cu=0):
     p.hi[:] = _pad(pb.hi, 4)
     p.flux_params[:] = _pad(pb.flux_params, 4)
     p.ic_params[:] = _pad(pb.ic_params, 8)
+    p.relax_tau = float(getattr(pb, "relax_tau", 0.0))
+    p.relax_theta = float(getattr(pb, "relax_theta", 1.0))
     c = Config()
     c.root_cells = pb.nr
     c.finest_level = pb.nl

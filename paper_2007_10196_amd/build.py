@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libsgweno.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["api.hip", "batch.hip", "staging.hip", "kernels_stage.hip", "kernels_step.hip", "kernels_prolong.hip",
-           "calibrate.hip", "noalloc.hip"]
+           "calibrate.hip", "noalloc.hip", "kernels_relax.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SGW_OFFLOAD_ARCH", "gfx950")

@@ -510,17 +510,25 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.5)) return sgw_fail(SGW_ERR_INVALID_ARG, "cfl %g outside (0, 1.5]", cfg->cfl);
     if (!(cfg->eps_flux > 0.0) || !(cfg->eps_interp > 0.0))
         return sgw_fail(SGW_ERR_INVALID_ARG, "epsilon must be positive");
-    if (pb->flux < 0 || pb->flux > 2) return sgw_fail(SGW_ERR_INVALID_ARG, "unknown flux %d", pb->flux);
-    if (pb->ic < 0 || pb->ic > 1) return sgw_fail(SGW_ERR_INVALID_ARG, "unknown initial condition %d", pb->ic);
+    if (pb->flux < 0 || pb->flux > 3) return sgw_fail(SGW_ERR_INVALID_ARG, "unknown flux %d", pb->flux);
+    if (pb->ic < 0 || pb->ic > 2) return sgw_fail(SGW_ERR_INVALID_ARG, "unknown initial condition %d", pb->ic);
     if (pb->reserved0 != 0) return sgw_fail(SGW_ERR_INVALID_ARG, "reserved0 must be 0");
+    int zmask = 0;
     for (int k = 0; k < d; k++) {
         if (pb->bc[k] != SGW_BC_PERIODIC && pb->bc[k] != SGW_BC_ZERO)
             return sgw_fail(SGW_ERR_INVALID_ARG, "unknown boundary condition %d in direction %d", pb->bc[k], k);
-        if (pb->bc[k] != SGW_BC_PERIODIC)
-            return sgw_fail(SGW_ERR_UNSUPPORTED, "boundary condition %d in direction %d (only periodic)", pb->bc[k], k);
+        if (pb->bc[k] == SGW_BC_ZERO) zmask |= 1 << k;
     }
-    if ((pb->flux == SGW_FLUX_VLASOV_FIXED_E || pb->ic == SGW_IC_MAXWELL_COS) && (d % 2))
-        return sgw_fail(SGW_ERR_INVALID_ARG, "phase-space problems need an even dim");
+    if (!(pb->relax_tau >= 0.0) || !std::isfinite(pb->relax_tau))
+        return sgw_fail(SGW_ERR_INVALID_ARG, "relax_tau %g must be finite and >= 0", pb->relax_tau);
+    const bool relax = pb->relax_tau > 0.0;
+    if (relax && !(pb->relax_theta > 0.0 && std::isfinite(pb->relax_theta)))
+        return sgw_fail(SGW_ERR_INVALID_ARG, "relax_theta %g must be finite and > 0", pb->relax_theta);
+    const bool phase = pb->flux == SGW_FLUX_VLASOV_FIXED_E || pb->flux == SGW_FLUX_VLASOV_HARMONIC ||
+                       pb->ic == SGW_IC_MAXWELL_COS || pb->ic == SGW_IC_VLASOV_BOLTZMANN || relax;
+    if (phase && (d % 2)) return sgw_fail(SGW_ERR_INVALID_ARG, "phase-space problems need an even dim");
+    if (pb->ic == SGW_IC_VLASOV_BOLTZMANN && d != 2 && d != 4)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "the Vlasov-Boltzmann initial condition needs dim 2 or 4");
     if (cfg->dt_mode != SGW_DT_CFL && cfg->dt_mode != SGW_DT_POW53)
         return sgw_fail(SGW_ERR_INVALID_ARG, "unknown dt_mode %d", cfg->dt_mode);
     if (cfg->prolong != SGW_PROLONG_WENO5 && cfg->prolong != SGW_PROLONG_LAGRANGE5)
@@ -586,10 +594,16 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
         tot += n;
         bool manual = false;
         for (int k = 0; k < d; k++) manual |= cfg->box[k] > 0;
-        if (d == 4 && !manual) {
-            // 4D: the line sweep (no stage boxes); a work item is SGW_LWAVE segments of
-            // SGW_LSEG nodes, enough items for the direction with the most segments
+        if (manual && (zmask || relax)) {
+            delete p;
+            return sgw_fail(SGW_ERR_UNSUPPORTED, "manual stage boxes with a zero boundary or relaxation");
+        }
+        if ((d == 4 || zmask || relax) && !manual) {
+            // 4D, zero boundaries and relaxation: the line sweep (no stage boxes); a work item
+            // is SGW_LWAVE segments of SGW_LSEG nodes, enough items for the direction with the
+            // most segments
             gd.line_mode = 1;
+            gd.zmask = zmask;
             int64_t most = 0;
             for (int k = 0; k < SGW_MAX_DIM; k++) gd.fd_n[k] = make_fastdiv((uint32_t)gd.n[k]);
             for (int k = 0; k < d; k++) {
@@ -634,6 +648,25 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     }
     p->offsets[p->G] = tot;
     p->total_nodes = tot;
+    p->zmask = zmask;
+    p->relax = relax;
+    // density of the relaxation source: per grid, blocks of SGW_RHO_COLS x nodes times chunks of
+    // SGW_RHO_CHUNK velocity rows
+    p->nrho_items = 0;
+    if (relax)
+        for (int g = 0; g < p->G; g++) {
+            GridDev& gd = p->grids[g];
+            const int m = d / 2;
+            int64_t nx = 1, nv = 1;
+            for (int k = 0; k < m; k++) nx *= gd.n[k];
+            for (int k = m; k < d; k++) nv *= gd.n[k];
+            gd.relax = 1;
+            gd.nxr = (int32_t)nx;
+            gd.nvr = (int32_t)nv;
+            gd.rho_cb = (int32_t)((nx + SGW_RHO_COLS - 1) / SGW_RHO_COLS);
+            gd.rho_nchunk = (int32_t)((nv + SGW_RHO_CHUNK - 1) / SGW_RHO_CHUNK);
+            p->nrho_items += (int64_t)gd.rho_cb * gd.rho_nchunk;
+        }
     // the box list holds the grids that are one box first (their three stages run in one
     // launch), then the boxes of the others, grid by grid
     p->nitems = 0;
@@ -681,7 +714,7 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     p->off_alpha = take(sizeof(unsigned long long) * 4 * p->G);
     p->coef_off.assign((size_t)p->G * SGW_MAX_DIM, 0);
     uint64_t coef_elems = 0;
-    if (pb->flux == SGW_FLUX_VLASOV_FIXED_E) {
+    if (pb->flux == SGW_FLUX_VLASOV_FIXED_E || pb->flux == SGW_FLUX_VLASOV_HARMONIC) {
         const int m = d / 2;
         for (int g = 0; g < p->G; g++)
             for (int k = 0; k < d; k++) {
@@ -701,6 +734,25 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     uint64_t foot = 0;
     if (pb->flux == SGW_FLUX_VLASOV_FIXED_E) foot = sizeof(double) * 2 * (uint64_t)(d / 2) * N * N;
     p->off_foot = take(foot ? foot : 8);
+    // relaxation: velocity factor tables, density, its partial sums, arrival counters, work items
+    p->mu_off.assign((size_t)p->G * SGW_MAX_DIM, 0);
+    uint64_t mu_elems = 0, rho_elems = 0, part_elems = 0, cnt_elems = 0;
+    if (relax)
+        for (int g = 0; g < p->G; g++) {
+            const GridDev& gd = p->grids[g];
+            for (int k = d / 2; k < d; k++) {
+                p->mu_off[(size_t)g * SGW_MAX_DIM + k] = (int64_t)mu_elems;
+                mu_elems += (uint64_t)gd.n[k];
+            }
+            rho_elems += (uint64_t)gd.nxr;
+            part_elems += (uint64_t)gd.nxr * (uint64_t)gd.rho_nchunk;
+            cnt_elems += (uint64_t)gd.rho_cb;
+        }
+    p->off_mu = take(sizeof(double) * (mu_elems ? mu_elems : 1));
+    p->off_rho = take(sizeof(double) * (rho_elems ? rho_elems : 1));
+    p->off_rho_part = take(sizeof(double) * (part_elems ? part_elems : 1));
+    p->off_rho_cnt = take(sizeof(unsigned int) * (cnt_elems ? cnt_elems : 1));
+    p->off_rho_items = take(sizeof(RhoItem) * (p->nrho_items ? p->nrho_items : 1));
     p->scratch_bytes = off;
     *out = p;
     return SGW_OK;
@@ -790,6 +842,7 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
     s->partials_d = (double*)(s->scratch + p->off_partials);
     s->result_d = (double*)(s->scratch + p->off_result);
     s->foot_d = (double*)(s->scratch + p->off_foot);
+    s->rho_items_d = (RhoItem*)(s->scratch + p->off_rho_items);
 
     const bool dyn = p->pb.flux == SGW_FLUX_BURGERS;
     const int N = p->N;
@@ -819,11 +872,46 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
             if (p->pb.flux == SGW_FLUX_ADVECTION) {
                 gd.lin_c[k] = p->pb.flux_params[k];
                 gd.alpha_c[k] = std::fabs(p->pb.flux_params[k]);
-            } else if (p->pb.flux == SGW_FLUX_VLASOV_FIXED_E) {
+            } else if (p->pb.flux == SGW_FLUX_VLASOV_FIXED_E || p->pb.flux == SGW_FLUX_VLASOV_HARMONIC) {
                 const int m = d / 2;
                 gd.coef_src[k] = k < m ? m + k : k - m;
                 gd.coef[k] = s->coef_d + p->coef_off[(size_t)g * SGW_MAX_DIM + k];
             }
+        }
+    }
+    // relaxation: velocity factors, density and its partial sums per grid, work items
+    std::vector<double> mu_h;
+    std::vector<RhoItem> rho_items_h;
+    if (p->relax) {
+        const double th = p->pb.relax_theta;
+        const double norm1 = 1.0 / std::sqrt(2.0 * M_PI * th);
+        double* mu_base = (double*)(s->scratch + p->off_mu);
+        double* rho_base = (double*)(s->scratch + p->off_rho);
+        double* part_base = (double*)(s->scratch + p->off_rho_part);
+        unsigned int* cnt_base = (unsigned int*)(s->scratch + p->off_rho_cnt);
+        int64_t rho_off = 0, part_off = 0, cnt_off = 0;
+        for (int g = 0; g < p->G; g++) {
+            GridDev& gd = s->grids_h[g];
+            gd.inv_tau = 1.0 / p->pb.relax_tau;
+            gd.hv = 1.0;
+            for (int k = d / 2; k < d; k++) {
+                const int64_t o = p->mu_off[(size_t)g * SGW_MAX_DIM + k];
+                gd.mu[k] = mu_base + o;
+                gd.hv *= gd.h[k];
+                if ((int64_t)mu_h.size() < o + gd.n[k]) mu_h.resize((size_t)(o + gd.n[k]));
+                for (int j = 0; j < gd.n[k]; j++) {
+                    const double v = gd.lo[k] + j * gd.h[k];
+                    mu_h[(size_t)(o + j)] = std::exp(-v * v / (2.0 * th)) * norm1;
+                }
+            }
+            gd.rho = rho_base + rho_off;
+            gd.rho_part = part_base + part_off;
+            gd.rho_cnt = cnt_base + cnt_off;
+            rho_off += gd.nxr;
+            part_off += (int64_t)gd.nxr * gd.rho_nchunk;
+            cnt_off += gd.rho_cb;
+            for (int c = 0; c < gd.rho_nchunk; c++)
+                for (int b = 0; b < gd.rho_cb; b++) rho_items_h.push_back(RhoItem{s->grids_d + g, b, c});
         }
     }
     // time-step record
@@ -888,6 +976,7 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
     s->fine_h.G = p->G;
     s->fine_h.lagrange = p->cfg.prolong == SGW_PROLONG_LAGRANGE5;
     s->fine_h.eps = p->cfg.eps_interp;
+    s->fine_h.zmask = p->zmask;
     s->fine_h.pad0 = (int32_t)p->pro_buf_elems;
     s->fine_h.pad1 = (int32_t)p->pro_bufb_elems;
     int pts = 1;
@@ -941,7 +1030,18 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
     cp(s->pro_d, s->pro_h.data(), sizeof(ProDev) * p->G);
     cp(s->fine_d, &s->fine_h, sizeof(FineDev));
     cp(s->scratch + p->off_stab, s->stab_h.data(), s->stab_h.size());
-    if (rc == SGW_OK && p->pb.flux == SGW_FLUX_VLASOV_FIXED_E) {
+    if (p->relax) {
+        cp(s->scratch + p->off_mu, mu_h.data(), sizeof(double) * mu_h.size());
+        cp(s->rho_items_d, rho_items_h.data(), sizeof(RhoItem) * rho_items_h.size());
+        if (rc == SGW_OK) {
+            // arrival counters start at zero; the last workgroup of each block resets its own
+            size_t cnt = 0;
+            for (int g = 0; g < p->G; g++) cnt += (size_t)s->grids_h[g].rho_cb;
+            hipError_t e = hipMemsetAsync(s->scratch + p->off_rho_cnt, 0, sizeof(unsigned int) * cnt, st);
+            if (e != hipSuccess) rc = sgw_hip_fail(e, "density counters");
+        }
+    }
+    if (rc == SGW_OK && (p->pb.flux == SGW_FLUX_VLASOV_FIXED_E || p->pb.flux == SGW_FLUX_VLASOV_HARMONIC)) {
         hipError_t e = launch_coef_init(s->grids_d, s->grids_h.data(), p->G, s->coef_d, s->coef_off_d, &p->pb, st);
         if (e != hipSuccess) rc = sgw_hip_fail(e, "coefficient tables");
         // the host mirrors the constant wave speeds to plan the number of steps
@@ -1086,14 +1186,21 @@ static hipError_t enqueue_step(sgw_solver* s, int mode, hipStream_t st)
     const sgw_plan* p = s->plan;
     hipError_t e = launch_dt_one(s->req_d, st);
     if (e != hipSuccess) return e;
+    // relaxation: rho(x) of each stage's input, before the stage's line sweeps
+    const int nrho = p->relax ? (int)p->nrho_items : 0;
     if (mode == SGW_RUN_PLAIN) {
-        for (int stage = 0; stage < 3; stage++)
+        for (int stage = 0; stage < 3; stage++) {
+            if (nrho) {
+                e = launch_rho(s->rho_items_d, nrho, stage, p->cfg.precision, st);
+                if (e != hipSuccess) return e;
+            }
             for (int g = 0; g < p->G; g++) {
                 e = launch_stage(s->items_d + p->grids[g].first_item, p->grids[g].nbox, stage, p->cfg.precision,
                                  p->pb.dim, stage_lds_bytes(p->grids[g], p->cfg.precision), 0, st,
                                  p->grids[g].line_mode != 0);
                 if (e != hipSuccess) return e;
             }
+        }
         return hipSuccess;
     }
     // grids that are one box: all three stages in one launch; the others stage by stage
@@ -1103,6 +1210,10 @@ static hipError_t enqueue_step(sgw_solver* s, int mode, hipStream_t st)
         if (e != hipSuccess) return e;
     }
     for (int stage = 0; stage < 3 && nbx; stage++) {
+        if (nrho) {
+            e = launch_rho(s->rho_items_d, nrho, stage, p->cfg.precision, st);
+            if (e != hipSuccess) return e;
+        }
         e = launch_stage(s->items_d + nw, nbx, stage, p->cfg.precision, p->pb.dim, p->lds_boxed, s->grid, st,
                          p->line_mode);
         if (e != hipSuccess) return e;
@@ -1216,6 +1327,8 @@ extern "C" sgw_status sgw_exact(sgw_solver_t* s, double t, double* out_dev)
         return sgw_fail(SGW_ERR_UNSUPPORTED, "Burgers exact solution needs a sine initial condition");
     if (p->pb.flux == SGW_FLUX_VLASOV_FIXED_E && p->pb.ic != SGW_IC_MAXWELL_COS)
         return sgw_fail(SGW_ERR_UNSUPPORTED, "Vlasov exact solution needs the Maxwellian initial condition");
+    if (p->pb.flux == SGW_FLUX_VLASOV_HARMONIC || p->pb.ic == SGW_IC_VLASOV_BOLTZMANN || p->relax || p->zmask)
+        return sgw_fail(SGW_ERR_UNSUPPORTED, "no closed-form solution for the Vlasov-Boltzmann model");
     ExactDev e;
     std::memset(&e, 0, sizeof(e));
     e.d = p->pb.dim;
@@ -1230,6 +1343,27 @@ extern "C" sgw_status sgw_exact(sgw_solver_t* s, double t, double* out_dev)
     for (int i = 0; i < 8; i++) e.ip[i] = p->pb.ic_params[i];
     e.t = t;
     HIPCHK(launch_exact(e, out_dev, s->foot_d, s->stream), "exact solution");
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_entropies(sgw_solver_t* s, const double* f, double* result_host)
+{
+    if (!s || !f || !result_host) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    const sgw_plan* p = s->plan;
+    const int d = p->pb.dim;
+    const double th = p->pb.relax_theta;
+    if (d % 2) return sgw_fail(SGW_ERR_INVALID_ARG, "entropies need an even dim (x and v)");
+    if (!(th > 0.0) || !std::isfinite(th)) return sgw_fail(SGW_ERR_INVALID_ARG, "relax_theta %g must be > 0", th);
+    // int_x exp(-|x|^2/(2 theta)) dx over the x domain: a product of erf differences
+    double zx = 1.0;
+    for (int k = 0; k < d / 2; k++)
+        zx *= std::sqrt(0.5 * M_PI * th) *
+              (std::erf(p->pb.hi[k] / std::sqrt(2.0 * th)) - std::erf(p->pb.lo[k] / std::sqrt(2.0 * th)));
+    HIPCHK(launch_entropies(s->fine_h, p->pb.lo, p->pb.hi, th, zx, f, s->partials_d, s->result_d, s->stream),
+           "entropies");
+    HIPCHK(hipMemcpyAsync(result_host, s->result_d, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream),
+           "read entropies");
+    HIPCHK(hipStreamSynchronize(s->stream), "synchronise");
     return SGW_OK;
 }
 

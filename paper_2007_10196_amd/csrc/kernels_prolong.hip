@@ -66,7 +66,9 @@ __device__ __forceinline__ Real interp5(Real a, Real b, Real c, Real d, Real e, 
     return rdiv(w0 * P0 + w1 * P1 + w2 * P2, w0 + w1 + w2);
 }
 
-template <typename Real, int D>
+// ZB: the problem has a zero boundary (FineDev.zmask): coarse positions beyond either end of
+// such a direction read 0 instead of wrapping.
+template <typename Real, int D, bool ZB>
 __device__ __forceinline__ void prolong_tile(ProC pro, FineC F, double* __restrict__ out, int tile)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -98,10 +100,11 @@ __device__ __forceinline__ void prolong_tile(ProC pro, FineC F, double* __restri
             const int m = p->m[k];
             cl[k] = (m == 0) ? J0[k] : (((2 * J0[k] + (1 << m)) >> (m + 1)) - 2);
         }
-        // ---- coarse block this tile depends on (periodic wrap)
+        // ---- coarse block this tile depends on (periodic wrap, or 0 beyond a zero boundary)
         for (int e = tid; e < p->load_total; e += SGW_BLOCK) {
             uint32_t r = (uint32_t)e;
             int gi = 0;
+            bool zero = false;
 #pragma unroll
             for (int k = 0; k < D; k++) {
                 const uint32_t q = FDIV(r, p->fd_c[k]);
@@ -111,8 +114,9 @@ __device__ __forceinline__ void prolong_tile(ProC pro, FineC F, double* __restri
                 const uint32_t xw = (uint32_t)(cl[k] + c + 2 * p->n[k]);
                 const int x = (int)(xw - FDIV(xw, p->fd_n[k]) * (uint32_t)p->n[k]);
                 gi += x * p->stride[k];
+                if (ZB && ((F->zmask >> k) & 1)) zero |= (cl[k] + c < 0) || (cl[k] + c >= p->n[k]);
             }
-            bufA[e] = u[gi];
+            bufA[e] = zero ? Real(0) : u[gi];
         }
         __syncthreads();
         Real* src = bufA;
@@ -277,7 +281,7 @@ __device__ __forceinline__ Real centre_value(const Centre<Real>& z, const SGW_CO
     return rdiv(num, fma(t.c2, z.E2, fma(t.c1, z.E1, t.c0 * z.E0)));
 }
 
-template <typename Real, int D, bool LAG>
+template <typename Real, int D, bool LAG, bool ZB>
 __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __restrict__ out, int tile)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -314,10 +318,13 @@ __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __
         }
         const int kl = p->klast;
         // element offset of row r of the coarse block (its position along directions 2..d,
-        // periodic wrap: cl + c + 2n >= 0 takes its remainder by n with the fast division)
+        // periodic wrap: cl + c + 2n >= 0 takes its remainder by n with the fast division);
+        // -1 for a row beyond either end of a zero-boundary direction (all its values are 0)
+        const int zm = ZB ? F->zmask : 0;
         auto row_offset = [&](int r) {
             uint32_t rr = (uint32_t)r;
             int gi = 0;
+            bool zero = false;
 #pragma unroll
             for (int k = 1; k < D; k++) {
                 const uint32_t q = FDIV(rr, p->fd_c[k]);
@@ -325,12 +332,15 @@ __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __
                 rr = q;
                 const uint32_t xw = (uint32_t)(cl[k] + c + 2 * p->n[k]);
                 gi += (int)(xw - FDIV(xw, p->fd_n[k]) * (uint32_t)p->n[k]) * p->stride[k];
+                if (ZB && ((zm >> k) & 1)) zero |= (cl[k] + c < 0) || (cl[k] + c >= p->n[k]);
             }
-            return gi;
+            return zero ? -1 : gi;
         };
-        // wrapped position along direction 1 of coarse index cl_1 + l: the same for every lane
+        // wrapped position along direction 1 of coarse index cl_1 + l: the same for every lane;
+        // -1 beyond either end of a zero boundary
         const int c0 = p->c[0], n0 = p->n[0];
         auto wrap0 = [&](int l) {
+            if (ZB && (zm & 1) && (cl[0] + l < 0 || cl[0] + l >= n0)) return -1;
             const uint32_t xw = (uint32_t)(cl[0] + l + 2 * n0);
             return (int)(xw - FDIV(xw, p->fd_n[0]) * (uint32_t)n0);
         };
@@ -348,7 +358,13 @@ __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __
                 const int x0 = e - (int)row * c0;
                 const uint32_t xw = (uint32_t)(cl[0] + x0 + 2 * n0);
                 const int x = (int)(xw - FDIV(xw, p->fd_n[0]) * (uint32_t)n0);
-                bufA[e] = u[rowoff[row] + x];
+                if (ZB) {
+                    const int ro = rowoff[row];
+                    const bool out0 = (zm & 1) && (cl[0] + x0 < 0 || cl[0] + x0 >= n0);
+                    bufA[e] = (ro < 0 || out0) ? Real(0) : u[ro + x];
+                } else {
+                    bufA[e] = u[rowoff[row] + x];
+                }
             }
             __syncthreads();
         } else {
@@ -359,17 +375,24 @@ __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __
             const int ifirst = (2 * Jk + R) >> (m + 1);
             const TabC tb = stab + (R - 2);
             for (int L = tid; L < lines; L += SGW_BLOCK) {
-                const Real* __restrict__ up = u + row_offset(L);
+                const int ro = row_offset(L);
+                const Real* __restrict__ up = u + (ro < 0 ? 0 : ro);
+                // coarse value l of the row (0 beyond a zero boundary)
+                auto val = [&](int l) {
+                    if (!ZB) return up[wrap0(l)];
+                    const int x = wrap0(l);
+                    return (ro < 0 || x < 0) ? Real(0) : up[x];
+                };
                 Real* dp = bufB + L * T0;
                 Slide<Real> w;
-                slide_init<Real, LAG>(w, up[wrap0(0)], up[wrap0(1)], up[wrap0(2)], up[wrap0(3)], up[wrap0(4)], eps4);
+                slide_init<Real, LAG>(w, val(0), val(1), val(2), val(3), val(4), eps4);
                 int li = 5;
                 Centre<Real> z;
                 centre_setup<Real, LAG>(z, w);
                 int next = ifirst * R + half - Jk;
                 for (int t = 0; t < T0; t++) {
                     if (t == next) {
-                        slide_next<Real, LAG>(w, up[wrap0(li)], eps4);
+                        slide_next<Real, LAG>(w, val(li), eps4);
                         li++;
                         centre_setup<Real, LAG>(z, w);
                         next += R;
@@ -508,14 +531,24 @@ __device__ __forceinline__ void prolong_any(ProC pro, FineC F, double* out, int 
 {
     if constexpr (D >= 3) {
         if (F->lines) {
-            if (F->lagrange)
-                prolong_tile_lines<Real, D, true>(pro, F, out, tile);
-            else
-                prolong_tile_lines<Real, D, false>(pro, F, out, tile);
+            if (F->zmask) {
+                if (F->lagrange)
+                    prolong_tile_lines<Real, D, true, true>(pro, F, out, tile);
+                else
+                    prolong_tile_lines<Real, D, false, true>(pro, F, out, tile);
+            } else {
+                if (F->lagrange)
+                    prolong_tile_lines<Real, D, true, false>(pro, F, out, tile);
+                else
+                    prolong_tile_lines<Real, D, false, false>(pro, F, out, tile);
+            }
             return;
         }
     }
-    prolong_tile<Real, D>(pro, F, out, tile);
+    if (F->zmask)
+        prolong_tile<Real, D, true>(pro, F, out, tile);
+    else
+        prolong_tile<Real, D, false>(pro, F, out, tile);
 }
 
 template <typename Real, int D>

@@ -1,0 +1,180 @@
+// Kernels of the Vlasov-Boltzmann model (Sec. 3.4, Example 5) around the line sweep: the
+// macroscopic density rho(x) = int f dv of each Runge-Kutta stage's input, which the
+// relaxation source (mu_inf(v) rho(x) - f) / tau reads, and the entropy functionals H_2 and
+// H_log of a finest-grid solution.
+#include <cmath>
+
+#include "sgw_internal.h"
+
+// descriptors are read through the constant address space (scalar loads)
+#define SGW_CONST __attribute__((address_space(4)))
+typedef const SGW_CONST GridDev* GridC;
+
+namespace {
+
+// rho(x) = h_v * (sum over the velocity nodes of the grid) of the stage input.  The grid is an
+// nvr x nxr matrix with the x nodes fastest.  Workgroup (grid, column block cb, chunk c) sums
+// rows c * SGW_RHO_CHUNK .. + SGW_RHO_CHUNK of SGW_RHO_COLS columns: lane (col, r) takes rows
+// r, r + L, r + 2L, ... (L row lanes) in FP64, the L row lanes are added in order through LDS
+// and the block's sums go to rho_part[c][x].  The last workgroup of a column block to arrive
+// (an arrival counter) adds the chunks in order, scales by h_v, writes rho and resets the
+// counter.  Every sum runs in a fixed order, so rho is bitwise repeatable.
+template <typename Real>
+__global__ void __launch_bounds__(SGW_BLOCK) rho_kernel(const RhoItem* __restrict__ items, int stage)
+{
+    constexpr int L = SGW_BLOCK / SGW_RHO_COLS;
+    __shared__ double part[SGW_BLOCK];
+    __shared__ int last;
+    const SGW_CONST RhoItem* it = (const SGW_CONST RhoItem*)items + blockIdx.x;
+    GridC g = (GridC)it->g;
+    if (((const SGW_CONST ReqDev*)g->req)->done) return;
+    const Real* __restrict__ in = (const Real*)(stage == 0 ? g->u : stage == 1 ? g->a : g->b);
+    const int nx = g->nxr, nv = g->nvr, cb = it->cb, chunk = it->chunk;
+    const int col = threadIdx.x % SGW_RHO_COLS, lane = threadIdx.x / SGW_RHO_COLS;
+    const int x = cb * SGW_RHO_COLS + col;
+    const int r0 = chunk * SGW_RHO_CHUNK + lane;
+    double sum = 0.0;
+    if (x < nx) {
+#pragma unroll
+        for (int i = 0; i < SGW_RHO_RPT; i++) {
+            const int r = r0 + i * L;
+            if (r < nv) sum += (double)in[(int64_t)r * nx + x];
+        }
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    double* __restrict__ rp = g->rho_part;
+    if (lane == 0 && x < nx) {
+        double s = part[col];
+#pragma unroll
+        for (int l = 1; l < L; l++) s += part[col + l * SGW_RHO_COLS];
+        rp[(int64_t)chunk * nx + x] = s;
+    }
+    // the partial sums are visible device-wide before this workgroup counts itself in
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int prev = atomicAdd(g->rho_cnt + cb, 1u);
+        last = prev == (unsigned int)(g->rho_nchunk - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (lane == 0 && x < nx) {
+        double s = 0.0;
+        for (int c = 0; c < g->rho_nchunk; c++)
+            s += __hip_atomic_load(rp + (int64_t)c * nx + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        g->rho[x] = s * g->hv;
+    }
+    if (threadIdx.x == 0) g->rho_cnt[cb] = 0u;
+}
+
+struct EntArgs {
+    int32_t d, m;
+    int64_t N, n;
+    double lo[SGW_MAX_DIM], h[SGW_MAX_DIM];
+    double inv_theta, mnorm;
+};
+
+// First pass: workgroup blk of `parts` sums H^2 M and H log(H) M (0 where H <= 0) over its
+// strided share of the finest nodes, with M(x, v) = mnorm exp(-(|v|^2 + |x|^2) / (2 theta)),
+// in a fixed tree order.
+__global__ void __launch_bounds__(SGW_BLOCK) entropies_partial_kernel(EntArgs a, const double* __restrict__ f,
+                                                                      double* partials)
+{
+    __shared__ double s2[SGW_BLOCK], sl[SGW_BLOCK];
+    const int parts = gridDim.x;
+    double q2 = 0.0, ql = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)SGW_BLOCK + threadIdx.x; i < a.n; i += (int64_t)parts * SGW_BLOCK) {
+        int64_t r = i;
+        double r2 = 0.0;
+        for (int k = 0; k < a.d; k++) {
+            const int64_t q = r / a.N;
+            const double x = a.lo[k] + (double)(r - q * a.N) * a.h[k];
+            r = q;
+            r2 += x * x;
+        }
+        const double M = a.mnorm * exp(-0.5 * r2 * a.inv_theta);
+        const double H = f[i] / M;
+        q2 += H * H * M;
+        if (H > 0.0) ql += H * log(H) * M;
+    }
+    s2[threadIdx.x] = q2;
+    sl[threadIdx.x] = ql;
+    __syncthreads();
+    for (int w = SGW_BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s2[threadIdx.x] += s2[threadIdx.x + w];
+            sl[threadIdx.x] += sl[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s2[0];
+        partials[2 * blockIdx.x + 1] = sl[0];
+    }
+}
+
+// Second pass: the np partials, zero-padded to SGW_NPART, in a fixed tree order, times the
+// finest cell volume.
+__global__ void __launch_bounds__(SGW_BLOCK) entropies_final_kernel(const double* partials, int np, double cell,
+                                                                    double* result)
+{
+    __shared__ double s2[SGW_NPART], sl[SGW_NPART];
+    for (int i = threadIdx.x; i < SGW_NPART; i += blockDim.x) {
+        s2[i] = i < np ? partials[2 * i] : 0.0;
+        sl[i] = i < np ? partials[2 * i + 1] : 0.0;
+    }
+    __syncthreads();
+    for (int w = SGW_NPART / 2; w > 0; w >>= 1) {
+        for (int i = threadIdx.x; i < w; i += blockDim.x) {
+            s2[i] += s2[i + w];
+            sl[i] += sl[i + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        result[0] = s2[0] * cell;
+        result[1] = sl[0] * cell;
+    }
+}
+
+} // namespace
+
+hipError_t launch_rho(const RhoItem* items, int nitems, int stage, int precision, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (precision == SGW_FP64)
+        hipLaunchKernelGGL(rho_kernel<double>, dim3(nitems), dim3(SGW_BLOCK), 0, s, items, stage);
+    else
+        hipLaunchKernelGGL(rho_kernel<float>, dim3(nitems), dim3(SGW_BLOCK), 0, s, items, stage);
+    return hipGetLastError();
+}
+
+hipError_t launch_entropies(const FineDev& f, const double* lo, const double* hi, double theta, double zx,
+                            const double* fsol, double* partials, double* result, hipStream_t s)
+{
+    EntArgs a;
+    a.d = f.d;
+    a.m = f.d / 2;
+    a.N = f.N;
+    a.n = 1;
+    double cell = 1.0;
+    for (int k = 0; k < SGW_MAX_DIM; k++) {
+        a.lo[k] = k < f.d ? lo[k] : 0.0;
+        a.h[k] = k < f.d ? (hi[k] - lo[k]) / f.N : 0.0;
+        if (k < f.d) {
+            a.n *= f.N;
+            cell *= a.h[k];
+        }
+    }
+    a.inv_theta = 1.0 / theta;
+    a.mnorm = 1.0 / (std::pow(2.0 * M_PI * theta, 0.5 * a.m) * zx);
+    const int64_t pb = (a.n + SGW_BLOCK - 1) / SGW_BLOCK;
+    const int parts = pb < 1 ? 1 : (pb > SGW_NPART ? SGW_NPART : (int)pb);
+    hipLaunchKernelGGL(entropies_partial_kernel, dim3(parts), dim3(SGW_BLOCK), 0, s, a, fsol, partials);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(entropies_final_kernel, dim3(1), dim3(SGW_BLOCK), 0, s, partials, parts, cell, result);
+    return hipGetLastError();
+}

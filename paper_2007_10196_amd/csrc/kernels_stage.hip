@@ -602,17 +602,19 @@ __global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __rest
     }
 }
 
-// ---------------------------------------------------------------- line sweep (4D)
+// ---------------------------------------------------------------- line sweep (4D; zero boundary, relaxation)
 //
 // The same stage with one launch per direction k and no halo: a lane takes a segment of
 // SGW_LSEG nodes of one grid line along k, reads the SGW_LSEG + 6 values its interface fluxes
-// need (periodic wrap along the line) straight from memory, forms the SGW_LSEG + 1 fluxes
-// with window_fluxes (the box kernel's arithmetic, so the same bits) and adds
-// (F_{i-1/2} - F_{i+1/2}) / h_k of its nodes to the sum of the earlier directions.  That
-// partial sum waits in a state copy the stage does not read: the stage output for stages 1
-// and 2, the stage-1 buffer in stage 3.  The last direction applies the Runge-Kutta
-// combination, writes the stage output and reduces the next wave speed.
-template <typename Real, int D, int k, bool LIN>
+// need (periodic wrap along the line, or 0 beyond a zero boundary) straight from memory,
+// forms the SGW_LSEG + 1 fluxes with window_fluxes (the box kernel's arithmetic, so the same
+// bits) and adds (F_{i-1/2} - F_{i+1/2}) / h_k of its nodes to the sum of the earlier
+// directions.  That partial sum waits in a state copy the stage does not read: the stage
+// output for stages 1 and 2, the stage-1 buffer in stage 3.  The last direction adds the
+// relaxation source (mu_inf(v) rho(x) - u) / tau of the Vlasov-Boltzmann model (Sec. 3.4,
+// Example 5) where the grid has one, applies the Runge-Kutta combination, writes the stage
+// output and reduces the next wave speed.
+template <typename Real, int D, int k, bool LIN, bool ZB>
 __device__ __forceinline__ void line_segment(GridC g, int blk, int stage, Real alpha, Real& amax)
 {
     const int lane = threadIdx.x;
@@ -633,7 +635,10 @@ __device__ __forceinline__ void line_segment(GridC g, int blk, int stage, Real a
     }
     // the line's position: t over the directions other than k, direction 1 fastest
     const int csrc = g->coef_src[k];
-    int base = 0, xc = 0;
+    constexpr bool last = k == D - 1;
+    const bool relax = last && g->relax;
+    int base = 0, xc = 0, ix = 0;
+    double muf = 1.0;
     {
         uint32_t r = (uint32_t)t;
 #pragma unroll
@@ -644,13 +649,25 @@ __device__ __forceinline__ void line_segment(GridC g, int blk, int stage, Real a
             r = qq;
             base += x * g->stride[j];
             if (j == csrc) xc = x;
+            if (relax) {
+                // the x directions come first, so the x part of the offset is the x-node index
+                if (2 * j < D) ix += x * g->stride[j];
+                else muf *= g->mu[j][x];
+            }
         }
     }
     const int stride = g->stride[k];
     const int i0 = q * SGW_LSEG;
     const Real* __restrict__ in = (const Real*)(stage == 0 ? g->u : stage == 1 ? g->a : g->b);
     Real v[SGW_LSEG + 6]; // u_{i0-3} .. u_{i0+SGW_LSEG+2}
-    if ((g->pow2_mask >> k) & 1) {
+    if (ZB && ((g->zmask >> k) & 1)) {
+        // zero boundary: nothing wraps, positions beyond either end read 0
+#pragma unroll
+        for (int c = 0; c < SGW_LSEG + 6; c++) {
+            const int p = i0 - 3 + c;
+            v[c] = (p >= 0 && p < n) ? in[base + p * stride] : Real(0);
+        }
+    } else if ((g->pow2_mask >> k) & 1) {
 #pragma unroll
         for (int c = 0; c < SGW_LSEG + 6; c++) v[c] = in[base + ((i0 - 3 + c) & (n - 1)) * stride];
     } else {
@@ -667,7 +684,6 @@ __device__ __forceinline__ void line_segment(GridC g, int blk, int stage, Real a
     }
     // the sum of the earlier directions and (last direction, stages 2 and 3) u^n of the
     // segment's nodes are loaded with the window, so their latency overlaps it
-    constexpr bool last = k == D - 1;
     Real* __restrict__ part = (Real*)(stage == 1 ? g->b : g->a);
     const Real* __restrict__ u0 = (const Real*)g->u;
     Real pin[SGW_LSEG], un[SGW_LSEG];
@@ -700,10 +716,18 @@ __device__ __forceinline__ void line_segment(GridC g, int blk, int stage, Real a
     //      u = 1/3 u + 2/3 (u2 + dt L(u2))
     const Real dtr = (Real)((const SGW_CONST ReqDev*)g->req)->dt;
     Real* __restrict__ out = (Real*)(stage == 0 ? g->a : stage == 1 ? g->b : g->u);
+    Real rmu = Real(0), itau = Real(0);
+    const double* __restrict__ muk = g->mu[k];
+    if (relax) {
+        // rho(x) of this stage's input times the velocity factors of the other directions
+        rmu = (Real)(muf * g->rho[ix]);
+        itau = (Real)g->inv_tau;
+    }
 #pragma unroll
     for (int i = 0; i < SGW_LSEG; i++)
         if (i0 + i < n) {
-            const Real acc = fma(F[i] - F[i + 1], ih, pin[i]);
+            Real acc = fma(F[i] - F[i + 1], ih, pin[i]);
+            if (relax) acc = fma(fma(rmu, (Real)muk[i0 + i], -v[i + 3]), itau, acc);
             const Real val = fma(dtr, acc, v[i + 3]);
             Real res;
             if (stage == 0) res = val;
@@ -739,10 +763,17 @@ __global__ void __launch_bounds__(SGW_LWAVE) line_kernel(const WorkItem* __restr
         const Real alpha =
             g->dyn_alpha ? (Real)__longlong_as_double((long long)g->alpha[stage]) : (Real)g->alpha_c[k];
         Real amax = Real(0);
-        if (g->linear)
-            line_segment<Real, D, k, true>(g, it->box, stage, alpha, amax);
-        else
-            line_segment<Real, D, k, false>(g, it->box, stage, alpha, amax);
+        if (g->zmask) {
+            if (g->linear)
+                line_segment<Real, D, k, true, true>(g, it->box, stage, alpha, amax);
+            else
+                line_segment<Real, D, k, false, true>(g, it->box, stage, alpha, amax);
+        } else {
+            if (g->linear)
+                line_segment<Real, D, k, true, false>(g, it->box, stage, alpha, amax);
+            else
+                line_segment<Real, D, k, false, false>(g, it->box, stage, alpha, amax);
+        }
         if (k == D - 1 && g->dyn_alpha) {
             // one atomic max per wavefront on the bit pattern (order-free)
             const double m = wave_max((double)amax);
@@ -755,14 +786,20 @@ template <typename Real>
 hipError_t launch_lines(const WorkItem* items, int nitems, const int* range_dev, int blocks, int stage, int dim,
                         hipStream_t s)
 {
-    if (dim != 4) return hipErrorInvalidValue;
-#define SGW_LINE(K)                                                                                                   \
-    hipLaunchKernelGGL((line_kernel<Real, 4, K>), dim3(blocks), dim3(SGW_LWAVE), 0, s, items, nitems, range_dev, stage); \
-    if (hipGetLastError() != hipSuccess) return hipGetLastError();
-    SGW_LINE(0)
-    SGW_LINE(1)
-    SGW_LINE(2)
-    SGW_LINE(3)
+#define SGW_LINE(DD, K)                                                                                        \
+    hipLaunchKernelGGL((line_kernel<Real, DD, K>), dim3(blocks), dim3(SGW_LWAVE), 0, s, items, nitems, range_dev, \
+                       stage);                                                                                  \
+    {                                                                                                           \
+        const hipError_t e_ = hipGetLastError();                                                                \
+        if (e_ != hipSuccess) return e_;                                                                        \
+    }
+    switch (dim) {
+    case 1: SGW_LINE(1, 0) break;
+    case 2: SGW_LINE(2, 0) SGW_LINE(2, 1) break;
+    case 3: SGW_LINE(3, 0) SGW_LINE(3, 1) SGW_LINE(3, 2) break;
+    case 4: SGW_LINE(4, 0) SGW_LINE(4, 1) SGW_LINE(4, 2) SGW_LINE(4, 3) break;
+    default: return hipErrorInvalidValue;
+    }
 #undef SGW_LINE
     return hipSuccess;
 }

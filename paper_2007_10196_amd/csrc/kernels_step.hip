@@ -14,9 +14,11 @@ __global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long 
 }
 
 // Coefficient tables of the fixed-field Vlasov flux and the constant LF speeds:
-// f_{x_k} = v_k u (coefficient indexed by the v_k node), f_{v_k} = E_k(x_k) u.
+// f_{x_k} = v_k u (coefficient indexed by the v_k node), f_{v_k} = E_k(x_k) u with
+// E_k = amp sin(kE x_k), or E_k = -x_k (harmonic: the field of the Vlasov-Boltzmann model).
 // One workgroup per (grid, direction); the max over the table is the LF speed.
-__global__ void coef_init_kernel(GridDev* grids, double* coef_base, const int64_t* coef_off, double amp, double kE)
+__global__ void coef_init_kernel(GridDev* grids, double* coef_base, const int64_t* coef_off, double amp, double kE,
+                                 int harmonic)
 {
     __shared__ double red[SGW_BLOCK / 64];
     GridDev* g = grids + blockIdx.x;
@@ -29,7 +31,7 @@ __global__ void coef_init_kernel(GridDev* grids, double* coef_base, const int64_
     double amax = 0.0;
     for (int j = threadIdx.x; j < n; j += SGW_BLOCK) {
         const double x = g->lo[src] + j * g->h[src];
-        const double c = (k < m) ? x : amp * sin(kE * x);
+        const double c = (k < m) ? x : harmonic ? -x : amp * sin(kE * x);
         tab[j] = c;
         amax = fmax(amax, fabs(c));
     }
@@ -66,6 +68,16 @@ __device__ __forceinline__ double ic_value(const GridDev* g, int64_t idx, int ic
         return ip[0] + ip[1] * sin(ip[2] * s + ip[3]);
     }
     const int m = g->d / 2;
+    if (ic == SGW_IC_VLASOV_BOLTZMANN) {
+        // Sec. 3.4, Example 5: sin(x_1^2/2)^2 [cos(x_2^2/2)^2] exp(-(|x|^2 + |v|^2)/2) / s
+        double shape = 1.0, r2 = 0.0;
+        for (int k = 0; k < m; k++) {
+            const double q = (k == 0) ? sin(0.5 * x[k] * x[k]) : cos(0.5 * x[k] * x[k]);
+            shape *= q * q;
+        }
+        for (int k = 0; k < g->d; k++) r2 += x[k] * x[k];
+        return ip[0] * shape * exp(-0.5 * r2);
+    }
     double v2 = 0.0, pert = 1.0, norm = 1.0;
     for (int k = 0; k < m; k++) {
         v2 += x[m + k] * x[m + k];
@@ -279,7 +291,8 @@ hipError_t launch_coef_init(GridDev* grids_dev, const GridDev* grids_host, int G
     (void)grids_host;
     if (G <= 0) return hipSuccess;
     hipLaunchKernelGGL(coef_init_kernel, dim3(G, SGW_MAX_DIM), dim3(SGW_BLOCK), 0, s, grids_dev, coef_base,
-                       coef_off_dev, pb->flux_params[0], pb->flux_params[1]);
+                       coef_off_dev, pb->flux_params[0], pb->flux_params[1],
+                       pb->flux == SGW_FLUX_VLASOV_HARMONIC ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -26,12 +26,18 @@ struct sgw_plan {
     size_t pro_buf_elems = 0;                  // prolongation LDS buffer A (and B in the old form)
     size_t pro_bufb_elems = 0;                 // buffer B
     bool fine_lines = false;                   // 3D/4D line form of the prolongation
-    bool line_mode = false;                    // 4D: the stage runs as line sweeps (no boxes)
+    bool line_mode = false;                    // the stage runs as line sweeps (no boxes): 4D, zero
+                                               // boundary or relaxation
+    bool relax = false;                        // relaxation source on
+    int zmask = 0;                             // bit k: zero boundary in direction k
+    int64_t nrho_items = 0;                    // density work items over all grids
+    std::vector<int64_t> mu_off;               // [G][4] offsets into the velocity factor tables
     size_t pro_rows_max = 0;                   // its LDS row-offset table entries
     size_t pro_lds = 0;                        // LDS bytes of a prolongation workgroup
     uint64_t copy_bytes = 0, state_bytes = 0, scratch_bytes = 0;
     uint64_t off_grids = 0, off_req = 0, off_items = 0, off_alpha = 0, off_coef = 0, off_coef_off = 0;
     uint64_t off_pro = 0, off_fine = 0, off_partials = 0, off_result = 0, off_foot = 0, off_stab = 0;
+    uint64_t off_mu = 0, off_rho = 0, off_rho_part = 0, off_rho_cnt = 0, off_rho_items = 0;
 };
 
 struct sgw_solver {
@@ -50,6 +56,7 @@ struct sgw_solver {
     double* partials_d = nullptr;
     double* result_d = nullptr;
     double* foot_d = nullptr;
+    RhoItem* rho_items_d = nullptr;
     std::vector<GridDev> grids_h;
     std::vector<WorkItem> items_h;
     std::vector<ProDev> pro_h;

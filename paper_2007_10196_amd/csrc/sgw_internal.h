@@ -137,6 +137,28 @@ struct alignas(64) GridDev {
     int32_t ltrans[SGW_MAX_DIM];     // lines along k: prod_{j != k} n[j]
     FastDiv fd_lsegl[SGW_MAX_DIM];
     FastDiv fd_ltrans[SGW_MAX_DIM];
+    // zero boundary and the relaxation source of the Vlasov-Boltzmann model (line sweep only)
+    int32_t zmask;                   // bit k: every value beyond either end of direction k is 0
+    int32_t relax;                   // 1: the last direction adds (mu_inf(v) rho(x) - u) / tau
+    int32_t nxr, nvr;                // x nodes (prod of the first d/2 extents) and velocity nodes
+    int32_t rho_cb, rho_nchunk;      // density launch: blocks of SGW_RHO_COLS x nodes, chunks of rows
+    const double* mu[SGW_MAX_DIM];   // velocity direction k: exp(-v^2/(2 theta)) / sqrt(2 pi theta) per node
+    double* rho;                     // nxr: rho(x) of the current stage input
+    double* rho_part;                // rho_nchunk x nxr partial sums
+    unsigned int* rho_cnt;           // rho_cb arrival counters, zero between launches
+    double inv_tau, hv;              // 1 / tau and the velocity cell volume
+};
+
+// density launch: SGW_RHO_COLS x nodes per workgroup, SGW_BLOCK / SGW_RHO_COLS row lanes,
+// SGW_RHO_RPT rows per lane and chunk
+#define SGW_RHO_COLS 64
+#define SGW_RHO_RPT 16
+#define SGW_RHO_CHUNK (SGW_RHO_RPT * (SGW_BLOCK / SGW_RHO_COLS))
+
+// One (grid, block of x nodes, chunk of velocity rows) of the density launch.
+struct RhoItem {
+    const GridDev* g;
+    int32_t cb, chunk;
 };
 
 #ifndef SGW_LSEG
@@ -182,7 +204,8 @@ struct alignas(64) FineDev {
     int32_t T[SGW_MAX_DIM];
     int32_t ntile[SGW_MAX_DIM];
     int32_t inner[SGW_MAX_DIM];      // prod_{j<k} T[j]
-    int32_t tile_points, pad0, pad1, pad2; // pad0, pad1: LDS elements of prolongation buffers A, B
+    int32_t tile_points, pad0, pad1; // pad0, pad1: LDS elements of prolongation buffers A, B
+    int32_t zmask;                   // bit k: coarse values beyond either end of direction k are 0
     FastDiv fd_T[SGW_MAX_DIM];
     FastDiv fd_inner[SGW_MAX_DIM];
     double eps;
@@ -251,6 +274,11 @@ struct ExactDev {
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_coef_init(GridDev* grids_dev, const GridDev* grids_host, int G, double* coef_base,
                             const int64_t* coef_off_host, const sgw_problem* pb, hipStream_t s);
+// rho(x) of the stage input of every relaxation grid: items[0..nitems), one workgroup each
+hipError_t launch_rho(const RhoItem* items, int nitems, int stage, int precision, hipStream_t s);
+// H_2 and H_log of a finest-grid solution: partial sums in partials, the two values in result
+hipError_t launch_entropies(const FineDev& f, const double* lo, const double* hi, double theta, double zx,
+                            const double* fsol, double* partials, double* result, hipStream_t s);
 hipError_t launch_restrict(const GridDev* grids_dev, const GridDev* grids_host, int G, int precision,
                            const sgw_problem* pb, hipStream_t s);
 hipError_t launch_req_reset(ReqDev* r, hipStream_t s);

@@ -119,6 +119,14 @@ class Solver:
         B.check(B.lib().sgw_norms(self.handle, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), res))
         return res[0], res[1]
 
+    def entropies(self, f: torch.Tensor) -> Tuple[float, float]:
+        """(H_2, H_log) of a finest-grid solution (FP64) relative to the stationary state of the
+        Vlasov-Boltzmann model."""
+        assert f.dtype == torch.float64 and f.is_cuda and f.numel() >= self.plan.fine_nodes
+        res = (C.c_double * 2)()
+        B.check(B.lib().sgw_entropies(self.handle, C.c_void_p(f.data_ptr()), res))
+        return res[0], res[1]
+
     def norms_async(self, a: torch.Tensor, b: torch.Tensor, result: torch.Tensor):
         """L1, Linf into result[0:2] (device FP64) without synchronising."""
         assert result.dtype == torch.float64 and result.numel() >= 2 and result.is_cuda

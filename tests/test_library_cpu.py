@@ -99,8 +99,30 @@ def test_plan_rejects_invalid_arguments():
     _expect_status(good, -2, fine_tile=[5, 5])    # 5 does not divide 32
     _expect_status(good, -1, box_target=32)
     _expect_status(good.replace(bc=(0, 2)), -1)     # unknown boundary condition
-    _expect_status(good.replace(bc=(0, 1)), -2)     # zero ghost values: reserved, refused
+    _expect_status(good.replace(bc=(0, 1)), -2, box=[4, 4])  # zero boundary: line sweeps, no manual boxes
     Plan(good.replace(bc=(0, 0, 1, 1)))            # entries beyond dim are ignored
+    vb = W.paper_example5(2, nr=8, nl=2)
+    _expect_status(vb.replace(relax_tau=-1.0), -1)
+    _expect_status(vb.replace(relax_tau=float("inf")), -1)
+    _expect_status(vb.replace(relax_theta=0.0), -1)
+    _expect_status(vb.replace(d=3, lo=(-5.0,) * 3, hi=(5.0,) * 3, bc=(1,) * 3), -1)  # phase space: even dim
+    _expect_status(vb.replace(flux=4), -1)
+    _expect_status(vb.replace(ic=3), -1)
+    Plan(vb.replace(relax_theta=0.0, relax_tau=0.0))  # theta is not read without relaxation
+
+
+@pytest.mark.parametrize("d,bc,tau", [(2, (1, 1), 1.0), (2, (1, 0), 0.0), (3, (1, 1, 1), 0.0), (4, (1,) * 4, 1.0)])
+def test_zero_boundary_and_relaxation_plans_run_line_sweeps(d, bc, tau):
+    """Plans with a zero boundary or relaxation march every grid as line sweeps (no boxes), in
+    any dimension, and the same component grids as the oracle."""
+    if d in (2, 4):
+        pb = W.paper_example5(d, nr=8, nl=2).replace(bc=bc, relax_tau=tau)
+    else:
+        pb = W.c3_advection_3d(nr=4, nl=2).replace(bc=bc)
+    plan = Plan(pb)
+    assert plan.total_nodes == O.total_nodes(pb)
+    for info in plan.grids:
+        assert info["box"] == (0,) * d
 
 
 def test_error_strings():
