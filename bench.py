@@ -822,6 +822,102 @@ def paper_sweep(torch):
     return out
 
 
+# The paper's Vlasov-Boltzmann comparison (Sec. 3.4, Example 5): CPU seconds of the sparse-grid and
+# single-grid computations to time t (Tables tb:ex5acpu, tb:ex5bcpu).
+EX5_TABLES = {
+    "ex5a_2d": {"table": "Table tb:ex5acpu", "d": 2, "nr": 40, "nl": 3, "t": (0.5, 1.0, 2.0, 3.0, 6.0),
+                "cpu_single_s": (13111.313, 25185.141, 50756.395, 82253.965, 153593.745),
+                "cpu_sparse_s": (11720.746, 21371.762, 39493.979, 57898.835, 110626.464)},
+    "ex5b_4d": {"table": "Table tb:ex5bcpu", "d": 4, "nr": 10, "nl": 3, "t": (0.5, 1.0, 2.0, 3.0),
+                "cpu_single_s": (56231.125, 112539.000, 225612.000, 332706.250),
+                "cpu_sparse_s": (3918.468, 7876.233, 14468.500, 22821.125)},
+}
+
+
+def example5_run(torch, pb, times):
+    """One FP64 solve of the Vlasov-Boltzmann model marched through `times`: at each t the GPU
+    time of restriction + march to t + one prolongation and combination (HIP events on the solver
+    stream around each piece; the entropy reductions between checkpoints are not counted), and
+    the entropy functionals and mass of the combined solution."""
+    from paper_2007_10196_amd.solver import Solver
+    s = Solver(pb, device="cuda:0")
+    out = torch.empty(s.plan.fine_nodes, dtype=torch.float64, device="cuda:0")
+    # warm-up: graph capture and first launches, then start over
+    s.restrict()
+    s.advance(min(times[0], 0.01))
+    s.prolongate_combine(out)
+    torch.cuda.synchronize()
+    rows = []
+    r0, r1 = ev(torch), ev(torch)
+    r0.record(s.stream)
+    s.restrict()
+    r1.record(s.stream)
+    torch.cuda.synchronize()
+    march_ms = r0.elapsed_time(r1)
+    cell = (10.0 / pb.n_fine) ** pb.d
+    # analysis only: H_2 over the ball |(x, v)| <= 4 (M >= e^-8 M(0)), where the far field's
+    # division by M (down to e^-50 M(0) at the 4D corners) does not weigh in
+    n, m = pb.n_fine, pb.d // 2
+    g = -5.0 + (10.0 / n) * torch.arange(n, dtype=torch.float64, device="cuda:0")
+    r2 = torch.zeros((), dtype=torch.float64, device="cuda:0")
+    for k in range(pb.d):
+        r2 = r2.unsqueeze(-1) + (g * g).reshape((1,) * k + (n,))
+    r2 = r2.reshape(-1)
+    zx = (math.sqrt(2.0 * math.pi) * math.erf(5.0 / math.sqrt(2.0))) ** m
+    Minv = torch.exp(0.5 * r2) * ((2.0 * math.pi) ** (m / 2) * zx)
+    inner = r2 <= 16.0
+    del r2
+    for t in times:
+        e0, e1, e2 = ev(torch), ev(torch), ev(torch)
+        e0.record(s.stream)
+        s.advance(t)
+        e1.record(s.stream)
+        s.prolongate_combine(out)
+        e2.record(s.stream)
+        torch.cuda.synchronize()
+        march_ms += e0.elapsed_time(e1)
+        h2, hl = s.entropies(out)
+        mass = float(out.sum().item()) * cell
+        h2_inner = float((out * out * Minv)[inner].sum().item()) * cell
+        _, steps = s.query()
+        rows.append({"t": t, "ms": march_ms + e1.elapsed_time(e2), "march_ms": march_ms,
+                     "prolong_ms": e1.elapsed_time(e2), "time_steps": steps, "H2": h2, "Hlog": hl, "mass": mass,
+                     "H2_inner_ball_r4": h2_inner})
+    res = {"nodes": s.plan.total_nodes, "fine_nodes": s.plan.fine_nodes, "rows": rows}
+    del s, out, Minv, inner
+    torch.cuda.empty_cache()
+    return res
+
+
+def example5(torch):
+    """Sparse grid against single grid for the Vlasov-Boltzmann model at the paper's settings
+    (Example 5(a): 2D, root 40, level 3, 320^2; (b): 4D, root 10, level 3, 80^4; theta = tau = 1,
+    zero boundaries, CFL 0.4, FP64) at the times of Tables tb:ex5acpu and tb:ex5bcpu, with the
+    entropy decay of both computations."""
+    out = {}
+    for name, spec in EX5_TABLES.items():
+        d, nr, nl = spec["d"], spec["nr"], spec["nl"]
+        sp = example5_run(torch, W.paper_example5(d, nr=nr, nl=nl), spec["t"])
+        si = example5_run(torch, W.paper_example5(d, nr=nr << nl, nl=0), spec["t"])
+        rows = []
+        for i, t in enumerate(spec["t"]):
+            a, b = sp["rows"][i], si["rows"][i]
+            rows.append({"t": t, "sparse_ms": a["ms"], "single_ms": b["ms"], "gpu_ratio": a["ms"] / b["ms"],
+                         "paper_cpu_ratio": spec["cpu_sparse_s"][i] / spec["cpu_single_s"][i],
+                         "time_steps": a["time_steps"], "H2_sparse": a["H2"], "H2_single": b["H2"],
+                         "Hlog_sparse": a["Hlog"], "Hlog_single": b["Hlog"], "mass_sparse": a["mass"],
+                         "mass_single": b["mass"], "prolong_ms_sparse": a["prolong_ms"],
+                         "H2_inner_sparse": a["H2_inner_ball_r4"], "H2_inner_single": b["H2_inner_ball_r4"]})
+            print(f"[bench] {name} t={t}: sparse {a['ms']:.1f} ms, single {b['ms']:.1f} ms "
+                  f"(ratio {a['ms'] / b['ms']:.3f}, paper {rows[-1]['paper_cpu_ratio']:.3f}); "
+                  f"H2 {a['H2']:.5f}/{b['H2']:.5f} (|z|<=4: {a['H2_inner_ball_r4']:.5f}/{b['H2_inner_ball_r4']:.5f}), "
+                  f"Hlog {a['Hlog']:.5f}/{b['Hlog']:.5f}",
+                  file=sys.stderr, flush=True)
+        out[name] = {"table": spec["table"], "nodes_sparse": sp["nodes"], "nodes_single": si["nodes"],
+                     "finest_nodes": sp["fine_nodes"], "rows": rows}
+    return out
+
+
 def large_roofline(torch, reps=10):
     """Stage launches of one time step on the scaled cases whose state exceeds the 256 MB MALL: 3D
     advection at root 32 (32.5 M nodes, box kernel) and the 4D Vlasov workload at root 16 (50.3 M
@@ -898,6 +994,8 @@ def main():
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32", help="with --path-workload")
     ap.add_argument("--paper-sweep", action="store_true",
                     help="only run sparse against single grid at the paper's resolutions (and equal error)")
+    ap.add_argument("--example5", action="store_true",
+                    help="only run the Vlasov-Boltzmann sparse/single comparison of Tables tb:ex5acpu, tb:ex5bcpu")
     ap.add_argument("--large-roofline", action="store_true",
                     help="only time the stage launches of the scaled 3D/4D cases that exceed the MALL")
     args = ap.parse_args()
@@ -913,10 +1011,13 @@ def main():
     if args.path_workload:
         path_workload(args.path_workload, args.precision, args.box_target, args.blocks_per_cu, args.stage_reps)
         return
-    if args.paper_sweep or args.large_roofline:
+    if args.paper_sweep or args.large_roofline or args.example5:
         import torch
         torch.cuda.set_device(0)
-        res = {"paper_sweep": paper_sweep(torch)} if args.paper_sweep else {"large_roofline": large_roofline(torch)}
+        if args.example5:
+            res = {"example5": example5(torch)}
+        else:
+            res = {"paper_sweep": paper_sweep(torch)} if args.paper_sweep else {"large_roofline": large_roofline(torch)}
         print(json.dumps(res), flush=True)
         return
 

@@ -653,6 +653,7 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     // density of the relaxation source: per grid, blocks of SGW_RHO_COLS x nodes times chunks of
     // SGW_RHO_CHUNK velocity rows
     p->nrho_items = 0;
+    p->nrho_final = 0;
     if (relax)
         for (int g = 0; g < p->G; g++) {
             GridDev& gd = p->grids[g];
@@ -666,6 +667,7 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
             gd.rho_cb = (int32_t)((nx + SGW_RHO_COLS - 1) / SGW_RHO_COLS);
             gd.rho_nchunk = (int32_t)((nv + SGW_RHO_CHUNK - 1) / SGW_RHO_CHUNK);
             p->nrho_items += (int64_t)gd.rho_cb * gd.rho_nchunk;
+            p->nrho_final += gd.rho_cb;
         }
     // the box list holds the grids that are one box first (their three stages run in one
     // launch), then the boxes of the others, grid by grid
@@ -734,9 +736,9 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     uint64_t foot = 0;
     if (pb->flux == SGW_FLUX_VLASOV_FIXED_E) foot = sizeof(double) * 2 * (uint64_t)(d / 2) * N * N;
     p->off_foot = take(foot ? foot : 8);
-    // relaxation: velocity factor tables, density, its partial sums, arrival counters, work items
+    // relaxation: velocity factor tables, density, its partial sums, work items of both passes
     p->mu_off.assign((size_t)p->G * SGW_MAX_DIM, 0);
-    uint64_t mu_elems = 0, rho_elems = 0, part_elems = 0, cnt_elems = 0;
+    uint64_t mu_elems = 0, rho_elems = 0, part_elems = 0;
     if (relax)
         for (int g = 0; g < p->G; g++) {
             const GridDev& gd = p->grids[g];
@@ -746,13 +748,11 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
             }
             rho_elems += (uint64_t)gd.nxr;
             part_elems += (uint64_t)gd.nxr * (uint64_t)gd.rho_nchunk;
-            cnt_elems += (uint64_t)gd.rho_cb;
         }
     p->off_mu = take(sizeof(double) * (mu_elems ? mu_elems : 1));
     p->off_rho = take(sizeof(double) * (rho_elems ? rho_elems : 1));
     p->off_rho_part = take(sizeof(double) * (part_elems ? part_elems : 1));
-    p->off_rho_cnt = take(sizeof(unsigned int) * (cnt_elems ? cnt_elems : 1));
-    p->off_rho_items = take(sizeof(RhoItem) * (p->nrho_items ? p->nrho_items : 1));
+    p->off_rho_items = take(sizeof(RhoItem) * (p->nrho_items + p->nrho_final + 1));
     p->scratch_bytes = off;
     *out = p;
     return SGW_OK;
@@ -888,8 +888,7 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
         double* mu_base = (double*)(s->scratch + p->off_mu);
         double* rho_base = (double*)(s->scratch + p->off_rho);
         double* part_base = (double*)(s->scratch + p->off_rho_part);
-        unsigned int* cnt_base = (unsigned int*)(s->scratch + p->off_rho_cnt);
-        int64_t rho_off = 0, part_off = 0, cnt_off = 0;
+        int64_t rho_off = 0, part_off = 0;
         for (int g = 0; g < p->G; g++) {
             GridDev& gd = s->grids_h[g];
             gd.inv_tau = 1.0 / p->pb.relax_tau;
@@ -906,13 +905,14 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
             }
             gd.rho = rho_base + rho_off;
             gd.rho_part = part_base + part_off;
-            gd.rho_cnt = cnt_base + cnt_off;
             rho_off += gd.nxr;
             part_off += (int64_t)gd.nxr * gd.rho_nchunk;
-            cnt_off += gd.rho_cb;
             for (int c = 0; c < gd.rho_nchunk; c++)
                 for (int b = 0; b < gd.rho_cb; b++) rho_items_h.push_back(RhoItem{s->grids_d + g, b, c});
         }
+        // second pass: one item per (grid, column block), after the first pass's
+        for (int g = 0; g < p->G; g++)
+            for (int b = 0; b < s->grids_h[g].rho_cb; b++) rho_items_h.push_back(RhoItem{s->grids_d + g, b, 0});
     }
     // time-step record
     std::memset(&s->req_h, 0, sizeof(ReqDev));
@@ -1033,13 +1033,6 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
     if (p->relax) {
         cp(s->scratch + p->off_mu, mu_h.data(), sizeof(double) * mu_h.size());
         cp(s->rho_items_d, rho_items_h.data(), sizeof(RhoItem) * rho_items_h.size());
-        if (rc == SGW_OK) {
-            // arrival counters start at zero; the last workgroup of each block resets its own
-            size_t cnt = 0;
-            for (int g = 0; g < p->G; g++) cnt += (size_t)s->grids_h[g].rho_cb;
-            hipError_t e = hipMemsetAsync(s->scratch + p->off_rho_cnt, 0, sizeof(unsigned int) * cnt, st);
-            if (e != hipSuccess) rc = sgw_hip_fail(e, "density counters");
-        }
     }
     if (rc == SGW_OK && (p->pb.flux == SGW_FLUX_VLASOV_FIXED_E || p->pb.flux == SGW_FLUX_VLASOV_HARMONIC)) {
         hipError_t e = launch_coef_init(s->grids_d, s->grids_h.data(), p->G, s->coef_d, s->coef_off_d, &p->pb, st);
@@ -1191,7 +1184,7 @@ static hipError_t enqueue_step(sgw_solver* s, int mode, hipStream_t st)
     if (mode == SGW_RUN_PLAIN) {
         for (int stage = 0; stage < 3; stage++) {
             if (nrho) {
-                e = launch_rho(s->rho_items_d, nrho, stage, p->cfg.precision, st);
+                e = launch_rho(s->rho_items_d, nrho, (int)p->nrho_final, stage, p->cfg.precision, st);
                 if (e != hipSuccess) return e;
             }
             for (int g = 0; g < p->G; g++) {
@@ -1211,7 +1204,7 @@ static hipError_t enqueue_step(sgw_solver* s, int mode, hipStream_t st)
     }
     for (int stage = 0; stage < 3 && nbx; stage++) {
         if (nrho) {
-            e = launch_rho(s->rho_items_d, nrho, stage, p->cfg.precision, st);
+            e = launch_rho(s->rho_items_d, nrho, (int)p->nrho_final, stage, p->cfg.precision, st);
             if (e != hipSuccess) return e;
         }
         e = launch_stage(s->items_d + nw, nbx, stage, p->cfg.precision, p->pb.dim, p->lds_boxed, s->grid, st,

@@ -12,26 +12,26 @@ typedef const SGW_CONST GridDev* GridC;
 
 namespace {
 
-// rho(x) = h_v * (sum over the velocity nodes of the grid) of the stage input.  The grid is an
-// nvr x nxr matrix with the x nodes fastest.  Workgroup (grid, column block cb, chunk c) sums
-// rows c * SGW_RHO_CHUNK .. + SGW_RHO_CHUNK of SGW_RHO_COLS columns: lane (col, r) takes rows
-// r, r + L, r + 2L, ... (L row lanes) in FP64, the L row lanes are added in order through LDS
-// and the block's sums go to rho_part[c][x].  The last workgroup of a column block to arrive
-// (an arrival counter) adds the chunks in order, scales by h_v, writes rho and resets the
-// counter.  Every sum runs in a fixed order, so rho is bitwise repeatable.
+// rho(x) = h_v * (sum over the velocity nodes of the grid) of the stage input, in two launches
+// (the launch boundary orders the passes; no fences or counters).  The grid is an nvr x nxr
+// matrix with the x nodes fastest.
+//
+// First pass: workgroup (grid, column block cb, chunk c) sums rows c * SGW_RHO_CHUNK ..
+// + SGW_RHO_CHUNK of SGW_RHO_COLS columns: lane (col, r) takes rows r, r + L, r + 2L, ... (L row
+// lanes) in FP64, the L row lanes are added in order through LDS and the block's sums go to
+// rho_part[c][x].
 template <typename Real>
-__global__ void __launch_bounds__(SGW_BLOCK) rho_kernel(const RhoItem* __restrict__ items, int stage)
+__global__ void __launch_bounds__(SGW_BLOCK) rho_partial_kernel(const RhoItem* __restrict__ items, int stage)
 {
     constexpr int L = SGW_BLOCK / SGW_RHO_COLS;
     __shared__ double part[SGW_BLOCK];
-    __shared__ int last;
     const SGW_CONST RhoItem* it = (const SGW_CONST RhoItem*)items + blockIdx.x;
     GridC g = (GridC)it->g;
     if (((const SGW_CONST ReqDev*)g->req)->done) return;
     const Real* __restrict__ in = (const Real*)(stage == 0 ? g->u : stage == 1 ? g->a : g->b);
-    const int nx = g->nxr, nv = g->nvr, cb = it->cb, chunk = it->chunk;
+    const int nx = g->nxr, nv = g->nvr, chunk = it->chunk;
     const int col = threadIdx.x % SGW_RHO_COLS, lane = threadIdx.x / SGW_RHO_COLS;
-    const int x = cb * SGW_RHO_COLS + col;
+    const int x = it->cb * SGW_RHO_COLS + col;
     const int r0 = chunk * SGW_RHO_CHUNK + lane;
     double sum = 0.0;
     if (x < nx) {
@@ -43,30 +43,39 @@ __global__ void __launch_bounds__(SGW_BLOCK) rho_kernel(const RhoItem* __restric
     }
     part[threadIdx.x] = sum;
     __syncthreads();
-    double* __restrict__ rp = g->rho_part;
     if (lane == 0 && x < nx) {
         double s = part[col];
 #pragma unroll
         for (int l = 1; l < L; l++) s += part[col + l * SGW_RHO_COLS];
-        rp[(int64_t)chunk * nx + x] = s;
+        g->rho_part[(int64_t)chunk * nx + x] = s;
     }
-    // the partial sums are visible device-wide before this workgroup counts itself in
-    __threadfence();
+}
+
+// Second pass: workgroup (grid, column block cb) adds the chunks of its SGW_RHO_COLS columns:
+// row lane l takes chunks l, l + L, ... in order, the lanes are added in order, the sum is
+// scaled by h_v.  Every sum runs in a fixed order, so rho is bitwise repeatable.
+__global__ void __launch_bounds__(SGW_BLOCK) rho_final_kernel(const RhoItem* __restrict__ items)
+{
+    constexpr int L = SGW_BLOCK / SGW_RHO_COLS;
+    __shared__ double part[SGW_BLOCK];
+    const SGW_CONST RhoItem* it = (const SGW_CONST RhoItem*)items + blockIdx.x;
+    GridC g = (GridC)it->g;
+    if (((const SGW_CONST ReqDev*)g->req)->done) return;
+    const int nx = g->nxr, nch = g->rho_nchunk;
+    const int col = threadIdx.x % SGW_RHO_COLS, lane = threadIdx.x / SGW_RHO_COLS;
+    const int x = it->cb * SGW_RHO_COLS + col;
+    const double* __restrict__ rp = g->rho_part;
+    double sum = 0.0;
+    if (x < nx)
+        for (int c = lane; c < nch; c += L) sum += rp[(int64_t)c * nx + x];
+    part[threadIdx.x] = sum;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned int prev = atomicAdd(g->rho_cnt + cb, 1u);
-        last = prev == (unsigned int)(g->rho_nchunk - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
     if (lane == 0 && x < nx) {
-        double s = 0.0;
-        for (int c = 0; c < g->rho_nchunk; c++)
-            s += __hip_atomic_load(rp + (int64_t)c * nx + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        double s = part[col];
+#pragma unroll
+        for (int l = 1; l < L; l++) s += part[col + l * SGW_RHO_COLS];
         g->rho[x] = s * g->hv;
     }
-    if (threadIdx.x == 0) g->rho_cnt[cb] = 0u;
 }
 
 struct EntArgs {
@@ -141,13 +150,16 @@ __global__ void __launch_bounds__(SGW_BLOCK) entropies_final_kernel(const double
 
 } // namespace
 
-hipError_t launch_rho(const RhoItem* items, int nitems, int stage, int precision, hipStream_t s)
+hipError_t launch_rho(const RhoItem* items, int npartial, int nfinal, int stage, int precision, hipStream_t s)
 {
-    if (nitems <= 0) return hipSuccess;
+    if (npartial <= 0) return hipSuccess;
     if (precision == SGW_FP64)
-        hipLaunchKernelGGL(rho_kernel<double>, dim3(nitems), dim3(SGW_BLOCK), 0, s, items, stage);
+        hipLaunchKernelGGL(rho_partial_kernel<double>, dim3(npartial), dim3(SGW_BLOCK), 0, s, items, stage);
     else
-        hipLaunchKernelGGL(rho_kernel<float>, dim3(nitems), dim3(SGW_BLOCK), 0, s, items, stage);
+        hipLaunchKernelGGL(rho_partial_kernel<float>, dim3(npartial), dim3(SGW_BLOCK), 0, s, items, stage);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(rho_final_kernel, dim3(nfinal), dim3(SGW_BLOCK), 0, s, items + npartial);
     return hipGetLastError();
 }
 

@@ -30,14 +30,15 @@ struct sgw_plan {
                                                // boundary or relaxation
     bool relax = false;                        // relaxation source on
     int zmask = 0;                             // bit k: zero boundary in direction k
-    int64_t nrho_items = 0;                    // density work items over all grids
+    int64_t nrho_items = 0;                    // density first-pass work items over all grids
+    int64_t nrho_final = 0;                    // density second-pass work items (column blocks)
     std::vector<int64_t> mu_off;               // [G][4] offsets into the velocity factor tables
     size_t pro_rows_max = 0;                   // its LDS row-offset table entries
     size_t pro_lds = 0;                        // LDS bytes of a prolongation workgroup
     uint64_t copy_bytes = 0, state_bytes = 0, scratch_bytes = 0;
     uint64_t off_grids = 0, off_req = 0, off_items = 0, off_alpha = 0, off_coef = 0, off_coef_off = 0;
     uint64_t off_pro = 0, off_fine = 0, off_partials = 0, off_result = 0, off_foot = 0, off_stab = 0;
-    uint64_t off_mu = 0, off_rho = 0, off_rho_part = 0, off_rho_cnt = 0, off_rho_items = 0;
+    uint64_t off_mu = 0, off_rho = 0, off_rho_part = 0, off_rho_items = 0;
 };
 
 struct sgw_solver {

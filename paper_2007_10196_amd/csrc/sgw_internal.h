@@ -145,7 +145,6 @@ struct alignas(64) GridDev {
     const double* mu[SGW_MAX_DIM];   // velocity direction k: exp(-v^2/(2 theta)) / sqrt(2 pi theta) per node
     double* rho;                     // nxr: rho(x) of the current stage input
     double* rho_part;                // rho_nchunk x nxr partial sums
-    unsigned int* rho_cnt;           // rho_cb arrival counters, zero between launches
     double inv_tau, hv;              // 1 / tau and the velocity cell volume
 };
 
@@ -155,7 +154,8 @@ struct alignas(64) GridDev {
 #define SGW_RHO_RPT 16
 #define SGW_RHO_CHUNK (SGW_RHO_RPT * (SGW_BLOCK / SGW_RHO_COLS))
 
-// One (grid, block of x nodes, chunk of velocity rows) of the density launch.
+// One (grid, block of x nodes, chunk of velocity rows) of the density's first pass, or one (grid,
+// block of x nodes) of its second (chunk unused).
 struct RhoItem {
     const GridDev* g;
     int32_t cb, chunk;
@@ -274,8 +274,9 @@ struct ExactDev {
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_coef_init(GridDev* grids_dev, const GridDev* grids_host, int G, double* coef_base,
                             const int64_t* coef_off_host, const sgw_problem* pb, hipStream_t s);
-// rho(x) of the stage input of every relaxation grid: items[0..nitems), one workgroup each
-hipError_t launch_rho(const RhoItem* items, int nitems, int stage, int precision, hipStream_t s);
+// rho(x) of the stage input of every relaxation grid: first-pass items[0..npartial), then
+// second-pass items[npartial..npartial + nfinal), one workgroup each
+hipError_t launch_rho(const RhoItem* items, int npartial, int nfinal, int stage, int precision, hipStream_t s);
 // H_2 and H_log of a finest-grid solution: partial sums in partials, the two values in result
 hipError_t launch_entropies(const FineDev& f, const double* lo, const double* hi, double theta, double zx,
                             const double* fsol, double* partials, double* result, hipStream_t s);
