@@ -75,6 +75,14 @@ def lib():
         L.orc_max_threads.restype = C.c_int
         L.orc_entropies.argtypes = [C.POINTER(_Problem), C.POINTER(_Config), _dp, C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]
+        L.orc_evolve_fields.argtypes = [C.POINTER(_Problem), C.POINTER(_Config), C.c_double, _dp, C.c_void_p,
+                                        C.c_void_p, C.POINTER(_Stats)]
+        L.orc_evolve_fields.restype = C.c_int
+        L.orc_total_fields.argtypes = [C.POINTER(_Problem), C.POINTER(_Config)]
+        L.orc_total_fields.restype = C.c_int64
+        L.orc_fields_init.argtypes = [C.POINTER(_Problem), C.POINTER(_Config), _dp]
+        L.orc_fields_combine.argtypes = [C.POINTER(_Problem), C.POINTER(_Config), _dp, _dp]
+        L.orc_rhs_vm.argtypes = [C.POINTER(_Problem), C.POINTER(_Config), _ip, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -176,18 +184,70 @@ def rhs(pb, level, u: np.ndarray) -> np.ndarray:
     return L
 
 
-def evolve(pb, state: np.ndarray, T: Optional[float] = None, mask=None, nthreads: int = 0):
-    """Alg. Step 2 in place on ``state``; returns a stats dict."""
+def evolve(pb, state: np.ndarray, T: Optional[float] = None, mask=None, nthreads: int = 0,
+           fields: Optional[np.ndarray] = None):
+    """Alg. Step 2 in place on ``state`` (and, for the Vlasov-Maxwell system, on ``fields``, the
+    grids' B_3, E_1, E_2 back to back); returns a stats dict."""
     p, c = _structs(pb, nthreads)
     st = _Stats()
     mptr = None
     if mask is not None:
         m = np.ascontiguousarray(mask, dtype=np.uint8)
         mptr = m.ctypes.data_as(C.c_void_p)
-    rc = lib().orc_evolve(C.byref(p), C.byref(c), pb.T if T is None else T, state, mptr, C.byref(st))
+    fptr = None
+    if fields is not None:
+        assert fields.dtype == np.float64 and fields.flags.c_contiguous and fields.size == total_fields(pb)
+        fptr = fields.ctypes.data_as(C.c_void_p)
+    rc = lib().orc_evolve_fields(C.byref(p), C.byref(c), pb.T if T is None else T, state, fptr, mptr,
+                                 C.byref(st))
+    if rc == -5:
+        raise ValueError("oracle: the Vlasov-Maxwell system needs dim 3 and its fields")
     if rc != 0:
         raise FloatingPointError("oracle: non-finite wave speed")
     return {"steps": st.steps, "t": st.t, "last_dt": st.last_dt, "min_dt": st.min_dt, "max_dt": st.max_dt}
+
+
+def total_fields(pb) -> int:
+    """Field values over all component grids: 3 n_1 per grid (Vlasov-Maxwell), else 0."""
+    p, c = _structs(pb)
+    return int(lib().orc_total_fields(C.byref(p), C.byref(c)))
+
+
+def fields_init(pb) -> np.ndarray:
+    """Initial fields of every grid (B_3 = b sin(k0 x_2), E = 0), grids back to back."""
+    p, c = _structs(pb)
+    out = np.zeros(total_fields(pb))
+    lib().orc_fields_init(C.byref(p), C.byref(c), out)
+    return out
+
+
+def fields_combine(pb, fields: np.ndarray) -> np.ndarray:
+    """(3, N) array: B_3, E_1, E_2 combined on the finest x_2 grid."""
+    p, c = _structs(pb)
+    out = np.zeros(3 * pb.n_fine)
+    lib().orc_fields_combine(C.byref(p), C.byref(c), np.ascontiguousarray(fields, dtype=np.float64), out)
+    return out.reshape(3, pb.n_fine)
+
+
+def rhs_vm(pb, level, u: np.ndarray, fld: np.ndarray):
+    """Spatial operators of f and of the fields of one Vlasov-Maxwell component grid."""
+    p, c = _structs(pb)
+    lv = np.array(_pad([int(x) for x in level], 4, 0), dtype=np.int32)
+    u = np.ascontiguousarray(u, dtype=np.float64).ravel()
+    fld = np.ascontiguousarray(fld, dtype=np.float64).ravel()
+    L = np.zeros_like(u)
+    Lf = np.zeros_like(fld)
+    lib().orc_rhs_vm(C.byref(p), C.byref(c), lv, u, fld, L, Lf)
+    return L, Lf
+
+
+def solve_vm(pb, nthreads: int = 0):
+    """Vlasov-Maxwell: restrict, initial fields, march, combine.  Returns (U_hat, state, fields,
+    combined fields (3, N), stats)."""
+    st = restrict(pb)
+    fl = fields_init(pb)
+    stats = evolve(pb, st, nthreads=nthreads, fields=fl)
+    return prolong_combine(pb, st), st, fl, fields_combine(pb, fl), stats
 
 
 def prolong(pb, level, u: np.ndarray) -> np.ndarray:

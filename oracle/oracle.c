@@ -28,6 +28,11 @@
  *                                    Maxwellian mu_inf and the density rho = int f dv, zero
  *                                    boundary conditions, and the entropy functionals H_2, H_log
  *                                    relative to the stationary state M(x, v)
+ *   - Sec. 3.4, Example 6          : the 3D Vlasov-Maxwell system in (x_2, xi_1, xi_2): transport
+ *                                    with the Lorentz force (E_1 + xi_2 B_3, E_2 - xi_1 B_3), the
+ *                                    field equations B_3' = dE_1/dx_2, E_1' = dB_3/dx_2 - j_1,
+ *                                    E_2' = -j_2, the currents j = int f xi dxi, and the initial
+ *                                    condition (two drifting Maxwellians in xi_1, B_3 = b sin(k_0 x_2))
  *
  * Readings of points the paper leaves open (all of them listed in the design
  * notes of the repository):
@@ -51,7 +56,15 @@
  *   - the density rho(x) = int f dv is the sum over the velocity nodes of the grid times the
  *     velocity cell volume; the relaxation source is added to the spatial operator of every
  *     Runge-Kutta stage, with rho taken from the stage input;
- *   - the entropy H log H is taken as 0 where f <= 0.
+ *   - the entropy H log H is taken as 0 where f <= 0;
+ *   - Vlasov-Maxwell: every component grid carries its own fields E_1, E_2, B_3 on its x_2 nodes,
+ *     driven by its own currents, and is marched as one coupled system (Alg. Step 2 applied to the
+ *     whole system); the currents are sums over the grid's velocity nodes times the velocity cell
+ *     area; the field equations B_3' = dE_1/dx_2, E_1' = dB_3/dx_2 - j_1 are discretised by the same
+ *     WENO5 with global LF splitting, F(B_3, E_1) = (-E_1, -B_3) and alpha = 1 (the system's
+ *     characteristic speeds are +-1), each component reconstructed on its own; fields and f take
+ *     the same TVD-RK3 stages; the LF speeds of f in xi_1, xi_2 are the maxima over the grid's nodes
+ *     of |E_1 + xi_2 B_3| and |E_2 - xi_1 B_3| of the stage's fields.
  *
  * Compiled with -O2 -ffp-contract=off (no fused multiply-add, no fast math).
  */
@@ -67,9 +80,15 @@
 
 /* flux families of eq. (1) used by the examples of Sec. 3; VLASOV_HARMONIC is the transport of
    Example 5 with E = -x */
-enum { ORC_FLUX_ADVECTION = 0, ORC_FLUX_BURGERS = 1, ORC_FLUX_VLASOV = 2, ORC_FLUX_VLASOV_HARMONIC = 3 };
+enum {
+    ORC_FLUX_ADVECTION = 0,
+    ORC_FLUX_BURGERS = 1,
+    ORC_FLUX_VLASOV = 2,
+    ORC_FLUX_VLASOV_HARMONIC = 3,
+    ORC_FLUX_VLASOV_MAXWELL = 4 /* Example 6: d = 3, directions x_2, xi_1, xi_2 */
+};
 /* initial conditions */
-enum { ORC_IC_SINE = 0, ORC_IC_MAXWELL_COS = 1, ORC_IC_VB = 2 };
+enum { ORC_IC_SINE = 0, ORC_IC_MAXWELL_COS = 1, ORC_IC_VB = 2, ORC_IC_VM = 3 };
 enum { ORC_BC_PERIODIC = 0, ORC_BC_ZERO = 1 };
 enum { ORC_DT_CFL = 0, ORC_DT_POW53 = 1 };
 enum { ORC_PROLONG_WENO5 = 0, ORC_PROLONG_LAGRANGE5 = 1 };
@@ -87,7 +106,10 @@ typedef struct {
     /* sine:        u0 = ip[0] + ip[1] * sin(ip[2] * sum_k x_k + ip[3])
        maxwell_cos: f0 = M(v) * (1 + ip[0] * prod_k cos(ip[1] * x_k + ip[2+k]))
        vb:          f0 = ip[0] * sin(x_1^2/2)^2 [* cos(x_2^2/2)^2] * exp(-(|x|^2 + |v|^2)/2),
-                    ip[0] = 1/s, the normalisation of Example 5 */
+                    ip[0] = 1/s, the normalisation of Example 5
+       vm:          f0 = exp(-xi_2^2/beta) (delta exp(-(xi_1 - v01)^2/beta)
+                         + (1 - delta) exp(-(xi_1 + v02)^2/beta)) / (pi beta),
+                    B_3 = b sin(k0 x_2), E = 0; ip = (beta, b, delta, v01, v02, k0) (Example 6) */
     double ip[8];
     int32_t bc[ORC_MAXD];   /* ORC_BC_* per direction */
     /* relaxation source (mu_inf(v) rho(x) - f) / tau of Example 5, off when tau <= 0; the first
@@ -267,6 +289,12 @@ static double orc_u0(const orc_problem *p, const double *x)
         for (int k = 0; k < p->d; k++) s += x[k];
         return p->ip[0] + p->ip[1] * sin(p->ip[2] * s + p->ip[3]);
     }
+    if (p->ic == ORC_IC_VM) {
+        /* Example 6: two drifting Maxwellians in xi_1 (x[1]) times a Maxwellian in xi_2 (x[2]) */
+        double be = p->ip[0], de = p->ip[2], v1 = p->ip[3], v2 = p->ip[4];
+        double a = x[1] - v1, b = x[1] + v2;
+        return exp(-x[2] * x[2] / be) * (de * exp(-a * a / be) + (1.0 - de) * exp(-b * b / be)) / (M_PI * be);
+    }
     int dx = p->d / 2;
     if (p->ic == ORC_IC_VB) {
         /* Example 5: sin(x_1^2/2)^2 (and cos(x_2^2/2)^2 in 4D) times a Gaussian in (x, v) */
@@ -398,11 +426,103 @@ static void orc_relax_add(const orc_problem *p, const orc_grid *g, const double 
     free(rho);
 }
 
-/* Spatial operator L(u) = -sum_k (F_{i+1/2} - F_{i-1/2}) / h_k, eq. (2.9), with the
-   LF-split WENO5 fluxes F = F^+ + F^- of Sec. 2.1. */
-static void orc_rhs_grid(const orc_problem *p, const orc_config *c, const orc_grid *g,
-                         const double *u, double *L)
+/* ------------------------------------------------------------------------- */
+/* Vlasov-Maxwell (Sec. 3.4, Example 6): directions x_2, xi_1, xi_2; the fields of a component
+   grid are B_3, E_1, E_2 at its x_2 nodes, back to back (3 n_1 values). */
+
+/* Coefficient c of the flux c f in direction k at node j of grid g (the Lorentz force) */
+static double orc_vm_coef(const orc_problem *p, const orc_grid *g, const double *fld, int k, const int *j)
 {
+    int n0 = g->n[0];
+    const double *B3 = fld, *E1 = fld + n0, *E2 = fld + 2 * n0;
+    double xi1 = orc_coord(p, 1, j[1], g->n[1]);
+    double xi2 = orc_coord(p, 2, j[2], g->n[2]);
+    if (k == 0) return xi2;                         /* xi_2 f_{x_2} */
+    if (k == 1) return E1[j[0]] + xi2 * B3[j[0]];   /* (E_1 + xi_2 B_3) f_{xi_1} */
+    return E2[j[0]] - xi1 * B3[j[0]];               /* (E_2 - xi_1 B_3) f_{xi_2} */
+}
+
+/* Global LF speed of direction k on grid g: max over its nodes of |c| */
+static double orc_vm_alpha(const orc_problem *p, const orc_grid *g, const double *fld, int k)
+{
+    double a = 0.0;
+    for (int64_t idx = 0; idx < g->size; idx++) {
+        int j[ORC_MAXD];
+        orc_index_to_coords(g, idx, j);
+        double cc = fabs(orc_vm_coef(p, g, fld, k, j));
+        if (cc > a || isnan(cc)) a = cc;
+    }
+    return a;
+}
+
+/* Currents j_1 = int f xi_1, j_2 = int f xi_2 at the x_2 nodes of grid g: sums over the grid's
+   velocity nodes times h_{xi_1} h_{xi_2} */
+static void orc_vm_currents(const orc_problem *p, const orc_grid *g, const double *u, double *j1, double *j2)
+{
+    int n0 = g->n[0], n1 = g->n[1], n2 = g->n[2];
+    double area = g->h[1] * g->h[2];
+    for (int i = 0; i < n0; i++) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int b = 0; b < n2; b++)
+            for (int a = 0; a < n1; a++) {
+                double f = u[i + (int64_t)n0 * (a + (int64_t)n1 * b)];
+                s1 += f * orc_coord(p, 1, a, n1);
+                s2 += f * orc_coord(p, 2, b, n2);
+            }
+        j1[i] = s1 * area;
+        j2[i] = s2 * area;
+    }
+}
+
+/* Right-hand side of the field equations of grid g: B_3' = dE_1/dx_2, E_1' = dB_3/dx_2 - j_1,
+   E_2' = -j_2, with B_3' + d(-E_1)/dx_2 = 0 and E_1' + d(-B_3)/dx_2 = -j_1 discretised by WENO5 with
+   global LF splitting (alpha = 1) of each component, as in eq. (2.9). */
+static void orc_vm_fields_rhs(const orc_problem *p, const orc_config *c, const orc_grid *g, const double *u,
+                              const double *fld, double *Lf)
+{
+    int n = g->n[0];
+    const double *B3 = fld, *E1 = fld + n;
+    double *j1 = malloc(sizeof(double) * n), *j2 = malloc(sizeof(double) * n);
+    double *pB = malloc(sizeof(double) * n), *mB = malloc(sizeof(double) * n);
+    double *pE = malloc(sizeof(double) * n), *mE = malloc(sizeof(double) * n);
+    double *FB = malloc(sizeof(double) * (n + 1)), *FE = malloc(sizeof(double) * (n + 1));
+    orc_vm_currents(p, g, u, j1, j2);
+    for (int i = 0; i < n; i++) {
+        pB[i] = 0.5 * (-E1[i] + B3[i]);
+        mB[i] = 0.5 * (-E1[i] - B3[i]);
+        pE[i] = 0.5 * (-B3[i] + E1[i]);
+        mE[i] = 0.5 * (-B3[i] - E1[i]);
+    }
+    int zero = p->bc[0] == ORC_BC_ZERO;
+    for (int i = -1; i < n; i++) {
+#define G(a, j) orc_ghost((a), (j), n, zero)
+        FB[i + 1] = orc_weno5(G(pB, i - 2), G(pB, i - 1), G(pB, i), G(pB, i + 1), G(pB, i + 2), c->eps_flux, c->linear) +
+                    orc_weno5(G(mB, i + 3), G(mB, i + 2), G(mB, i + 1), G(mB, i), G(mB, i - 1), c->eps_flux, c->linear);
+        FE[i + 1] = orc_weno5(G(pE, i - 2), G(pE, i - 1), G(pE, i), G(pE, i + 1), G(pE, i + 2), c->eps_flux, c->linear) +
+                    orc_weno5(G(mE, i + 3), G(mE, i + 2), G(mE, i + 1), G(mE, i), G(mE, i - 1), c->eps_flux, c->linear);
+#undef G
+    }
+    for (int i = 0; i < n; i++) {
+        Lf[i] = -(FB[i + 1] - FB[i]) / g->h[0];
+        Lf[n + i] = -(FE[i + 1] - FE[i]) / g->h[0] - j1[i];
+        Lf[2 * n + i] = -j2[i];
+    }
+    free(j1);
+    free(j2);
+    free(pB);
+    free(mB);
+    free(pE);
+    free(mE);
+    free(FB);
+    free(FE);
+}
+
+/* Spatial operator L(u) = -sum_k (F_{i+1/2} - F_{i-1/2}) / h_k, eq. (2.9), with the
+   LF-split WENO5 fluxes F = F^+ + F^- of Sec. 2.1.  fld: the grid's fields (Vlasov-Maxwell only). */
+static void orc_rhs_grid(const orc_problem *p, const orc_config *c, const orc_grid *g,
+                         const double *u, const double *fld, double *L)
+{
+    const int vm = p->flux == ORC_FLUX_VLASOV_MAXWELL;
     for (int64_t i = 0; i < g->size; i++) L[i] = 0.0;
     int nmax = 0;
     for (int k = 0; k < g->d; k++)
@@ -413,7 +533,7 @@ static void orc_rhs_grid(const orc_problem *p, const orc_config *c, const orc_gr
     for (int k = 0; k < g->d; k++) {
         int n = g->n[k];
         int64_t st = g->stride[k];
-        double alpha = orc_alpha(p, g, u, k);
+        double alpha = vm ? orc_vm_alpha(p, g, fld, k) : orc_alpha(p, g, u, k);
         /* every line along direction k starts at a node with j_k = 0 */
         for (int64_t base = 0; base < g->size; base++) {
             int jb[ORC_MAXD];
@@ -425,7 +545,13 @@ static void orc_rhs_grid(const orc_problem *p, const orc_config *c, const orc_gr
                 for (int kk = 0; kk < g->d; kk++)
                     x[kk] = orc_coord(p, kk, kk == k ? i : jb[kk], g->n[kk]);
                 double f, fp;
-                orc_flux(p, k, u[idx], x, &f, &fp);
+                if (vm) {
+                    int jn[ORC_MAXD];
+                    for (int kk = 0; kk < ORC_MAXD; kk++) jn[kk] = kk == k ? i : jb[kk];
+                    f = orc_vm_coef(p, g, fld, k, jn) * u[idx];
+                } else {
+                    orc_flux(p, k, u[idx], x, &f, &fp);
+                }
                 pl[i] = 0.5 * (f + alpha * u[idx]); /* f^+ */
                 mi[i] = 0.5 * (f - alpha * u[idx]); /* f^- */
             }
@@ -573,30 +699,75 @@ void orc_rhs(const orc_problem *p, const orc_config *c, const int *level, const 
 {
     orc_grid g;
     orc_grid_make(p, c->nr, level, &g);
-    orc_rhs_grid(p, c, &g, u, L);
+    orc_rhs_grid(p, c, &g, u, NULL, L);
+}
+
+/* Spatial operators of f and of the fields of one Vlasov-Maxwell component grid (for the tests). */
+void orc_rhs_vm(const orc_problem *p, const orc_config *c, const int *level, const double *u, const double *fld,
+                double *L, double *Lf)
+{
+    orc_grid g;
+    orc_grid_make(p, c->nr, level, &g);
+    orc_rhs_grid(p, c, &g, u, fld, L);
+    orc_vm_fields_rhs(p, c, &g, u, fld, Lf);
 }
 
 static void orc_rk3_step(const orc_problem *p, const orc_config *c, const orc_grid *g, double *u, double dt,
                          double *u1, double *u2, double *L)
 {
     int64_t n = g->size;
-    orc_rhs_grid(p, c, g, u, L);
+    orc_rhs_grid(p, c, g, u, NULL, L);
     for (int64_t i = 0; i < n; i++) u1[i] = u[i] + dt * L[i];
-    orc_rhs_grid(p, c, g, u1, L);
+    orc_rhs_grid(p, c, g, u1, NULL, L);
     for (int64_t i = 0; i < n; i++) u2[i] = 0.75 * u[i] + 0.25 * (u1[i] + dt * L[i]);
-    orc_rhs_grid(p, c, g, u2, L);
+    orc_rhs_grid(p, c, g, u2, NULL, L);
     for (int64_t i = 0; i < n; i++) u[i] = u[i] / 3.0 + 2.0 / 3.0 * (u2[i] + dt * L[i]);
+}
+
+/* The same stages for a Vlasov-Maxwell grid: f and its fields fld advance together, each stage's
+   operators taken from that stage's f and fields. */
+static void orc_rk3_step_vm(const orc_problem *p, const orc_config *c, const orc_grid *g, double *u, double *fld,
+                            double dt)
+{
+    int64_t n = g->size;
+    int nf = 3 * g->n[0];
+    double *u1 = malloc(sizeof(double) * n), *u2 = malloc(sizeof(double) * n), *L = malloc(sizeof(double) * n);
+    double *f1 = malloc(sizeof(double) * nf), *f2 = malloc(sizeof(double) * nf), *Lf = malloc(sizeof(double) * nf);
+    orc_rhs_grid(p, c, g, u, fld, L);
+    orc_vm_fields_rhs(p, c, g, u, fld, Lf);
+    for (int64_t i = 0; i < n; i++) u1[i] = u[i] + dt * L[i];
+    for (int i = 0; i < nf; i++) f1[i] = fld[i] + dt * Lf[i];
+    orc_rhs_grid(p, c, g, u1, f1, L);
+    orc_vm_fields_rhs(p, c, g, u1, f1, Lf);
+    for (int64_t i = 0; i < n; i++) u2[i] = 0.75 * u[i] + 0.25 * (u1[i] + dt * L[i]);
+    for (int i = 0; i < nf; i++) f2[i] = 0.75 * fld[i] + 0.25 * (f1[i] + dt * Lf[i]);
+    orc_rhs_grid(p, c, g, u2, f2, L);
+    orc_vm_fields_rhs(p, c, g, u2, f2, Lf);
+    for (int64_t i = 0; i < n; i++) u[i] = u[i] / 3.0 + 2.0 / 3.0 * (u2[i] + dt * L[i]);
+    for (int i = 0; i < nf; i++) fld[i] = fld[i] / 3.0 + 2.0 / 3.0 * (f2[i] + dt * Lf[i]);
+    free(u1);
+    free(u2);
+    free(L);
+    free(f1);
+    free(f2);
+    free(Lf);
 }
 
 /* Alg. Step 2: march every component grid (mask[g] != 0, or all when mask is NULL)
    from t = 0 to T with one shared dt per step (Sec. 3 intro).  In CFL mode the
    wave speed is taken over the masked grids only; a mask is therefore only
    meaningful for problems whose wave speed does not depend on the state. */
-int orc_evolve(const orc_problem *p, const orc_config *c, double T, double *state, const unsigned char *mask,
-               orc_stats *st)
+int orc_evolve_fields(const orc_problem *p, const orc_config *c, double T, double *state, double *fields,
+                      const unsigned char *mask, orc_stats *st)
 {
+    const int vm = p->flux == ORC_FLUX_VLASOV_MAXWELL;
+    if (vm && (!fields || p->d != 3)) return -5;
     orc_set s;
     orc_set_make(p, c, &s);
+    /* field offsets: 3 n_1 values per grid, grids back to back */
+    int64_t *fo = malloc(sizeof(int64_t) * (s.G + 1));
+    fo[0] = 0;
+    for (int g = 0; g < s.G; g++) fo[g + 1] = fo[g] + 3 * (int64_t)s.grids[g].n[0];
     double hfin[ORC_MAXD];
     int nfin = c->nr << c->nl;
     double hmin = INFINITY;
@@ -622,13 +793,15 @@ int orc_evolve(const orc_problem *p, const orc_config *c, double T, double *stat
                 double A = 0.0;
                 for (int g = 0; g < s.G; g++) {
                     if (mask && !mask[g]) continue;
-                    double a = orc_alpha(p, &s.grids[g], state + s.offsets[g], k);
+                    double a = vm ? orc_vm_alpha(p, &s.grids[g], fields + fo[g], k)
+                                  : orc_alpha(p, &s.grids[g], state + s.offsets[g], k);
                     if (a > A || isnan(a)) A = a;
                 }
                 denom += A / hfin[k];
             }
             if (isnan(denom)) {
                 orc_set_free(&s);
+                free(fo);
                 return -4;
             }
             dt = denom > 0.0 ? c->cfl / denom : T - t;
@@ -638,6 +811,10 @@ int orc_evolve(const orc_problem *p, const orc_config *c, double T, double *stat
 #pragma omp parallel for schedule(dynamic, 1)
         for (int g = 0; g < G; g++) {
             if (mask && !mask[g]) continue;
+            if (vm) {
+                orc_rk3_step_vm(p, c, &s.grids[g], state + s.offsets[g], fields + fo[g], dt);
+                continue;
+            }
             int64_t n = s.grids[g].size;
             double *buf = malloc(sizeof(double) * 3 * n);
             orc_rk3_step(p, c, &s.grids[g], state + s.offsets[g], dt, buf, buf + n, buf + 2 * n);
@@ -657,10 +834,79 @@ int orc_evolve(const orc_problem *p, const orc_config *c, double T, double *stat
         st->max_dt = maxdt;
     }
     orc_set_free(&s);
+    free(fo);
 #ifdef _OPENMP
     omp_set_num_threads(prev_threads);
 #endif
     return 0;
+}
+
+int orc_evolve(const orc_problem *p, const orc_config *c, double T, double *state, const unsigned char *mask,
+               orc_stats *st)
+{
+    return orc_evolve_fields(p, c, T, state, NULL, mask, st);
+}
+
+/* Number of field values over all component grids (3 n_1 per grid; 0 unless Vlasov-Maxwell). */
+int64_t orc_total_fields(const orc_problem *p, const orc_config *c)
+{
+    if (p->flux != ORC_FLUX_VLASOV_MAXWELL) return 0;
+    orc_set s;
+    orc_set_make(p, c, &s);
+    int64_t n = 0;
+    for (int g = 0; g < s.G; g++) n += 3 * (int64_t)s.grids[g].n[0];
+    orc_set_free(&s);
+    return n;
+}
+
+/* Initial fields of Example 6 on every grid: B_3 = b sin(k0 x_2), E_1 = E_2 = 0. */
+void orc_fields_init(const orc_problem *p, const orc_config *c, double *fields)
+{
+    orc_set s;
+    orc_set_make(p, c, &s);
+    int64_t o = 0;
+    for (int g = 0; g < s.G; g++) {
+        int n = s.grids[g].n[0];
+        for (int i = 0; i < n; i++) {
+            fields[o + i] = p->ip[1] * sin(p->ip[5] * orc_coord(p, 0, i, n));
+            fields[o + n + i] = 0.0;
+            fields[o + 2 * n + i] = 0.0;
+        }
+        o += 3 * n;
+    }
+    orc_set_free(&s);
+}
+
+/* Combination of the fields on the finest x_2 grid: out[q N + J] = sum_g c_g (P f_{g,q})(J) for
+   q = B_3, E_1, E_2, with P the one-dimensional prolongation of Sec. 2.2.1 along x_2. */
+void orc_fields_combine(const orc_problem *p, const orc_config *c, const double *fields, double *out)
+{
+    orc_set s;
+    orc_set_make(p, c, &s);
+    int N = c->nr << c->nl;
+    for (int64_t i = 0; i < 3 * (int64_t)N; i++) out[i] = 0.0;
+    double *a = malloc(sizeof(double) * N), *b = malloc(sizeof(double) * N);
+    int64_t o = 0;
+    for (int g = 0; g < s.G; g++) {
+        int n0 = s.grids[g].n[0];
+        int m = c->nl - s.levels[g * ORC_MAXD];
+        for (int q = 0; q < 3; q++) {
+            const double *src = fields + o + (int64_t)q * n0;
+            if (m == 0) {
+                memcpy(a, src, sizeof(double) * N);
+            } else {
+                int n[ORC_MAXD] = {n0, 1, 1, 1};
+                memcpy(b, src, sizeof(double) * n0);
+                orc_refine_dim(n, 0, 1 << m, b, a, c->eps_interp, c->prolong == ORC_PROLONG_LAGRANGE5,
+                               p->bc[0] == ORC_BC_ZERO);
+            }
+            for (int J = 0; J < N; J++) out[(int64_t)q * N + J] += s.coefs[g] * a[J];
+        }
+        o += 3 * n0;
+    }
+    free(a);
+    free(b);
+    orc_set_free(&s);
 }
 
 /* Prolongation of one component grid onto the finest grid, directions in

@@ -30,10 +30,12 @@ FLUX_ADVECTION = 0
 FLUX_BURGERS = 1
 FLUX_VLASOV = 2
 FLUX_VLASOV_HARMONIC = 3
+FLUX_VLASOV_MAXWELL = 4
 
 IC_SINE = 0
 IC_MAXWELL_COS = 1
 IC_VB = 2
+IC_VM = 3
 
 DT_CFL = 0
 DT_POW53 = 1
@@ -178,6 +180,16 @@ def paper_example5(d: int = 2, nr: Optional[int] = None, nl: int = 3, T: float =
                    ic=IC_VB, ic_params=(1.0 / vb_normalisation(d),), nr=nr, nl=nl, T=T, cfl=0.4,
                    precision=precision, bc=(BC_ZERO,) * d, relax_tau=1.0, relax_theta=1.0,
                    name=f"paper_example5_{d}d")
+
+
+def paper_example6(nr: int = 20, nl: int = 3, T: float = 10.0, precision: int = PREC_FP64,
+                   beta: float = 0.01, b: float = 0.001, delta: float = 0.5, v01: float = 0.3, v02: float = 0.3,
+                   k0: float = 0.2) -> Problem:
+    """Example 6 of Sec. 3.4, the 3D Vlasov-Maxwell system in (x_2, xi_1, xi_2) on
+    [0, 2 pi/k0] x [-1.2, 1.2]^2, periodic, CFL 0.4: 20^3 root grid, finest level 3 (160^3)."""
+    return Problem(d=3, lo=(0.0, -1.2, -1.2), hi=(2.0 * math.pi / k0, 1.2, 1.2), flux=FLUX_VLASOV_MAXWELL,
+                   flux_params=(), ic=IC_VM, ic_params=(beta, b, delta, v01, v02, k0), nr=nr, nl=nl, T=T,
+                   cfl=0.4, precision=precision, name="paper_example6")
 
 
 FAMILIES = {
