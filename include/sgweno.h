@@ -60,12 +60,27 @@ typedef int32_t sgw_status;
                                       E_k = flux_params[0] sin(flux_params[1] x_k)                     */
 #define SGW_FLUX_VLASOV_HARMONIC 3 /* the same transport with E = -grad |x|^2/2 = -x, the field of the
                                       Vlasov-Boltzmann model (Sec. 3.4, Example 5)                      */
+#define SGW_FLUX_VLASOV_MAXWELL 4  /* dim = 3, directions x_2, xi_1, xi_2 (Sec. 3.4, Example 6):
+                                      f_{x_2} = xi_2 f, f_{xi_1} = (E_1 + xi_2 B_3) f,
+                                      f_{xi_2} = (E_2 - xi_1 B_3) f, with fields E_1, E_2, B_3 of x_2
+                                      that every component grid carries at its x_2 nodes and advances
+                                      in the same Runge-Kutta stages: B_3' = dE_1/dx_2,
+                                      E_1' = dB_3/dx_2 - j_1, E_2' = -j_2 (WENO5 with global LF splitting,
+                                      F(B_3, E_1) = (-E_1, -B_3), alpha = 1), currents
+                                      j_q = int f xi_q dxi as sums over the grid's velocity nodes times
+                                      the velocity cell area; the LF speeds of the xi directions are
+                                      the maxima over the grid's nodes of |E_1 + xi_2 B_3| and
+                                      |E_2 - xi_1 B_3| of each stage's fields; periodic boundaries */
 
 /* Initial conditions */
 #define SGW_IC_SINE 0              /* u0 = p0 + p1 sin(p2 sum_k x_k + p3)                               */
 #define SGW_IC_MAXWELL_COS 1       /* f0 = exp(-|v|^2/2) / (2 pi)^(m/2) (1 + p0 prod_k cos(p1 x_k + p_{2+k})) */
 #define SGW_IC_VLASOV_BOLTZMANN 2  /* f0 = p0 sin(x_1^2/2)^2 [cos(x_2^2/2)^2] exp(-(|x|^2 + |v|^2)/2), m = 1
                                       [m = 2]; p0 = 1/s normalises the integral (Sec. 3.4, Example 5)   */
+#define SGW_IC_VLASOV_MAXWELL 3    /* Example 6, (p0..p5) = (beta, b, delta, v01, v02, k0):
+                                      f0 = exp(-xi_2^2/beta) (delta exp(-(xi_1 - v01)^2/beta)
+                                           + (1 - delta) exp(-(xi_1 + v02)^2/beta)) / (pi beta),
+                                      B_3 = b sin(k0 x_2), E_1 = E_2 = 0                                */
 
 #define SGW_DT_CFL 0               /* dt = cfl / sum_k (A_k / h_k^fine), A_k = max wave speed (Sec. 3) */
 #define SGW_DT_POW53 1             /* dt = (min_k h_k^fine)^(5/3), the accuracy-test rule of Sec. 3     */
@@ -145,7 +160,9 @@ typedef struct sgw_batch sgw_batch_t;
  * than 2^40 nodes, box_target outside 64..2048, blocks_per_cu outside 0..64,
  * reserved0 not 0 or an unknown boundary condition; SGW_ERR_UNSUPPORTED for a box or
  * tile that does not divide the extents or does not fit one workgroup, and for manual
- * stage boxes with a zero boundary or relaxation (those run as line sweeps).  With
+ * stage boxes with a zero boundary, relaxation or the Vlasov-Maxwell flux (those run as line
+ * sweeps), and for the Vlasov-Maxwell flux with a zero boundary.  The Vlasov-Maxwell flux needs
+ * dim 3 and its initial condition (SGW_ERR_INVALID_ARG otherwise, also with relaxation).  With
  * fine_tile 0 the prolongation tile is searched over divisors of the finest
  * extent (interpolations, staging, writes and LDS occupancy weighed). */
 sgw_status sgw_plan_create(const sgw_problem* problem, const sgw_config* config, sgw_plan_t** out);
@@ -167,11 +184,18 @@ sgw_status sgw_plan_info(const sgw_plan_t* plan, int32_t* num_grids, int64_t* to
 sgw_status sgw_plan_grid(const sgw_plan_t* plan, int32_t g, int32_t level[SGW_MAX_DIM],
                          int32_t shape[SGW_MAX_DIM], int32_t* coef, int64_t* offset);
 
+/* Vlasov-Maxwell plans: every state copy holds, after the component grids' nodes, the fields of
+ * every grid in FP64 (B_3, E_1, E_2 at its x_2 nodes, 3 n_1 values, grids in plan order), from
+ * byte offset *offset_bytes of the copy; *count = the number of field values.  Both 0 for other
+ * plans.  Copy 0 is u^n (sgw_snapshot and sgw_restore carry the fields with it). */
+sgw_status sgw_plan_fields(const sgw_plan_t* plan, uint64_t* offset_bytes, int64_t* count);
+
 /* Finest-grid tile the prolongation kernel uses (one workgroup per tile). */
 sgw_status sgw_plan_fine_tile(const sgw_plan_t* plan, int32_t tile[SGW_MAX_DIM]);
 
 /* Box extents the stage kernel uses for grid g (one workgroup per box).  4D grids
- * without manual boxes, and every grid of a plan with a zero boundary or relaxation,
+ * without manual boxes, and every grid of a plan with a zero boundary, relaxation or the
+ * Vlasov-Maxwell flux,
  * march as line sweeps (one launch per direction, a lane per segment of a grid line,
  * no boxes) and report all-zero extents. */
 sgw_status sgw_plan_grid_box(const sgw_plan_t* plan, int32_t g, int32_t box[SGW_MAX_DIM]);
@@ -211,6 +235,12 @@ sgw_status sgw_prolongate_combine(sgw_solver_t* solver, double* out_dev);
  * characteristic, classical RK4 with steps of at most 1e-3.  SGW_ERR_UNSUPPORTED
  * for the Vlasov-Boltzmann model (no closed form). */
 sgw_status sgw_exact(sgw_solver_t* solver, double t, double* out_dev);
+
+/* Vlasov-Maxwell (Sec. 3.4, Example 6): out_dev (FP64, 3 N values, N = N_r 2^N_L) = the fields
+ * B_3, E_1, E_2 of u^n combined on the finest x_2 grid, sum_g c_g P f_g with P the one-dimensional
+ * prolongation of Sec. 2.2.1 along x_2, accumulated in FP64 in grid order.  SGW_ERR_INVALID_ARG for
+ * other plans. */
+sgw_status sgw_fields_combine(sgw_solver_t* solver, double* out_dev);
 
 /* Entropy functionals of the Vlasov-Boltzmann model (Sec. 3.4, Example 5) of a
  * finest-grid solution f_dev (FP64, the layout sgw_prolongate_combine writes):

@@ -16,8 +16,8 @@ SGW_OK = 0
 ERRORS = {-1: "invalid argument", -2: "unsupported", -3: "out of memory", -4: "non-finite",
           -5: "HIP error", -6: "call out of order"}
 
-FLUX_ADVECTION, FLUX_BURGERS, FLUX_VLASOV_FIXED_E, FLUX_VLASOV_HARMONIC = 0, 1, 2, 3
-IC_SINE, IC_MAXWELL_COS, IC_VLASOV_BOLTZMANN = 0, 1, 2
+FLUX_ADVECTION, FLUX_BURGERS, FLUX_VLASOV_FIXED_E, FLUX_VLASOV_HARMONIC, FLUX_VLASOV_MAXWELL = 0, 1, 2, 3, 4
+IC_SINE, IC_MAXWELL_COS, IC_VLASOV_BOLTZMANN, IC_VLASOV_MAXWELL = 0, 1, 2, 3
 DT_CFL, DT_POW53 = 0, 1
 PROLONG_WENO5, PROLONG_LAGRANGE5 = 0, 1
 FP64, FP32_SWEEP = 0, 1
@@ -67,6 +67,8 @@ _SIGS = {
     "sgw_exact": (C.c_int32, [C.c_void_p, C.c_double, C.c_void_p]),
     "sgw_norms": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "sgw_entropies": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "sgw_fields_combine": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "sgw_plan_fields": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_int64)]),
     "sgw_query": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "sgw_set_grid": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
     "sgw_snapshot_bytes": (C.c_uint64, [C.c_void_p]),

@@ -510,8 +510,8 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.5)) return sgw_fail(SGW_ERR_INVALID_ARG, "cfl %g outside (0, 1.5]", cfg->cfl);
     if (!(cfg->eps_flux > 0.0) || !(cfg->eps_interp > 0.0))
         return sgw_fail(SGW_ERR_INVALID_ARG, "epsilon must be positive");
-    if (pb->flux < 0 || pb->flux > 3) return sgw_fail(SGW_ERR_INVALID_ARG, "unknown flux %d", pb->flux);
-    if (pb->ic < 0 || pb->ic > 2) return sgw_fail(SGW_ERR_INVALID_ARG, "unknown initial condition %d", pb->ic);
+    if (pb->flux < 0 || pb->flux > 4) return sgw_fail(SGW_ERR_INVALID_ARG, "unknown flux %d", pb->flux);
+    if (pb->ic < 0 || pb->ic > 3) return sgw_fail(SGW_ERR_INVALID_ARG, "unknown initial condition %d", pb->ic);
     if (pb->reserved0 != 0) return sgw_fail(SGW_ERR_INVALID_ARG, "reserved0 must be 0");
     int zmask = 0;
     for (int k = 0; k < d; k++) {
@@ -527,6 +527,12 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     const bool phase = pb->flux == SGW_FLUX_VLASOV_FIXED_E || pb->flux == SGW_FLUX_VLASOV_HARMONIC ||
                        pb->ic == SGW_IC_MAXWELL_COS || pb->ic == SGW_IC_VLASOV_BOLTZMANN || relax;
     if (phase && (d % 2)) return sgw_fail(SGW_ERR_INVALID_ARG, "phase-space problems need an even dim");
+    const bool vm = pb->flux == SGW_FLUX_VLASOV_MAXWELL;
+    if (vm != (pb->ic == SGW_IC_VLASOV_MAXWELL))
+        return sgw_fail(SGW_ERR_INVALID_ARG, "the Vlasov-Maxwell flux and initial condition go together");
+    if (vm && d != 3) return sgw_fail(SGW_ERR_INVALID_ARG, "the Vlasov-Maxwell system needs dim 3");
+    if (vm && relax) return sgw_fail(SGW_ERR_INVALID_ARG, "relaxation is not part of the Vlasov-Maxwell system");
+    if (vm && zmask) return sgw_fail(SGW_ERR_UNSUPPORTED, "the Vlasov-Maxwell system runs with periodic boundaries");
     if (pb->ic == SGW_IC_VLASOV_BOLTZMANN && d != 2 && d != 4)
         return sgw_fail(SGW_ERR_INVALID_ARG, "the Vlasov-Boltzmann initial condition needs dim 2 or 4");
     if (cfg->dt_mode != SGW_DT_CFL && cfg->dt_mode != SGW_DT_POW53)
@@ -594,11 +600,11 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
         tot += n;
         bool manual = false;
         for (int k = 0; k < d; k++) manual |= cfg->box[k] > 0;
-        if (manual && (zmask || relax)) {
+        if (manual && (zmask || relax || vm)) {
             delete p;
-            return sgw_fail(SGW_ERR_UNSUPPORTED, "manual stage boxes with a zero boundary or relaxation");
+            return sgw_fail(SGW_ERR_UNSUPPORTED, "manual stage boxes with a zero boundary, relaxation or fields");
         }
-        if ((d == 4 || zmask || relax) && !manual) {
+        if ((d == 4 || zmask || relax || vm) && !manual) {
             // 4D, zero boundaries and relaxation: the line sweep (no stage boxes); a work item
             // is SGW_LWAVE segments of SGW_LSEG nodes, enough items for the direction with the
             // most segments
@@ -650,18 +656,21 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     p->total_nodes = tot;
     p->zmask = zmask;
     p->relax = relax;
-    // density of the relaxation source: per grid, blocks of SGW_RHO_COLS x nodes times chunks of
-    // SGW_RHO_CHUNK velocity rows
+    p->vm = vm;
+    // velocity moments (the density of the relaxation source, the currents of the Vlasov-Maxwell
+    // system): per grid, blocks of SGW_RHO_COLS x nodes times chunks of SGW_RHO_CHUNK velocity rows
     p->nrho_items = 0;
     p->nrho_final = 0;
-    if (relax)
+    if (relax || vm)
         for (int g = 0; g < p->G; g++) {
             GridDev& gd = p->grids[g];
-            const int m = d / 2;
+            const int m = vm ? 1 : d / 2; // x directions: the first d/2, or x_2 alone
             int64_t nx = 1, nv = 1;
             for (int k = 0; k < m; k++) nx *= gd.n[k];
             for (int k = m; k < d; k++) nv *= gd.n[k];
-            gd.relax = 1;
+            gd.relax = relax ? 1 : 0;
+            gd.vm = vm ? 1 : 0;
+            gd.nmom = vm ? 2 : 1;
             gd.nxr = (int32_t)nx;
             gd.nvr = (int32_t)nv;
             gd.rho_cb = (int32_t)((nx + SGW_RHO_COLS - 1) / SGW_RHO_COLS);
@@ -703,6 +712,18 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     // byte layout
     const uint64_t rs = cfg->precision == SGW_FP64 ? 8 : 4;
     p->copy_bytes = align256((uint64_t)tot * rs);
+    // Vlasov-Maxwell: the fields of every grid (FP64, 3 n_1 values) follow the nodes in each copy
+    p->fields_total = 0;
+    p->fields_off = 0;
+    if (vm) {
+        p->fields_off = p->copy_bytes;
+        for (int g = 0; g < p->G; g++) {
+            p->grids[g].fld_bytes =
+                (int64_t)p->fields_off + 8 * p->fields_total - (int64_t)p->offsets[g] * (int64_t)rs;
+            p->fields_total += 3 * (int64_t)p->grids[g].n[0];
+        }
+        p->copy_bytes = align256(p->fields_off + 8 * (uint64_t)p->fields_total);
+    }
     p->state_bytes = 3 * p->copy_bytes;
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
@@ -724,6 +745,13 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
                 const int src = k < m ? m + k : k - m;
                 coef_elems += (uint64_t)p->grids[g].n[src];
             }
+    } else if (vm) {
+        // x_2 direction only: the coefficient xi_2 by the xi_2 node; the xi directions take theirs
+        // from the fields
+        for (int g = 0; g < p->G; g++) {
+            p->coef_off[(size_t)g * SGW_MAX_DIM] = (int64_t)coef_elems;
+            coef_elems += (uint64_t)p->grids[g].n[2];
+        }
     }
     p->off_coef = take(sizeof(double) * (coef_elems ? coef_elems : 1));
     p->off_coef_off = take(sizeof(int64_t) * p->coef_off.size());
@@ -739,20 +767,22 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     // relaxation: velocity factor tables, density, its partial sums, work items of both passes
     p->mu_off.assign((size_t)p->G * SGW_MAX_DIM, 0);
     uint64_t mu_elems = 0, rho_elems = 0, part_elems = 0;
-    if (relax)
+    if (relax || vm)
         for (int g = 0; g < p->G; g++) {
             const GridDev& gd = p->grids[g];
-            for (int k = d / 2; k < d; k++) {
-                p->mu_off[(size_t)g * SGW_MAX_DIM + k] = (int64_t)mu_elems;
-                mu_elems += (uint64_t)gd.n[k];
-            }
-            rho_elems += (uint64_t)gd.nxr;
-            part_elems += (uint64_t)gd.nxr * (uint64_t)gd.rho_nchunk;
+            if (relax)
+                for (int k = d / 2; k < d; k++) {
+                    p->mu_off[(size_t)g * SGW_MAX_DIM + k] = (int64_t)mu_elems;
+                    mu_elems += (uint64_t)gd.n[k];
+                }
+            rho_elems += (uint64_t)gd.nmom * gd.nxr;
+            part_elems += (uint64_t)gd.nmom * gd.nxr * (uint64_t)gd.rho_nchunk;
         }
     p->off_mu = take(sizeof(double) * (mu_elems ? mu_elems : 1));
     p->off_rho = take(sizeof(double) * (rho_elems ? rho_elems : 1));
     p->off_rho_part = take(sizeof(double) * (part_elems ? part_elems : 1));
     p->off_rho_items = take(sizeof(RhoItem) * (p->nrho_items + p->nrho_final + 1));
+    p->off_vm_alpha = take(sizeof(double) * 6 * (vm ? p->G : 1));
     p->scratch_bytes = off;
     *out = p;
     return SGW_OK;
@@ -876,27 +906,33 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
                 const int m = d / 2;
                 gd.coef_src[k] = k < m ? m + k : k - m;
                 gd.coef[k] = s->coef_d + p->coef_off[(size_t)g * SGW_MAX_DIM + k];
+            } else if (p->vm && k == 0) {
+                gd.coef_src[0] = 2;
+                gd.coef[0] = s->coef_d + p->coef_off[(size_t)g * SGW_MAX_DIM];
             }
         }
+        if (p->vm) gd.vm_alpha = (double*)(s->scratch + p->off_vm_alpha) + 6 * g;
     }
-    // relaxation: velocity factors, density and its partial sums per grid, work items
+    // velocity moments (relaxation: the velocity factors and the density; Vlasov-Maxwell: the
+    // currents), their partial sums per grid, work items
     std::vector<double> mu_h;
     std::vector<RhoItem> rho_items_h;
-    if (p->relax) {
+    if (p->relax || p->vm) {
         const double th = p->pb.relax_theta;
-        const double norm1 = 1.0 / std::sqrt(2.0 * M_PI * th);
+        const double norm1 = p->relax ? 1.0 / std::sqrt(2.0 * M_PI * th) : 0.0;
         double* mu_base = (double*)(s->scratch + p->off_mu);
         double* rho_base = (double*)(s->scratch + p->off_rho);
         double* part_base = (double*)(s->scratch + p->off_rho_part);
         int64_t rho_off = 0, part_off = 0;
         for (int g = 0; g < p->G; g++) {
             GridDev& gd = s->grids_h[g];
-            gd.inv_tau = 1.0 / p->pb.relax_tau;
+            gd.inv_tau = p->relax ? 1.0 / p->pb.relax_tau : 0.0;
             gd.hv = 1.0;
-            for (int k = d / 2; k < d; k++) {
+            for (int k = p->vm ? 1 : d / 2; k < d; k++) {
+                gd.hv *= gd.h[k];
+                if (!p->relax) continue;
                 const int64_t o = p->mu_off[(size_t)g * SGW_MAX_DIM + k];
                 gd.mu[k] = mu_base + o;
-                gd.hv *= gd.h[k];
                 if ((int64_t)mu_h.size() < o + gd.n[k]) mu_h.resize((size_t)(o + gd.n[k]));
                 for (int j = 0; j < gd.n[k]; j++) {
                     const double v = gd.lo[k] + j * gd.h[k];
@@ -905,8 +941,8 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
             }
             gd.rho = rho_base + rho_off;
             gd.rho_part = part_base + part_off;
-            rho_off += gd.nxr;
-            part_off += (int64_t)gd.nxr * gd.rho_nchunk;
+            rho_off += (int64_t)gd.nmom * gd.nxr;
+            part_off += (int64_t)gd.nmom * gd.nxr * gd.rho_nchunk;
             for (int c = 0; c < gd.rho_nchunk; c++)
                 for (int b = 0; b < gd.rho_cb; b++) rho_items_h.push_back(RhoItem{s->grids_d + g, b, c});
         }
@@ -924,6 +960,7 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
     s->req_h.ngrids = p->G;
     s->req_h.dyn_alpha = dyn ? 1 : 0;
     s->req_h.active = 1;
+    s->req_h.vm = p->vm ? 1 : 0;
     double hmin = INFINITY;
     for (int k = 0; k < d; k++) {
         s->req_h.hfin[k] = (p->pb.hi[k] - p->pb.lo[k]) / N;
@@ -1030,11 +1067,9 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
     cp(s->pro_d, s->pro_h.data(), sizeof(ProDev) * p->G);
     cp(s->fine_d, &s->fine_h, sizeof(FineDev));
     cp(s->scratch + p->off_stab, s->stab_h.data(), s->stab_h.size());
-    if (p->relax) {
-        cp(s->scratch + p->off_mu, mu_h.data(), sizeof(double) * mu_h.size());
-        cp(s->rho_items_d, rho_items_h.data(), sizeof(RhoItem) * rho_items_h.size());
-    }
-    if (rc == SGW_OK && (p->pb.flux == SGW_FLUX_VLASOV_FIXED_E || p->pb.flux == SGW_FLUX_VLASOV_HARMONIC)) {
+    if (p->relax) cp(s->scratch + p->off_mu, mu_h.data(), sizeof(double) * mu_h.size());
+    if (p->relax || p->vm) cp(s->rho_items_d, rho_items_h.data(), sizeof(RhoItem) * rho_items_h.size());
+    if (rc == SGW_OK && (p->pb.flux == SGW_FLUX_VLASOV_FIXED_E || p->pb.flux == SGW_FLUX_VLASOV_HARMONIC || p->vm)) {
         hipError_t e = launch_coef_init(s->grids_d, s->grids_h.data(), p->G, s->coef_d, s->coef_off_d, &p->pb, st);
         if (e != hipSuccess) rc = sgw_hip_fail(e, "coefficient tables");
         // the host mirrors the constant wave speeds to plan the number of steps
@@ -1099,6 +1134,10 @@ extern "C" sgw_status sgw_restrict_initial(sgw_solver_t* s)
     const sgw_plan* p = s->plan;
     HIPCHK(launch_fill_u64(s->alpha_d, 4 * (int64_t)p->G, 0ull, s->stream), "clear wave speeds");
     HIPCHK(launch_restrict(s->grids_d, s->grids_h.data(), p->G, p->cfg.precision, &p->pb, s->stream), "restrict");
+    if (p->vm)
+        HIPCHK(launch_vm_fields(s->grids_d, p->G, -1, p->cfg.precision, p->pb.ic_params[1], p->pb.ic_params[5],
+                                p->cfg.linear_weights, s->stream),
+               "initial fields");
     HIPCHK(launch_req_reset(s->req_d, s->stream), "reset time");
     s->restricted = true;
     s->t_host = 0.0;
@@ -1179,14 +1218,21 @@ static hipError_t enqueue_step(sgw_solver* s, int mode, hipStream_t st)
     const sgw_plan* p = s->plan;
     hipError_t e = launch_dt_one(s->req_d, st);
     if (e != hipSuccess) return e;
-    // relaxation: rho(x) of each stage's input, before the stage's line sweeps
-    const int nrho = p->relax ? (int)p->nrho_items : 0;
+    // relaxation: rho(x) of each stage's input, before the stage's line sweeps; Vlasov-Maxwell: the
+    // currents of the stage input, then the stage's field update (it writes the next stage's fields
+    // and speeds, which the sweeps of this stage do not read)
+    const int nrho = (p->relax || p->vm) ? (int)p->nrho_items : 0;
+    auto moments = [&](int stage) {
+        hipError_t r = hipSuccess;
+        if (nrho) r = launch_rho(s->rho_items_d, nrho, (int)p->nrho_final, stage, p->cfg.precision, st);
+        if (r == hipSuccess && p->vm)
+            r = launch_vm_fields(s->grids_d, p->G, stage, p->cfg.precision, 0.0, 0.0, p->cfg.linear_weights, st);
+        return r;
+    };
     if (mode == SGW_RUN_PLAIN) {
         for (int stage = 0; stage < 3; stage++) {
-            if (nrho) {
-                e = launch_rho(s->rho_items_d, nrho, (int)p->nrho_final, stage, p->cfg.precision, st);
-                if (e != hipSuccess) return e;
-            }
+            e = moments(stage);
+            if (e != hipSuccess) return e;
             for (int g = 0; g < p->G; g++) {
                 e = launch_stage(s->items_d + p->grids[g].first_item, p->grids[g].nbox, stage, p->cfg.precision,
                                  p->pb.dim, stage_lds_bytes(p->grids[g], p->cfg.precision), 0, st,
@@ -1203,10 +1249,8 @@ static hipError_t enqueue_step(sgw_solver* s, int mode, hipStream_t st)
         if (e != hipSuccess) return e;
     }
     for (int stage = 0; stage < 3 && nbx; stage++) {
-        if (nrho) {
-            e = launch_rho(s->rho_items_d, nrho, (int)p->nrho_final, stage, p->cfg.precision, st);
-            if (e != hipSuccess) return e;
-        }
+        e = moments(stage);
+        if (e != hipSuccess) return e;
         e = launch_stage(s->items_d + nw, nbx, stage, p->cfg.precision, p->pb.dim, p->lds_boxed, s->grid, st,
                          p->line_mode);
         if (e != hipSuccess) return e;
@@ -1297,7 +1341,14 @@ extern "C" sgw_status sgw_advance(sgw_solver_t* s, double t_final, int32_t mode)
         if (rc != SGW_OK) return rc;
         if (s->req_pinned->nonfinite) return sgw_fail(SGW_ERR_NONFINITE, "non-finite wave speed or time step");
         if (s->req_pinned->done) break;
-        todo = 4; // state-dependent speed: a few more steps, then look again
+        // state-dependent speeds: the steps the last dt would take to t_final (at least 4), then
+        // look again; steps past the end return at once
+        todo = 4;
+        const double dtl = s->req_pinned->dt, rem = t_final - s->req_pinned->t;
+        if (dtl > 0.0 && rem > 0.0 && rem / dtl < 1e6) {
+            const int64_t est = (int64_t)(0.9 * rem / dtl);
+            todo = est > todo ? est : todo;
+        }
     }
     return SGW_OK;
 }
@@ -1322,6 +1373,7 @@ extern "C" sgw_status sgw_exact(sgw_solver_t* s, double t, double* out_dev)
         return sgw_fail(SGW_ERR_UNSUPPORTED, "Vlasov exact solution needs the Maxwellian initial condition");
     if (p->pb.flux == SGW_FLUX_VLASOV_HARMONIC || p->pb.ic == SGW_IC_VLASOV_BOLTZMANN || p->relax || p->zmask)
         return sgw_fail(SGW_ERR_UNSUPPORTED, "no closed-form solution for the Vlasov-Boltzmann model");
+    if (p->vm) return sgw_fail(SGW_ERR_UNSUPPORTED, "no closed-form solution for the Vlasov-Maxwell system");
     ExactDev e;
     std::memset(&e, 0, sizeof(e));
     e.d = p->pb.dim;
@@ -1336,6 +1388,24 @@ extern "C" sgw_status sgw_exact(sgw_solver_t* s, double t, double* out_dev)
     for (int i = 0; i < 8; i++) e.ip[i] = p->pb.ic_params[i];
     e.t = t;
     HIPCHK(launch_exact(e, out_dev, s->foot_d, s->stream), "exact solution");
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_fields_combine(sgw_solver_t* s, double* out_dev)
+{
+    if (!s || !out_dev) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    const sgw_plan* p = s->plan;
+    if (!p->vm) return sgw_fail(SGW_ERR_INVALID_ARG, "the plan carries no fields");
+    if (!s->restricted) return sgw_fail(SGW_ERR_STATE, "fields before restrict");
+    HIPCHK(launch_fields_combine(s->grids_d, s->pro_d, s->fine_h, s->fine_d, out_dev, s->stream), "fields combine");
+    return SGW_OK;
+}
+
+extern "C" sgw_status sgw_plan_fields(const sgw_plan_t* p, uint64_t* offset_bytes, int64_t* count)
+{
+    if (!p) return sgw_fail(SGW_ERR_INVALID_ARG, "null plan");
+    if (offset_bytes) *offset_bytes = p->fields_off;
+    if (count) *count = p->fields_total;
     return SGW_OK;
 }
 
@@ -1503,6 +1573,8 @@ extern "C" sgw_status sgw_restrict_initial_many(sgw_solver_t* const* solvers, in
         if (!solvers[i]) return sgw_fail(SGW_ERR_INVALID_ARG, "null solver %d", i);
         if (solvers[i]->plan->cfg.precision != prec)
             return sgw_fail(SGW_ERR_INVALID_ARG, "solvers of one call must share their precision");
+        if (solvers[i]->plan->vm)
+            return sgw_fail(SGW_ERR_UNSUPPORTED, "Vlasov-Maxwell solvers restrict alone (sgw_restrict_initial)");
     }
     const uint64_t need = sgw_restrict_many_scratch_bytes(solvers, n);
     if (need > scratch_bytes)

@@ -308,8 +308,9 @@ static sgw_status admit_one(sgw_batch_t* b, sgw_solver_t* s, double t_final, int
     if (s->plan->pb.dim == 4 && !s->plan->line_mode)
         return sgw_fail(SGW_ERR_UNSUPPORTED, "4D solvers with manual stage boxes run alone, not in a batch");
     // the batch launches carry no density pass and run 2D/3D grids as boxes
-    if (s->plan->relax || s->plan->zmask)
-        return sgw_fail(SGW_ERR_UNSUPPORTED, "zero-boundary and relaxation solvers run alone, not in a batch");
+    if (s->plan->relax || s->plan->zmask || s->plan->vm)
+        return sgw_fail(SGW_ERR_UNSUPPORTED,
+                        "zero-boundary, relaxation and Vlasov-Maxwell solvers run alone, not in a batch");
     if (!(t_final >= 0.0)) return sgw_fail(SGW_ERR_INVALID_ARG, "bad final time");
     const uint64_t need = solver_bytes(s);
     if (b->used + need > b->budget)

@@ -756,7 +756,55 @@ __global__ void norms_final_many_kernel(const NormItem* items, const double* par
     norms_final_block(partials + (size_t)blockIdx.x * stride, it->parts, it->n, it->result);
 }
 
+// ---------------------------------------------------------------- Vlasov-Maxwell fields
+
+// Thread (q, J): field q (B_3, E_1, E_2) at finest x_2 node J, the combination over the grids in
+// plan order of c_g times the grid's field at J, prolongated along x_2 as in Sec. 2.2.1 (node J
+// refines coarse node i = floor(J/R + 1/2) at offset s = J/R - i, periodic stencil i-2..i+2).
+__global__ void fields_combine_kernel(const GridDev* grids, const ProDev* pro, const FineDev* fine, double* out)
+{
+    const int N = fine->N, G = fine->G;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 3 * N) return;
+    const int q = e / N, J = e - q * N;
+    const double eps4 = 4.0 * fine->eps;
+    const int lagrange = fine->lagrange;
+    double acc = 0.0;
+    for (int g = 0; g < G; g++) {
+        const GridDev* gd = grids + g;
+        const int n0 = gd->n[0], m = pro[g].m[0];
+        const double* f = (const double*)((const char*)gd->u + gd->fld_bytes) + q * n0;
+        double v;
+        if (m == 0) {
+            v = f[J];
+        } else {
+            const int R = 1 << m;
+            const int i = (2 * J + R) >> (m + 1);
+            const double sv = (double)(J - i * R) / (double)R;
+            double st[5];
+            for (int t = 0; t < 5; t++) {
+                int p = i - 2 + t;
+                p += p < 0 ? n0 : 0;
+                p -= p >= n0 ? n0 : 0;
+                st[t] = f[p];
+            }
+            v = interp5<double>(st[0], st[1], st[2], st[3], st[4], sv, eps4, lagrange);
+        }
+        acc = fma((double)pro[g].coef, v, acc);
+    }
+    out[e] = acc;
+}
+
 } // namespace
+
+hipError_t launch_fields_combine(const GridDev* grids_dev, const ProDev* pro_dev, const FineDev& fine_host,
+                                 const FineDev* fine_dev, double* out, hipStream_t s)
+{
+    const int n = 3 * fine_host.N;
+    hipLaunchKernelGGL(fields_combine_kernel, dim3((n + SGW_BLOCK - 1) / SGW_BLOCK), dim3(SGW_BLOCK), 0, s, grids_dev,
+                       pro_dev, fine_dev, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_prolong(const ProDev* pro_dev, const FineDev* fine_dev, const FineDev& fh, int precision,
                           size_t lds_bytes, double* out, hipStream_t s)

@@ -1,7 +1,7 @@
-// Kernels of the Vlasov-Boltzmann model (Sec. 3.4, Example 5) around the line sweep: the
-// macroscopic density rho(x) = int f dv of each Runge-Kutta stage's input, which the
-// relaxation source (mu_inf(v) rho(x) - f) / tau reads, and the entropy functionals H_2 and
-// H_log of a finest-grid solution.
+// Kernels of the kinetic models of Sec. 3.4 around the line sweep: the velocity moments of each
+// Runge-Kutta stage's input (the density rho(x) = int f dv that the relaxation source
+// (mu_inf(v) rho(x) - f) / tau of Example 5 reads; the currents j_q = int f xi_q dxi that drive the
+// fields of Example 6), and the entropy functionals H_2 and H_log of a finest-grid solution.
 #include <cmath>
 
 #include "sgw_internal.h"
@@ -12,43 +12,60 @@ typedef const SGW_CONST GridDev* GridC;
 
 namespace {
 
-// rho(x) = h_v * (sum over the velocity nodes of the grid) of the stage input, in two launches
-// (the launch boundary orders the passes; no fences or counters).  The grid is an nvr x nxr
-// matrix with the x nodes fastest.
+// The moments h_v * (sum over the velocity nodes of the grid of w f) of the stage input, with
+// w = 1 (rho; nmom = 1) or w = xi_1, xi_2 (Vlasov-Maxwell, directions 2 and 3; nmom = 2), in two
+// launches (the launch boundary orders the passes; no fences or counters).  The grid is an
+// nvr x nxr matrix with the x nodes fastest.
 //
 // First pass: workgroup (grid, column block cb, chunk c) sums rows c * SGW_RHO_CHUNK ..
 // + SGW_RHO_CHUNK of SGW_RHO_COLS columns: lane (col, r) takes rows r, r + L, r + 2L, ... (L row
 // lanes) in FP64, the L row lanes are added in order through LDS and the block's sums go to
-// rho_part[c][x].
+// rho_part[moment][c][x].
 template <typename Real>
 __global__ void __launch_bounds__(SGW_BLOCK) rho_partial_kernel(const RhoItem* __restrict__ items, int stage)
 {
     constexpr int L = SGW_BLOCK / SGW_RHO_COLS;
-    __shared__ double part[SGW_BLOCK];
+    __shared__ double part[2][SGW_BLOCK];
     const SGW_CONST RhoItem* it = (const SGW_CONST RhoItem*)items + blockIdx.x;
     GridC g = (GridC)it->g;
     if (((const SGW_CONST ReqDev*)g->req)->done) return;
     const Real* __restrict__ in = (const Real*)(stage == 0 ? g->u : stage == 1 ? g->a : g->b);
-    const int nx = g->nxr, nv = g->nvr, chunk = it->chunk;
+    const int nx = g->nxr, nv = g->nvr, chunk = it->chunk, nch = g->rho_nchunk;
     const int col = threadIdx.x % SGW_RHO_COLS, lane = threadIdx.x / SGW_RHO_COLS;
     const int x = it->cb * SGW_RHO_COLS + col;
     const int r0 = chunk * SGW_RHO_CHUNK + lane;
-    double sum = 0.0;
-    if (x < nx) {
+    double sum = 0.0, sum2 = 0.0;
+    if (g->nmom == 1) {
+        if (x < nx) {
 #pragma unroll
+            for (int i = 0; i < SGW_RHO_RPT; i++) {
+                const int r = r0 + i * L;
+                if (r < nv) sum += (double)in[(int64_t)r * nx + x];
+            }
+        }
+    } else if (x < nx) {
+        // Vlasov-Maxwell: row r is velocity node (a, b) = (r mod n_2, r / n_2) of directions 2, 3
+        const int n1 = g->n[1];
         for (int i = 0; i < SGW_RHO_RPT; i++) {
             const int r = r0 + i * L;
-            if (r < nv) sum += (double)in[(int64_t)r * nx + x];
+            if (r < nv) {
+                const int bb = r / n1, a = r - bb * n1;
+                const double f = (double)in[(int64_t)r * nx + x];
+                sum = fma(f, g->lo[1] + a * g->h[1], sum);
+                sum2 = fma(f, g->lo[2] + bb * g->h[2], sum2);
+            }
         }
     }
-    part[threadIdx.x] = sum;
+    part[0][threadIdx.x] = sum;
+    part[1][threadIdx.x] = sum2;
     __syncthreads();
-    if (lane == 0 && x < nx) {
-        double s = part[col];
+    if (lane == 0 && x < nx)
+        for (int m = 0; m < g->nmom; m++) {
+            double s = part[m][col];
 #pragma unroll
-        for (int l = 1; l < L; l++) s += part[col + l * SGW_RHO_COLS];
-        g->rho_part[(int64_t)chunk * nx + x] = s;
-    }
+            for (int l = 1; l < L; l++) s += part[m][col + l * SGW_RHO_COLS];
+            g->rho_part[((int64_t)m * nch + chunk) * nx + x] = s;
+        }
 }
 
 // Second pass: workgroup (grid, column block cb) adds the chunks of its SGW_RHO_COLS columns:
@@ -64,17 +81,20 @@ __global__ void __launch_bounds__(SGW_BLOCK) rho_final_kernel(const RhoItem* __r
     const int nx = g->nxr, nch = g->rho_nchunk;
     const int col = threadIdx.x % SGW_RHO_COLS, lane = threadIdx.x / SGW_RHO_COLS;
     const int x = it->cb * SGW_RHO_COLS + col;
-    const double* __restrict__ rp = g->rho_part;
-    double sum = 0.0;
-    if (x < nx)
-        for (int c = lane; c < nch; c += L) sum += rp[(int64_t)c * nx + x];
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    if (lane == 0 && x < nx) {
-        double s = part[col];
+    for (int m = 0; m < g->nmom; m++) {
+        const double* __restrict__ rp = g->rho_part + (int64_t)m * nch * nx;
+        double sum = 0.0;
+        if (x < nx)
+            for (int c = lane; c < nch; c += L) sum += rp[(int64_t)c * nx + x];
+        part[threadIdx.x] = sum;
+        __syncthreads();
+        if (lane == 0 && x < nx) {
+            double s = part[col];
 #pragma unroll
-        for (int l = 1; l < L; l++) s += part[col + l * SGW_RHO_COLS];
-        g->rho[x] = s * g->hv;
+            for (int l = 1; l < L; l++) s += part[col + l * SGW_RHO_COLS];
+            g->rho[(int64_t)m * nx + x] = s * g->hv;
+        }
+        __syncthreads();
     }
 }
 

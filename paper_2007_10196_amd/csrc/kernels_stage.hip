@@ -93,11 +93,52 @@ __device__ __forceinline__ Real weno5s(Real c, Real D0, Real D1, Real D2, Real D
     return wsum(c, num, den);
 }
 
-// NI consecutive interface fluxes F_{i+1/2}, i = i0..i0+NI-1, from the NI+5 values
-// u_{i0-2} .. u_{i0+NI+2} of one line: LF split f^+- (eq. LFflux), the positive-wind
-// reconstruction of f^+ on i-2..i+2 plus the mirrored one of f^- on i+3..i-1.  A
-// split part that is identically zero (c = -+alpha for a linear flux) contributes
-// exactly zero and is skipped.  epsT = 4 eps.  LINEAR: the linear weights d_r.
+// NI consecutive interface fluxes F_{i+1/2}, i = i0..i0+NI-1, from the NI+5 split values
+// f^+-_{i0-2} .. f^+-_{i0+NI+2} of one line (eq. LFflux): the positive-wind reconstruction of
+// f^+ on i-2..i+2 plus the mirrored one of f^- on i+3..i-1.  A split part flagged identically zero
+// contributes exactly zero and is skipped.  epsT = 4 eps.  LINEAR: the linear weights d_r.
+template <typename Real, int NI, bool LINEAR>
+__device__ __forceinline__ void split_fluxes(const Real* pv, const Real* mv, bool plus, bool minus, Real epsT,
+                                             Real* F)
+{
+    if (plus) {
+        Real dp[NI + 4], tp[NI + 4];
+#pragma unroll
+        for (int q = 0; q < NI + 4; q++) dp[q] = pv[q + 1] - pv[q];
+        tp[0] = Real(0);
+#pragma unroll
+        for (int q = 1; q < NI + 4; q++) {
+            const Real sp = dp[q] - dp[q - 1];
+            tp[q] = fma(Real(13.0 / 3.0) * sp, sp, epsT);
+        }
+#pragma unroll
+        for (int s = 0; s < NI; s++)
+            F[s] = weno5s<Real, LINEAR>(pv[s + 2], dp[s], dp[s + 1], dp[s + 2], dp[s + 3], tp[s + 1], tp[s + 2],
+                                        tp[s + 3]);
+    } else {
+#pragma unroll
+        for (int s = 0; s < NI; s++) F[s] = Real(0);
+    }
+    if (minus) {
+        Real dm[NI + 4], tm[NI + 4];
+#pragma unroll
+        for (int q = 0; q < NI + 4; q++) dm[q] = mv[q + 1] - mv[q];
+        tm[0] = Real(0);
+#pragma unroll
+        for (int q = 1; q < NI + 4; q++) {
+            const Real sm = dm[q] - dm[q - 1];
+            tm[q] = fma(Real(13.0 / 3.0) * sm, sm, epsT);
+        }
+#pragma unroll
+        for (int s = 0; s < NI; s++)
+            F[s] += weno5s<Real, LINEAR>(mv[s + 3], -dm[s + 4], -dm[s + 3], -dm[s + 2], -dm[s + 1], tm[s + 4],
+                                         tm[s + 3], tm[s + 2]);
+    }
+}
+
+// The same from the NI+5 values u_{i0-2} .. u_{i0+NI+2} of one line: LF split f^+- (eq.
+// LFflux) of Burgers' flux or of a linear flux c u (f^+- = cp u, cm u with cp, cm = (c +- alpha)/2;
+// a part with cp or cm = 0 is skipped).
 template <typename Real, int NI, bool LINEAR>
 __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real cp, Real cm, Real alpha, Real epsT,
                                               Real* F)
@@ -119,39 +160,7 @@ __device__ __forceinline__ void window_fluxes(const Real* v, bool burgers, Real 
             mv[q] = cm * v[q];
         }
     }
-    if (burgers || cp != Real(0)) {
-        Real dp[NI + 4], tp[NI + 4];
-#pragma unroll
-        for (int q = 0; q < NI + 4; q++) dp[q] = pv[q + 1] - pv[q];
-        tp[0] = Real(0);
-#pragma unroll
-        for (int q = 1; q < NI + 4; q++) {
-            const Real sp = dp[q] - dp[q - 1];
-            tp[q] = fma(Real(13.0 / 3.0) * sp, sp, epsT);
-        }
-#pragma unroll
-        for (int s = 0; s < NI; s++)
-            F[s] = weno5s<Real, LINEAR>(pv[s + 2], dp[s], dp[s + 1], dp[s + 2], dp[s + 3], tp[s + 1], tp[s + 2],
-                                        tp[s + 3]);
-    } else {
-#pragma unroll
-        for (int s = 0; s < NI; s++) F[s] = Real(0);
-    }
-    if (burgers || cm != Real(0)) {
-        Real dm[NI + 4], tm[NI + 4];
-#pragma unroll
-        for (int q = 0; q < NI + 4; q++) dm[q] = mv[q + 1] - mv[q];
-        tm[0] = Real(0);
-#pragma unroll
-        for (int q = 1; q < NI + 4; q++) {
-            const Real sm = dm[q] - dm[q - 1];
-            tm[q] = fma(Real(13.0 / 3.0) * sm, sm, epsT);
-        }
-#pragma unroll
-        for (int s = 0; s < NI; s++)
-            F[s] += weno5s<Real, LINEAR>(mv[s + 3], -dm[s + 4], -dm[s + 3], -dm[s + 2], -dm[s + 1], tm[s + 4],
-                                         tm[s + 3], tm[s + 2]);
-    }
+    split_fluxes<Real, NI, LINEAR>(pv, mv, burgers || cp != Real(0), burgers || cm != Real(0), epsT, F);
 }
 
 // One RK stage of one box (FUSED = false), or all three stages of a box that is its
@@ -638,15 +647,18 @@ __device__ __forceinline__ void line_segment(GridC g, int blk, int stage, Real a
     constexpr bool last = k == D - 1;
     const bool relax = last && g->relax;
     int base = 0, xc = 0, ix = 0;
+    int xj[D]; // the line's node index along each other direction
     double muf = 1.0;
     {
         uint32_t r = (uint32_t)t;
 #pragma unroll
         for (int j = 0; j < D; j++) {
+            xj[j] = 0;
             if (j == k) continue;
             const uint32_t qq = FDIV(r, g->fd_n[j]);
             const int x = (int)(r - qq * (uint32_t)g->n[j]);
             r = qq;
+            xj[j] = x;
             base += x * g->stride[j];
             if (j == csrc) xc = x;
             if (relax) {
@@ -700,6 +712,22 @@ __device__ __forceinline__ void line_segment(GridC g, int blk, int stage, Real a
         // f_k = c u along the line (advection, Vlasov): f^+- = (c +- alpha)/2 u
         Real c = (Real)g->lin_c[k];
         if (csrc >= 0) c = (Real)g->coef[k][xc];
+        if constexpr (D == 3 && k > 0) {
+            if (g->vm) {
+                // Vlasov-Maxwell: the Lorentz force of this stage's fields at the line's x_2 node,
+                // E_1 + xi_2 B_3 (direction xi_1) or E_2 - xi_1 B_3 (direction xi_2)
+                const double* fld = (const double*)((const char*)in + g->fld_bytes);
+                const int n0 = g->n[0], i2 = xj[0];
+                const double B = fld[i2];
+                if (k == 1) {
+                    const double xi2 = g->lo[2] + xj[2] * g->h[2];
+                    c = (Real)(fld[n0 + i2] + xi2 * B);
+                } else {
+                    const double xi1 = g->lo[1] + xj[1] * g->h[1];
+                    c = (Real)(fld[2 * n0 + i2] - xi1 * B);
+                }
+            }
+        }
         cp = Real(0.5) * (c + alpha);
         cm = Real(0.5) * (c - alpha);
     }
@@ -760,8 +788,9 @@ __global__ void __launch_bounds__(SGW_LWAVE) line_kernel(const WorkItem* __restr
         if (((const SGW_CONST ReqDev*)g->req)->done) continue;
         // the wave-speed slot the next stage reads is cleared by the stage before it
         if (k == 0 && g->dyn_alpha && it->box == 0 && threadIdx.x == 0) g->alpha[(stage + 2) % 3] = 0ull;
-        const Real alpha =
-            g->dyn_alpha ? (Real)__longlong_as_double((long long)g->alpha[stage]) : (Real)g->alpha_c[k];
+        Real alpha = g->dyn_alpha ? (Real)__longlong_as_double((long long)g->alpha[stage]) : (Real)g->alpha_c[k];
+        // Vlasov-Maxwell: the xi directions' speeds of this stage's fields
+        if (D == 3 && k > 0 && g->vm) alpha = (Real)g->vm_alpha[2 * stage + k - 1];
         Real amax = Real(0);
         if (g->zmask) {
             if (g->linear)
@@ -802,6 +831,105 @@ hipError_t launch_lines(const WorkItem* items, int nitems, const int* range_dev,
     }
 #undef SGW_LINE
     return hipSuccess;
+}
+
+// ---------------------------------------------------------------- Vlasov-Maxwell fields
+//
+// One workgroup per component grid.  stage < 0: the initial fields of u^n, B_3 = b sin(k0 x_2),
+// E_1 = E_2 = 0.  stage s = 0..2: the Runge-Kutta stage s of the field equations B_3' = dE_1/dx_2,
+// E_1' = dB_3/dx_2 - j_1, E_2' = -j_2 (Sec. 3.4, Example 6), discretised like eq. (2.9): WENO5
+// with global LF splitting of F(B_3, E_1) = (-E_1, -B_3) at alpha = 1, each component on its own,
+// the currents of the stage input from the moment pass.  The output is the next stage's fields
+// (u^{n+1}'s after stage 2), whose xi-direction LF speeds go to the next stage's slots.
+template <bool LIN>
+__device__ void vm_fields_grid(const GridDev* g, int stage, double b, double k0, double* red)
+{
+    const int n = g->n[0];
+    const double h = g->h[0];
+    double* f0 = (double*)((char*)g->u + g->fld_bytes);
+    if (stage < 0) {
+        for (int i = threadIdx.x; i < n; i += SGW_BLOCK) {
+            f0[i] = b * sin(k0 * (g->lo[0] + i * g->h[0]));
+            f0[n + i] = 0.0;
+            f0[2 * n + i] = 0.0;
+        }
+        return;
+    }
+    const double* fin = (const double*)((const char*)(stage == 0 ? g->u : stage == 1 ? g->a : g->b) + g->fld_bytes);
+    double* out = (double*)((char*)(stage == 0 ? g->a : stage == 1 ? g->b : g->u) + g->fld_bytes);
+    const double dt = ((const ReqDev*)g->req)->dt;
+    const double* j1 = g->rho;
+    const double* j2 = g->rho + g->nxr;
+    const double epsT = 4.0 * g->eps;
+    const double x1lo = g->lo[1], x1hi = g->lo[1] + (g->n[1] - 1) * g->h[1];
+    const double x2lo = g->lo[2], x2hi = g->lo[2] + (g->n[2] - 1) * g->h[2];
+    double m1 = 0.0, m2 = 0.0;
+    for (int i = threadIdx.x; i < n; i += SGW_BLOCK) {
+        // split values at i-3 .. i+3 (periodic), then the interface fluxes at i-1/2 and i+1/2
+        double pB[7], mB[7], pE[7], mE[7];
+#pragma unroll
+        for (int q = 0; q < 7; q++) {
+            int p = i - 3 + q;
+            p += p < 0 ? n : 0;
+            p -= p >= n ? n : 0;
+            const double B = fin[p], E = fin[n + p];
+            pB[q] = 0.5 * (-E + B);
+            mB[q] = 0.5 * (-E - B);
+            pE[q] = 0.5 * (-B + E);
+            mE[q] = 0.5 * (-B - E);
+        }
+        double FB[2], FE[2];
+        split_fluxes<double, 2, LIN>(pB, mB, true, true, epsT, FB);
+        split_fluxes<double, 2, LIN>(pE, mE, true, true, epsT, FE);
+        const double LB = -(FB[1] - FB[0]) / h;
+        const double LE1 = -(FE[1] - FE[0]) / h - j1[i];
+        const double LE2 = -j2[i];
+        const double w[3] = {LB, LE1, LE2};
+        double v[3];
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            const double y = fin[q * n + i] + dt * w[q];
+            if (stage == 0) v[q] = y;
+            else if (stage == 1) v[q] = 0.75 * f0[q * n + i] + 0.25 * y;
+            else v[q] = f0[q * n + i] / 3.0 + 2.0 / 3.0 * y;
+        }
+        // stage 2 writes u^n's fields in place: this thread read them above
+#pragma unroll
+        for (int q = 0; q < 3; q++) out[q * n + i] = v[q];
+        const double p1 = x2lo * v[0], q1 = x2hi * v[0], p2 = x1lo * v[0], q2 = x1hi * v[0];
+        m1 = nanmax(m1, nanmax(fabs(v[1] + p1), fabs(v[1] + q1)));
+        m2 = nanmax(m2, nanmax(fabs(v[2] - p2), fabs(v[2] - q2)));
+    }
+    if (stage == 2) return; // the time-step kernel takes u^{n+1}'s speeds
+    m1 = wave_max(m1);
+    m2 = wave_max(m2);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[2 * wave] = m1;
+        red[2 * wave + 1] = m2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a1 = red[0], a2 = red[1];
+        for (int w2 = 1; w2 < SGW_BLOCK / 64; w2++) {
+            a1 = nanmax(a1, red[2 * w2]);
+            a2 = nanmax(a2, red[2 * w2 + 1]);
+        }
+        g->vm_alpha[2 * (stage + 1)] = a1;
+        g->vm_alpha[2 * (stage + 1) + 1] = a2;
+    }
+}
+
+__global__ void __launch_bounds__(SGW_BLOCK) vm_fields_kernel(const GridDev* grids, int stage, double b, double k0,
+                                                              int linear)
+{
+    __shared__ double red[2 * (SGW_BLOCK / 64)];
+    const GridDev* g = grids + blockIdx.x;
+    if (stage >= 0 && ((const ReqDev*)g->req)->done) return;
+    if (linear)
+        vm_fields_grid<true>(g, stage, b, k0, red);
+    else
+        vm_fields_grid<false>(g, stage, b, k0, red);
 }
 
 template <typename Real, int D, bool FUSED>
@@ -912,6 +1040,15 @@ hipError_t launch_stage(const WorkItem* items, int nitems, int stage, int precis
     if (grid_cap > 0 && blocks > grid_cap) blocks = grid_cap;
     if (precision == SGW_FP64) return launch_r<double>(dim, items, nitems, nullptr, blocks, stage, lds_bytes, s);
     return launch_r<float>(dim, items, nitems, nullptr, blocks, stage, lds_bytes, s);
+}
+
+hipError_t launch_vm_fields(const GridDev* grids_dev, int G, int stage, int precision, double b, double k0,
+                            int linear, hipStream_t s)
+{
+    (void)precision;
+    if (G <= 0) return hipSuccess;
+    hipLaunchKernelGGL(vm_fields_kernel, dim3(G), dim3(SGW_BLOCK), 0, s, grids_dev, stage, b, k0, linear);
+    return hipGetLastError();
 }
 
 hipError_t launch_stage_range(const WorkItem* items, const int* range_dev, int blocks, int stage, int precision,

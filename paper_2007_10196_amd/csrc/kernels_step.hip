@@ -15,15 +15,17 @@ __global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long 
 
 // Coefficient tables of the fixed-field Vlasov flux and the constant LF speeds:
 // f_{x_k} = v_k u (coefficient indexed by the v_k node), f_{v_k} = E_k(x_k) u with
-// E_k = amp sin(kE x_k), or E_k = -x_k (harmonic: the field of the Vlasov-Boltzmann model).
-// One workgroup per (grid, direction); the max over the table is the LF speed.
+// E_k = amp sin(kE x_k), or E_k = -x_k (harmonic: the field of the Vlasov-Boltzmann model); for
+// the Vlasov-Maxwell system only direction x_2, whose coefficient is xi_2 (the xi directions take
+// theirs from the fields).  One workgroup per (grid, direction); the max over the table is the LF
+// speed.
 __global__ void coef_init_kernel(GridDev* grids, double* coef_base, const int64_t* coef_off, double amp, double kE,
                                  int harmonic)
 {
     __shared__ double red[SGW_BLOCK / 64];
     GridDev* g = grids + blockIdx.x;
     const int k = blockIdx.y;
-    if (k >= g->d) return;
+    if (k >= g->d || g->coef_src[k] < 0) return;
     const int m = g->d / 2;
     const int src = g->coef_src[k];
     double* tab = coef_base + coef_off[blockIdx.x * SGW_MAX_DIM + k];
@@ -66,6 +68,13 @@ __device__ __forceinline__ double ic_value(const GridDev* g, int64_t idx, int ic
         double s = 0.0;
         for (int k = 0; k < g->d; k++) s += x[k];
         return ip[0] + ip[1] * sin(ip[2] * s + ip[3]);
+    }
+    if (ic == SGW_IC_VLASOV_MAXWELL) {
+        // Sec. 3.4, Example 6: two drifting Maxwellians in xi_1 times a Maxwellian in xi_2,
+        // ip = (beta, b, delta, v01, v02, k0)
+        const double be = ip[0], de = ip[2];
+        const double a = x[1] - ip[3], c = x[1] + ip[4];
+        return exp(-x[2] * x[2] / be) * (de * exp(-a * a / be) + (1.0 - de) * exp(-c * c / be)) / (M_PI * be);
     }
     const int m = g->d / 2;
     if (ic == SGW_IC_VLASOV_BOLTZMANN) {
@@ -161,6 +170,27 @@ __global__ void req_set_final_many_kernel(ReqDev* const* reqs, const double* tf,
     r->done = r->nonfinite ? 1 : 0;
 }
 
+// Largest |E_1 + xi_2 B_3| and |E_2 - xi_1 B_3| over the x_2 nodes i = first, first + step, ...
+// of one Vlasov-Maxwell grid's fields fld (B_3, E_1, E_2) and the end nodes of the other velocity
+// direction (for fixed fields the rounded expression is monotone in xi, so its largest magnitude
+// over all nodes sits at an end node).
+__device__ void vm_field_speeds(const GridDev* g, const double* fld, int first, int step, double* a1, double* a2)
+{
+#pragma clang fp contract(off)
+    const int n0 = g->n[0];
+    const double x1lo = g->lo[1], x1hi = g->lo[1] + (g->n[1] - 1) * g->h[1];
+    const double x2lo = g->lo[2], x2hi = g->lo[2] + (g->n[2] - 1) * g->h[2];
+    double m1 = 0.0, m2 = 0.0;
+    for (int i = first; i < n0; i += step) {
+        const double B = fld[i], E1 = fld[n0 + i], E2 = fld[2 * n0 + i];
+        const double p1 = x2lo * B, q1 = x2hi * B, p2 = x1lo * B, q2 = x1hi * B;
+        m1 = nanmax(m1, nanmax(fabs(E1 + p1), fabs(E1 + q1)));
+        m2 = nanmax(m2, nanmax(fabs(E2 - p2), fabs(E2 - q2)));
+    }
+    *a1 = m1;
+    *a2 = m2;
+}
+
 // The shared time step (Sec. 3): dt = cfl / sum_k (A_k / h_k^fine), A_k the
 // largest LF speed over all component grids of the solve at u^n, clipped so the
 // last step lands on T.  One wavefront per solve: lanes over grids, then a
@@ -196,11 +226,33 @@ __device__ void dt_wave(ReqDev* r)
         return;
     }
     double dt;
-    if (dt_mode == SGW_DT_POW53) {
+    if (dt_mode == SGW_DT_POW53 && !rc->vm) {
         dt = dt_pow53;
     } else {
         double denom = 0.0;
-        if (dyn) {
+        if (rc->vm) {
+            // Vlasov-Maxwell: x_2 at its constant speed; xi_1, xi_2 at the maxima over each grid's
+            // nodes of |E_1 + xi_2 B_3| and |E_2 - xi_1 B_3| of u^n's fields, attained at the end
+            // nodes of the other velocity direction (the rounded expression is monotone in it);
+            // each grid's pair goes to its stage-0 speed slots
+            double A0 = 0.0, A1 = 0.0, A2 = 0.0;
+            for (int g = lane; g < ngrids; g += 64) A0 = nanmax(A0, grids[g].alpha_c[0]);
+            for (int g = 0; g < ngrids; g++) {
+                const GridDev* G = grids + g;
+                double a1, a2;
+                vm_field_speeds(G, (const double*)((const char*)G->u + G->fld_bytes), lane, 64, &a1, &a2);
+                a1 = wave_max(a1);
+                a2 = wave_max(a2);
+                if (lane == 0) {
+                    G->vm_alpha[0] = a1;
+                    G->vm_alpha[1] = a2;
+                }
+                A1 = nanmax(A1, a1);
+                A2 = nanmax(A2, a2);
+            }
+            A0 = wave_max(A0);
+            denom = dt_mode == SGW_DT_POW53 ? 0.0 : A0 / hfin[0] + A1 / hfin[1] + A2 / hfin[2];
+        } else if (dyn) {
             // every grid of a solve has the same flux: one maximum of the state-dependent
             // speeds serves all directions
             double A = 0.0;
@@ -223,7 +275,7 @@ __device__ void dt_wave(ReqDev* r)
             }
             return;
         }
-        dt = denom > 0.0 ? cfl / denom : rem;
+        dt = dt_mode == SGW_DT_POW53 ? dt_pow53 : denom > 0.0 ? cfl / denom : rem;
     }
     if (dt > rem) dt = rem;
     if (lane == 0) {

@@ -29,6 +29,9 @@ struct sgw_plan {
     bool line_mode = false;                    // the stage runs as line sweeps (no boxes): 4D, zero
                                                // boundary or relaxation
     bool relax = false;                        // relaxation source on
+    bool vm = false;                           // Vlasov-Maxwell: fields per grid
+    uint64_t fields_off = 0;                   // byte offset of the fields in a state copy
+    int64_t fields_total = 0;                  // field values over all grids (3 n_1 each)
     int zmask = 0;                             // bit k: zero boundary in direction k
     int64_t nrho_items = 0;                    // density first-pass work items over all grids
     int64_t nrho_final = 0;                    // density second-pass work items (column blocks)
@@ -38,7 +41,7 @@ struct sgw_plan {
     uint64_t copy_bytes = 0, state_bytes = 0, scratch_bytes = 0;
     uint64_t off_grids = 0, off_req = 0, off_items = 0, off_alpha = 0, off_coef = 0, off_coef_off = 0;
     uint64_t off_pro = 0, off_fine = 0, off_partials = 0, off_result = 0, off_foot = 0, off_stab = 0;
-    uint64_t off_mu = 0, off_rho = 0, off_rho_part = 0, off_rho_items = 0;
+    uint64_t off_mu = 0, off_rho = 0, off_rho_part = 0, off_rho_items = 0, off_vm_alpha = 0;
 };
 
 struct sgw_solver {

@@ -140,12 +140,17 @@ struct alignas(64) GridDev {
     // zero boundary and the relaxation source of the Vlasov-Boltzmann model (line sweep only)
     int32_t zmask;                   // bit k: every value beyond either end of direction k is 0
     int32_t relax;                   // 1: the last direction adds (mu_inf(v) rho(x) - u) / tau
-    int32_t nxr, nvr;                // x nodes (prod of the first d/2 extents) and velocity nodes
-    int32_t rho_cb, rho_nchunk;      // density launch: blocks of SGW_RHO_COLS x nodes, chunks of rows
+    int32_t nxr, nvr;                // x nodes (prod of the x extents) and velocity nodes
+    int32_t rho_cb, rho_nchunk;      // moment launch: blocks of SGW_RHO_COLS x nodes, chunks of rows
     const double* mu[SGW_MAX_DIM];   // velocity direction k: exp(-v^2/(2 theta)) / sqrt(2 pi theta) per node
-    double* rho;                     // nxr: rho(x) of the current stage input
-    double* rho_part;                // rho_nchunk x nxr partial sums
+    double* rho;                     // nmom x nxr: the velocity moments of the current stage input
+    double* rho_part;                // nmom x rho_nchunk x nxr partial sums
     double inv_tau, hv;              // 1 / tau and the velocity cell volume
+    // Vlasov-Maxwell (d = 3: x_2, xi_1, xi_2): the grid's fields B_3, E_1, E_2 at its n[0] x_2 nodes,
+    // FP64, fld_bytes past the grid's first node in each state copy
+    int32_t vm, nmom;                // nmom: moments of the moment launch (1: rho; 2: j_1, j_2)
+    int64_t fld_bytes;
+    double* vm_alpha;                // [3 stages][2]: LF speeds of xi_1, xi_2 of each stage's fields
 };
 
 // density launch: SGW_RHO_COLS x nodes per workgroup, SGW_BLOCK / SGW_RHO_COLS row lanes,
@@ -174,7 +179,7 @@ struct alignas(64) ReqDev {
     const GridDev* grids;
     const unsigned long long* alpha; // the solve's wave-speed slots, 4 per grid (slot 0: max |u^n|)
     int32_t ngrids, d, dt_mode, done;
-    int32_t nonfinite, dyn_alpha, active, pad;
+    int32_t nonfinite, dyn_alpha, active, vm; // vm: speeds of the xi directions from the fields
 };
 
 struct WorkItem {
@@ -278,6 +283,13 @@ hipError_t launch_coef_init(GridDev* grids_dev, const GridDev* grids_host, int G
 // second-pass items[npartial..npartial + nfinal), one workgroup each
 hipError_t launch_rho(const RhoItem* items, int npartial, int nfinal, int stage, int precision, hipStream_t s);
 // H_2 and H_log of a finest-grid solution: partial sums in partials, the two values in result
+// Vlasov-Maxwell fields of every grid: stage 0..2 update from the stage's currents (one workgroup
+// per grid), or (stage < 0) the initial fields B_3 = b sin(k0 x_2), E = 0 in u^n
+hipError_t launch_vm_fields(const GridDev* grids_dev, int G, int stage, int precision, double b, double k0,
+                            int eps_linear, hipStream_t s);
+// the fields of u^n combined on the finest x_2 grid (3 N values)
+hipError_t launch_fields_combine(const GridDev* grids_dev, const ProDev* pro_dev, const FineDev& fine_host,
+                                 const FineDev* fine_dev, double* out, hipStream_t s);
 hipError_t launch_entropies(const FineDev& f, const double* lo, const double* hi, double theta, double zx,
                             const double* fsol, double* partials, double* result, hipStream_t s);
 hipError_t launch_restrict(const GridDev* grids_dev, const GridDev* grids_host, int G, int precision,

@@ -29,6 +29,9 @@ class Plan:
         g, tn, fn = C.c_int32(), C.c_int64(), C.c_int64()
         B.check(B.lib().sgw_plan_info(h, C.byref(g), C.byref(tn), C.byref(fn)))
         self.num_grids, self.total_nodes, self.fine_nodes = g.value, tn.value, fn.value
+        fo, fc = C.c_uint64(), C.c_int64()
+        B.check(B.lib().sgw_plan_fields(h, C.byref(fo), C.byref(fc)))
+        self.fields_offset, self.fields_count = fo.value, fc.value
         ft = (C.c_int32 * 4)()
         B.check(B.lib().sgw_plan_fine_tile(h, ft))
         self.fine_tile = tuple(ft[:problem.d])
@@ -118,6 +121,23 @@ class Solver:
         res = (C.c_double * 2)()
         B.check(B.lib().sgw_norms(self.handle, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), res))
         return res[0], res[1]
+
+    def fields(self, which: int = 0) -> torch.Tensor:
+        """Vlasov-Maxwell: the FP64 fields of every grid (B_3, E_1, E_2 at its x_2 nodes, grids back
+        to back) in state copy `which` (0: u^n), a view into the state buffer."""
+        assert self.plan.fields_count > 0
+        copy = self.plan.state_bytes // 3
+        start = which * copy + self.plan.fields_offset
+        return self.state[start:start + 8 * self.plan.fields_count].view(torch.float64)
+
+    def fields_combine(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Vlasov-Maxwell: (3, N) FP64 combination of the fields of u^n on the finest x_2 grid."""
+        n = self.problem.nr << self.problem.nl
+        if out is None:
+            out = torch.empty(3 * n, dtype=torch.float64, device=self.device)
+        assert out.dtype == torch.float64 and out.numel() >= 3 * n
+        B.check(B.lib().sgw_fields_combine(self.handle, C.c_void_p(out.data_ptr())))
+        return out[:3 * n].view(3, n)
 
     def entropies(self, f: torch.Tensor) -> Tuple[float, float]:
         """(H_2, H_log) of a finest-grid solution (FP64) relative to the stationary state of the

@@ -222,3 +222,21 @@ def test_valu_calibration_hook_validates_before_launching():
     for op, blocks, out in ((5, 1, 1), (-1, 1, 1), (0, 0, 1), (0, 1, None)):
         st = B.lib().sgw_calibrate_valu(op, blocks, C.c_void_p(out), None, C.byref(n))
         assert st == -1  # SGW_ERR_INVALID_ARG
+
+
+def test_vlasov_maxwell_plans():
+    """The Vlasov-Maxwell system: dim 3 with its own initial condition, periodic, no relaxation and no
+    manual boxes; its plans march as line sweeps and carry 3 n_1 FP64 field values per grid after
+    the nodes of each state copy."""
+    vm = W.paper_example6(nr=8, nl=2)
+    plan = Plan(vm)
+    assert plan.fields_count == O.total_fields(vm) == sum(3 * g["shape"][0] for g in plan.grids)
+    assert plan.fields_offset % 256 == 0 and plan.fields_offset >= 8 * plan.total_nodes
+    assert plan.state_bytes >= 3 * (plan.fields_offset + 8 * plan.fields_count)
+    assert all(g["box"] == (0, 0, 0) for g in plan.grids)
+    _expect_status(vm.replace(ic=W.IC_SINE), -1)                         # the flux needs its initial condition
+    _expect_status(W.c3_advection_3d(nr=8, nl=2).replace(ic=W.IC_VM), -1)  # and the other way round
+    _expect_status(vm.replace(relax_tau=1.0), -1)
+    _expect_status(vm.replace(bc=(1, 0, 0)), -2)
+    _expect_status(vm, -2, box=[8, 8, 8])
+    assert Plan(W.c3_advection_3d(nr=8, nl=2)).fields_count == 0
