@@ -918,6 +918,69 @@ def example5(torch):
     return out
 
 
+def example6_run(torch, pb):
+    """One FP64 Vlasov-Maxwell solve to T: GPU time of restriction + march + prolongation and
+    combination of f + combination of the fields (HIP events on the solver stream), the field
+    energies and the distribution's mass, kinetic energy and extrema."""
+    from paper_2007_10196_amd.solver import Solver
+    s = Solver(pb, device="cuda:0")
+    out = torch.empty(s.plan.fine_nodes, dtype=torch.float64, device="cuda:0")
+    s.restrict()
+    s.advance(min(pb.T, 0.5))
+    s.prolongate_combine(out)
+    s.fields_combine()
+    torch.cuda.synchronize()
+    e0, e1, e2, e3 = ev(torch), ev(torch), ev(torch), ev(torch)
+    e0.record(s.stream)
+    s.restrict()
+    s.advance()
+    e1.record(s.stream)
+    s.prolongate_combine(out)
+    e2.record(s.stream)
+    F = s.fields_combine()
+    e3.record(s.stream)
+    torch.cuda.synchronize()
+    t, steps = s.query()
+    n = pb.n_fine
+    hx, hv = (pb.hi[0] - pb.lo[0]) / n, 2.4 / n
+    xi = -1.2 + hv * torch.arange(n, dtype=torch.float64, device="cuda:0")
+    f3 = out.view(n, n, n)  # [xi_2, xi_1, x_2]
+    kinetic = 0.5 * float(((xi * xi).view(n, 1, 1) * f3).sum() + ((xi * xi).view(1, n, 1) * f3).sum()) * hx * hv * hv
+    res = {"ms": e0.elapsed_time(e3), "march_ms": e0.elapsed_time(e1), "prolong_ms": e1.elapsed_time(e2),
+           "fields_combine_ms": e2.elapsed_time(e3), "time_steps": steps, "t": t, "nodes": s.plan.total_nodes,
+           "mass": float(out.sum()) * hx * hv * hv, "kinetic_energy": kinetic,
+           "field_energy_B3": 0.5 * float((F[0] * F[0]).sum()) * hx,
+           "field_energy_E1": 0.5 * float((F[1] * F[1]).sum()) * hx,
+           "field_energy_E2": 0.5 * float((F[2] * F[2]).sum()) * hx,
+           "f_min": float(out.min()), "f_max": float(out.max())}
+    res["fields"] = F
+    res["f"] = out
+    return res
+
+
+def example6(torch):
+    """Sparse grid against single grid for the 3D Vlasov-Maxwell system at the paper's setting
+    (Example 6: root 20, level 3 against 160^3, CFL 0.4, T = 10, FP64); the paper prints CPU times
+    3585.81 s (sparse) and 10331.04 s (single)."""
+    sp = example6_run(torch, W.paper_example6(nr=20, nl=3))
+    si = example6_run(torch, W.paper_example6(nr=160, nl=0))
+    df = (sp["f"] - si["f"]).abs()
+    dF = (sp["fields"] - si["fields"]).abs()
+    out = {"table": "Example 6 (CPU 3585.81 s sparse, 10331.04 s single)", "paper_cpu_ratio": 3585.81 / 10331.04,
+           "sparse": {k: v for k, v in sp.items() if k not in ("f", "fields")},
+           "single": {k: v for k, v in si.items() if k not in ("f", "fields")},
+           "gpu_ratio": sp["ms"] / si["ms"],
+           "f_sparse_minus_single": {"l1": float(df.mean()), "linf": float(df.max())},
+           "fields_sparse_minus_single_linf": [float(dF[q].max()) for q in range(3)]}
+    print(f"[bench] example6: sparse {sp['ms']:.1f} ms ({sp['time_steps']} steps), single {si['ms']:.1f} ms "
+          f"({si['time_steps']} steps), ratio {out['gpu_ratio']:.3f} (paper {out['paper_cpu_ratio']:.3f}); "
+          f"f sparse-single L1 {out['f_sparse_minus_single']['l1']:.3e} Linf {out['f_sparse_minus_single']['linf']:.3e}",
+          file=sys.stderr, flush=True)
+    del sp, si, df, dF
+    torch.cuda.empty_cache()
+    return out
+
+
 def large_roofline(torch, reps=10):
     """Stage launches of one time step on the scaled cases whose state exceeds the 256 MB MALL: 3D
     advection at root 32 (32.5 M nodes, box kernel) and the 4D Vlasov workload at root 16 (50.3 M
@@ -996,6 +1059,8 @@ def main():
                     help="only run sparse against single grid at the paper's resolutions (and equal error)")
     ap.add_argument("--example5", action="store_true",
                     help="only run the Vlasov-Boltzmann sparse/single comparison of Tables tb:ex5acpu, tb:ex5bcpu")
+    ap.add_argument("--example6", action="store_true",
+                    help="only run the Vlasov-Maxwell sparse/single comparison of Example 6")
     ap.add_argument("--large-roofline", action="store_true",
                     help="only time the stage launches of the scaled 3D/4D cases that exceed the MALL")
     args = ap.parse_args()
@@ -1011,11 +1076,13 @@ def main():
     if args.path_workload:
         path_workload(args.path_workload, args.precision, args.box_target, args.blocks_per_cu, args.stage_reps)
         return
-    if args.paper_sweep or args.large_roofline or args.example5:
+    if args.paper_sweep or args.large_roofline or args.example5 or args.example6:
         import torch
         torch.cuda.set_device(0)
         if args.example5:
             res = {"example5": example5(torch)}
+        elif args.example6:
+            res = {"example6": example6(torch)}
         else:
             res = {"paper_sweep": paper_sweep(torch)} if args.paper_sweep else {"large_roofline": large_roofline(torch)}
         print(json.dumps(res), flush=True)
