@@ -161,9 +161,10 @@ def source_hash(name):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(key):
-    """HBM bytes per launch of a kernel from its committed counter summary, or None when the
-    kernel's source changed since the counters were taken (or none were taken)."""
+def measured_traffic(key, kernel=None):
+    """HBM bytes per launch of a kernel from its committed counter summary (`kernel`: one entry of a
+    summary that covers several kernels), or None when the kernel's source changed since the
+    counters were taken (or none were taken)."""
     fname, src = TRAFFIC[key]
     try:
         with open(os.path.join(ROOT, "profiles", fname)) as f:
@@ -172,6 +173,8 @@ def measured_traffic(key):
         return None
     if rec.get("kernel_source_sha256_16") != source_hash(src):
         return None
+    if kernel is not None:
+        return rec.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
     return rec.get("hbm_bytes_per_launch")
 
 
@@ -378,7 +381,7 @@ def path_workload(name, precision, box_target, bpc, reps):
     batch.launch_stage(3, reps)
     e1.record(st)
     torch.cuda.synchronize()
-    stage_us = e0.elapsed_time(e1) / reps * 1e3
+    batch_stage_us = e0.elapsed_time(e1) / reps * 1e3
     info = batch.info()
     batch.release(slot)
     batch.close()
@@ -399,14 +402,27 @@ def path_workload(name, precision, box_target, bpc, reps):
         e3.record(s.stream)
         torch.cuda.synchronize()
     march_ms = e0.elapsed_time(e1)
+    pro_ms = e2.elapsed_time(e3)
+    # the stage launches of one time step as the solver enqueues them (measurement hook; this
+    # spoils the solve's state, which is not read again)
+    for stage in range(3):
+        s.launch_stage(stage, 0, 1)
+    e4, e5 = ev(), ev()
+    e4.record(s.stream)
+    for _ in range(reps):
+        for stage in range(3):
+            s.launch_stage(stage, 0, 1)
+    e5.record(s.stream)
+    torch.cuda.synchronize()
     print(json.dumps({
         "workload": f"{pb.name}: d={pb.d}, root {pb.nr}, finest level {pb.nl}, {len(s.plan.grids)} component grids, "
                     f"{s.plan.total_nodes} nodes, finest grid {s.plan.fine_nodes} nodes, T={pb.T}",
         "precision": precision, "boxes": info["boxes"], "box_target": box_target, "blocks_per_cu": bpc,
-        "stage_launches_per_step_us": stage_us, "steps": steps, "t": t, "march_ms": march_ms,
+        "stage_launches_per_step_us": e4.elapsed_time(e5) / reps * 1e3,
+        "batch_stage_launches_per_step_us": batch_stage_us, "steps": steps, "t": t, "march_ms": march_ms,
         "march_ms_per_step": march_ms / max(steps, 1),
         "march_cell_updates_per_s": steps * s.plan.total_nodes / (march_ms * 1e-3),
-        "prolong_combine_ms": e2.elapsed_time(e3)}), flush=True)
+        "prolong_combine_ms": pro_ms}), flush=True)
 
 
 def valu_calibration():
@@ -439,37 +455,32 @@ def ev(torch):
     return torch.cuda.Event(enable_timing=True)
 
 
-def stage_launch_us(torch, pb, box_target, bpc, reps):
-    """Average duration of one stage-kernel launch over all boxes of the solve, in the launch
-    shape the step graphs use: HIP events on the batch stream around `reps` repetitions of the
-    stage launches of one step (the measurement hook), divided by the launches of a step.
-    Returns (microseconds per launch, launches per step, batch info)."""
-    from paper_2007_10196_amd.solver import Batch, Solver
-    s = Solver(pb, device="cuda:0", box_target=box_target, blocks_per_cu=bpc)
-    if all(not any(g["box"]) for g in s.plan.grids):
-        # line sweeps (4D): one launch per direction and RK stage
-        launches = 3 * pb.d
-    else:
-        # grids that are one stage box take their three stages in one launch; the others one per stage
-        whole = [g["box"] == g["shape"] for g in s.plan.grids]
-        launches = (1 if any(whole) else 0) + (3 if not all(whole) else 0)
-    batch = Batch(max_solvers=1, precision=pb.precision, hbm_budget=1 << 40, max_items=1 << 20)
-    if bpc:
-        batch.set_blocks_per_cu(bpc)
-    s.restrict()
-    slot = batch.admit(s)
-    batch.step(1)
-    st = batch.stream
+def stage_kernels_us(torch, s, reps):
+    """Average launch duration of each kernel of a 4D stage (the plane launch, the line sweeps of
+    directions 3 and 4) over the three RK stages, and of a whole time step, each event-timed alone
+    on the solver stream through the measurement hook after the solve (whose state it spoils)."""
+    out = {}
+    for key, part in (("plane", 1), ("line3", 4), ("line4", 5)):
+        by_stage = []
+        for stage in range(3):
+            s.launch_stage(stage, part, 2)
+            e0, e1 = ev(torch), ev(torch)
+            e0.record(s.stream)
+            s.launch_stage(stage, part, reps)
+            e1.record(s.stream)
+            torch.cuda.synchronize()
+            by_stage.append(e0.elapsed_time(e1) * 1e3 / reps)
+        out[key] = sum(by_stage) / 3
+        out[key + "_by_stage"] = by_stage
     e0, e1 = ev(torch), ev(torch)
-    batch.launch_stage(3, 2)
-    e0.record(st)
-    batch.launch_stage(3, reps)
-    e1.record(st)
+    e0.record(s.stream)
+    for _ in range(reps):
+        for stage in range(3):
+            s.launch_stage(stage, 0, 1)
+    e1.record(s.stream)
     torch.cuda.synchronize()
-    info = batch.info()
-    batch.release(slot)
-    batch.close()
-    return e0.elapsed_time(e1) * 1e3 / reps / launches, launches, info
+    out["step_us"] = e0.elapsed_time(e1) * 1e3 / reps
+    return out
 
 
 def solve_run(torch, pb, steps, warmup, box_target, bpc):
@@ -549,21 +560,28 @@ def c4_headline(args, torch):
     print(f"[bench] 4D Vlasov FP64: {r['ms_per_solve']:.1f} ms per solve, {value:.3e} cell-updates/s, "
           f"L1 {r['l1']:.3e}", file=sys.stderr, flush=True)
 
-    # ---- the two kernels that take the solve's time, against their rooflines
-    st_us, launches, info = stage_launch_us(torch, pb, bt, bpc, args.stage_reps)
-    # a time step is 3 RK stages of 140 d + 5 flops per node, spread over its launches
-    stage_flops = nodes * 3 * flops_per_node_stage(pb.d) / launches
-    stage = kernel_roofline(
-        "line_kernel<double, 4, k> (one direction of one WENO5-LF + TVD-RK3 stage over every grid line of the "
-        "solve; 4 launches per stage)", st_us,
-        stage_flops, PEAK_FP64_TFLOPS, measured_traffic("stage_c4_fp64"),
-        {"launches_per_time_step": launches, "work_items_per_launch": info["boxes"], "nodes_per_launch": nodes,
-         "flops_per_node_stage": flops_per_node_stage(pb.d),
-         # a stage reads its input once per direction, writes and reads back the partial sum
-         # between directions (d - 1 times each), writes the output and (stages 2, 3) reads u^n:
-         # 3d - 1/3 words per node over the three stages, spread over the d launches of a stage
-         "algorithmic_bytes_per_launch": nodes * 8 * (3 * pb.d - 1.0 / 3.0) / pb.d,
-         "time_per_solve_ms": st_us * launches * r["time_steps"] * 1e-3})
+    # ---- the kernels that take the solve's time, against their rooflines.  A 4D stage is the plane
+    # launch (directions 1 and 2 over whole planes in LDS) and the line sweeps of directions 3 and 4;
+    # each is event-timed alone on the solver stream through the measurement hook, in each RK stage
+    stage_parts = stage_kernels_us(torch, s, args.stage_reps)
+    steps = r["time_steps"]
+    fl = 140  # flops per node and direction of the WENO5-LF flux difference
+    # algorithmic words per node: the plane launch reads the stage input and writes the partial sum;
+    # direction 3 reads the input and the partial sum and writes it back; direction 4 reads both and
+    # writes the output, and in stages 2 and 3 also reads u^n
+    spec = {"plane": ("plane_kernel<double> (directions 1 and 2 of one WENO5-LF stage over whole (x_1, x_2) planes "
+                      "staged in LDS)", 2 * fl, 2.0),
+            "line3": ("line_kernel<double, 4, 2> (direction 3 of one stage over every grid line)", fl, 3.0),
+            "line4": ("line_kernel<double, 4, 3> (direction 4 and the TVD-RK3 combination of one stage)", fl + 5,
+                      3.0 + 2.0 / 3.0)}
+    stage_k = []
+    for key, (name, fpn, words) in spec.items():
+        us = stage_parts[key]
+        stage_k.append(kernel_roofline(
+            name, us, nodes * fpn, PEAK_FP64_TFLOPS, measured_traffic("stage_c4_fp64", key),
+            {"launches_per_time_step": 3, "nodes_per_launch": nodes, "flops_per_node": fpn,
+             "algorithmic_bytes_per_launch": nodes * 8 * words, "time_per_solve_ms": us * 3 * steps * 1e-3,
+             "per_stage_us": stage_parts[key + "_by_stage"]}))
     pro_us = r["parts"]["prolong_combine_ms"] * 1e3
     interps = interpolation_count(s.plan)
     prolong = kernel_roofline(
@@ -572,7 +590,7 @@ def c4_headline(args, torch):
         {"interpolations_per_launch": interps, "flops_per_interpolation": INTERP_FLOPS,
          "algorithmic_bytes_per_launch": fine * 8 + nodes * 8,
          "achieved_write_GBs": fine * 8 / (pro_us * 1e-6) / 1e9, "time_per_solve_ms": pro_us * 1e-3})
-    by_time = sorted((stage, prolong), key=lambda k: -k["time_per_solve_ms"])
+    by_time = sorted(stage_k + [prolong], key=lambda k: -k["time_per_solve_ms"])
 
     # ---- the same solve with FP32 sweeps (FP64 combination and norms)
     fp32 = None
@@ -614,7 +632,8 @@ def c4_headline(args, torch):
     head = {"value": value, "ms_per_solve": r["ms_per_solve"], "l1": r["l1"], "linf": r["linf"],
             "time_steps": r["time_steps"], "t": r["t"], "nodes": nodes, "fine": fine, "parts": r["parts"],
             "finest_equivalent_cell_updates_per_s": r["time_steps"] * fine / (r["ms_per_solve"] * 1e-3),
-            "roofline": by_time[0], "roofline_other": by_time[1], "fp32": fp32, "plain": plain,
+            "roofline": by_time[0], "roofline_other": by_time[1:],
+            "stage_step_us": stage_parts["step_us"], "fp32": fp32, "plain": plain,
             "autotune": {"box_target": bt, "blocks_per_cu": bpc, "stage_us_by_target_and_cap": tune["us"]}}
     del r
     return head
@@ -1108,7 +1127,8 @@ def main():
                               "boxes, gather-fused WENO5 prolongation with FP64 combination"},
            "l1": head["l1"], "linf": head["linf"], "parts_ms": head["parts"],
            "finest_equivalent_cell_updates_per_s": head["finest_equivalent_cell_updates_per_s"],
-           "roofline": head["roofline"], "roofline_other": head["roofline_other"], "cpu_baseline": cpu,
+           "roofline": head["roofline"], "roofline_other": head["roofline_other"],
+           "stage_step_us": head["stage_step_us"], "cpu_baseline": cpu,
            "fp32_sweeps": head["fp32"], "plain": head["plain"], "latency": serving, "batched_2d_burgers": c2,
            "autotune": head["autotune"]}
     print(json.dumps(out), flush=True)

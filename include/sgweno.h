@@ -142,6 +142,10 @@ typedef struct sgw_config {
                                       automatic box search may pick, 64..2048                      */
     int32_t blocks_per_cu;         /* 0: as many resident stage workgroups per compute unit as
                                       fit; else at most this many (1..64), a tuning knob         */
+    int32_t sweep_form;            /* line sweeps of 4D plans: 0 automatic (directions 1 and 2 in one
+                                      launch over whole (x_1, x_2) planes staged in LDS, then one
+                                      launch per remaining direction); 1 one launch per direction.
+                                      Both give the same bits.                                    */
 } sgw_config;
 
 typedef struct sgw_plan sgw_plan_t;

@@ -23,6 +23,17 @@ extern "C" {
  * without advancing t.  Either way the solves' wave-speed slots are disturbed,
  * so re-restrict before trusting later results. */
 sgw_status sgw_batch_launch_stage(sgw_batch_t* batch, int32_t stage, int32_t reps);
+/* Measurement hook for one solver, outside any graph (callers time it with events
+ * on the solver's stream): reps repetitions of one part of RK stage `stage` (0..2)
+ * of the solver's current step, as sgw_advance enqueues it.  part 0: the whole
+ * stage (moment pass, field launch, plane launch, sweeps or boxes); part 1: the
+ * plane launch of a 4D plan (directions 1 and 2); part 2 + k: the line sweep of
+ * direction k + 1 alone (line-mode plans).  Call it after sgw_advance has taken at
+ * least one step; it reopens the solve (the final time goes to infinity) so the
+ * kernels do their work, and it leaves the solve's state meaningless: re-restrict
+ * before trusting later results.  SGW_ERR_INVALID_ARG for a part the plan does
+ * not have. */
+sgw_status sgw_solver_launch_stage(sgw_solver_t* solver, int32_t stage, int32_t part, int32_t reps);
 /* Measurement hook for the VALU issue rates that price kernel issue floors (not
  * part of the method): enqueues on hip_stream one launch of `blocks` workgroups
  * of 256 threads running long chains of independent instructions of one class,

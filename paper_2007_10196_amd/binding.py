@@ -42,7 +42,7 @@ class Config(C.Structure):
                 ("prolong", C.c_int32), ("linear_weights", C.c_int32), ("precision", C.c_int32),
                 ("cfl", C.c_double), ("eps_flux", C.c_double), ("eps_interp", C.c_double),
                 ("box", C.c_int32 * 4), ("fine_tile", C.c_int32 * 4), ("box_target", C.c_int32),
-                ("blocks_per_cu", C.c_int32)]
+                ("blocks_per_cu", C.c_int32), ("sweep_form", C.c_int32)]
 
 
 _lib = None
@@ -101,6 +101,7 @@ _SIGS = {
     "sgw_batch_poll_end": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "sgw_batch_release": (C.c_int32, [C.c_void_p, C.c_int32]),
     "sgw_batch_launch_stage": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
+    "sgw_solver_launch_stage": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
     "sgw_calibrate_valu": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "sgw_batch_set_blocks_per_cu": (C.c_int32, [C.c_void_p, C.c_int32]),
     "sgw_batch_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
@@ -136,7 +137,7 @@ def _pad(v, n, fill=0.0):
     return v + [fill] * (n - len(v))
 
 
-def make_structs(pb, box=None, fine_tile=None, box_target=0, blocks_per_cu=0):
+def make_structs(pb, box=None, fine_tile=None, box_target=0, blocks_per_cu=0, sweep_form=0):
     """Problem/Config structs from a problem description with the fields of
     sgw_inputs.Problem (d, lo, hi, flux, flux_params, ic, ic_params, nr, nl, cfl,
     dt_mode, prolong, linear, precision, eps_flux, eps_interp, bc, relax_tau, relax_theta)."""
@@ -166,4 +167,5 @@ def make_structs(pb, box=None, fine_tile=None, box_target=0, blocks_per_cu=0):
     c.fine_tile[:] = _pad(fine_tile or [], 4, 0)
     c.box_target = int(box_target or 0)
     c.blocks_per_cu = int(blocks_per_cu or 0)
+    c.sweep_form = int(sweep_form or 0)
     return p, c

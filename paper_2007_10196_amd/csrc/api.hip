@@ -575,6 +575,8 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     int target = 1024;
     if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64)
         return sgw_fail(SGW_ERR_INVALID_ARG, "blocks_per_cu %d outside 0..64", cfg->blocks_per_cu);
+    if (cfg->sweep_form < 0 || cfg->sweep_form > 1)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "sweep_form %d outside 0..1", cfg->sweep_form);
     if (cfg->box_target) {
         if (cfg->box_target < 64 || cfg->box_target > SGW_BLOCK * SGW_MAXR) {
             delete p;
@@ -654,6 +656,20 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     }
     p->offsets[p->G] = tot;
     p->total_nodes = tot;
+    // 4D line sweeps: directions 1 and 2 in one launch over whole (x_1, x_2) planes when every grid's
+    // plane fits a work item
+    p->plane01 = d == 4 && p->line_mode && cfg->sweep_form == 0;
+    for (int g = 0; g < p->G && p->plane01; g++)
+        p->plane01 = p->grids[g].line_mode && p->grids[g].n[0] * p->grids[g].n[1] <= SGW_PLANE_CAP;
+    p->nplane_items = 0;
+    if (p->plane01)
+        for (int g = 0; g < p->G; g++) {
+            GridDev& gd = p->grids[g];
+            gd.plane_nodes = gd.n[0] * gd.n[1];
+            gd.nplanes = gd.n[2] * gd.n[3];
+            gd.ppi = SGW_PLANE_CAP / gd.plane_nodes;
+            p->nplane_items += (gd.nplanes + gd.ppi - 1) / gd.ppi;
+        }
     p->zmask = zmask;
     p->relax = relax;
     p->vm = vm;
@@ -783,6 +799,7 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     p->off_rho_part = take(sizeof(double) * (part_elems ? part_elems : 1));
     p->off_rho_items = take(sizeof(RhoItem) * (p->nrho_items + p->nrho_final + 1));
     p->off_vm_alpha = take(sizeof(double) * 6 * (vm ? p->G : 1));
+    p->off_plane_items = take(sizeof(WorkItem) * (p->nplane_items ? p->nplane_items : 1));
     p->scratch_bytes = off;
     *out = p;
     return SGW_OK;
@@ -873,6 +890,7 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
     s->result_d = (double*)(s->scratch + p->off_result);
     s->foot_d = (double*)(s->scratch + p->off_foot);
     s->rho_items_d = (RhoItem*)(s->scratch + p->off_rho_items);
+    s->plane_items_d = (WorkItem*)(s->scratch + p->off_plane_items);
 
     const bool dyn = p->pb.flux == SGW_FLUX_BURGERS;
     const int N = p->N;
@@ -967,6 +985,16 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
         hmin = s->req_h.hfin[k] < hmin ? s->req_h.hfin[k] : hmin;
     }
     s->req_h.dt_pow53 = std::pow(hmin, 5.0 / 3.0);
+    // plane work list (4D): ppi consecutive planes per item, grid by grid
+    s->plane_first.assign(p->G + 1, 0);
+    std::vector<WorkItem> plane_items_h;
+    for (int g = 0; g < p->G; g++) {
+        s->plane_first[g] = (int)plane_items_h.size();
+        if (!p->plane01) continue;
+        const GridDev& gd = p->grids[g];
+        for (int b = 0; b < (gd.nplanes + gd.ppi - 1) / gd.ppi; b++) plane_items_h.push_back(WorkItem{s->grids_d + g, b, 0});
+    }
+    s->plane_first[p->G] = (int)plane_items_h.size();
     // work list: boxes of every grid, grid by grid
     s->items_h.resize(p->nitems);
     for (int g = 0; g < p->G; g++)
@@ -1069,6 +1097,7 @@ extern "C" sgw_status sgw_solver_create(sgw_plan_t* p, void* state_dev, void* sc
     cp(s->scratch + p->off_stab, s->stab_h.data(), s->stab_h.size());
     if (p->relax) cp(s->scratch + p->off_mu, mu_h.data(), sizeof(double) * mu_h.size());
     if (p->relax || p->vm) cp(s->rho_items_d, rho_items_h.data(), sizeof(RhoItem) * rho_items_h.size());
+    if (p->plane01) cp(s->plane_items_d, plane_items_h.data(), sizeof(WorkItem) * plane_items_h.size());
     if (rc == SGW_OK && (p->pb.flux == SGW_FLUX_VLASOV_FIXED_E || p->pb.flux == SGW_FLUX_VLASOV_HARMONIC || p->vm)) {
         hipError_t e = launch_coef_init(s->grids_d, s->grids_h.data(), p->G, s->coef_d, s->coef_off_d, &p->pb, st);
         if (e != hipSuccess) rc = sgw_hip_fail(e, "coefficient tables");
@@ -1229,14 +1258,20 @@ static hipError_t enqueue_step(sgw_solver* s, int mode, hipStream_t st)
             r = launch_vm_fields(s->grids_d, p->G, stage, p->cfg.precision, 0.0, 0.0, p->cfg.linear_weights, st);
         return r;
     };
+    const int first_dir = p->plane01 ? 2 : 0;
     if (mode == SGW_RUN_PLAIN) {
         for (int stage = 0; stage < 3; stage++) {
             e = moments(stage);
             if (e != hipSuccess) return e;
             for (int g = 0; g < p->G; g++) {
+                if (p->plane01) {
+                    e = launch_planes(s->plane_items_d + s->plane_first[g], s->plane_first[g + 1] - s->plane_first[g],
+                                      stage, p->cfg.precision, st);
+                    if (e != hipSuccess) return e;
+                }
                 e = launch_stage(s->items_d + p->grids[g].first_item, p->grids[g].nbox, stage, p->cfg.precision,
                                  p->pb.dim, stage_lds_bytes(p->grids[g], p->cfg.precision), 0, st,
-                                 p->grids[g].line_mode != 0);
+                                 p->grids[g].line_mode != 0, first_dir);
                 if (e != hipSuccess) return e;
             }
         }
@@ -1251,11 +1286,54 @@ static hipError_t enqueue_step(sgw_solver* s, int mode, hipStream_t st)
     for (int stage = 0; stage < 3 && nbx; stage++) {
         e = moments(stage);
         if (e != hipSuccess) return e;
+        if (p->plane01) {
+            e = launch_planes(s->plane_items_d, (int)p->nplane_items, stage, p->cfg.precision, st);
+            if (e != hipSuccess) return e;
+        }
         e = launch_stage(s->items_d + nw, nbx, stage, p->cfg.precision, p->pb.dim, p->lds_boxed, s->grid, st,
-                         p->line_mode);
+                         p->line_mode, first_dir);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+extern "C" sgw_status sgw_solver_launch_stage(sgw_solver_t* s, int32_t stage, int32_t part, int32_t reps)
+{
+    if (!s) return sgw_fail(SGW_ERR_INVALID_ARG, "null solver");
+    if (stage < 0 || stage > 2 || reps < 0) return sgw_fail(SGW_ERR_INVALID_ARG, "stage %d or reps %d", stage, reps);
+    if (!s->restricted) return sgw_fail(SGW_ERR_STATE, "launch before restrict");
+    const sgw_plan* p = s->plan;
+    const int d = p->pb.dim;
+    if (part < 0 || part > 1 + d || (part == 1 && !p->plane01) || (part >= 2 && !p->line_mode))
+        return sgw_fail(SGW_ERR_INVALID_ARG, "part %d is not a part of this plan's stage", part);
+    // reopen the solve so that every launch does its work
+    HIPCHK(launch_req_set_final(s->req_d, INFINITY, s->stream), "reopen");
+    const int nw = (int)p->nitems_whole, nbx = (int)(p->nitems - p->nitems_whole);
+    for (int r = 0; r < reps; r++) {
+        hipError_t e = hipSuccess;
+        if (part == 0) {
+            if (p->relax || p->vm) e = launch_rho(s->rho_items_d, (int)p->nrho_items, (int)p->nrho_final, stage,
+                                                  p->cfg.precision, s->stream);
+            if (e == hipSuccess && p->vm)
+                e = launch_vm_fields(s->grids_d, p->G, stage, p->cfg.precision, 0.0, 0.0, p->cfg.linear_weights,
+                                     s->stream);
+            if (e == hipSuccess && p->plane01)
+                e = launch_planes(s->plane_items_d, (int)p->nplane_items, stage, p->cfg.precision, s->stream);
+            if (e == hipSuccess && nw)
+                e = launch_stage(s->items_d, nw, SGW_STAGE_FUSED, p->cfg.precision, d, p->lds_whole, s->grid_whole,
+                                 s->stream);
+            if (e == hipSuccess && nbx)
+                e = launch_stage(s->items_d + nw, nbx, stage, p->cfg.precision, d, p->lds_boxed, s->grid, s->stream,
+                                 p->line_mode, p->plane01 ? 2 : 0);
+        } else if (part == 1) {
+            e = launch_planes(s->plane_items_d, (int)p->nplane_items, stage, p->cfg.precision, s->stream);
+        } else {
+            e = launch_stage(s->items_d + nw, nbx, stage, p->cfg.precision, d, p->lds_boxed, s->grid, s->stream, true,
+                             part - 2, part - 2);
+        }
+        if (e != hipSuccess) return sgw_hip_fail(e, "measured stage launch");
+    }
+    return SGW_OK;
 }
 
 static sgw_status build_graph(sgw_solver* s, int steps_per_graph)

@@ -33,6 +33,8 @@ struct sgw_plan {
     uint64_t fields_off = 0;                   // byte offset of the fields in a state copy
     int64_t fields_total = 0;                  // field values over all grids (3 n_1 each)
     int zmask = 0;                             // bit k: zero boundary in direction k
+    bool plane01 = false;                      // 4D: directions 1 and 2 in one plane launch per stage
+    int64_t nplane_items = 0;                  // its work items over all grids
     int64_t nrho_items = 0;                    // density first-pass work items over all grids
     int64_t nrho_final = 0;                    // density second-pass work items (column blocks)
     std::vector<int64_t> mu_off;               // [G][4] offsets into the velocity factor tables
@@ -41,7 +43,7 @@ struct sgw_plan {
     uint64_t copy_bytes = 0, state_bytes = 0, scratch_bytes = 0;
     uint64_t off_grids = 0, off_req = 0, off_items = 0, off_alpha = 0, off_coef = 0, off_coef_off = 0;
     uint64_t off_pro = 0, off_fine = 0, off_partials = 0, off_result = 0, off_foot = 0, off_stab = 0;
-    uint64_t off_mu = 0, off_rho = 0, off_rho_part = 0, off_rho_items = 0, off_vm_alpha = 0;
+    uint64_t off_mu = 0, off_rho = 0, off_rho_part = 0, off_rho_items = 0, off_vm_alpha = 0, off_plane_items = 0;
 };
 
 struct sgw_solver {
@@ -61,6 +63,8 @@ struct sgw_solver {
     double* result_d = nullptr;
     double* foot_d = nullptr;
     RhoItem* rho_items_d = nullptr;
+    WorkItem* plane_items_d = nullptr;
+    std::vector<int> plane_first;              // first plane item of each grid (G + 1 entries)
     std::vector<GridDev> grids_h;
     std::vector<WorkItem> items_h;
     std::vector<ProDev> pro_h;

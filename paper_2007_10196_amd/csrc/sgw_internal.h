@@ -151,7 +151,13 @@ struct alignas(64) GridDev {
     int32_t vm, nmom;                // nmom: moments of the moment launch (1: rho; 2: j_1, j_2)
     int64_t fld_bytes;
     double* vm_alpha;                // [3 stages][2]: LF speeds of xi_1, xi_2 of each stage's fields
+    // 4D plane launch: directions 1 and 2 of a stage over whole (x_1, x_2) planes in LDS, ppi
+    // consecutive planes (n[0] n[1] nodes each, contiguous) per work item
+    int32_t ppi, nplanes, plane_nodes, pad3_;
 };
+
+// nodes of one plane-launch work item (its planes staged in LDS, with their flux sums)
+#define SGW_PLANE_CAP 2048
 
 // density launch: SGW_RHO_COLS x nodes per workgroup, SGW_BLOCK / SGW_RHO_COLS row lanes,
 // SGW_RHO_RPT rows per lane and chunk
@@ -307,7 +313,9 @@ hipError_t launch_dt_one(ReqDev* req, hipStream_t s);
 // stage SGW_STAGE_FUSED: the three stages of whole-grid boxes in one launch.  lines: the
 // items are line-sweep items (4D), one launch per direction.
 hipError_t launch_stage(const WorkItem* items, int nitems, int stage, int precision, int dim, size_t lds_bytes,
-                        int grid_cap, hipStream_t s, bool lines = false);
+                        int grid_cap, hipStream_t s, bool lines = false, int first_dir = 0, int last_dir = 3);
+// 4D: directions 1 and 2 of stage `stage` over the plane work items[0..nitems)
+hipError_t launch_planes(const WorkItem* items, int nitems, int stage, int precision, hipStream_t s);
 // the same over items[range_dev[0] .. + range_dev[1]) read on the device (batches, graphs)
 hipError_t launch_stage_range(const WorkItem* items, const int* range_dev, int blocks, int stage, int precision,
                               int dim, size_t lds_bytes, hipStream_t s, bool lines = false);

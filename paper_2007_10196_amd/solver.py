@@ -17,9 +17,9 @@ from . import binding as B
 class Plan:
     """Host-only plan: the component grids of the index set, their layout and tiling."""
 
-    def __init__(self, problem, box=None, fine_tile=None, box_target=0, blocks_per_cu=0):
+    def __init__(self, problem, box=None, fine_tile=None, box_target=0, blocks_per_cu=0, sweep_form=0):
         self.problem = problem
-        self._pb, self._cfg = B.make_structs(problem, box, fine_tile, box_target, blocks_per_cu)
+        self._pb, self._cfg = B.make_structs(problem, box, fine_tile, box_target, blocks_per_cu, sweep_form)
         h = C.c_void_p()
         B.check(B.lib().sgw_plan_create(C.byref(self._pb), C.byref(self._cfg), C.byref(h)))
         self.handle = h
@@ -70,11 +70,11 @@ class Solver:
 
     def __init__(self, problem, device: str = "cuda", stream: Optional[torch.cuda.Stream] = None,
                  box=None, fine_tile=None, plan: Optional[Plan] = None, box_target: int = 0,
-                 blocks_per_cu: int = 0):
+                 blocks_per_cu: int = 0, sweep_form: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("sgweno needs a ROCm GPU; none is visible")
         self.problem = problem
-        self.plan = plan or Plan(problem, box, fine_tile, box_target, blocks_per_cu)
+        self.plan = plan or Plan(problem, box, fine_tile, box_target, blocks_per_cu, sweep_form)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         # torch's caching allocator returns 512-byte aligned blocks
@@ -121,6 +121,12 @@ class Solver:
         res = (C.c_double * 2)()
         B.check(B.lib().sgw_norms(self.handle, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), res))
         return res[0], res[1]
+
+    def launch_stage(self, stage: int, part: int = 0, reps: int = 1):
+        """Measurement hook: reps repetitions of one part of RK stage `stage` on the solver stream
+        (part 0 the whole stage, 1 the 4D plane launch, 2 + k the line sweep of direction k + 1);
+        leaves the solve's state meaningless."""
+        B.check(B.lib().sgw_solver_launch_stage(self.handle, stage, part, reps))
 
     def fields(self, which: int = 0) -> torch.Tensor:
         """Vlasov-Maxwell: the FP64 fields of every grid (B_3, E_1, E_2 at its x_2 nodes, grids back

@@ -129,6 +129,27 @@ def test_4d_line_sweep_equals_box_kernel_bitwise():
                 assert np.max(np.abs(U_l.cpu().numpy() - U_o)) <= TOL64
 
 
+def test_4d_plane_launch_equals_four_line_launches_bitwise():
+    """4D stages run directions 1 and 2 in one launch over whole (x_1, x_2) planes in LDS, then line
+    sweeps for directions 3 and 4 (sweep_form 0); sweep_form 1 runs four line sweeps.  The two give
+    the same bits for every flux kind, linear weights, zero boundaries with relaxation, FP64 and FP32,
+    in the graph and the per-grid modes."""
+    cases = []
+    for prec in (W.PREC_FP64, W.PREC_FP32):
+        cases += [(pb, 2) for pb in _four_d_cases(prec)]
+        cases.append((W.paper_example5(4, nr=4, nl=2, T=0.1, precision=prec), 2))
+    cases.append((W.c4_vlasov_4d(nl=2, T=0.1, precision=W.PREC_FP64).replace(linear=True), 2))
+    cases.append((W.c4_vlasov_4d(nl=2, T=0.1, precision=W.PREC_FP64), 0))
+    for pb, mode in cases:
+        _announce(f"4D plane launch vs line launches {pb.name} nr={pb.nr} nl={pb.nl} precision={pb.precision} "
+                  f"mode={mode}")
+        _, st_p, U_p, t_p, n_p = gpu_solve(pb, mode)
+        _, st_l, U_l, t_l, n_l = gpu_solve(pb, mode, sweep_form=1)
+        assert n_p == n_l and t_p == t_l
+        assert np.array_equal(st_p, st_l)
+        assert bool((U_p == U_l).all())
+
+
 def test_paper_sparse_weno_row_on_gpu():
     # Table ex3aweno, sparse grid with WENO prolongation, N_r = 10, N_L = 3 (N_h = 80)
     pb = W.paper_example3a(80, nr=10, nl=3)
