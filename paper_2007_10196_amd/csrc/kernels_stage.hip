@@ -816,7 +816,9 @@ __global__ void __launch_bounds__(SGW_LWAVE) line_kernel(const WorkItem* __restr
 // segments of SGW_PSEG nodes: a work item of SGW_PLANE_CAP nodes gives every thread one segment
 // per direction (a flux depends only on its window's values, so the segment length does not change
 // the bits; 4-node segments over 1024-node items measured 8 % slower on the 4D Vlasov solve)
+#ifndef SGW_PSEG
 #define SGW_PSEG 8
+#endif
 //
 // A work item is ppi consecutive (x_1, x_2) planes of one 4D grid (contiguous in memory, at most
 // SGW_PLANE_CAP nodes).  The workgroup stages them in LDS, forms the direction-1 flux differences of

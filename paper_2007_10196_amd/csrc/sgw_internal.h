@@ -157,7 +157,9 @@ struct alignas(64) GridDev {
 };
 
 // nodes of one plane-launch work item (its planes staged in LDS, with their flux sums)
+#ifndef SGW_PLANE_CAP
 #define SGW_PLANE_CAP 2048
+#endif
 
 // density launch: SGW_RHO_COLS x nodes per workgroup, SGW_BLOCK / SGW_RHO_COLS row lanes,
 // SGW_RHO_RPT rows per lane and chunk
