@@ -608,14 +608,15 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
         }
         if ((d == 4 || zmask || relax || vm) && !manual) {
             // 4D, zero boundaries and relaxation: the line sweep (no stage boxes); a work item
-            // is SGW_LWAVE segments of SGW_LSEG nodes, enough items for the direction with the
+            // is SGW_LWAVE segments of sgw_lseg() nodes, enough items for the direction with the
             // most segments
             gd.line_mode = 1;
             gd.zmask = zmask;
             int64_t most = 0;
             for (int k = 0; k < SGW_MAX_DIM; k++) gd.fd_n[k] = make_fastdiv((uint32_t)gd.n[k]);
             for (int k = 0; k < d; k++) {
-                gd.lsegl[k] = (gd.n[k] + SGW_LSEG - 1) / SGW_LSEG;
+                const int ls = sgw_lseg(cfg->precision == SGW_FP64);
+                gd.lsegl[k] = (gd.n[k] + ls - 1) / ls;
                 gd.ltrans[k] = (int32_t)(n / gd.n[k]);
                 gd.fd_lsegl[k] = make_fastdiv((uint32_t)gd.lsegl[k]);
                 gd.fd_ltrans[k] = make_fastdiv((uint32_t)gd.ltrans[k]);

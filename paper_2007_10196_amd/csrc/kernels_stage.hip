@@ -614,9 +614,9 @@ __global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __rest
 // ---------------------------------------------------------------- line sweep (4D; zero boundary, relaxation)
 //
 // The same stage with one launch per direction k and no halo: a lane takes a segment of
-// SGW_LSEG nodes of one grid line along k, reads the SGW_LSEG + 6 values its interface fluxes
+// sgw_lseg() nodes of one grid line along k, reads the 6 more values its interface fluxes
 // need (periodic wrap along the line, or 0 beyond a zero boundary) straight from memory,
-// forms the SGW_LSEG + 1 fluxes with window_fluxes (the box kernel's arithmetic, so the same
+// forms their fluxes with window_fluxes (the box kernel's arithmetic, so the same
 // bits) and adds (F_{i-1/2} - F_{i+1/2}) / h_k of its nodes to the sum of the earlier
 // directions.  That partial sum waits in a state copy the stage does not read: the stage
 // output for stages 1 and 2, the stage-1 buffer in stage 3.  The last direction adds the
@@ -626,6 +626,7 @@ __global__ void __launch_bounds__(SGW_BLOCK) stage_kernel(const WorkItem* __rest
 template <typename Real, int D, int k, bool LIN, bool ZB>
 __device__ __forceinline__ void line_segment(GridC g, int blk, int stage, Real alpha, Real& amax)
 {
+    constexpr int SGW_LS = sgw_lseg(sizeof(Real) == 8);
     const int lane = threadIdx.x;
     const int n = g->n[k], segl = g->lsegl[k], trans = g->ltrans[k];
     const int sid = blk * SGW_LWAVE + lane;
@@ -669,23 +670,23 @@ __device__ __forceinline__ void line_segment(GridC g, int blk, int stage, Real a
         }
     }
     const int stride = g->stride[k];
-    const int i0 = q * SGW_LSEG;
+    const int i0 = q * SGW_LS;
     const Real* __restrict__ in = (const Real*)(stage == 0 ? g->u : stage == 1 ? g->a : g->b);
-    Real v[SGW_LSEG + 6]; // u_{i0-3} .. u_{i0+SGW_LSEG+2}
+    Real v[SGW_LS + 6]; // u_{i0-3} .. u_{i0+SGW_LS+2}
     if (ZB && ((g->zmask >> k) & 1)) {
         // zero boundary: nothing wraps, positions beyond either end read 0
 #pragma unroll
-        for (int c = 0; c < SGW_LSEG + 6; c++) {
+        for (int c = 0; c < SGW_LS + 6; c++) {
             const int p = i0 - 3 + c;
             v[c] = (p >= 0 && p < n) ? in[base + p * stride] : Real(0);
         }
     } else if ((g->pow2_mask >> k) & 1) {
 #pragma unroll
-        for (int c = 0; c < SGW_LSEG + 6; c++) v[c] = in[base + ((i0 - 3 + c) & (n - 1)) * stride];
+        for (int c = 0; c < SGW_LS + 6; c++) v[c] = in[base + ((i0 - 3 + c) & (n - 1)) * stride];
     } else {
         // n >= 4: positions -3 .. n + 9 need at most one addition or three subtractions
 #pragma unroll
-        for (int c = 0; c < SGW_LSEG + 6; c++) {
+        for (int c = 0; c < SGW_LS + 6; c++) {
             int p = i0 - 3 + c;
             p += p < 0 ? n : 0;
             p -= p >= n ? n : 0;
@@ -698,9 +699,9 @@ __device__ __forceinline__ void line_segment(GridC g, int blk, int stage, Real a
     // segment's nodes are loaded with the window, so their latency overlaps it
     Real* __restrict__ part = (Real*)(stage == 1 ? g->b : g->a);
     const Real* __restrict__ u0 = (const Real*)g->u;
-    Real pin[SGW_LSEG], un[SGW_LSEG];
+    Real pin[SGW_LS], un[SGW_LS];
 #pragma unroll
-    for (int i = 0; i < SGW_LSEG; i++) {
+    for (int i = 0; i < SGW_LS; i++) {
         const bool in_line = i0 + i < n;
         const int gi = base + (i0 + i) * stride;
         pin[i] = (k > 0 && in_line) ? part[gi] : Real(0);
@@ -731,12 +732,12 @@ __device__ __forceinline__ void line_segment(GridC g, int blk, int stage, Real a
         cp = Real(0.5) * (c + alpha);
         cm = Real(0.5) * (c - alpha);
     }
-    Real F[SGW_LSEG + 1]; // F_{i0-1/2} .. F_{i0+SGW_LSEG-1/2}
-    window_fluxes<Real, SGW_LSEG + 1, LIN>(v, burgers, cp, cm, alpha, (Real)(g->eps * 4.0), F);
+    Real F[SGW_LS + 1]; // F_{i0-1/2} .. F_{i0+SGW_LS-1/2}
+    window_fluxes<Real, SGW_LS + 1, LIN>(v, burgers, cp, cm, alpha, (Real)(g->eps * 4.0), F);
     const Real ih = (Real)g->inv_h[k];
     if constexpr (!last) {
 #pragma unroll
-        for (int i = 0; i < SGW_LSEG; i++)
+        for (int i = 0; i < SGW_LS; i++)
             if (i0 + i < n) part[base + (i0 + i) * stride] = fma(F[i] - F[i + 1], ih, pin[i]);
         return;
     }
@@ -752,7 +753,7 @@ __device__ __forceinline__ void line_segment(GridC g, int blk, int stage, Real a
         itau = (Real)g->inv_tau;
     }
 #pragma unroll
-    for (int i = 0; i < SGW_LSEG; i++)
+    for (int i = 0; i < SGW_LS; i++)
         if (i0 + i < n) {
             Real acc = fma(F[i] - F[i + 1], ih, pin[i]);
             if (relax) acc = fma(fma(rmu, (Real)muk[i0 + i], -v[i + 3]), itau, acc);
@@ -817,7 +818,7 @@ __global__ void __launch_bounds__(SGW_LWAVE) line_kernel(const WorkItem* __restr
 // per direction (a flux depends only on its window's values, so the segment length does not change
 // the bits; 4-node segments over 1024-node items measured 8 % slower on the 4D Vlasov solve)
 #ifndef SGW_PSEG
-#define SGW_PSEG 8
+#define SGW_PSEG 8  // the plane launch keeps 8-node segments in both precisions
 #endif
 //
 // A work item is ppi consecutive (x_1, x_2) planes of one 4D grid (contiguous in memory, at most
