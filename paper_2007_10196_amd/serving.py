@@ -1,10 +1,13 @@
 """Continuous-batching serving loop over the batch runtime (sgw_batch_*).
 
 Requests arrive over time (each with a problem and an arrival time on the host
-monotonic clock).  The loop admits queued requests in arrival order while a
-batch slot is free and the request's device footprint (state + scratch +
-finest-grid output) fits the HBM budget, so a request that arrives while others
-are on the GPU joins the next time step of the running batch.  Each tick
+monotonic clock).  The loop admits queued requests while a batch slot is free
+and the request's device footprint (state + scratch + finest-grid output) fits
+the HBM budget, so a request that arrives while others are on the GPU joins the
+next time step of the running batch.  Admission goes in arrival order and
+backfills: a request that does not fit what is left of the budget is passed
+over by later ones that do, until it has waited ``max_bypass_s``; from then on
+nothing behind it is admitted before it (no starvation of large requests).  Each tick
 advances every admitted solve by a few time steps (graph launches on the batch
 stream) and reads the completion flags gathered after the previous tick, whose
 copy overlapped this tick's steps.  A finished solve leaves the batch and is prolongated and
@@ -22,6 +25,24 @@ import torch
 
 from . import binding as B
 from .solver import Batch, Plan, Solver
+
+
+def backfill_choice(footprints: List[int], waits: List[float], used: int, budget: int, free_slots: int,
+                    max_bypass_s: float) -> List[int]:
+    """Positions (in arrival order) of the queued requests to admit now: every request whose
+    footprint fits what is left of the budget, at most ``free_slots`` of them; a request that does
+    not fit is passed over while it has waited less than ``max_bypass_s``, and stops the scan once
+    it has waited that long (``max_bypass_s = 0``: strict arrival order)."""
+    picks: List[int] = []
+    for i, (fp, wait) in enumerate(zip(footprints, waits)):
+        if len(picks) >= free_slots:
+            break
+        if used + fp <= budget:
+            picks.append(i)
+            used += fp
+        elif wait >= max_bypass_s:
+            break
+    return picks
 
 
 @dataclasses.dataclass
@@ -43,8 +64,9 @@ class Result:
 class ServingLoop:
     def __init__(self, precision: int = B.FP32_SWEEP, max_active: int = 64, hbm_budget: int = 64 << 30,
                  steps_per_tick: int = 8, keep_outputs: bool = False, box_target: int = 0,
-                 blocks_per_cu: int = 0, device: str = "cuda"):
+                 blocks_per_cu: int = 0, device: str = "cuda", max_bypass_s: float = 0.5):
         self.precision = precision
+        self.max_bypass_s = max_bypass_s
         self.max_active = max_active
         self.budget = int(hbm_budget)
         self.steps_per_tick = steps_per_tick
@@ -78,27 +100,35 @@ class ServingLoop:
             now = clock() - t0
             while pending and pending[0].arrival_s <= now:
                 queue.append(pending.popleft())
-            # admission in arrival order, by slot and device footprint
-            while queue and len(active) < self.max_active:
-                req = queue[0]
-                plan = plans.get(req.rid)
-                if plan is None:
-                    tp = clock()
-                    plan = plans[req.rid] = Plan(req.problem, box_target=self.box_target)
-                    self.stats["plan"] += clock() - tp
-                if used + plan.footprint > self.budget:
-                    if not active and not finishing:
-                        raise MemoryError(f"request {req.rid} needs {plan.footprint} B, budget {self.budget} B")
-                    break
+            # admission by slot and device footprint, in arrival order with backfilling
+            if queue and len(active) < self.max_active:
                 tp = clock()
-                with torch.cuda.stream(self.setup):
-                    solver = Solver(req.problem, device=str(self.device), stream=self.setup, plan=plan)
-                    solver.restrict()
-                slot = self.batch.admit(solver)  # orders the restriction before the batch's next step
-                self.stats["admit"] += clock() - tp
-                queue.popleft()
-                used += plan.footprint
-                active[slot] = (req, solver, clock() - t0, plan.footprint)
+                for req in queue:
+                    if req.rid not in plans:
+                        plans[req.rid] = Plan(req.problem, box_target=self.box_target)
+                self.stats["plan"] += clock() - tp
+                for req in queue:
+                    if plans[req.rid].footprint > self.budget:
+                        raise MemoryError(f"request {req.rid} needs {plans[req.rid].footprint} B, "
+                                          f"budget {self.budget} B")
+                now = clock() - t0
+                picks = backfill_choice([plans[r.rid].footprint for r in queue], [now - r.arrival_s for r in queue],
+                                        used, self.budget, self.max_active - len(active), self.max_bypass_s)
+                admitted = set()
+                for i in picks:
+                    req = queue[i]
+                    plan = plans[req.rid]
+                    tp = clock()
+                    with torch.cuda.stream(self.setup):
+                        solver = Solver(req.problem, device=str(self.device), stream=self.setup, plan=plan)
+                        solver.restrict()
+                    slot = self.batch.admit(solver)  # orders the restriction before the batch's next step
+                    self.stats["admit"] += clock() - tp
+                    used += plan.footprint
+                    active[slot] = (req, solver, clock() - t0, plan.footprint)
+                    admitted.add(i)
+                if admitted:
+                    queue = collections.deque(r for i, r in enumerate(queue) if i not in admitted)
             # solves whose combination has completed
             still = []
             for req, solver, admit_s, fp, ev, U, steps in finishing:

@@ -114,6 +114,35 @@ def test_admission_waits_for_memory_and_rejects_oversize():
     tiny.close()
 
 
+def test_admission_backfills_past_a_request_that_does_not_fit():
+    """Three requests queued at once, the largest first: the second largest does not fit beside it,
+    the smallest does.  With backfilling the smallest is admitted before the second largest; with a
+    bypass bound of 0 admission keeps arrival order.  Every result is bitwise the same either way."""
+    import torch
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.serving import ServingLoop
+    from paper_2007_10196_amd.solver import Plan
+    pool = _mixed_stream(n=12, seed=9, levels=(3,))
+    pool.sort(key=lambda r: Plan(r.problem).footprint)
+    small, big2, big1 = pool[0], pool[-2], pool[-1]
+    fp = {r.rid: Plan(r.problem).footprint for r in (small, big2, big1)}
+    assert fp[big2.rid] > fp[small.rid]
+    budget = fp[big1.rid] + fp[small.rid] + (fp[big2.rid] - fp[small.rid]) // 2
+    reqs = [W.Request(rid=i, arrival_s=0.0, problem=r.problem, family=r.family)
+            for i, r in enumerate((big1, big2, small))]
+    runs = {}
+    for bound in (10.0, 0.0):
+        loop = ServingLoop(precision=B.FP32_SWEEP, max_active=8, hbm_budget=budget, keep_outputs=True,
+                           max_bypass_s=bound)
+        runs[bound] = {r.rid: r for r in loop.run(reqs)}
+        loop.close()
+    bf, fifo = runs[10.0], runs[0.0]
+    assert bf[2].admit_s < bf[1].admit_s
+    assert fifo[2].admit_s >= fifo[1].admit_s
+    for rid in range(3):
+        assert torch.equal(bf[rid].out, fifo[rid].out)
+
+
 def test_autotuner_picks_and_caches(tmp_path):
     from paper_2007_10196_amd import binding as B
     from paper_2007_10196_amd.autotune import tune_box_target
