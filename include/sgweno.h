@@ -197,6 +197,9 @@ sgw_status sgw_plan_fields(const sgw_plan_t* plan, uint64_t* offset_bytes, int64
 /* Finest-grid tile the prolongation kernel uses (one workgroup per tile). */
 sgw_status sgw_plan_fine_tile(const sgw_plan_t* plan, int32_t tile[SGW_MAX_DIM]);
 
+/* Number of finest-grid tiles of the prolongation: prod_k N / tile[k]. */
+sgw_status sgw_plan_fine_tile_count(const sgw_plan_t* plan, int64_t* count);
+
 /* Box extents the stage kernel uses for grid g (one workgroup per box).  4D grids
  * without manual boxes, and every grid of a plan with a zero boundary, relaxation or the
  * Vlasov-Maxwell flux,
@@ -232,6 +235,16 @@ sgw_status sgw_advance(sgw_solver_t* solver, double t_final, int32_t mode);
  * P the dimension-by-dimension WENO5 (or Lagrange5) prolongation of Sec. 2.2.1
  * in increasing direction order; accumulated in FP64 in grid order. */
 sgw_status sgw_prolongate_combine(sgw_solver_t* solver, double* out_dev);
+
+/* Step 3 over part of the finest grid: the same values as sgw_prolongate_combine at the
+ * finest-grid tiles first_tile .. first_tile + num_tiles - 1 (tiles of the extents
+ * sgw_plan_fine_tile reports, numbered with direction 1 fastest; sgw_plan_fine_tile_count
+ * gives their number), bitwise; every other entry of out_dev is left as it was.  Calls over
+ * ranges that cover every tile once give sgw_prolongate_combine's output, so a caller can
+ * spread a large combination over several launches (a serving loop interleaving it with other
+ * solves' steps).  SGW_ERR_INVALID_ARG for a range outside 0..count; num_tiles 0 is a no-op. */
+sgw_status sgw_prolongate_combine_tiles(sgw_solver_t* solver, double* out_dev, int64_t first_tile,
+                                        int64_t num_tiles);
 
 /* Exact solution at time t on the finest grid (FP64), for the error norms:
  * advection: u0(x - a t); Burgers with a sine: characteristics solved by

@@ -57,6 +57,7 @@ _SIGS = {
     "sgw_plan_grid": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32 * 4, C.c_int32 * 4, C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int64)]),
     "sgw_plan_fine_tile": (C.c_int32, [C.c_void_p, C.c_int32 * 4]),
+    "sgw_plan_fine_tile_count": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
     "sgw_plan_grid_box": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32 * 4]),
     "sgw_solver_create": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "sgw_solver_free": (None, [C.c_void_p]),
@@ -64,6 +65,7 @@ _SIGS = {
     "sgw_restrict_initial": (C.c_int32, [C.c_void_p]),
     "sgw_advance": (C.c_int32, [C.c_void_p, C.c_double, C.c_int32]),
     "sgw_prolongate_combine": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "sgw_prolongate_combine_tiles": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64]),
     "sgw_exact": (C.c_int32, [C.c_void_p, C.c_double, C.c_void_p]),
     "sgw_norms": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "sgw_entropies": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),

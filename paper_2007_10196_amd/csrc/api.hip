@@ -850,6 +850,15 @@ extern "C" sgw_status sgw_plan_fine_tile(const sgw_plan_t* p, int32_t tile[SGW_M
     return SGW_OK;
 }
 
+extern "C" sgw_status sgw_plan_fine_tile_count(const sgw_plan_t* p, int64_t* count)
+{
+    if (!p || !count) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    int64_t n = 1;
+    for (int k = 0; k < p->pb.dim; k++) n *= p->N / p->fine_T[k];
+    *count = n;
+    return SGW_OK;
+}
+
 extern "C" sgw_status sgw_plan_grid_box(const sgw_plan_t* p, int32_t g, int32_t box[SGW_MAX_DIM])
 {
     if (!p || g < 0 || g >= p->G || !box) return sgw_fail(SGW_ERR_INVALID_ARG, "bad grid");
@@ -1432,14 +1441,29 @@ extern "C" sgw_status sgw_advance(sgw_solver_t* s, double t_final, int32_t mode)
     return SGW_OK;
 }
 
-extern "C" sgw_status sgw_prolongate_combine(sgw_solver_t* s, double* out_dev)
+static int64_t fine_tiles(const sgw_solver* s);
+
+extern "C" sgw_status sgw_prolongate_combine_tiles(sgw_solver_t* s, double* out_dev, int64_t first_tile,
+                                                   int64_t num_tiles)
 {
     if (!s || !out_dev) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
     if (!s->restricted) return sgw_fail(SGW_ERR_STATE, "prolongate before restrict");
+    const int64_t nt = fine_tiles(s);
+    if (first_tile < 0 || num_tiles < 0 || first_tile > nt || num_tiles > nt - first_tile)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "tiles %lld + %lld outside 0..%lld", (long long)first_tile,
+                        (long long)num_tiles, (long long)nt);
+    if (nt > 0x7fffffff) return sgw_fail(SGW_ERR_UNSUPPORTED, "too many tiles");
     const sgw_plan* p = s->plan;
-    const size_t lds = p->pro_lds;
-    HIPCHK(launch_prolong(s->pro_d, s->fine_d, s->fine_h, p->cfg.precision, lds, out_dev, s->stream), "prolongate");
+    HIPCHK(launch_prolong(s->pro_d, s->fine_d, s->fine_h, p->cfg.precision, p->pro_lds, out_dev, (int)first_tile,
+                          (int)num_tiles, s->stream),
+           "prolongate");
     return SGW_OK;
+}
+
+extern "C" sgw_status sgw_prolongate_combine(sgw_solver_t* s, double* out_dev)
+{
+    if (!s || !out_dev) return sgw_fail(SGW_ERR_INVALID_ARG, "null argument");
+    return sgw_prolongate_combine_tiles(s, out_dev, 0, fine_tiles(s));
 }
 
 extern "C" sgw_status sgw_exact(sgw_solver_t* s, double t, double* out_dev)

@@ -561,15 +561,16 @@ __device__ __forceinline__ void prolong_any(ProC pro, FineC F, double* out, int 
 }
 
 template <typename Real, int D>
-__global__ void __launch_bounds__(SGW_BLOCK) prolong_kernel(const ProDev* pro, const FineDev* fine, double* out)
+__global__ void __launch_bounds__(SGW_BLOCK) prolong_kernel(const ProDev* pro, const FineDev* fine, double* out,
+                                                            int first_tile)
 {
     // XCD-aware order: workgroups go to the 8 XCDs in turn, so XCD x takes the contiguous tile
-    // range [x n/8, (x+1) n/8) and neighbouring tiles share its L2 (coarse blocks, partly written
-    // output lines)
+    // range [x n/8, (x+1) n/8) of the launch's tiles first_tile .. first_tile + n - 1 and
+    // neighbouring tiles share its L2 (coarse blocks, partly written output lines)
     int b = blockIdx.x;
     const int nt = gridDim.x;
     if ((nt & 7) == 0) b = (b & 7) * (nt >> 3) + (b >> 3);
-    prolong_any<Real, D>((ProC)pro, (FineC)fine, out, b);
+    prolong_any<Real, D>((ProC)pro, (FineC)fine, out, first_tile + b);
 }
 
 // one workgroup per (solve, tile) over many solves of one dimension and precision
@@ -816,12 +817,12 @@ hipError_t launch_fields_combine(const GridDev* grids_dev, const ProDev* pro_dev
 }
 
 hipError_t launch_prolong(const ProDev* pro_dev, const FineDev* fine_dev, const FineDev& fh, int precision,
-                          size_t lds_bytes, double* out, hipStream_t s)
+                          size_t lds_bytes, double* out, int first_tile, int num_tiles, hipStream_t s)
 {
-    int tiles = 1;
-    for (int k = 0; k < fh.d; k++) tiles *= fh.ntile[k];
-#define SGW_PRO(R, DD) \
-    hipLaunchKernelGGL((prolong_kernel<R, DD>), dim3(tiles), dim3(SGW_BLOCK), lds_bytes, s, pro_dev, fine_dev, out)
+    if (num_tiles <= 0) return hipSuccess;
+#define SGW_PRO(R, DD)                                                                                       \
+    hipLaunchKernelGGL((prolong_kernel<R, DD>), dim3(num_tiles), dim3(SGW_BLOCK), lds_bytes, s, pro_dev, fine_dev, \
+                       out, first_tile)
     if (precision == SGW_FP64) {
         switch (fh.d) {
         case 1: SGW_PRO(double, 1); break;

@@ -332,8 +332,10 @@ size_t stage_lds_bytes(const GridDev& g, int precision);
 int stage_occupancy(int precision, int dim, size_t lds_bytes, bool fused = false);
 // persistent grid: blocks per CU x CUs
 int stage_grid(int precision, int dim, size_t lds_bytes, int blocks_per_cu, bool fused = false);
+// finest-grid tiles first_tile .. first_tile + num_tiles - 1 (tile index: direction 1 fastest)
 hipError_t launch_prolong(const ProDev* pro_dev, const FineDev* fine_dev, const FineDev& fine_host,
-                          int precision, size_t lds_bytes, double* out, hipStream_t s);
+                          int precision, size_t lds_bytes, double* out, int first_tile, int num_tiles,
+                          hipStream_t s);
 // items: one per solve (n <= 65535); max_tiles: the largest ntiles
 hipError_t launch_prolong_many(const ProItem* items, int nitems, int max_tiles, int d, int precision,
                                size_t lds_bytes, hipStream_t s);

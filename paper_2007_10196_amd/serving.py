@@ -12,7 +12,9 @@ advances every admitted solve by a few time steps (graph launches on the batch
 stream) and reads the completion flags gathered after the previous tick, whose
 copy overlapped this tick's steps.  A finished solve leaves the batch and is prolongated and
 combined on a second stream while the batch keeps stepping; its latency is
-finish - arrival.
+finish - arrival.  A combination onto a large finest grid (a 256^4 grid is about a second of the
+whole GPU) goes in chunks of finest-grid tiles, one chunk in flight at a time, so the batch's
+steps keep running between them instead of waiting behind it.
 """
 from __future__ import annotations
 
@@ -64,9 +66,12 @@ class Result:
 class ServingLoop:
     def __init__(self, precision: int = B.FP32_SWEEP, max_active: int = 64, hbm_budget: int = 64 << 30,
                  steps_per_tick: int = 8, keep_outputs: bool = False, box_target: int = 0,
-                 blocks_per_cu: int = 0, device: str = "cuda", max_bypass_s: float = 0.5):
+                 blocks_per_cu: int = 0, device: str = "cuda", max_bypass_s: float = 0.5,
+                 chunk_fine_nodes: int = 1 << 25):
         self.precision = precision
         self.max_bypass_s = max_bypass_s
+        # combinations onto more than 2 chunk_fine_nodes finest nodes go in chunks of about that many
+        self.chunk_fine_nodes = int(chunk_fine_nodes)
         self.max_active = max_active
         self.budget = int(hbm_budget)
         self.steps_per_tick = steps_per_tick
@@ -91,12 +96,13 @@ class ServingLoop:
         queue = collections.deque()
         active: Dict[int, tuple] = {}
         finishing: List[tuple] = []
+        combining: List[list] = []  # chunked combinations, oldest first
         used = 0
         results: List[Result] = []
         plans: Dict[int, Plan] = {}
         t0 = clock()
         polling = False  # a poll_begin whose flags have not been read yet
-        while pending or queue or active or finishing:
+        while pending or queue or active or finishing or combining:
             now = clock() - t0
             while pending and pending[0].arrival_s <= now:
                 queue.append(pending.popleft())
@@ -147,12 +153,26 @@ class ServingLoop:
                 else:
                     still.append((req, solver, admit_s, fp, ev, U, steps))
             finishing = still
+            # the oldest chunked combination: its next chunk once the previous one has run
+            if combining:
+                job = combining[0]
+                req, solver, admit_s, fp, U, steps, nxt, per, ev = job
+                if ev is None or ev.query():
+                    n = min(per, solver.plan.fine_tile_count - nxt)
+                    with torch.cuda.stream(self.side):
+                        solver.prolongate_combine_tiles(U, nxt, n)
+                        ev = torch.cuda.Event()
+                        ev.record(self.side)
+                    job[6], job[8] = nxt + n, ev
+                    if job[6] == solver.plan.fine_tile_count:
+                        combining.pop(0)
+                        finishing.append((req, solver, admit_s, fp, ev, U, steps))
             if not active:
                 if polling:
                     # nothing left to report: a released slot is never reported
                     self.batch.poll_end()
                     polling = False
-                if finishing:
+                if finishing or combining:
                     time.sleep(0.0002)
                 elif pending:
                     wait = pending[0].arrival_s - (clock() - t0)
@@ -176,6 +196,14 @@ class ServingLoop:
                 # the batch stream has finished this solve's steps (poll synchronised it); the
                 # set-up stream's restriction was ordered before its admission
                 solver.set_stream(self.side)
+                plan = solver.plan
+                if plan.fine_nodes > 2 * self.chunk_fine_nodes:
+                    with torch.cuda.stream(self.side):
+                        U = torch.empty(plan.fine_nodes, dtype=torch.float64, device=self.device)
+                    tile_nodes = plan.fine_nodes // plan.fine_tile_count
+                    combining.append([req, solver, admit_s, fp, U, steps, 0,
+                                      max(1, self.chunk_fine_nodes // tile_nodes), None])
+                    continue
                 with torch.cuda.stream(self.side):
                     U = solver.prolongate_combine()
                     ev = torch.cuda.Event()

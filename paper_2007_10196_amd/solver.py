@@ -35,6 +35,9 @@ class Plan:
         ft = (C.c_int32 * 4)()
         B.check(B.lib().sgw_plan_fine_tile(h, ft))
         self.fine_tile = tuple(ft[:problem.d])
+        ntile = C.c_int64()
+        B.check(B.lib().sgw_plan_fine_tile_count(h, C.byref(ntile)))
+        self.fine_tile_count = ntile.value
         self.grids = []
         for i in range(self.num_grids):
             lv, sh = (C.c_int32 * 4)(), (C.c_int32 * 4)()
@@ -107,6 +110,13 @@ class Solver:
             out = torch.empty(self.plan.fine_nodes, dtype=torch.float64, device=self.device)
         assert out.dtype == torch.float64 and out.numel() >= self.plan.fine_nodes and out.is_contiguous()
         B.check(B.lib().sgw_prolongate_combine(self.handle, C.c_void_p(out.data_ptr())))
+        return out
+
+    def prolongate_combine_tiles(self, out: torch.Tensor, first_tile: int, num_tiles: int) -> torch.Tensor:
+        """Step 3 at finest-grid tiles first_tile .. first_tile + num_tiles - 1 of ``out``."""
+        assert out.dtype == torch.float64 and out.numel() >= self.plan.fine_nodes and out.is_contiguous()
+        B.check(B.lib().sgw_prolongate_combine_tiles(self.handle, C.c_void_p(out.data_ptr()), int(first_tile),
+                                                     int(num_tiles)))
         return out
 
     def exact(self, t: float, out: Optional[torch.Tensor] = None) -> torch.Tensor:

@@ -255,6 +255,44 @@ def test_full_size_sampled(name, make):
     assert np.max(np.abs(ex - np.array(gd["fine_exact"]))) < 1e-13
 
 
+@pytest.mark.parametrize("name,make", [("2d", lambda: W.c2_burgers_2d(nl=4, precision=0)),
+                                       ("3d", lambda: W.c3_advection_3d(nr=8, nl=3, precision=1)),
+                                       ("4d", lambda: W.c4_vlasov_4d(nl=3, precision=0))])
+def test_prolongation_over_tile_ranges_equals_one_call(name, make):
+    """sgw_prolongate_combine_tiles over uneven ranges that cover every finest-grid tile once (an
+    empty range among them) gives sgw_prolongate_combine's output bitwise, leaves the entries of
+    other tiles untouched, and refuses ranges outside 0..count."""
+    torch, B, Solver, _ = _lib()
+    pb = make()
+    _announce(f"tile ranges {name}")
+    s = Solver(pb)
+    noise = W.component_noise(s.plan.total_nodes, seed=23)
+    dev = torch.from_numpy(noise).cuda()
+    for g, info in enumerate(s.plan.grids):
+        n = int(np.prod(info["shape"]))
+        s.set_grid(g, dev[info["offset"]: info["offset"] + n].to(dtype=s.real))
+    whole = s.prolongate_combine()
+    nt = s.plan.fine_tile_count
+    assert nt == s.plan.fine_nodes // int(np.prod(s.plan.fine_tile))
+    out = torch.full_like(whole, float("nan"))
+    cuts = sorted({0, nt, 1, nt // 3, nt // 3, nt // 2 + 1, nt - 1})
+    cuts = [c for c in cuts if 0 <= c <= nt]
+    first_part = None
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        s.prolongate_combine_tiles(out, a, b - a)
+        if first_part is None:
+            torch.cuda.synchronize()
+            first_part = int(torch.isnan(out).sum().item())
+    s.prolongate_combine_tiles(out, nt // 3, 0)
+    torch.cuda.synchronize()
+    assert first_part == (nt - cuts[1]) * int(np.prod(s.plan.fine_tile))
+    assert torch.equal(out, whole)
+    for a, n in ((-1, 1), (0, nt + 1), (nt, 1), (2, -1)):
+        with pytest.raises(B.SgwError) as e:
+            s.prolongate_combine_tiles(out, a, n)
+        assert e.value.status == -1
+
+
 @pytest.mark.parametrize("name,make", [("c3", lambda: W.c3_advection_3d(precision=0)),
                                        ("c4", lambda: W.c4_vlasov_4d(precision=0))])
 def test_full_size_prolongation_whole_tiles(name, make):

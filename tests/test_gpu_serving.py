@@ -46,6 +46,26 @@ def test_serving_results_equal_solo_results():
     loop.close()
 
 
+def test_chunked_combinations_equal_solo_results():
+    """Every combination forced into chunks of a few finest-grid tiles (chunk_fine_nodes tiny): the
+    served results are still bitwise the solo ones."""
+    import torch
+    from paper_2007_10196_amd import binding as B
+    from paper_2007_10196_amd.serving import ServingLoop
+    from paper_2007_10196_amd.solver import Solver
+    reqs = _mixed_stream(n=6, seed=41)
+    loop = ServingLoop(precision=B.FP32_SWEEP, max_active=4, hbm_budget=8 << 30, steps_per_tick=4,
+                       keep_outputs=True, chunk_fine_nodes=3000)
+    res = loop.run(reqs)
+    torch.cuda.synchronize()
+    assert sorted(r.rid for r in res) == [r.rid for r in reqs]
+    by_id = {r.rid: r for r in reqs}
+    for r in res:
+        solo = Solver(by_id[r.rid].problem).solve(mode=B.RUN_GRAPH).cpu().numpy()
+        assert np.array_equal(r.out.cpu().numpy(), solo), r.rid
+    loop.close()
+
+
 def test_serving_fp32_results_close_to_fp64_oracle():
     import torch
     from paper_2007_10196_amd import binding as B
