@@ -13,8 +13,9 @@ stream) and reads the completion flags gathered after the previous tick, whose
 copy overlapped this tick's steps.  A finished solve leaves the batch and is prolongated and
 combined on a second stream while the batch keeps stepping; its latency is
 finish - arrival.  A combination onto a large finest grid (a 256^4 grid is about a second of the
-whole GPU) goes in chunks of finest-grid tiles, one chunk in flight at a time, so the batch's
-steps keep running between them instead of waiting behind it.
+whole GPU) goes in chunks of finest-grid tiles, one chunk in flight at a time for each of the
+max_chunked such combinations with the fewest tiles left, so the batch's steps keep running
+between them instead of waiting behind them.
 """
 from __future__ import annotations
 
@@ -67,11 +68,12 @@ class ServingLoop:
     def __init__(self, precision: int = B.FP32_SWEEP, max_active: int = 64, hbm_budget: int = 64 << 30,
                  steps_per_tick: int = 8, keep_outputs: bool = False, box_target: int = 0,
                  blocks_per_cu: int = 0, device: str = "cuda", max_bypass_s: float = 0.5,
-                 chunk_fine_nodes: int = 1 << 25):
+                 chunk_fine_nodes: int = 1 << 25, max_chunked: int = 1):
         self.precision = precision
         self.max_bypass_s = max_bypass_s
         # combinations onto more than 2 chunk_fine_nodes finest nodes go in chunks of about that many
         self.chunk_fine_nodes = int(chunk_fine_nodes)
+        self.max_chunked = max(1, int(max_chunked))
         self.max_active = max_active
         self.budget = int(hbm_budget)
         self.steps_per_tick = steps_per_tick
@@ -96,7 +98,7 @@ class ServingLoop:
         queue = collections.deque()
         active: Dict[int, tuple] = {}
         finishing: List[tuple] = []
-        combining: List[list] = []  # chunked combinations, oldest first
+        combining: List[list] = []  # chunked combinations
         used = 0
         results: List[Result] = []
         plans: Dict[int, Plan] = {}
@@ -153,9 +155,14 @@ class ServingLoop:
                 else:
                     still.append((req, solver, admit_s, fp, ev, U, steps))
             finishing = still
-            # the oldest chunked combination: its next chunk once the previous one has run
-            if combining:
-                job = combining[0]
+            # chunked combinations, the max_chunked with the fewest tiles left (a short one is not
+            # held up behind a long one): each one's next chunk once its previous one has run
+            combining.sort(key=lambda job: job[1].plan.fine_tile_count - job[6])
+            still = []
+            for j, job in enumerate(combining):
+                if j >= self.max_chunked:
+                    still.append(job)
+                    continue
                 req, solver, admit_s, fp, U, steps, nxt, per, ev = job
                 if ev is None or ev.query():
                     n = min(per, solver.plan.fine_tile_count - nxt)
@@ -165,8 +172,10 @@ class ServingLoop:
                         ev.record(self.side)
                     job[6], job[8] = nxt + n, ev
                     if job[6] == solver.plan.fine_tile_count:
-                        combining.pop(0)
                         finishing.append((req, solver, admit_s, fp, ev, U, steps))
+                        continue
+                still.append(job)
+            combining = still
             if not active:
                 if polling:
                     # nothing left to report: a released slot is never reported
