@@ -208,6 +208,10 @@ def serving_run(box_target, n=None, loads=(0.7,), blocks_per_cu=0):
     probe = W.serving_stream(n=n, rate_hz=1.0)
 
     def serve(reqs):
+        # each run starts from an empty allocator cache: blocks cached by the previous run (the
+        # 34 GB outputs among them) would otherwise meet this run's allocations, and torch's
+        # free-and-retry on a full device synchronises it in the middle of the run
+        torch.cuda.empty_cache()
         loop = ServingLoop(precision=B.FP32_SWEEP, max_active=64, hbm_budget=160 << 30, steps_per_tick=8,
                            box_target=box_target, blocks_per_cu=blocks_per_cu)
         t0 = time.perf_counter()

@@ -166,6 +166,8 @@ class ServingLoop:
                 req, solver, admit_s, fp, U, steps, nxt, per, ev = job
                 if ev is None or ev.query():
                     n = min(per, solver.plan.fine_tile_count - nxt)
+                    if not (active or queue or pending):
+                        n = solver.plan.fine_tile_count - nxt  # nothing can wait behind it any more
                     with torch.cuda.stream(self.side):
                         solver.prolongate_combine_tiles(U, nxt, n)
                         ev = torch.cuda.Event()
