@@ -393,6 +393,7 @@ __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __
                     int li = 5;
                     centre_setup<Real, LAG>(z, w);
                     int next = ifirst * R + half - Jk;
+#pragma unroll 2
                     for (int t = 0; t < T0; t++) {
                         if (t == next) {
                             slide_next<Real, LAG>(w, val(li), eps4);
@@ -431,6 +432,7 @@ __device__ __forceinline__ void prolong_tile_lines(ProC pro, FineC F, double* __
                     const Real* nx = sp + 5 * inner;
                     centre_setup<Real, LAG>(z, w);
                     int next = ifirst * R + half - Jk; // first node of the next centre
+#pragma unroll 4
                     for (int t = 0; t < Tk; t++) {
                         if (t == next) {
                             slide_next<Real, LAG>(w, *nx, eps4);
