@@ -854,6 +854,7 @@ __device__ __forceinline__ void plane_item(GridC g, int item, int stage, Real al
     // LDS rows of n0 values at the odd stride RS = n0 + 1: threads on neighbouring rows (direction 1)
     // and on neighbouring columns (direction 2) hit distinct banks
     const int RS = n0 + 1;
+#pragma unroll 8
     for (int e = tid; e < N; e += SGW_BLOCK) {
         const int row = (int)FDIV((uint32_t)e, g->fd_n[0]);
         V[row * RS + (e - row * n0)] = in[e];
@@ -866,6 +867,7 @@ __device__ __forceinline__ void plane_item(GridC g, int item, int stage, Real al
         const int nseg = (n0 + SGW_PSEG - 1) / SGW_PSEG, rows = np * n1, csrc = g->coef_src[0];
         const Real ih = (Real)g->inv_h[0];
         const bool zero = ZB && (g->zmask & 1);
+#pragma unroll 2
         for (int sgi = tid; sgi < rows * nseg; sgi += SGW_BLOCK) {
             const int q = sgi / rows, row = sgi - q * rows;
             const int i0 = q * SGW_PSEG;
@@ -907,6 +909,7 @@ __device__ __forceinline__ void plane_item(GridC g, int item, int stage, Real al
         const int nseg = (n1 + SGW_PSEG - 1) / SGW_PSEG, cols = np * n0, csrc = g->coef_src[1];
         const Real ih = (Real)g->inv_h[1];
         const bool zero = ZB && ((g->zmask >> 1) & 1);
+#pragma unroll 2
         for (int sgi = tid; sgi < cols * nseg; sgi += SGW_BLOCK) {
             const int q = sgi / cols, col = sgi - q * cols;
             const int pl = col / n0, x0 = col - pl * n0;
@@ -942,6 +945,7 @@ __device__ __forceinline__ void plane_item(GridC g, int item, int stage, Real al
         }
     }
     __syncthreads();
+#pragma unroll 8
     for (int e = tid; e < N; e += SGW_BLOCK) {
         const int row = (int)FDIV((uint32_t)e, g->fd_n[0]);
         part[e] = A[row * RS + (e - row * n0)];
