@@ -878,3 +878,108 @@ def test_snapshot_restore_resumes_bitwise():
         assert a.query() == b.query()
         assert a.query()[0] == pb.T
         assert torch.equal(a.prolongate_combine(), b.prolongate_combine())
+
+
+# --------------------------------------------------------------------------- translation and canaries
+
+def _adv4():
+    """4D advection (line sweeps with the plane launch) on a small sparse grid."""
+    return W.Problem(d=4, lo=(0.0,) * 4, hi=(2.0,) * 4, flux=W.FLUX_ADVECTION, flux_params=(1.0, -0.5, 0.75, 0.25),
+                     ic=W.IC_SINE, ic_params=(0.0, 1.0, math.pi, 0.3), nr=4, nl=2, T=0.1, cfl=0.5,
+                     precision=W.PREC_FP64, name="advection_4d")
+
+
+def _shifted_grids(s, pb, k):
+    """u^n of every grid of solver s cyclically shifted by one root cell along direction k (2^{l_k}
+    nodes), as a list of device tensors in the solver's precision."""
+    torch = __import__("torch")
+    out = []
+    for info in s.plan.grids:
+        shape = info["shape"]
+        n = int(np.prod(shape))
+        a = s.state_copy()[info["offset"]: info["offset"] + n].reshape(tuple(reversed(shape)))
+        out.append(torch.roll(a, shifts=1 << info["level"][k], dims=pb.d - 1 - k).contiguous().reshape(-1))
+    return out
+
+
+@pytest.mark.parametrize("name,make,k", [
+    ("burgers_2d_x", lambda: W.c2_burgers_2d(nl=4, T=0.05, precision=0), 0),
+    ("burgers_2d_y", lambda: W.c2_burgers_2d(nl=4, T=0.05, precision=1), 1),
+    ("advection_3d_z", lambda: W.c3_advection_3d(nr=8, nl=3, T=0.1, precision=0), 2),
+    ("advection_4d_x", lambda: _adv4(), 0),
+    ("advection_4d_w", lambda: _adv4(), 3),
+])
+def test_translation_by_one_root_cell_is_exact(name, make, k):
+    """Translation invariance on the GPU: initial grids shifted cyclically by one root cell along
+    direction k (set through sgw_set_grid) march to the shifted component grids and combine to the
+    finest-grid solution shifted by 2^{N_L} nodes, bit for bit (the shift moves every node across
+    stage-box and prolongation-tile edges, which do not move)."""
+    torch, B, Solver, _ = _lib()
+    pb = make()
+    _announce(f"translation {name}")
+    a = Solver(pb)
+    a.restrict()
+    shifted = _shifted_grids(a, pb, k)
+    a.advance()
+    Ua = a.prolongate_combine()
+    b = Solver(pb)
+    for g, v in enumerate(shifted):
+        b.set_grid(g, v)
+    b.advance()
+    Ub = b.prolongate_combine()
+    assert a.query() == b.query()
+    for ga, gb in zip(_shifted_grids(a, pb, k), (b.grid(g) for g in range(len(b.plan.grids)))):
+        assert torch.equal(ga, gb)
+    n = pb.n_fine
+    Ua_s = torch.roll(Ua.reshape((n,) * pb.d), shifts=1 << pb.nl, dims=pb.d - 1 - k).reshape(-1)
+    assert torch.equal(Ua_s, Ub)
+
+
+@pytest.mark.parametrize("k", [0, 3])
+def test_4d_prolongation_translation_by_one_root_cell_is_exact(k):
+    """The 4D line-form prolongation of seeded noise: grids shifted by one root cell along direction
+    k combine to the finest grid shifted by 2^{N_L} nodes, bit for bit."""
+    torch, B, Solver, _ = _lib()
+    pb = W.c4_vlasov_4d(nl=3, precision=0)
+    _announce(f"4D prolongation translation along direction {k + 1}")
+    a = Solver(pb)
+    noise = torch.from_numpy(W.component_noise(a.plan.total_nodes, seed=29)).cuda()
+    for g, info in enumerate(a.plan.grids):
+        n = int(np.prod(info["shape"]))
+        a.set_grid(g, noise[info["offset"]: info["offset"] + n].clone())
+    Ua = a.prolongate_combine()
+    b = Solver(pb)
+    for g, v in enumerate(_shifted_grids(a, pb, k)):
+        b.set_grid(g, v)
+    Ub = b.prolongate_combine()
+    n = pb.n_fine
+    assert torch.equal(torch.roll(Ua.reshape((n,) * 4), shifts=1 << pb.nl, dims=3 - k).reshape(-1), Ub)
+
+
+@pytest.mark.parametrize("name,make", [("2d", lambda: W.c2_burgers_2d(nl=4, T=0.02, precision=1)),
+                                       ("4d", lambda: W.c4_vlasov_4d(nl=2, T=0.02, precision=0))])
+def test_outputs_leave_canaries_beyond_the_finest_grid(name, make):
+    """Output canaries: the combination, its tile-range form, the exact solution and the batched
+    combination write the finest grid and nothing after it (a canary tail of 4096 entries)."""
+    torch, B, Solver, _ = _lib()
+    from paper_2007_10196_amd.solver import prolongate_combine_many
+    pb = make()
+    _announce(f"canaries {name}")
+    s = Solver(pb)
+    s.restrict()
+    s.advance()
+    nf, tail = s.plan.fine_nodes, 4096
+    canary = -1.2345e300
+    for fill in ("combine", "tiles", "exact", "many"):
+        out = torch.full((nf + tail,), canary, dtype=torch.float64, device="cuda")
+        if fill == "combine":
+            s.prolongate_combine(out)
+        elif fill == "tiles":
+            s.prolongate_combine_tiles(out, 0, s.plan.fine_tile_count)
+        elif fill == "exact":
+            s.exact(pb.T, out)
+        else:
+            prolongate_combine_many([s], [out])
+        torch.cuda.synchronize()
+        assert bool((out[nf:] == canary).all()), fill
+        assert not bool((out[:nf] == canary).any()), fill
