@@ -983,3 +983,34 @@ def test_outputs_leave_canaries_beyond_the_finest_grid(name, make):
         torch.cuda.synchronize()
         assert bool((out[nf:] == canary).all()), fill
         assert not bool((out[:nf] == canary).any()), fill
+
+
+@pytest.mark.parametrize("name,make", [("2d_fp32", lambda: W.c2_burgers_2d(nr=10, nl=3, T=0.05, precision=1)),
+                                       ("3d_fp64", lambda: W.c3_advection_3d(nr=6, nl=2, T=0.1, precision=0)),
+                                       ("4d_fp64", lambda: _adv4().replace(nr=5))])
+def test_state_padding_canaries(name, make):
+    """Pad canaries: the bytes after the component grids in each of the three state copies (up to
+    the 256-byte aligned copy size) hold NaN patterns through a whole solve; they are never written,
+    and never read into a result (bitwise the same solve without them)."""
+    torch, B, Solver, _ = _lib()
+    pb = make()
+    _announce(f"pad canaries {name}")
+    esz = 8 if pb.precision == W.PREC_FP64 else 4
+    a = Solver(pb)
+    copy = a.plan.state_bytes // 3
+    used = a.plan.total_nodes * esz
+    if copy - used < esz:
+        pytest.skip(f"no padding after the grids ({copy} = {used} bytes)")
+    a.restrict()
+    pads = [a.state[c * copy + used: (c + 1) * copy] for c in range(3)]
+    for p in pads:
+        p.fill_(0xFF)
+    a.advance()
+    Ua = a.prolongate_combine()
+    b = Solver(pb)
+    b.restrict()
+    b.advance()
+    Ub = b.prolongate_combine()
+    torch.cuda.synchronize()
+    assert all(bool((p == 0xFF).all()) for p in pads)
+    assert torch.equal(Ua, Ub) and torch.equal(a.state_copy(), b.state_copy())
