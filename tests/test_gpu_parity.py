@@ -1014,3 +1014,59 @@ def test_state_padding_canaries(name, make):
     torch.cuda.synchronize()
     assert all(bool((p == 0xFF).all()) for p in pads)
     assert torch.equal(Ua, Ub) and torch.equal(a.state_copy(), b.state_copy())
+
+
+def test_cancelled_solve_leaves_the_others_and_resumes_alone_bitwise():
+    """A solve released from a running batch halfway (a cancel) leaves the other solves' results
+    bitwise equal to their solo runs, and itself resumes alone to the same bits as its solo run."""
+    torch, B, Solver, Batch = _lib()
+    rng = np.random.default_rng(17)
+    probs = [W.randomized(f, nl, rng, precision=W.PREC_FP64) for f, nl in [(1, 3), (2, 3), (3, 2)]]
+    probs = [p.replace(T=min(p.T, 0.15)) for p in probs]
+    solo = [Solver(p).solve(mode=B.RUN_GRAPH).cpu().numpy() for p in probs]
+    _announce("cancel in a batch")
+    batch = Batch(max_solvers=4, precision=B.FP64, hbm_budget=1 << 34)
+    solvers, slots = [], []
+    for p in probs:
+        s = Solver(p)
+        s.restrict()
+        slots.append(batch.admit(s))
+        solvers.append(s)
+    batch.step(3)
+    cancelled = batch.release(slots[1])
+    assert cancelled is solvers[1]
+    t_mid, steps_mid = cancelled.query()
+    assert 0 < t_mid < probs[1].T and steps_mid == 3
+    done = set()
+    for _ in range(400):
+        batch.step(4)
+        done |= set(batch.poll())
+        if done >= {slots[0], slots[2]}:
+            break
+    assert done >= {slots[0], slots[2]} and slots[1] not in done
+    for i in (0, 2):
+        assert np.array_equal(solvers[i].prolongate_combine().cpu().numpy(), solo[i])
+    cancelled.advance()
+    assert np.array_equal(cancelled.prolongate_combine().cpu().numpy(), solo[1])
+    for sl in (slots[0], slots[2]):
+        batch.release(sl)
+    batch.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_zero_wave_speed_takes_one_step(prec):
+    """With every wave speed 0 the CFL step has no bound: the solve takes one step to T (dt = T - t),
+    as the oracle does, and the fluxes vanish, so the combined solution is the initial one up to the
+    rounding of the Runge-Kutta combinations (3/4 u + 1/4 u, 1/3 u + 2/3 u)."""
+    torch, B, Solver, _ = _lib()
+    pb = W.c1_advection_2d(nr=8, nl=3).replace(flux_params=(0.0, 0.0), T=0.7, precision=prec)
+    _announce(f"zero speed precision {prec}")
+    s = Solver(pb)
+    s.restrict()
+    U0 = s.prolongate_combine().clone()
+    s.advance()
+    t, steps = s.query()
+    stats = O.evolve(pb.replace(precision=W.PREC_FP64), O.restrict(pb.replace(precision=W.PREC_FP64)))
+    assert steps == 1 == stats["steps"] and t == pb.T == stats["t"]
+    tol = 1e-14 if prec == 0 else 1e-6
+    assert float((s.prolongate_combine() - U0).abs().max()) <= tol
