@@ -142,10 +142,13 @@ typedef struct sgw_config {
                                       automatic box search may pick, 64..2048                      */
     int32_t blocks_per_cu;         /* 0: as many resident stage workgroups per compute unit as
                                       fit; else at most this many (1..64), a tuning knob         */
-    int32_t sweep_form;            /* line sweeps of 4D plans: 0 automatic (directions 1 and 2 in one
-                                      launch over whole (x_1, x_2) planes staged in LDS, then one
-                                      launch per remaining direction); 1 one launch per direction.
-                                      Both give the same bits.                                    */
+    int32_t sweep_form;            /* 3D and 4D stages: 0 automatic (line sweeps, directions 1 and 2
+                                      in one launch over whole (x_1, x_2) planes staged in LDS where
+                                      every grid's planes fit 2048 nodes, then one launch per
+                                      remaining direction); 1 line sweeps, one launch per
+                                      direction; 2 stage boxes for 3D (a grid that is one box runs
+                                      its three RK stages in one launch: many small 3D solves in a
+                                      batch), 4D as 0.  All give the same bits.                   */
 } sgw_config;
 
 typedef struct sgw_plan sgw_plan_t;
@@ -200,11 +203,10 @@ sgw_status sgw_plan_fine_tile(const sgw_plan_t* plan, int32_t tile[SGW_MAX_DIM])
 /* Number of finest-grid tiles of the prolongation: prod_k N / tile[k]. */
 sgw_status sgw_plan_fine_tile_count(const sgw_plan_t* plan, int64_t* count);
 
-/* Box extents the stage kernel uses for grid g (one workgroup per box).  4D grids
- * without manual boxes, and every grid of a plan with a zero boundary, relaxation or the
- * Vlasov-Maxwell flux,
- * march as line sweeps (one launch per direction, a lane per segment of a grid line,
- * no boxes) and report all-zero extents. */
+/* Box extents the stage kernel uses for grid g (one workgroup per box).  3D and 4D grids
+ * without manual boxes (3D: unless sweep_form is 2), and every grid of a plan with a zero
+ * boundary, relaxation or the Vlasov-Maxwell flux, march as line sweeps (a lane per segment
+ * of a grid line, no boxes) and report all-zero extents. */
 sgw_status sgw_plan_grid_box(const sgw_plan_t* plan, int32_t g, int32_t box[SGW_MAX_DIM]);
 
 /* ---------------------------------------------------------------- solvers

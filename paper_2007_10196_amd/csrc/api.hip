@@ -575,8 +575,8 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     int target = 1024;
     if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64)
         return sgw_fail(SGW_ERR_INVALID_ARG, "blocks_per_cu %d outside 0..64", cfg->blocks_per_cu);
-    if (cfg->sweep_form < 0 || cfg->sweep_form > 1)
-        return sgw_fail(SGW_ERR_INVALID_ARG, "sweep_form %d outside 0..1", cfg->sweep_form);
+    if (cfg->sweep_form < 0 || cfg->sweep_form > 2)
+        return sgw_fail(SGW_ERR_INVALID_ARG, "sweep_form %d outside 0..2", cfg->sweep_form);
     if (cfg->box_target) {
         if (cfg->box_target < 64 || cfg->box_target > SGW_BLOCK * SGW_MAXR) {
             delete p;
@@ -606,10 +606,10 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
             delete p;
             return sgw_fail(SGW_ERR_UNSUPPORTED, "manual stage boxes with a zero boundary, relaxation or fields");
         }
-        if ((d == 4 || zmask || relax || vm) && !manual) {
-            // 4D, zero boundaries and relaxation: the line sweep (no stage boxes); a work item
-            // is SGW_LWAVE segments of sgw_lseg() nodes, enough items for the direction with the
-            // most segments
+        if ((d == 4 || (d == 3 && cfg->sweep_form != 2) || zmask || relax || vm) && !manual) {
+            // 3D and 4D (3D stage boxes on request), zero boundaries and relaxation: the line
+            // sweep (no stage boxes); a work item is SGW_LWAVE segments of sgw_lseg() nodes,
+            // enough items for the direction with the most segments
             gd.line_mode = 1;
             gd.zmask = zmask;
             int64_t most = 0;
@@ -657,9 +657,10 @@ extern "C" sgw_status sgw_plan_create(const sgw_problem* pb, const sgw_config* c
     }
     p->offsets[p->G] = tot;
     p->total_nodes = tot;
-    // 4D line sweeps: directions 1 and 2 in one launch over whole (x_1, x_2) planes when every grid's
-    // plane fits a work item
-    p->plane01 = d == 4 && p->line_mode && cfg->sweep_form == 0;
+    // 3D and 4D line sweeps: directions 1 and 2 in one launch over whole (x_1, x_2) planes when every
+    // grid's plane fits a work item (the Vlasov-Maxwell coefficients come from the fields in the line
+    // sweep only)
+    p->plane01 = p->line_mode && !vm && ((d == 4 && cfg->sweep_form != 1) || (d == 3 && cfg->sweep_form == 0));
     for (int g = 0; g < p->G && p->plane01; g++)
         p->plane01 = p->grids[g].line_mode && p->grids[g].n[0] * p->grids[g].n[1] <= SGW_PLANE_CAP;
     p->nplane_items = 0;

@@ -52,6 +52,9 @@ struct sgw_batch {
     bool dirty = true;
     size_t lds[2][4] = {};          // LDS of the captured launches, [kind][dimension - 1] (0: not captured)
     int blocks[2][4] = {};
+    // the 3D solvers of a batch share one sweep form: line sweeps (lines3) or stage boxes; the
+    // captured graphs were built for cap_lines3
+    bool lines3 = false, cap_lines3 = false;
     int blocks_per_cu = 0;          // cap on resident stage workgroups per CU (0: occupancy)
     hipStream_t cap = nullptr;
     hipGraph_t graph[6] = {};           // graph[j]: 2^j steps
@@ -162,7 +165,7 @@ static hipError_t enqueue_stages(sgw_batch* b, int stage, hipStream_t st)
             const size_t l = b->lds[0][d] > b->lds[1][d] ? b->lds[0][d] : b->lds[1][d];
             e = launch_stage_range(b->items_d, b->ranges_d + (2 * 4 + d) * 2,
                                    stage_grid(b->precision, d + 1, l, b->blocks_per_cu), stage, b->precision, d + 1, l,
-                                   st, d == 3);
+                                   st, d == 3 || (d == 2 && b->lines3));
         }
         return e;
     }
@@ -176,7 +179,7 @@ static hipError_t enqueue_stages(sgw_batch* b, int stage, hipStream_t st)
         for (int d = 0; d < 4 && e == hipSuccess; d++)
             if (b->lds[1][d] && (all || b->ranges_h[1][d][1]))
                 e = launch_stage_range(b->items_d, b->ranges_d + (4 + d) * 2, b->blocks[1][d], s, b->precision, d + 1,
-                                       b->lds[1][d], st, d == 3);
+                                       b->lds[1][d], st, d == 3 || (d == 2 && b->lines3));
     return e;
 }
 
@@ -241,6 +244,12 @@ static sgw_status batch_sync(sgw_batch* b)
     }
     bool recapture = false;
     for (int j = 0; j < SGW_GRAPH_LEVELS; j++) recapture |= !b->exec[j];
+    for (int i = 0; i < b->max_solvers; i++)
+        if (b->slots[i] && b->slots[i]->plan->pb.dim == 3) {
+            b->lines3 = b->slots[i]->plan->line_mode;
+            break;
+        }
+    recapture |= b->lines3 != b->cap_lines3;
     for (int k = 0; k < 2; k++)
         for (int d = 0; d < 4; d++) recapture |= lds[k][d] > b->lds[k][d];
     if (recapture) {
@@ -257,6 +266,7 @@ static sgw_status batch_sync(sgw_batch* b)
                 b->blocks[k][d] =
                     b->lds[k][d] ? stage_grid(b->precision, d + 1, b->lds[k][d], b->blocks_per_cu, k == 0) : 0;
             }
+        b->cap_lines3 = b->lines3;
         e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
         if (e != hipSuccess) return sgw_hip_fail(e, "capture stream");
         for (int which = 0; which < SGW_GRAPH_LEVELS; which++) {
@@ -307,10 +317,16 @@ static sgw_status admit_one(sgw_batch_t* b, sgw_solver_t* s, double t_final, int
     // a batch runs its 4D grids as line sweeps
     if (s->plan->pb.dim == 4 && !s->plan->line_mode)
         return sgw_fail(SGW_ERR_UNSUPPORTED, "4D solvers with manual stage boxes run alone, not in a batch");
-    // the batch launches carry no density pass and run 2D/3D grids as boxes
+    // the batch launches carry no density pass
     if (s->plan->relax || s->plan->zmask || s->plan->vm)
         return sgw_fail(SGW_ERR_UNSUPPORTED,
                         "zero-boundary, relaxation and Vlasov-Maxwell solvers run alone, not in a batch");
+    // its 3D solvers share one sweep form (line sweeps, or stage boxes with sweep_form 2)
+    if (s->plan->pb.dim == 3)
+        for (int i = 0; i < b->max_solvers; i++)
+            if (b->slots[i] && b->slots[i]->plan->pb.dim == 3 && b->slots[i]->plan->line_mode != s->plan->line_mode)
+                return sgw_fail(SGW_ERR_UNSUPPORTED,
+                                "3D solvers of one batch share their sweep form (line sweeps or stage boxes)");
     if (!(t_final >= 0.0)) return sgw_fail(SGW_ERR_INVALID_ARG, "bad final time");
     const uint64_t need = solver_bytes(s);
     if (b->used + need > b->budget)

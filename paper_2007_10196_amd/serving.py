@@ -113,7 +113,9 @@ class ServingLoop:
                 tp = clock()
                 for req in queue:
                     if req.rid not in plans:
-                        plans[req.rid] = Plan(req.problem, box_target=self.box_target)
+                        # 3D requests as stage boxes: most of them are small grids that run
+                        # their three RK stages in one launch
+                        plans[req.rid] = Plan(req.problem, box_target=self.box_target, sweep_form=2)
                 self.stats["plan"] += clock() - tp
                 for req in queue:
                     if plans[req.rid].footprint > self.budget:

@@ -93,6 +93,44 @@ def test_small_configs_fp64(name, make):
     _check_fp64(make())
 
 
+@pytest.mark.parametrize("name,make", [s for s in SMALL if s[0].startswith(("c3", "single_grid_3d", "negative"))],
+                         ids=[s[0] for s in SMALL if s[0].startswith(("c3", "single_grid_3d", "negative"))])
+def test_small_3d_configs_as_stage_boxes_fp64(name, make):
+    """The 3D configurations with stage boxes (sweep_form 2) instead of the default line sweeps."""
+    _check_fp64(make(), sweep_form=2)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_3d_sweep_forms_give_the_same_bits(prec):
+    """3D: line sweeps with the plane launch (default), one line launch per direction, and stage
+    boxes give the same bits, in a solve and in a batch."""
+    torch, B, Solver, Batch = _lib()
+    pb = W.c3_advection_3d(nr=8, nl=3, T=0.2, precision=prec).replace(
+        flux=W.FLUX_BURGERS, flux_params=(), ic_params=(0.3, 0.6, math.pi, 0.4))
+    outs = {}
+    for sf in (0, 1, 2):
+        _announce(f"3D sweep form {sf} precision {prec}")
+        outs[sf] = Solver(pb, sweep_form=sf).solve().cpu().numpy()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    for sf in (0, 2):
+        batch = Batch(max_solvers=2, precision=B.FP64 if prec == 0 else B.FP32_SWEEP, hbm_budget=1 << 34)
+        s = Solver(pb, sweep_form=sf)
+        s.restrict()
+        slot = batch.admit(s)
+        other = Solver(pb, sweep_form=2 - sf)
+        other.restrict()
+        with pytest.raises(B.SgwError) as e:
+            batch.admit(other)
+        assert e.value.status == -2
+        for _ in range(200):
+            batch.step(8)
+            if slot in batch.poll():
+                break
+        batch.release(slot)
+        assert np.array_equal(s.prolongate_combine().cpu().numpy(), outs[0])
+        batch.close()
+
+
 def test_boxes_smaller_than_the_automatic_choice():
     # several boxes per grid, halos in every direction, odd box extents
     _check_fp64(W.c3_advection_3d(nr=6, nl=2, T=0.2), box=[3, 3, 3])

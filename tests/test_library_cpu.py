@@ -56,9 +56,9 @@ def test_plan_grid_set_matches_oracle(d, nl):
         assert info["shape"] == tuple(pb.nr << int(x) for x in lv[g])
         assert info["offset"] == off
         off += int(np.prod(info["shape"]))
-        if d == 4:
-            # 4D grids march as line sweeps: no stage boxes
-            assert info["box"] == (0, 0, 0, 0)
+        if d >= 3:
+            # 3D and 4D grids march as line sweeps by default: no stage boxes
+            assert info["box"] == (0,) * d
             continue
         for n, t in zip(info["shape"], info["box"]):
             assert n % t == 0
@@ -71,11 +71,14 @@ def test_plan_grid_set_matches_oracle(d, nl):
 
 @pytest.mark.parametrize("nr", [4, 5, 6, 7, 10, 12])
 def test_plan_handles_non_power_of_two_roots(nr):
+    """Stage boxes (3D with sweep_form 2) divide every extent; the default line sweeps plan for
+    the same roots."""
     pb = W.c3_advection_3d(nr=nr, nl=3)
-    plan = Plan(pb)
+    plan = Plan(pb, sweep_form=2)
     for info in plan.grids:
         for n, t in zip(info["shape"], info["box"]):
             assert n % t == 0
+    assert all(info["box"] == (0, 0, 0) for info in Plan(pb).grids)
 
 
 def _expect_status(pb, status, **kw):
