@@ -1006,8 +1006,9 @@ def example6(torch):
 
 def large_roofline(torch, reps=10):
     """Stage launches of one time step on the scaled cases whose state exceeds the 256 MB MALL: 3D
-    advection at root 32 (32.5 M nodes, box kernel) and the 4D Vlasov workload at root 16 (50.3 M
-    nodes, line sweep), FP64 and FP32, event-timed through the batch measurement hook."""
+    advection at root 32 (32.5 M nodes) and the 4D Vlasov workload at root 16 (50.3 M nodes), both as
+    line sweeps, one launch per direction and stage, FP64 and FP32, event-timed through the batch
+    measurement hook."""
     from paper_2007_10196_amd.solver import Batch, Solver
     out = []
     for name, make in (("c3_large", lambda p: W.c3_advection_3d(nr=32, precision=p)),
@@ -1030,9 +1031,11 @@ def large_roofline(torch, reps=10):
             nodes = s.plan.total_nodes
             esz = 8 if prec == W.PREC_FP64 else 4
             flops = nodes * flops_per_cell_update(pb.d)
-            # fused 3-stage minimum: stage 1 reads u and writes u1, stages 2 and 3 also read u^n (8 words);
-            # the 4D line sweep also moves its partial sums: 3 (3d - 1/3) words per step
-            words = 8.0 if pb.d == 3 else 3 * (3 * pb.d - 1.0 / 3.0)
+            # stage boxes, fused 3-stage minimum: stage 1 reads u and writes u1, stages 2 and 3 also read
+            # u^n (8 words); the line sweep (3D and 4D, one launch per direction in a batch) also moves
+            # its partial sums: 3 (3d - 1/3) words per step
+            boxes = s.plan.grids[0]["box"] != (0,) * pb.d
+            words = 8.0 if boxes else 3 * (3 * pb.d - 1.0 / 3.0)
             peak = PEAK_FP64_TFLOPS if prec == W.PREC_FP64 else PEAK_FP32_TFLOPS
             row = {"case": name, "precision": "fp64" if prec == W.PREC_FP64 else "fp32", "nodes": nodes,
                    "state_MB": 3 * nodes * esz / 1e6, "step_stage_us": us,
