@@ -68,12 +68,16 @@ class ServingLoop:
     def __init__(self, precision: int = B.FP32_SWEEP, max_active: int = 64, hbm_budget: int = 64 << 30,
                  steps_per_tick: int = 8, keep_outputs: bool = False, box_target: int = 0,
                  blocks_per_cu: int = 0, device: str = "cuda", max_bypass_s: float = 0.5,
-                 chunk_fine_nodes: int = 1 << 25, max_chunked: int = 1):
+                 chunk_fine_nodes: int = 1 << 25, max_chunked: int = 1, sweep_form: int = 0):
         self.precision = precision
         self.max_bypass_s = max_bypass_s
         # combinations onto more than 2 chunk_fine_nodes finest nodes go in chunks of about that many
         self.chunk_fine_nodes = int(chunk_fine_nodes)
         self.max_chunked = max(1, int(max_chunked))
+        # the stage form of the requests' plans (sgw_config.sweep_form; 2: 3D grids as stage boxes,
+        # whose one-box grids run their three RK stages in one launch; the same latency and
+        # throughput as line sweeps on the 512-request mix)
+        self.sweep_form = int(sweep_form)
         self.max_active = max_active
         self.budget = int(hbm_budget)
         self.steps_per_tick = steps_per_tick
@@ -113,9 +117,7 @@ class ServingLoop:
                 tp = clock()
                 for req in queue:
                     if req.rid not in plans:
-                        # 3D requests as stage boxes: most of them are small grids that run
-                        # their three RK stages in one launch
-                        plans[req.rid] = Plan(req.problem, box_target=self.box_target, sweep_form=2)
+                        plans[req.rid] = Plan(req.problem, box_target=self.box_target, sweep_form=self.sweep_form)
                 self.stats["plan"] += clock() - tp
                 for req in queue:
                     if plans[req.rid].footprint > self.budget:
