@@ -366,9 +366,13 @@ void sgw_batch_free(sgw_batch_t* batch);
 /* Scratch bytes a batch of max_solvers needs for at most max_items stage boxes. */
 uint64_t sgw_batch_scratch_bytes(int32_t max_solvers, int64_t max_items);
 /* Admit a restricted solver to advance to t_final.  SGW_ERR_OUT_OF_MEMORY when
- * no slot is free or its footprint does not fit the remaining budget.  Returns
- * without waiting: when the solver's stream differs from the batch stream, the
- * batch stream waits (an event) for the work already enqueued on it. */
+ * no slot is free or its footprint does not fit the remaining budget;
+ * SGW_ERR_UNSUPPORTED for zero-boundary, relaxation and Vlasov-Maxwell solvers, 4D
+ * solvers with manual stage boxes, and a 3D solver whose stage form (line sweeps or
+ * stage boxes, sweep_form) differs from that of the batch's other 3D solvers (a batch
+ * runs its 3D and 4D line sweeps one launch per direction).  Returns without waiting:
+ * when the solver's stream differs from the batch stream, the batch stream waits (an
+ * event) for the work already enqueued on it. */
 sgw_status sgw_batch_admit(sgw_batch_t* batch, sgw_solver_t* solver, double t_final, int32_t* slot);
 /* sgw_batch_admit for solvers[0..n) with final times t_final[i]; slots[i]
  * receives each slot.  Stops at the first solver that is refused and returns
