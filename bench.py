@@ -554,8 +554,11 @@ def c4_headline(args, torch):
     else:
         tune = tune_box_target([pb], pb.precision, reps=5)
     bt, bpc = int(tune["best"]), int(tune.get("blocks_per_cu", 0))
-    print(f"[bench] 4D Vlasov FP64: box target {bt}, {bpc or 'max'} workgroups per CU "
-          f"({'cached' if tune['cached'] else 'measured'})", file=sys.stderr, flush=True)
+    if tune.get("line_sweeps"):
+        print("[bench] 4D Vlasov FP64: line sweeps (no stage boxes to shape)", file=sys.stderr, flush=True)
+    else:
+        print(f"[bench] 4D Vlasov FP64: box target {bt}, {bpc or 'max'} workgroups per CU "
+              f"({'cached' if tune['cached'] else 'measured'})", file=sys.stderr, flush=True)
     r = solve_run(torch, pb, args.steps, args.warmup, bt, bpc)
     s = r["solver"]
     nodes, fine = s.plan.total_nodes, s.plan.fine_nodes
@@ -638,7 +641,8 @@ def c4_headline(args, torch):
             "finest_equivalent_cell_updates_per_s": r["time_steps"] * fine / (r["ms_per_solve"] * 1e-3),
             "roofline": by_time[0], "roofline_other": by_time[1:],
             "stage_step_us": stage_parts["step_us"], "fp32": fp32, "plain": plain,
-            "autotune": {"box_target": bt, "blocks_per_cu": bpc, "stage_us_by_target_and_cap": tune["us"]}}
+            "autotune": {"box_target": bt, "blocks_per_cu": bpc, "stage_us_by_target_and_cap": tune["us"],
+                         "line_sweeps": bool(tune.get("line_sweeps"))}}
     del r
     return head
 

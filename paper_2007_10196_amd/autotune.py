@@ -76,7 +76,12 @@ def tune_box_target(problems: Sequence, precision: int, candidates: Iterable[int
                     cache_path: Optional[str] = None, reps: int = 10, force: bool = False,
                     blocks_per_cu: Iterable[int] = BLOCKS_PER_CU) -> Dict:
     """Pick the fastest (box target, workgroups per CU) for this batch; returns
-    {"best": target, "blocks_per_cu": cap, "us": {"target/cap": us}, "cached": bool}."""
+    {"best": target, "blocks_per_cu": cap, "us": {"target/cap": us}, "cached": bool}.  Problems
+    whose grids all march as line sweeps (3D and 4D by default) have no stage boxes to shape:
+    then nothing is measured and {"best": 0, "blocks_per_cu": 0, "us": {}, "line_sweeps": True}
+    comes back (the library's defaults)."""
+    if all(not any(info["box"]) for p in problems for info in Plan(p).grids):
+        return {"best": 0, "blocks_per_cu": 0, "us": {}, "cached": False, "line_sweeps": True}
     path = cache_path or default_cache_path()
     key = workload_key(problems, precision)
     cache = _load(path)

@@ -243,3 +243,12 @@ def test_vlasov_maxwell_plans():
     _expect_status(vm.replace(bc=(1, 0, 0)), -2)
     _expect_status(vm, -2, box=[8, 8, 8])
     assert Plan(W.c3_advection_3d(nr=8, nl=2)).fields_count == 0
+
+
+def test_autotuner_skips_plans_without_stage_boxes():
+    """3D and 4D plans march as line sweeps by default: the launch-shape tuner has no box to shape
+    and returns the library's defaults without measuring (no GPU needed)."""
+    from paper_2007_10196_amd.autotune import tune_box_target
+    for pb in (W.c4_vlasov_4d(nl=2), W.c3_advection_3d(nl=2)):
+        rec = tune_box_target([pb], pb.precision)
+        assert rec["line_sweeps"] and rec["best"] == 0 and rec["blocks_per_cu"] == 0 and rec["us"] == {}
