@@ -49,6 +49,24 @@ def backfill_choice(footprints: List[int], waits: List[float], used: int, budget
 
 
 @dataclasses.dataclass
+class _Combining:
+    """A finished solve whose combination goes in chunks of finest-grid tiles."""
+    req: object
+    solver: Solver
+    admit_s: float
+    footprint: int
+    out: torch.Tensor
+    steps: int
+    per_chunk: int                  # tiles per chunk
+    next_tile: int = 0
+    event: Optional[torch.cuda.Event] = None  # behind the chunk in flight
+
+    @property
+    def tiles_left(self) -> int:
+        return self.solver.plan.fine_tile_count - self.next_tile
+
+
+@dataclasses.dataclass
 class Result:
     rid: int
     arrival_s: float
@@ -102,7 +120,7 @@ class ServingLoop:
         queue = collections.deque()
         active: Dict[int, tuple] = {}
         finishing: List[tuple] = []
-        combining: List[list] = []  # chunked combinations
+        combining: List[_Combining] = []
         used = 0
         results: List[Result] = []
         plans: Dict[int, Plan] = {}
@@ -161,24 +179,21 @@ class ServingLoop:
             finishing = still
             # chunked combinations, the max_chunked with the fewest tiles left (a short one is not
             # held up behind a long one): each one's next chunk once its previous one has run
-            combining.sort(key=lambda job: job[1].plan.fine_tile_count - job[6])
+            combining.sort(key=lambda job: job.tiles_left)
             still = []
             for j, job in enumerate(combining):
-                if j >= self.max_chunked:
-                    still.append(job)
-                    continue
-                req, solver, admit_s, fp, U, steps, nxt, per, ev = job
-                if ev is None or ev.query():
-                    n = min(per, solver.plan.fine_tile_count - nxt)
+                if j < self.max_chunked and (job.event is None or job.event.query()):
+                    n = min(job.per_chunk, job.tiles_left)
                     if not (active or queue or pending):
-                        n = solver.plan.fine_tile_count - nxt  # nothing can wait behind it any more
+                        n = job.tiles_left  # nothing can wait behind it any more
                     with torch.cuda.stream(self.side):
-                        solver.prolongate_combine_tiles(U, nxt, n)
-                        ev = torch.cuda.Event()
-                        ev.record(self.side)
-                    job[6], job[8] = nxt + n, ev
-                    if job[6] == solver.plan.fine_tile_count:
-                        finishing.append((req, solver, admit_s, fp, ev, U, steps))
+                        job.solver.prolongate_combine_tiles(job.out, job.next_tile, n)
+                        job.event = torch.cuda.Event()
+                        job.event.record(self.side)
+                    job.next_tile += n
+                    if job.tiles_left == 0:
+                        finishing.append((job.req, job.solver, job.admit_s, job.footprint, job.event, job.out,
+                                          job.steps))
                         continue
                 still.append(job)
             combining = still
@@ -216,8 +231,8 @@ class ServingLoop:
                     with torch.cuda.stream(self.side):
                         U = torch.empty(plan.fine_nodes, dtype=torch.float64, device=self.device)
                     tile_nodes = plan.fine_nodes // plan.fine_tile_count
-                    combining.append([req, solver, admit_s, fp, U, steps, 0,
-                                      max(1, self.chunk_fine_nodes // tile_nodes), None])
+                    combining.append(_Combining(req, solver, admit_s, fp, U, steps,
+                                                per_chunk=max(1, self.chunk_fine_nodes // tile_nodes)))
                     continue
                 with torch.cuda.stream(self.side):
                     U = solver.prolongate_combine()
