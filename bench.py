@@ -6,8 +6,9 @@ One step = the whole method for one solve of the 4D Vlasov workload at FP64
 E = 0.01 (sin(x1/2), sin(x2/2)), f0 = Maxwellian x (1 + 0.01 cos(x1/2) cos(x2/2));
 root grid 8^4, finest level 4 (128^4 finest nodes), 69 component grids,
 CFL 0.4, T = 1, 307 time steps): restriction, the shared-dt TVD-RK3 march of
-every component grid (step graphs, one persistent stage launch per RK stage over
-all boxes), WENO5 prolongation + FP64 combination onto the finest grid, and the
+every component grid (step graphs; per RK stage a plane launch for directions 1
+and 2 and a line sweep for each of directions 3 and 4, each persistent over every
+grid), WENO5 prolongation + FP64 combination onto the finest grid, and the
 L1/Linf norms against the exact solution (computed once, before timing).
 
 Prints one JSON line.  `value` is component-grid cell-updates per second of
@@ -1134,8 +1135,9 @@ def main():
                                   "grids, CFL 0.4, T = 1; FP64 throughout; one solve per step",
                       "component_nodes": head["nodes"], "finest_nodes": head["fine"],
                       "time_steps": head["time_steps"],
-                      "mode": "step graphs, one persistent WENO5-LF + TVD-RK3 stage launch per RK stage over all "
-                              "boxes, gather-fused WENO5 prolongation with FP64 combination"},
+                      "mode": "step graphs; per RK stage one plane launch (directions 1, 2) and one line sweep "
+                              "for each of directions 3, 4, each persistent over every grid; WENO5 prolongation "
+                              "(line form) with FP64 combination in one launch"},
            "l1": head["l1"], "linf": head["linf"], "parts_ms": head["parts"],
            "finest_equivalent_cell_updates_per_s": head["finest_equivalent_cell_updates_per_s"],
            "roofline": head["roofline"], "roofline_other": head["roofline_other"],
